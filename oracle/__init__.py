@@ -1,0 +1,191 @@
+"""Python access to the plain FP64 CPU oracle (oracle.c).
+
+TEST INFRASTRUCTURE ONLY: imported by the tests, the smoke check and the
+CPU-baseline leg of the benchmark, never by the product path.  It does not
+import the GPU package; matrices are passed as any object with `n`,
+`row_ptr`, `col` and `val` attributes (or as explicit arrays).
+
+Each function is the definition written out in oracle.c; see the comments
+there for the paper passage it follows.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+from . import build as _build
+
+TARGET_PLAIN = 0
+TARGET_RESIDUAL = 1
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        path = _build.build()
+        L = C.CDLL(path)
+        P = C.c_void_p
+        i32, i64, u64, f64 = C.c_int, C.c_int64, C.c_uint64, C.c_double
+        sig = {
+            "oracle_splitmix64_nth": (u64, [u64, u64]),
+            "oracle_tv_init": (None, [i64, i64, i32, u64, P]),
+            "oracle_jacobi": (i32, [i32, P, P, P, i32, f64, i32, P]),
+            "oracle_jacobi_rows": (None, [i32, P, P, P, i32, f64, P, i32, P, P]),
+            "oracle_color_gs": (i32, [i32, P, P, P, i32, P, i32, i32, P]),
+            "oracle_color_gs_rows": (None, [i32, P, P, P, i32, P, i32, P, P, i32, P, P]),
+            "oracle_algdist": (i32, [i32, P, P, P, i32, P, P, i32, i32, P, P, P]),
+            "oracle_strength": (None, [i32, P, P, P, f64, P, P, P]),
+            "oracle_ls_interp": (None, [i32, P, P, P, i32, P, P, P, P, i32, i32, i32, P, P, P, P, P]),
+            "oracle_ls_loss": (f64, [i32, P, P, P, i32, P, i32, f64, P, P, i32]),
+            "oracle_ls_loss_grad": (f64, [i32, P, P, P, i32, P, i32, f64, P, P, i32, P, P]),
+        }
+        for name, (res, args) in sig.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _p(a):
+    return None if a is None else a.ctypes.data_as(C.c_void_p)
+
+
+def _csr(A):
+    rp = np.ascontiguousarray(A.row_ptr, dtype=np.int32)
+    ci = np.ascontiguousarray(A.col, dtype=np.int32)
+    va = np.ascontiguousarray(A.val, dtype=np.float64)
+    return int(A.n), rp, ci, va
+
+
+def _f64(x):
+    return np.ascontiguousarray(x, dtype=np.float64)
+
+
+def _rows(rows):
+    return None if rows is None else np.ascontiguousarray(rows, dtype=np.int32)
+
+
+def splitmix64_nth(seed: int, n: int) -> int:
+    return int(lib().oracle_splitmix64_nth(seed & (2**64 - 1), n))
+
+
+def tv_init(nrows: int, K: int, seed: int, row0: int = 0) -> np.ndarray:
+    X = np.empty((nrows, K), dtype=np.float64)
+    lib().oracle_tv_init(row0, nrows, K, seed & (2**64 - 1), _p(X))
+    return X
+
+
+def jacobi(A, X0, omega: float, sweeps: int):
+    n, rp, ci, va = _csr(A)
+    X = _f64(X0).copy()
+    K = X.shape[1]
+    z = lib().oracle_jacobi(n, _p(rp), _p(ci), _p(va), K, float(omega), int(sweeps), _p(X))
+    return X, z
+
+
+def jacobi_rows(A, X, omega: float, rows):
+    n, rp, ci, va = _csr(A)
+    X = _f64(X)
+    rows = _rows(rows)
+    out = np.empty((len(rows), X.shape[1]))
+    lib().oracle_jacobi_rows(n, _p(rp), _p(ci), _p(va), X.shape[1], float(omega), _p(X),
+                             len(rows), _p(rows), _p(out))
+    return out
+
+
+def color_gs(A, X0, color, ncolors: int, sweeps: int):
+    n, rp, ci, va = _csr(A)
+    X = _f64(X0).copy()
+    col = np.ascontiguousarray(color, dtype=np.int32)
+    h = lib().oracle_color_gs(n, _p(rp), _p(ci), _p(va), X.shape[1], _p(col), int(ncolors),
+                              int(sweeps), _p(X))
+    return X, h
+
+
+def color_gs_rows(A, color, ncolors: int, Xold, Xnew, rows):
+    n, rp, ci, va = _csr(A)
+    Xold, Xnew = _f64(Xold), _f64(Xnew)
+    col = np.ascontiguousarray(color, dtype=np.int32)
+    rows = _rows(rows)
+    out = np.empty((len(rows), Xold.shape[1]))
+    lib().oracle_color_gs_rows(n, _p(rp), _p(ci), _p(va), Xold.shape[1], _p(col), int(ncolors),
+                               _p(Xold), _p(Xnew), len(rows), _p(rows), _p(out))
+    return out
+
+
+def packed_len(A, rows) -> int:
+    rp = np.asarray(A.row_ptr, dtype=np.int64)
+    if rows is None:
+        return int(rp[-1])
+    rows = np.asarray(rows, dtype=np.int64)
+    return int((rp[rows + 1] - rp[rows]).sum())
+
+
+def algdist(A, X, w=None, target: int = TARGET_PLAIN, rows=None, want_p: bool = False):
+    """mu (and p) per stored entry of the selected rows, packed in row order."""
+    n, rp, ci, va = _csr(A)
+    X = _f64(X)
+    w = None if w is None else _f64(w)
+    r = _rows(rows)
+    m = packed_len(A, rows)
+    mu = np.empty(m)
+    p = np.empty(m) if want_p else None
+    bad = lib().oracle_algdist(n, _p(rp), _p(ci), _p(va), X.shape[1], _p(X), _p(w), int(target),
+                               0 if r is None else len(r), _p(r), _p(mu), _p(p))
+    return (mu, p, bad) if want_p else mu
+
+
+def strength(A, mu, theta: float, fmask=None):
+    n, rp, ci, va = _csr(A)
+    mu = _f64(mu)
+    fm = None if fmask is None else np.ascontiguousarray(fmask, dtype=np.uint8)
+    strong = np.empty(len(ci), dtype=np.uint8)
+    ns = np.empty(n, dtype=np.int32)
+    lib().oracle_strength(n, _p(rp), _p(ci), _p(mu), float(theta), _p(fm), _p(strong), _p(ns))
+    return strong, ns
+
+
+def ls_interp(A, X, w, cf, mu, caliber: int, target: int = TARGET_PLAIN, rows=None):
+    n, rp, ci, va = _csr(A)
+    X = _f64(X)
+    w = None if w is None else _f64(w)
+    cf = np.ascontiguousarray(cf, dtype=np.uint8)
+    mu = _f64(mu)
+    r = _rows(rows)
+    m = n if r is None else len(r)
+    Pc = np.empty((m, caliber), dtype=np.int32)
+    Pv = np.empty((m, caliber))
+    ls = np.empty(m)
+    st = np.empty(m, dtype=np.int32)
+    lib().oracle_ls_interp(n, _p(rp), _p(ci), _p(va), X.shape[1], _p(X), _p(w), _p(cf), _p(mu),
+                           int(caliber), int(target), 0 if r is None else len(r), _p(r),
+                           _p(Pc), _p(Pv), _p(ls), _p(st))
+    return Pc, Pv, ls, st
+
+
+def ls_loss(A, X0, sweeps: int, omega: float, w, cf, caliber: int, val=None) -> float:
+    n, rp, ci, va = _csr(A)
+    if val is not None:
+        va = _f64(val)
+    X0 = _f64(X0)
+    w = None if w is None else _f64(w)
+    cf = np.ascontiguousarray(cf, dtype=np.uint8)
+    return float(lib().oracle_ls_loss(n, _p(rp), _p(ci), _p(va), X0.shape[1], _p(X0), int(sweeps),
+                                      float(omega), _p(w), _p(cf), int(caliber)))
+
+
+def ls_loss_grad(A, X0, sweeps: int, omega: float, w, cf, caliber: int):
+    n, rp, ci, va = _csr(A)
+    X0 = _f64(X0)
+    w = None if w is None else _f64(w)
+    cf = np.ascontiguousarray(cf, dtype=np.uint8)
+    g = np.empty(len(ci))
+    gw = C.c_double(0.0)
+    L = lib().oracle_ls_loss_grad(n, _p(rp), _p(ci), _p(va), X0.shape[1], _p(X0), int(sweeps),
+                                  float(omega), _p(w), _p(cf), int(caliber), _p(g), C.byref(gw))
+    return float(L), g, float(gw.value)

@@ -1,0 +1,605 @@
+/*
+ * oracle.c -- plain, slow FP64 reference of the algebraic-distance setup path.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product path may call, link or
+ * load this file: only the tests, the smoke check and the CPU-baseline leg of
+ * the benchmark do.  It shares no code, header, table or helper with the GPU
+ * library; the two are tied together only by the published definitions they
+ * both implement and by the seeded inputs the tests feed them.
+ *
+ * Every routine is the paper's definition written out in FP64 with plain
+ * loops, in the order the definition states it.  Paper references are to
+ * Brandt, Brannick, Kahl, Livshits, "An algebraic distances measure of AMG
+ * strength of connection" (arXiv:1106.5990).
+ *
+ * Conventions shared with the caller (Python wrapper in __init__.py):
+ *   CSR: rp[n+1], ci[nnz] (sorted per row, diagonal present), a[nnz] FP64.
+ *   Panels: row-major n x K, entry (i, k) at X[i*K + k].
+ *   Weights w[K] (NULL means all ones).
+ *   A row subset `rows` (NULL = every row) selects which rows are computed;
+ *   per-row outputs are then packed in the order of `rows`.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define TARGET_PLAIN 0
+#define TARGET_RESIDUAL 1
+
+/* ---------------------------------------------------------------------- */
+/* Test-vector start: splitmix64 (Steele, Lea and Flood, OOPSLA 2014).     */
+/* The generator's state advances by the golden-ratio increment; each      */
+/* output is the state pushed through its xor-shift-multiply finaliser.    */
+/* Entry (r, k) of the start panel is the (r*K + k + 1)-th output of the   */
+/* generator seeded with `seed`; its top 53 bits give u in [0, 1) and the  */
+/* entry is 2u - 1, uniform on [-1, 1).                                    */
+/* ---------------------------------------------------------------------- */
+static uint64_t splitmix64_next(uint64_t *state)
+{
+    uint64_t z;
+    *state += 0x9e3779b97f4a7c15ULL;
+    z = *state;
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ULL;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebULL;
+    return z ^ (z >> 31);
+}
+
+uint64_t oracle_splitmix64_nth(uint64_t seed, uint64_t n_outputs)
+{
+    /* the n-th output (n >= 1) of the generator seeded with `seed` */
+    uint64_t s = seed, z = 0, m;
+    for (m = 0; m < n_outputs; ++m) z = splitmix64_next(&s);
+    return z;
+}
+
+void oracle_tv_init(int64_t row0, int64_t nrows, int K, uint64_t seed, double *X)
+{
+    int64_t r;
+    int k;
+    for (r = 0; r < nrows; ++r)
+        for (k = 0; k < K; ++k) {
+            /* jump the state straight to just before output number c + 1 */
+            uint64_t c = (uint64_t)(row0 + r) * (uint64_t)K + (uint64_t)k;
+            uint64_t s = seed + c * 0x9e3779b97f4a7c15ULL;
+            uint64_t z = splitmix64_next(&s);
+            double u = (double)(z >> 11) * (1.0 / 9007199254740992.0); /* 2^-53 */
+            X[r * K + k] = 2.0 * u - 1.0;
+        }
+}
+
+/* ---------------------------------------------------------------------- */
+/* helpers                                                                 */
+/* ---------------------------------------------------------------------- */
+static double diag_of(const int *rp, const int *ci, const double *a, int i)
+{
+    int e;
+    for (e = rp[i]; e < rp[i + 1]; ++e)
+        if (ci[e] == i) return a[e];
+    return 0.0;
+}
+
+static double weight(const double *w, int k) { return w ? w[k] : 1.0; }
+
+/* (A x)_i for every column k of the panel */
+static void row_apply(const int *rp, const int *ci, const double *a, int K,
+                      const double *X, int i, double *y)
+{
+    int e, k;
+    for (k = 0; k < K; ++k) y[k] = 0.0;
+    for (e = rp[i]; e < rp[i + 1]; ++e)
+        for (k = 0; k < K; ++k) y[k] += a[e] * X[(int64_t)ci[e] * K + k];
+}
+
+/* ---------------------------------------------------------------------- */
+/* Relaxation of the homogeneous system A x = 0 (Sec. 3: test vectors are  */
+/* produced by relaxing Ax = 0 from distinct starts).                      */
+/* ---------------------------------------------------------------------- */
+
+/* Damped Jacobi, whole vector at once: x <- x - omega D^{-1} A x.
+ * A row with a zero diagonal is left unchanged.  Returns the number of
+ * zero-diagonal rows met (0 when all is well). */
+int oracle_jacobi(int n, const int *rp, const int *ci, const double *a, int K,
+                  double omega, int sweeps, double *X)
+{
+    double *nx = (double *)malloc(sizeof(double) * (size_t)n * K);
+    double *y = (double *)malloc(sizeof(double) * K);
+    int s, i, k, zero = 0;
+    for (s = 0; s < sweeps; ++s) {
+        for (i = 0; i < n; ++i) {
+            double d = diag_of(rp, ci, a, i);
+            if (d == 0.0) {
+                for (k = 0; k < K; ++k) nx[(int64_t)i * K + k] = X[(int64_t)i * K + k];
+                if (s == 0) ++zero;
+                continue;
+            }
+            row_apply(rp, ci, a, K, X, i, y);
+            for (k = 0; k < K; ++k)
+                nx[(int64_t)i * K + k] = X[(int64_t)i * K + k] - omega * y[k] / d;
+        }
+        memcpy(X, nx, sizeof(double) * (size_t)n * K);
+    }
+    free(nx);
+    free(y);
+    return zero;
+}
+
+/* One Jacobi sweep evaluated only on `rows`: out (packed) = x - omega D^-1 A x. */
+void oracle_jacobi_rows(int n, const int *rp, const int *ci, const double *a, int K,
+                        double omega, const double *X, int nrows, const int *rows,
+                        double *out)
+{
+    double *y = (double *)malloc(sizeof(double) * K);
+    int r, k;
+    (void)n;
+    for (r = 0; r < nrows; ++r) {
+        int i = rows[r];
+        double d = diag_of(rp, ci, a, i);
+        if (d == 0.0) {
+            for (k = 0; k < K; ++k) out[(int64_t)r * K + k] = X[(int64_t)i * K + k];
+            continue;
+        }
+        row_apply(rp, ci, a, K, X, i, y);
+        for (k = 0; k < K; ++k)
+            out[(int64_t)r * K + k] = X[(int64_t)i * K + k] - omega * y[k] / d;
+    }
+    free(y);
+}
+
+/* Colour-phase Gauss-Seidel (omega = 1).  Within one sweep the colours are
+ * visited in the order 0, 1, ..., ncolors-1; a row of colour c is replaced by
+ *     x_i - (A z)_i / a_ii,   z_j = new x_j if colour(j) < c, else old x_j,
+ * i.e. neighbours already updated in this sweep are read new and every other
+ * value (same colour, later colours, the row itself) is read as it was when
+ * the sweep began.  For a valid colouring this is Gauss-Seidel in colour
+ * order.  Rows whose colour is outside [0, ncolors) and rows with a zero
+ * diagonal are held fixed.  Returns the number of such rows. */
+int oracle_color_gs(int n, const int *rp, const int *ci, const double *a, int K,
+                    const int *color, int ncolors, int sweeps, double *X)
+{
+    double *nx = (double *)malloc(sizeof(double) * (size_t)n * K);
+    double *y = (double *)malloc(sizeof(double) * K);
+    int s, c, i, e, k, held = 0;
+    for (s = 0; s < sweeps; ++s) {
+        for (i = 0; i < n; ++i)
+            if (color[i] < 0 || color[i] >= ncolors || diag_of(rp, ci, a, i) == 0.0) {
+                for (k = 0; k < K; ++k) nx[(int64_t)i * K + k] = X[(int64_t)i * K + k];
+                if (s == 0) ++held;
+            }
+        for (c = 0; c < ncolors; ++c) {
+            for (i = 0; i < n; ++i) {
+                double d;
+                if (color[i] != c) continue;
+                d = diag_of(rp, ci, a, i);
+                if (d == 0.0) continue;
+                for (k = 0; k < K; ++k) y[k] = 0.0;
+                for (e = rp[i]; e < rp[i + 1]; ++e) {
+                    int j = ci[e];
+                    const double *z = (color[j] >= 0 && color[j] < c) ? nx : X;
+                    for (k = 0; k < K; ++k) y[k] += a[e] * z[(int64_t)j * K + k];
+                }
+                for (k = 0; k < K; ++k)
+                    nx[(int64_t)i * K + k] = X[(int64_t)i * K + k] - y[k] / d;
+            }
+        }
+        memcpy(X, nx, sizeof(double) * (size_t)n * K);
+    }
+    free(nx);
+    free(y);
+    return held;
+}
+
+/* The colour-phase rule evaluated on `rows` only, given the panel at the
+ * start of a sweep (Xold) and at its end (Xnew): out (packed) is what the
+ * sweep must produce for those rows. */
+void oracle_color_gs_rows(int n, const int *rp, const int *ci, const double *a, int K,
+                          const int *color, int ncolors, const double *Xold,
+                          const double *Xnew, int nrows, const int *rows, double *out)
+{
+    int r, e, k;
+    double *y = (double *)malloc(sizeof(double) * K);
+    (void)n;
+    for (r = 0; r < nrows; ++r) {
+        int i = rows[r], c = color[i];
+        double d = diag_of(rp, ci, a, i);
+        if (c < 0 || c >= ncolors || d == 0.0) {
+            for (k = 0; k < K; ++k) out[(int64_t)r * K + k] = Xold[(int64_t)i * K + k];
+            continue;
+        }
+        for (k = 0; k < K; ++k) y[k] = 0.0;
+        for (e = rp[i]; e < rp[i + 1]; ++e) {
+            int j = ci[e];
+            const double *z = (color[j] >= 0 && color[j] < c) ? Xnew : Xold;
+            for (k = 0; k < K; ++k) y[k] += a[e] * z[(int64_t)j * K + k];
+        }
+        for (k = 0; k < K; ++k)
+            out[(int64_t)r * K + k] = Xold[(int64_t)i * K + k] - y[k] / d;
+    }
+    free(y);
+}
+
+/* ---------------------------------------------------------------------- */
+/* Fit target of row i: v_i (plain LS functional, Sec. 3.1 eq:LSfuncrowi)  */
+/* or v_i - r_i / a_ii with r = A v (residual form, Sec. 3.1 eq:modls and  */
+/* Sec. 4.1 eq:measure).  Returns 1 if a residual target met a zero        */
+/* diagonal (the plain value is used then), else 0.                        */
+/* ---------------------------------------------------------------------- */
+static int fit_target(const int *rp, const int *ci, const double *a, int K,
+                      const double *X, int i, int target, double *t, double *scratch)
+{
+    int k;
+    for (k = 0; k < K; ++k) t[k] = X[(int64_t)i * K + k];
+    if (target == TARGET_RESIDUAL) {
+        double d = diag_of(rp, ci, a, i);
+        if (d == 0.0) return 1;
+        row_apply(rp, ci, a, K, X, i, scratch);
+        for (k = 0; k < K; ++k) t[k] = t[k] - scratch[k] / d;
+    }
+    return 0;
+}
+
+/* ---------------------------------------------------------------------- */
+/* Algebraic distance (Sec. 4.1, eq:measure).  For every stored entry      */
+/* (i, j) of the selected rows, the one-point least-squares problem        */
+/*     min_p  sum_k w_k (t_i^k - p x_j^k)^2                               */
+/* is solved by its normal equation p = <t, x_j>_w / <x_j, x_j>_w (p = 0   */
+/* when x_j vanishes), and mu_ij is the functional at that p, evaluated    */
+/* as written.  The paper's strength is r_ij = 1 / mu_ij.                  */
+/* mu (and p, if not NULL) are packed over the selected rows' entries.     */
+/* Returns the number of residual targets that met a zero diagonal.        */
+/* ---------------------------------------------------------------------- */
+int oracle_algdist(int n, const int *rp, const int *ci, const double *a, int K,
+                   const double *X, const double *w, int target, int nrows,
+                   const int *rows, double *mu, double *p)
+{
+    double *t = (double *)malloc(sizeof(double) * K);
+    double *sc = (double *)malloc(sizeof(double) * K);
+    int64_t out = 0;
+    int r, e, k, bad = 0;
+    int cnt = rows ? nrows : n;
+    for (r = 0; r < cnt; ++r) {
+        int i = rows ? rows[r] : r;
+        bad += fit_target(rp, ci, a, K, X, i, target, t, sc);
+        for (e = rp[i]; e < rp[i + 1]; ++e, ++out) {
+            const double *xj = X + (int64_t)ci[e] * K;
+            double sab = 0.0, sbb = 0.0, pij, m = 0.0;
+            for (k = 0; k < K; ++k) {
+                sab += weight(w, k) * t[k] * xj[k];
+                sbb += weight(w, k) * xj[k] * xj[k];
+            }
+            pij = (sbb > 0.0) ? sab / sbb : 0.0;
+            for (k = 0; k < K; ++k) {
+                double res = t[k] - pij * xj[k];
+                m += weight(w, k) * res * res;
+            }
+            mu[out] = m;
+            if (p) p[out] = pij;
+        }
+    }
+    free(t);
+    free(sc);
+    return bad;
+}
+
+/* ---------------------------------------------------------------------- */
+/* Strength graph (Sec. 4.2, eq:strength_graph): for i in F, the edge      */
+/* (i, j), j in F, j != i, is strong iff r_ij > theta * max_k r_ik over    */
+/* the row's F-neighbours k != i.  With r = 1/mu this is                   */
+/*     m_i > theta * mu_ij,   m_i = min_k mu_ik,                           */
+/* and when m_i = 0 (an infinite strength) exactly the zero-distance edges */
+/* are strong.  fmask[i] != 0 marks F (NULL: every row is in F).  The      */
+/* comparison is made in FP64.                                             */
+/* ---------------------------------------------------------------------- */
+void oracle_strength(int n, const int *rp, const int *ci, const double *mu, double theta,
+                     const unsigned char *fmask, unsigned char *strong, int *nstrong)
+{
+    int i, e;
+    for (i = 0; i < n; ++i) {
+        double m = INFINITY;
+        int cnt = 0;
+        int in_f = fmask ? (fmask[i] != 0) : 1;
+        for (e = rp[i]; e < rp[i + 1]; ++e) {
+            int j = ci[e];
+            if (!in_f || j == i || (fmask && !fmask[j])) continue;
+            if (mu[e] < m) m = mu[e];
+        }
+        for (e = rp[i]; e < rp[i + 1]; ++e) {
+            int j = ci[e], s = 0;
+            if (in_f && j != i && (!fmask || fmask[j])) {
+                if (m > 0.0) s = (theta * mu[e] < m);
+                else s = (mu[e] == 0.0);
+            }
+            strong[e] = (unsigned char)s;
+            cnt += s;
+        }
+        if (nstrong) nstrong[i] = cnt;
+    }
+}
+
+/* ---------------------------------------------------------------------- */
+/* Least-squares interpolation (Sec. 3.1 eq:LSfuncrowi / eq:modls) on a    */
+/* set C_i chosen by the one-sided distances (Sec. 4.3, final remark: a    */
+/* systematic scan guided by the one-point measure): C_i is the caliber    */
+/* C-neighbours j != i with the smallest mu_ij (ties: lower column).       */
+/*                                                                         */
+/* The weighted problem min_p sum_k w_k (t^k - sum_j p_j x_j^k)^2 is       */
+/* solved by Householder QR of the sqrt(w)-scaled K x |C_i| matrix, the    */
+/* columns taken in increasing-mu order.  A column whose part orthogonal   */
+/* to the columns already kept has squared norm <= 1e-12 times its own     */
+/* squared norm is dropped (status 2).  The uniqueness remark of Sec. 3.1  */
+/* (K >= caliber and spanning vectors) is what makes the kept columns      */
+/* well posed.  ls_val is the functional at the minimiser, evaluated by    */
+/* its definition.                                                         */
+/*                                                                         */
+/* Output per row i (row-major n x caliber): P_col (fine column index,     */
+/* -1 padded, in increasing-mu order), P_val, ls_val, status:              */
+/*   0 ok, 1 F row without C-neighbour, 2 column(s) dropped, 3 residual    */
+/*   target with zero diagonal.  A C row interpolates itself with weight 1.*/
+/* ---------------------------------------------------------------------- */
+#define ORACLE_MAX_CAL 16
+
+static int is_candidate(const int *ci, const unsigned char *cf, const double *mu, int i, int e)
+{
+    int j = ci[e];
+    return j != i && cf[j] && !isnan(mu[e]);
+}
+
+void oracle_ls_interp(int n, const int *rp, const int *ci, const double *a, int K,
+                      const double *X, const double *w, const unsigned char *cf,
+                      const double *mu, int caliber, int target, int nrows, const int *rows,
+                      int *P_col, double *P_val, double *ls_val, int *status)
+{
+    int cnt = rows ? nrows : n;
+    int r, k, s, e, jj;
+    double *t = (double *)malloc(sizeof(double) * K);
+    double *sc = (double *)malloc(sizeof(double) * K);
+    double *M = (double *)malloc(sizeof(double) * K * ORACLE_MAX_CAL); /* column-major */
+    double *b = (double *)malloc(sizeof(double) * K);
+    double *v = (double *)malloc(sizeof(double) * K);
+    (void)n;
+    for (r = 0; r < cnt; ++r) {
+        int i = rows ? rows[r] : r;
+        int *pc = P_col + (int64_t)r * caliber;
+        double *pv = P_val + (int64_t)r * caliber;
+        int sel_e[ORACLE_MAX_CAL];
+        int nsel = 0, st = 0, kept = 0;
+        int kept_col[ORACLE_MAX_CAL];
+        double R[ORACLE_MAX_CAL][ORACLE_MAX_CAL];
+        double coef[ORACLE_MAX_CAL];
+        double val;
+
+        for (s = 0; s < caliber; ++s) { pc[s] = -1; pv[s] = 0.0; }
+        if (cf[i]) { /* a C point interpolates itself */
+            pc[0] = i;
+            pv[0] = 1.0;
+            ls_val[r] = 0.0;
+            status[r] = 0;
+            continue;
+        }
+        if (fit_target(rp, ci, a, K, X, i, target, t, sc)) st = 3;
+
+        /* C_i: repeatedly take the unselected candidate of least (mu, column) */
+        for (s = 0; s < caliber; ++s) {
+            int best = -1;
+            for (e = rp[i]; e < rp[i + 1]; ++e) {
+                int taken = 0, q;
+                if (!is_candidate(ci, cf, mu, i, e)) continue;
+                for (q = 0; q < nsel; ++q) taken |= (sel_e[q] == e);
+                if (taken) continue;
+                if (best < 0 || mu[e] < mu[best] || (mu[e] == mu[best] && ci[e] < ci[best]))
+                    best = e;
+            }
+            if (best < 0) break;
+            sel_e[nsel++] = best;
+        }
+        if (nsel == 0) {
+            double f = 0.0;
+            for (k = 0; k < K; ++k) f += weight(w, k) * t[k] * t[k];
+            ls_val[r] = f;
+            status[r] = st ? st : 1;
+            continue;
+        }
+
+        /* scaled system: column q is sqrt(w) .* x_{c_q}, right side sqrt(w) .* t */
+        for (s = 0; s < nsel; ++s)
+            for (k = 0; k < K; ++k)
+                M[s * K + k] = sqrt(weight(w, k)) * X[(int64_t)ci[sel_e[s]] * K + k];
+        for (k = 0; k < K; ++k) b[k] = sqrt(weight(w, k)) * t[k];
+
+        /* Householder QR with the column-drop rule */
+        for (s = 0; s < nsel; ++s) {
+            double *col = M + s * K;
+            double full = 0.0, tail = 0.0, alpha, vnorm2, dot;
+            int q;
+            for (k = 0; k < K; ++k) full += col[k] * col[k];
+            for (k = kept; k < K; ++k) tail += col[k] * col[k];
+            if (kept >= K || tail <= 1e-12 * full) { /* (numerically) dependent column */
+                st = st ? st : 2;
+                continue;
+            }
+            /* reflector H = I - 2 v v^T / (v^T v) mapping col[kept:] to alpha e_kept */
+            alpha = (col[kept] > 0.0) ? -sqrt(tail) : sqrt(tail);
+            for (k = 0; k < K; ++k) v[k] = 0.0;
+            for (k = kept; k < K; ++k) v[k] = col[k];
+            v[kept] -= alpha;
+            vnorm2 = 0.0;
+            for (k = kept; k < K; ++k) vnorm2 += v[k] * v[k];
+            /* apply to this and every later column, and to b */
+            for (q = s; q < nsel; ++q) {
+                double *cq = M + q * K;
+                dot = 0.0;
+                for (k = kept; k < K; ++k) dot += v[k] * cq[k];
+                for (k = kept; k < K; ++k) cq[k] -= 2.0 * dot / vnorm2 * v[k];
+            }
+            dot = 0.0;
+            for (k = kept; k < K; ++k) dot += v[k] * b[k];
+            for (k = kept; k < K; ++k) b[k] -= 2.0 * dot / vnorm2 * v[k];
+            /* row `kept` of R holds this column's entries for the kept columns */
+            for (q = 0; q <= kept; ++q) R[q][kept] = col[q];
+            kept_col[kept] = s;
+            ++kept;
+            /* columns already dropped are never revisited; later columns now
+               carry their rotated entries in M and are read when kept */
+        }
+        /* back substitution R coef = Q^T b (first `kept` entries of b) */
+        for (jj = kept - 1; jj >= 0; --jj) {
+            double acc = b[jj];
+            int q;
+            for (q = jj + 1; q < kept; ++q) acc -= R[jj][q] * coef[q];
+            coef[jj] = acc / R[jj][jj];
+        }
+        /* LS functional at the minimiser, by its definition */
+        val = 0.0;
+        for (k = 0; k < K; ++k) {
+            double res = t[k];
+            for (s = 0; s < kept; ++s)
+                res -= coef[s] * X[(int64_t)ci[sel_e[kept_col[s]]] * K + k];
+            val += weight(w, k) * res * res;
+        }
+        for (s = 0; s < kept; ++s) {
+            pc[s] = ci[sel_e[kept_col[s]]];
+            pv[s] = coef[s];
+        }
+        ls_val[r] = val;
+        status[r] = st;
+    }
+    free(t);
+    free(sc);
+    free(M);
+    free(b);
+    free(v);
+}
+
+/* ---------------------------------------------------------------------- */
+/* LS interpolation loss and its gradient.                                 */
+/*                                                                         */
+/* x^0 = X0, x^{s+1} = x^s - omega D^{-1} A x^s (s < sweeps), and          */
+/*     L = sum_{i in F} sum_k w_k (x_i^k - sum_j p_ij x_j^k)^2             */
+/* with the plain target and p the LS rows fitted to x^sweeps (C_i chosen  */
+/* by the distances of x^sweeps, as oracle_ls_interp does).  Because p     */
+/* minimises each row's functional, dL/dx^S is the partial derivative at   */
+/* fixed p; it is then carried back through the sweeps by the chain rule:  */
+/*     y = D^{-1} g,  g <- g - omega A^T y,                                */
+/*     dL/domega -= <y, A x^s>,                                            */
+/*     dL/da_ij  -= omega <y_i, x_j^s>, and for j = i also                 */
+/*     dL/da_ii  += omega <y_i, (A x^s)_i> / a_ii.                         */
+/* Returns L.                                                              */
+/* ---------------------------------------------------------------------- */
+static void ls_rows_for(int n, const int *rp, const int *ci, const double *a, int K,
+                        const double *X, const double *w, const unsigned char *cf, int caliber,
+                        int *Pc, double *Pv, double *ls, int *st)
+{
+    int64_t nnz = rp[n];
+    double *mu = (double *)malloc(sizeof(double) * (size_t)(nnz > 0 ? nnz : 1));
+    oracle_algdist(n, rp, ci, a, K, X, w, TARGET_PLAIN, 0, NULL, mu, NULL);
+    oracle_ls_interp(n, rp, ci, a, K, X, w, cf, mu, caliber, TARGET_PLAIN, 0, NULL, Pc, Pv, ls, st);
+    free(mu);
+}
+
+double oracle_ls_loss(int n, const int *rp, const int *ci, const double *a, int K,
+                      const double *X0, int sweeps, double omega, const double *w,
+                      const unsigned char *cf, int caliber)
+{
+    size_t nk = (size_t)n * K;
+    double *X = (double *)malloc(sizeof(double) * nk);
+    int *Pc = (int *)malloc(sizeof(int) * (size_t)n * caliber);
+    double *Pv = (double *)malloc(sizeof(double) * (size_t)n * caliber);
+    double *ls = (double *)malloc(sizeof(double) * n);
+    int *st = (int *)malloc(sizeof(int) * n);
+    double L = 0.0;
+    int i;
+    memcpy(X, X0, sizeof(double) * nk);
+    oracle_jacobi(n, rp, ci, a, K, omega, sweeps, X);
+    ls_rows_for(n, rp, ci, a, K, X, w, cf, caliber, Pc, Pv, ls, st);
+    for (i = 0; i < n; ++i)
+        if (!cf[i]) L += ls[i];
+    free(X); free(Pc); free(Pv); free(ls); free(st);
+    return L;
+}
+
+double oracle_ls_loss_grad(int n, const int *rp, const int *ci, const double *a, int K,
+                           const double *X0, int sweeps, double omega, const double *w,
+                           const unsigned char *cf, int caliber, double *grad_val,
+                           double *grad_omega)
+{
+    size_t nk = (size_t)n * K;
+    int64_t nnz = rp[n];
+    double **it = (double **)malloc(sizeof(double *) * (sweeps + 1));
+    double *g = (double *)malloc(sizeof(double) * nk);
+    double *gn = (double *)malloc(sizeof(double) * nk);
+    double *yv = (double *)malloc(sizeof(double) * nk);
+    double *z = (double *)malloc(sizeof(double) * K);
+    int *Pc = (int *)malloc(sizeof(int) * (size_t)n * caliber);
+    double *Pv = (double *)malloc(sizeof(double) * (size_t)n * caliber);
+    double *ls = (double *)malloc(sizeof(double) * n);
+    int *st = (int *)malloc(sizeof(int) * n);
+    double L = 0.0, gw = 0.0;
+    int s, i, k, e, q;
+    int64_t ee;
+
+    /* forward, keeping every iterate */
+    for (s = 0; s <= sweeps; ++s) it[s] = (double *)malloc(sizeof(double) * nk);
+    memcpy(it[0], X0, sizeof(double) * nk);
+    for (s = 0; s < sweeps; ++s) {
+        memcpy(it[s + 1], it[s], sizeof(double) * nk);
+        oracle_jacobi(n, rp, ci, a, K, omega, 1, it[s + 1]);
+    }
+    ls_rows_for(n, rp, ci, a, K, it[sweeps], w, cf, caliber, Pc, Pv, ls, st);
+
+    /* dL/dx^S at fixed p */
+    for (ee = 0; ee < (int64_t)nk; ++ee) g[ee] = 0.0;
+    for (i = 0; i < n; ++i) {
+        const double *x = it[sweeps];
+        if (cf[i]) continue;
+        L += ls[i];
+        for (k = 0; k < K; ++k) {
+            double res = x[(int64_t)i * K + k];
+            for (q = 0; q < caliber; ++q)
+                if (Pc[(int64_t)i * caliber + q] >= 0)
+                    res -= Pv[(int64_t)i * caliber + q] * x[(int64_t)Pc[(int64_t)i * caliber + q] * K + k];
+            g[(int64_t)i * K + k] += 2.0 * weight(w, k) * res;
+            for (q = 0; q < caliber; ++q) {
+                int j = Pc[(int64_t)i * caliber + q];
+                if (j >= 0)
+                    g[(int64_t)j * K + k] -= 2.0 * weight(w, k) * res * Pv[(int64_t)i * caliber + q];
+            }
+        }
+    }
+
+    for (e = 0; e < nnz; ++e) grad_val[e] = 0.0;
+    /* backward through the sweeps */
+    for (s = sweeps - 1; s >= 0; --s) {
+        const double *x = it[s];
+        for (i = 0; i < n; ++i) {
+            double d = diag_of(rp, ci, a, i);
+            for (k = 0; k < K; ++k) yv[(int64_t)i * K + k] = (d != 0.0) ? g[(int64_t)i * K + k] / d : 0.0;
+        }
+        memcpy(gn, g, sizeof(double) * nk);
+        for (i = 0; i < n; ++i) {
+            double d = diag_of(rp, ci, a, i);
+            if (d == 0.0) continue;
+            row_apply(rp, ci, a, K, x, i, z);
+            for (k = 0; k < K; ++k) gw -= yv[(int64_t)i * K + k] * z[k];
+            for (e = rp[i]; e < rp[i + 1]; ++e) {
+                int j = ci[e];
+                double acc = 0.0;
+                for (k = 0; k < K; ++k) acc += yv[(int64_t)i * K + k] * x[(int64_t)j * K + k];
+                grad_val[e] -= omega * acc;
+                if (j == i) {
+                    double acc2 = 0.0;
+                    for (k = 0; k < K; ++k) acc2 += yv[(int64_t)i * K + k] * z[k];
+                    grad_val[e] += omega * acc2 / d;
+                }
+                /* (A^T y)_j gets a_ij y_i */
+                for (k = 0; k < K; ++k) gn[(int64_t)j * K + k] -= omega * a[e] * yv[(int64_t)i * K + k];
+            }
+        }
+        memcpy(g, gn, sizeof(double) * nk);
+    }
+    *grad_omega = gw;
+
+    for (s = 0; s <= sweeps; ++s) free(it[s]);
+    free(it); free(g); free(gn); free(yv); free(z);
+    free(Pc); free(Pv); free(ls); free(st);
+    return L;
+}
