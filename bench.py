@@ -1,0 +1,271 @@
+#!/usr/bin/env python3
+"""Throughput of the algebraic-distance AMG setup hot path on one MI355X.
+
+One step = the whole path over one synthetic operator resident in HBM:
+  test-vector start + relaxation (setup_testvectors)
+  -> per-edge distances with the fused strength graph (algebraic_distance)
+  -> LS interpolation rows with their F-row sum (ls_interp).
+The metric is edges/s: off-diagonal CSR entries (the directed pairs on which
+distances are computed) per second of step time.
+
+Default workload: the rotated anisotropic diffusion operator (alpha = pi/6,
+eps = 1e-3) with the central 9-point stencil on a 2048 x 2048 grid, K = 16
+test vectors, 5 red-black colour-phase Gauss-Seidel sweeps, theta = 0.25,
+caliber 4 from the red C/F split; FP32 relaxation and distances with FP64
+interpolation solves.  The plain FP64 path on the same workload is timed
+beside it, and the CPU oracle on a bounded sample of the same workload on the
+host cores.  Prints ONE JSON line.
+
+  python bench.py [--steps K] [--warmup W] [--workload aniso2d|varcoef3d|laplace2d]
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="aniso2d", choices=["aniso2d", "varcoef3d", "laplace2d"])
+    ap.add_argument("--size", type=int, default=None, help="grid side override (tests only)")
+    ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 leg")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample", type=int, default=None, help="grid side of the oracle sample")
+    ap.add_argument("--graph", action="store_true", help="replay the step as a captured HIP graph")
+    return ap.parse_args()
+
+
+WORKLOAD_INDEX = {"laplace2d": 1, "aniso2d": 2, "varcoef3d": 3}
+
+
+def build_inputs(wl, dtype, torch, ad):
+    A = ad.Csr.from_host(wl.A, dtype=dtype)
+    dev = A.device
+    n, nnz, K = wl.A.n, wl.A.nnz, wl.K
+    buf = {
+        "A": A,
+        "X": torch.empty((n, K), dtype=dtype, device=dev),
+        "mu": torch.empty(nnz, dtype=dtype, device=dev),
+        "strong": torch.empty(nnz, dtype=torch.uint8, device=dev),
+        "ns": torch.empty(n, dtype=torch.int32, device=dev),
+        "cf": torch.as_tensor(wl.cf, device=dev),
+        "Pc": torch.empty((n, wl.caliber), dtype=torch.int32, device=dev),
+        "Pv": torch.empty((n, wl.caliber), dtype=torch.float64, device=dev),
+        "ls": torch.empty(n, dtype=torch.float64, device=dev),
+        "st": torch.empty(n, dtype=torch.int32, device=dev),
+        "lsum": torch.empty(1, dtype=torch.float64, device=dev),
+        "color": None if wl.color is None else torch.as_tensor(wl.color, device=dev),
+    }
+    return buf
+
+
+def make_step(wl, b, ad):
+    def step():
+        ad.setup_testvectors(b["A"], wl.K, seed=wl.tv_seed, relax=wl.relax, sweeps=wl.sweeps,
+                             omega=wl.omega, color=b["color"], ncolors=wl.ncolors, out=b["X"])
+        ad.algebraic_distance(b["A"], b["X"], mu=b["mu"], fuse=True, theta=wl.theta,
+                              strong=b["strong"], nstrong=b["ns"])
+        ad.ls_interp(b["A"], b["X"], b["cf"], b["mu"], wl.caliber, P_col=b["Pc"], P_val=b["Pv"],
+                     ls_val=b["ls"], row_status=b["st"], ls_sum=b["lsum"], want_sum=True)
+    return step
+
+
+def timed(step, steps, warmup, torch, ad, graph=False):
+    """Run warmup steps, then time `steps` steps bracketed by synchronisation;
+    per-kernel HIP events (the library's timing record) run over the same
+    timed region."""
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    g = None
+    if graph:
+        s = torch.cuda.Stream()
+        s.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(s):
+            step()
+        torch.cuda.current_stream().wait_stream(s)
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            step()
+        g.replay()
+        torch.cuda.synchronize()
+    run = g.replay if g is not None else step
+    ad.timing(not graph)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e0.record()
+    for _ in range(steps):
+        run()
+    e1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kernels = ad.timing_report() if not graph else {}
+    ad.timing(False)
+    return e0.elapsed_time(e1) / steps, wall / steps * 1e3, kernels
+
+
+def kernel_bytes(wl, s):
+    """Algorithmic HBM bytes per launch of each kernel (s = panel bytes per
+    value).  Every operand is read or written once; neighbour re-reads of the
+    panel are taken to hit in cache."""
+    A = wl.A
+    n, nnz, K = A.n, A.nnz, wl.K
+    rp = A.row_ptr.astype(np.int64)
+    deg = np.diff(rp)
+    panel = n * K * s
+    out = {"tv_init": panel}
+    out["jacobi"] = (n + 1) * 4 + nnz * (4 + s) + 2 * panel
+    if wl.color is not None:
+        per = []
+        for c in range(wl.ncolors):
+            rows = wl.color == c
+            nc_, nnzc = int(rows.sum()), int(deg[rows].sum())
+            per.append(nc_ * (4 + 8) + nnzc * (4 + s) + panel + nc_ * K * s + (n * 4 if c > 0 else 0))
+        out["gs_phase"] = float(np.mean(per))
+        out["color_partition"] = n * 4 * 3
+    out["algdist"] = (n + 1) * 4 + nnz * 4 + panel + nnz * s + nnz + n * 4
+    F = wl.cf == 0
+    nnzF = int(deg[F].sum())
+    out["ls_interp"] = (n + (n + 1) * 4 + nnzF * (4 + s + 1) + panel
+                        + n * wl.caliber * (4 + 8) + n * (8 + 4))
+    out["strength"] = (n + 1) * 4 + nnz * (4 + s + 1) + n * 4
+    return out
+
+
+def step_bytes(wl, s, kb):
+    sweeps = wl.sweeps
+    b = kb["tv_init"] + kb["algdist"] + kb["ls_interp"]
+    if wl.relax == "gs":
+        b += kb["color_partition"] + sweeps * wl.ncolors * kb["gs_phase"]
+    else:
+        b += sweeps * kb["jacobi"]
+    return b
+
+
+def cpu_baseline(idx, side):
+    """The oracle, as it stands, on a bounded sample of the same workload:
+    the same operator family and parameters on a smaller grid."""
+    import oracle
+    from paper_1106_5990_amd import workloads as W
+    wl = W.workload(idx, "f64", size=side)
+    A = wl.A
+    t0 = time.perf_counter()
+    X0 = oracle.tv_init(A.n, wl.K, wl.tv_seed)
+    if wl.relax == "gs":
+        X, _ = oracle.color_gs(A, X0, wl.color, wl.ncolors, wl.sweeps)
+    else:
+        X, _ = oracle.jacobi(A, X0, wl.omega, wl.sweeps)
+    mu = oracle.algdist(A, X)
+    oracle.strength(A, mu, wl.theta)
+    oracle.ls_interp(A, X, None, wl.cf, mu, wl.caliber)
+    dt = time.perf_counter() - t0
+    return {"value": A.n_edges / dt, "unit": "edges/s", "cores": 1, "kind": "oracle",
+            "sample": "%s (%d rows, %d edges), whole path once, single-threaded C oracle, %.1f s"
+                      % (wl.name, A.n, A.n_edges, dt)}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(the sharding design is described in DESIGN.md); got --gpus %d" % args.gpus,
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_1106_5990_amd import algdist as ad
+    from paper_1106_5990_amd import workloads as W
+
+    idx = WORKLOAD_INDEX[args.workload]
+    print("[bench] building %s" % args.workload, file=sys.stderr, flush=True)
+    wl = W.workload(idx, "f32", size=args.size)
+    E = wl.A.n_edges
+
+    res = {}
+    for tag, dtype, steps in (("f32", torch.float32, args.steps),
+                              ("f64", torch.float64, max(3, args.steps // 2))):
+        if tag == "f64" and args.no_fp64:
+            continue
+        b = build_inputs(wl, dtype, torch, ad)
+        step = make_step(wl, b, ad)
+        print("[bench] timing %s leg: %d warmup + %d steps" % (tag, args.warmup, steps),
+              file=sys.stderr, flush=True)
+        ms, wall_ms, kern = timed(step, steps, args.warmup, torch, ad, graph=args.graph)
+        bits = ad.status(clear=True)
+        s = 4 if dtype == torch.float32 else 8
+        kb = kernel_bytes(wl, s)
+        res[tag] = {"ms": ms, "wall_ms": wall_ms, "kernels": kern, "kb": kb,
+                    "step_bytes": step_bytes(wl, s, kb), "status": bits, "steps": steps}
+        del b, step
+        torch.cuda.empty_cache()
+
+    main_leg = res["f32"]
+    kern = main_leg["kernels"]
+    ms = main_leg["ms"]
+    value = E / (ms * 1e-3)
+    roof = None
+    kstats = {}
+    for lab, (cnt, tot) in kern.items():
+        avg = tot / cnt
+        by = main_leg["kb"].get(lab)
+        kstats[lab] = {"launches_per_step": cnt / main_leg["steps"], "avg_ms": round(avg, 5),
+                       "GB/s": None if by is None else round(by / (avg * 1e-3) / 1e9, 1)}
+    if kern:
+        dom = max(kern, key=lambda k: kern[k][1])
+        cnt, tot = kern[dom]
+        avg = tot / cnt
+        ach = main_leg["kb"][dom] / (avg * 1e-3) / 1e9
+        roof = {"bound": "hbm", "kernel": dom, "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
+                "algorithmic_bytes_per_launch": int(main_leg["kb"][dom]),
+                "avg_launch_ms": round(avg, 5)}
+    out = {
+        "metric": "edges/s (relax+algdist+ls_interp)",
+        "value": round(value, 1),
+        "unit": "edges/s",
+        "n_gpus": 1,
+        "steps": main_leg["steps"],
+        "warmup": args.warmup,
+        "ms_per_step": round(ms, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": wl.name, "n": wl.A.n, "nnz": wl.A.nnz, "edges": E, "K": wl.K,
+                   "relax": "%d %s sweeps" % (wl.sweeps, "red-black colour-phase GS" if wl.relax == "gs"
+                                              else "Jacobi omega=%.3g" % wl.omega),
+                   "theta": wl.theta, "caliber": wl.caliber,
+                   "precision": "FP32 relaxation and distances, FP64 interpolation solves",
+                   "graph": bool(args.graph)},
+        "roofline": roof,
+        "step_hbm_frac": round(main_leg["step_bytes"] / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+        "kernels": kstats,
+        "wall_ms_per_step": round(main_leg["wall_ms"], 4),
+        "device_status_bits": main_leg["status"],
+    }
+    if "f64" in res:
+        r = res["f64"]
+        out["fp64_plain"] = {"value": round(E / (r["ms"] * 1e-3), 1), "ms_per_step": round(r["ms"], 4),
+                             "step_hbm_frac": round(r["step_bytes"] / (r["ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                             "speedup_f32_over_f64": round(r["ms"] / ms, 3)}
+    if not args.no_cpu_baseline:
+        side = args.cpu_sample or args.size or {1: 32, 2: 2048, 3: 160}[idx]
+        print("[bench] cpu baseline: oracle on a side-%d sample" % side, file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(idx, side)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,235 @@
+/*
+ * algdist.h -- C ABI of libalgdist.so, the MI355X (gfx950) implementation of
+ * the data-parallel hot path of algebraic-distance AMG setup:
+ *
+ *   1. relax K test vectors on A x = 0            (setup_testvectors)
+ *   2. per-edge least-squares algebraic distance  (algebraic_distance)
+ *   3. strength graph from the distances          (strength_graph)
+ *   4. least-squares interpolation rows           (ls_interp)
+ *
+ * after Brandt, Brannick, Kahl, Livshits, "An algebraic distances measure of
+ * AMG strength of connection" (arXiv:1106.5990).  Section and equation names
+ * below are that paper's.
+ *
+ * Conventions for every call
+ * --------------------------
+ * - All array arguments are DEVICE pointers unless marked "host".  The caller
+ *   allocates and owns every buffer; the library never frees caller memory.
+ *   The handle owns only its internal workspace (grown on demand, freed by
+ *   algdist_destroy).
+ * - Every compute call is asynchronous on `stream` (a hipStream_t passed as
+ *   void*; NULL = the legacy default stream) and returns after enqueueing.
+ * - Return value: an ad_status.  Argument errors are detected on the host,
+ *   before anything is enqueued, and leave all outputs untouched; the
+ *   message is available from algdist_last_error().  Conditions that can only
+ *   be seen on the device (a zero diagonal, a bad colour, a non-finite
+ *   distance, a malformed CSR in csr_validate) set bits of a sticky device
+ *   status word read by algdist_status().
+ * - CSR: int32 row_ptr[n+1] (row_ptr[0] = 0, nondecreasing), int32 col[nnz]
+ *   sorted ascending within each row with the diagonal present, values of
+ *   the type named by `dtype`.  Panels (test vectors) are row-major n x K:
+ *   entry (i, k) at X[i*K + k], K contiguous; the panel type is the CSR's
+ *   dtype.  Device pointers to panels must be 16-byte aligned.
+ * - K must be one of 2, 4, 8, 16, 32, 64.
+ * - Calls on one handle must not overlap in time across host threads.
+ */
+#ifndef ALGDIST_H
+#define ALGDIST_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define ALGDIST_VERSION 1
+
+typedef enum { AD_F32 = 0, AD_F64 = 1 } ad_dtype;
+typedef enum { AD_JACOBI = 0, AD_MULTICOLOR_GS = 1 } ad_relax;
+typedef enum { AD_TARGET_PLAIN = 0, AD_TARGET_RESIDUAL = 1 } ad_target;
+
+typedef enum {
+    AD_OK = 0,
+    AD_EINVAL = 1,      /* bad argument (null pointer, size, alignment, K) */
+    AD_EDTYPE = 2,      /* unsupported or mismatched dtype */
+    AD_ECALIBER = 3,    /* caliber out of range or K < caliber */
+    AD_ESTRUCT = 4,     /* inconsistent sizes (nnz, n) */
+    AD_EDEVICE = 5,     /* a HIP runtime call failed */
+    AD_ENOMEM = 6,      /* workspace allocation failed */
+    AD_EUNSUPPORTED = 7 /* valid request the library does not implement */
+} ad_status;
+
+/* sticky device status bits (algdist_status) */
+#define AD_STAT_ZERO_DIAG   0x01u /* a row with a zero diagonal was relaxed or used as a residual target */
+#define AD_STAT_BAD_COLOR   0x02u /* a colour outside [0, ncolors) was met; such rows were held fixed */
+#define AD_STAT_NONFINITE   0x04u /* a distance came out NaN or infinite */
+#define AD_STAT_CSR_ROWPTR  0x08u /* csr_validate: row_ptr not nondecreasing or row_ptr[n] != nnz */
+#define AD_STAT_CSR_COLS    0x10u /* csr_validate: column out of range or not strictly increasing */
+#define AD_STAT_CSR_NODIAG  0x20u /* csr_validate: a row has no diagonal entry */
+#define AD_STAT_TIMEOUT     0x40u /* batched path: a bounded inter-workgroup wait gave up */
+
+typedef struct ad_handle_s *ad_handle;
+
+/* A square sparse matrix in CSR form (device arrays). */
+typedef struct {
+    int32_t n;              /* rows (= columns), >= 0 */
+    int64_t nnz;            /* stored entries, row_ptr[n]; <= INT32_MAX */
+    const int32_t *row_ptr; /* [n+1] */
+    const int32_t *col;     /* [nnz], sorted per row, diagonal present */
+    const void *val;        /* [nnz] float or double, per dtype */
+    int32_t dtype;          /* ad_dtype */
+} ad_csr;
+
+/* ------------------------------------------------------------------ */
+/* handle                                                              */
+/* ------------------------------------------------------------------ */
+
+/* Create a handle bound to HIP device `device`.  *h receives the handle. */
+int algdist_create(ad_handle *h, int device);
+
+/* Wait for the device, then free the handle and its workspace. */
+int algdist_destroy(ad_handle h);
+
+/* Synchronise the handle's device and return the sticky status bits in
+ * *bits (host).  clear != 0 resets them to zero afterwards. */
+int algdist_status(ad_handle h, uint32_t *bits, int clear);
+
+/* Message describing the last host-side error on this handle ("" if none).
+ * The string stays valid until the next call on the handle. */
+const char *algdist_last_error(ad_handle h);
+
+int algdist_version(void);
+
+/* Per-kernel timing for measurement.  enable != 0 starts a fresh record:
+ * from then on every launch the handle makes is bracketed by two HIP events
+ * on its own stream; enable == 0 stops recording.  Kernels are labelled
+ * tv_init, color_partition, jacobi, gs_phase, algdist, strength and
+ * ls_interp (the last includes its tiny block-sum kernel when ls_sum is
+ * requested). */
+int algdist_timing(ad_handle h, int enable);
+
+/* Synchronise the device and return the record as text, one line per label:
+ * "<label> <launches> <total milliseconds>".  The string stays valid until
+ * the next call on the handle. */
+const char *algdist_timing_report(ad_handle h);
+
+/* Check the CSR invariants listed above on the device; violations set
+ * AD_STAT_CSR_* bits.  Not needed on the hot path (no other call reads
+ * more than it is given, but their results are defined only for valid
+ * CSRs). */
+int csr_validate(ad_handle h, const ad_csr *A, void *stream);
+
+/* ------------------------------------------------------------------ */
+/* 1. test vectors                                                     */
+/* ------------------------------------------------------------------ */
+
+/* Produce K test vectors by relaxing the homogeneous system A x = 0 from
+ * K starts (Sec. 3: "relaxing the homogeneous system Ax = 0 with a
+ * different starting vector"; Sec. 5.2 uses Gauss-Seidel).
+ *
+ * Start: X0 (device, n x K, may be NULL).  When NULL, entry (i, k) is
+ * 2u - 1 with u the top 53 bits of output number i*K + k + 1 of splitmix64
+ * seeded with `seed`, times 2^-53 (uniform on [-1, 1); rounded to FP32 for
+ * an FP32 panel).
+ *
+ * relax = AD_JACOBI:        x <- x - omega D^{-1} A x, whole vector per sweep.
+ * relax = AD_MULTICOLOR_GS: omega is ignored (1).  Per sweep, colours
+ *   c = 0..ncolors-1 in turn; a row of colour c becomes x_i - (A z)_i / a_ii
+ *   where z_j is the value of this sweep for neighbours of a smaller colour
+ *   and the value at the start of the sweep otherwise (same colour included).
+ *   This is Gauss-Seidel in colour order for a valid colouring and a
+ *   deterministic, race-free rule for any other.  color[n] (device int32);
+ *   1 <= ncolors <= 64.
+ * Rows with a zero diagonal (AD_STAT_ZERO_DIAG) or a colour outside
+ * [0, ncolors) (AD_STAT_BAD_COLOR) are held fixed.
+ *
+ * Output X (device, n x K) receives x^sweeps.  X must not alias X0.
+ * ckpt (device, may be NULL): with ckpt_every = c > 0, receives the iterates
+ * x^0, x^c, x^2c, ... (every s < sweeps with s % c == 0) as consecutive
+ * n x K panels, ceil(sweeps / c) of them (one, x^0, if sweeps == 0).
+ */
+int setup_testvectors(ad_handle h, const ad_csr *A, int32_t K, uint64_t seed,
+                      const void *X0, int32_t relax, int32_t sweeps, double omega,
+                      const int32_t *color, int32_t ncolors,
+                      void *X, void *ckpt, int32_t ckpt_every, void *stream);
+
+/* ------------------------------------------------------------------ */
+/* 2. algebraic distance (+ fused strength graph)                      */
+/* ------------------------------------------------------------------ */
+
+/* For every stored entry (i, j) of A (the diagonal included; Sec. 4.1,
+ * eq:measure with j ranging over V_i):
+ *     t_i    = x_i                         (target PLAIN, eq:LSfuncrowi), or
+ *              x_i - (A x)_i / a_ii        (target RESIDUAL, eq:modls, eq:measure)
+ *     p_ij   = <t_i, x_j>_w / <x_j, x_j>_w (0 if x_j = 0)
+ *     mu_ij  = sum_k w_k (t_i^k - p_ij x_j^k)^2
+ * i.e. mu_ij is the minimum of the one-point least-squares functional and
+ * the paper's strength is r_ij = 1 / mu_ij.
+ *
+ * X: the n x K panel (A's dtype).  w: K FP64 weights (device; NULL = all
+ * ones).  mu (device, nnz, A's dtype) receives mu.  p (device, nnz FP64,
+ * may be NULL) receives p.  The FP32 path accumulates in FP32 and recomputes
+ * in FP64, from the same FP32 inputs, every edge with mu < 1e-4 sum_k w_k t_k^2.
+ *
+ * Fused strength graph: if strong != NULL (then theta must be in (0, 1)),
+ * the strength_graph() outputs below are produced in the same pass.
+ */
+int algebraic_distance(ad_handle h, const ad_csr *A, int32_t K, const void *X,
+                       const double *w, int32_t target, void *mu, double *p,
+                       double theta, const uint8_t *fmask, uint8_t *strong,
+                       int32_t *nstrong, void *stream);
+
+/* ------------------------------------------------------------------ */
+/* 3. strength graph                                                   */
+/* ------------------------------------------------------------------ */
+
+/* Sec. 4.2, eq:strength_graph: for i in F the edge (i, j), j in F, j != i,
+ * is strong iff r_ij > theta max_k r_ik (k over the row's F-neighbours,
+ * k != i), r = 1/mu.  Evaluated division-free in FP64 as
+ *     m_i > theta mu_ij  with m_i = min_k mu_ik,
+ * and, when m_i = 0, exactly the edges with mu_ij = 0 are strong.
+ * fmask (device, n bytes, may be NULL = all rows in F): nonzero marks F.
+ * strong (device, nnz bytes) receives 0/1 (0 on the diagonal and outside
+ * F); nstrong (device, n int32, may be NULL) the per-row count.
+ * 0 < theta < 1. */
+int strength_graph(ad_handle h, const ad_csr *A, const void *mu, double theta,
+                   const uint8_t *fmask, uint8_t *strong, int32_t *nstrong, void *stream);
+
+/* ------------------------------------------------------------------ */
+/* 4. least-squares interpolation                                      */
+/* ------------------------------------------------------------------ */
+
+/* Sec. 3.1, eq:LSfuncrowi (target PLAIN) / eq:modls (target RESIDUAL): for
+ * each F row i (cf[i] == 0) the row p_i minimising
+ *     sum_k w_k (t_i^k - sum_{j in C_i} p_ij x_j^k)^2,
+ * with C_i the (at most) `caliber` C-neighbours (cf[j] != 0, j != i,
+ * a_ij stored) of smallest mu_ij, ties to the lower column -- the
+ * one-sided-distance scan the final remark of Sec. 4.3 describes.
+ * The normal equations are formed and solved in FP64 (Cholesky), also for
+ * an FP32 panel.  Columns are taken in increasing-mu order; one whose pivot
+ * is <= 1e-12 times its Gram diagonal (numerically in the span of those
+ * kept) is dropped.
+ *
+ * Outputs (device, row-major n x caliber for P):
+ *   P_col:  fine column index of each weight, in increasing-mu order,
+ *           -1 padded; C rows: P_col[i][0] = i.
+ *   P_val:  FP64 weights (0 padded); C rows: 1.
+ *   ls_val: FP64 functional at the minimiser (0 for C rows).
+ *   row_status: 0 ok, 1 F row without C-neighbour (empty row, ls_val =
+ *           sum w t^2), 2 a column was dropped, 3 residual target with a
+ *           zero diagonal (plain target used).
+ *   ls_sum (may be NULL): one FP64, the sum of ls_val over F rows, summed
+ *           in a fixed order (run-to-run identical).
+ * 1 <= caliber <= 8 and caliber <= K (the uniqueness remark of Sec. 3.1).
+ * mu is A's dtype (as produced by algebraic_distance).
+ */
+int ls_interp(ad_handle h, const ad_csr *A, int32_t K, const void *X, const double *w,
+              const uint8_t *cf, const void *mu, int32_t caliber, int32_t target,
+              int32_t *P_col, double *P_val, double *ls_val, int32_t *row_status,
+              double *ls_sum, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ALGDIST_H */

@@ -1,0 +1,254 @@
+"""Thin ctypes binding of libalgdist.so (C ABI in include/algdist.h).
+
+Argument marshalling only: every step of the path runs in the library's HIP
+kernels.  torch tensors provide device memory (data_ptr) and the stream
+(torch.cuda.current_stream()).  Outputs not passed in are allocated here
+with torch.empty on the input's device.  A non-zero status raises
+AlgdistError with the library's message.
+
+Importing this module raises ImportError when libalgdist.so has not been
+built: there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libalgdist.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(
+        "libalgdist.so is not built (expected at %s); run `python -m paper_1106_5990_amd.build`"
+        % LIB_PATH)
+
+_lib = C.CDLL(LIB_PATH)
+
+AD_F32, AD_F64 = 0, 1
+AD_JACOBI, AD_MULTICOLOR_GS = 0, 1
+AD_TARGET_PLAIN, AD_TARGET_RESIDUAL = 0, 1
+
+STAT_ZERO_DIAG = 0x01
+STAT_BAD_COLOR = 0x02
+STAT_NONFINITE = 0x04
+STAT_CSR_ROWPTR = 0x08
+STAT_CSR_COLS = 0x10
+STAT_CSR_NODIAG = 0x20
+STAT_TIMEOUT = 0x40
+
+STATUS_NAMES = {0: "AD_OK", 1: "AD_EINVAL", 2: "AD_EDTYPE", 3: "AD_ECALIBER", 4: "AD_ESTRUCT",
+                5: "AD_EDEVICE", 6: "AD_ENOMEM", 7: "AD_EUNSUPPORTED"}
+
+
+class ad_csr(C.Structure):
+    _fields_ = [("n", C.c_int32), ("nnz", C.c_int64), ("row_ptr", C.c_void_p),
+                ("col", C.c_void_p), ("val", C.c_void_p), ("dtype", C.c_int32)]
+
+
+_P = C.c_void_p
+_i32, _i64, _u64, _f64 = C.c_int32, C.c_int64, C.c_uint64, C.c_double
+_CSRP = C.POINTER(ad_csr)
+
+_SIGS = {
+    "algdist_version": (_i32, []),
+    "algdist_create": (_i32, [C.POINTER(C.c_void_p), C.c_int]),
+    "algdist_destroy": (_i32, [_P]),
+    "algdist_status": (_i32, [_P, C.POINTER(C.c_uint32), C.c_int]),
+    "algdist_last_error": (C.c_char_p, [_P]),
+    "algdist_timing": (_i32, [_P, C.c_int]),
+    "algdist_timing_report": (C.c_char_p, [_P]),
+    "csr_validate": (_i32, [_P, _CSRP, _P]),
+    "setup_testvectors": (_i32, [_P, _CSRP, _i32, _u64, _P, _i32, _i32, _f64, _P, _i32, _P, _P,
+                                 _i32, _P]),
+    "algebraic_distance": (_i32, [_P, _CSRP, _i32, _P, _P, _i32, _P, _P, _f64, _P, _P, _P, _P]),
+    "strength_graph": (_i32, [_P, _CSRP, _P, _f64, _P, _P, _P, _P]),
+    "ls_interp": (_i32, [_P, _CSRP, _i32, _P, _P, _P, _P, _i32, _i32, _P, _P, _P, _P, _P, _P]),
+}
+for _name, (_res, _args) in _SIGS.items():
+    _fn = getattr(_lib, _name)
+    _fn.restype = _res
+    _fn.argtypes = _args
+
+
+class AlgdistError(RuntimeError):
+    pass
+
+
+_handles = {}
+
+
+def handle(device: Optional[int] = None):
+    dev = torch.cuda.current_device() if device is None else int(device)
+    h = _handles.get(dev)
+    if h is None:
+        hp = C.c_void_p()
+        rc = _lib.algdist_create(C.byref(hp), dev)
+        if rc != 0:
+            raise AlgdistError("algdist_create(device=%d) failed: %s" % (dev, STATUS_NAMES.get(rc, rc)))
+        h = hp.value
+        _handles[dev] = h
+    return h
+
+
+def _check(rc: int, h, what: str):
+    if rc != 0:
+        msg = _lib.algdist_last_error(h).decode() if h else ""
+        raise AlgdistError("%s: %s %s" % (what, STATUS_NAMES.get(rc, rc), msg))
+
+
+def _ptr(t):
+    return None if t is None else t.data_ptr()
+
+
+def _stream(stream=None):
+    s = torch.cuda.current_stream() if stream is None else stream
+    return s.cuda_stream
+
+
+def _dtype_code(dt: torch.dtype) -> int:
+    if dt == torch.float32:
+        return AD_F32
+    if dt == torch.float64:
+        return AD_F64
+    raise AlgdistError("unsupported dtype %s" % dt)
+
+
+class Csr:
+    """Device CSR: int32 row_ptr[n+1], int32 col[nnz], val[nnz] (float32/64)."""
+
+    def __init__(self, row_ptr: torch.Tensor, col: torch.Tensor, val: torch.Tensor):
+        for t, name in ((row_ptr, "row_ptr"), (col, "col")):
+            if t.dtype != torch.int32 or not t.is_contiguous():
+                raise AlgdistError("%s must be a contiguous int32 tensor" % name)
+        if not val.is_contiguous():
+            raise AlgdistError("val must be contiguous")
+        self.row_ptr, self.col, self.val = row_ptr, col, val
+        self.n = row_ptr.numel() - 1
+        self.nnz = col.numel()
+        self.dtype = val.dtype
+        self.device = val.device
+        self._s = ad_csr(self.n, self.nnz, row_ptr.data_ptr(), col.data_ptr(), val.data_ptr(),
+                         _dtype_code(val.dtype))
+
+    @classmethod
+    def from_host(cls, A, dtype=torch.float64, device="cuda"):
+        """From any object with numpy row_ptr/col/val (e.g. workloads.CSR)."""
+        return cls(torch.as_tensor(A.row_ptr).to(device=device, dtype=torch.int32).contiguous(),
+                   torch.as_tensor(A.col).to(device=device, dtype=torch.int32).contiguous(),
+                   torch.as_tensor(A.val).to(device=device, dtype=dtype).contiguous())
+
+    def with_values(self, val: torch.Tensor) -> "Csr":
+        return Csr(self.row_ptr, self.col, val)
+
+    def ref(self):
+        return C.byref(self._s)
+
+
+def status(clear: bool = False, device: Optional[int] = None) -> int:
+    """Sticky device status bits (synchronises the device)."""
+    h = handle(device)
+    bits = C.c_uint32(0)
+    _check(_lib.algdist_status(h, C.byref(bits), int(clear)), h, "algdist_status")
+    return int(bits.value)
+
+
+def timing(enable: bool, device: Optional[int] = None) -> None:
+    """Start (enable=True, fresh record) or stop per-kernel HIP-event timing."""
+    h = handle(device)
+    _check(_lib.algdist_timing(h, int(enable)), h, "algdist_timing")
+
+
+def timing_report(device: Optional[int] = None) -> dict:
+    """{label: (launches, total_ms)} of the kernels timed since timing(True)."""
+    h = handle(device)
+    txt = _lib.algdist_timing_report(h).decode()
+    out = {}
+    for line in txt.splitlines():
+        lab, cnt, ms = line.split()
+        out[lab] = (int(cnt), float(ms))
+    return out
+
+
+def csr_validate(A: Csr, stream=None) -> None:
+    h = handle(A.device.index)
+    _check(_lib.csr_validate(h, A.ref(), _stream(stream)), h, "csr_validate")
+
+
+def setup_testvectors(A: Csr, K: int, seed: int = 0, X0: Optional[torch.Tensor] = None,
+                      relax: str = "jacobi", sweeps: int = 1, omega: float = 2.0 / 3.0,
+                      color: Optional[torch.Tensor] = None, ncolors: int = 0,
+                      out: Optional[torch.Tensor] = None, ckpt: Optional[torch.Tensor] = None,
+                      ckpt_every: int = 0, stream=None) -> torch.Tensor:
+    h = handle(A.device.index)
+    X = out if out is not None else torch.empty((A.n, K), dtype=A.dtype, device=A.device)
+    kind = {"jacobi": AD_JACOBI, "gs": AD_MULTICOLOR_GS}[relax]
+    rc = _lib.setup_testvectors(h, A.ref(), K, seed & (2 ** 64 - 1), _ptr(X0), kind, sweeps,
+                                float(omega), _ptr(color), ncolors, _ptr(X), _ptr(ckpt),
+                                ckpt_every, _stream(stream))
+    _check(rc, h, "setup_testvectors")
+    return X
+
+
+def algebraic_distance(A: Csr, X: torch.Tensor, w: Optional[torch.Tensor] = None,
+                       target: str = "plain", mu: Optional[torch.Tensor] = None,
+                       p: Optional[torch.Tensor] = None, want_p: bool = False,
+                       theta: float = 0.0, fmask: Optional[torch.Tensor] = None,
+                       strong: Optional[torch.Tensor] = None,
+                       nstrong: Optional[torch.Tensor] = None, fuse: bool = False, stream=None):
+    """Returns mu, or (mu, strong, nstrong) when fuse=True, plus p if want_p."""
+    h = handle(A.device.index)
+    K = X.shape[1]
+    mu = mu if mu is not None else torch.empty(A.nnz, dtype=A.dtype, device=A.device)
+    if want_p and p is None:
+        p = torch.empty(A.nnz, dtype=torch.float64, device=A.device)
+    if fuse:
+        strong = strong if strong is not None else torch.empty(A.nnz, dtype=torch.uint8, device=A.device)
+        nstrong = nstrong if nstrong is not None else torch.empty(A.n, dtype=torch.int32, device=A.device)
+    tg = {"plain": AD_TARGET_PLAIN, "residual": AD_TARGET_RESIDUAL}[target]
+    rc = _lib.algebraic_distance(h, A.ref(), K, _ptr(X), _ptr(w), tg, _ptr(mu), _ptr(p),
+                                 float(theta), _ptr(fmask), _ptr(strong) if fuse else None,
+                                 _ptr(nstrong) if fuse else None, _stream(stream))
+    _check(rc, h, "algebraic_distance")
+    res = (mu, strong, nstrong) if fuse else (mu,)
+    if want_p:
+        res = res + (p,)
+    return res if len(res) > 1 else res[0]
+
+
+def strength_graph(A: Csr, mu: torch.Tensor, theta: float, fmask: Optional[torch.Tensor] = None,
+                   strong: Optional[torch.Tensor] = None, nstrong: Optional[torch.Tensor] = None,
+                   stream=None):
+    h = handle(A.device.index)
+    strong = strong if strong is not None else torch.empty(A.nnz, dtype=torch.uint8, device=A.device)
+    nstrong = nstrong if nstrong is not None else torch.empty(A.n, dtype=torch.int32, device=A.device)
+    rc = _lib.strength_graph(h, A.ref(), _ptr(mu), float(theta), _ptr(fmask), _ptr(strong),
+                             _ptr(nstrong), _stream(stream))
+    _check(rc, h, "strength_graph")
+    return strong, nstrong
+
+
+def ls_interp(A: Csr, X: torch.Tensor, cf: torch.Tensor, mu: torch.Tensor, caliber: int,
+              w: Optional[torch.Tensor] = None, target: str = "plain",
+              P_col: Optional[torch.Tensor] = None, P_val: Optional[torch.Tensor] = None,
+              ls_val: Optional[torch.Tensor] = None, row_status: Optional[torch.Tensor] = None,
+              ls_sum: Optional[torch.Tensor] = None, want_sum: bool = False, stream=None):
+    """Returns (P_col, P_val, ls_val, row_status) and ls_sum if want_sum."""
+    h = handle(A.device.index)
+    K = X.shape[1]
+    dev = A.device
+    P_col = P_col if P_col is not None else torch.empty((A.n, caliber), dtype=torch.int32, device=dev)
+    P_val = P_val if P_val is not None else torch.empty((A.n, caliber), dtype=torch.float64, device=dev)
+    ls_val = ls_val if ls_val is not None else torch.empty(A.n, dtype=torch.float64, device=dev)
+    row_status = row_status if row_status is not None else torch.empty(A.n, dtype=torch.int32, device=dev)
+    if want_sum and ls_sum is None:
+        ls_sum = torch.empty(1, dtype=torch.float64, device=dev)
+    tg = {"plain": AD_TARGET_PLAIN, "residual": AD_TARGET_RESIDUAL}[target]
+    rc = _lib.ls_interp(h, A.ref(), K, _ptr(X), _ptr(w), _ptr(cf), _ptr(mu), caliber, tg,
+                        _ptr(P_col), _ptr(P_val), _ptr(ls_val), _ptr(row_status),
+                        _ptr(ls_sum) if want_sum else None, _stream(stream))
+    _check(rc, h, "ls_interp")
+    out = (P_col, P_val, ls_val, row_status)
+    return out + (ls_sum,) if want_sum else out

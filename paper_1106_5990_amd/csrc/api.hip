@@ -1,0 +1,354 @@
+// api.hip -- the exported C ABI (include/algdist.h): argument checks on the
+// host, workspace management, and the launch schedule of each call.
+#include <stdio.h>
+#include <string.h>
+
+#include <string>
+#include <vector>
+#include <stdarg.h>
+
+#include "device.h"
+#include "internal.h"
+
+using namespace ad;
+
+namespace {
+
+int fail(ad_handle h, int code, const char* fmt, ...) __attribute__((format(printf, 3, 4)));
+int fail(ad_handle h, int code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    if (h) h->err = buf;
+    return code;
+}
+
+bool k_ok(int K) { return K == 2 || K == 4 || K == 8 || K == 16 || K == 32 || K == 64; }
+size_t dsize(int dtype) { return dtype == AD_F32 ? 4 : 8; }
+bool aligned16(const void* p) { return ((uintptr_t)p & 15u) == 0; }
+
+// Common CSR argument checks (host side: sizes and pointers only).
+int check_csr(ad_handle h, const ad_csr* A) {
+    if (!A) return fail(h, AD_EINVAL, "A is NULL");
+    if (A->n < 0) return fail(h, AD_EINVAL, "n = %d < 0", A->n);
+    if (A->nnz < 0 || A->nnz > 0x7fffffffLL)
+        return fail(h, AD_ESTRUCT, "nnz = %lld outside [0, 2^31)", (long long)A->nnz);
+    if (A->dtype != AD_F32 && A->dtype != AD_F64)
+        return fail(h, AD_EDTYPE, "dtype %d is neither AD_F32 nor AD_F64", A->dtype);
+    if (A->n > 0 && (!A->row_ptr || (A->nnz > 0 && (!A->col || !A->val))))
+        return fail(h, AD_EINVAL, "null CSR array");
+    if (A->n > 0 && A->nnz < A->n)
+        return fail(h, AD_ESTRUCT, "nnz = %lld < n = %d: every row needs its diagonal",
+                    (long long)A->nnz, A->n);
+    return AD_OK;
+}
+
+int check_panel(ad_handle h, const void* X, const char* name, int n) {
+    if (n > 0 && !X) return fail(h, AD_EINVAL, "%s is NULL", name);
+    if (X && !aligned16(X)) return fail(h, AD_EINVAL, "%s is not 16-byte aligned", name);
+    return AD_OK;
+}
+
+}  // namespace
+
+namespace ad {
+TimedScope::TimedScope(ad_handle h, const char* label, hipStream_t s) : h_(h), label_(label), s_(s) {
+    if (!h_->timing) return;
+    if (h_->events_used + 2 > h_->event_pool.size()) {
+        for (int q = 0; q < 2; ++q) {
+            hipEvent_t e;
+            if (hipEventCreate(&e) != hipSuccess) return;
+            h_->event_pool.push_back(e);
+        }
+    }
+    a_ = h_->event_pool[h_->events_used++];
+    if (hipEventRecord(a_, s_) != hipSuccess) a_ = nullptr;
+}
+
+TimedScope::~TimedScope() {
+    if (!a_) return;
+    hipEvent_t b = h_->event_pool[h_->events_used++];
+    if (hipEventRecord(b, s_) == hipSuccess) h_->timed.push_back({label_, a_, b});
+}
+
+int ws_reserve(ad_handle h, size_t bytes) {
+    if (bytes <= h->ws_bytes) return AD_OK;
+    // earlier calls may still use the old buffer
+    AD_HIP(hipDeviceSynchronize());
+    if (h->ws) AD_HIP(hipFree(h->ws));
+    h->ws = nullptr;
+    h->ws_bytes = 0;
+    size_t want = bytes + bytes / 4;
+    if (hipMalloc(&h->ws, want) != hipSuccess) {
+        h->ws = nullptr;
+        return AD_ENOMEM;
+    }
+    h->ws_bytes = want;
+    return AD_OK;
+}
+}  // namespace ad
+
+extern "C" {
+
+int algdist_version(void) { return ALGDIST_VERSION; }
+
+int algdist_create(ad_handle* out, int device) {
+    if (!out) return AD_EINVAL;
+    *out = nullptr;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return AD_EDEVICE;
+    ad_handle h = new ad_handle_s();
+    h->device = device;
+    if (hipSetDevice(device) != hipSuccess) {
+        delete h;
+        return AD_EDEVICE;
+    }
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) == hipSuccess) h->cu_count = prop.multiProcessorCount;
+    if (hipMalloc((void**)&h->status, sizeof(unsigned)) != hipSuccess) {
+        delete h;
+        return AD_ENOMEM;
+    }
+    if (hipMemset(h->status, 0, sizeof(unsigned)) != hipSuccess) {
+        (void)hipFree(h->status);
+        delete h;
+        return AD_EDEVICE;
+    }
+    *out = h;
+    return AD_OK;
+}
+
+int algdist_destroy(ad_handle h) {
+    if (!h) return AD_EINVAL;
+    (void)hipSetDevice(h->device);
+    (void)hipDeviceSynchronize();
+    if (h->ws) (void)hipFree(h->ws);
+    if (h->status) (void)hipFree(h->status);
+    for (hipEvent_t e : h->event_pool) (void)hipEventDestroy(e);
+    delete h;
+    return AD_OK;
+}
+
+int algdist_status(ad_handle h, uint32_t* bits, int clear) {
+    if (!h || !bits) return AD_EINVAL;
+    AD_HIP(hipSetDevice(h->device));
+    AD_HIP(hipDeviceSynchronize());
+    unsigned v = 0;
+    AD_HIP(hipMemcpy(&v, h->status, sizeof v, hipMemcpyDeviceToHost));
+    *bits = v;
+    if (clear) AD_HIP(hipMemset(h->status, 0, sizeof(unsigned)));
+    return AD_OK;
+}
+
+const char* algdist_last_error(ad_handle h) { return h ? h->err.c_str() : "null handle"; }
+
+int algdist_timing(ad_handle h, int enable) {
+    if (!h) return AD_EINVAL;
+    if (enable) {
+        h->timed.clear();
+        h->events_used = 0;
+    }
+    h->timing = enable != 0;
+    return AD_OK;
+}
+
+const char* algdist_timing_report(ad_handle h) {
+    if (!h) return "";
+    h->report.clear();
+    if (hipSetDevice(h->device) != hipSuccess || hipDeviceSynchronize() != hipSuccess) return "";
+    std::vector<std::string> labels;
+    std::vector<int> count;
+    std::vector<double> total;
+    for (const auto& t : h->timed) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, t.a, t.b) != hipSuccess) continue;
+        size_t q = 0;
+        while (q < labels.size() && labels[q] != t.label) ++q;
+        if (q == labels.size()) {
+            labels.push_back(t.label);
+            count.push_back(0);
+            total.push_back(0.0);
+        }
+        ++count[q];
+        total[q] += ms;
+    }
+    char line[160];
+    for (size_t q = 0; q < labels.size(); ++q) {
+        snprintf(line, sizeof line, "%s %d %.6f\n", labels[q].c_str(), count[q], total[q]);
+        h->report += line;
+    }
+    return h->report.c_str();
+}
+
+int csr_validate(ad_handle h, const ad_csr* A, void* stream) {
+    if (!h) return AD_EINVAL;
+    h->err.clear();
+    int rc = check_csr(h, A);
+    if (rc) return rc;
+    if (A->n == 0) return AD_OK;
+    AD_HIP(hipSetDevice(h->device));
+    return launch_csr_validate(A, h->status, (hipStream_t)stream);
+}
+
+int setup_testvectors(ad_handle h, const ad_csr* A, int32_t K, uint64_t seed, const void* X0,
+                      int32_t relax, int32_t sweeps, double omega, const int32_t* color,
+                      int32_t ncolors, void* X, void* ckpt, int32_t ckpt_every, void* stream) {
+    if (!h) return AD_EINVAL;
+    h->err.clear();
+    int rc = check_csr(h, A);
+    if (rc) return rc;
+    if (!k_ok(K)) return fail(h, AD_EINVAL, "K = %d: must be 2, 4, 8, 16, 32 or 64", K);
+    if (sweeps < 0) return fail(h, AD_EINVAL, "sweeps = %d < 0", sweeps);
+    if (relax != AD_JACOBI && relax != AD_MULTICOLOR_GS)
+        return fail(h, AD_EINVAL, "relax = %d is neither AD_JACOBI nor AD_MULTICOLOR_GS", relax);
+    if (relax == AD_MULTICOLOR_GS && sweeps > 0) {
+        if (ncolors < 1 || ncolors > 64)
+            return fail(h, AD_EINVAL, "ncolors = %d outside [1, 64]", ncolors);
+        if (A->n > 0 && !color) return fail(h, AD_EINVAL, "color is NULL");
+    }
+    if ((rc = check_panel(h, X, "X", A->n))) return rc;
+    if ((rc = check_panel(h, X0, "X0", 0))) return rc;
+    if (X0 && X0 == X) return fail(h, AD_EINVAL, "X0 and X alias");
+    if (ckpt) {
+        if (ckpt_every <= 0) return fail(h, AD_EINVAL, "ckpt_every = %d <= 0", ckpt_every);
+        if ((rc = check_panel(h, ckpt, "ckpt", A->n))) return rc;
+    }
+    if (A->n == 0) return AD_OK;
+    AD_HIP(hipSetDevice(h->device));
+    hipStream_t s = (hipStream_t)stream;
+    const int dt = A->dtype;
+    const size_t panel = (size_t)A->n * K * dsize(dt);
+
+    // Workspace: one extra panel for the ping-pong, plus the colour lists.
+    WsReq req;
+    const size_t o_pp = req.add(panel);
+    size_t o_rl = 0, o_seg = 0, o_cnt = 0;
+    int nblk = 0;
+    const bool gs = relax == AD_MULTICOLOR_GS && sweeps > 0;
+    if (gs) {
+        nblk = color_partition_blocks(A->n);
+        o_rl = req.add(sizeof(int32_t) * (size_t)A->n);
+        o_seg = req.add(sizeof(int32_t) * (ncolors + 2));
+        o_cnt = req.add(sizeof(int32_t) * (size_t)(ncolors + 1) * nblk);
+    }
+    if ((rc = ws_reserve(h, req.off))) return fail(h, rc, "workspace of %zu bytes", req.off);
+    char* ws = (char*)h->ws;
+    void* W = ws + o_pp;
+
+    // Buffer of iterate q (0..sweeps): x^sweeps lands in X; a checkpointed
+    // iterate lives in its checkpoint slot; the others alternate between X
+    // and W so that every sweep reads and writes different buffers.
+    const int ns = sweeps;
+    std::vector<void*> buf(ns + 1);
+    buf[ns] = X;
+    for (int q = ns - 1; q >= 0; --q) {
+        if (ckpt && q % ckpt_every == 0) buf[q] = (char*)ckpt + (size_t)(q / ckpt_every) * panel;
+        else buf[q] = (buf[q + 1] == X) ? W : X;
+    }
+    if (X0 && ns > 0 && !ckpt) {
+        buf[0] = (void*)X0;  // read-only start: sweep 0 reads it in place
+    } else if (X0) {
+        AD_HIP(hipMemcpyAsync(buf[0], X0, panel, hipMemcpyDeviceToDevice, s));
+    } else {
+        TimedScope ts(h, "tv_init", s);
+        if ((rc = launch_tv_init(dt, 0, A->n, K, seed, buf[0], s))) return fail(h, rc, "tv_init launch");
+    }
+    if (ns == 0 && ckpt) AD_HIP(hipMemcpyAsync(ckpt, X, panel, hipMemcpyDeviceToDevice, s));
+
+    int32_t* rowlist = gs ? (int32_t*)(ws + o_rl) : nullptr;
+    int32_t* seg = gs ? (int32_t*)(ws + o_seg) : nullptr;
+    if (gs) {
+        TimedScope ts(h, "color_partition", s);
+        rc = launch_color_partition(A->n, color, ncolors, rowlist, seg, (int32_t*)(ws + o_cnt),
+                                    nblk, h->status, s);
+        if (rc) return fail(h, rc, "colour partition launch");
+    }
+    LaunchCfg cfg;
+    for (int q = 0; q < ns; ++q) {
+        if (relax == AD_JACOBI) {
+            TimedScope ts(h, "jacobi", s);
+            rc = launch_jacobi(dt, K, A, buf[q], buf[q + 1], omega, h->status, cfg, s);
+        } else {
+            for (int c = 0; c < ncolors && !rc; ++c) {
+                TimedScope ts(h, "gs_phase", s);
+                rc = launch_gs_phase(dt, K, A, color, c, ncolors, rowlist, seg, buf[q], buf[q + 1],
+                                     h->status, cfg, s);
+            }
+        }
+        if (rc) return fail(h, rc, "relaxation launch");
+    }
+    return AD_OK;
+}
+
+int algebraic_distance(ad_handle h, const ad_csr* A, int32_t K, const void* X, const double* w,
+                       int32_t target, void* mu, double* p, double theta, const uint8_t* fmask,
+                       uint8_t* strong, int32_t* nstrong, void* stream) {
+    if (!h) return AD_EINVAL;
+    h->err.clear();
+    int rc = check_csr(h, A);
+    if (rc) return rc;
+    if (!k_ok(K)) return fail(h, AD_EINVAL, "K = %d: must be 2, 4, 8, 16, 32 or 64", K);
+    if (target != AD_TARGET_PLAIN && target != AD_TARGET_RESIDUAL)
+        return fail(h, AD_EINVAL, "target = %d", target);
+    if ((rc = check_panel(h, X, "X", A->n))) return rc;
+    if (A->nnz > 0 && !mu) return fail(h, AD_EINVAL, "mu is NULL");
+    if (strong && !(theta > 0.0 && theta < 1.0))
+        return fail(h, AD_EINVAL, "theta = %g outside (0, 1)", theta);
+    if (A->n == 0) return AD_OK;
+    AD_HIP(hipSetDevice(h->device));
+    LaunchCfg cfg;
+    TimedScope ts(h, "algdist", (hipStream_t)stream);
+    rc = launch_algdist(A->dtype, K, A, X, w, target, mu, p, theta, fmask, strong, nstrong,
+                        h->status, cfg, (hipStream_t)stream);
+    return rc ? fail(h, rc, "algebraic_distance launch") : AD_OK;
+}
+
+int strength_graph(ad_handle h, const ad_csr* A, const void* mu, double theta,
+                   const uint8_t* fmask, uint8_t* strong, int32_t* nstrong, void* stream) {
+    if (!h) return AD_EINVAL;
+    h->err.clear();
+    int rc = check_csr(h, A);
+    if (rc) return rc;
+    if (!(theta > 0.0 && theta < 1.0)) return fail(h, AD_EINVAL, "theta = %g outside (0, 1)", theta);
+    if (A->nnz > 0 && (!mu || !strong)) return fail(h, AD_EINVAL, "mu or strong is NULL");
+    if (A->n == 0) return AD_OK;
+    AD_HIP(hipSetDevice(h->device));
+    TimedScope ts(h, "strength", (hipStream_t)stream);
+    rc = launch_strength(A->dtype, A, mu, theta, fmask, strong, nstrong, (hipStream_t)stream);
+    return rc ? fail(h, rc, "strength_graph launch") : AD_OK;
+}
+
+int ls_interp(ad_handle h, const ad_csr* A, int32_t K, const void* X, const double* w,
+              const uint8_t* cf, const void* mu, int32_t caliber, int32_t target, int32_t* P_col,
+              double* P_val, double* ls_val, int32_t* row_status, double* ls_sum, void* stream) {
+    if (!h) return AD_EINVAL;
+    h->err.clear();
+    int rc = check_csr(h, A);
+    if (rc) return rc;
+    if (!k_ok(K)) return fail(h, AD_EINVAL, "K = %d: must be 2, 4, 8, 16, 32 or 64", K);
+    if (caliber < 1 || caliber > 8) return fail(h, AD_ECALIBER, "caliber = %d outside [1, 8]", caliber);
+    if (caliber > K)
+        return fail(h, AD_ECALIBER, "caliber = %d > K = %d: LS rows would not be unique", caliber, K);
+    if (target != AD_TARGET_PLAIN && target != AD_TARGET_RESIDUAL)
+        return fail(h, AD_EINVAL, "target = %d", target);
+    if ((rc = check_panel(h, X, "X", A->n))) return rc;
+    if (A->n > 0 && (!cf || !mu || !P_col || !P_val || !ls_val || !row_status))
+        return fail(h, AD_EINVAL, "null output or input array");
+    AD_HIP(hipSetDevice(h->device));
+    LaunchCfg cfg;
+    double* bs = nullptr;
+    if (ls_sum && A->n > 0) {
+        const int nb = ls_interp_blocks(A->dtype, K, A->n, cfg);
+        if ((rc = ws_reserve(h, sizeof(double) * (size_t)nb)))
+            return fail(h, rc, "workspace for %d block sums", nb);
+        bs = (double*)h->ws;
+    }
+    TimedScope ts(h, "ls_interp", (hipStream_t)stream);
+    rc = launch_ls_interp(A->dtype, K, caliber, A, X, w, cf, mu, target, P_col, P_val, ls_val,
+                          row_status, bs, ls_sum, h->status, cfg, (hipStream_t)stream);
+    return rc ? fail(h, rc, "ls_interp launch") : AD_OK;
+}
+
+}  // extern "C"

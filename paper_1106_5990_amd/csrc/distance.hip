@@ -1,0 +1,299 @@
+// distance.hip -- per-edge algebraic distance (Sec. 4.1, eq:measure) and the
+// strength graph built from it (Sec. 4.2, eq:strength_graph).
+//
+// One row group per row i: the target t_i (x_i, or x_i - (A x)_i / a_ii) is
+// held in registers; for each stored entry (i, j) the group gathers x_j and
+// computes, with two butterfly reductions over K,
+//     p = <t, x_j>_w / <x_j, x_j>_w,   mu = sum_k w_k (t_k - p x_jk)^2,
+// the residual pass re-using the register-resident x_j.  In FP32 an edge
+// whose mu falls below 1e-4 * <t, t>_w (where the FP32 residual loses too
+// many digits) is recomputed in FP64 from the same FP32 values.  The strength
+// mask needs the row minimum of mu, known only after the row: the lane that
+// stored mu_ij re-reads its own store (program order) in a second pass.
+#include <math.h>
+
+#include "device.h"
+#include "internal.h"
+
+namespace ad {
+
+template <typename T> struct Guard { static constexpr bool on = false; };
+template <> struct Guard<float> { static constexpr bool on = true; };
+
+template <typename T, int K>
+__global__ __launch_bounds__(kBlock) void algdist_kernel(
+    int n, const int* __restrict__ rp, const int* __restrict__ ci, const T* __restrict__ av,
+    const T* __restrict__ X, const double* __restrict__ w, int target, T* __restrict__ mu,
+    double* __restrict__ pout, double theta, const uint8_t* __restrict__ fmask,
+    uint8_t* __restrict__ strong, int* __restrict__ nstrong, int iter, int xcd,
+    unsigned* status) {
+    using S = Shape<T, K>;
+    constexpr int V = S::V, LPR = S::LPR;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int g = lane / LPR, l = lane % LPR;
+    const int wv = threadIdx.x / kWave;
+    const int64_t rows_per_tile = (int64_t)S::RPB * iter;
+    const int64_t ntiles = (n + rows_per_tile - 1) / rows_per_tile;
+    const int64_t tile = xcd ? xcd_tile(ntiles) : (int64_t)blockIdx.x;
+    if (tile < 0 || tile >= ntiles) return;
+
+    double wd[V];
+    T wt[V];
+#pragma unroll
+    for (int q = 0; q < V; ++q) {
+        wd[q] = w ? w[l * V + q] : 1.0;
+        wt[q] = (T)wd[q];
+    }
+    const bool fuse = strong != nullptr;
+
+    for (int it = 0; it < iter; ++it) {
+        const int64_t i64 = tile * rows_per_tile + (int64_t)it * S::RPB + wv * S::RPW + g;
+        if (i64 >= n) break;
+        const int i = (int)i64;
+        const int e0 = rp[i], e1 = rp[i + 1];
+
+        // target t_i; the residual form is built in FP64 (products of two
+        // panel-type values are exact there), then rounded to the panel type
+        // for the main pass; the FP64 copy feeds the guard-band recompute.
+        Frag<T, V> t = load_frag<T, V>(X + (size_t)i * K + l * V);
+        double t64[V];
+#pragma unroll
+        for (int q = 0; q < V; ++q) t64[q] = (double)t.v[q];
+        if (target == AD_TARGET_RESIDUAL) {
+            double y[V];
+#pragma unroll
+            for (int q = 0; q < V; ++q) y[q] = 0.0;
+            double d = 0.0;
+            for (int e = e0; e < e1; ++e) {
+                const int j = ci[e];
+                const double a = (double)av[e];
+                Frag<T, V> xj = load_frag<T, V>(X + (size_t)j * K + l * V);
+#pragma unroll
+                for (int q = 0; q < V; ++q) y[q] = fma(a, (double)xj.v[q], y[q]);
+                if (j == i) d = a;
+            }
+            if (d != 0.0) {
+#pragma unroll
+                for (int q = 0; q < V; ++q) {
+                    t64[q] = t64[q] - y[q] / d;
+                    t.v[q] = (T)t64[q];
+                }
+            } else if (l == 0) {
+                flag(status, AD_STAT_ZERO_DIAG);
+            }
+        }
+        T wtt[V];
+        T saa = T(0);
+#pragma unroll
+        for (int q = 0; q < V; ++q) {
+            wtt[q] = wt[q] * t.v[q];
+            saa = fma(wtt[q], t.v[q], saa);
+        }
+        saa = group_sum<LPR>(saa);
+        const T guard = (T)1e-4 * saa;
+
+        const bool in_f = fmask ? (fmask[i] != 0) : true;
+        T mmin = (T)INFINITY;
+        bool bad = false;
+        for (int e = e0; e < e1; ++e) {
+            const int j = ci[e];
+            Frag<T, V> xj = load_frag<T, V>(X + (size_t)j * K + l * V);
+            T sab = T(0), sbb = T(0);
+#pragma unroll
+            for (int q = 0; q < V; ++q) {
+                sab = fma(wtt[q], xj.v[q], sab);
+                sbb = fma(wt[q] * xj.v[q], xj.v[q], sbb);
+            }
+            sab = group_sum<LPR>(sab);
+            sbb = group_sum<LPR>(sbb);
+            T p = (sbb > T(0)) ? sab / sbb : T(0);
+            T m = T(0);
+#pragma unroll
+            for (int q = 0; q < V; ++q) {
+                const T r = t.v[q] - p * xj.v[q];
+                m = fma(wt[q] * r, r, m);
+            }
+            m = group_sum<LPR>(m);
+            double pd = (double)p;
+            if (Guard<T>::on && m < guard) {
+                // FP64 recompute from the same FP32 inputs
+                double a2 = 0.0, b2 = 0.0;
+#pragma unroll
+                for (int q = 0; q < V; ++q) {
+                    const double xq = (double)xj.v[q], tq = t64[q];
+                    a2 = fma(wd[q] * tq, xq, a2);
+                    b2 = fma(wd[q] * xq, xq, b2);
+                }
+                a2 = group_sum<LPR>(a2);
+                b2 = group_sum<LPR>(b2);
+                pd = (b2 > 0.0) ? a2 / b2 : 0.0;
+                double m2 = 0.0;
+#pragma unroll
+                for (int q = 0; q < V; ++q) {
+                    const double r = t64[q] - pd * (double)xj.v[q];
+                    m2 = fma(wd[q] * r, r, m2);
+                }
+                m = (T)group_sum<LPR>(m2);
+            }
+            bad |= !isfinite(m);
+            if (((e - e0) & (LPR - 1)) == l) {
+                mu[e] = m;
+                if (pout) pout[e] = pd;
+            }
+            if (j != i && (!fmask || fmask[j])) mmin = (m < mmin) ? m : mmin;
+        }
+        if (bad && l == 0) flag(status, AD_STAT_NONFINITE);
+
+        if (fuse) {
+            // second pass: each lane re-reads the mu values it stored
+            int cnt = 0;
+            const double md = (double)mmin;
+            for (int e = e0 + l; e < e1; e += LPR) {
+                const int j = ci[e];
+                int s = 0;
+                if (in_f && j != i && (!fmask || fmask[j])) {
+                    const double me = (double)mu[e];
+                    s = (md > 0.0) ? (theta * me < md) : (me == 0.0);
+                }
+                strong[e] = (uint8_t)s;
+                cnt += s;
+            }
+            cnt = group_sum<LPR>(cnt);
+            if (l == 0 && nstrong) nstrong[i] = cnt;
+        }
+    }
+}
+
+template <typename T, int K>
+static void algdist_go(const ad_csr* A, const void* X, const double* w, int target, void* mu,
+                       double* p, double theta, const uint8_t* fmask, uint8_t* strong,
+                       int32_t* nstrong, unsigned* st, const LaunchCfg& cfg, hipStream_t s) {
+    using S = Shape<T, K>;
+    const int64_t rpt = (int64_t)S::RPB * cfg.iter;
+    const int64_t ntiles = (A->n + rpt - 1) / rpt;
+    const int grid = cfg.xcd_map ? grid_for_tiles(ntiles) : (int)ntiles;
+    algdist_kernel<T, K><<<dim3(grid), dim3(kBlock), 0, s>>>(
+        A->n, A->row_ptr, A->col, (const T*)A->val, (const T*)X, w, target, (T*)mu, p, theta,
+        fmask, strong, nstrong, cfg.iter, cfg.xcd_map, st);
+}
+
+#define AD_K_SWITCH(T, FN, ...)                         \
+    switch (K) {                                        \
+        case 2: FN<T, 2>(__VA_ARGS__); break;           \
+        case 4: FN<T, 4>(__VA_ARGS__); break;           \
+        case 8: FN<T, 8>(__VA_ARGS__); break;           \
+        case 16: FN<T, 16>(__VA_ARGS__); break;         \
+        case 32: FN<T, 32>(__VA_ARGS__); break;         \
+        case 64: FN<T, 64>(__VA_ARGS__); break;         \
+        default: return AD_EINVAL;                      \
+    }
+
+int launch_algdist(int dtype, int K, const ad_csr* A, const void* X, const double* w, int target,
+                   void* mu, double* p, double theta, const uint8_t* fmask, uint8_t* strong,
+                   int32_t* nstrong, unsigned* status, const LaunchCfg& cfg, hipStream_t s) {
+    if (A->n == 0) return AD_OK;
+    if (dtype == AD_F32) {
+        AD_K_SWITCH(float, algdist_go, A, X, w, target, mu, p, theta, fmask, strong, nstrong,
+                    status, cfg, s);
+    } else {
+        AD_K_SWITCH(double, algdist_go, A, X, w, target, mu, p, theta, fmask, strong, nstrong,
+                    status, cfg, s);
+    }
+    AD_HIP(hipGetLastError());
+    return AD_OK;
+}
+
+// ---------------------------------------------------------------- strength graph
+// One 8-lane group per row: row minimum of mu over F-neighbours j != i, then
+// the division-free test m_i > theta mu_ij (zero-distance edges when m_i = 0).
+constexpr int kStrLanes = 8;
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void strength_kernel(int n, const int* __restrict__ rp,
+                                                          const int* __restrict__ ci,
+                                                          const T* __restrict__ mu, double theta,
+                                                          const uint8_t* __restrict__ fmask,
+                                                          uint8_t* __restrict__ strong,
+                                                          int* __restrict__ nstrong) {
+    const int l = threadIdx.x % kStrLanes;
+    const int64_t i64 = ((int64_t)blockIdx.x * kBlock + threadIdx.x) / kStrLanes;
+    if (i64 >= n) return;  // whole groups exit together
+    const int i = (int)i64;
+    const int e0 = rp[i], e1 = rp[i + 1];
+    const bool in_f = fmask ? (fmask[i] != 0) : true;
+    T m = (T)INFINITY;
+    for (int e = e0 + l; e < e1; e += kStrLanes) {
+        const int j = ci[e];
+        if (in_f && j != i && (!fmask || fmask[j])) m = (mu[e] < m) ? mu[e] : m;
+    }
+    m = group_min<kStrLanes>(m);
+    const double md = (double)m;
+    int cnt = 0;
+    for (int e = e0 + l; e < e1; e += kStrLanes) {
+        const int j = ci[e];
+        int s = 0;
+        if (in_f && j != i && (!fmask || fmask[j])) {
+            const double me = (double)mu[e];
+            s = (md > 0.0) ? (theta * me < md) : (me == 0.0);
+        }
+        strong[e] = (uint8_t)s;
+        cnt += s;
+    }
+    cnt = group_sum<kStrLanes>(cnt);
+    if (l == 0 && nstrong) nstrong[i] = cnt;
+}
+
+int launch_strength(int dtype, const ad_csr* A, const void* mu, double theta,
+                    const uint8_t* fmask, uint8_t* strong, int32_t* nstrong, hipStream_t s) {
+    if (A->n == 0) return AD_OK;
+    const int64_t blocks = ((int64_t)A->n * kStrLanes + kBlock - 1) / kBlock;
+    if (dtype == AD_F32)
+        strength_kernel<float><<<dim3((unsigned)blocks), dim3(kBlock), 0, s>>>(
+            A->n, A->row_ptr, A->col, (const float*)mu, theta, fmask, strong, nstrong);
+    else
+        strength_kernel<double><<<dim3((unsigned)blocks), dim3(kBlock), 0, s>>>(
+            A->n, A->row_ptr, A->col, (const double*)mu, theta, fmask, strong, nstrong);
+    AD_HIP(hipGetLastError());
+    return AD_OK;
+}
+
+// ---------------------------------------------------------------- CSR check
+// One thread per row.  Reads only inside row_ptr[0..n] and, for rows whose
+// bounds are sane (0 <= rp[i] <= rp[i+1] <= nnz), inside col[].
+__global__ __launch_bounds__(kBlock) void csr_validate_kernel(int n, int64_t nnz,
+                                                              const int* __restrict__ rp,
+                                                              const int* __restrict__ ci,
+                                                              unsigned* status) {
+    const int64_t i64 = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i64 > n) return;
+    const int i = (int)i64;
+    if (i == n) {
+        if (rp[n] != nnz || rp[0] != 0) flag(status, AD_STAT_CSR_ROWPTR);
+        return;
+    }
+    const int b = rp[i], e = rp[i + 1];
+    if (b < 0 || e < b || e > nnz) {
+        flag(status, AD_STAT_CSR_ROWPTR);
+        return;
+    }
+    bool diag = false, cols_ok = true;
+    int prev = -1;
+    for (int q = b; q < e; ++q) {
+        const int j = ci[q];
+        if (j < 0 || j >= n || j <= prev) cols_ok = false;
+        diag |= (j == i);
+        prev = j;
+    }
+    if (!cols_ok) flag(status, AD_STAT_CSR_COLS);
+    if (!diag) flag(status, AD_STAT_CSR_NODIAG);
+}
+
+int launch_csr_validate(const ad_csr* A, unsigned* status, hipStream_t s) {
+    const int64_t blocks = ((int64_t)A->n + 1 + kBlock - 1) / kBlock;
+    csr_validate_kernel<<<dim3((unsigned)blocks), dim3(kBlock), 0, s>>>(A->n, A->nnz, A->row_ptr,
+                                                                        A->col, status);
+    AD_HIP(hipGetLastError());
+    return AD_OK;
+}
+
+}  // namespace ad

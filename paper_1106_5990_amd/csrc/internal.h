@@ -1,0 +1,111 @@
+// internal.h -- host-side internals of libalgdist: the handle, its
+// workspace, launch wrappers shared between translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "algdist.h"
+
+// One timed launch: HIP events recorded on the launch stream around it.
+struct ad_timed_launch {
+    const char* label;
+    hipEvent_t a, b;
+};
+
+struct ad_handle_s {
+    int device = 0;
+    unsigned* status = nullptr;  // sticky device status word
+    void* ws = nullptr;          // workspace (grown on demand)
+    size_t ws_bytes = 0;
+    std::string err;
+    int cu_count = 256;
+    // per-kernel timing (algdist_timing / algdist_timing_report)
+    bool timing = false;
+    std::vector<ad_timed_launch> timed;
+    std::vector<hipEvent_t> event_pool;
+    size_t events_used = 0;
+    std::string report;
+};
+
+namespace ad {
+
+// Kernel launch knobs picked per call (the autotuner may override them).
+struct LaunchCfg {
+    int iter = 1;     // row-block steps per workgroup ("rows per wavefront" multiplier)
+    int xcd_map = 1;  // 1: XCD-contiguous tile mapping
+};
+
+// Workspace carve-up helper: returns aligned sub-buffers of the handle's
+// workspace, growing it first if needed (growth synchronises the device).
+struct WsReq {
+    size_t off = 0;
+    size_t add(size_t bytes) {
+        size_t o = off;
+        off += (bytes + 255) & ~size_t(255);
+        return o;
+    }
+};
+int ws_reserve(ad_handle h, size_t bytes);
+
+// Records HIP events around the launches made in its lifetime when the
+// handle's timing is on (no-op otherwise).
+class TimedScope {
+   public:
+    TimedScope(ad_handle h, const char* label, hipStream_t s);
+    ~TimedScope();
+
+   private:
+    ad_handle h_;
+    const char* label_;
+    hipStream_t s_;
+    hipEvent_t a_ = nullptr;
+};
+
+// ---- relax.hip
+int launch_tv_init(int dtype, int64_t row0, int64_t nrows, int K, uint64_t seed, void* X,
+                   hipStream_t s);
+int launch_jacobi(int dtype, int K, const ad_csr* A, const void* Xin, void* Xout, double omega,
+                  unsigned* status, const LaunchCfg& cfg, hipStream_t s);
+// Builds the colour-sorted row list: rowlist[n] and seg[ncolors + 2]
+// (seg[c]..seg[c+1] are the rows of colour c; seg[ncolors]..seg[ncolors+1]
+// the rows with an invalid colour).  counts: (ncolors+1) * nblocks ints.
+int launch_color_partition(int n, const int32_t* color, int ncolors, int32_t* rowlist,
+                           int32_t* seg, int32_t* counts, int nblocks, unsigned* status,
+                           hipStream_t s);
+int color_partition_blocks(int n);
+int launch_gs_phase(int dtype, int K, const ad_csr* A, const int32_t* color, int c, int ncolors,
+                    const int32_t* rowlist, const int32_t* seg, const void* Xold, void* Xnew,
+                    unsigned* status, const LaunchCfg& cfg, hipStream_t s);
+
+// ---- distance.hip
+int launch_algdist(int dtype, int K, const ad_csr* A, const void* X, const double* w, int target,
+                   void* mu, double* p, double theta, const uint8_t* fmask, uint8_t* strong,
+                   int32_t* nstrong, unsigned* status, const LaunchCfg& cfg, hipStream_t s);
+int launch_strength(int dtype, const ad_csr* A, const void* mu, double theta,
+                    const uint8_t* fmask, uint8_t* strong, int32_t* nstrong, hipStream_t s);
+int launch_csr_validate(const ad_csr* A, unsigned* status, hipStream_t s);
+
+// ---- interp.hip
+int launch_ls_interp(int dtype, int K, int caliber, const ad_csr* A, const void* X,
+                     const double* w, const uint8_t* cf, const void* mu, int target,
+                     int32_t* P_col, double* P_val, double* ls_val, int32_t* row_status,
+                     double* block_sums, double* ls_sum, unsigned* status,
+                     const LaunchCfg& cfg, hipStream_t s);
+int ls_interp_blocks(int dtype, int K, int n, const LaunchCfg& cfg);
+
+inline int grid_for_tiles(int64_t ntiles) {
+    int64_t per = (ntiles + 7) / 8;
+    return (int)(8 * (per > 0 ? per : 1));
+}
+
+}  // namespace ad
+
+#define AD_HIP(call)                                       \
+    do {                                                   \
+        hipError_t e_ = (call);                            \
+        if (e_ != hipSuccess) return AD_EDEVICE;           \
+    } while (0)

@@ -1,0 +1,377 @@
+// relax.hip -- test-vector start and relaxation of A x = 0 over a K-wide
+// panel (Sec. 3: test vectors are relaxed solutions of the homogeneous
+// system from distinct starts; Sec. 5.2 relaxes them by Gauss-Seidel).
+//
+// Both relaxations are a CSR row-block SpMM: each row group (LPR lanes, one
+// 16-byte fragment per lane) walks its row's nonzeros, gathers the
+// neighbour's panel row and accumulates a_ij x_j in the panel type.  The
+// matrix is streamed once per sweep; neighbour panel rows are re-read
+// through L2 (the tile mapping keeps a row range on one XCD).
+#include "device.h"
+#include "internal.h"
+
+namespace ad {
+
+// ---------------------------------------------------------------- start
+template <typename T>
+__global__ __launch_bounds__(kBlock) void tv_init_kernel(int64_t total, int64_t c0, uint64_t seed,
+                                                         T* __restrict__ X) {
+    constexpr int E = 16 / sizeof(T);
+    const int64_t base = ((int64_t)blockIdx.x * kBlock + threadIdx.x) * E;
+    if (base >= total) return;
+    Frag<T, E> f;
+#pragma unroll
+    for (int q = 0; q < E; ++q)
+        f.v[q] = (T)uniform_pm1(splitmix64_at(seed, (uint64_t)(c0 + base + q)));
+    if (base + E <= total) {
+        store_frag<T, E>(X + base, f);
+    } else {
+        for (int q = 0; q < E && base + q < total; ++q) X[base + q] = f.v[q];
+    }
+}
+
+int launch_tv_init(int dtype, int64_t row0, int64_t nrows, int K, uint64_t seed, void* X,
+                   hipStream_t s) {
+    const int64_t total = nrows * K;
+    if (total == 0) return AD_OK;
+    const int E = dtype == AD_F32 ? 4 : 2;
+    const int64_t threads = (total + E - 1) / E;
+    const int64_t blocks = (threads + kBlock - 1) / kBlock;
+    if (dtype == AD_F32)
+        tv_init_kernel<float><<<dim3((unsigned)blocks), dim3(kBlock), 0, s>>>(total, row0 * K, seed,
+                                                                              (float*)X);
+    else
+        tv_init_kernel<double><<<dim3((unsigned)blocks), dim3(kBlock), 0, s>>>(total, row0 * K, seed,
+                                                                               (double*)X);
+    AD_HIP(hipGetLastError());
+    return AD_OK;
+}
+
+// ---------------------------------------------------------------- row SpMM core
+// y = sum_e a_e x_{col e} over the row's entries, in CSR order (FMA per term);
+// also returns the diagonal value and the row's own fragment.
+// PICK(j) chooses which panel a neighbour is read from.
+template <typename T, int K, typename Pick>
+__device__ __forceinline__ void row_spmm(int i, int e0, int e1, const int* __restrict__ ci,
+                                         const T* __restrict__ av, int l, Pick pick,
+                                         T (&y)[Shape<T, K>::V], T& d,
+                                         Frag<T, Shape<T, K>::V>& xi) {
+    constexpr int V = Shape<T, K>::V;
+#pragma unroll
+    for (int q = 0; q < V; ++q) y[q] = T(0);
+    d = T(0);
+    int e = e0;
+    // four independent gathers in flight per step
+    for (; e + 4 <= e1; e += 4) {
+        int j[4];
+        T a[4];
+        Frag<T, V> x[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            j[u] = ci[e + u];
+            a[u] = av[e + u];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) x[u] = load_frag<T, V>(pick(j[u]) + (size_t)j[u] * K + l * V);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+#pragma unroll
+            for (int q = 0; q < V; ++q) y[q] = fma(a[u], x[u].v[q], y[q]);
+            if (j[u] == i) {
+                d = a[u];
+                xi = x[u];
+            }
+        }
+    }
+    for (; e < e1; ++e) {
+        const int j = ci[e];
+        const T a = av[e];
+        Frag<T, V> x = load_frag<T, V>(pick(j) + (size_t)j * K + l * V);
+#pragma unroll
+        for (int q = 0; q < V; ++q) y[q] = fma(a, x.v[q], y[q]);
+        if (j == i) {
+            d = a;
+            xi = x;
+        }
+    }
+}
+
+// ---------------------------------------------------------------- Jacobi
+// x_new = x - omega * (A x) / a_ii  (row held fixed if a_ii == 0)
+template <typename T, int K>
+__global__ __launch_bounds__(kBlock) void jacobi_kernel(int n, const int* __restrict__ rp,
+                                                        const int* __restrict__ ci,
+                                                        const T* __restrict__ av,
+                                                        const T* __restrict__ Xin,
+                                                        T* __restrict__ Xout, T omega, int iter,
+                                                        int xcd, unsigned* status) {
+    using S = Shape<T, K>;
+    constexpr int V = S::V;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int g = lane / S::LPR, l = lane % S::LPR;
+    const int wv = threadIdx.x / kWave;
+    const int64_t rows_per_tile = (int64_t)S::RPB * iter;
+    const int64_t ntiles = (n + rows_per_tile - 1) / rows_per_tile;
+    const int64_t tile = xcd ? xcd_tile(ntiles) : (int64_t)blockIdx.x;
+    if (tile < 0 || tile >= ntiles) return;
+    for (int it = 0; it < iter; ++it) {
+        const int64_t i64 = tile * rows_per_tile + (int64_t)it * S::RPB + wv * S::RPW + g;
+        if (i64 >= n) break;
+        const int i = (int)i64;
+        T y[V], d;
+        Frag<T, V> xi;
+        row_spmm<T, K>(i, rp[i], rp[i + 1], ci, av, l, [&](int) { return Xin; }, y, d, xi);
+        Frag<T, V> out;
+        if (d == T(0)) {
+            out = load_frag<T, V>(Xin + (size_t)i * K + l * V);
+            if (l == 0) flag(status, AD_STAT_ZERO_DIAG);
+        } else {
+#pragma unroll
+            for (int q = 0; q < V; ++q) out.v[q] = xi.v[q] - omega * y[q] / d;
+        }
+        store_frag<T, V>(Xout + (size_t)i * K + l * V, out);
+    }
+}
+
+template <typename T, int K>
+static void jacobi_go(const ad_csr* A, const void* Xin, void* Xout, double omega, unsigned* st,
+                      const LaunchCfg& cfg, hipStream_t s) {
+    using S = Shape<T, K>;
+    const int64_t rpt = (int64_t)S::RPB * cfg.iter;
+    const int64_t ntiles = (A->n + rpt - 1) / rpt;
+    const int grid = cfg.xcd_map ? grid_for_tiles(ntiles) : (int)ntiles;
+    jacobi_kernel<T, K><<<dim3(grid), dim3(kBlock), 0, s>>>(
+        A->n, A->row_ptr, A->col, (const T*)A->val, (const T*)Xin, (T*)Xout, (T)omega, cfg.iter,
+        cfg.xcd_map, st);
+}
+
+#define AD_K_SWITCH(T, FN, ...)                         \
+    switch (K) {                                        \
+        case 2: FN<T, 2>(__VA_ARGS__); break;           \
+        case 4: FN<T, 4>(__VA_ARGS__); break;           \
+        case 8: FN<T, 8>(__VA_ARGS__); break;           \
+        case 16: FN<T, 16>(__VA_ARGS__); break;         \
+        case 32: FN<T, 32>(__VA_ARGS__); break;         \
+        case 64: FN<T, 64>(__VA_ARGS__); break;         \
+        default: return AD_EINVAL;                      \
+    }
+
+int launch_jacobi(int dtype, int K, const ad_csr* A, const void* Xin, void* Xout, double omega,
+                  unsigned* status, const LaunchCfg& cfg, hipStream_t s) {
+    if (A->n == 0) return AD_OK;
+    if (dtype == AD_F32) {
+        AD_K_SWITCH(float, jacobi_go, A, Xin, Xout, omega, status, cfg, s);
+    } else {
+        AD_K_SWITCH(double, jacobi_go, A, Xin, Xout, omega, status, cfg, s);
+    }
+    AD_HIP(hipGetLastError());
+    return AD_OK;
+}
+
+// ---------------------------------------------------------------- colour partition
+// Stable partition of the rows by colour: rows of colour 0 first (in index
+// order), then colour 1, ..., then rows with an invalid colour.  Three
+// launches: per-block class counts, one exclusive scan of the class-major
+// count table, per-block scatter with wave ballots for stable ranks.
+constexpr int kPartRows = 1024;  // rows per partition block (4 per thread)
+constexpr int kMaxColors = 64;
+
+int color_partition_blocks(int n) { return (n + kPartRows - 1) / kPartRows; }
+
+__device__ __forceinline__ int color_class(int c, int nc) {
+    return ((unsigned)c < (unsigned)nc) ? c : nc;
+}
+
+__global__ __launch_bounds__(kBlock) void color_count_kernel(int n, const int* __restrict__ color,
+                                                             int nc, int* __restrict__ counts,
+                                                             int nblocks) {
+    __shared__ int cnt[kMaxColors + 1];
+    for (int q = threadIdx.x; q <= nc; q += kBlock) cnt[q] = 0;
+    __syncthreads();
+    const int base = blockIdx.x * kPartRows;
+    for (int k = 0; k < kPartRows / kBlock; ++k) {
+        const int r = base + k * kBlock + threadIdx.x;
+        if (r < n) atomicAdd(&cnt[color_class(color[r], nc)], 1);
+    }
+    __syncthreads();
+    for (int q = threadIdx.x; q <= nc; q += kBlock) counts[(size_t)q * nblocks + blockIdx.x] = cnt[q];
+}
+
+// Exclusive scan of counts[0 .. m) in place (single workgroup of 1024
+// threads), plus seg[q] = scanned value at q * nblocks, seg[nc + 1] = n.
+__global__ __launch_bounds__(1024) void scan_counts_kernel(int* __restrict__ counts, int m,
+                                                           int nblocks, int nc, int n,
+                                                           int* __restrict__ seg) {
+    __shared__ int part[1024];
+    const int t = threadIdx.x;
+    const int chunk = (m + 1023) / 1024;
+    const int b = t * chunk, e = min(m, b + chunk);
+    int s = 0;
+    for (int q = b; q < e; ++q) s += counts[q];
+    part[t] = s;
+    __syncthreads();
+    // Hillis-Steele inclusive scan over the 1024 chunk sums
+    for (int o = 1; o < 1024; o <<= 1) {
+        int v = (t >= o) ? part[t - o] : 0;
+        __syncthreads();
+        part[t] += v;
+        __syncthreads();
+    }
+    int run = (t > 0) ? part[t - 1] : 0;
+    for (int q = b; q < e; ++q) {
+        int c = counts[q];
+        counts[q] = run;
+        run += c;
+    }
+    __syncthreads();
+    for (int q = t; q <= nc; q += 1024) seg[q] = counts[(size_t)q * nblocks];
+    if (t == 0) seg[nc + 1] = n;
+}
+
+__global__ __launch_bounds__(kBlock) void color_scatter_kernel(int n, const int* __restrict__ color,
+                                                               int nc,
+                                                               const int* __restrict__ offsets,
+                                                               int nblocks,
+                                                               int* __restrict__ rowlist,
+                                                               unsigned* status) {
+    __shared__ int base[kMaxColors + 1];
+    __shared__ int wcnt[kWavesPerBlock][kMaxColors + 1];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    for (int q = threadIdx.x; q <= nc; q += kBlock) base[q] = offsets[(size_t)q * nblocks + blockIdx.x];
+    __syncthreads();
+    const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    bool bad = false;
+    for (int k = 0; k < kPartRows / kBlock; ++k) {
+        const int r = blockIdx.x * kPartRows + k * kBlock + threadIdx.x;
+        const bool valid = r < n;
+        const int c = valid ? color_class(color[r], nc) : -1;
+        bad |= (valid && c == nc);
+        int rank = 0;
+        for (int q = 0; q <= nc; ++q) {
+            const uint64_t m = __ballot(c == q);
+            if (lane == 0) wcnt[wv][q] = __popcll(m);
+            if (c == q) rank = __popcll(m & lt);
+        }
+        __syncthreads();
+        if (valid) {
+            int pos = base[c] + rank;
+            for (int w = 0; w < wv; ++w) pos += wcnt[w][c];
+            rowlist[pos] = r;
+        }
+        __syncthreads();
+        for (int q = threadIdx.x; q <= nc; q += kBlock) {
+            int add = 0;
+            for (int w = 0; w < kWavesPerBlock; ++w) add += wcnt[w][q];
+            base[q] += add;
+        }
+        __syncthreads();
+    }
+    if (bad) flag(status, AD_STAT_BAD_COLOR);
+}
+
+int launch_color_partition(int n, const int32_t* color, int ncolors, int32_t* rowlist,
+                           int32_t* seg, int32_t* counts, int nblocks, unsigned* status,
+                           hipStream_t s) {
+    if (n == 0) {
+        AD_HIP(hipMemsetAsync(seg, 0, sizeof(int32_t) * (ncolors + 2), s));
+        return AD_OK;
+    }
+    color_count_kernel<<<dim3(nblocks), dim3(kBlock), 0, s>>>(n, color, ncolors, counts, nblocks);
+    scan_counts_kernel<<<dim3(1), dim3(1024), 0, s>>>(counts, (ncolors + 1) * nblocks, nblocks,
+                                                      ncolors, n, seg);
+    color_scatter_kernel<<<dim3(nblocks), dim3(kBlock), 0, s>>>(n, color, ncolors, counts,
+                                                                nblocks, rowlist, status);
+    AD_HIP(hipGetLastError());
+    return AD_OK;
+}
+
+// ---------------------------------------------------------------- colour phase
+// Rows of colour c (list segment seg[c]..seg[c+1]):
+//   x_new_i = x_i - (A z)_i / a_ii,  z_j = Xnew_j if colour(j) < c else Xold_j.
+// The phase of colour 0 also copies rows with an invalid colour (held fixed).
+template <typename T, int K, bool FIRST>
+__global__ __launch_bounds__(kBlock) void gs_phase_kernel(
+    const int* __restrict__ rp, const int* __restrict__ ci, const T* __restrict__ av,
+    const int* __restrict__ color, int c, int nc, const int* __restrict__ rowlist,
+    const int* __restrict__ seg, const T* __restrict__ Xold, T* __restrict__ Xnew, int iter,
+    int xcd, unsigned* status) {
+    using S = Shape<T, K>;
+    constexpr int V = S::V;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int g = lane / S::LPR, l = lane % S::LPR;
+    const int wv = threadIdx.x / kWave;
+    const int b0 = seg[c], b1 = seg[c + 1];
+    const int64_t rows_per_tile = (int64_t)S::RPB * iter;
+    const int64_t ntiles = (b1 - b0 + rows_per_tile - 1) / rows_per_tile;
+    const int64_t tile = xcd ? xcd_tile(ntiles) : (int64_t)blockIdx.x;
+    if (tile >= 0 && tile < ntiles) {
+        for (int it = 0; it < iter; ++it) {
+            const int64_t p = b0 + tile * rows_per_tile + (int64_t)it * S::RPB + wv * S::RPW + g;
+            if (p >= b1) break;
+            const int i = rowlist[p];
+            T y[V], d;
+            Frag<T, V> xi;
+            if (FIRST) {
+                row_spmm<T, K>(i, rp[i], rp[i + 1], ci, av, l, [&](int) { return Xold; }, y, d, xi);
+            } else {
+                row_spmm<T, K>(
+                    i, rp[i], rp[i + 1], ci, av, l,
+                    [&](int j) { return ((unsigned)color[j] < (unsigned)c) ? (const T*)Xnew : Xold; },
+                    y, d, xi);
+            }
+            Frag<T, V> out;
+            if (d == T(0)) {
+                out = load_frag<T, V>(Xold + (size_t)i * K + l * V);
+                if (l == 0) flag(status, AD_STAT_ZERO_DIAG);
+            } else {
+#pragma unroll
+                for (int q = 0; q < V; ++q) out.v[q] = xi.v[q] - y[q] / d;
+            }
+            store_frag<T, V>(Xnew + (size_t)i * K + l * V, out);
+        }
+    }
+    if (FIRST) {  // rows with an invalid colour are held fixed
+        const int q0 = seg[nc], q1 = seg[nc + 1];
+        const int64_t stride = (int64_t)gridDim.x * S::RPB;
+        for (int64_t p = q0 + (int64_t)blockIdx.x * S::RPB + wv * S::RPW + g; p < q1; p += stride) {
+            const int i = rowlist[p];
+            store_frag<T, V>(Xnew + (size_t)i * K + l * V,
+                             load_frag<T, V>(Xold + (size_t)i * K + l * V));
+        }
+    }
+}
+
+template <typename T, int K>
+static void gs_go(const ad_csr* A, const int32_t* color, int c, int nc, const int32_t* rowlist,
+                  const int32_t* seg, const void* Xold, void* Xnew, unsigned* st,
+                  const LaunchCfg& cfg, hipStream_t s) {
+    using S = Shape<T, K>;
+    // the per-colour row count is known only on the device: size the grid
+    // for all n rows; workgroups beyond the colour's tiles exit at once.
+    const int64_t rpt = (int64_t)S::RPB * cfg.iter;
+    const int64_t ntiles = (A->n + rpt - 1) / rpt;
+    const int grid = cfg.xcd_map ? grid_for_tiles(ntiles) : (int)ntiles;
+    if (c == 0)
+        gs_phase_kernel<T, K, true><<<dim3(grid), dim3(kBlock), 0, s>>>(
+            A->row_ptr, A->col, (const T*)A->val, color, c, nc, rowlist, seg, (const T*)Xold,
+            (T*)Xnew, cfg.iter, cfg.xcd_map, st);
+    else
+        gs_phase_kernel<T, K, false><<<dim3(grid), dim3(kBlock), 0, s>>>(
+            A->row_ptr, A->col, (const T*)A->val, color, c, nc, rowlist, seg, (const T*)Xold,
+            (T*)Xnew, cfg.iter, cfg.xcd_map, st);
+}
+
+int launch_gs_phase(int dtype, int K, const ad_csr* A, const int32_t* color, int c, int ncolors,
+                    const int32_t* rowlist, const int32_t* seg, const void* Xold, void* Xnew,
+                    unsigned* status, const LaunchCfg& cfg, hipStream_t s) {
+    if (A->n == 0) return AD_OK;
+    if (dtype == AD_F32) {
+        AD_K_SWITCH(float, gs_go, A, color, c, ncolors, rowlist, seg, Xold, Xnew, status, cfg, s);
+    } else {
+        AD_K_SWITCH(double, gs_go, A, color, c, ncolors, rowlist, seg, Xold, Xnew, status, cfg, s);
+    }
+    AD_HIP(hipGetLastError());
+    return AD_OK;
+}
+
+}  // namespace ad

@@ -1,0 +1,164 @@
+"""Parity at the full workload sizes, in the launch configuration bench.py
+times: the 2048^2 rotated anisotropic 9-point operator (K = 16, 5 red-black
+colour-phase GS sweeps) and the 160^3 log-normal 7-point operator (K = 32,
+4 Jacobi sweeps, omega = 0.8).
+
+FP64 path: every output against the oracle run on the whole workload.
+FP32 path: each step against the oracle fed the same FP32 inputs (promoted
+exactly) -- the last sweep and the LS rows on sampled rows, the distances on
+sampled rows, the strength graph on every row -- and the FP32 chain against
+the all-FP64 chain as a reported error distribution."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1106_5990_amd import workloads as W
+from gpu_common import (check_ls, check_mu, dev_csr, lib, row_abs_bound, saa_per_edge, say,
+                        to_np)
+
+pytestmark = pytest.mark.gpu
+
+_cache = {}
+
+
+def wl(i):
+    if i not in _cache:
+        say("generating workload %d" % i)
+        _cache[i] = W.workload(i)
+    return _cache[i]
+
+
+def run_setup(w, Ad, dtype, sweeps):
+    ad = lib()
+    color = None if w.color is None else torch.as_tensor(w.color, device="cuda")
+    return ad.setup_testvectors(Ad, w.K, seed=w.tv_seed, relax=w.relax, sweeps=sweeps,
+                                omega=w.omega, color=color, ncolors=w.ncolors)
+
+
+def sample_rows(n, m=2048, seed=0):
+    rng = np.random.default_rng(seed)
+    rows = np.unique(np.concatenate([rng.choice(n, m, replace=False), [0, 1, n - 2, n - 1]]))
+    return rows.astype(np.int32)
+
+
+def packed(A, vec, rows):
+    rp = A.row_ptr.astype(np.int64)
+    return np.concatenate([vec[rp[r]:rp[r + 1]] for r in rows])
+
+
+@pytest.mark.parametrize("i", [2, 3])
+def test_fullsize_fp32_steps(i):
+    ad = lib()
+    w = wl(i)
+    A = w.A
+    say("full-size FP32 steps, workload %s" % w.name)
+    A32 = W.CSR(A.n, A.row_ptr, A.col, A.val.astype(np.float32).astype(np.float64))
+    Ad = dev_csr(A, torch.float32)
+    ad.status(clear=True)
+    Xp = to_np(run_setup(w, Ad, torch.float32, w.sweeps - 1)).astype(np.float64)
+    X = run_setup(w, Ad, torch.float32, w.sweeps)
+    x = to_np(X).astype(np.float64)
+    rows = sample_rows(A.n)
+    # last sweep on sampled rows
+    if w.relax == "gs":
+        want = oracle.color_gs_rows(A32, w.color, w.ncolors, Xp, x, rows)
+        Z = np.where((w.color == 0)[:, None], x, Xp)
+        bound = np.maximum(row_abs_bound(A32, Z, Xp, 1.0, rows=rows),
+                           row_abs_bound(A32, Xp, Xp, 1.0, rows=rows))
+    else:
+        want = oracle.jacobi_rows(A32, Xp, w.omega, rows)
+        bound = row_abs_bound(A32, Xp, Xp, w.omega, rows=rows)
+    err = np.abs(x[rows] - want)
+    say("  last sweep: max err/bound %.3g" % np.max(err / bound))
+    assert np.all(err <= bound)
+    # distances (+ fused strength) as bench runs them
+    mu, strong, ns = ad.algebraic_distance(Ad, X, fuse=True, theta=w.theta)
+    mu_h = to_np(mu).astype(np.float64)
+    mu_ref = oracle.algdist(A32, x, rows=rows)
+    saa = (x[rows] ** 2).sum(1)
+    saa_e = np.repeat(saa, np.diff(A.row_ptr.astype(np.int64))[rows])
+    check_mu(packed(A, mu_h, rows), mu_ref, saa_e, torch.float32, "sampled rows")
+    s_ref, ns_ref = oracle.strength(A, mu_h, w.theta)
+    assert np.array_equal(to_np(strong), s_ref)
+    assert np.array_equal(to_np(ns), ns_ref)
+    # LS rows on the sampled rows
+    cf = torch.as_tensor(w.cf, device="cuda")
+    Pc, Pv, ls, st, tot = ad.ls_interp(Ad, X, cf, mu, w.caliber, want_sum=True)
+    ref = oracle.ls_interp(A32, x, None, w.cf, mu_h, w.caliber, rows=rows)
+    got = tuple(to_np(t)[rows] for t in (Pc, Pv, ls, st))
+    check_ls(got, ref, torch.float32, (x[rows] ** 2).sum(1))
+    lsn = to_np(ls)
+    assert abs(float(tot) - lsn[w.cf == 0].sum()) <= 1e-12 * lsn.sum()
+    assert ad.status(clear=True) == 0
+
+
+@pytest.mark.parametrize("i", [2, 3])
+def test_fullsize_fp64_whole_path(i):
+    ad = lib()
+    w = wl(i)
+    A = w.A
+    say("full-size FP64 whole path, workload %s" % w.name)
+    Ad = dev_csr(A, torch.float64)
+    X = run_setup(w, Ad, torch.float64, w.sweeps)
+    X0 = oracle.tv_init(A.n, w.K, w.tv_seed)
+    if w.relax == "gs":
+        xr, _ = oracle.color_gs(A, X0, w.color, w.ncolors, w.sweeps)
+    else:
+        xr, _ = oracle.jacobi(A, X0, w.omega, w.sweeps)
+    x = to_np(X)
+    del X0
+    rel = np.max(np.abs(x - xr)) / np.max(np.abs(xr))
+    say("  relaxation max rel err %.3g" % rel)
+    assert rel <= 1e-12
+    mu, strong, ns = ad.algebraic_distance(Ad, X, fuse=True, theta=w.theta)
+    mu_h = to_np(mu)
+    mu_ref = oracle.algdist(A, x)
+    check_mu(mu_h, mu_ref, saa_per_edge(A, x), torch.float64, "all edges")
+    s_ref, ns_ref = oracle.strength(A, mu_h, w.theta)
+    assert np.array_equal(to_np(strong), s_ref) and np.array_equal(to_np(ns), ns_ref)
+    cf = torch.as_tensor(w.cf, device="cuda")
+    got = ad.ls_interp(Ad, X, cf, mu, w.caliber)
+    ref = oracle.ls_interp(A, x, None, w.cf, mu_h, w.caliber)
+    check_ls(tuple(to_np(t) for t in got), ref, torch.float64, (x * x).sum(1))
+
+
+def test_fullsize_fp32_chain_against_fp64_chain():
+    """The FP32 chain end to end against the all-FP64 chain (workload 2):
+    the distance error distribution and the strong-mask flips are reported;
+    a flip is allowed only for an edge whose threshold margin is inside
+    twice that edge's measured distance error."""
+    ad = lib()
+    w = wl(2)
+    A = w.A
+    say("FP32 chain vs FP64 chain, workload %s" % w.name)
+    out = {}
+    for dt in (torch.float32, torch.float64):
+        Ad = dev_csr(A, dt)
+        X = run_setup(w, Ad, dt, w.sweeps)
+        mu, strong, ns = ad.algebraic_distance(Ad, X, fuse=True, theta=w.theta)
+        out[dt] = (to_np(mu).astype(np.float64), to_np(strong))
+        del X, mu
+    m32, s32 = out[torch.float32]
+    m64, s64 = out[torch.float64]
+    rid = A.row_ids()
+    off = A.col != rid
+    rel = np.abs(m32 - m64)[off] / np.maximum(m64[off], 1e-300)
+    say("  mu rel err: max %.3g p99 %.3g p50 %.3g; > 1e-4: %d of %d"
+        % (rel.max(), np.quantile(rel, 0.99), np.median(rel), int((rel > 1e-4).sum()), rel.size))
+    # row minima of the FP64 chain give each edge's threshold margin
+    mmin = np.full(A.n, np.inf)
+    np.minimum.at(mmin, rid[off], m64[off])
+    margin = np.abs(w.theta * m64 / mmin[rid] - 1.0)
+    flips = (s32 != s64)
+    bands = [(1e-6, int((flips & (margin <= 1e-6)).sum())),
+             (1e-5, int((flips & (margin <= 1e-5)).sum())),
+             (1e-4, int((flips & (margin <= 1e-4)).sum()))]
+    say("  mask flips: %d total; within margin 1e-6/1e-5/1e-4: %s" % (int(flips.sum()), bands))
+    # a flip needs the threshold inside the combined error of mu_ij and m_i
+    err = np.abs(m32 - m64) / np.maximum(m64, 1e-300)
+    row_err = np.zeros(A.n)
+    np.maximum.at(row_err, rid[off], err[off])
+    allowed = margin <= 2.0 * (err + row_err[rid]) + 1e-6
+    assert np.all(allowed[flips]), "mask flips away from the threshold band: %d" % int(
+        (flips & ~allowed).sum())
