@@ -41,6 +41,9 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=None, help="grid side of the oracle sample")
     ap.add_argument("--graph", action="store_true", help="replay the step as a captured HIP graph")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run one 1 GiB device-to-device copy (a kernel of known traffic "
+                         "for scaling hardware byte counters)")
     return ap.parse_args()
 
 
@@ -210,6 +213,12 @@ def main():
         del b, step
         torch.cuda.empty_cache()
 
+    if args.copy_calibration:
+        src = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     main_leg = res["f32"]
     kern = main_leg["kernels"]
     ms = main_leg["ms"]

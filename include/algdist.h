@@ -113,6 +113,21 @@ int algdist_timing(ad_handle h, int enable);
  * the next call on the handle. */
 const char *algdist_timing_report(ad_handle h);
 
+/* Launch shape of one kernel family, for a (dtype, K, stored-entries-per-row
+ * bucket) key.  kernel: "jacobi", "gs_phase", "algdist" or "ls_interp".
+ * bucket: 0 (< 8 entries per row), 1 (< 16), 2 (< 32), 3 (>= 32), or -1 for
+ * all four.  lanes_per_row: lanes sharing one panel row (0 = default; must
+ * divide K with K / lanes_per_row entries per lane fitting 64 bytes and
+ * being at least 8 bytes).  rows_per_lane: consecutive row steps per
+ * workgroup tile (>= 1; ignored by ls_interp, which compacts the F rows of
+ * fixed 128-row windows).
+ * xcd_map: 1 maps contiguous row tiles to each XCD, 0 uses the plain block
+ * order.  The kernels' results do not depend on the shape except for the
+ * order of the K-reductions inside algdist (all orders stay within the
+ * parity bars).  Returns AD_EINVAL for a shape the kernel does not support. */
+int algdist_set_launch(ad_handle h, const char *kernel, int32_t dtype, int32_t K, int32_t bucket,
+                       int32_t lanes_per_row, int32_t rows_per_lane, int32_t xcd_map);
+
 /* Check the CSR invariants listed above on the device; violations set
  * AD_STAT_CSR_* bits.  Not needed on the hot path (no other call reads
  * more than it is given, but their results are defined only for valid

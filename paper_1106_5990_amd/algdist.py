@@ -60,6 +60,7 @@ _SIGS = {
     "algdist_last_error": (C.c_char_p, [_P]),
     "algdist_timing": (_i32, [_P, C.c_int]),
     "algdist_timing_report": (C.c_char_p, [_P]),
+    "algdist_set_launch": (_i32, [_P, C.c_char_p, _i32, _i32, _i32, _i32, _i32, _i32]),
     "csr_validate": (_i32, [_P, _CSRP, _P]),
     "setup_testvectors": (_i32, [_P, _CSRP, _i32, _u64, _P, _i32, _i32, _f64, _P, _i32, _P, _P,
                                  _i32, _P]),
@@ -170,6 +171,16 @@ def timing_report(device: Optional[int] = None) -> dict:
         lab, cnt, ms = line.split()
         out[lab] = (int(cnt), float(ms))
     return out
+
+
+def set_launch(kernel: str, dtype: torch.dtype, K: int, lanes_per_row: int = 0,
+               rows_per_lane: int = 1, xcd_map: bool = True, bucket: int = -1,
+               device: Optional[int] = None) -> None:
+    """Force the launch shape of one kernel family (see algdist_set_launch)."""
+    h = handle(device)
+    rc = _lib.algdist_set_launch(h, kernel.encode(), _dtype_code(dtype), K, bucket, lanes_per_row,
+                                 rows_per_lane, int(xcd_map))
+    _check(rc, h, "algdist_set_launch")
 
 
 def csr_validate(A: Csr, stream=None) -> None:

@@ -73,6 +73,25 @@ TimedScope::~TimedScope() {
     if (hipEventRecord(b, s_) == hipSuccess) h_->timed.push_back({label_, a_, b});
 }
 
+int k_slot(int K) {
+    for (int q = 1; q < kNumKSlots; ++q)
+        if (K == (1 << q)) return q;
+    return -1;
+}
+
+int nnz_bucket(int64_t nnz, int n) {
+    const double r = n > 0 ? (double)nnz / n : 0.0;
+    return r < 8 ? 0 : r < 16 ? 1 : r < 32 ? 2 : 3;
+}
+
+LaunchCfg cfg_for(ad_handle h, int kernel, int dtype, int K, const ad_csr* A) {
+    const int ks = k_slot(K);
+    const int b = nnz_bucket(A->nnz, A->n);
+    if (ks >= 0 && (dtype == AD_F32 || dtype == AD_F64) && h->has_tuned[kernel][dtype][ks][b])
+        return h->tuned[kernel][dtype][ks][b];
+    return LaunchCfg();
+}
+
 int ws_reserve(ad_handle h, size_t bytes) {
     if (bytes <= h->ws_bytes) return AD_OK;
     // earlier calls may still use the old buffer
@@ -182,6 +201,39 @@ const char* algdist_timing_report(ad_handle h) {
     return h->report.c_str();
 }
 
+static bool lpr_valid(int dtype, int K, int L) {
+    return dtype == AD_F32 ? lpr_ok<float>(K, L) : lpr_ok<double>(K, L);
+}
+
+int algdist_set_launch(ad_handle h, const char* kernel, int32_t dtype, int32_t K, int32_t bucket,
+                       int32_t lanes_per_row, int32_t rows_per_lane, int32_t xcd_map) {
+    if (!h || !kernel) return AD_EINVAL;
+    h->err.clear();
+    int kn = -1;
+    if (!strcmp(kernel, "jacobi")) kn = KN_JACOBI;
+    else if (!strcmp(kernel, "gs_phase")) kn = KN_GS;
+    else if (!strcmp(kernel, "algdist")) kn = KN_ALGDIST;
+    else if (!strcmp(kernel, "ls_interp")) kn = KN_LS;
+    if (kn < 0) return fail(h, AD_EINVAL, "unknown kernel family '%s'", kernel);
+    if (dtype != AD_F32 && dtype != AD_F64) return fail(h, AD_EDTYPE, "dtype %d", dtype);
+    const int ks = k_slot(K);
+    if (ks < 0) return fail(h, AD_EINVAL, "K = %d", K);
+    if (bucket < -1 || bucket >= kNumBuckets) return fail(h, AD_EINVAL, "bucket %d", bucket);
+    if (rows_per_lane < 1 || rows_per_lane > 64) return fail(h, AD_EINVAL, "rows_per_lane %d", rows_per_lane);
+    if (lanes_per_row != 0 && !lpr_valid(dtype, K, lanes_per_row))
+        return fail(h, AD_EINVAL, "lanes_per_row %d unsupported for K = %d", lanes_per_row, K);
+    LaunchCfg c;
+    c.lpr = lanes_per_row;
+    c.iter = kn == KN_LS ? 1 : rows_per_lane;
+    c.xcd_map = xcd_map ? 1 : 0;
+    for (int b = 0; b < kNumBuckets; ++b)
+        if (bucket < 0 || bucket == b) {
+            h->tuned[kn][dtype][ks][b] = c;
+            h->has_tuned[kn][dtype][ks][b] = true;
+        }
+    return AD_OK;
+}
+
 int csr_validate(ad_handle h, const ad_csr* A, void* stream) {
     if (!h) return AD_EINVAL;
     h->err.clear();
@@ -265,7 +317,7 @@ int setup_testvectors(ad_handle h, const ad_csr* A, int32_t K, uint64_t seed, co
                                     nblk, h->status, s);
         if (rc) return fail(h, rc, "colour partition launch");
     }
-    LaunchCfg cfg;
+    const LaunchCfg cfg = cfg_for(h, relax == AD_JACOBI ? KN_JACOBI : KN_GS, dt, K, A);
     for (int q = 0; q < ns; ++q) {
         if (relax == AD_JACOBI) {
             TimedScope ts(h, "jacobi", s);
@@ -298,7 +350,7 @@ int algebraic_distance(ad_handle h, const ad_csr* A, int32_t K, const void* X, c
         return fail(h, AD_EINVAL, "theta = %g outside (0, 1)", theta);
     if (A->n == 0) return AD_OK;
     AD_HIP(hipSetDevice(h->device));
-    LaunchCfg cfg;
+    const LaunchCfg cfg = cfg_for(h, KN_ALGDIST, A->dtype, K, A);
     TimedScope ts(h, "algdist", (hipStream_t)stream);
     rc = launch_algdist(A->dtype, K, A, X, w, target, mu, p, theta, fmask, strong, nstrong,
                         h->status, cfg, (hipStream_t)stream);
@@ -337,7 +389,7 @@ int ls_interp(ad_handle h, const ad_csr* A, int32_t K, const void* X, const doub
     if (A->n > 0 && (!cf || !mu || !P_col || !P_val || !ls_val || !row_status))
         return fail(h, AD_EINVAL, "null output or input array");
     AD_HIP(hipSetDevice(h->device));
-    LaunchCfg cfg;
+    const LaunchCfg cfg = cfg_for(h, KN_LS, A->dtype, K, A);
     double* bs = nullptr;
     if (ls_sum && A->n > 0) {
         const int nb = ls_interp_blocks(A->dtype, K, A->n, cfg);

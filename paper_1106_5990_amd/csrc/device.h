@@ -1,12 +1,12 @@
 // device.h -- device-side building blocks shared by the libalgdist kernels.
 //
-// Work mapping used by every per-row kernel: a row of the n x K panel is
-// K * sizeof(T) contiguous bytes.  A "row group" of LPR lanes covers one
-// panel row, each lane holding V = min(K, 16 / sizeof(T)) consecutive
-// entries (one 16-byte load: float4 or double2), so one wavefront (64
-// lanes) works on RPW = 64 / LPR rows at once and a gathered neighbour row
-// is read as one fully used 16-byte-per-lane request.  Reductions over K
-// are xor-butterflies inside the row group; they leave the identical
+// Work mapping used by the per-row kernels: a row of the n x K panel is
+// K * sizeof(T) contiguous bytes.  A "row group" of LPR adjacent lanes
+// covers one panel row, each lane holding V = K / LPR consecutive entries
+// (16-byte chunk loads: float4 or double2), so one wavefront (64 lanes)
+// works on RPW = 64 / LPR rows at once and a gathered neighbour row is read
+// as LPR * V * sizeof(T) contiguous bytes.  Reductions over K are
+// xor-butterflies inside the row group; they leave the identical
 // (commutatively equal) sum in every lane of the group.
 #pragma once
 
@@ -19,17 +19,38 @@ constexpr int kWave = 64;
 constexpr int kBlock = 256;  // threads per workgroup of the per-row kernels
 constexpr int kWavesPerBlock = kBlock / kWave;
 
-template <typename T> struct MaxVec;
-template <> struct MaxVec<float> { static constexpr int v = 4; };
-template <> struct MaxVec<double> { static constexpr int v = 2; };
+// Lanes per row (LPR) is a launch choice: each lane of a row group holds
+// V = K / LPR consecutive panel entries, read as 16-byte chunks.  Allowed
+// shapes keep V within 64 bytes of registers (16 floats, 8 doubles) and at
+// least 8 bytes, and V >= vmax / 4 unless V = K (tiny K).
+template <typename T>
+constexpr int vmax_of() { return 64 / (int)sizeof(T); }
 
-template <typename T, int K>
+template <typename T>
+constexpr bool lpr_ok(int K, int L) {
+    return L >= 1 && L <= kWave && K % L == 0 && (K / L) <= vmax_of<T>() &&
+           (K / L) * (int)sizeof(T) >= 8 && ((K / L) >= vmax_of<T>() / 4 || (K / L) == K);
+}
+
+// Default LPR before tuning: 32 bytes per lane where the shape allows it.
+template <typename T>
+constexpr int lpr_default(int K) {
+    for (int L = 1; L <= kWave; L *= 2)
+        if (lpr_ok<T>(K, L) && (K / L) * (int)sizeof(T) <= 32) return L;
+    for (int L = kWave; L >= 1; L /= 2)
+        if (lpr_ok<T>(K, L)) return L;
+    return 1;
+}
+
+template <typename T, int K, int LPR_>
 struct Shape {
-    static constexpr int V = (K < MaxVec<T>::v) ? K : MaxVec<T>::v;  // entries per lane
-    static constexpr int LPR = K / V;                                  // lanes per row
-    static constexpr int RPW = kWave / LPR;                            // rows per wavefront
-    static constexpr int RPB = RPW * kWavesPerBlock;                   // rows per block step
-    static_assert(K % V == 0 && (LPR & (LPR - 1)) == 0, "K must be a power of two");
+    static constexpr int LPR = LPR_;                        // lanes per row
+    static constexpr int V = K / LPR;                       // entries per lane
+    static constexpr int C = (V * (int)sizeof(T) <= 16) ? V : 16 / (int)sizeof(T);  // per load
+    static constexpr int RPW = kWave / LPR;                 // rows per wavefront
+    static constexpr int RPB = RPW * kWavesPerBlock;        // rows per block step
+    static_assert(lpr_ok<T>(K, LPR_), "unsupported lanes-per-row for this K");
+    static_assert((LPR & (LPR - 1)) == 0, "LPR must be a power of two");
 };
 
 template <typename T, int V>
@@ -37,24 +58,57 @@ struct Frag {
     T v[V];
 };
 
-// Load V consecutive entries starting at p (p aligned to V * sizeof(T)).
+// Load V consecutive entries starting at p (p aligned to V * sizeof(T), V a
+// power of two with V * sizeof(T) <= 16).
 template <typename T, int V>
 __device__ __forceinline__ Frag<T, V> load_frag(const T* __restrict__ p) {
     Frag<T, V> f;
-    typedef T vec_t __attribute__((ext_vector_type(V)));
-    vec_t x = *reinterpret_cast<const vec_t*>(p);
+    if constexpr (V == 1) {
+        f.v[0] = *p;
+    } else {
+        typedef T vec_t __attribute__((ext_vector_type(V)));
+        vec_t x = *reinterpret_cast<const vec_t*>(p);
 #pragma unroll
-    for (int q = 0; q < V; ++q) f.v[q] = x[q];
+        for (int q = 0; q < V; ++q) f.v[q] = x[q];
+    }
     return f;
 }
 
 template <typename T, int V>
 __device__ __forceinline__ void store_frag(T* __restrict__ p, const Frag<T, V>& f) {
-    typedef T vec_t __attribute__((ext_vector_type(V)));
-    vec_t x;
+    if constexpr (V == 1) {
+        *p = f.v[0];
+    } else {
+        typedef T vec_t __attribute__((ext_vector_type(V)));
+        vec_t x;
 #pragma unroll
-    for (int q = 0; q < V; ++q) x[q] = f.v[q];
-    *reinterpret_cast<vec_t*>(p) = x;
+        for (int q = 0; q < V; ++q) x[q] = f.v[q];
+        *reinterpret_cast<vec_t*>(p) = x;
+    }
+}
+
+// A lane's V entries of a panel row, as V / C chunk loads.
+template <typename T, int V, int C>
+__device__ __forceinline__ Frag<T, V> load_lane(const T* __restrict__ p) {
+    Frag<T, V> f;
+#pragma unroll
+    for (int c = 0; c < V / C; ++c) {
+        Frag<T, C> x = load_frag<T, C>(p + c * C);
+#pragma unroll
+        for (int q = 0; q < C; ++q) f.v[c * C + q] = x.v[q];
+    }
+    return f;
+}
+
+template <typename T, int V, int C>
+__device__ __forceinline__ void store_lane(T* __restrict__ p, const Frag<T, V>& f) {
+#pragma unroll
+    for (int c = 0; c < V / C; ++c) {
+        Frag<T, C> x;
+#pragma unroll
+        for (int q = 0; q < C; ++q) x.v[q] = f.v[c * C + q];
+        store_frag<T, C>(p + c * C, x);
+    }
 }
 
 // Sum over the LPR lanes of a row group (groups are aligned lane ranges).

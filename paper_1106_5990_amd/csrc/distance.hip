@@ -20,15 +20,15 @@ namespace ad {
 template <typename T> struct Guard { static constexpr bool on = false; };
 template <> struct Guard<float> { static constexpr bool on = true; };
 
-template <typename T, int K>
+template <typename T, int K, int LPR>
 __global__ __launch_bounds__(kBlock) void algdist_kernel(
     int n, const int* __restrict__ rp, const int* __restrict__ ci, const T* __restrict__ av,
     const T* __restrict__ X, const double* __restrict__ w, int target, T* __restrict__ mu,
     double* __restrict__ pout, double theta, const uint8_t* __restrict__ fmask,
     uint8_t* __restrict__ strong, int* __restrict__ nstrong, int iter, int xcd,
     unsigned* status) {
-    using S = Shape<T, K>;
-    constexpr int V = S::V, LPR = S::LPR;
+    using S = Shape<T, K, LPR>;
+    constexpr int V = S::V, C = S::C;
     const int lane = threadIdx.x & (kWave - 1);
     const int g = lane / LPR, l = lane % LPR;
     const int wv = threadIdx.x / kWave;
@@ -45,6 +45,7 @@ __global__ __launch_bounds__(kBlock) void algdist_kernel(
         wt[q] = (T)wd[q];
     }
     const bool fuse = strong != nullptr;
+    const bool plain = target == AD_TARGET_PLAIN;
 
     for (int it = 0; it < iter; ++it) {
         const int64_t i64 = tile * rows_per_tile + (int64_t)it * S::RPB + wv * S::RPW + g;
@@ -55,11 +56,11 @@ __global__ __launch_bounds__(kBlock) void algdist_kernel(
         // target t_i; the residual form is built in FP64 (products of two
         // panel-type values are exact there), then rounded to the panel type
         // for the main pass; the FP64 copy feeds the guard-band recompute.
-        Frag<T, V> t = load_frag<T, V>(X + (size_t)i * K + l * V);
+        Frag<T, V> t = load_lane<T, V, C>(X + (size_t)i * K + l * V);
         double t64[V];
 #pragma unroll
         for (int q = 0; q < V; ++q) t64[q] = (double)t.v[q];
-        if (target == AD_TARGET_RESIDUAL) {
+        if (!plain) {
             double y[V];
 #pragma unroll
             for (int q = 0; q < V; ++q) y[q] = 0.0;
@@ -67,7 +68,7 @@ __global__ __launch_bounds__(kBlock) void algdist_kernel(
             for (int e = e0; e < e1; ++e) {
                 const int j = ci[e];
                 const double a = (double)av[e];
-                Frag<T, V> xj = load_frag<T, V>(X + (size_t)j * K + l * V);
+                Frag<T, V> xj = load_lane<T, V, C>(X + (size_t)j * K + l * V);
 #pragma unroll
                 for (int q = 0; q < V; ++q) y[q] = fma(a, (double)xj.v[q], y[q]);
                 if (j == i) d = a;
@@ -95,52 +96,74 @@ __global__ __launch_bounds__(kBlock) void algdist_kernel(
         const bool in_f = fmask ? (fmask[i] != 0) : true;
         T mmin = (T)INFINITY;
         bool bad = false;
-        for (int e = e0; e < e1; ++e) {
-            const int j = ci[e];
-            Frag<T, V> xj = load_frag<T, V>(X + (size_t)j * K + l * V);
-            T sab = T(0), sbb = T(0);
+        // U edges per step: their column and panel loads are issued together
+        constexpr int U = (V >= 16) ? 2 : 4;
+        for (int eb = e0; eb < e1; eb += U) {
+            int jj[U];
+            Frag<T, V> xs[U];
 #pragma unroll
-            for (int q = 0; q < V; ++q) {
-                sab = fma(wtt[q], xj.v[q], sab);
-                sbb = fma(wt[q] * xj.v[q], xj.v[q], sbb);
-            }
-            sab = group_sum<LPR>(sab);
-            sbb = group_sum<LPR>(sbb);
-            T p = (sbb > T(0)) ? sab / sbb : T(0);
-            T m = T(0);
+            for (int u = 0; u < U; ++u) jj[u] = (eb + u < e1) ? ci[eb + u] : i;
 #pragma unroll
-            for (int q = 0; q < V; ++q) {
-                const T r = t.v[q] - p * xj.v[q];
-                m = fma(wt[q] * r, r, m);
-            }
-            m = group_sum<LPR>(m);
-            double pd = (double)p;
-            if (Guard<T>::on && m < guard) {
-                // FP64 recompute from the same FP32 inputs
-                double a2 = 0.0, b2 = 0.0;
+            for (int u = 0; u < U; ++u) xs[u] = load_lane<T, V, C>(X + (size_t)jj[u] * K + l * V);
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int e = eb + u;
+                if (e >= e1) break;
+                const int j = jj[u];
+                const Frag<T, V>& xj = xs[u];
+                const bool mine = ((e - e0) & (LPR - 1)) == l;
+                if (plain && j == i) {
+                    // x_i against itself: p = 1 and mu = 0 exactly
+                    if (mine) {
+                        mu[e] = T(0);
+                        if (pout) pout[e] = 1.0;
+                    }
+                    continue;
+                }
+                T sab = T(0), sbb = T(0);
 #pragma unroll
                 for (int q = 0; q < V; ++q) {
-                    const double xq = (double)xj.v[q], tq = t64[q];
-                    a2 = fma(wd[q] * tq, xq, a2);
-                    b2 = fma(wd[q] * xq, xq, b2);
+                    sab = fma(wtt[q], xj.v[q], sab);
+                    sbb = fma(wt[q] * xj.v[q], xj.v[q], sbb);
                 }
-                a2 = group_sum<LPR>(a2);
-                b2 = group_sum<LPR>(b2);
-                pd = (b2 > 0.0) ? a2 / b2 : 0.0;
-                double m2 = 0.0;
+                sab = group_sum<LPR>(sab);
+                sbb = group_sum<LPR>(sbb);
+                T p = (sbb > T(0)) ? sab / sbb : T(0);
+                T m = T(0);
 #pragma unroll
                 for (int q = 0; q < V; ++q) {
-                    const double r = t64[q] - pd * (double)xj.v[q];
-                    m2 = fma(wd[q] * r, r, m2);
+                    const T r = t.v[q] - p * xj.v[q];
+                    m = fma(wt[q] * r, r, m);
                 }
-                m = (T)group_sum<LPR>(m2);
+                m = group_sum<LPR>(m);
+                double pd = (double)p;
+                if (Guard<T>::on && m < guard) {
+                    // FP64 recompute from the same FP32 inputs
+                    double a2 = 0.0, b2 = 0.0;
+#pragma unroll
+                    for (int q = 0; q < V; ++q) {
+                        const double xq = (double)xj.v[q], tq = t64[q];
+                        a2 = fma(wd[q] * tq, xq, a2);
+                        b2 = fma(wd[q] * xq, xq, b2);
+                    }
+                    a2 = group_sum<LPR>(a2);
+                    b2 = group_sum<LPR>(b2);
+                    pd = (b2 > 0.0) ? a2 / b2 : 0.0;
+                    double m2 = 0.0;
+#pragma unroll
+                    for (int q = 0; q < V; ++q) {
+                        const double r = t64[q] - pd * (double)xj.v[q];
+                        m2 = fma(wd[q] * r, r, m2);
+                    }
+                    m = (T)group_sum<LPR>(m2);
+                }
+                bad |= !isfinite(m);
+                if (mine) {
+                    mu[e] = m;
+                    if (pout) pout[e] = pd;
+                }
+                if (j != i && (!fmask || fmask[j])) mmin = (m < mmin) ? m : mmin;
             }
-            bad |= !isfinite(m);
-            if (((e - e0) & (LPR - 1)) == l) {
-                mu[e] = m;
-                if (pout) pout[e] = pd;
-            }
-            if (j != i && (!fmask || fmask[j])) mmin = (m < mmin) ? m : mmin;
         }
         if (bad && l == 0) flag(status, AD_STAT_NONFINITE);
 
@@ -164,41 +187,44 @@ __global__ __launch_bounds__(kBlock) void algdist_kernel(
     }
 }
 
-template <typename T, int K>
+template <typename T, int K, int LPR>
 static void algdist_go(const ad_csr* A, const void* X, const double* w, int target, void* mu,
                        double* p, double theta, const uint8_t* fmask, uint8_t* strong,
                        int32_t* nstrong, unsigned* st, const LaunchCfg& cfg, hipStream_t s) {
-    using S = Shape<T, K>;
+    using S = Shape<T, K, LPR>;
     const int64_t rpt = (int64_t)S::RPB * cfg.iter;
     const int64_t ntiles = (A->n + rpt - 1) / rpt;
     const int grid = cfg.xcd_map ? grid_for_tiles(ntiles) : (int)ntiles;
-    algdist_kernel<T, K><<<dim3(grid), dim3(kBlock), 0, s>>>(
+    algdist_kernel<T, K, LPR><<<dim3(grid), dim3(kBlock), 0, s>>>(
         A->n, A->row_ptr, A->col, (const T*)A->val, (const T*)X, w, target, (T*)mu, p, theta,
         fmask, strong, nstrong, cfg.iter, cfg.xcd_map, st);
 }
 
-#define AD_K_SWITCH(T, FN, ...)                         \
-    switch (K) {                                        \
-        case 2: FN<T, 2>(__VA_ARGS__); break;           \
-        case 4: FN<T, 4>(__VA_ARGS__); break;           \
-        case 8: FN<T, 8>(__VA_ARGS__); break;           \
-        case 16: FN<T, 16>(__VA_ARGS__); break;         \
-        case 32: FN<T, 32>(__VA_ARGS__); break;         \
-        case 64: FN<T, 64>(__VA_ARGS__); break;         \
-        default: return AD_EINVAL;                      \
-    }
+template <typename T>
+static int algdist_dispatch(int K, const ad_csr* A, const void* X, const double* w, int target,
+                            void* mu, double* p, double theta, const uint8_t* fmask,
+                            uint8_t* strong, int32_t* nstrong, unsigned* st, const LaunchCfg& cfg,
+                            hipStream_t s) {
+    return with_k<T>(K, [&](auto kc) {
+        constexpr int KK = decltype(kc)::value;
+        return with_lpr<T, KK>(cfg.lpr, [&](auto lc) {
+            constexpr int L = decltype(lc)::value;
+            algdist_go<T, KK, L>(A, X, w, target, mu, p, theta, fmask, strong, nstrong, st, cfg, s);
+        });
+    });
+}
 
 int launch_algdist(int dtype, int K, const ad_csr* A, const void* X, const double* w, int target,
                    void* mu, double* p, double theta, const uint8_t* fmask, uint8_t* strong,
                    int32_t* nstrong, unsigned* status, const LaunchCfg& cfg, hipStream_t s) {
     if (A->n == 0) return AD_OK;
-    if (dtype == AD_F32) {
-        AD_K_SWITCH(float, algdist_go, A, X, w, target, mu, p, theta, fmask, strong, nstrong,
-                    status, cfg, s);
-    } else {
-        AD_K_SWITCH(double, algdist_go, A, X, w, target, mu, p, theta, fmask, strong, nstrong,
-                    status, cfg, s);
-    }
+    const int rc =
+        (dtype == AD_F32)
+            ? algdist_dispatch<float>(K, A, X, w, target, mu, p, theta, fmask, strong, nstrong,
+                                      status, cfg, s)
+            : algdist_dispatch<double>(K, A, X, w, target, mu, p, theta, fmask, strong, nstrong,
+                                       status, cfg, s);
+    if (rc) return rc;
     AD_HIP(hipGetLastError());
     return AD_OK;
 }

@@ -6,15 +6,29 @@
 #include <stdint.h>
 
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "algdist.h"
+#include "device.h"
 
 // One timed launch: HIP events recorded on the launch stream around it.
 struct ad_timed_launch {
     const char* label;
     hipEvent_t a, b;
 };
+
+namespace ad {
+// Launch knobs picked per call (the autotuner may override them).
+struct LaunchCfg {
+    int lpr = 0;      // lanes per row (0: the shape's default)
+    int iter = 1;     // row-block steps per workgroup (rows per lane group per tile)
+    int xcd_map = 1;  // 1: XCD-contiguous tile mapping
+};
+enum KernelId { KN_JACOBI = 0, KN_GS = 1, KN_ALGDIST = 2, KN_LS = 3, KN_COUNT = 4 };
+constexpr int kNumKSlots = 7;   // log2(K) for K = 2 .. 64
+constexpr int kNumBuckets = 4;  // stored entries per row: < 8, < 16, < 32, >= 32
+}  // namespace ad
 
 struct ad_handle_s {
     int device = 0;
@@ -29,15 +43,54 @@ struct ad_handle_s {
     std::vector<hipEvent_t> event_pool;
     size_t events_used = 0;
     std::string report;
+    // launch configurations set by algdist_set_launch / algdist_autotune
+    ad::LaunchCfg tuned[ad::KN_COUNT][2][ad::kNumKSlots][ad::kNumBuckets];
+    bool has_tuned[ad::KN_COUNT][2][ad::kNumKSlots][ad::kNumBuckets] = {};
 };
 
 namespace ad {
 
-// Kernel launch knobs picked per call (the autotuner may override them).
-struct LaunchCfg {
-    int iter = 1;     // row-block steps per workgroup ("rows per wavefront" multiplier)
-    int xcd_map = 1;  // 1: XCD-contiguous tile mapping
-};
+int k_slot(int K);                  // log2(K), or -1
+int nnz_bucket(int64_t nnz, int n);  // 0..kNumBuckets-1
+LaunchCfg cfg_for(ad_handle h, int kernel, int dtype, int K, const ad_csr* A);
+
+// Compile-time dispatch over the supported K and lanes-per-row shapes.
+template <typename T, typename F>
+int with_k(int K, F&& f) {
+    switch (K) {
+        case 2: return f(std::integral_constant<int, 2>{});
+        case 4: return f(std::integral_constant<int, 4>{});
+        case 8: return f(std::integral_constant<int, 8>{});
+        case 16: return f(std::integral_constant<int, 16>{});
+        case 32: return f(std::integral_constant<int, 32>{});
+        case 64: return f(std::integral_constant<int, 64>{});
+        default: return AD_EINVAL;
+    }
+}
+
+template <typename T, int K, typename F>
+int with_lpr(int lpr, F&& f) {
+    if (lpr <= 0) lpr = lpr_default<T>(K);
+#define AD_LPR_CASE(L)                                                   \
+    case L:                                                              \
+        if constexpr (lpr_ok<T>(K, L)) {                                 \
+            f(std::integral_constant<int, L>{});                         \
+            return AD_OK;                                                \
+        } else {                                                         \
+            return AD_EINVAL;                                            \
+        }
+    switch (lpr) {
+        AD_LPR_CASE(1)
+        AD_LPR_CASE(2)
+        AD_LPR_CASE(4)
+        AD_LPR_CASE(8)
+        AD_LPR_CASE(16)
+        AD_LPR_CASE(32)
+        AD_LPR_CASE(64)
+        default: return AD_EINVAL;
+    }
+#undef AD_LPR_CASE
+}
 
 // Workspace carve-up helper: returns aligned sub-buffers of the handle's
 // workspace, growing it first if needed (growth synchronises the device).

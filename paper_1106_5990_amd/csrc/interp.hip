@@ -2,16 +2,26 @@
 // eq:modls) on interpolatory sets C_i picked by the one-point distances
 // (the systematic scan of the final remark of Sec. 4.3).
 //
-// One row group per row.  Every lane of the group scans the row's entries
-// (same addresses, one request per wave) and keeps the `caliber` C-neighbours
-// of smallest mu in a register-resident sorted list.  The group then gathers
-// those panel rows and the target, forms the FP64 normal equations
-//     G_ab = sum_k w_k x_a^k x_b^k,  h_a = sum_k w_k x_a^k t^k
-// (FP32 x FP32 products are exact in FP64), reduces them over K with
-// butterflies, and every lane solves the tiny system by Cholesky in
-// increasing-mu column order, dropping a column whose pivot is <= 1e-12 of
-// its Gram diagonal.  The functional at the minimiser is then evaluated
-// from its definition in FP64.
+// Work mapping: a group of LPR adjacent lanes per F row, each lane holding
+// V = K / LPR consecutive panel entries, so that one load instruction of the
+// group fetches a whole panel row (every fetched cache line fully used).
+// Each wavefront owns a window of 128 consecutive rows; it writes the
+// (trivial) C rows directly and compacts the window's F rows into an LDS list
+// with ballots, so that every lane group then solves a real LS problem
+// whatever the C/F pattern.  Per F row the group
+//   * scans the row's entries (same addresses in every lane of the group)
+//     and keeps the `caliber` C-neighbours of smallest mu (ties: lower
+//     column) in a register-resident sorted list;
+//   * gathers the target and those panel rows once into registers and forms
+//     the FP64 normal equations
+//         G_ab = sum_k w_k x_a^k x_b^k,  h_a = sum_k w_k x_a^k t^k
+//     (a product of two FP32 values is exact in FP64), reduced over the
+//     group with butterflies;
+//   * factors G by Cholesky in increasing-mu column order (every lane of the
+//     group, redundantly), dropping a column whose pivot is <= 1e-12 of its
+//     Gram diagonal, and solves;
+//   * evaluates the functional at the minimiser from its definition in FP64
+//     on the register-resident values.
 #include <math.h>
 
 #include "device.h"
@@ -19,310 +29,365 @@
 
 namespace ad {
 
-template <typename T, int K, int CALT>
+constexpr int kLsRowsPerLane = 2;                   // window rows per lane
+constexpr int kLsWindow = kWave * kLsRowsPerLane;   // rows per wavefront window
+
+template <typename T, int K, int LPR, int CALT>
+__device__ __forceinline__ double ls_row(int i, int l, const int* __restrict__ rp,
+                                         const int* __restrict__ ci, const T* __restrict__ av,
+                                         const T* __restrict__ X, const double (&wd)[K / LPR],
+                                         const uint8_t* __restrict__ cf, const T* __restrict__ mu,
+                                         int cal, int target, int* __restrict__ Pcol,
+                                         double* __restrict__ Pval, double* __restrict__ lsv,
+                                         int* __restrict__ rstat, unsigned* status) {
+    using S = Shape<T, K, LPR>;
+    constexpr int V = S::V, C = S::C;
+    constexpr int NG = CALT * (CALT + 1) / 2;
+    const int e0 = rp[i], e1 = rp[i + 1];
+    int st = 0;
+
+    // C_i: the cal candidates of least (mu, column), sorted; diagonal on the way
+    T smu[CALT];
+    int scol[CALT];
+    int nsel = 0;
+    double d = 0.0;
+#pragma unroll
+    for (int q = 0; q < CALT; ++q) {
+        smu[q] = T(0);
+        scol[q] = -1;
+    }
+    // entries are fetched SE at a time so that their loads are in flight
+    // together (the scan is otherwise a chain of dependent round trips)
+    constexpr int SE = 8;
+    for (int eb = e0; eb < e1; eb += SE) {
+        int jj[SE];
+        T mm[SE];
+        bool cand[SE];
+#pragma unroll
+        for (int u = 0; u < SE; ++u) jj[u] = (eb + u < e1) ? ci[eb + u] : -1;
+#pragma unroll
+        for (int u = 0; u < SE; ++u) mm[u] = (eb + u < e1) ? mu[eb + u] : T(0);
+#pragma unroll
+        for (int u = 0; u < SE; ++u) cand[u] = (jj[u] >= 0 && jj[u] != i) ? (cf[jj[u]] != 0) : false;
+#pragma unroll
+        for (int u = 0; u < SE; ++u)
+            if (jj[u] == i) d = (double)av[eb + u];
+#pragma unroll
+        for (int u = 0; u < SE; ++u) {
+            const T m = mm[u];
+            if (!cand[u] || m != m) continue;  // NaN distances are never chosen
+            int pos = 0;                       // insert after the equal ones (lower column)
+#pragma unroll
+            for (int q = 0; q < CALT; ++q)
+                if (q < nsel && smu[q] <= m) pos = q + 1;
+            if (pos >= cal) continue;
+#pragma unroll
+            for (int q = CALT - 1; q > 0; --q)
+                if (q > pos && q < cal) {
+                    smu[q] = smu[q - 1];
+                    scol[q] = scol[q - 1];
+                }
+#pragma unroll
+            for (int q = 0; q < CALT; ++q)
+                if (q == pos) {
+                    smu[q] = m;
+                    scol[q] = jj[u];
+                }
+            nsel = (nsel < cal) ? nsel + 1 : cal;
+        }
+    }
+
+    // target in FP64: x_i, or x_i - (A x)_i / a_ii (residual form)
+    double t[V];
+    {
+        Frag<T, V> f = load_lane<T, V, C>(X + (size_t)i * K + l * V);
+#pragma unroll
+        for (int q = 0; q < V; ++q) t[q] = (double)f.v[q];
+    }
+    if (target == AD_TARGET_RESIDUAL) {
+        if (d == 0.0) {
+            st = 3;
+            if (l == 0) flag(status, AD_STAT_ZERO_DIAG);
+        } else {
+            double y[V];
+#pragma unroll
+            for (int q = 0; q < V; ++q) y[q] = 0.0;
+            for (int e = e0; e < e1; ++e) {
+                const int j = ci[e];
+                const double a = (double)av[e];
+                Frag<T, V> xj = load_lane<T, V, C>(X + (size_t)j * K + l * V);
+#pragma unroll
+                for (int q = 0; q < V; ++q) y[q] = fma(a, (double)xj.v[q], y[q]);
+            }
+#pragma unroll
+            for (int q = 0; q < V; ++q) t[q] = t[q] - y[q] / d;
+        }
+    }
+
+    // gather the chosen neighbours once; normal equations in FP64
+    Frag<T, V> xs[CALT];
+#pragma unroll
+    for (int a = 0; a < CALT; ++a) {
+        if (a < nsel) {
+            xs[a] = load_lane<T, V, C>(X + (size_t)scol[a] * K + l * V);
+        } else {
+#pragma unroll
+            for (int q = 0; q < V; ++q) xs[a].v[q] = T(0);
+        }
+    }
+    double G[NG], hv[CALT], tt = 0.0;
+#pragma unroll
+    for (int q = 0; q < NG; ++q) G[q] = 0.0;
+#pragma unroll
+    for (int a = 0; a < CALT; ++a) hv[a] = 0.0;
+#pragma unroll
+    for (int q = 0; q < V; ++q) {
+        const double wt = wd[q] * t[q];
+        tt = fma(wt, t[q], tt);
+        int gi = 0;
+#pragma unroll
+        for (int a = 0; a < CALT; ++a) {
+            const double wx = wd[q] * (double)xs[a].v[q];
+            hv[a] = fma(wx, t[q], hv[a]);
+#pragma unroll
+            for (int b = 0; b <= a; ++b, ++gi) G[gi] = fma(wx, (double)xs[b].v[q], G[gi]);
+        }
+    }
+    if (nsel == 0) {
+        tt = group_sum<LPR>(tt);
+    } else {
+#pragma unroll
+        for (int q = 0; q < NG; ++q) G[q] = group_sum<LPR>(G[q]);
+#pragma unroll
+        for (int a = 0; a < CALT; ++a) hv[a] = group_sum<LPR>(hv[a]);
+    }
+
+    double val;
+    double coef[CALT];
+    bool keep[CALT];
+#pragma unroll
+    for (int q = 0; q < CALT; ++q) {
+        coef[q] = 0.0;
+        keep[q] = false;
+    }
+    if (nsel == 0) {
+        val = tt;
+        st = st ? st : 1;
+    } else {
+        // Cholesky (in place, packed lower) in increasing-mu order, drop rule
+#pragma unroll
+        for (int a = 0; a < CALT; ++a) {
+            if (a >= nsel) continue;
+            const int ra = a * (a + 1) / 2;
+            const double gaa = G[ra + a];
+#pragma unroll
+            for (int b = 0; b < a; ++b) {
+                const int rb = b * (b + 1) / 2;
+                double s = G[ra + b];
+#pragma unroll
+                for (int c = 0; c < b; ++c)
+                    if (keep[c]) s -= G[ra + c] * G[rb + c];
+                G[ra + b] = keep[b] ? s / G[rb + b] : 0.0;
+            }
+            double piv = gaa;
+#pragma unroll
+            for (int b = 0; b < a; ++b)
+                if (keep[b]) piv -= G[ra + b] * G[ra + b];
+            keep[a] = piv > 1e-12 * gaa;
+            G[ra + a] = keep[a] ? sqrt(piv) : 1.0;
+            if (!keep[a]) st = st ? st : 2;
+        }
+        double z[CALT];
+#pragma unroll
+        for (int a = 0; a < CALT; ++a) {
+            const int ra = a * (a + 1) / 2;
+            double s = hv[a];
+#pragma unroll
+            for (int b = 0; b < a; ++b)
+                if (keep[b]) s -= G[ra + b] * z[b];
+            z[a] = keep[a] ? s / G[ra + a] : 0.0;
+        }
+#pragma unroll
+        for (int a = CALT - 1; a >= 0; --a) {
+            double s = z[a];
+#pragma unroll
+            for (int b = a + 1; b < CALT; ++b)
+                if (keep[b]) s -= G[b * (b + 1) / 2 + a] * coef[b];
+            coef[a] = keep[a] ? s / G[a * (a + 1) / 2 + a] : 0.0;
+        }
+        // the functional at the minimiser, by its definition
+        double f = 0.0;
+#pragma unroll
+        for (int q = 0; q < V; ++q) {
+            double r = t[q];
+#pragma unroll
+            for (int a = 0; a < CALT; ++a)
+                if (keep[a]) r -= coef[a] * (double)xs[a].v[q];
+            f = fma(wd[q] * r, r, f);
+        }
+        val = group_sum<LPR>(f);
+    }
+    if (l == 0) {
+        int* pc = Pcol + (size_t)i * cal;
+        double* pv = Pval + (size_t)i * cal;
+        int o = 0;
+#pragma unroll
+        for (int a = 0; a < CALT; ++a)
+            if (keep[a]) {
+                pc[o] = scol[a];
+                pv[o] = coef[a];
+                ++o;
+            }
+        for (; o < cal; ++o) {
+            pc[o] = -1;
+            pv[o] = 0.0;
+        }
+        lsv[i] = val;
+        rstat[i] = st;
+    }
+    return val;
+}
+
+template <typename T, int K, int LPR, int CALT>
 __global__ __launch_bounds__(kBlock) void ls_interp_kernel(
     int n, const int* __restrict__ rp, const int* __restrict__ ci, const T* __restrict__ av,
     const T* __restrict__ X, const double* __restrict__ w, const uint8_t* __restrict__ cf,
     const T* __restrict__ mu, int cal, int target, int* __restrict__ Pcol,
     double* __restrict__ Pval, double* __restrict__ lsv, int* __restrict__ rstat,
-    double* __restrict__ block_sums, int iter, int xcd, unsigned* status) {
-    using S = Shape<T, K>;
-    constexpr int V = S::V, LPR = S::LPR;
-    constexpr int NG = CALT * (CALT + 1) / 2;
+    double* __restrict__ block_sums, int xcd, unsigned* status) {
+    using S = Shape<T, K, LPR>;
+    constexpr int V = S::V;
+    __shared__ int flist[kWavesPerBlock][kLsWindow];
+    __shared__ double wsum[kWavesPerBlock];
     const int lane = threadIdx.x & (kWave - 1);
-    const int g = lane / LPR, l = lane % LPR;
     const int wv = threadIdx.x / kWave;
-    const int64_t rows_per_tile = (int64_t)S::RPB * iter;
-    const int64_t ntiles = (n + rows_per_tile - 1) / rows_per_tile;
+    const int g = lane / LPR, l = lane % LPR;
+    const int64_t nwin = (n + kLsWindow - 1) / kLsWindow;
+    const int64_t ntiles = (nwin + kWavesPerBlock - 1) / kWavesPerBlock;
     const int64_t tile = xcd ? xcd_tile(ntiles) : (int64_t)blockIdx.x;
-    double fsum = 0.0;  // this group's F-row ls values (lane 0 of the group)
+    const int64_t win = (tile >= 0 && tile < ntiles) ? tile * kWavesPerBlock + wv : nwin;
+    const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+
+    // window scan: C rows written here, F rows listed
+    int cnt = 0;
+    if (win < nwin) {
+        const int64_t w0 = win * kLsWindow;
+#pragma unroll
+        for (int r = 0; r < kLsRowsPerLane; ++r) {
+            const int64_t row = w0 + r * kWave + lane;
+            const bool valid = row < n;
+            const bool isF = valid && cf[row] == 0;
+            if (valid && !isF) {  // a C point interpolates itself
+                int* pc = Pcol + (size_t)row * cal;
+                double* pv = Pval + (size_t)row * cal;
+                pc[0] = (int)row;
+                pv[0] = 1.0;
+                for (int q = 1; q < cal; ++q) {
+                    pc[q] = -1;
+                    pv[q] = 0.0;
+                }
+                lsv[row] = 0.0;
+                rstat[row] = 0;
+            }
+            const uint64_t m = __ballot(isF);
+            if (isF) flist[wv][cnt + __popcll(m & lt)] = (int)row;
+            cnt += __popcll(m);
+        }
+    }
+    __syncthreads();
 
     double wd[V];
 #pragma unroll
     for (int q = 0; q < V; ++q) wd[q] = w ? w[l * V + q] : 1.0;
-
-    if (tile >= 0 && tile < ntiles) {
-        for (int it = 0; it < iter; ++it) {
-            const int64_t i64 = tile * rows_per_tile + (int64_t)it * S::RPB + wv * S::RPW + g;
-            if (i64 >= n) break;
-            const int i = (int)i64;
-            int* pc = Pcol + (size_t)i * cal;
-            double* pv = Pval + (size_t)i * cal;
-            if (cf[i]) {  // a C point interpolates itself
-                for (int q = l; q < cal; q += LPR) {
-                    pc[q] = (q == 0) ? i : -1;
-                    pv[q] = (q == 0) ? 1.0 : 0.0;
-                }
-                if (l == 0) {
-                    lsv[i] = 0.0;
-                    rstat[i] = 0;
-                }
-                continue;
-            }
-            const int e0 = rp[i], e1 = rp[i + 1];
-            int st = 0;
-
-            // target, in FP64 from the panel type
-            Frag<T, V> tf = load_frag<T, V>(X + (size_t)i * K + l * V);
-            double t[V];
-#pragma unroll
-            for (int q = 0; q < V; ++q) t[q] = (double)tf.v[q];
-            if (target == AD_TARGET_RESIDUAL) {  // formed in FP64
-                double y[V];
-#pragma unroll
-                for (int q = 0; q < V; ++q) y[q] = 0.0;
-                double d = 0.0;
-                for (int e = e0; e < e1; ++e) {
-                    const int j = ci[e];
-                    const double a = (double)av[e];
-                    Frag<T, V> xj = load_frag<T, V>(X + (size_t)j * K + l * V);
-#pragma unroll
-                    for (int q = 0; q < V; ++q) y[q] = fma(a, (double)xj.v[q], y[q]);
-                    if (j == i) d = a;
-                }
-                if (d != 0.0) {
-#pragma unroll
-                    for (int q = 0; q < V; ++q) t[q] = t[q] - y[q] / d;
-                } else {
-                    st = 3;
-                    if (l == 0) flag(status, AD_STAT_ZERO_DIAG);
-                }
-            }
-
-            // C_i: the cal candidates of least (mu, column), sorted
-            T smu[CALT];
-            int scol[CALT];
-            int nsel = 0;
-#pragma unroll
-            for (int q = 0; q < CALT; ++q) {
-                smu[q] = T(0);
-                scol[q] = -1;
-            }
-            for (int e = e0; e < e1; ++e) {
-                const int j = ci[e];
-                if (j == i || !cf[j]) continue;
-                const T m = mu[e];
-                if (m != m) continue;  // NaN distances are never chosen
-                int pos = 0;           // insert after the equal ones (lower column)
-#pragma unroll
-                for (int q = 0; q < CALT; ++q)
-                    if (q < nsel && smu[q] <= m) pos = q + 1;
-                if (pos >= cal) continue;
-#pragma unroll
-                for (int q = CALT - 1; q > 0; --q)
-                    if (q > pos && q < cal) {
-                        smu[q] = smu[q - 1];
-                        scol[q] = scol[q - 1];
-                    }
-#pragma unroll
-                for (int q = 0; q < CALT; ++q)
-                    if (q == pos) {
-                        smu[q] = m;
-                        scol[q] = j;
-                    }
-                nsel = (nsel < cal) ? nsel + 1 : cal;
-            }
-
-            double val;
-            double coef[CALT];
-            bool keep[CALT];
-#pragma unroll
-            for (int q = 0; q < CALT; ++q) {
-                coef[q] = 0.0;
-                keep[q] = false;
-            }
-            if (nsel == 0) {
-                double f = 0.0;
-#pragma unroll
-                for (int q = 0; q < V; ++q) f = fma(wd[q] * t[q], t[q], f);
-                val = group_sum<LPR>(f);
-                st = st ? st : 1;
-            } else {
-                // gather the selected panel rows (FP64 copies)
-                double xs[CALT][V];
-#pragma unroll
-                for (int a = 0; a < CALT; ++a) {
-                    if (a < nsel) {
-                        Frag<T, V> f = load_frag<T, V>(X + (size_t)scol[a] * K + l * V);
-#pragma unroll
-                        for (int q = 0; q < V; ++q) xs[a][q] = (double)f.v[q];
-                    } else {
-#pragma unroll
-                        for (int q = 0; q < V; ++q) xs[a][q] = 0.0;
-                    }
-                }
-                // normal equations: lower triangle of G (row-major packed) and h
-                double G[NG], hv[CALT];
-                int gi = 0;
-#pragma unroll
-                for (int a = 0; a < CALT; ++a) {
-                    double ha = 0.0;
-#pragma unroll
-                    for (int q = 0; q < V; ++q) ha = fma(wd[q] * xs[a][q], t[q], ha);
-                    hv[a] = group_sum<LPR>(ha);
-#pragma unroll
-                    for (int b = 0; b <= a; ++b) {
-                        double gab = 0.0;
-#pragma unroll
-                        for (int q = 0; q < V; ++q) gab = fma(wd[q] * xs[a][q], xs[b][q], gab);
-                        G[gi++] = group_sum<LPR>(gab);
-                    }
-                }
-                // Cholesky in increasing-mu order with the drop rule
-                double L[NG];
-#pragma unroll
-                for (int q = 0; q < NG; ++q) L[q] = 0.0;
-#pragma unroll
-                for (int a = 0; a < CALT; ++a) {
-                    if (a >= nsel) continue;
-                    const int ra = a * (a + 1) / 2;
-#pragma unroll
-                    for (int b = 0; b < a; ++b) {
-                        const int rb = b * (b + 1) / 2;
-                        double s = G[ra + b];
-#pragma unroll
-                        for (int c = 0; c < b; ++c)
-                            if (keep[c]) s -= L[ra + c] * L[rb + c];
-                        L[ra + b] = keep[b] ? s / L[rb + b] : 0.0;
-                    }
-                    double dpiv = G[ra + a];
-#pragma unroll
-                    for (int b = 0; b < a; ++b)
-                        if (keep[b]) dpiv -= L[ra + b] * L[ra + b];
-                    keep[a] = dpiv > 1e-12 * G[ra + a];
-                    L[ra + a] = keep[a] ? sqrt(dpiv) : 1.0;
-                    if (!keep[a]) st = st ? st : 2;
-                }
-                // L z = h, then L^T coef = z, over the kept columns
-                double z[CALT];
-#pragma unroll
-                for (int a = 0; a < CALT; ++a) {
-                    const int ra = a * (a + 1) / 2;
-                    double s = hv[a];
-#pragma unroll
-                    for (int b = 0; b < a; ++b)
-                        if (keep[b]) s -= L[ra + b] * z[b];
-                    z[a] = keep[a] ? s / L[ra + a] : 0.0;
-                }
-#pragma unroll
-                for (int a = CALT - 1; a >= 0; --a) {
-                    double s = z[a];
-#pragma unroll
-                    for (int b = a + 1; b < CALT; ++b)
-                        if (keep[b]) s -= L[b * (b + 1) / 2 + a] * coef[b];
-                    coef[a] = keep[a] ? s / L[a * (a + 1) / 2 + a] : 0.0;
-                }
-                // functional at the minimiser, by its definition
-                double f = 0.0;
-#pragma unroll
-                for (int q = 0; q < V; ++q) {
-                    double r = t[q];
-#pragma unroll
-                    for (int a = 0; a < CALT; ++a)
-                        if (keep[a]) r -= coef[a] * xs[a][q];
-                    f = fma(wd[q] * r, r, f);
-                }
-                val = group_sum<LPR>(f);
-            }
-            if (l == 0) {
-                int o = 0;
-#pragma unroll
-                for (int a = 0; a < CALT; ++a)
-                    if (keep[a]) {
-                        pc[o] = scol[a];
-                        pv[o] = coef[a];
-                        ++o;
-                    }
-                for (; o < cal; ++o) {
-                    pc[o] = -1;
-                    pv[o] = 0.0;
-                }
-                lsv[i] = val;
-                rstat[i] = st;
-                fsum += val;
-            }
+    double fsum = 0.0;
+    for (int base = 0; base < cnt; base += S::RPW) {
+        const int idx = base + g;
+        if (idx < cnt) {
+            const double v = ls_row<T, K, LPR, CALT>(flist[wv][idx], l, rp, ci, av, X, wd, cf, mu,
+                                                     cal, target, Pcol, Pval, lsv, rstat, status);
+            if (l == 0) fsum += v;
         }
     }
     if (block_sums) {
-        // fixed-order block sum: groups in lane order, waves in order
-        __shared__ double part[kBlock];
-        part[threadIdx.x] = fsum;
+        // fixed-order reduction: xor butterfly in the wave, then waves in order
+#pragma unroll
+        for (int o = kWave / 2; o > 0; o >>= 1) fsum += __shfl_xor(fsum, o, kWave);
+        if (lane == 0) wsum[wv] = fsum;
         __syncthreads();
         if (threadIdx.x == 0) {
             double s = 0.0;
-            for (int q = 0; q < kBlock; ++q) s += part[q];
+            for (int q = 0; q < kWavesPerBlock; ++q) s += wsum[q];
             block_sums[blockIdx.x] = s;
         }
     }
 }
 
-__global__ __launch_bounds__(kBlock) void sum_blocks_kernel(const double* __restrict__ part,
-                                                            int m, double* __restrict__ out) {
-    __shared__ double acc[kBlock];
+// Sum of m block partials by one workgroup of 1024 threads in a fixed order:
+// contiguous per-thread runs, then an in-LDS pairwise tree.
+__global__ __launch_bounds__(1024) void sum_blocks_kernel(const double* __restrict__ part, int m,
+                                                          double* __restrict__ out) {
+    __shared__ double acc[1024];
+    const int t = threadIdx.x;
+    const int per = (m + 1023) / 1024;
     double s = 0.0;
-    for (int q = threadIdx.x; q < m; q += kBlock) s += part[q];
-    acc[threadIdx.x] = s;
+    for (int q = t * per; q < min(m, (t + 1) * per); ++q) s += part[q];
+    acc[t] = s;
     __syncthreads();
-    if (threadIdx.x == 0) {
-        double t = 0.0;
-        for (int q = 0; q < kBlock; ++q) t += acc[q];
-        *out = t;
+    for (int o = 512; o > 0; o >>= 1) {
+        if (t < o) acc[t] += acc[t + o];
+        __syncthreads();
     }
-}
-
-template <typename T, int K>
-static int ls_grid(int n, const LaunchCfg& cfg) {
-    using S = Shape<T, K>;
-    const int64_t rpt = (int64_t)S::RPB * cfg.iter;
-    const int64_t ntiles = (n + rpt - 1) / rpt;
-    return cfg.xcd_map ? grid_for_tiles(ntiles) : (int)(ntiles > 0 ? ntiles : 1);
+    if (t == 0) *out = acc[0];
 }
 
 int ls_interp_blocks(int dtype, int K, int n, const LaunchCfg& cfg) {
-#define G_(T)                                        \
-    switch (K) {                                     \
-        case 2: return ls_grid<T, 2>(n, cfg);        \
-        case 4: return ls_grid<T, 4>(n, cfg);        \
-        case 8: return ls_grid<T, 8>(n, cfg);        \
-        case 16: return ls_grid<T, 16>(n, cfg);      \
-        case 32: return ls_grid<T, 32>(n, cfg);      \
-        case 64: return ls_grid<T, 64>(n, cfg);      \
-        default: return 0;                           \
-    }
-    if (dtype == AD_F32) {
-        G_(float)
-    } else {
-        G_(double)
-    }
-#undef G_
+    (void)dtype;
+    (void)K;
+    const int64_t nwin = ((int64_t)n + kLsWindow - 1) / kLsWindow;
+    const int64_t ntiles = (nwin + kWavesPerBlock - 1) / kWavesPerBlock;
+    return cfg.xcd_map ? grid_for_tiles(ntiles) : (int)(ntiles > 0 ? ntiles : 1);
 }
 
-template <typename T, int K>
+template <typename T, int K, int LPR>
 static void ls_go(int caliber, const ad_csr* A, const void* X, const double* w, const uint8_t* cf,
                   const void* mu, int target, int32_t* P_col, double* P_val, double* ls_val,
                   int32_t* row_status, double* block_sums, unsigned* st, const LaunchCfg& cfg,
                   hipStream_t s) {
-    const int grid = ls_grid<T, K>(A->n, cfg);
+    const int grid = ls_interp_blocks(A->dtype, K, A->n, cfg);
     if (caliber <= 4)
-        ls_interp_kernel<T, K, 4><<<dim3(grid), dim3(kBlock), 0, s>>>(
+        ls_interp_kernel<T, K, LPR, 4><<<dim3(grid), dim3(kBlock), 0, s>>>(
             A->n, A->row_ptr, A->col, (const T*)A->val, (const T*)X, w, cf, (const T*)mu, caliber,
-            target, P_col, P_val, ls_val, row_status, block_sums, cfg.iter, cfg.xcd_map, st);
+            target, P_col, P_val, ls_val, row_status, block_sums, cfg.xcd_map, st);
     else
-        ls_interp_kernel<T, K, 8><<<dim3(grid), dim3(kBlock), 0, s>>>(
+        ls_interp_kernel<T, K, LPR, 8><<<dim3(grid), dim3(kBlock), 0, s>>>(
             A->n, A->row_ptr, A->col, (const T*)A->val, (const T*)X, w, cf, (const T*)mu, caliber,
-            target, P_col, P_val, ls_val, row_status, block_sums, cfg.iter, cfg.xcd_map, st);
+            target, P_col, P_val, ls_val, row_status, block_sums, cfg.xcd_map, st);
 }
 
-#define AD_K_SWITCH(T, FN, ...)                         \
-    switch (K) {                                        \
-        case 2: FN<T, 2>(__VA_ARGS__); break;           \
-        case 4: FN<T, 4>(__VA_ARGS__); break;           \
-        case 8: FN<T, 8>(__VA_ARGS__); break;           \
-        case 16: FN<T, 16>(__VA_ARGS__); break;         \
-        case 32: FN<T, 32>(__VA_ARGS__); break;         \
-        case 64: FN<T, 64>(__VA_ARGS__); break;         \
-        default: return AD_EINVAL;                      \
-    }
+// LS rows default to 16 bytes of panel per lane (one chunk), so that all
+// gathered rows stay in registers for the second pass.
+template <typename T>
+constexpr int ls_lpr_default(int K) {
+    for (int L = 1; L <= kWave; L *= 2)
+        if (lpr_ok<T>(K, L) && (K / L) * (int)sizeof(T) <= 16) return L;
+    return lpr_default<T>(K);
+}
+
+template <typename T>
+static int ls_dispatch(int K, int caliber, const ad_csr* A, const void* X, const double* w,
+                       const uint8_t* cf, const void* mu, int target, int32_t* P_col,
+                       double* P_val, double* ls_val, int32_t* row_status, double* bs,
+                       unsigned* st, const LaunchCfg& cfg, hipStream_t s) {
+    return with_k<T>(K, [&](auto kc) {
+        constexpr int KK = decltype(kc)::value;
+        const int lpr = cfg.lpr > 0 ? cfg.lpr : ls_lpr_default<T>(KK);
+        return with_lpr<T, KK>(lpr, [&](auto lc) {
+            constexpr int L = decltype(lc)::value;
+            ls_go<T, KK, L>(caliber, A, X, w, cf, mu, target, P_col, P_val, ls_val, row_status, bs,
+                            st, cfg, s);
+        });
+    });
+}
 
 int launch_ls_interp(int dtype, int K, int caliber, const ad_csr* A, const void* X,
                      const double* w, const uint8_t* cf, const void* mu, int target,
@@ -334,17 +399,16 @@ int launch_ls_interp(int dtype, int K, int caliber, const ad_csr* A, const void*
         return AD_OK;
     }
     double* bs = ls_sum ? block_sums : nullptr;
-    if (dtype == AD_F32) {
-        AD_K_SWITCH(float, ls_go, caliber, A, X, w, cf, mu, target, P_col, P_val, ls_val,
-                    row_status, bs, status, cfg, s);
-    } else {
-        AD_K_SWITCH(double, ls_go, caliber, A, X, w, cf, mu, target, P_col, P_val, ls_val,
-                    row_status, bs, status, cfg, s);
-    }
+    const int rc = (dtype == AD_F32)
+                       ? ls_dispatch<float>(K, caliber, A, X, w, cf, mu, target, P_col, P_val,
+                                            ls_val, row_status, bs, status, cfg, s)
+                       : ls_dispatch<double>(K, caliber, A, X, w, cf, mu, target, P_col, P_val,
+                                             ls_val, row_status, bs, status, cfg, s);
+    if (rc) return rc;
     AD_HIP(hipGetLastError());
     if (ls_sum) {
         const int nb = ls_interp_blocks(dtype, K, A->n, cfg);
-        sum_blocks_kernel<<<dim3(1), dim3(kBlock), 0, s>>>(block_sums, nb, ls_sum);
+        sum_blocks_kernel<<<dim3(1), dim3(1024), 0, s>>>(block_sums, nb, ls_sum);
         AD_HIP(hipGetLastError());
     }
     return AD_OK;

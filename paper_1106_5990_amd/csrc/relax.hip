@@ -50,31 +50,30 @@ int launch_tv_init(int dtype, int64_t row0, int64_t nrows, int K, uint64_t seed,
 // ---------------------------------------------------------------- row SpMM core
 // y = sum_e a_e x_{col e} over the row's entries, in CSR order (FMA per term);
 // also returns the diagonal value and the row's own fragment.
-// PICK(j) chooses which panel a neighbour is read from.
-template <typename T, int K, typename Pick>
+// pick(j) chooses which panel a neighbour is read from.
+template <typename S, typename T, int K, typename Pick>
 __device__ __forceinline__ void row_spmm(int i, int e0, int e1, const int* __restrict__ ci,
                                          const T* __restrict__ av, int l, Pick pick,
-                                         T (&y)[Shape<T, K>::V], T& d,
-                                         Frag<T, Shape<T, K>::V>& xi) {
-    constexpr int V = Shape<T, K>::V;
+                                         T (&y)[S::V], T& d, Frag<T, S::V>& xi) {
+    constexpr int V = S::V, C = S::C;
+    constexpr int U = (V >= 16) ? 2 : 4;  // independent gathers in flight per step
 #pragma unroll
     for (int q = 0; q < V; ++q) y[q] = T(0);
     d = T(0);
     int e = e0;
-    // four independent gathers in flight per step
-    for (; e + 4 <= e1; e += 4) {
-        int j[4];
-        T a[4];
-        Frag<T, V> x[4];
+    for (; e + U <= e1; e += U) {
+        int j[U];
+        T a[U];
+        Frag<T, V> x[U];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
+        for (int u = 0; u < U; ++u) {
             j[u] = ci[e + u];
             a[u] = av[e + u];
         }
 #pragma unroll
-        for (int u = 0; u < 4; ++u) x[u] = load_frag<T, V>(pick(j[u]) + (size_t)j[u] * K + l * V);
+        for (int u = 0; u < U; ++u) x[u] = load_lane<T, V, C>(pick(j[u]) + (size_t)j[u] * K + l * V);
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
+        for (int u = 0; u < U; ++u) {
 #pragma unroll
             for (int q = 0; q < V; ++q) y[q] = fma(a[u], x[u].v[q], y[q]);
             if (j[u] == i) {
@@ -86,7 +85,7 @@ __device__ __forceinline__ void row_spmm(int i, int e0, int e1, const int* __res
     for (; e < e1; ++e) {
         const int j = ci[e];
         const T a = av[e];
-        Frag<T, V> x = load_frag<T, V>(pick(j) + (size_t)j * K + l * V);
+        Frag<T, V> x = load_lane<T, V, C>(pick(j) + (size_t)j * K + l * V);
 #pragma unroll
         for (int q = 0; q < V; ++q) y[q] = fma(a, x.v[q], y[q]);
         if (j == i) {
@@ -98,17 +97,17 @@ __device__ __forceinline__ void row_spmm(int i, int e0, int e1, const int* __res
 
 // ---------------------------------------------------------------- Jacobi
 // x_new = x - omega * (A x) / a_ii  (row held fixed if a_ii == 0)
-template <typename T, int K>
+template <typename T, int K, int LPR>
 __global__ __launch_bounds__(kBlock) void jacobi_kernel(int n, const int* __restrict__ rp,
                                                         const int* __restrict__ ci,
                                                         const T* __restrict__ av,
                                                         const T* __restrict__ Xin,
                                                         T* __restrict__ Xout, T omega, int iter,
                                                         int xcd, unsigned* status) {
-    using S = Shape<T, K>;
-    constexpr int V = S::V;
+    using S = Shape<T, K, LPR>;
+    constexpr int V = S::V, C = S::C;
     const int lane = threadIdx.x & (kWave - 1);
-    const int g = lane / S::LPR, l = lane % S::LPR;
+    const int g = lane / LPR, l = lane % LPR;
     const int wv = threadIdx.x / kWave;
     const int64_t rows_per_tile = (int64_t)S::RPB * iter;
     const int64_t ntiles = (n + rows_per_tile - 1) / rows_per_tile;
@@ -120,50 +119,49 @@ __global__ __launch_bounds__(kBlock) void jacobi_kernel(int n, const int* __rest
         const int i = (int)i64;
         T y[V], d;
         Frag<T, V> xi;
-        row_spmm<T, K>(i, rp[i], rp[i + 1], ci, av, l, [&](int) { return Xin; }, y, d, xi);
+        row_spmm<S, T, K>(i, rp[i], rp[i + 1], ci, av, l, [&](int) { return Xin; }, y, d, xi);
         Frag<T, V> out;
         if (d == T(0)) {
-            out = load_frag<T, V>(Xin + (size_t)i * K + l * V);
+            out = load_lane<T, V, C>(Xin + (size_t)i * K + l * V);
             if (l == 0) flag(status, AD_STAT_ZERO_DIAG);
         } else {
 #pragma unroll
             for (int q = 0; q < V; ++q) out.v[q] = xi.v[q] - omega * y[q] / d;
         }
-        store_frag<T, V>(Xout + (size_t)i * K + l * V, out);
+        store_lane<T, V, C>(Xout + (size_t)i * K + l * V, out);
     }
 }
 
-template <typename T, int K>
+template <typename T, int K, int LPR>
 static void jacobi_go(const ad_csr* A, const void* Xin, void* Xout, double omega, unsigned* st,
                       const LaunchCfg& cfg, hipStream_t s) {
-    using S = Shape<T, K>;
+    using S = Shape<T, K, LPR>;
     const int64_t rpt = (int64_t)S::RPB * cfg.iter;
     const int64_t ntiles = (A->n + rpt - 1) / rpt;
     const int grid = cfg.xcd_map ? grid_for_tiles(ntiles) : (int)ntiles;
-    jacobi_kernel<T, K><<<dim3(grid), dim3(kBlock), 0, s>>>(
+    jacobi_kernel<T, K, LPR><<<dim3(grid), dim3(kBlock), 0, s>>>(
         A->n, A->row_ptr, A->col, (const T*)A->val, (const T*)Xin, (T*)Xout, (T)omega, cfg.iter,
         cfg.xcd_map, st);
 }
 
-#define AD_K_SWITCH(T, FN, ...)                         \
-    switch (K) {                                        \
-        case 2: FN<T, 2>(__VA_ARGS__); break;           \
-        case 4: FN<T, 4>(__VA_ARGS__); break;           \
-        case 8: FN<T, 8>(__VA_ARGS__); break;           \
-        case 16: FN<T, 16>(__VA_ARGS__); break;         \
-        case 32: FN<T, 32>(__VA_ARGS__); break;         \
-        case 64: FN<T, 64>(__VA_ARGS__); break;         \
-        default: return AD_EINVAL;                      \
-    }
+template <typename T>
+static int jacobi_dispatch(int K, const ad_csr* A, const void* Xin, void* Xout, double omega,
+                           unsigned* st, const LaunchCfg& cfg, hipStream_t s) {
+    return with_k<T>(K, [&](auto kc) {
+        constexpr int KK = decltype(kc)::value;
+        return with_lpr<T, KK>(cfg.lpr, [&](auto lc) {
+            constexpr int L = decltype(lc)::value;
+            jacobi_go<T, KK, L>(A, Xin, Xout, omega, st, cfg, s);
+        });
+    });
+}
 
 int launch_jacobi(int dtype, int K, const ad_csr* A, const void* Xin, void* Xout, double omega,
                   unsigned* status, const LaunchCfg& cfg, hipStream_t s) {
     if (A->n == 0) return AD_OK;
-    if (dtype == AD_F32) {
-        AD_K_SWITCH(float, jacobi_go, A, Xin, Xout, omega, status, cfg, s);
-    } else {
-        AD_K_SWITCH(double, jacobi_go, A, Xin, Xout, omega, status, cfg, s);
-    }
+    const int rc = (dtype == AD_F32) ? jacobi_dispatch<float>(K, A, Xin, Xout, omega, status, cfg, s)
+                                     : jacobi_dispatch<double>(K, A, Xin, Xout, omega, status, cfg, s);
+    if (rc) return rc;
     AD_HIP(hipGetLastError());
     return AD_OK;
 }
@@ -289,16 +287,16 @@ int launch_color_partition(int n, const int32_t* color, int ncolors, int32_t* ro
 // Rows of colour c (list segment seg[c]..seg[c+1]):
 //   x_new_i = x_i - (A z)_i / a_ii,  z_j = Xnew_j if colour(j) < c else Xold_j.
 // The phase of colour 0 also copies rows with an invalid colour (held fixed).
-template <typename T, int K, bool FIRST>
+template <typename T, int K, int LPR, bool FIRST>
 __global__ __launch_bounds__(kBlock) void gs_phase_kernel(
     const int* __restrict__ rp, const int* __restrict__ ci, const T* __restrict__ av,
     const int* __restrict__ color, int c, int nc, const int* __restrict__ rowlist,
     const int* __restrict__ seg, const T* __restrict__ Xold, T* __restrict__ Xnew, int iter,
     int xcd, unsigned* status) {
-    using S = Shape<T, K>;
-    constexpr int V = S::V;
+    using S = Shape<T, K, LPR>;
+    constexpr int V = S::V, C = S::C;
     const int lane = threadIdx.x & (kWave - 1);
-    const int g = lane / S::LPR, l = lane % S::LPR;
+    const int g = lane / LPR, l = lane % LPR;
     const int wv = threadIdx.x / kWave;
     const int b0 = seg[c], b1 = seg[c + 1];
     const int64_t rows_per_tile = (int64_t)S::RPB * iter;
@@ -312,22 +310,23 @@ __global__ __launch_bounds__(kBlock) void gs_phase_kernel(
             T y[V], d;
             Frag<T, V> xi;
             if (FIRST) {
-                row_spmm<T, K>(i, rp[i], rp[i + 1], ci, av, l, [&](int) { return Xold; }, y, d, xi);
+                row_spmm<S, T, K>(i, rp[i], rp[i + 1], ci, av, l, [&](int) { return Xold; }, y, d,
+                                  xi);
             } else {
-                row_spmm<T, K>(
+                row_spmm<S, T, K>(
                     i, rp[i], rp[i + 1], ci, av, l,
                     [&](int j) { return ((unsigned)color[j] < (unsigned)c) ? (const T*)Xnew : Xold; },
                     y, d, xi);
             }
             Frag<T, V> out;
             if (d == T(0)) {
-                out = load_frag<T, V>(Xold + (size_t)i * K + l * V);
+                out = load_lane<T, V, C>(Xold + (size_t)i * K + l * V);
                 if (l == 0) flag(status, AD_STAT_ZERO_DIAG);
             } else {
 #pragma unroll
                 for (int q = 0; q < V; ++q) out.v[q] = xi.v[q] - y[q] / d;
             }
-            store_frag<T, V>(Xnew + (size_t)i * K + l * V, out);
+            store_lane<T, V, C>(Xnew + (size_t)i * K + l * V, out);
         }
     }
     if (FIRST) {  // rows with an invalid colour are held fixed
@@ -335,41 +334,53 @@ __global__ __launch_bounds__(kBlock) void gs_phase_kernel(
         const int64_t stride = (int64_t)gridDim.x * S::RPB;
         for (int64_t p = q0 + (int64_t)blockIdx.x * S::RPB + wv * S::RPW + g; p < q1; p += stride) {
             const int i = rowlist[p];
-            store_frag<T, V>(Xnew + (size_t)i * K + l * V,
-                             load_frag<T, V>(Xold + (size_t)i * K + l * V));
+            store_lane<T, V, C>(Xnew + (size_t)i * K + l * V,
+                                load_lane<T, V, C>(Xold + (size_t)i * K + l * V));
         }
     }
 }
 
-template <typename T, int K>
+template <typename T, int K, int LPR>
 static void gs_go(const ad_csr* A, const int32_t* color, int c, int nc, const int32_t* rowlist,
                   const int32_t* seg, const void* Xold, void* Xnew, unsigned* st,
                   const LaunchCfg& cfg, hipStream_t s) {
-    using S = Shape<T, K>;
+    using S = Shape<T, K, LPR>;
     // the per-colour row count is known only on the device: size the grid
     // for all n rows; workgroups beyond the colour's tiles exit at once.
     const int64_t rpt = (int64_t)S::RPB * cfg.iter;
     const int64_t ntiles = (A->n + rpt - 1) / rpt;
     const int grid = cfg.xcd_map ? grid_for_tiles(ntiles) : (int)ntiles;
     if (c == 0)
-        gs_phase_kernel<T, K, true><<<dim3(grid), dim3(kBlock), 0, s>>>(
+        gs_phase_kernel<T, K, LPR, true><<<dim3(grid), dim3(kBlock), 0, s>>>(
             A->row_ptr, A->col, (const T*)A->val, color, c, nc, rowlist, seg, (const T*)Xold,
             (T*)Xnew, cfg.iter, cfg.xcd_map, st);
     else
-        gs_phase_kernel<T, K, false><<<dim3(grid), dim3(kBlock), 0, s>>>(
+        gs_phase_kernel<T, K, LPR, false><<<dim3(grid), dim3(kBlock), 0, s>>>(
             A->row_ptr, A->col, (const T*)A->val, color, c, nc, rowlist, seg, (const T*)Xold,
             (T*)Xnew, cfg.iter, cfg.xcd_map, st);
+}
+
+template <typename T>
+static int gs_dispatch(int K, const ad_csr* A, const int32_t* color, int c, int nc,
+                       const int32_t* rowlist, const int32_t* seg, const void* Xold, void* Xnew,
+                       unsigned* st, const LaunchCfg& cfg, hipStream_t s) {
+    return with_k<T>(K, [&](auto kc) {
+        constexpr int KK = decltype(kc)::value;
+        return with_lpr<T, KK>(cfg.lpr, [&](auto lc) {
+            constexpr int L = decltype(lc)::value;
+            gs_go<T, KK, L>(A, color, c, nc, rowlist, seg, Xold, Xnew, st, cfg, s);
+        });
+    });
 }
 
 int launch_gs_phase(int dtype, int K, const ad_csr* A, const int32_t* color, int c, int ncolors,
                     const int32_t* rowlist, const int32_t* seg, const void* Xold, void* Xnew,
                     unsigned* status, const LaunchCfg& cfg, hipStream_t s) {
     if (A->n == 0) return AD_OK;
-    if (dtype == AD_F32) {
-        AD_K_SWITCH(float, gs_go, A, color, c, ncolors, rowlist, seg, Xold, Xnew, status, cfg, s);
-    } else {
-        AD_K_SWITCH(double, gs_go, A, color, c, ncolors, rowlist, seg, Xold, Xnew, status, cfg, s);
-    }
+    const int rc = (dtype == AD_F32)
+                       ? gs_dispatch<float>(K, A, color, c, ncolors, rowlist, seg, Xold, Xnew, status, cfg, s)
+                       : gs_dispatch<double>(K, A, color, c, ncolors, rowlist, seg, Xold, Xnew, status, cfg, s);
+    if (rc) return rc;
     AD_HIP(hipGetLastError());
     return AD_OK;
 }

@@ -443,3 +443,58 @@ def test_csr_validate_flags():
     col[row] = np.where(col[row] == r, r + 50, col[row])  # no diagonal, unsorted too
     ad.csr_validate(dev_csr(W.CSR(A.n, A.row_ptr, col, A.val), torch.float64))
     assert ad.status(clear=True) & ad.STAT_CSR_NODIAG
+
+
+# ------------------------------------------------------------------ launch shapes
+def valid_lprs(dt, K):
+    """Lanes-per-row values the kernels accept (mirror of the library's rule)."""
+    size = 4 if dt == torch.float32 else 8
+    vmax = 64 // size
+    out = []
+    L = 1
+    while L <= 64:
+        V = K // L
+        if K % L == 0 and V <= vmax and V * size >= 8 and (V >= vmax // 4 or V == K):
+            out.append(L)
+        L *= 2
+    return out
+
+
+@pytest.mark.parametrize("dt", ["f32", "f64"])
+@pytest.mark.parametrize("K", [4, 16, 32])
+def test_every_launch_shape_gives_the_same_results(dt, K):
+    ad = lib()
+    dtype = DT[dt]
+    say("launch shapes %s K=%d lprs=%s" % (dt, K, valid_lprs(dtype, K)))
+    N = 39
+    A = aniso(N)
+    Ad = dev_csr(A, dtype)
+    color = torch.as_tensor(W.red_black((N, N)), device="cuda")
+    cf = torch.as_tensor(W.cf_red_is_coarse((N, N)), device="cuda")
+    ref = None
+    try:
+        for lpr in valid_lprs(dtype, K):
+            for it in (1, 3):
+                for xcd in (True, False):
+                    for kern in ("jacobi", "gs_phase", "algdist"):
+                        ad.set_launch(kern, dtype, K, lpr, it, xcd)
+                    ad.set_launch("ls_interp", dtype, K, 0, 1, xcd)
+                    Xg = ad.setup_testvectors(Ad, K, seed=3, relax="gs", sweeps=3, color=color, ncolors=2)
+                    Xj = ad.setup_testvectors(Ad, K, seed=3, relax="jacobi", sweeps=3, omega=0.7)
+                    mu, s, ns = ad.algebraic_distance(Ad, Xg, fuse=True, theta=0.25)
+                    P = ad.ls_interp(Ad, Xg, cf, mu, 4)
+                    if ref is None:
+                        ref = (Xg, Xj)
+                        x = to_np(Xg).astype(np.float64)
+                        mu_ref = oracle.algdist(as_oracle(A, dtype), x)
+                        saa = saa_per_edge(A, x)
+                    assert torch.equal(Xg, ref[0]) and torch.equal(Xj, ref[1]), (lpr, it, xcd)
+                    check_mu(to_np(mu).astype(np.float64), mu_ref, saa, dtype, "lpr=%d it=%d" % (lpr, it))
+                    mh = to_np(mu).astype(np.float64)
+                    sr, nsr = oracle.strength(A, mh, 0.25)
+                    assert np.array_equal(to_np(s), sr) and np.array_equal(to_np(ns), nsr)
+                    R = oracle.ls_interp(as_oracle(A, dtype), x, None, W.cf_red_is_coarse((N, N)), mh, 4)
+                    check_ls(tuple(to_np(t) for t in P), R, dtype, (x * x).sum(1))
+    finally:
+        for kern in ("jacobi", "gs_phase", "algdist", "ls_interp"):
+            ad.set_launch(kern, dtype, K, 0, 1, True)
