@@ -67,6 +67,7 @@ typedef enum {
 #define AD_STAT_CSR_COLS    0x10u /* csr_validate: column out of range or not strictly increasing */
 #define AD_STAT_CSR_NODIAG  0x20u /* csr_validate: a row has no diagonal entry */
 #define AD_STAT_TIMEOUT     0x40u /* batched path: a bounded inter-workgroup wait gave up */
+#define AD_STAT_ASYMMETRIC  0x80u /* backward: the sparsity pattern is not structurally symmetric */
 
 typedef struct ad_handle_s *ad_handle;
 
@@ -242,6 +243,37 @@ int ls_interp(ad_handle h, const ad_csr *A, int32_t K, const void *X, const doub
               const uint8_t *cf, const void *mu, int32_t caliber, int32_t target,
               int32_t *P_col, double *P_val, double *ls_val, int32_t *row_status,
               double *ls_sum, void *stream);
+
+/* ------------------------------------------------------------------ */
+/* adjoint of the LS interpolation loss                                */
+/* ------------------------------------------------------------------ */
+
+/* Gradient of L = sum_{i in F} ls_val_i, where ls_val is the plain-target LS
+ * functional of Sec. 3.1 (eq:LSfuncrowi) at the rows p fitted to
+ * x^S = J^S x^0, J x = x - omega D^{-1} A x (damped Jacobi, Sec. 3 test
+ * vectors), with respect to the stored values of A and to omega.
+ * Because each p_i minimises its row's functional, L's dependence through p
+ * vanishes to first order and p enters as fixed weights.  The chain rule
+ * runs the sweeps backward: y = D^{-1} g, dL/da_ij -= omega <y_i, x_j^s>,
+ * dL/da_ii += omega <y_i, (A x^s)_i> / a_ii, dL/domega -= <y, A x^s>,
+ * g <- g - omega A^T y, from the seed g = dL/dx^S.
+ *
+ * FP64 only (A->dtype == AD_F64).  The sparsity pattern must be
+ * structurally symmetric (entry (i, j) stored iff (j, i) is); otherwise
+ * AD_STAT_ASYMMETRIC is set and the result is undefined.
+ * Inputs (device): ckpt, the iterates x^0, x^c, x^2c, ... written by
+ * setup_testvectors with ckpt_every = c (others are recomputed forward);
+ * X_final = x^S; w (K, may be NULL); cf; P_col / P_val (n x caliber) from
+ * ls_interp on X_final with the plain target; dL, one FP64 (the upstream
+ * derivative, e.g. 1.0).
+ * Outputs (device): grad_val (nnz FP64, overwritten), grad_omega (one FP64).
+ * Uses handle workspace of about (4 + c) n K doubles + nnz ints.
+ */
+int ls_interp_loss_backward(ad_handle h, const ad_csr *A, int32_t K, const void *ckpt,
+                            int32_t ckpt_every, int32_t sweeps, double omega, const double *w,
+                            const uint8_t *cf, const int32_t *P_col, const double *P_val,
+                            int32_t caliber, const void *X_final, const double *dL,
+                            double *grad_val, double *grad_omega, void *stream);
 
 #ifdef __cplusplus
 }

@@ -38,6 +38,7 @@ STAT_CSR_ROWPTR = 0x08
 STAT_CSR_COLS = 0x10
 STAT_CSR_NODIAG = 0x20
 STAT_TIMEOUT = 0x40
+STAT_ASYMMETRIC = 0x80
 
 STATUS_NAMES = {0: "AD_OK", 1: "AD_EINVAL", 2: "AD_EDTYPE", 3: "AD_ECALIBER", 4: "AD_ESTRUCT",
                 5: "AD_EDEVICE", 6: "AD_ENOMEM", 7: "AD_EUNSUPPORTED"}
@@ -67,6 +68,8 @@ _SIGS = {
     "algebraic_distance": (_i32, [_P, _CSRP, _i32, _P, _P, _i32, _P, _P, _f64, _P, _P, _P, _P]),
     "strength_graph": (_i32, [_P, _CSRP, _P, _f64, _P, _P, _P, _P]),
     "ls_interp": (_i32, [_P, _CSRP, _i32, _P, _P, _P, _P, _i32, _i32, _P, _P, _P, _P, _P, _P]),
+    "ls_interp_loss_backward": (_i32, [_P, _CSRP, _i32, _P, _i32, _i32, _f64, _P, _P, _P, _P, _i32,
+                                       _P, _P, _P, _P, _P]),
 }
 for _name, (_res, _args) in _SIGS.items():
     _fn = getattr(_lib, _name)
@@ -263,3 +266,57 @@ def ls_interp(A: Csr, X: torch.Tensor, cf: torch.Tensor, mu: torch.Tensor, calib
     _check(rc, h, "ls_interp")
     out = (P_col, P_val, ls_val, row_status)
     return out + (ls_sum,) if want_sum else out
+
+
+def ls_interp_loss_backward(A: Csr, K: int, ckpt: torch.Tensor, ckpt_every: int, sweeps: int,
+                            omega: float, cf: torch.Tensor, P_col: torch.Tensor,
+                            P_val: torch.Tensor, X_final: torch.Tensor, dL: torch.Tensor,
+                            w: Optional[torch.Tensor] = None, grad_val: Optional[torch.Tensor] = None,
+                            grad_omega: Optional[torch.Tensor] = None, stream=None):
+    """(grad_val[nnz], grad_omega[1]) of the LS loss; see ls_interp_loss_backward in algdist.h."""
+    h = handle(A.device.index)
+    grad_val = grad_val if grad_val is not None else torch.empty(A.nnz, dtype=torch.float64, device=A.device)
+    grad_omega = grad_omega if grad_omega is not None else torch.empty(1, dtype=torch.float64, device=A.device)
+    rc = _lib.ls_interp_loss_backward(h, A.ref(), K, _ptr(ckpt), ckpt_every, sweeps, float(omega),
+                                      _ptr(w), _ptr(cf), _ptr(P_col), _ptr(P_val), P_col.shape[1],
+                                      _ptr(X_final), _ptr(dL), _ptr(grad_val), _ptr(grad_omega),
+                                      _stream(stream))
+    _check(rc, h, "ls_interp_loss_backward")
+    return grad_val, grad_omega
+
+
+class LSInterpLoss(torch.autograd.Function):
+    """L(values, omega) = sum over F rows of the LS interpolation functional
+    after `sweeps` damped-Jacobi sweeps of K test vectors (plain target).
+
+    apply(values, omega, row_ptr, col, K, seed, sweeps, cf, caliber,
+          ckpt_every=2, w=None, X0=None) -> 0-dim FP64 tensor.
+    values: FP64 CSR values (requires_grad); omega: 0-dim or 1-element FP64
+    tensor (requires_grad).  Forward: setup_testvectors (checkpointed),
+    algebraic_distance (which picks C_i), ls_interp with its F-row sum.
+    Backward: ls_interp_loss_backward.
+    """
+
+    @staticmethod
+    def forward(ctx, values, omega, row_ptr, col, K, seed, sweeps, cf, caliber, ckpt_every=2,
+                w=None, X0=None):
+        A = Csr(row_ptr, col, values.detach().contiguous())
+        om = float(omega.detach().reshape(-1)[0])
+        nck = max(1, -(-sweeps // ckpt_every))
+        ck = torch.empty((nck, A.n, K), dtype=torch.float64, device=A.device)
+        X = setup_testvectors(A, K, seed=seed, X0=X0, relax="jacobi", sweeps=sweeps, omega=om,
+                              ckpt=ck, ckpt_every=ckpt_every)
+        mu = algebraic_distance(A, X, w=w)
+        Pc, Pv, ls, st, tot = ls_interp(A, X, cf, mu, caliber, w=w, want_sum=True)
+        ctx.save_for_backward(values, ck, X, Pc, Pv, cf)
+        ctx.meta = (row_ptr, col, K, sweeps, ckpt_every, om, w, omega.shape)
+        return tot.reshape(())
+
+    @staticmethod
+    def backward(ctx, gL):
+        values, ck, X, Pc, Pv, cf = ctx.saved_tensors
+        row_ptr, col, K, sweeps, ce, om, w, oshape = ctx.meta
+        A = Csr(row_ptr, col, values.detach().contiguous())
+        dL = gL.detach().reshape(1).to(torch.float64).contiguous()
+        gv, go = ls_interp_loss_backward(A, K, ck, ce, sweeps, om, cf, Pc, Pv, X, dL, w=w)
+        return gv, go.reshape(oshape), None, None, None, None, None, None, None, None, None, None

@@ -1,0 +1,329 @@
+// adjoint.hip -- gradient of the LS interpolation loss with respect to the
+// matrix values and the Jacobi damping omega.
+//
+// Forward (done by the other calls): x^0 from the start, S damped-Jacobi
+// sweeps x^{s+1} = x^s - omega D^{-1} A x^s, LS rows p fitted to x^S (plain
+// target, Sec. 3.1 eq:LSfuncrowi), loss L = sum_{i in F} ls_val_i.
+//
+// Backward, all FP64:
+//   seed   g_i = dL (2 w (rho_i [i in F] - sum_{q: i in C_q} p_qi rho_q)),
+//          rho_q = x_q - sum_j p_qj x_j, p held fixed (it minimises each row's
+//          functional, so its own variation does not enter);
+//   sweep  s = S-1 .. 0:  y = D^{-1} g;
+//          dL/da_ij -= omega <y_i, x_j^s>;  dL/da_ii += omega <y_i, (A x^s)_i> / a_ii;
+//          dL/domega -= <y, A x^s>;  g <- g - omega A^T y.
+// The transpose products are gathers: the pattern must be structurally
+// symmetric, and tp[e] is the position of entry (j, i) for entry e = (i, j).
+// Iterates that are not checkpointed are recomputed forward from the last
+// checkpoint.  Every reduction has a fixed order (no atomics on values).
+#include <math.h>
+
+#include "device.h"
+#include "internal.h"
+
+namespace ad {
+
+// tp[e] = position of (col[e], i) in row col[e]; -1 (and a status bit) if absent.
+__global__ __launch_bounds__(kBlock) void transpose_perm_kernel(int n, const int* __restrict__ rp,
+                                                                const int* __restrict__ ci,
+                                                                int* __restrict__ tp,
+                                                                double* __restrict__ diag,
+                                                                const double* __restrict__ av,
+                                                                unsigned* status) {
+    const int64_t i64 = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i64 >= n) return;
+    const int i = (int)i64;
+    double d = 0.0;
+    for (int e = rp[i]; e < rp[i + 1]; ++e) {
+        const int j = ci[e];
+        if (j == i) d = av[e];
+        int lo = rp[j], hi = rp[j + 1] - 1, f = -1;
+        while (lo <= hi) {
+            const int mid = (lo + hi) >> 1;
+            const int c = ci[mid];
+            if (c == i) {
+                f = mid;
+                break;
+            }
+            if (c < i) lo = mid + 1;
+            else hi = mid - 1;
+        }
+        tp[e] = f;
+        if (f < 0) flag(status, AD_STAT_ASYMMETRIC);
+    }
+    diag[i] = d;
+    if (d == 0.0) flag(status, AD_STAT_ZERO_DIAG);
+}
+
+// R_i = 2 dL w .* rho_i for F rows (rho = x_i - sum_q P_val[i,q] x_{P_col[i,q]}), 0 for C rows.
+template <int K, int LPR>
+__global__ __launch_bounds__(kBlock) void ls_residual_kernel(int n, const double* __restrict__ X,
+                                                             const double* __restrict__ w,
+                                                             const uint8_t* __restrict__ cf,
+                                                             const int* __restrict__ Pcol,
+                                                             const double* __restrict__ Pval,
+                                                             int cal, const double* __restrict__ dL,
+                                                             double* __restrict__ R) {
+    using S = Shape<double, K, LPR>;
+    constexpr int V = S::V, C = S::C;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int g = lane / LPR, l = lane % LPR;
+    const int64_t i64 = ((int64_t)blockIdx.x * kWavesPerBlock + threadIdx.x / kWave) * S::RPW + g;
+    if (i64 >= n) return;
+    const int i = (int)i64;
+    Frag<double, V> r;
+    if (cf[i]) {
+#pragma unroll
+        for (int q = 0; q < V; ++q) r.v[q] = 0.0;
+    } else {
+        r = load_lane<double, V, C>(X + (size_t)i * K + l * V);
+        for (int q = 0; q < cal; ++q) {
+            const int j = Pcol[(size_t)i * cal + q];
+            if (j < 0) continue;
+            const double p = Pval[(size_t)i * cal + q];
+            Frag<double, V> xj = load_lane<double, V, C>(X + (size_t)j * K + l * V);
+#pragma unroll
+            for (int v = 0; v < V; ++v) r.v[v] -= p * xj.v[v];
+        }
+        const double s = 2.0 * (*dL);
+#pragma unroll
+        for (int v = 0; v < V; ++v) r.v[v] *= s * (w ? w[l * V + v] : 1.0);
+    }
+    store_lane<double, V, C>(R + (size_t)i * K + l * V, r);
+}
+
+// g_j = R_j - sum over neighbours q of j that interpolate from j of p_qj R_q.
+template <int K, int LPR>
+__global__ __launch_bounds__(kBlock) void ls_seed_kernel(int n, const int* __restrict__ rp,
+                                                         const int* __restrict__ ci,
+                                                         const uint8_t* __restrict__ cf,
+                                                         const int* __restrict__ Pcol,
+                                                         const double* __restrict__ Pval, int cal,
+                                                         const double* __restrict__ R,
+                                                         double* __restrict__ G) {
+    using S = Shape<double, K, LPR>;
+    constexpr int V = S::V, C = S::C;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int g = lane / LPR, l = lane % LPR;
+    const int64_t j64 = ((int64_t)blockIdx.x * kWavesPerBlock + threadIdx.x / kWave) * S::RPW + g;
+    if (j64 >= n) return;
+    const int j = (int)j64;
+    Frag<double, V> acc = load_lane<double, V, C>(R + (size_t)j * K + l * V);
+    for (int e = rp[j]; e < rp[j + 1]; ++e) {
+        const int q = ci[e];
+        if (q == j || cf[q]) continue;
+        double p = 0.0;
+        bool hit = false;
+        for (int c = 0; c < cal; ++c)
+            if (Pcol[(size_t)q * cal + c] == j) {
+                p = Pval[(size_t)q * cal + c];
+                hit = true;
+            }
+        if (!hit) continue;
+        Frag<double, V> rq = load_lane<double, V, C>(R + (size_t)q * K + l * V);
+#pragma unroll
+        for (int v = 0; v < V; ++v) acc.v[v] -= p * rq.v[v];
+    }
+    store_lane<double, V, C>(G + (size_t)j * K + l * V, acc);
+}
+
+// y = D^{-1} g (rows with a zero diagonal get y = 0)
+template <int K, int LPR>
+__global__ __launch_bounds__(kBlock) void dinv_kernel(int n, const double* __restrict__ diag,
+                                                      const double* __restrict__ G,
+                                                      double* __restrict__ Y) {
+    using S = Shape<double, K, LPR>;
+    constexpr int V = S::V, C = S::C;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int g = lane / LPR, l = lane % LPR;
+    const int64_t i64 = ((int64_t)blockIdx.x * kWavesPerBlock + threadIdx.x / kWave) * S::RPW + g;
+    if (i64 >= n) return;
+    const double d = diag[i64];
+    Frag<double, V> v = load_lane<double, V, C>(G + (size_t)i64 * K + l * V);
+#pragma unroll
+    for (int q = 0; q < V; ++q) v.v[q] = (d != 0.0) ? v.v[q] / d : 0.0;
+    store_lane<double, V, C>(Y + (size_t)i64 * K + l * V, v);
+}
+
+// One backward sweep for row i:
+//   z_i = (A x^s)_i, (A^T y)_i = sum_e a[tp[e]] y_{col e},
+//   gval[e] -= omega <y_i, x_col e>,  gval[diag] += omega <y_i, z_i> / a_ii,
+//   Gout_i = Gin_i - omega (A^T y)_i,  block partial of -<y_i, z_i>.
+template <int K, int LPR>
+__global__ __launch_bounds__(kBlock) void adjoint_sweep_kernel(
+    int n, const int* __restrict__ rp, const int* __restrict__ ci, const double* __restrict__ av,
+    const int* __restrict__ tp, const double* __restrict__ diag, const double* __restrict__ Xs,
+    const double* __restrict__ Y, const double* __restrict__ Gin, double* __restrict__ Gout,
+    double omega, double* __restrict__ gval, double* __restrict__ wpart) {
+    using S = Shape<double, K, LPR>;
+    constexpr int V = S::V, C = S::C;
+    __shared__ double part[kWavesPerBlock];
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wv = threadIdx.x / kWave;
+    const int g = lane / LPR, l = lane % LPR;
+    const int64_t i64 = ((int64_t)blockIdx.x * kWavesPerBlock + wv) * S::RPW + g;
+    double wsum = 0.0;  // -<y_i, z_i> (lane 0 of the group)
+    if (i64 < n) {
+        const int i = (int)i64;
+        const int e0 = rp[i], e1 = rp[i + 1];
+        const Frag<double, V> yi = load_lane<double, V, C>(Y + (size_t)i * K + l * V);
+        double z[V], aty[V];
+#pragma unroll
+        for (int q = 0; q < V; ++q) {
+            z[q] = 0.0;
+            aty[q] = 0.0;
+        }
+        int ediag = -1;
+        for (int e = e0; e < e1; ++e) {
+            const int j = ci[e];
+            const double a = av[e];
+            const int t = tp[e];
+            const double at = (t >= 0) ? av[t] : 0.0;
+            const Frag<double, V> xj = load_lane<double, V, C>(Xs + (size_t)j * K + l * V);
+            const Frag<double, V> yj = load_lane<double, V, C>(Y + (size_t)j * K + l * V);
+            double dot = 0.0;
+#pragma unroll
+            for (int q = 0; q < V; ++q) {
+                z[q] = fma(a, xj.v[q], z[q]);
+                aty[q] = fma(at, yj.v[q], aty[q]);
+                dot = fma(yi.v[q], xj.v[q], dot);
+            }
+            dot = group_sum<LPR>(dot);
+            if (j == i) ediag = e;
+            if (l == 0) gval[e] -= omega * dot;
+        }
+        double yz = 0.0;
+#pragma unroll
+        for (int q = 0; q < V; ++q) yz = fma(yi.v[q], z[q], yz);
+        yz = group_sum<LPR>(yz);
+        const double d = diag[i];
+        if (l == 0) {
+            if (ediag >= 0 && d != 0.0) gval[ediag] += omega * yz / d;
+            wsum = -yz;
+        }
+        Frag<double, V> gi = load_lane<double, V, C>(Gin + (size_t)i * K + l * V);
+#pragma unroll
+        for (int q = 0; q < V; ++q) gi.v[q] = fma(-omega, aty[q], gi.v[q]);
+        store_lane<double, V, C>(Gout + (size_t)i * K + l * V, gi);
+    }
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) wsum += __shfl_xor(wsum, o, kWave);
+    if (lane == 0) part[wv] = wsum;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double s = 0.0;
+        for (int q = 0; q < kWavesPerBlock; ++q) s += part[q];
+        wpart[blockIdx.x] = s;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void fill_kernel(double* __restrict__ p, int64_t m, double v) {
+    const int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (q < m) p[q] = v;
+}
+
+// Fixed-order sum of m partials into *out (one workgroup of 1024 threads).
+__global__ __launch_bounds__(1024) void sum_partials_kernel(const double* __restrict__ part,
+                                                            int64_t m, double* __restrict__ out) {
+    __shared__ double acc[1024];
+    const int t = threadIdx.x;
+    const int64_t per = (m + 1023) / 1024;
+    double s = 0.0;
+    for (int64_t q = t * per; q < m && q < (t + 1) * per; ++q) s += part[q];
+    acc[t] = s;
+    __syncthreads();
+    for (int o = 512; o > 0; o >>= 1) {
+        if (t < o) acc[t] += acc[t + o];
+        __syncthreads();
+    }
+    if (t == 0) *out = acc[0];
+}
+
+template <int K>
+static int adjoint_go(ad_handle h, const ad_csr* A, const void* ckpt, int ce, int sweeps,
+                      double omega, const double* w, const uint8_t* cf, const int32_t* P_col,
+                      const double* P_val, int cal, const void* X_final, const double* dL,
+                      double* grad_val, double* grad_omega, hipStream_t s) {
+    constexpr int LPR = lpr_default<double>(K);
+    using Sh = Shape<double, K, LPR>;
+    const int n = A->n;
+    const int64_t nnz = A->nnz;
+    const size_t panel = (size_t)n * K * sizeof(double);
+    const int rblocks = (int)(((int64_t)n + Sh::RPB - 1) / Sh::RPB);
+    const int nblk_e = (int)((nnz + kBlock - 1) / kBlock);
+    const int nblk_n = (int)(((int64_t)n + kBlock - 1) / kBlock);
+    const int extra = ce - 1;  // recomputed iterates inside one checkpoint segment
+
+    WsReq req;
+    const size_t o_tp = req.add(sizeof(int) * (size_t)nnz);
+    const size_t o_dg = req.add(sizeof(double) * (size_t)n);
+    const size_t o_g0 = req.add(panel);
+    const size_t o_g1 = req.add(panel);
+    const size_t o_y = req.add(panel);
+    const size_t o_xr = req.add(panel * (size_t)(extra > 0 ? extra : 0));
+    const size_t o_wp = req.add(sizeof(double) * (size_t)rblocks * (sweeps > 0 ? sweeps : 1));
+    int rc = ws_reserve(h, req.off);
+    if (rc) return rc;
+    char* ws = (char*)h->ws;
+    int* tp = (int*)(ws + o_tp);
+    double* diag = (double*)(ws + o_dg);
+    double* G[2] = {(double*)(ws + o_g0), (double*)(ws + o_g1)};
+    double* Y = (double*)(ws + o_y);
+    double* Xr = (double*)(ws + o_xr);
+    double* wp = (double*)(ws + o_wp);
+    const double* av = (const double*)A->val;
+
+    transpose_perm_kernel<<<dim3(nblk_n), dim3(kBlock), 0, s>>>(n, A->row_ptr, A->col, tp, diag, av,
+                                                                h->status);
+    fill_kernel<<<dim3(nblk_e > 0 ? nblk_e : 1), dim3(kBlock), 0, s>>>(grad_val, nnz, 0.0);
+    // seed: R into Y (as scratch), then g into G[0]
+    ls_residual_kernel<K, LPR><<<dim3(rblocks), dim3(kBlock), 0, s>>>(
+        n, (const double*)X_final, w, cf, P_col, P_val, cal, dL, Y);
+    ls_seed_kernel<K, LPR><<<dim3(rblocks), dim3(kBlock), 0, s>>>(n, A->row_ptr, A->col, cf, P_col,
+                                                                   P_val, cal, Y, G[0]);
+    AD_HIP(hipGetLastError());
+    int cur = 0;
+    const int nseg = (sweeps + ce - 1) / ce;
+    for (int q = nseg - 1; q >= 0; --q) {
+        const int s0 = q * ce;
+        const int s1 = (s0 + ce < sweeps) ? s0 + ce : sweeps;  // segment sweeps s0 .. s1-1
+        const double* xck = (const double*)((const char*)ckpt + (size_t)q * panel);
+        // recompute x^{s0+1} .. x^{s1-1}
+        LaunchCfg cfg;
+        for (int r = 1; r < s1 - s0; ++r) {
+            const void* src = (r == 1) ? (const void*)xck : (const void*)(Xr + (size_t)(r - 2) * n * K);
+            rc = launch_jacobi(AD_F64, K, A, src, Xr + (size_t)(r - 1) * n * K, omega, h->status, cfg, s);
+            if (rc) return rc;
+        }
+        for (int st = s1 - 1; st >= s0; --st) {
+            const double* xs = (st == s0) ? xck : Xr + (size_t)(st - s0 - 1) * n * K;
+            dinv_kernel<K, LPR><<<dim3(rblocks), dim3(kBlock), 0, s>>>(n, diag, G[cur], Y);
+            adjoint_sweep_kernel<K, LPR><<<dim3(rblocks), dim3(kBlock), 0, s>>>(
+                n, A->row_ptr, A->col, av, tp, diag, xs, Y, G[cur], G[cur ^ 1], omega, grad_val,
+                wp + (size_t)st * rblocks);
+            AD_HIP(hipGetLastError());
+            cur ^= 1;
+        }
+    }
+    sum_partials_kernel<<<dim3(1), dim3(1024), 0, s>>>(wp, (int64_t)rblocks * sweeps, grad_omega);
+    AD_HIP(hipGetLastError());
+    return AD_OK;
+}
+
+int launch_ls_loss_backward(ad_handle h, int K, const ad_csr* A, const void* ckpt, int ce,
+                            int sweeps, double omega, const double* w, const uint8_t* cf,
+                            const int32_t* P_col, const double* P_val, int cal,
+                            const void* X_final, const double* dL, double* grad_val,
+                            double* grad_omega, hipStream_t s) {
+    switch (K) {
+        case 2: return adjoint_go<2>(h, A, ckpt, ce, sweeps, omega, w, cf, P_col, P_val, cal, X_final, dL, grad_val, grad_omega, s);
+        case 4: return adjoint_go<4>(h, A, ckpt, ce, sweeps, omega, w, cf, P_col, P_val, cal, X_final, dL, grad_val, grad_omega, s);
+        case 8: return adjoint_go<8>(h, A, ckpt, ce, sweeps, omega, w, cf, P_col, P_val, cal, X_final, dL, grad_val, grad_omega, s);
+        case 16: return adjoint_go<16>(h, A, ckpt, ce, sweeps, omega, w, cf, P_col, P_val, cal, X_final, dL, grad_val, grad_omega, s);
+        case 32: return adjoint_go<32>(h, A, ckpt, ce, sweeps, omega, w, cf, P_col, P_val, cal, X_final, dL, grad_val, grad_omega, s);
+        case 64: return adjoint_go<64>(h, A, ckpt, ce, sweeps, omega, w, cf, P_col, P_val, cal, X_final, dL, grad_val, grad_omega, s);
+        default: return AD_EINVAL;
+    }
+}
+
+}  // namespace ad

@@ -403,4 +403,34 @@ int ls_interp(ad_handle h, const ad_csr* A, int32_t K, const void* X, const doub
     return rc ? fail(h, rc, "ls_interp launch") : AD_OK;
 }
 
+int ls_interp_loss_backward(ad_handle h, const ad_csr* A, int32_t K, const void* ckpt,
+                            int32_t ckpt_every, int32_t sweeps, double omega, const double* w,
+                            const uint8_t* cf, const int32_t* P_col, const double* P_val,
+                            int32_t caliber, const void* X_final, const double* dL,
+                            double* grad_val, double* grad_omega, void* stream) {
+    if (!h) return AD_EINVAL;
+    h->err.clear();
+    int rc = check_csr(h, A);
+    if (rc) return rc;
+    if (A->dtype != AD_F64) return fail(h, AD_EDTYPE, "the backward pass is FP64 only");
+    if (!k_ok(K)) return fail(h, AD_EINVAL, "K = %d: must be 2, 4, 8, 16, 32 or 64", K);
+    if (sweeps < 0) return fail(h, AD_EINVAL, "sweeps = %d < 0", sweeps);
+    if (ckpt_every < 1) return fail(h, AD_EINVAL, "ckpt_every = %d < 1", ckpt_every);
+    if (caliber < 1 || caliber > 8) return fail(h, AD_ECALIBER, "caliber = %d outside [1, 8]", caliber);
+    if (!grad_omega || !dL) return fail(h, AD_EINVAL, "grad_omega or dL is NULL");
+    if (A->n > 0 && (!ckpt || !X_final || !cf || !P_col || !P_val || !grad_val))
+        return fail(h, AD_EINVAL, "null input or output array");
+    if ((rc = check_panel(h, ckpt, "ckpt", A->n)) || (rc = check_panel(h, X_final, "X_final", A->n)))
+        return rc;
+    AD_HIP(hipSetDevice(h->device));
+    if (A->n == 0) {
+        AD_HIP(hipMemsetAsync(grad_omega, 0, sizeof(double), (hipStream_t)stream));
+        return AD_OK;
+    }
+    TimedScope ts(h, "ls_loss_backward", (hipStream_t)stream);
+    rc = launch_ls_loss_backward(h, K, A, ckpt, ckpt_every, sweeps, omega, w, cf, P_col, P_val,
+                                 caliber, X_final, dL, grad_val, grad_omega, (hipStream_t)stream);
+    return rc ? fail(h, rc, "ls_interp_loss_backward launch") : AD_OK;
+}
+
 }  // extern "C"

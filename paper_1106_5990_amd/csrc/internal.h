@@ -150,6 +150,13 @@ int launch_ls_interp(int dtype, int K, int caliber, const ad_csr* A, const void*
                      const LaunchCfg& cfg, hipStream_t s);
 int ls_interp_blocks(int dtype, int K, int n, const LaunchCfg& cfg);
 
+// ---- adjoint.hip
+int launch_ls_loss_backward(ad_handle h, int K, const ad_csr* A, const void* ckpt, int ce,
+                            int sweeps, double omega, const double* w, const uint8_t* cf,
+                            const int32_t* P_col, const double* P_val, int cal,
+                            const void* X_final, const double* dL, double* grad_val,
+                            double* grad_omega, hipStream_t s);
+
 inline int grid_for_tiles(int64_t ntiles) {
     int64_t per = (ntiles + 7) / 8;
     return (int)(8 * (per > 0 ? per : 1));

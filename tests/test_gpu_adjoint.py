@@ -1,0 +1,171 @@
+"""The adjoint of the LS interpolation loss on the GPU: against the oracle's
+gradient (every entry), against central finite differences of the GPU loss
+at the full 512^2 size (omega, sampled entries including diagonals and
+boundary rows, random directions), checkpoint-interval invariance and the
+torch.autograd.Function."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1106_5990_amd import workloads as W
+from gpu_common import lib, say, to_np
+
+pytestmark = pytest.mark.gpu
+
+
+def skewed(A, seed):
+    """Same pattern, values made non-symmetric (a_ij != a_ji)."""
+    rid = A.row_ids()
+    f = 1.0 + 0.3 * np.random.default_rng(seed).random(A.nnz)
+    return W.CSR(A.n, A.row_ptr, A.col, np.where(A.col != rid, A.val * f, A.val))
+
+
+def gpu_loss_and_grad(A, K, seed, sweeps, omega, cf, cal, w=None, ce=2):
+    ad = lib()
+    vals = torch.as_tensor(A.val, dtype=torch.float64, device="cuda").requires_grad_(True)
+    om = torch.tensor(omega, dtype=torch.float64, device="cuda", requires_grad=True)
+    rp = torch.as_tensor(A.row_ptr, device="cuda")
+    col = torch.as_tensor(A.col, device="cuda")
+    cft = torch.as_tensor(cf, device="cuda")
+    wt = None if w is None else torch.as_tensor(w, device="cuda")
+    L = ad.LSInterpLoss.apply(vals, om, rp, col, K, seed, sweeps, cft, cal, ce, wt)
+    gv, go = torch.autograd.grad(L, (vals, om))
+    return float(L), to_np(gv), float(go)
+
+
+@pytest.mark.parametrize("weighted", [False, True])
+@pytest.mark.parametrize("skew", [False, True])
+def test_adjoint_matches_oracle(weighted, skew):
+    say("adjoint vs oracle weighted=%s skew=%s" % (weighted, skew))
+    N, K, sweeps, omega, cal = 40, 16, 6, 0.7, 4
+    A = W.lognormal_2d_5pt(N, 1.0, 5995)
+    if skew:
+        A = skewed(A, 3)
+    cf = W.cf_red_is_coarse((N, N))
+    w = (0.5 + np.random.default_rng(1).random(K)) if weighted else None
+    L, g, gw = gpu_loss_and_grad(A, K, 1111, sweeps, omega, cf, cal, w)
+    Lr, gr, gwr = oracle.ls_loss_grad(A, oracle.tv_init(A.n, K, 1111), sweeps, omega, w, cf, cal)
+    say("  L %.12g vs %.12g; domega %.12g vs %.12g" % (L, Lr, gw, gwr))
+    assert abs(L - Lr) <= 1e-12 * abs(Lr)
+    assert abs(gw - gwr) <= 1e-10 * abs(gwr)
+    scale = np.abs(gr).max()
+    err = np.abs(g - gr)
+    say("  max |dg| / max|g| = %.3g" % (err.max() / scale))
+    assert np.all(err <= 1e-10 * np.maximum(np.abs(gr), 1e-3 * scale))
+    assert lib().status(clear=True) == 0
+
+
+def test_checkpoint_interval_does_not_change_the_gradient():
+    say("adjoint checkpoint intervals")
+    N, K = 32, 8
+    A = skewed(W.lognormal_2d_5pt(N, 1.0, 7), 9)
+    cf = W.cf_red_is_coarse((N, N))
+    ref = None
+    for ce in (1, 2, 3, 6, 7):
+        L, g, gw = gpu_loss_and_grad(A, K, 5, 6, 0.6, cf, 4, ce=ce)
+        if ref is None:
+            ref = (L, g, gw)
+        assert L == ref[0] and np.array_equal(g, ref[1]) and gw == ref[2], ce
+
+
+def test_zero_sweeps_and_asymmetric_pattern_flag():
+    ad = lib()
+    say("adjoint: zero sweeps, asymmetric pattern")
+    N, K = 12, 4
+    A = W.lognormal_2d_5pt(N, 1.0, 2)
+    cf = W.cf_red_is_coarse((N, N))
+    L, g, gw = gpu_loss_and_grad(A, K, 3, 0, 0.5, cf, 4)
+    Lr, gr, gwr = oracle.ls_loss_grad(A, oracle.tv_init(A.n, K, 3), 0, 0.5, None, cf, 4)
+    assert abs(L - Lr) <= 1e-12 * Lr and np.all(g == 0) and gw == 0.0 and np.all(gr == 0)
+    # drop one off-diagonal entry (row 5, its first neighbour): pattern no longer symmetric
+    rp = A.row_ptr.copy()
+    drop = A.row_ptr[5]
+    keep = np.ones(A.nnz, bool)
+    keep[drop] = False
+    rp[6:] -= 1
+    B = W.CSR(A.n, rp, A.col[keep], A.val[keep])
+    ad.status(clear=True)
+    gpu_loss_and_grad(B, K, 3, 2, 0.5, cf, 4)
+    assert ad.status(clear=True) & ad.STAT_ASYMMETRIC
+
+
+def test_adjoint_against_central_differences_full_size():
+    """Workload 5 at full size (512^2 log-normal 5-point, K = 16, 6 sweeps,
+    learnable omega, checkpoints every 2 sweeps): central differences with
+    h = 1e-6 max(1, |theta|) on omega, 4096 sampled entries (diagonals and
+    boundary rows included) and 16 random directions;
+    |g - g_FD| <= 1e-5 |g_FD| + 1e-9 max|g|."""
+    ad = lib()
+    wl = W.workload(5)
+    A = wl.A
+    say("adjoint FD, workload %s" % wl.name)
+    K, sweeps, omega, cal = wl.K, wl.sweeps, wl.omega, wl.caliber
+    dev = "cuda"
+    rp = torch.as_tensor(A.row_ptr, device=dev)
+    col = torch.as_tensor(A.col, device=dev)
+    cf = torch.as_tensor(wl.cf, device=dev)
+    v0 = torch.as_tensor(A.val, dtype=torch.float64, device=dev)
+    nck = -(-sweeps // 2)
+    ck = torch.empty((nck, A.n, K), dtype=torch.float64, device=dev)
+    X = torch.empty((A.n, K), dtype=torch.float64, device=dev)
+    mu = torch.empty(A.nnz, dtype=torch.float64, device=dev)
+    outs = [torch.empty((A.n, cal), dtype=torch.int32, device=dev),
+            torch.empty((A.n, cal), dtype=torch.float64, device=dev),
+            torch.empty(A.n, dtype=torch.float64, device=dev),
+            torch.empty(A.n, dtype=torch.int32, device=dev),
+            torch.empty(1, dtype=torch.float64, device=dev)]
+
+    def loss(vals, om):
+        Ad = ad.Csr(rp, col, vals)
+        ad.setup_testvectors(Ad, K, seed=wl.tv_seed, relax="jacobi", sweeps=sweeps, omega=om,
+                             out=X, ckpt=ck, ckpt_every=2)
+        ad.algebraic_distance(Ad, X, mu=mu)
+        ad.ls_interp(Ad, X, cf, mu, cal, P_col=outs[0], P_val=outs[1], ls_val=outs[2],
+                     row_status=outs[3], ls_sum=outs[4], want_sum=True)
+        return float(outs[4])
+
+    L0 = loss(v0, omega)
+    Ad = ad.Csr(rp, col, v0)
+    one = torch.ones(1, dtype=torch.float64, device=dev)
+    g, gw = ad.ls_interp_loss_backward(Ad, K, ck, 2, sweeps, omega, cf, outs[0], outs[1], X, one)
+    g = to_np(g)
+    gw = float(gw)
+    gmax = np.abs(g).max()
+    say("  L = %.10g, dL/domega = %.10g, max|g| = %.4g" % (L0, gw, gmax))
+
+    def check(fd, an, what):
+        ok = abs(an - fd) <= 1e-5 * abs(fd) + 1e-9 * gmax
+        assert ok, "%s: adjoint %.10g FD %.10g" % (what, an, fd)
+
+    h = 1e-6 * max(1.0, abs(omega))
+    check((loss(v0, omega + h) - loss(v0, omega - h)) / (2 * h), gw, "omega")
+    rng = np.random.default_rng(0)
+    rid = A.row_ids()
+    diag = np.nonzero(A.col == rid)[0]
+    N = A.grid[0]
+    iy, ix = np.divmod(rid, N)
+    boundary = np.nonzero((ix == 0) | (iy == 0) | (ix == N - 1) | (iy == N - 1))[0]
+    sample = np.unique(np.concatenate([rng.choice(A.nnz, 3584, replace=False),
+                                       rng.choice(diag, 256, replace=False),
+                                       rng.choice(boundary, 256, replace=False)]))
+    worst = 0.0
+    for e in sample:
+        he = 1e-6 * max(1.0, abs(A.val[e]))
+        vp = v0.clone()
+        vp[e] += he
+        vm = v0.clone()
+        vm[e] -= he
+        fd = (loss(vp, omega) - loss(vm, omega)) / (2 * he)
+        worst = max(worst, abs(g[e] - fd) / (1e-5 * abs(fd) + 1e-9 * gmax))
+        check(fd, g[e], "entry %d" % e)
+    say("  %d entries: worst err / bound = %.3g" % (len(sample), worst))
+    for q in range(16):
+        d = rng.standard_normal(A.nnz)
+        dw = rng.standard_normal()
+        dt = torch.as_tensor(d, device=dev)
+        hd = 1e-6
+        fd = (loss(v0 + hd * dt, omega + hd * dw) - loss(v0 - hd * dt, omega - hd * dw)) / (2 * hd)
+        an = float(g @ d + gw * dw)
+        assert abs(an - fd) <= 1e-5 * abs(fd) + 1e-9 * gmax * np.abs(d).sum() / np.sqrt(len(d)), q
+    assert ad.status(clear=True) == 0
