@@ -115,7 +115,7 @@ int algdist_timing(ad_handle h, int enable);
 const char *algdist_timing_report(ad_handle h);
 
 /* Launch shape of one kernel family, for a (dtype, K, stored-entries-per-row
- * bucket) key.  kernel: "jacobi", "gs_phase", "algdist" or "ls_interp".
+ * bucket) key.  kernel: "jacobi", "gs_phase", "algdist", "ls_interp" or "batched".
  * bucket: 0 (< 8 entries per row), 1 (< 16), 2 (< 32), 3 (>= 32), or -1 for
  * all four.  lanes_per_row: lanes sharing one panel row (0 = default; must
  * divide K with K / lanes_per_row entries per lane fitting 64 bytes and
@@ -243,6 +243,32 @@ int ls_interp(ad_handle h, const ad_csr *A, int32_t K, const void *X, const doub
               const uint8_t *cf, const void *mu, int32_t caliber, int32_t target,
               int32_t *P_col, double *P_val, double *ls_val, int32_t *row_status,
               double *ls_sum, void *stream);
+
+/* ------------------------------------------------------------------ */
+/* batched relaxation + distances                                      */
+/* ------------------------------------------------------------------ */
+
+/* For each of nmat matrices As[m] (host array of device CSRs, one dtype):
+ * the test-vector start, `sweeps` damped-Jacobi sweeps with omega, and the
+ * distances of Sec. 4.1 (plain target) with the fused strength graph of
+ * Sec. 4.2 (theta; all rows in F) -- exactly what setup_testvectors +
+ * algebraic_distance compute for the block-diagonal matrix made of the
+ * batch -- in one persistent launch.
+ * Outputs are concatenated in matrix order: X (sum n) x K, mu (sum nnz,
+ * the CSR's dtype), strong (sum nnz, may be NULL), nstrong (sum n, may be
+ * NULL).  Start values use the global row index: entry (r, k) of the
+ * concatenated panel is the (r*K + k + 1)-th splitmix64 output from seed.
+ * w (K FP64, may be NULL) weights the distances.
+ * The first call for a given argument set builds the task table (largest
+ * matrices first) and captures the launch in a HIP graph; repeated calls
+ * with the same arguments replay it.  The batch state is owned by the
+ * handle.  Launch shape: algdist_set_launch("batched", ...) with
+ * lanes_per_row and rows_per_lane (a tile is rows_per_lane row steps of
+ * one workgroup; matrices of at most 4 tiles are run whole by one
+ * workgroup). */
+int relax_algdist_batched(ad_handle h, int32_t nmat, const ad_csr *As, int32_t K, uint64_t seed,
+                          int32_t sweeps, double omega, const double *w, void *X, void *mu,
+                          double theta, uint8_t *strong, int32_t *nstrong, void *stream);
 
 /* ------------------------------------------------------------------ */
 /* adjoint of the LS interpolation loss                                */

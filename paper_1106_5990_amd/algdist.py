@@ -68,6 +68,8 @@ _SIGS = {
     "algebraic_distance": (_i32, [_P, _CSRP, _i32, _P, _P, _i32, _P, _P, _f64, _P, _P, _P, _P]),
     "strength_graph": (_i32, [_P, _CSRP, _P, _f64, _P, _P, _P, _P]),
     "ls_interp": (_i32, [_P, _CSRP, _i32, _P, _P, _P, _P, _i32, _i32, _P, _P, _P, _P, _P, _P]),
+    "relax_algdist_batched": (_i32, [_P, _i32, _CSRP, _i32, _u64, _i32, _f64, _P, _P, _P, _f64, _P,
+                                     _P, _P]),
     "ls_interp_loss_backward": (_i32, [_P, _CSRP, _i32, _P, _i32, _i32, _f64, _P, _P, _P, _P, _i32,
                                        _P, _P, _P, _P, _P]),
 }
@@ -266,6 +268,33 @@ def ls_interp(A: Csr, X: torch.Tensor, cf: torch.Tensor, mu: torch.Tensor, calib
     _check(rc, h, "ls_interp")
     out = (P_col, P_val, ls_val, row_status)
     return out + (ls_sum,) if want_sum else out
+
+
+def relax_algdist_batched(mats, K: int, seed: int = 0, sweeps: int = 4, omega: float = 2.0 / 3.0,
+                          w: Optional[torch.Tensor] = None, theta: float = 0.25, fuse: bool = True,
+                          X: Optional[torch.Tensor] = None, mu: Optional[torch.Tensor] = None,
+                          strong: Optional[torch.Tensor] = None,
+                          nstrong: Optional[torch.Tensor] = None, stream=None):
+    """Start + Jacobi sweeps + distances (+ strength) for a list of Csr in one
+    persistent launch.  Returns (X, mu, strong, nstrong), concatenated in list
+    order (strong/nstrong None when fuse=False)."""
+    dev = mats[0].device
+    h = handle(dev.index)
+    dt = mats[0].dtype
+    rows = sum(m.n for m in mats)
+    ents = sum(m.nnz for m in mats)
+    X = X if X is not None else torch.empty((rows, K), dtype=dt, device=dev)
+    mu = mu if mu is not None else torch.empty(ents, dtype=dt, device=dev)
+    if fuse:
+        strong = strong if strong is not None else torch.empty(ents, dtype=torch.uint8, device=dev)
+        nstrong = nstrong if nstrong is not None else torch.empty(rows, dtype=torch.int32, device=dev)
+    arr = (ad_csr * len(mats))(*[m._s for m in mats])
+    rc = _lib.relax_algdist_batched(h, len(mats), arr, K, seed & (2 ** 64 - 1), sweeps, float(omega),
+                                    _ptr(w), _ptr(X), _ptr(mu), float(theta),
+                                    _ptr(strong) if fuse else None, _ptr(nstrong) if fuse else None,
+                                    _stream(stream))
+    _check(rc, h, "relax_algdist_batched")
+    return X, mu, (strong if fuse else None), (nstrong if fuse else None)
 
 
 def ls_interp_loss_backward(A: Csr, K: int, ckpt: torch.Tensor, ckpt_every: int, sweeps: int,

@@ -146,6 +146,7 @@ int algdist_destroy(ad_handle h) {
     if (h->ws) (void)hipFree(h->ws);
     if (h->status) (void)hipFree(h->status);
     for (hipEvent_t e : h->event_pool) (void)hipEventDestroy(e);
+    batch_state_free(h);
     delete h;
     return AD_OK;
 }
@@ -214,12 +215,13 @@ int algdist_set_launch(ad_handle h, const char* kernel, int32_t dtype, int32_t K
     else if (!strcmp(kernel, "gs_phase")) kn = KN_GS;
     else if (!strcmp(kernel, "algdist")) kn = KN_ALGDIST;
     else if (!strcmp(kernel, "ls_interp")) kn = KN_LS;
+    else if (!strcmp(kernel, "batched")) kn = KN_BATCHED;
     if (kn < 0) return fail(h, AD_EINVAL, "unknown kernel family '%s'", kernel);
     if (dtype != AD_F32 && dtype != AD_F64) return fail(h, AD_EDTYPE, "dtype %d", dtype);
     const int ks = k_slot(K);
     if (ks < 0) return fail(h, AD_EINVAL, "K = %d", K);
     if (bucket < -1 || bucket >= kNumBuckets) return fail(h, AD_EINVAL, "bucket %d", bucket);
-    if (rows_per_lane < 1 || rows_per_lane > 64) return fail(h, AD_EINVAL, "rows_per_lane %d", rows_per_lane);
+    if (rows_per_lane < 1 || rows_per_lane > 1024) return fail(h, AD_EINVAL, "rows_per_lane %d", rows_per_lane);
     if (lanes_per_row != 0 && !lpr_valid(dtype, K, lanes_per_row))
         return fail(h, AD_EINVAL, "lanes_per_row %d unsupported for K = %d", lanes_per_row, K);
     LaunchCfg c;
@@ -401,6 +403,39 @@ int ls_interp(ad_handle h, const ad_csr* A, int32_t K, const void* X, const doub
     rc = launch_ls_interp(A->dtype, K, caliber, A, X, w, cf, mu, target, P_col, P_val, ls_val,
                           row_status, bs, ls_sum, h->status, cfg, (hipStream_t)stream);
     return rc ? fail(h, rc, "ls_interp launch") : AD_OK;
+}
+
+int relax_algdist_batched(ad_handle h, int32_t nmat, const ad_csr* As, int32_t K, uint64_t seed,
+                          int32_t sweeps, double omega, const double* w, void* X, void* mu,
+                          double theta, uint8_t* strong, int32_t* nstrong, void* stream) {
+    if (!h) return AD_EINVAL;
+    h->err.clear();
+    if (nmat < 1 || !As) return fail(h, AD_EINVAL, "nmat = %d or As is NULL", nmat);
+    int rc;
+    int64_t rows = 0, ents = 0;
+    for (int m = 0; m < nmat; ++m) {
+        if ((rc = check_csr(h, &As[m]))) return fail(h, rc, "matrix %d: %s", m, h->err.c_str());
+        if (As[m].dtype != As[0].dtype) return fail(h, AD_EDTYPE, "matrix %d has another dtype", m);
+        rows += As[m].n;
+        ents += As[m].nnz;
+    }
+    if (!k_ok(K)) return fail(h, AD_EINVAL, "K = %d: must be 2, 4, 8, 16, 32 or 64", K);
+    if (sweeps < 0) return fail(h, AD_EINVAL, "sweeps = %d < 0", sweeps);
+    if (rows * K > ((int64_t)1 << 40)) return fail(h, AD_ESTRUCT, "batch too large");
+    if ((rc = check_panel(h, X, "X", (int)(rows > 0)))) return rc;
+    if (ents > 0 && !mu) return fail(h, AD_EINVAL, "mu is NULL");
+    if (strong && !(theta > 0.0 && theta < 1.0))
+        return fail(h, AD_EINVAL, "theta = %g outside (0, 1)", theta);
+    if (rows == 0) return AD_OK;
+    AD_HIP(hipSetDevice(h->device));
+    ad_csr probe = As[0];
+    probe.n = (int32_t)(rows / nmat > 0 ? rows / nmat : 1);
+    probe.nnz = ents / nmat;
+    const LaunchCfg cfg = cfg_for(h, KN_BATCHED, As[0].dtype, K, &probe);
+    TimedScope ts(h, "batched", (hipStream_t)stream);
+    rc = launch_batched(h, nmat, As, K, seed, sweeps, omega, w, X, mu, theta, strong, nstrong, cfg,
+                        (hipStream_t)stream);
+    return rc ? fail(h, rc, "relax_algdist_batched launch") : AD_OK;
 }
 
 int ls_interp_loss_backward(ad_handle h, const ad_csr* A, int32_t K, const void* ckpt,

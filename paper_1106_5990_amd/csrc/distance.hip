@@ -14,11 +14,9 @@
 
 #include "device.h"
 #include "internal.h"
+#include "rowops.h"
 
 namespace ad {
-
-template <typename T> struct Guard { static constexpr bool on = false; };
-template <> struct Guard<float> { static constexpr bool on = true; };
 
 template <typename T, int K, int LPR>
 __global__ __launch_bounds__(kBlock) void algdist_kernel(
@@ -28,7 +26,7 @@ __global__ __launch_bounds__(kBlock) void algdist_kernel(
     uint8_t* __restrict__ strong, int* __restrict__ nstrong, int iter, int xcd,
     unsigned* status) {
     using S = Shape<T, K, LPR>;
-    constexpr int V = S::V, C = S::C;
+    constexpr int V = S::V;
     const int lane = threadIdx.x & (kWave - 1);
     const int g = lane / LPR, l = lane % LPR;
     const int wv = threadIdx.x / kWave;
@@ -44,146 +42,13 @@ __global__ __launch_bounds__(kBlock) void algdist_kernel(
         wd[q] = w ? w[l * V + q] : 1.0;
         wt[q] = (T)wd[q];
     }
-    const bool fuse = strong != nullptr;
     const bool plain = target == AD_TARGET_PLAIN;
 
     for (int it = 0; it < iter; ++it) {
         const int64_t i64 = tile * rows_per_tile + (int64_t)it * S::RPB + wv * S::RPW + g;
         if (i64 >= n) break;
-        const int i = (int)i64;
-        const int e0 = rp[i], e1 = rp[i + 1];
-
-        // target t_i; the residual form is built in FP64 (products of two
-        // panel-type values are exact there), then rounded to the panel type
-        // for the main pass; the FP64 copy feeds the guard-band recompute.
-        Frag<T, V> t = load_lane<T, V, C>(X + (size_t)i * K + l * V);
-        double t64[V];
-#pragma unroll
-        for (int q = 0; q < V; ++q) t64[q] = (double)t.v[q];
-        if (!plain) {
-            double y[V];
-#pragma unroll
-            for (int q = 0; q < V; ++q) y[q] = 0.0;
-            double d = 0.0;
-            for (int e = e0; e < e1; ++e) {
-                const int j = ci[e];
-                const double a = (double)av[e];
-                Frag<T, V> xj = load_lane<T, V, C>(X + (size_t)j * K + l * V);
-#pragma unroll
-                for (int q = 0; q < V; ++q) y[q] = fma(a, (double)xj.v[q], y[q]);
-                if (j == i) d = a;
-            }
-            if (d != 0.0) {
-#pragma unroll
-                for (int q = 0; q < V; ++q) {
-                    t64[q] = t64[q] - y[q] / d;
-                    t.v[q] = (T)t64[q];
-                }
-            } else if (l == 0) {
-                flag(status, AD_STAT_ZERO_DIAG);
-            }
-        }
-        T wtt[V];
-        T saa = T(0);
-#pragma unroll
-        for (int q = 0; q < V; ++q) {
-            wtt[q] = wt[q] * t.v[q];
-            saa = fma(wtt[q], t.v[q], saa);
-        }
-        saa = group_sum<LPR>(saa);
-        const T guard = (T)1e-4 * saa;
-
-        const bool in_f = fmask ? (fmask[i] != 0) : true;
-        T mmin = (T)INFINITY;
-        bool bad = false;
-        // U edges per step: their column and panel loads are issued together
-        constexpr int U = (V >= 16) ? 2 : 4;
-        for (int eb = e0; eb < e1; eb += U) {
-            int jj[U];
-            Frag<T, V> xs[U];
-#pragma unroll
-            for (int u = 0; u < U; ++u) jj[u] = (eb + u < e1) ? ci[eb + u] : i;
-#pragma unroll
-            for (int u = 0; u < U; ++u) xs[u] = load_lane<T, V, C>(X + (size_t)jj[u] * K + l * V);
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const int e = eb + u;
-                if (e >= e1) break;
-                const int j = jj[u];
-                const Frag<T, V>& xj = xs[u];
-                const bool mine = ((e - e0) & (LPR - 1)) == l;
-                if (plain && j == i) {
-                    // x_i against itself: p = 1 and mu = 0 exactly
-                    if (mine) {
-                        mu[e] = T(0);
-                        if (pout) pout[e] = 1.0;
-                    }
-                    continue;
-                }
-                T sab = T(0), sbb = T(0);
-#pragma unroll
-                for (int q = 0; q < V; ++q) {
-                    sab = fma(wtt[q], xj.v[q], sab);
-                    sbb = fma(wt[q] * xj.v[q], xj.v[q], sbb);
-                }
-                sab = group_sum<LPR>(sab);
-                sbb = group_sum<LPR>(sbb);
-                T p = (sbb > T(0)) ? sab / sbb : T(0);
-                T m = T(0);
-#pragma unroll
-                for (int q = 0; q < V; ++q) {
-                    const T r = t.v[q] - p * xj.v[q];
-                    m = fma(wt[q] * r, r, m);
-                }
-                m = group_sum<LPR>(m);
-                double pd = (double)p;
-                if (Guard<T>::on && m < guard) {
-                    // FP64 recompute from the same FP32 inputs
-                    double a2 = 0.0, b2 = 0.0;
-#pragma unroll
-                    for (int q = 0; q < V; ++q) {
-                        const double xq = (double)xj.v[q], tq = t64[q];
-                        a2 = fma(wd[q] * tq, xq, a2);
-                        b2 = fma(wd[q] * xq, xq, b2);
-                    }
-                    a2 = group_sum<LPR>(a2);
-                    b2 = group_sum<LPR>(b2);
-                    pd = (b2 > 0.0) ? a2 / b2 : 0.0;
-                    double m2 = 0.0;
-#pragma unroll
-                    for (int q = 0; q < V; ++q) {
-                        const double r = t64[q] - pd * (double)xj.v[q];
-                        m2 = fma(wd[q] * r, r, m2);
-                    }
-                    m = (T)group_sum<LPR>(m2);
-                }
-                bad |= !isfinite(m);
-                if (mine) {
-                    mu[e] = m;
-                    if (pout) pout[e] = pd;
-                }
-                if (j != i && (!fmask || fmask[j])) mmin = (m < mmin) ? m : mmin;
-            }
-        }
-        if (bad && l == 0) flag(status, AD_STAT_NONFINITE);
-
-        if (fuse) {
-            // second pass: each lane re-reads the mu values it stored
-            int cnt = 0;
-            const double md = (double)mmin;
-            for (int e = e0 + l; e < e1; e += LPR) {
-                const int j = ci[e];
-                int s = 0;
-                if (in_f && j != i && (!fmask || fmask[j])) {
-                    const double me = (double)mu[e];
-                    s = (md > 0.0) ? (theta * me < md) : (me == 0.0);
-                }
-                strong[e] = (uint8_t)s;
-                cnt += s;
-            }
-            cnt = group_sum<LPR>(cnt);
-            if (l == 0 && nstrong) nstrong[i] = cnt;
-        }
+        algdist_row<S, T, K>((int)i64, l, rp, ci, av, X, wd, wt, plain, mu, pout, theta, fmask,
+                             strong, nstrong, status);
     }
 }
 

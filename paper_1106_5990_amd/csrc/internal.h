@@ -25,7 +25,7 @@ struct LaunchCfg {
     int iter = 1;     // row-block steps per workgroup (rows per lane group per tile)
     int xcd_map = 1;  // 1: XCD-contiguous tile mapping
 };
-enum KernelId { KN_JACOBI = 0, KN_GS = 1, KN_ALGDIST = 2, KN_LS = 3, KN_COUNT = 4 };
+enum KernelId { KN_JACOBI = 0, KN_GS = 1, KN_ALGDIST = 2, KN_LS = 3, KN_BATCHED = 4, KN_COUNT = 5 };
 constexpr int kNumKSlots = 7;   // log2(K) for K = 2 .. 64
 constexpr int kNumBuckets = 4;  // stored entries per row: < 8, < 16, < 32, >= 32
 }  // namespace ad
@@ -46,6 +46,7 @@ struct ad_handle_s {
     // launch configurations set by algdist_set_launch / algdist_autotune
     ad::LaunchCfg tuned[ad::KN_COUNT][2][ad::kNumKSlots][ad::kNumBuckets];
     bool has_tuned[ad::KN_COUNT][2][ad::kNumKSlots][ad::kNumBuckets] = {};
+    void* batch = nullptr;  // state of the batched path (batched.hip)
 };
 
 namespace ad {
@@ -149,6 +150,12 @@ int launch_ls_interp(int dtype, int K, int caliber, const ad_csr* A, const void*
                      double* block_sums, double* ls_sum, unsigned* status,
                      const LaunchCfg& cfg, hipStream_t s);
 int ls_interp_blocks(int dtype, int K, int n, const LaunchCfg& cfg);
+
+// ---- batched.hip
+int launch_batched(ad_handle h, int nmat, const ad_csr* As, int K, uint64_t seed, int sweeps,
+                   double omega, const double* w, void* X, void* mu, double theta,
+                   uint8_t* strong, int32_t* nstrong, const LaunchCfg& cfg, hipStream_t s);
+void batch_state_free(ad_handle h);
 
 // ---- adjoint.hip
 int launch_ls_loss_backward(ad_handle h, int K, const ad_csr* A, const void* ckpt, int ce,

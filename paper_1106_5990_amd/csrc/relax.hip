@@ -9,6 +9,7 @@
 // through L2 (the tile mapping keeps a row range on one XCD).
 #include "device.h"
 #include "internal.h"
+#include "rowops.h"
 
 namespace ad {
 
@@ -47,54 +48,6 @@ int launch_tv_init(int dtype, int64_t row0, int64_t nrows, int K, uint64_t seed,
     return AD_OK;
 }
 
-// ---------------------------------------------------------------- row SpMM core
-// y = sum_e a_e x_{col e} over the row's entries, in CSR order (FMA per term);
-// also returns the diagonal value and the row's own fragment.
-// pick(j) chooses which panel a neighbour is read from.
-template <typename S, typename T, int K, typename Pick>
-__device__ __forceinline__ void row_spmm(int i, int e0, int e1, const int* __restrict__ ci,
-                                         const T* __restrict__ av, int l, Pick pick,
-                                         T (&y)[S::V], T& d, Frag<T, S::V>& xi) {
-    constexpr int V = S::V, C = S::C;
-    constexpr int U = (V >= 16) ? 2 : 4;  // independent gathers in flight per step
-#pragma unroll
-    for (int q = 0; q < V; ++q) y[q] = T(0);
-    d = T(0);
-    int e = e0;
-    for (; e + U <= e1; e += U) {
-        int j[U];
-        T a[U];
-        Frag<T, V> x[U];
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            j[u] = ci[e + u];
-            a[u] = av[e + u];
-        }
-#pragma unroll
-        for (int u = 0; u < U; ++u) x[u] = load_lane<T, V, C>(pick(j[u]) + (size_t)j[u] * K + l * V);
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-#pragma unroll
-            for (int q = 0; q < V; ++q) y[q] = fma(a[u], x[u].v[q], y[q]);
-            if (j[u] == i) {
-                d = a[u];
-                xi = x[u];
-            }
-        }
-    }
-    for (; e < e1; ++e) {
-        const int j = ci[e];
-        const T a = av[e];
-        Frag<T, V> x = load_lane<T, V, C>(pick(j) + (size_t)j * K + l * V);
-#pragma unroll
-        for (int q = 0; q < V; ++q) y[q] = fma(a, x.v[q], y[q]);
-        if (j == i) {
-            d = a;
-            xi = x;
-        }
-    }
-}
-
 // ---------------------------------------------------------------- Jacobi
 // x_new = x - omega * (A x) / a_ii  (row held fixed if a_ii == 0)
 template <typename T, int K, int LPR>
@@ -105,7 +58,6 @@ __global__ __launch_bounds__(kBlock) void jacobi_kernel(int n, const int* __rest
                                                         T* __restrict__ Xout, T omega, int iter,
                                                         int xcd, unsigned* status) {
     using S = Shape<T, K, LPR>;
-    constexpr int V = S::V, C = S::C;
     const int lane = threadIdx.x & (kWave - 1);
     const int g = lane / LPR, l = lane % LPR;
     const int wv = threadIdx.x / kWave;
@@ -116,19 +68,7 @@ __global__ __launch_bounds__(kBlock) void jacobi_kernel(int n, const int* __rest
     for (int it = 0; it < iter; ++it) {
         const int64_t i64 = tile * rows_per_tile + (int64_t)it * S::RPB + wv * S::RPW + g;
         if (i64 >= n) break;
-        const int i = (int)i64;
-        T y[V], d;
-        Frag<T, V> xi;
-        row_spmm<S, T, K>(i, rp[i], rp[i + 1], ci, av, l, [&](int) { return Xin; }, y, d, xi);
-        Frag<T, V> out;
-        if (d == T(0)) {
-            out = load_lane<T, V, C>(Xin + (size_t)i * K + l * V);
-            if (l == 0) flag(status, AD_STAT_ZERO_DIAG);
-        } else {
-#pragma unroll
-            for (int q = 0; q < V; ++q) out.v[q] = xi.v[q] - omega * y[q] / d;
-        }
-        store_lane<T, V, C>(Xout + (size_t)i * K + l * V, out);
+        jacobi_row<S, T, K>((int)i64, l, rp, ci, av, Xin, Xout, omega, status);
     }
 }
 

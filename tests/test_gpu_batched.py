@@ -1,0 +1,102 @@
+"""The batched persistent path against the single-matrix kernels run on the
+block-diagonal concatenation of the batch (bitwise: same per-row code and
+the same start stream), against the oracle, under graph replay, with tiny
+tiles (many inter-workgroup dependencies) and with empty members."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1106_5990_amd import workloads as W
+from gpu_common import check_mu, lib, say, to_np
+
+pytestmark = pytest.mark.gpu
+
+
+def batch(sizes, seed=0):
+    return [W.rgg_laplacian(int(n), 6.0 + (q * 7) % 23, (seed, q)) for q, n in enumerate(sizes)]
+
+
+def reference(mats, dtype, K, seed, sweeps, omega, theta):
+    ad = lib()
+    B = W.concat_csr(mats)
+    Bd = ad.Csr.from_host(B, dtype=dtype)
+    X = ad.setup_testvectors(Bd, K, seed=seed, relax="jacobi", sweeps=sweeps, omega=omega)
+    mu, s, ns = ad.algebraic_distance(Bd, X, fuse=True, theta=theta)
+    return B, X, mu, s, ns
+
+
+@pytest.mark.parametrize("dt", [torch.float32, torch.float64])
+@pytest.mark.parametrize("K", [16, 8])
+def test_batched_equals_concatenated_single_matrix_path(dt, K):
+    ad = lib()
+    say("batched vs concatenated %s K=%d" % (dt, K))
+    mats = batch([300, 2500, 9000, 17000, 40000, 1200, 6100, 23000], seed=1)
+    dm = [ad.Csr.from_host(m, dtype=dt) for m in mats]
+    ad.status(clear=True)
+    X, mu, s, ns = ad.relax_algdist_batched(dm, K, seed=42, sweeps=4, omega=2 / 3, theta=0.25)
+    B, Xr, mur, sr, nsr = reference(mats, dt, K, 42, 4, 2 / 3, 0.25)
+    assert torch.equal(X, Xr)
+    assert torch.equal(mu, mur)
+    assert torch.equal(s, sr) and torch.equal(ns, nsr)
+    assert ad.status(clear=True) == 0
+    # and against the oracle on the concatenation
+    Bo = W.CSR(B.n, B.row_ptr, B.col, to_np(Bd_vals(B, dt)))
+    x = to_np(X).astype(np.float64)
+    mu_ref = oracle.algdist(Bo, x)
+    check_mu(to_np(mu).astype(np.float64), mu_ref, (x * x).sum(1)[B.row_ids()], dt)
+    s_ref, ns_ref = oracle.strength(B, to_np(mu).astype(np.float64), 0.25)
+    assert np.array_equal(to_np(s), s_ref) and np.array_equal(to_np(ns), ns_ref)
+
+
+def Bd_vals(B, dt):
+    return torch.as_tensor(B.val).to(dt).to(torch.float64)
+
+
+def test_batched_replay_tiny_tiles_and_edge_members():
+    ad = lib()
+    say("batched: replay, tiny tiles, empty members")
+    dt, K = torch.float32, 16
+    mats = batch([5000, 0, 1, 30000, 700], seed=2)
+    mats[1] = W.CSR(0, np.zeros(1, np.int32), np.zeros(0, np.int32), np.zeros(0))
+    dm = [ad.Csr.from_host(m, dtype=dt) for m in mats]
+    B, Xr, mur, sr, nsr = reference(mats, dt, K, 7, 3, 0.6, 0.3)
+    outs = []
+    try:
+        for it in (16, 1, 3):  # tile of it row steps; it=1 -> 128-row tiles, many dependencies
+            ad.set_launch("batched", dt, K, 0, it, True)
+            for rep in range(3):  # first call captures a graph, later ones replay it
+                X, mu, s, ns = ad.relax_algdist_batched(dm, K, seed=7, sweeps=3, omega=0.6, theta=0.3)
+                assert torch.equal(X, Xr) and torch.equal(mu, mur), (it, rep)
+                assert torch.equal(s, sr) and torch.equal(ns, nsr), (it, rep)
+        # timing mode launches without the graph
+        ad.timing(True)
+        X, mu, s, ns = ad.relax_algdist_batched(dm, K, seed=7, sweeps=3, omega=0.6, theta=0.3)
+        rep = ad.timing_report()
+        ad.timing(False)
+        assert "batched" in rep and torch.equal(X, Xr) and torch.equal(mu, mur)
+    finally:
+        ad.set_launch("batched", dt, K, 0, 16, True)
+    assert ad.status(clear=True) == 0
+    # zero sweeps: the start itself, then distances
+    X, mu, s, ns = ad.relax_algdist_batched(dm, K, seed=9, sweeps=0, theta=0.3)
+    B, Xr, mur, sr, nsr = reference(mats, dt, K, 9, 0, 0.6, 0.3)
+    assert torch.equal(X, Xr) and torch.equal(mu, mur) and torch.equal(s, sr)
+
+
+def test_batched_every_lane_shape():
+    ad = lib()
+    dt, K = torch.float32, 16
+    mats = batch([4000, 15000, 800], seed=3)
+    dm = [ad.Csr.from_host(m, dtype=dt) for m in mats]
+    for lpr in (1, 2, 4):
+        say("batched lpr=%d" % lpr)
+        try:
+            ad.set_launch("batched", dt, K, lpr, 4, True)
+            ad.set_launch("algdist", dt, K, lpr, 1, True)
+            X, mu, s, ns = ad.relax_algdist_batched(dm, K, seed=5, sweeps=4, omega=2 / 3, theta=0.25)
+            B, Xr, mur, sr, nsr = reference(mats, dt, K, 5, 4, 2 / 3, 0.25)
+            assert torch.equal(X, Xr) and torch.equal(mu, mur) and torch.equal(s, sr), lpr
+        finally:
+            ad.set_launch("batched", dt, K, 0, 16, True)
+            ad.set_launch("algdist", dt, K, 0, 1, True)
