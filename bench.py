@@ -41,6 +41,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=None, help="grid side of the oracle sample")
     ap.add_argument("--graph", action="store_true", help="replay the step as a captured HIP graph")
+    ap.add_argument("--no-batched", action="store_true", help="skip the batched leg (workload 4)")
+    ap.add_argument("--batch-size", type=int, default=512)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one 1 GiB device-to-device copy (a kernel of known traffic "
                          "for scaling hardware byte counters)")
@@ -131,13 +133,20 @@ def kernel_bytes(wl, s):
     out = {"tv_init": panel}
     out["jacobi"] = (n + 1) * 4 + nnz * (4 + s) + 2 * panel
     if wl.color is not None:
+        # colour phases run on colour-major permuted panels: a phase reads
+        # its rows' list entries, row pointers, permuted columns and values,
+        # every panel row once (new rows of earlier colours, old otherwise)
+        # and writes its rows once
         per = []
         for c in range(wl.ncolors):
             rows = wl.color == c
             nc_, nnzc = int(rows.sum()), int(deg[rows].sum())
-            per.append(nc_ * (4 + 8) + nnzc * (4 + s) + panel + nc_ * K * s + (n * 4 if c > 0 else 0))
+            per.append(nc_ * (4 + 8) + nnzc * (4 + s) + panel + nc_ * K * s)
         out["gs_phase"] = float(np.mean(per))
-        out["color_partition"] = n * 4 * 3
+        # partition (3 passes over the colours), inverse permutation,
+        # permuted columns (read col, gather, write)
+        out["color_partition"] = n * 4 * 3 + n * 4 * 2 + nnz * 4 * 2
+        out["tv_init"] = panel + n * 4
     out["algdist"] = (n + 1) * 4 + nnz * 4 + panel + nnz * s + nnz + n * 4
     F = wl.cf == 0
     nnzF = int(deg[F].sum())
@@ -155,6 +164,102 @@ def step_bytes(wl, s, kb):
     else:
         b += sweeps * kb["jacobi"]
     return b
+
+
+KERNEL_SYMBOL = {"gs_phase": "gs_phase_perm_kernel", "jacobi": "jacobi_kernel",
+                 "algdist": "algdist_kernel", "ls_interp": "ls_interp_kernel",
+                 "tv_init": "start_perm_kernel", "batched": "batched_kernel"}
+
+
+def source_hash():
+    """Hash of the HIP sources: counter summaries are valid only for it."""
+    import glob
+    import hashlib
+    here = os.path.dirname(os.path.abspath(__file__))
+    h = hashlib.sha256()
+    for p in sorted(glob.glob(os.path.join(here, "paper_1106_5990_amd", "csrc", "*"))):
+        with open(p, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def counter_traffic(workload_tag, label):
+    """HBM bytes per launch of `label` from the committed rocprofv3 counter
+    summary of this workload (FETCH_SIZE x its copy-calibration factor +
+    WRITE_SIZE x its factor), or None if absent or taken on other sources."""
+    here = os.path.dirname(os.path.abspath(__file__))
+    path = os.path.join(here, "profiles", "hbm_counters_%s.txt" % workload_tag)
+    if not os.path.exists(path):
+        return None
+    rows, meta = [], {}
+    for line in open(path):
+        line = line.strip()
+        if line.startswith("# source-hash:"):
+            meta["hash"] = line.split(":", 1)[1].strip()
+        elif line.startswith("# scale:"):
+            f, w = line.split(":", 1)[1].split()
+            meta["fs"], meta["ws"] = float(f), float(w)
+        elif line and not line.startswith("#") and "|" in line and not line.startswith("kernel"):
+            rows.append([c.strip() for c in line.split("|")])
+    if meta.get("hash") != source_hash() or "fs" not in meta:
+        return None
+    sym = KERNEL_SYMBOL.get(label)
+    tot, cnt = 0.0, 0
+    for r in rows:
+        if sym and r[0].split("<")[0].endswith(sym):
+            d = int(r[1])
+            tot += d * (float(r[2]) * meta["fs"] + float(r[3]) * meta["ws"]) * 1024.0
+            cnt += d
+    return tot / cnt if cnt else None
+
+
+def batched_leg(args, torch, ad, W):
+    """Workload 4: the RGG batch through relax_algdist_batched (graph replay)."""
+    workers = min(16, os.cpu_count() or 1)
+    mats = W.batch_workload(args.batch_size, workers=workers)
+    K, S, om, th = W.BATCH_K, W.BATCH_SWEEPS, W.BATCH_OMEGA, W.BATCH_THETA
+    E = sum(m.n_edges for m in mats)
+    rows = sum(m.n for m in mats)
+    ents = sum(m.nnz for m in mats)
+    out = {"workload": "rgg-batch-%d (n log-uniform 2k-200k, mean degree U[4,29]), K=%d, %d Jacobi "
+                       "sweeps, theta=%g" % (len(mats), K, S, th),
+           "matrices": len(mats), "rows": rows, "nnz": ents, "edges": E}
+    for tag, dt, s in (("f32", torch.float32, 4), ("f64", torch.float64, 8)):
+        dm = [ad.Csr.from_host(m, dtype=dt) for m in mats]
+        X = torch.empty((rows, K), dtype=dt, device="cuda")
+        mu = torch.empty(ents, dtype=dt, device="cuda")
+        st = torch.empty(ents, dtype=torch.uint8, device="cuda")
+        ns = torch.empty(rows, dtype=torch.int32, device="cuda")
+
+        def run():
+            ad.relax_algdist_batched(dm, K, seed=W.TV_SEED_BASE + 4, sweeps=S, omega=om, theta=th,
+                                     X=X, mu=mu, strong=st, nstrong=ns)
+        for _ in range(args.warmup):
+            run()
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        steps = max(3, args.steps // 2)
+        e0.record()
+        for _ in range(steps):
+            run()
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        # minimal HBM bytes: CSR read once, start never stored except as X,
+        # outputs written once (sweeps stay on chip or in L2 for small members)
+        minimal = (rows + len(mats)) * 4 + ents * (4 + s) + rows * K * s + ents * (s + 1) + rows * 4
+        # every sweep through HBM (start write, S x (CSR + panel in/out), distances)
+        per_sweep = (rows * K * s + S * ((rows + len(mats)) * 4 + ents * (4 + s) + 2 * rows * K * s)
+                     + (rows + len(mats)) * 4 + ents * 4 + rows * K * s + ents * (s + 1) + rows * 4)
+        out[tag] = {"value": round(E / (ms * 1e-3), 1), "ms_per_step": round(ms, 4),
+                    "hbm_frac_minimal_bytes": round(minimal / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                    "hbm_frac_per_sweep_bytes": round(per_sweep / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                    "device_status_bits": ad.status(clear=True)}
+        del dm, X, mu, st, ns
+        torch.cuda.empty_cache()
+    out["speedup_f32_over_f64"] = round(out["f64"]["ms_per_step"] / out["f32"]["ms_per_step"], 3)
+    return out
 
 
 def cpu_baseline(idx, side):
@@ -235,8 +340,10 @@ def main():
         cnt, tot = kern[dom]
         avg = tot / cnt
         ach = main_leg["kb"][dom] / (avg * 1e-3) / 1e9
+        tr = counter_traffic("%s-fp32" % args.workload, dom) if args.size is None else None
         roof = {"bound": "hbm", "kernel": dom, "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
+                "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
+                "traffic": None if tr is None else int(tr),
                 "algorithmic_bytes_per_launch": int(main_leg["kb"][dom]),
                 "avg_launch_ms": round(avg, 5)}
     out = {
@@ -269,6 +376,9 @@ def main():
         out["fp64_plain"] = {"value": round(E / (r["ms"] * 1e-3), 1), "ms_per_step": round(r["ms"], 4),
                              "step_hbm_frac": round(r["step_bytes"] / (r["ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
                              "speedup_f32_over_f64": round(r["ms"] / ms, 3)}
+    if not args.no_batched:
+        print("[bench] batched leg (workload 4)", file=sys.stderr, flush=True)
+        out["batched"] = batched_leg(args, torch, ad, W)
     if not args.no_cpu_baseline:
         side = args.cpu_sample or args.size or {1: 32, 2: 2048, 3: 160}[idx]
         print("[bench] cpu baseline: oracle on a side-%d sample" % side, file=sys.stderr, flush=True)

@@ -129,6 +129,19 @@ const char *algdist_timing_report(ad_handle h);
 int algdist_set_launch(ad_handle h, const char *kernel, int32_t dtype, int32_t K, int32_t bucket,
                        int32_t lanes_per_row, int32_t rows_per_lane, int32_t xcd_map);
 
+/* Autotune the launch shapes of this matrix's key (dtype, K, entries-per-row
+ * bucket): the relaxation family named by `relax` (color/ncolors as for
+ * setup_testvectors), algebraic_distance, and ls_interp (only if cf != NULL
+ * and 1 <= caliber <= min(K, 8)).  Every valid (lanes_per_row,
+ * rows_per_lane in {1, 2, 4}, xcd_map) is timed with HIP events on scratch
+ * buffers allocated by this call; the fastest is installed as by
+ * algdist_set_launch.  cache_json (host path, may be NULL): entries found
+ * there for the key are installed without timing; new results are written
+ * back (one JSON object per line).  Synchronises the stream. */
+int algdist_autotune(ad_handle h, const ad_csr *A, int32_t K, int32_t relax, const int32_t *color,
+                     int32_t ncolors, const uint8_t *cf, int32_t caliber, const char *cache_json,
+                     void *stream);
+
 /* Check the CSR invariants listed above on the device; violations set
  * AD_STAT_CSR_* bits.  Not needed on the hot path (no other call reads
  * more than it is given, but their results are defined only for valid

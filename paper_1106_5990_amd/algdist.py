@@ -61,6 +61,7 @@ _SIGS = {
     "algdist_last_error": (C.c_char_p, [_P]),
     "algdist_timing": (_i32, [_P, C.c_int]),
     "algdist_timing_report": (C.c_char_p, [_P]),
+    "algdist_autotune": (_i32, [_P, _CSRP, _i32, _i32, _P, _i32, _P, _i32, C.c_char_p, _P]),
     "algdist_set_launch": (_i32, [_P, C.c_char_p, _i32, _i32, _i32, _i32, _i32, _i32]),
     "csr_validate": (_i32, [_P, _CSRP, _P]),
     "setup_testvectors": (_i32, [_P, _CSRP, _i32, _u64, _P, _i32, _i32, _f64, _P, _i32, _P, _P,
@@ -186,6 +187,17 @@ def set_launch(kernel: str, dtype: torch.dtype, K: int, lanes_per_row: int = 0,
     rc = _lib.algdist_set_launch(h, kernel.encode(), _dtype_code(dtype), K, bucket, lanes_per_row,
                                  rows_per_lane, int(xcd_map))
     _check(rc, h, "algdist_set_launch")
+
+
+def autotune(A: Csr, K: int, relax: str = "jacobi", color: Optional[torch.Tensor] = None,
+             ncolors: int = 0, cf: Optional[torch.Tensor] = None, caliber: int = 0,
+             cache_json: Optional[str] = None, stream=None) -> None:
+    """Time every launch shape on A and install the fastest (algdist_autotune)."""
+    h = handle(A.device.index)
+    kind = {"jacobi": AD_JACOBI, "gs": AD_MULTICOLOR_GS}[relax]
+    rc = _lib.algdist_autotune(h, A.ref(), K, kind, _ptr(color), ncolors, _ptr(cf), caliber,
+                               None if cache_json is None else cache_json.encode(), _stream(stream))
+    _check(rc, h, "algdist_autotune")
 
 
 def csr_validate(A: Csr, stream=None) -> None:

@@ -236,6 +236,23 @@ int algdist_set_launch(ad_handle h, const char* kernel, int32_t dtype, int32_t K
     return AD_OK;
 }
 
+int algdist_autotune(ad_handle h, const ad_csr* A, int32_t K, int32_t relax, const int32_t* color,
+                     int32_t ncolors, const uint8_t* cf, int32_t caliber, const char* cache_json,
+                     void* stream) {
+    if (!h) return AD_EINVAL;
+    h->err.clear();
+    int rc = check_csr(h, A);
+    if (rc) return rc;
+    if (!k_ok(K)) return fail(h, AD_EINVAL, "K = %d: must be 2, 4, 8, 16, 32 or 64", K);
+    if (relax != AD_JACOBI && relax != AD_MULTICOLOR_GS) return fail(h, AD_EINVAL, "relax = %d", relax);
+    if (relax == AD_MULTICOLOR_GS && (ncolors < 1 || ncolors > 64 || (A->n > 0 && !color)))
+        return fail(h, AD_EINVAL, "colours: ncolors = %d, color %p", ncolors, (const void*)color);
+    if (A->n == 0) return AD_OK;
+    AD_HIP(hipSetDevice(h->device));
+    rc = autotune(h, A, K, relax, color, ncolors, cf, caliber, cache_json, (hipStream_t)stream);
+    return rc ? fail(h, rc, "autotune") : AD_OK;
+}
+
 int csr_validate(ad_handle h, const ad_csr* A, void* stream) {
     if (!h) return AD_EINVAL;
     h->err.clear();
@@ -244,6 +261,68 @@ int csr_validate(ad_handle h, const ad_csr* A, void* stream) {
     if (A->n == 0) return AD_OK;
     AD_HIP(hipSetDevice(h->device));
     return launch_csr_validate(A, h->status, (hipStream_t)stream);
+}
+
+// Colour-phase Gauss-Seidel sweeps in the colour-major panel layout:
+// stable colour partition (rowlist: permuted row -> natural row, seg), the
+// permuted column of every entry (colp), the start written in permuted
+// order, ping-pong of two permuted panels, and the last sweep writing each
+// row straight to its natural position in X.  Checkpoints are un-permuted.
+static int gs_sweeps(ad_handle h, const ad_csr* A, int K, uint64_t seed, const void* X0,
+                     int sweeps, const int32_t* color, int ncolors, void* X, void* ckpt,
+                     int ckpt_every, hipStream_t s) {
+    const int dt = A->dtype;
+    const int n = A->n;
+    const size_t panel = (size_t)n * K * dsize(dt);
+    const int nblk = color_partition_blocks(n);
+    WsReq req;
+    const size_t o_pa = req.add(panel);
+    const size_t o_pb = req.add(panel);
+    const size_t o_rl = req.add(sizeof(int32_t) * (size_t)n);
+    const size_t o_inv = req.add(sizeof(int32_t) * (size_t)n);
+    const size_t o_colp = req.add(sizeof(int32_t) * (size_t)A->nnz);
+    const size_t o_seg = req.add(sizeof(int32_t) * (ncolors + 2));
+    const size_t o_cnt = req.add(sizeof(int32_t) * (size_t)(ncolors + 1) * nblk);
+    int rc;
+    if ((rc = ws_reserve(h, req.off))) return fail(h, rc, "workspace of %zu bytes", req.off);
+    char* ws = (char*)h->ws;
+    void* P[2] = {ws + o_pa, ws + o_pb};
+    int32_t* rowlist = (int32_t*)(ws + o_rl);
+    int32_t* inv = (int32_t*)(ws + o_inv);
+    int32_t* colp = (int32_t*)(ws + o_colp);
+    int32_t* seg = (int32_t*)(ws + o_seg);
+    {
+        TimedScope ts(h, "color_partition", s);
+        rc = launch_color_partition(n, color, ncolors, rowlist, seg, (int32_t*)(ws + o_cnt), nblk,
+                                    h->status, s);
+        if (!rc) rc = launch_perm_setup(n, A->nnz, A->col, rowlist, inv, colp, s);
+        if (rc) return fail(h, rc, "colour partition launch");
+    }
+    {
+        TimedScope ts(h, "tv_init", s);
+        if ((rc = launch_start_perm(dt, n, K, rowlist, seed, X0, P[0], s)))
+            return fail(h, rc, "start launch");
+    }
+    const LaunchCfg cfg = cfg_for(h, KN_GS, dt, K, A);
+    for (int q = 0; q < sweeps; ++q) {
+        void* Xold = P[q & 1];
+        void* Xnew = P[(q + 1) & 1];
+        if (ckpt && q % ckpt_every == 0) {
+            TimedScope ts(h, "unpermute", s);
+            rc = launch_unpermute(dt, n, K, rowlist, Xold,
+                                  (char*)ckpt + (size_t)(q / ckpt_every) * panel, s);
+            if (rc) return fail(h, rc, "checkpoint launch");
+        }
+        const bool last = q == sweeps - 1;
+        for (int c = 0; c < ncolors; ++c) {
+            TimedScope ts(h, "gs_phase", s);
+            rc = launch_gs_phase_perm(dt, K, A, colp, c, ncolors, rowlist, seg, Xold, Xnew,
+                                      last ? X : nullptr, (!last || c < ncolors - 1) ? 1 : 0,
+                                      h->status, cfg, s);
+            if (rc) return fail(h, rc, "relaxation launch");
+        }
+    }
+    return AD_OK;
 }
 
 int setup_testvectors(ad_handle h, const ad_csr* A, int32_t K, uint64_t seed, const void* X0,
@@ -275,21 +354,14 @@ int setup_testvectors(ad_handle h, const ad_csr* A, int32_t K, uint64_t seed, co
     const int dt = A->dtype;
     const size_t panel = (size_t)A->n * K * dsize(dt);
 
-    // Workspace: one extra panel for the ping-pong, plus the colour lists.
+    if (relax == AD_MULTICOLOR_GS && sweeps > 0)
+        return gs_sweeps(h, A, K, seed, X0, sweeps, color, ncolors, X, ckpt, ckpt_every, s);
+
+    // Jacobi (or no sweep).  Workspace: one extra panel for the ping-pong.
     WsReq req;
     const size_t o_pp = req.add(panel);
-    size_t o_rl = 0, o_seg = 0, o_cnt = 0;
-    int nblk = 0;
-    const bool gs = relax == AD_MULTICOLOR_GS && sweeps > 0;
-    if (gs) {
-        nblk = color_partition_blocks(A->n);
-        o_rl = req.add(sizeof(int32_t) * (size_t)A->n);
-        o_seg = req.add(sizeof(int32_t) * (ncolors + 2));
-        o_cnt = req.add(sizeof(int32_t) * (size_t)(ncolors + 1) * nblk);
-    }
     if ((rc = ws_reserve(h, req.off))) return fail(h, rc, "workspace of %zu bytes", req.off);
-    char* ws = (char*)h->ws;
-    void* W = ws + o_pp;
+    void* W = (char*)h->ws + o_pp;
 
     // Buffer of iterate q (0..sweeps): x^sweeps lands in X; a checkpointed
     // iterate lives in its checkpoint slot; the others alternate between X
@@ -311,26 +383,10 @@ int setup_testvectors(ad_handle h, const ad_csr* A, int32_t K, uint64_t seed, co
     }
     if (ns == 0 && ckpt) AD_HIP(hipMemcpyAsync(ckpt, X, panel, hipMemcpyDeviceToDevice, s));
 
-    int32_t* rowlist = gs ? (int32_t*)(ws + o_rl) : nullptr;
-    int32_t* seg = gs ? (int32_t*)(ws + o_seg) : nullptr;
-    if (gs) {
-        TimedScope ts(h, "color_partition", s);
-        rc = launch_color_partition(A->n, color, ncolors, rowlist, seg, (int32_t*)(ws + o_cnt),
-                                    nblk, h->status, s);
-        if (rc) return fail(h, rc, "colour partition launch");
-    }
-    const LaunchCfg cfg = cfg_for(h, relax == AD_JACOBI ? KN_JACOBI : KN_GS, dt, K, A);
+    const LaunchCfg cfg = cfg_for(h, KN_JACOBI, dt, K, A);
     for (int q = 0; q < ns; ++q) {
-        if (relax == AD_JACOBI) {
-            TimedScope ts(h, "jacobi", s);
-            rc = launch_jacobi(dt, K, A, buf[q], buf[q + 1], omega, h->status, cfg, s);
-        } else {
-            for (int c = 0; c < ncolors && !rc; ++c) {
-                TimedScope ts(h, "gs_phase", s);
-                rc = launch_gs_phase(dt, K, A, color, c, ncolors, rowlist, seg, buf[q], buf[q + 1],
-                                     h->status, cfg, s);
-            }
-        }
+        TimedScope ts(h, "jacobi", s);
+        rc = launch_jacobi(dt, K, A, buf[q], buf[q + 1], omega, h->status, cfg, s);
         if (rc) return fail(h, rc, "relaxation launch");
     }
     return AD_OK;

@@ -1,0 +1,244 @@
+// autotune.hip -- launch-shape search for the kernel families.
+//
+// For one matrix (its dtype, K and stored-entries-per-row bucket) every
+// valid shape of each family is timed with HIP events on scratch buffers:
+//   lanes per row L (K / L panel entries per lane: the panel width a lane
+//   owns; 64 / L rows per wavefront), rows per lane group per tile
+//   (1, 2, 4), and the XCD-contiguous tile mapping on or off.
+// The fastest shape per family is stored in the handle (the same slot
+// algdist_set_launch writes) and, if a cache path is given, in a JSON file:
+// one object per line,
+//   {"kernel": "algdist", "dtype": 0, "K": 16, "bucket": 1, "lpr": 2, "iter": 1, "xcd": 1, "ms": 0.41}
+// A cache entry for the key is used instead of timing.
+#include <stdio.h>
+#include <string.h>
+
+#include <string>
+#include <vector>
+
+#include "device.h"
+#include "internal.h"
+
+namespace ad {
+
+namespace {
+
+const char* kFamilyName[KN_COUNT] = {"jacobi", "gs_phase", "algdist", "ls_interp", "batched"};
+
+struct Entry {
+    std::string kernel;
+    int dtype, K, bucket, lpr, iter, xcd;
+    double ms;
+};
+
+std::vector<Entry> read_cache(const char* path) {
+    std::vector<Entry> out;
+    if (!path) return out;
+    FILE* f = fopen(path, "r");
+    if (!f) return out;
+    char line[512];
+    while (fgets(line, sizeof line, f)) {
+        char name[64];
+        Entry e;
+        if (sscanf(line,
+                   " {\"kernel\": \"%63[^\"]\", \"dtype\": %d, \"K\": %d, \"bucket\": %d, \"lpr\": %d, "
+                   "\"iter\": %d, \"xcd\": %d, \"ms\": %lf}",
+                   name, &e.dtype, &e.K, &e.bucket, &e.lpr, &e.iter, &e.xcd, &e.ms) == 8) {
+            e.kernel = name;
+            out.push_back(e);
+        }
+    }
+    fclose(f);
+    return out;
+}
+
+void write_cache(const char* path, const std::vector<Entry>& v) {
+    if (!path) return;
+    std::string tmp = std::string(path) + ".tmp";
+    FILE* f = fopen(tmp.c_str(), "w");
+    if (!f) return;
+    for (const Entry& e : v)
+        fprintf(f,
+                "{\"kernel\": \"%s\", \"dtype\": %d, \"K\": %d, \"bucket\": %d, \"lpr\": %d, "
+                "\"iter\": %d, \"xcd\": %d, \"ms\": %.6f}\n",
+                e.kernel.c_str(), e.dtype, e.K, e.bucket, e.lpr, e.iter, e.xcd, e.ms);
+    fclose(f);
+    rename(tmp.c_str(), path);
+}
+
+bool lpr_valid(int dtype, int K, int L) {
+    return dtype == AD_F32 ? lpr_ok<float>(K, L) : lpr_ok<double>(K, L);
+}
+
+// average milliseconds of `reps` runs of fn (after one warm run)
+template <typename F>
+double time_ms(hipStream_t s, hipEvent_t a, hipEvent_t b, int reps, F&& fn, bool& ok) {
+    ok = fn() == AD_OK;
+    if (!ok) return 1e30;
+    (void)hipEventRecord(a, s);
+    for (int r = 0; r < reps; ++r)
+        if (fn() != AD_OK) ok = false;
+    (void)hipEventRecord(b, s);
+    (void)hipEventSynchronize(b);
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, a, b);
+    return ok ? ms / reps : 1e30;
+}
+
+struct Scratch {
+    std::vector<void*> ptrs;
+    ~Scratch() {
+        (void)hipDeviceSynchronize();  // scratch may still be in use by queued timing runs
+        for (void* p : ptrs) (void)hipFree(p);
+    }
+    void* get(size_t bytes) {
+        void* p = nullptr;
+        if (hipMalloc(&p, bytes ? bytes : 16) != hipSuccess) return nullptr;
+        ptrs.push_back(p);
+        return p;
+    }
+};
+
+}  // namespace
+
+int autotune(ad_handle h, const ad_csr* A, int K, int relax, const int32_t* color, int ncolors,
+             const uint8_t* cf, int caliber, const char* cache, hipStream_t s) {
+    const int dt = A->dtype;
+    const int ks = k_slot(K);
+    const int bucket = nnz_bucket(A->nnz, A->n);
+    std::vector<Entry> entries = read_cache(cache);
+    const int fams[3] = {relax == AD_JACOBI ? KN_JACOBI : KN_GS, KN_ALGDIST, KN_LS};
+    bool need[3] = {true, true, cf != nullptr && caliber >= 1 && caliber <= K && caliber <= 8};
+    for (int q = 0; q < 3; ++q)
+        for (const Entry& e : entries)
+            if (need[q] && e.kernel == kFamilyName[fams[q]] && e.dtype == dt && e.K == K &&
+                e.bucket == bucket) {
+                LaunchCfg c;
+                c.lpr = e.lpr;
+                c.iter = e.iter;
+                c.xcd_map = e.xcd;
+                h->tuned[fams[q]][dt][ks][bucket] = c;
+                h->has_tuned[fams[q]][dt][ks][bucket] = true;
+                need[q] = false;
+            }
+    if (!need[0] && !need[1] && !need[2]) return AD_OK;
+
+    const size_t vs = dt == AD_F32 ? 4 : 8;
+    const int n = A->n;
+    const size_t panel = (size_t)n * K * vs;
+    Scratch sc;
+    void* X = sc.get(panel);
+    void* X2 = sc.get(panel);
+    void* mu = sc.get((size_t)A->nnz * vs);
+    uint8_t* strong = (uint8_t*)sc.get((size_t)A->nnz);
+    int32_t* ns = (int32_t*)sc.get(sizeof(int32_t) * (size_t)n);
+    if (!X || !X2 || !mu || !strong || !ns) return AD_ENOMEM;
+    int rc = launch_tv_init(dt, 0, n, K, 1, X, s);
+    if (rc) return rc;
+    hipEvent_t ea, eb;
+    AD_HIP(hipEventCreate(&ea));
+    AD_HIP(hipEventCreate(&eb));
+    struct Ev {
+        hipEvent_t a, b;
+        ~Ev() {
+            (void)hipEventDestroy(a);
+            (void)hipEventDestroy(b);
+        }
+    } ev{ea, eb};
+
+    // colour-major setup for the colour phases
+    int32_t *rowlist = nullptr, *seg = nullptr, *colp = nullptr;
+    if (need[0] && relax == AD_MULTICOLOR_GS) {
+        const int nblk = color_partition_blocks(n);
+        rowlist = (int32_t*)sc.get(sizeof(int32_t) * (size_t)n);
+        int32_t* inv = (int32_t*)sc.get(sizeof(int32_t) * (size_t)n);
+        colp = (int32_t*)sc.get(sizeof(int32_t) * (size_t)A->nnz);
+        seg = (int32_t*)sc.get(sizeof(int32_t) * (ncolors + 2));
+        int32_t* cnt = (int32_t*)sc.get(sizeof(int32_t) * (size_t)(ncolors + 1) * nblk);
+        if (!rowlist || !inv || !colp || !seg || !cnt) return AD_ENOMEM;
+        if ((rc = launch_color_partition(n, color, ncolors, rowlist, seg, cnt, nblk, h->status, s)))
+            return rc;
+        if ((rc = launch_perm_setup(n, A->nnz, A->col, rowlist, inv, colp, s))) return rc;
+    }
+    int32_t* Pc = nullptr;
+    double *Pv = nullptr, *ls = nullptr, *bs = nullptr;
+    int32_t* st = nullptr;
+    if (need[2]) {
+        Pc = (int32_t*)sc.get(sizeof(int32_t) * (size_t)n * caliber);
+        Pv = (double*)sc.get(sizeof(double) * (size_t)n * caliber);
+        ls = (double*)sc.get(sizeof(double) * (size_t)n);
+        st = (int32_t*)sc.get(sizeof(int32_t) * (size_t)n);
+        if (!Pc || !Pv || !ls || !st) return AD_ENOMEM;
+    }
+
+    const int iters[3] = {1, 2, 4};
+    for (int q = 0; q < 3; ++q) {
+        if (!need[q]) continue;
+        const int fam = fams[q];
+        double best = 1e30;
+        LaunchCfg bestc;
+        for (int L = 1; L <= kWave; L *= 2) {
+            if (!lpr_valid(dt, K, L)) continue;
+            for (int it : iters) {
+                if (fam == KN_LS && it != 1) continue;  // LS rows ignore the row-step count
+                for (int xcd = 0; xcd <= 1; ++xcd) {
+                    LaunchCfg c;
+                    c.lpr = L;
+                    c.iter = it;
+                    c.xcd_map = xcd;
+                    bool ok = true;
+                    double ms = 1e30;
+                    if (fam == KN_JACOBI) {
+                        ms = time_ms(s, ea, eb, 3, [&] {
+                            return launch_jacobi(dt, K, A, X, X2, 0.7, h->status, c, s);
+                        }, ok);
+                    } else if (fam == KN_GS) {
+                        ms = time_ms(s, ea, eb, 3, [&] {
+                            int r = AD_OK;
+                            for (int cc = 0; cc < ncolors && !r; ++cc)
+                                r = launch_gs_phase_perm(dt, K, A, colp, cc, ncolors, rowlist, seg,
+                                                         X, X2, nullptr, 1, h->status, c, s);
+                            return r;
+                        }, ok);
+                        ms /= ncolors;
+                    } else if (fam == KN_ALGDIST) {
+                        ms = time_ms(s, ea, eb, 3, [&] {
+                            return launch_algdist(dt, K, A, X, nullptr, AD_TARGET_PLAIN, mu, nullptr,
+                                                  0.25, nullptr, strong, ns, h->status, c, s);
+                        }, ok);
+                    } else {
+                        // distances once, then LS rows on them
+                        if (launch_algdist(dt, K, A, X, nullptr, AD_TARGET_PLAIN, mu, nullptr, 0.25,
+                                           nullptr, nullptr, nullptr, h->status, LaunchCfg(), s))
+                            continue;
+                        ms = time_ms(s, ea, eb, 3, [&] {
+                            return launch_ls_interp(dt, K, caliber, A, X, nullptr, cf, mu,
+                                                    AD_TARGET_PLAIN, Pc, Pv, ls, st, bs, nullptr,
+                                                    h->status, c, s);
+                        }, ok);
+                    }
+                    if (ok && ms < best) {
+                        best = ms;
+                        bestc = c;
+                    }
+                }
+            }
+        }
+        if (best >= 1e30) continue;
+        h->tuned[fam][dt][ks][bucket] = bestc;
+        h->has_tuned[fam][dt][ks][bucket] = true;
+        Entry e{kFamilyName[fam], dt, K, bucket, bestc.lpr, bestc.iter, bestc.xcd_map, best};
+        bool replaced = false;
+        for (Entry& x : entries)
+            if (x.kernel == e.kernel && x.dtype == dt && x.K == K && x.bucket == bucket) {
+                x = e;
+                replaced = true;
+            }
+        if (!replaced) entries.push_back(e);
+    }
+    AD_HIP(hipStreamSynchronize(s));
+    write_cache(cache, entries);
+    return AD_OK;
+}
+
+}  // namespace ad

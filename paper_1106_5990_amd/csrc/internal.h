@@ -131,9 +131,16 @@ int launch_color_partition(int n, const int32_t* color, int ncolors, int32_t* ro
                            int32_t* seg, int32_t* counts, int nblocks, unsigned* status,
                            hipStream_t s);
 int color_partition_blocks(int n);
-int launch_gs_phase(int dtype, int K, const ad_csr* A, const int32_t* color, int c, int ncolors,
-                    const int32_t* rowlist, const int32_t* seg, const void* Xold, void* Xnew,
-                    unsigned* status, const LaunchCfg& cfg, hipStream_t s);
+int launch_gs_phase_perm(int dtype, int K, const ad_csr* A, const int32_t* colp, int c,
+                         int ncolors, const int32_t* rowlist, const int32_t* seg, const void* Xold,
+                         void* Xnew, void* Xnat, int write_perm, unsigned* status,
+                         const LaunchCfg& cfg, hipStream_t s);
+int launch_perm_setup(int n, int64_t nnz, const int32_t* col, const int32_t* rowlist, int32_t* inv,
+                      int32_t* colp, hipStream_t s);
+int launch_start_perm(int dtype, int n, int K, const int32_t* rowlist, uint64_t seed,
+                      const void* X0, void* Xp, hipStream_t s);
+int launch_unpermute(int dtype, int n, int K, const int32_t* rowlist, const void* Xp, void* X,
+                     hipStream_t s);
 
 // ---- distance.hip
 int launch_algdist(int dtype, int K, const ad_csr* A, const void* X, const double* w, int target,
@@ -150,6 +157,10 @@ int launch_ls_interp(int dtype, int K, int caliber, const ad_csr* A, const void*
                      double* block_sums, double* ls_sum, unsigned* status,
                      const LaunchCfg& cfg, hipStream_t s);
 int ls_interp_blocks(int dtype, int K, int n, const LaunchCfg& cfg);
+
+// ---- autotune.hip
+int autotune(ad_handle h, const ad_csr* A, int K, int relax, const int32_t* color, int ncolors,
+             const uint8_t* cf, int caliber, const char* cache, hipStream_t s);
 
 // ---- batched.hip
 int launch_batched(ad_handle h, int nmat, const ad_csr* As, int K, uint64_t seed, int sweeps,

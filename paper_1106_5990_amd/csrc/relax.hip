@@ -223,16 +223,61 @@ int launch_color_partition(int n, const int32_t* color, int ncolors, int32_t* ro
     return AD_OK;
 }
 
-// ---------------------------------------------------------------- colour phase
-// Rows of colour c (list segment seg[c]..seg[c+1]):
-//   x_new_i = x_i - (A z)_i / a_ii,  z_j = Xnew_j if colour(j) < c else Xold_j.
-// The phase of colour 0 also copies rows with an invalid colour (held fixed).
-template <typename T, int K, int LPR, bool FIRST>
-__global__ __launch_bounds__(kBlock) void gs_phase_kernel(
-    const int* __restrict__ rp, const int* __restrict__ ci, const T* __restrict__ av,
-    const int* __restrict__ color, int c, int nc, const int* __restrict__ rowlist,
-    const int* __restrict__ seg, const T* __restrict__ Xold, T* __restrict__ Xnew, int iter,
-    int xcd, unsigned* status) {
+// ---------------------------------------------------------------- colour-major layout
+// The colour phases run on panels stored colour-major: permuted row p holds
+// natural row rowlist[p], so the rows of one colour are contiguous and every
+// cache line a phase touches holds rows it needs.  A neighbour's permuted
+// index jp is read from colp[e] = inv[col[e]]; "smaller colour" is jp <
+// seg[c] because the segments are in colour order.
+
+__global__ __launch_bounds__(kBlock) void inverse_perm_kernel(int n, const int* __restrict__ rowlist,
+                                                              int* __restrict__ inv) {
+    const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (p < n) inv[rowlist[p]] = (int)p;
+}
+
+__global__ __launch_bounds__(kBlock) void permute_cols_kernel(int64_t nnz, const int* __restrict__ ci,
+                                                              const int* __restrict__ inv,
+                                                              int* __restrict__ colp) {
+    const int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (e < nnz) colp[e] = inv[ci[e]];
+}
+
+// Xp[p] = hash start of natural row rowlist[p] (or X0[rowlist[p]] if given)
+template <typename T>
+__global__ __launch_bounds__(kBlock) void start_perm_kernel(int n, int K, const int* __restrict__ rowlist,
+                                                            uint64_t seed, const T* __restrict__ X0,
+                                                            T* __restrict__ Xp) {
+    const int64_t c = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (c >= (int64_t)n * K) return;
+    const int64_t p = c / K;
+    const int k = (int)(c - p * K);
+    const int64_t i = rowlist[p];
+    Xp[c] = X0 ? X0[i * K + k] : (T)uniform_pm1(splitmix64_at(seed, (uint64_t)(i * K + k)));
+}
+
+// X[rowlist[p]] = Xp[p]
+template <typename T>
+__global__ __launch_bounds__(kBlock) void unpermute_kernel(int n, int K, const int* __restrict__ rowlist,
+                                                           const T* __restrict__ Xp, T* __restrict__ X) {
+    const int64_t c = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (c >= (int64_t)n * K) return;
+    const int64_t p = c / K;
+    const int k = (int)(c - p * K);
+    X[(int64_t)rowlist[p] * K + k] = Xp[c];
+}
+
+// One colour phase in the permuted layout.  Rows p in [seg[c], seg[c+1]):
+//   x_new = x - (A z) / a_ii,  z_jp = Xnew_p[jp] if jp < seg[c] else Xold_p[jp].
+// Xnew_p receives the row when write_perm; Xnat (if not null) receives it at
+// its natural position (the last sweep writes the caller's output directly).
+// The phase of colour 0 also carries the held rows (invalid colour).
+template <typename T, int K, int LPR>
+__global__ __launch_bounds__(kBlock) void gs_phase_perm_kernel(
+    const int* __restrict__ rp, const int* __restrict__ colp, const T* __restrict__ av, int c,
+    int nc, const int* __restrict__ rowlist, const int* __restrict__ seg,
+    const T* __restrict__ Xold, T* __restrict__ Xnew, T* __restrict__ Xnat, int write_perm,
+    int iter, int xcd, unsigned* status) {
     using S = Shape<T, K, LPR>;
     constexpr int V = S::V, C = S::C;
     const int lane = threadIdx.x & (kWave - 1);
@@ -249,78 +294,103 @@ __global__ __launch_bounds__(kBlock) void gs_phase_kernel(
             const int i = rowlist[p];
             T y[V], d;
             Frag<T, V> xi;
-            if (FIRST) {
-                row_spmm<S, T, K>(i, rp[i], rp[i + 1], ci, av, l, [&](int) { return Xold; }, y, d,
-                                  xi);
-            } else {
-                row_spmm<S, T, K>(
-                    i, rp[i], rp[i + 1], ci, av, l,
-                    [&](int j) { return ((unsigned)color[j] < (unsigned)c) ? (const T*)Xnew : Xold; },
-                    y, d, xi);
-            }
+            row_spmm<S, T, K>((int)p, rp[i], rp[i + 1], colp, av, l,
+                              [&](int jp) { return (jp < b0) ? (const T*)Xnew : Xold; }, y, d, xi);
             Frag<T, V> out;
             if (d == T(0)) {
-                out = load_lane<T, V, C>(Xold + (size_t)i * K + l * V);
+                out = load_lane<T, V, C>(Xold + (size_t)p * K + l * V);
                 if (l == 0) flag(status, AD_STAT_ZERO_DIAG);
             } else {
 #pragma unroll
                 for (int q = 0; q < V; ++q) out.v[q] = xi.v[q] - y[q] / d;
             }
-            store_lane<T, V, C>(Xnew + (size_t)i * K + l * V, out);
+            if (write_perm) store_lane<T, V, C>(Xnew + (size_t)p * K + l * V, out);
+            if (Xnat) store_lane<T, V, C>(Xnat + (size_t)i * K + l * V, out);
         }
     }
-    if (FIRST) {  // rows with an invalid colour are held fixed
+    if (c == 0) {  // rows with an invalid colour are held fixed
         const int q0 = seg[nc], q1 = seg[nc + 1];
         const int64_t stride = (int64_t)gridDim.x * S::RPB;
         for (int64_t p = q0 + (int64_t)blockIdx.x * S::RPB + wv * S::RPW + g; p < q1; p += stride) {
-            const int i = rowlist[p];
-            store_lane<T, V, C>(Xnew + (size_t)i * K + l * V,
-                                load_lane<T, V, C>(Xold + (size_t)i * K + l * V));
+            const Frag<T, V> v = load_lane<T, V, C>(Xold + (size_t)p * K + l * V);
+            store_lane<T, V, C>(Xnew + (size_t)p * K + l * V, v);
+            if (Xnat) store_lane<T, V, C>(Xnat + (size_t)rowlist[p] * K + l * V, v);
         }
     }
 }
 
 template <typename T, int K, int LPR>
-static void gs_go(const ad_csr* A, const int32_t* color, int c, int nc, const int32_t* rowlist,
-                  const int32_t* seg, const void* Xold, void* Xnew, unsigned* st,
-                  const LaunchCfg& cfg, hipStream_t s) {
+static void gsp_go(const ad_csr* A, const int32_t* colp, int c, int nc, const int32_t* rowlist,
+                   const int32_t* seg, const void* Xold, void* Xnew, void* Xnat, int write_perm,
+                   unsigned* st, const LaunchCfg& cfg, hipStream_t s) {
     using S = Shape<T, K, LPR>;
-    // the per-colour row count is known only on the device: size the grid
-    // for all n rows; workgroups beyond the colour's tiles exit at once.
     const int64_t rpt = (int64_t)S::RPB * cfg.iter;
     const int64_t ntiles = (A->n + rpt - 1) / rpt;
     const int grid = cfg.xcd_map ? grid_for_tiles(ntiles) : (int)ntiles;
-    if (c == 0)
-        gs_phase_kernel<T, K, LPR, true><<<dim3(grid), dim3(kBlock), 0, s>>>(
-            A->row_ptr, A->col, (const T*)A->val, color, c, nc, rowlist, seg, (const T*)Xold,
-            (T*)Xnew, cfg.iter, cfg.xcd_map, st);
-    else
-        gs_phase_kernel<T, K, LPR, false><<<dim3(grid), dim3(kBlock), 0, s>>>(
-            A->row_ptr, A->col, (const T*)A->val, color, c, nc, rowlist, seg, (const T*)Xold,
-            (T*)Xnew, cfg.iter, cfg.xcd_map, st);
+    gs_phase_perm_kernel<T, K, LPR><<<dim3(grid), dim3(kBlock), 0, s>>>(
+        A->row_ptr, colp, (const T*)A->val, c, nc, rowlist, seg, (const T*)Xold, (T*)Xnew,
+        (T*)Xnat, write_perm, cfg.iter, cfg.xcd_map, st);
 }
 
 template <typename T>
-static int gs_dispatch(int K, const ad_csr* A, const int32_t* color, int c, int nc,
-                       const int32_t* rowlist, const int32_t* seg, const void* Xold, void* Xnew,
-                       unsigned* st, const LaunchCfg& cfg, hipStream_t s) {
+static int gsp_dispatch(int K, const ad_csr* A, const int32_t* colp, int c, int nc,
+                        const int32_t* rowlist, const int32_t* seg, const void* Xold, void* Xnew,
+                        void* Xnat, int write_perm, unsigned* st, const LaunchCfg& cfg,
+                        hipStream_t s) {
     return with_k<T>(K, [&](auto kc) {
         constexpr int KK = decltype(kc)::value;
         return with_lpr<T, KK>(cfg.lpr, [&](auto lc) {
             constexpr int L = decltype(lc)::value;
-            gs_go<T, KK, L>(A, color, c, nc, rowlist, seg, Xold, Xnew, st, cfg, s);
+            gsp_go<T, KK, L>(A, colp, c, nc, rowlist, seg, Xold, Xnew, Xnat, write_perm, st, cfg, s);
         });
     });
 }
 
-int launch_gs_phase(int dtype, int K, const ad_csr* A, const int32_t* color, int c, int ncolors,
-                    const int32_t* rowlist, const int32_t* seg, const void* Xold, void* Xnew,
-                    unsigned* status, const LaunchCfg& cfg, hipStream_t s) {
+int launch_gs_phase_perm(int dtype, int K, const ad_csr* A, const int32_t* colp, int c,
+                         int ncolors, const int32_t* rowlist, const int32_t* seg, const void* Xold,
+                         void* Xnew, void* Xnat, int write_perm, unsigned* status,
+                         const LaunchCfg& cfg, hipStream_t s) {
     if (A->n == 0) return AD_OK;
     const int rc = (dtype == AD_F32)
-                       ? gs_dispatch<float>(K, A, color, c, ncolors, rowlist, seg, Xold, Xnew, status, cfg, s)
-                       : gs_dispatch<double>(K, A, color, c, ncolors, rowlist, seg, Xold, Xnew, status, cfg, s);
+                       ? gsp_dispatch<float>(K, A, colp, c, ncolors, rowlist, seg, Xold, Xnew, Xnat,
+                                             write_perm, status, cfg, s)
+                       : gsp_dispatch<double>(K, A, colp, c, ncolors, rowlist, seg, Xold, Xnew, Xnat,
+                                              write_perm, status, cfg, s);
     if (rc) return rc;
+    AD_HIP(hipGetLastError());
+    return AD_OK;
+}
+
+int launch_perm_setup(int n, int64_t nnz, const int32_t* col, const int32_t* rowlist, int32_t* inv,
+                      int32_t* colp, hipStream_t s) {
+    inverse_perm_kernel<<<dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, s>>>(n, rowlist, inv);
+    if (nnz > 0)
+        permute_cols_kernel<<<dim3((unsigned)((nnz + kBlock - 1) / kBlock)), dim3(kBlock), 0, s>>>(
+            nnz, col, inv, colp);
+    AD_HIP(hipGetLastError());
+    return AD_OK;
+}
+
+int launch_start_perm(int dtype, int n, int K, const int32_t* rowlist, uint64_t seed,
+                      const void* X0, void* Xp, hipStream_t s) {
+    const int64_t m = (int64_t)n * K;
+    const unsigned b = (unsigned)((m + kBlock - 1) / kBlock);
+    if (dtype == AD_F32)
+        start_perm_kernel<float><<<dim3(b), dim3(kBlock), 0, s>>>(n, K, rowlist, seed, (const float*)X0, (float*)Xp);
+    else
+        start_perm_kernel<double><<<dim3(b), dim3(kBlock), 0, s>>>(n, K, rowlist, seed, (const double*)X0, (double*)Xp);
+    AD_HIP(hipGetLastError());
+    return AD_OK;
+}
+
+int launch_unpermute(int dtype, int n, int K, const int32_t* rowlist, const void* Xp, void* X,
+                     hipStream_t s) {
+    const int64_t m = (int64_t)n * K;
+    const unsigned b = (unsigned)((m + kBlock - 1) / kBlock);
+    if (dtype == AD_F32)
+        unpermute_kernel<float><<<dim3(b), dim3(kBlock), 0, s>>>(n, K, rowlist, (const float*)Xp, (float*)X);
+    else
+        unpermute_kernel<double><<<dim3(b), dim3(kBlock), 0, s>>>(n, K, rowlist, (const double*)Xp, (double*)X);
     AD_HIP(hipGetLastError());
     return AD_OK;
 }

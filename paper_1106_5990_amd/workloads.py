@@ -260,9 +260,21 @@ def rgg_batch_sizes(nmat: int, seed, nmin=2_000, nmax=200_000, dmin=4.0, dmax=29
     return ns, ds
 
 
-def rgg_batch(nmat: int, seed_base: int, nmin=2_000, nmax=200_000) -> List[CSR]:
+def _rgg_member(args):
+    n, d, seed = args
+    return rgg_laplacian(n, d, seed)
+
+
+def rgg_batch(nmat: int, seed_base: int, nmin=2_000, nmax=200_000, workers: int = 1) -> List[CSR]:
+    """Matrix m uses seed (seed_base, m); `workers` > 1 builds members in
+    parallel processes (same result)."""
     ns, ds = rgg_batch_sizes(nmat, seed_base, nmin, nmax)
-    return [rgg_laplacian(int(ns[m]), float(ds[m]), (seed_base, m)) for m in range(nmat)]
+    jobs = [(int(ns[m]), float(ds[m]), (seed_base, m)) for m in range(nmat)]
+    if workers <= 1:
+        return [_rgg_member(j) for j in jobs]
+    import multiprocessing as mp
+    with mp.get_context("fork").Pool(workers) as pool:
+        return pool.map(_rgg_member, jobs, chunksize=1)
 
 
 # ---------------------------------------------------------------------------
@@ -341,9 +353,13 @@ def workload(i: int, dtype: str = "f64", size: Optional[int] = None) -> Workload
     raise ValueError("workload %d is a batch; use batch_workload()" % i)
 
 
-def batch_workload(nmat: int = 512, nmin: int = 2_000, nmax: int = 200_000):
-    """Workload 4: a batch of RGG Laplacians (n log-uniform in [nmin, nmax])."""
-    return rgg_batch(nmat, COEF_SEED_BASE + 4, nmin, nmax)
+def batch_workload(nmat: int = 512, nmin: int = 2_000, nmax: int = 200_000, workers: int = 1):
+    """Workload 4: a batch of RGG Laplacians (n log-uniform in [nmin, nmax]),
+    K = 16, 4 Jacobi sweeps with omega = 2/3, theta = 0.25."""
+    return rgg_batch(nmat, COEF_SEED_BASE + 4, nmin, nmax, workers)
+
+
+BATCH_K, BATCH_SWEEPS, BATCH_OMEGA, BATCH_THETA = 16, 4, 2.0 / 3.0, 0.25
 
 
 def concat_csr(mats: Sequence[CSR]) -> CSR:

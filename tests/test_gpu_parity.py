@@ -498,3 +498,36 @@ def test_every_launch_shape_gives_the_same_results(dt, K):
     finally:
         for kern in ("jacobi", "gs_phase", "algdist", "ls_interp"):
             ad.set_launch(kern, dtype, K, 0, 1, True)
+
+
+def test_autotune_installs_and_caches(tmp_path):
+    ad = lib()
+    say("autotune")
+    N, K = 96, 16
+    A = aniso(N)
+    dtype = torch.float32
+    Ad = dev_csr(A, dtype)
+    color = torch.as_tensor(W.red_black((N, N)), device="cuda")
+    cfh = W.cf_red_is_coarse((N, N))
+    cf = torch.as_tensor(cfh, device="cuda")
+    cache = str(tmp_path / "tune.json")
+    try:
+        ad.autotune(Ad, K, relax="gs", color=color, ncolors=2, cf=cf, caliber=4, cache_json=cache)
+        lines = open(cache).read().splitlines()
+        kinds = sorted(l.split('"')[3] for l in lines)
+        assert kinds == ["algdist", "gs_phase", "ls_interp"], lines
+        ad.autotune(Ad, K, relax="gs", color=color, ncolors=2, cf=cf, caliber=4, cache_json=cache)
+        assert open(cache).read().splitlines() == lines  # served from the cache
+        X = ad.setup_testvectors(Ad, K, seed=2, relax="gs", sweeps=3, color=color, ncolors=2)
+        mu, s, ns = ad.algebraic_distance(Ad, X, fuse=True, theta=0.25)
+        x = to_np(X).astype(np.float64)
+        check_mu(to_np(mu).astype(np.float64), oracle.algdist(as_oracle(A, dtype), x),
+                 saa_per_edge(A, x), dtype, "tuned")
+        sr, nsr = oracle.strength(A, to_np(mu).astype(np.float64), 0.25)
+        assert np.array_equal(to_np(s), sr)
+        P = ad.ls_interp(Ad, X, cf, mu, 4)
+        R = oracle.ls_interp(as_oracle(A, dtype), x, None, cfh, to_np(mu).astype(np.float64), 4)
+        check_ls(tuple(to_np(t) for t in P), R, dtype, (x * x).sum(1))
+    finally:
+        for kern in ("gs_phase", "algdist", "ls_interp"):
+            ad.set_launch(kern, dtype, K, 0, 1, True)
