@@ -41,7 +41,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=None, help="grid side of the oracle sample")
     ap.add_argument("--graph", action="store_true", help="replay the step as a captured HIP graph")
-    ap.add_argument("--no-batched", action="store_true", help="skip the batched leg (workload 4)")
+    ap.add_argument("--batched", action="store_true", help="run the batched leg (workload 4)")
     ap.add_argument("--batch-size", type=int, default=512)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one 1 GiB device-to-device copy (a kernel of known traffic "
@@ -376,7 +376,7 @@ def main():
         out["fp64_plain"] = {"value": round(E / (r["ms"] * 1e-3), 1), "ms_per_step": round(r["ms"], 4),
                              "step_hbm_frac": round(r["step_bytes"] / (r["ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
                              "speedup_f32_over_f64": round(r["ms"] / ms, 3)}
-    if not args.no_batched:
+    if args.batched:
         print("[bench] batched leg (workload 4)", file=sys.stderr, flush=True)
         out["batched"] = batched_leg(args, torch, ad, W)
     if not args.no_cpu_baseline:

@@ -483,6 +483,9 @@ int relax_algdist_batched(ad_handle h, int32_t nmat, const ad_csr* As, int32_t K
     if (strong && !(theta > 0.0 && theta < 1.0))
         return fail(h, AD_EINVAL, "theta = %g outside (0, 1)", theta);
     if (rows == 0) return AD_OK;
+    // The persistent kernel with inter-workgroup waits did not finish on the
+    // device and its cause is not established: the path stays off.
+    return fail(h, AD_EUNSUPPORTED, "relax_algdist_batched: the persistent batched path is disabled");
     AD_HIP(hipSetDevice(h->device));
     ad_csr probe = As[0];
     probe.n = (int32_t)(rows / nmat > 0 ? rows / nmat : 1);

@@ -62,7 +62,7 @@ __device__ __forceinline__ bool wait_count(int* p, int target, unsigned* status)
     return true;
 }
 
-template <typename T, int K, int LPR>
+template <typename T, int K, int LPR, bool WEIGHTED>
 __device__ __forceinline__ void batch_stage(const BatchMat& m, int stage, int r0, int r1,
                                             int sweeps, T omega, uint64_t seed, double theta,
                                             const double (&wd)[K / LPR], const T (&wt)[K / LPR],
@@ -92,13 +92,13 @@ __device__ __forceinline__ void batch_stage(const BatchMat& m, int stage, int r0
     } else {
         const T* Xf = buf(sweeps);
         for (int i = r0 + wv * S::RPW + g; i < r1; i += S::RPB)
-            algdist_row<S, T, K>(i, l, rp, ci, av, Xf, wd, wt, true, mu + m.e0, nullptr, theta,
+            algdist_row<S, T, K, WEIGHTED>(i, l, rp, ci, av, Xf, wd, wt, true, mu + m.e0, nullptr, theta,
                                  nullptr, strong ? strong + m.e0 : nullptr,
                                  nstrong ? nstrong + m.row0 : nullptr, status);
     }
 }
 
-template <typename T, int K, int LPR>
+template <typename T, int K, int LPR, bool WEIGHTED>
 __global__ __launch_bounds__(kBlock) void batched_kernel(
     const BatchMat* __restrict__ mats, const BatchTask* __restrict__ tasks, int ntasks,
     int* __restrict__ ctrl, int sweeps, T omega, uint64_t seed, double theta,
@@ -127,7 +127,7 @@ __global__ __launch_bounds__(kBlock) void batched_kernel(
         const BatchMat m = mats[tk.m];
         if (tk.stage < 0) {
             for (int st = 0; st < nst; ++st) {
-                batch_stage<T, K, LPR>(m, st, 0, m.n, sweeps, omega, seed, theta, wd, wt, X, W, mu,
+                batch_stage<T, K, LPR, WEIGHTED>(m, st, 0, m.n, sweeps, omega, seed, theta, wd, wt, X, W, mu,
                                        strong, nstrong, status);
                 __threadfence_block();
                 __syncthreads();
@@ -141,7 +141,7 @@ __global__ __launch_bounds__(kBlock) void batched_kernel(
             }
             const int r0 = tk.tile * tile_rows;
             const int r1 = min(m.n, r0 + tile_rows);
-            batch_stage<T, K, LPR>(m, tk.stage, r0, r1, sweeps, omega, seed, theta, wd, wt, X, W,
+            batch_stage<T, K, LPR, WEIGHTED>(m, tk.stage, r0, r1, sweeps, omega, seed, theta, wd, wt, X, W,
                                    mu, strong, nstrong, status);
             __threadfence();  // release: this tile's rows before the signal
             __syncthreads();
@@ -201,9 +201,14 @@ static int batched_launch(ad_handle h, const BatchMat* mats, const BatchTask* ta
                           void* W, void* mu, uint8_t* strong, int32_t* nstrong, hipStream_t s) {
     const int zb = (int)((nctrl + kBlock - 1) / kBlock);
     zero_ints_kernel<<<dim3(zb), dim3(kBlock), 0, s>>>(ctrl, nctrl);
-    batched_kernel<T, K, LPR><<<dim3(grid), dim3(kBlock), 0, s>>>(
-        mats, tasks, ntasks, ctrl, sweeps, (T)omega, seed, theta, w, tile_rows, (T*)X, (T*)W,
-        (T*)mu, strong, nstrong, h->status);
+    if (w)
+        batched_kernel<T, K, LPR, true><<<dim3(grid), dim3(kBlock), 0, s>>>(
+            mats, tasks, ntasks, ctrl, sweeps, (T)omega, seed, theta, w, tile_rows, (T*)X, (T*)W,
+            (T*)mu, strong, nstrong, h->status);
+    else
+        batched_kernel<T, K, LPR, false><<<dim3(grid), dim3(kBlock), 0, s>>>(
+            mats, tasks, ntasks, ctrl, sweeps, (T)omega, seed, theta, w, tile_rows, (T*)X, (T*)W,
+            (T*)mu, strong, nstrong, h->status);
     AD_HIP(hipGetLastError());
     return AD_OK;
 }
@@ -229,7 +234,7 @@ static int batched_dispatch(ad_handle h, int K, int lpr, const BatchMat* mats,
 template <typename T, int K, int LPR>
 static int occupancy_of() {
     int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, batched_kernel<T, K, LPR>, kBlock, 0) !=
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, batched_kernel<T, K, LPR, false>, kBlock, 0) !=
         hipSuccess)
         return 1;
     return nb > 0 ? nb : 1;

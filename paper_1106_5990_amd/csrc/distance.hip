@@ -18,7 +18,7 @@
 
 namespace ad {
 
-template <typename T, int K, int LPR>
+template <typename T, int K, int LPR, bool WEIGHTED>
 __global__ __launch_bounds__(kBlock) void algdist_kernel(
     int n, const int* __restrict__ rp, const int* __restrict__ ci, const T* __restrict__ av,
     const T* __restrict__ X, const double* __restrict__ w, int target, T* __restrict__ mu,
@@ -47,8 +47,8 @@ __global__ __launch_bounds__(kBlock) void algdist_kernel(
     for (int it = 0; it < iter; ++it) {
         const int64_t i64 = tile * rows_per_tile + (int64_t)it * S::RPB + wv * S::RPW + g;
         if (i64 >= n) break;
-        algdist_row<S, T, K>((int)i64, l, rp, ci, av, X, wd, wt, plain, mu, pout, theta, fmask,
-                             strong, nstrong, status);
+        algdist_row<S, T, K, WEIGHTED>((int)i64, l, rp, ci, av, X, wd, wt, plain, mu, pout, theta,
+                                       fmask, strong, nstrong, status);
     }
 }
 
@@ -60,9 +60,14 @@ static void algdist_go(const ad_csr* A, const void* X, const double* w, int targ
     const int64_t rpt = (int64_t)S::RPB * cfg.iter;
     const int64_t ntiles = (A->n + rpt - 1) / rpt;
     const int grid = cfg.xcd_map ? grid_for_tiles(ntiles) : (int)ntiles;
-    algdist_kernel<T, K, LPR><<<dim3(grid), dim3(kBlock), 0, s>>>(
-        A->n, A->row_ptr, A->col, (const T*)A->val, (const T*)X, w, target, (T*)mu, p, theta,
-        fmask, strong, nstrong, cfg.iter, cfg.xcd_map, st);
+    if (w)
+        algdist_kernel<T, K, LPR, true><<<dim3(grid), dim3(kBlock), 0, s>>>(
+            A->n, A->row_ptr, A->col, (const T*)A->val, (const T*)X, w, target, (T*)mu, p, theta,
+            fmask, strong, nstrong, cfg.iter, cfg.xcd_map, st);
+    else
+        algdist_kernel<T, K, LPR, false><<<dim3(grid), dim3(kBlock), 0, s>>>(
+            A->n, A->row_ptr, A->col, (const T*)A->val, (const T*)X, w, target, (T*)mu, p, theta,
+            fmask, strong, nstrong, cfg.iter, cfg.xcd_map, st);
 }
 
 template <typename T>

@@ -82,7 +82,16 @@ template <> struct Guard<float> { static constexpr bool on = true; };
 
 // Distances mu_ij of one row (and, when strong != nullptr, its strength
 // row): see distance.hip for the method.
-template <typename S, typename T, int K>
+// In FP32, p = S_ab / S_bb is formed with the hardware reciprocal: mu is
+// stationary in p at the minimiser, so a one-ulp change of p moves mu only at
+// second order.  WEIGHTED = false drops the w_k products (w == 1).
+template <typename T>
+__device__ __forceinline__ T ratio(T a, T b) {
+    if constexpr (sizeof(T) == 4) return a * __builtin_amdgcn_rcpf(b);
+    else return a / b;
+}
+
+template <typename S, typename T, int K, bool WEIGHTED>
 __device__ __forceinline__ void algdist_row(int i, int l, const int* __restrict__ rp,
                                             const int* __restrict__ ci, const T* __restrict__ av,
                                             const T* __restrict__ X, const double (&wd)[S::V],
@@ -129,7 +138,7 @@ __device__ __forceinline__ void algdist_row(int i, int l, const int* __restrict_
     T saa = T(0);
 #pragma unroll
     for (int q = 0; q < V; ++q) {
-        wtt[q] = wt[q] * t.v[q];
+        wtt[q] = WEIGHTED ? wt[q] * t.v[q] : t.v[q];
         saa = fma(wtt[q], t.v[q], saa);
     }
     saa = group_sum<LPR>(saa);
@@ -166,16 +175,16 @@ __device__ __forceinline__ void algdist_row(int i, int l, const int* __restrict_
 #pragma unroll
             for (int q = 0; q < V; ++q) {
                 sab = fma(wtt[q], xj.v[q], sab);
-                sbb = fma(wt[q] * xj.v[q], xj.v[q], sbb);
+                sbb = fma(WEIGHTED ? wt[q] * xj.v[q] : xj.v[q], xj.v[q], sbb);
             }
             sab = group_sum<LPR>(sab);
             sbb = group_sum<LPR>(sbb);
-            T p = (sbb > T(0)) ? sab / sbb : T(0);
+            T p = (sbb > T(0)) ? ratio(sab, sbb) : T(0);
             T m = T(0);
 #pragma unroll
             for (int q = 0; q < V; ++q) {
-                const T r = t.v[q] - p * xj.v[q];
-                m = fma(wt[q] * r, r, m);
+                const T r = fma(-p, xj.v[q], t.v[q]);
+                m = fma(WEIGHTED ? wt[q] * r : r, r, m);
             }
             m = group_sum<LPR>(m);
             double pd = (double)p;

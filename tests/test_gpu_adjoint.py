@@ -92,10 +92,15 @@ def test_zero_sweeps_and_asymmetric_pattern_flag():
 
 def test_adjoint_against_central_differences_full_size():
     """Workload 5 at full size (512^2 log-normal 5-point, K = 16, 6 sweeps,
-    learnable omega, checkpoints every 2 sweeps): central differences with
-    h = 1e-6 max(1, |theta|) on omega, 4096 sampled entries (diagonals and
-    boundary rows included) and 16 random directions;
-    |g - g_FD| <= 1e-5 |g_FD| + 1e-9 max|g|."""
+    learnable omega, checkpoints every 2 sweeps): central differences on
+    omega, 4096 sampled entries (diagonals and boundary rows included) and 16
+    random directions, at two steps:
+      h = 1e-6 max(1, |theta|) and h = 1e-4 max(1, |theta|):
+      |g - g_FD| <= 1e-5 |g_FD| + 1e-9 max|g| + 4 eps |L| / h.
+    The last term is the rounding floor of a central difference of a loss
+    evaluated to relative precision ~eps (2 eps |L| / (2 h), doubled); here
+    L ~ 270 while max|g| ~ 0.07, so for h = 1e-6 it dominates and the larger
+    step gives the sharper check (its truncation error is O(h^2))."""
     ad = lib()
     wl = W.workload(5)
     A = wl.A
@@ -134,12 +139,16 @@ def test_adjoint_against_central_differences_full_size():
     gmax = np.abs(g).max()
     say("  L = %.10g, dL/domega = %.10g, max|g| = %.4g" % (L0, gw, gmax))
 
-    def check(fd, an, what):
-        ok = abs(an - fd) <= 1e-5 * abs(fd) + 1e-9 * gmax
-        assert ok, "%s: adjoint %.10g FD %.10g" % (what, an, fd)
+    eps = np.finfo(np.float64).eps
 
-    h = 1e-6 * max(1.0, abs(omega))
-    check((loss(v0, omega + h) - loss(v0, omega - h)) / (2 * h), gw, "omega")
+    def check(fd, an, what, h):
+        lim = 1e-5 * abs(fd) + 1e-9 * gmax + 4 * eps * abs(L0) / h
+        assert abs(an - fd) <= lim, "%s (h=%g): adjoint %.10g FD %.10g" % (what, h, an, fd)
+        return abs(an - fd) / lim
+
+    for rel in (1e-6, 1e-4):
+        h = rel * max(1.0, abs(omega))
+        check((loss(v0, omega + h) - loss(v0, omega - h)) / (2 * h), gw, "omega", h)
     rng = np.random.default_rng(0)
     rid = A.row_ids()
     diag = np.nonzero(A.col == rid)[0]
@@ -149,23 +158,23 @@ def test_adjoint_against_central_differences_full_size():
     sample = np.unique(np.concatenate([rng.choice(A.nnz, 3584, replace=False),
                                        rng.choice(diag, 256, replace=False),
                                        rng.choice(boundary, 256, replace=False)]))
-    worst = 0.0
-    for e in sample:
-        he = 1e-6 * max(1.0, abs(A.val[e]))
-        vp = v0.clone()
-        vp[e] += he
-        vm = v0.clone()
-        vm[e] -= he
-        fd = (loss(vp, omega) - loss(vm, omega)) / (2 * he)
-        worst = max(worst, abs(g[e] - fd) / (1e-5 * abs(fd) + 1e-9 * gmax))
-        check(fd, g[e], "entry %d" % e)
-    say("  %d entries: worst err / bound = %.3g" % (len(sample), worst))
+    for rel in (1e-6, 1e-4):
+        worst = 0.0
+        for e in sample:
+            he = rel * max(1.0, abs(A.val[e]))
+            vp = v0.clone()
+            vp[e] += he
+            vm = v0.clone()
+            vm[e] -= he
+            fd = (loss(vp, omega) - loss(vm, omega)) / (2 * he)
+            worst = max(worst, check(fd, g[e], "entry %d" % e, he))
+        say("  h=%g: %d entries, worst err / bound = %.3g" % (rel, len(sample), worst))
     for q in range(16):
         d = rng.standard_normal(A.nnz)
         dw = rng.standard_normal()
         dt = torch.as_tensor(d, device=dev)
-        hd = 1e-6
-        fd = (loss(v0 + hd * dt, omega + hd * dw) - loss(v0 - hd * dt, omega - hd * dw)) / (2 * hd)
-        an = float(g @ d + gw * dw)
-        assert abs(an - fd) <= 1e-5 * abs(fd) + 1e-9 * gmax * np.abs(d).sum() / np.sqrt(len(d)), q
+        for hd in (1e-6, 1e-4):
+            fd = (loss(v0 + hd * dt, omega + hd * dw) - loss(v0 - hd * dt, omega - hd * dw)) / (2 * hd)
+            an = float(g @ d + gw * dw)
+            check(fd, an, "direction %d" % q, hd)
     assert ad.status(clear=True) == 0
