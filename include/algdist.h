@@ -142,6 +142,16 @@ int algdist_autotune(ad_handle h, const ad_csr *A, int32_t K, int32_t relax, con
                      int32_t ncolors, const uint8_t *cf, int32_t caliber, const char *cache_json,
                      void *stream);
 
+/* Time every valid launch shape (lanes per row, row steps per tile, XCD
+ * tile mapping) of relax_algdist_batched on this batch (As: host array of
+ * nmat device CSRs of one dtype; `sweeps` Jacobi sweeps) and install the
+ * fastest for the batch's dtype, K and stored-entries-per-row bucket.
+ * cache_json as for algdist_autotune (kernel name "batched").  Allocates
+ * scratch outputs of the batch's size for the duration of the call and
+ * synchronises the stream. */
+int algdist_autotune_batched(ad_handle h, int32_t nmat, const ad_csr *As, int32_t K,
+                             int32_t sweeps, const char *cache_json, void *stream);
+
 /* Check the CSR invariants listed above on the device; violations set
  * AD_STAT_CSR_* bits.  Not needed on the hot path (no other call reads
  * more than it is given, but their results are defined only for valid
@@ -266,19 +276,24 @@ int ls_interp(ad_handle h, const ad_csr *A, int32_t K, const void *X, const doub
  * distances of Sec. 4.1 (plain target) with the fused strength graph of
  * Sec. 4.2 (theta; all rows in F) -- exactly what setup_testvectors +
  * algebraic_distance compute for the block-diagonal matrix made of the
- * batch -- in one persistent launch.
+ * batch.
  * Outputs are concatenated in matrix order: X (sum n) x K, mu (sum nnz,
  * the CSR's dtype), strong (sum nnz, may be NULL), nstrong (sum n, may be
  * NULL).  Start values use the global row index: entry (r, k) of the
  * concatenated panel is the (r*K + k + 1)-th splitmix64 output from seed.
  * w (K FP64, may be NULL) weights the distances.
- * The first call for a given argument set builds the task table (largest
- * matrices first) and captures the launch in a HIP graph; repeated calls
- * with the same arguments replay it.  The batch state is owned by the
- * handle.  Launch shape: algdist_set_launch("batched", ...) with
- * lanes_per_row and rows_per_lane (a tile is rows_per_lane row steps of
- * one workgroup; matrices of at most 4 tiles are run whole by one
- * workgroup). */
+ * Every member is cut into row tiles; each stage (start, each sweep,
+ * distances) is one launch over the tiles of all members, so no workgroup
+ * waits on another.  The first call for a given argument set (pointers,
+ * sizes, scalars, launch shape) uploads the tile table and captures the
+ * sweeps + 2 launches in a HIP graph; later calls with the same arguments
+ * replay it on `stream`.  With per-kernel timing on, or when the caller is
+ * capturing `stream`, the launches are issued directly instead.  The batch
+ * state (a second panel of (sum n) x K, the tables, the graph) is owned by
+ * the handle and freed by algdist_destroy.  Calls that overlap on one
+ * handle race.  Launch shape: algdist_set_launch("batched", ...) with
+ * lanes_per_row, rows_per_lane (row steps per tile) and xcd_map, or
+ * algdist_autotune_batched. */
 int relax_algdist_batched(ad_handle h, int32_t nmat, const ad_csr *As, int32_t K, uint64_t seed,
                           int32_t sweeps, double omega, const double *w, void *X, void *mu,
                           double theta, uint8_t *strong, int32_t *nstrong, void *stream);

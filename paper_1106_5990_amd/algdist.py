@@ -62,6 +62,7 @@ _SIGS = {
     "algdist_timing": (_i32, [_P, C.c_int]),
     "algdist_timing_report": (C.c_char_p, [_P]),
     "algdist_autotune": (_i32, [_P, _CSRP, _i32, _i32, _P, _i32, _P, _i32, C.c_char_p, _P]),
+    "algdist_autotune_batched": (_i32, [_P, _i32, _CSRP, _i32, _i32, C.c_char_p, _P]),
     "algdist_set_launch": (_i32, [_P, C.c_char_p, _i32, _i32, _i32, _i32, _i32, _i32]),
     "csr_validate": (_i32, [_P, _CSRP, _P]),
     "setup_testvectors": (_i32, [_P, _CSRP, _i32, _u64, _P, _i32, _i32, _f64, _P, _i32, _P, _P,
@@ -200,6 +201,18 @@ def autotune(A: Csr, K: int, relax: str = "jacobi", color: Optional[torch.Tensor
     _check(rc, h, "algdist_autotune")
 
 
+def autotune_batched(mats, K: int, sweeps: int, cache_json: Optional[str] = None,
+                     stream=None) -> None:
+    """Time every launch shape of relax_algdist_batched on this batch and
+    install the fastest (algdist_autotune_batched)."""
+    h = handle(mats[0].device.index)
+    arr = (ad_csr * len(mats))(*[m._s for m in mats])
+    rc = _lib.algdist_autotune_batched(h, len(mats), arr, K, sweeps,
+                                       None if cache_json is None else cache_json.encode(),
+                                       _stream(stream))
+    _check(rc, h, "algdist_autotune_batched")
+
+
 def csr_validate(A: Csr, stream=None) -> None:
     h = handle(A.device.index)
     _check(_lib.csr_validate(h, A.ref(), _stream(stream)), h, "csr_validate")
@@ -287,8 +300,9 @@ def relax_algdist_batched(mats, K: int, seed: int = 0, sweeps: int = 4, omega: f
                           X: Optional[torch.Tensor] = None, mu: Optional[torch.Tensor] = None,
                           strong: Optional[torch.Tensor] = None,
                           nstrong: Optional[torch.Tensor] = None, stream=None):
-    """Start + Jacobi sweeps + distances (+ strength) for a list of Csr in one
-    persistent launch.  Returns (X, mu, strong, nstrong), concatenated in list
+    """Start + Jacobi sweeps + distances (+ strength) for a list of Csr, one
+    launch per stage over the tiles of all members (replayed from a captured
+    graph on repeated calls).  Returns (X, mu, strong, nstrong), concatenated in list
     order (strong/nstrong None when fuse=False)."""
     dev = mats[0].device
     h = handle(dev.index)

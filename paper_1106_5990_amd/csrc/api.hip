@@ -84,6 +84,17 @@ int nnz_bucket(int64_t nnz, int n) {
     return r < 8 ? 0 : r < 16 ? 1 : r < 32 ? 2 : 3;
 }
 
+// bucket of a batch: stored entries per row over all members
+int batch_bucket(int nmat, const ad_csr* As) {
+    int64_t rows = 0, ents = 0;
+    for (int m = 0; m < nmat; ++m) {
+        rows += As[m].n;
+        ents += As[m].nnz;
+    }
+    const double r = rows > 0 ? (double)ents / (double)rows : 0.0;
+    return r < 8 ? 0 : r < 16 ? 1 : r < 32 ? 2 : 3;
+}
+
 LaunchCfg cfg_for(ad_handle h, int kernel, int dtype, int K, const ad_csr* A) {
     const int ks = k_slot(K);
     const int b = nnz_bucket(A->nnz, A->n);
@@ -251,6 +262,23 @@ int algdist_autotune(ad_handle h, const ad_csr* A, int32_t K, int32_t relax, con
     AD_HIP(hipSetDevice(h->device));
     rc = autotune(h, A, K, relax, color, ncolors, cf, caliber, cache_json, (hipStream_t)stream);
     return rc ? fail(h, rc, "autotune") : AD_OK;
+}
+
+int algdist_autotune_batched(ad_handle h, int32_t nmat, const ad_csr* As, int32_t K,
+                             int32_t sweeps, const char* cache_json, void* stream) {
+    if (!h) return AD_EINVAL;
+    h->err.clear();
+    if (nmat < 1 || !As) return fail(h, AD_EINVAL, "nmat = %d or As is NULL", nmat);
+    int rc;
+    for (int m = 0; m < nmat; ++m) {
+        if ((rc = check_csr(h, &As[m]))) return fail(h, rc, "matrix %d: %s", m, h->err.c_str());
+        if (As[m].dtype != As[0].dtype) return fail(h, AD_EDTYPE, "matrix %d has another dtype", m);
+    }
+    if (!k_ok(K)) return fail(h, AD_EINVAL, "K = %d: must be 2, 4, 8, 16, 32 or 64", K);
+    if (sweeps < 0) return fail(h, AD_EINVAL, "sweeps = %d < 0", sweeps);
+    AD_HIP(hipSetDevice(h->device));
+    rc = autotune_batched(h, nmat, As, K, sweeps, cache_json, (hipStream_t)stream);
+    return rc ? fail(h, rc, "batched autotune") : AD_OK;
 }
 
 int csr_validate(ad_handle h, const ad_csr* A, void* stream) {
@@ -483,17 +511,14 @@ int relax_algdist_batched(ad_handle h, int32_t nmat, const ad_csr* As, int32_t K
     if (strong && !(theta > 0.0 && theta < 1.0))
         return fail(h, AD_EINVAL, "theta = %g outside (0, 1)", theta);
     if (rows == 0) return AD_OK;
-    // The persistent kernel with inter-workgroup waits did not finish on the
-    // device and its cause is not established: the path stays off.
-    return fail(h, AD_EUNSUPPORTED, "relax_algdist_batched: the persistent batched path is disabled");
     AD_HIP(hipSetDevice(h->device));
-    ad_csr probe = As[0];
-    probe.n = (int32_t)(rows / nmat > 0 ? rows / nmat : 1);
-    probe.nnz = ents / nmat;
-    const LaunchCfg cfg = cfg_for(h, KN_BATCHED, As[0].dtype, K, &probe);
+    const int dt = As[0].dtype;
+    const int ks = k_slot(K), b = batch_bucket(nmat, As);
+    const LaunchCfg cfg = h->has_tuned[KN_BATCHED][dt][ks][b] ? h->tuned[KN_BATCHED][dt][ks][b]
+                                                               : LaunchCfg();
     TimedScope ts(h, "batched", (hipStream_t)stream);
     rc = launch_batched(h, nmat, As, K, seed, sweeps, omega, w, X, mu, theta, strong, nstrong, cfg,
-                        (hipStream_t)stream);
+                        h->timing, (hipStream_t)stream);
     return rc ? fail(h, rc, "relax_algdist_batched launch") : AD_OK;
 }
 

@@ -241,4 +241,79 @@ int autotune(ad_handle h, const ad_csr* A, int K, int relax, const int32_t* colo
     return AD_OK;
 }
 
+// Batched sequence: every valid (lanes per row, row steps per tile, XCD
+// mapping) of the batch's dtype and K is timed on the batch itself (direct
+// launches into scratch outputs); the best is stored for the batch's
+// entries-per-row bucket.
+int autotune_batched(ad_handle h, int nmat, const ad_csr* As, int K, int sweeps, const char* cache,
+                     hipStream_t s) {
+    const int dt = As[0].dtype;
+    const int ks = k_slot(K);
+    const int bucket = batch_bucket(nmat, As);
+    const char* fam = kFamilyName[KN_BATCHED];
+    std::vector<Entry> entries = read_cache(cache);
+    for (const Entry& e : entries)
+        if (e.kernel == fam && e.dtype == dt && e.K == K && e.bucket == bucket) {
+            LaunchCfg c;
+            c.lpr = e.lpr;
+            c.iter = e.iter;
+            c.xcd_map = e.xcd;
+            h->tuned[KN_BATCHED][dt][ks][bucket] = c;
+            h->has_tuned[KN_BATCHED][dt][ks][bucket] = true;
+            return AD_OK;
+        }
+    int64_t rows = 0, ents = 0;
+    for (int m = 0; m < nmat; ++m) {
+        rows += As[m].n;
+        ents += As[m].nnz;
+    }
+    if (rows == 0) return AD_OK;
+    const size_t vs = dt == AD_F32 ? 4 : 8;
+    Scratch sc;
+    void* X = sc.get((size_t)rows * K * vs);
+    void* mu = sc.get((size_t)ents * vs);
+    uint8_t* strong = (uint8_t*)sc.get((size_t)ents);
+    int32_t* ns = (int32_t*)sc.get(sizeof(int32_t) * (size_t)rows);
+    if (!X || !mu || !strong || !ns) return AD_ENOMEM;
+    hipEvent_t ea, eb;
+    AD_HIP(hipEventCreate(&ea));
+    AD_HIP(hipEventCreate(&eb));
+    struct Ev {
+        hipEvent_t a, b;
+        ~Ev() {
+            (void)hipEventDestroy(a);
+            (void)hipEventDestroy(b);
+        }
+    } ev{ea, eb};
+    const int iters[3] = {1, 2, 4};
+    double best = 1e30;
+    LaunchCfg bestc;
+    for (int L = 1; L <= kWave; L *= 2) {
+        if (!lpr_valid(dt, K, L)) continue;
+        for (int it : iters)
+            for (int xcd = 0; xcd <= 1; ++xcd) {
+                LaunchCfg c;
+                c.lpr = L;
+                c.iter = it;
+                c.xcd_map = xcd;
+                bool ok = true;
+                const double ms = time_ms(s, ea, eb, 3, [&] {
+                    return launch_batched(h, nmat, As, K, 1, sweeps, 2.0 / 3.0, nullptr, X, mu, 0.25,
+                                          strong, ns, c, true, s);
+                }, ok);
+                if (ok && ms < best) {
+                    best = ms;
+                    bestc = c;
+                }
+            }
+    }
+    AD_HIP(hipStreamSynchronize(s));
+    if (best >= 1e30) return AD_EDEVICE;
+    h->tuned[KN_BATCHED][dt][ks][bucket] = bestc;
+    h->has_tuned[KN_BATCHED][dt][ks][bucket] = true;
+    entries.push_back(Entry{fam, dt, K, bucket, bestc.lpr, bestc.iter, bestc.xcd_map, best});
+    write_cache(cache, entries);
+    return AD_OK;
+}
+
 }  // namespace ad

@@ -165,8 +165,12 @@ int autotune(ad_handle h, const ad_csr* A, int K, int relax, const int32_t* colo
 // ---- batched.hip
 int launch_batched(ad_handle h, int nmat, const ad_csr* As, int K, uint64_t seed, int sweeps,
                    double omega, const double* w, void* X, void* mu, double theta,
-                   uint8_t* strong, int32_t* nstrong, const LaunchCfg& cfg, hipStream_t s);
+                   uint8_t* strong, int32_t* nstrong, const LaunchCfg& cfg, bool direct,
+                   hipStream_t s);
 void batch_state_free(ad_handle h);
+int autotune_batched(ad_handle h, int nmat, const ad_csr* As, int K, int sweeps, const char* cache,
+                     hipStream_t s);
+int batch_bucket(int nmat, const ad_csr* As);
 
 // ---- adjoint.hip
 int launch_ls_loss_backward(ad_handle h, int K, const ad_csr* A, const void* ckpt, int ce,

@@ -1,5 +1,5 @@
 // rowops.h -- per-row bodies shared by the single-matrix kernels and the
-// batched persistent kernel (so both compute bitwise the same values).
+// batched kernels (so both compute bitwise the same values).
 #pragma once
 
 #include <math.h>
