@@ -23,6 +23,7 @@ import json
 import math
 import os
 import sys
+import tempfile
 import time
 
 import numpy as np
@@ -42,6 +43,8 @@ def parse():
     ap.add_argument("--cpu-sample", type=int, default=None, help="grid side of the oracle sample")
     ap.add_argument("--graph", action="store_true", help="replay the step as a captured HIP graph")
     ap.add_argument("--batched", action="store_true", help="run the batched leg (workload 4)")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the default launch shapes instead of the autotuner's")
     ap.add_argument("--batch-size", type=int, default=512)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one 1 GiB device-to-device copy (a kernel of known traffic "
@@ -133,19 +136,21 @@ def kernel_bytes(wl, s):
     out = {"tv_init": panel}
     out["jacobi"] = (n + 1) * 4 + nnz * (4 + s) + 2 * panel
     if wl.color is not None:
-        # colour phases run on colour-major permuted panels: a phase reads
-        # its rows' list entries, row pointers, permuted columns and values,
-        # every panel row once (new rows of earlier colours, old otherwise)
-        # and writes its rows once
+        # colour phases run on a colour-major copy of the CSR and permuted
+        # panels: a phase reads its rows' pointers, permuted columns and
+        # values, every panel row once (new rows of earlier colours, old
+        # otherwise), writes its rows once, and in the last sweep reads its
+        # rows' natural indices (averaged over the sweeps)
         per = []
         for c in range(wl.ncolors):
             rows = wl.color == c
             nc_, nnzc = int(rows.sum()), int(deg[rows].sum())
-            per.append(nc_ * (4 + 8) + nnzc * (4 + s) + panel + nc_ * K * s)
+            per.append(nc_ * 4 + nnzc * (4 + s) + panel + nc_ * K * s + nc_ * 4 / wl.sweeps)
         out["gs_phase"] = float(np.mean(per))
-        # partition (3 passes over the colours), inverse permutation,
-        # permuted columns (read col, gather, write)
-        out["color_partition"] = n * 4 * 3 + n * 4 * 2 + nnz * 4 * 2
+        # colour counts, scatter of the row list, inverse permutation,
+        # permuted row lengths (sums, then pointers) and the entry copy
+        # (columns through the inverse, values)
+        out["color_partition"] = n * 4 * 14 + nnz * (8 + 2 * s)
         out["tv_init"] = panel + n * 4
     out["algdist"] = (n + 1) * 4 + nnz * 4 + panel + nnz * s + nnz + n * 4
     F = wl.cf == 0
@@ -219,8 +224,6 @@ def batched_leg(args, torch, ad, W):
     shape is picked by the batch autotuner (outside the timed region); the
     timed region replays the captured stage graph; a separate pass with
     per-kernel timing gives the sweep kernel's rate for the roofline."""
-    import json
-    import tempfile
     workers = min(16, os.cpu_count() or 1)
     mats = W.batch_workload(args.batch_size, workers=workers)
     K, S, om, th = W.BATCH_K, W.BATCH_SWEEPS, W.BATCH_OMEGA, W.BATCH_THETA
@@ -334,13 +337,24 @@ def main():
             continue
         b = build_inputs(wl, dtype, torch, ad)
         step = make_step(wl, b, ad)
+        if not args.no_autotune:
+            # launch shapes picked by the library's autotuner on this matrix
+            # (outside the timed region)
+            print("[bench] autotune %s" % tag, file=sys.stderr, flush=True)
+            cache = os.path.join(tempfile.mkdtemp(prefix="algdist_tune_"), "shapes.jsonl")
+            ad.autotune(b["A"], wl.K, relax=wl.relax, color=b["color"], ncolors=wl.ncolors,
+                        cf=b["cf"], caliber=wl.caliber, cache_json=cache)
+            shapes = {e["kernel"]: {k: e[k] for k in ("lpr", "iter", "xcd")}
+                      for e in (json.loads(l) for l in open(cache))}
+        else:
+            shapes = "defaults"
         print("[bench] timing %s leg: %d warmup + %d steps" % (tag, args.warmup, steps),
               file=sys.stderr, flush=True)
         ms, wall_ms, kern = timed(step, steps, args.warmup, torch, ad, graph=args.graph)
         bits = ad.status(clear=True)
         s = 4 if dtype == torch.float32 else 8
         kb = kernel_bytes(wl, s)
-        res[tag] = {"ms": ms, "wall_ms": wall_ms, "kernels": kern, "kb": kb,
+        res[tag] = {"ms": ms, "wall_ms": wall_ms, "kernels": kern, "kb": kb, "shapes": shapes,
                     "step_bytes": step_bytes(wl, s, kb), "status": bits, "steps": steps}
         del b, step
         torch.cuda.empty_cache()
@@ -391,7 +405,7 @@ def main():
                                               else "Jacobi omega=%.3g" % wl.omega),
                    "theta": wl.theta, "caliber": wl.caliber,
                    "precision": "FP32 relaxation and distances, FP64 interpolation solves",
-                   "graph": bool(args.graph)},
+                   "graph": bool(args.graph), "launch_shapes": main_leg["shapes"]},
         "roofline": roof,
         "step_hbm_frac": round(main_leg["step_bytes"] / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
         "kernels": kstats,

@@ -291,11 +291,12 @@ int csr_validate(ad_handle h, const ad_csr* A, void* stream) {
     return launch_csr_validate(A, h->status, (hipStream_t)stream);
 }
 
-// Colour-phase Gauss-Seidel sweeps in the colour-major panel layout:
-// stable colour partition (rowlist: permuted row -> natural row, seg), the
-// permuted column of every entry (colp), the start written in permuted
-// order, ping-pong of two permuted panels, and the last sweep writing each
-// row straight to its natural position in X.  Checkpoints are un-permuted.
+// Colour-phase Gauss-Seidel sweeps in the colour-major layout: stable
+// colour partition (rowlist: permuted row -> natural row, seg), a
+// colour-major copy of the CSR (rows of one colour contiguous, permuted
+// columns), the start written in permuted order, ping-pong of two permuted
+// panels, and the last sweep writing each row straight to its natural
+// position in X.  Checkpoints are un-permuted.
 static int gs_sweeps(ad_handle h, const ad_csr* A, int K, uint64_t seed, const void* X0,
                      int sweeps, const int32_t* color, int ncolors, void* X, void* ckpt,
                      int ckpt_every, hipStream_t s) {
@@ -308,22 +309,24 @@ static int gs_sweeps(ad_handle h, const ad_csr* A, int K, uint64_t seed, const v
     const size_t o_pb = req.add(panel);
     const size_t o_rl = req.add(sizeof(int32_t) * (size_t)n);
     const size_t o_inv = req.add(sizeof(int32_t) * (size_t)n);
+    const size_t o_rpp = req.add(sizeof(int32_t) * ((size_t)n + 1));
     const size_t o_colp = req.add(sizeof(int32_t) * (size_t)A->nnz);
+    const size_t o_valp = req.add(dsize(dt) * (size_t)A->nnz);
     const size_t o_seg = req.add(sizeof(int32_t) * (ncolors + 2));
     const size_t o_cnt = req.add(sizeof(int32_t) * (size_t)(ncolors + 1) * nblk);
+    const size_t o_bs = req.add(sizeof(int32_t) * (size_t)perm_scan_blocks(n));
     int rc;
     if ((rc = ws_reserve(h, req.off))) return fail(h, rc, "workspace of %zu bytes", req.off);
     char* ws = (char*)h->ws;
     void* P[2] = {ws + o_pa, ws + o_pb};
     int32_t* rowlist = (int32_t*)(ws + o_rl);
-    int32_t* inv = (int32_t*)(ws + o_inv);
-    int32_t* colp = (int32_t*)(ws + o_colp);
     int32_t* seg = (int32_t*)(ws + o_seg);
+    PermCsr pc{n, rowlist, seg, (int32_t*)(ws + o_rpp), (int32_t*)(ws + o_colp), ws + o_valp};
     {
         TimedScope ts(h, "color_partition", s);
         rc = launch_color_partition(n, color, ncolors, rowlist, seg, (int32_t*)(ws + o_cnt), nblk,
                                     h->status, s);
-        if (!rc) rc = launch_perm_setup(n, A->nnz, A->col, rowlist, inv, colp, s);
+        if (!rc) rc = launch_perm_setup(dt, A, pc, (int32_t*)(ws + o_inv), (int32_t*)(ws + o_bs), s);
         if (rc) return fail(h, rc, "colour partition launch");
     }
     {
@@ -344,9 +347,8 @@ static int gs_sweeps(ad_handle h, const ad_csr* A, int K, uint64_t seed, const v
         const bool last = q == sweeps - 1;
         for (int c = 0; c < ncolors; ++c) {
             TimedScope ts(h, "gs_phase", s);
-            rc = launch_gs_phase_perm(dt, K, A, colp, c, ncolors, rowlist, seg, Xold, Xnew,
-                                      last ? X : nullptr, (!last || c < ncolors - 1) ? 1 : 0,
-                                      h->status, cfg, s);
+            rc = launch_gs_phase_perm(dt, K, pc, c, ncolors, Xold, Xnew, last ? X : nullptr,
+                                      (!last || c < ncolors - 1) ? 1 : 0, h->status, cfg, s);
             if (rc) return fail(h, rc, "relaxation launch");
         }
     }

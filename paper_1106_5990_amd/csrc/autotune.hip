@@ -147,18 +147,22 @@ int autotune(ad_handle h, const ad_csr* A, int K, int relax, const int32_t* colo
     } ev{ea, eb};
 
     // colour-major setup for the colour phases
-    int32_t *rowlist = nullptr, *seg = nullptr, *colp = nullptr;
+    PermCsr pc{n, nullptr, nullptr, nullptr, nullptr, nullptr};
     if (need[0] && relax == AD_MULTICOLOR_GS) {
         const int nblk = color_partition_blocks(n);
-        rowlist = (int32_t*)sc.get(sizeof(int32_t) * (size_t)n);
+        int32_t* rowlist = (int32_t*)sc.get(sizeof(int32_t) * (size_t)n);
         int32_t* inv = (int32_t*)sc.get(sizeof(int32_t) * (size_t)n);
-        colp = (int32_t*)sc.get(sizeof(int32_t) * (size_t)A->nnz);
-        seg = (int32_t*)sc.get(sizeof(int32_t) * (ncolors + 2));
+        int32_t* rpp = (int32_t*)sc.get(sizeof(int32_t) * ((size_t)n + 1));
+        int32_t* colp = (int32_t*)sc.get(sizeof(int32_t) * (size_t)A->nnz);
+        void* valp = sc.get(vs * (size_t)A->nnz);
+        int32_t* seg = (int32_t*)sc.get(sizeof(int32_t) * (ncolors + 2));
         int32_t* cnt = (int32_t*)sc.get(sizeof(int32_t) * (size_t)(ncolors + 1) * nblk);
-        if (!rowlist || !inv || !colp || !seg || !cnt) return AD_ENOMEM;
+        int32_t* bsum = (int32_t*)sc.get(sizeof(int32_t) * (size_t)perm_scan_blocks(n));
+        if (!rowlist || !inv || !rpp || !colp || !valp || !seg || !cnt || !bsum) return AD_ENOMEM;
         if ((rc = launch_color_partition(n, color, ncolors, rowlist, seg, cnt, nblk, h->status, s)))
             return rc;
-        if ((rc = launch_perm_setup(n, A->nnz, A->col, rowlist, inv, colp, s))) return rc;
+        pc = PermCsr{n, rowlist, seg, rpp, colp, valp};
+        if ((rc = launch_perm_setup(dt, A, pc, inv, bsum, s))) return rc;
     }
     int32_t* Pc = nullptr;
     double *Pv = nullptr, *ls = nullptr, *bs = nullptr;
@@ -196,8 +200,8 @@ int autotune(ad_handle h, const ad_csr* A, int K, int relax, const int32_t* colo
                         ms = time_ms(s, ea, eb, 3, [&] {
                             int r = AD_OK;
                             for (int cc = 0; cc < ncolors && !r; ++cc)
-                                r = launch_gs_phase_perm(dt, K, A, colp, cc, ncolors, rowlist, seg,
-                                                         X, X2, nullptr, 1, h->status, c, s);
+                                r = launch_gs_phase_perm(dt, K, pc, cc, ncolors, X, X2, nullptr, 1,
+                                                         h->status, c, s);
                             return r;
                         }, ok);
                         ms /= ncolors;

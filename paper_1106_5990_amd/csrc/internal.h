@@ -131,12 +131,23 @@ int launch_color_partition(int n, const int32_t* color, int ncolors, int32_t* ro
                            int32_t* seg, int32_t* counts, int nblocks, unsigned* status,
                            hipStream_t s);
 int color_partition_blocks(int n);
-int launch_gs_phase_perm(int dtype, int K, const ad_csr* A, const int32_t* colp, int c,
-                         int ncolors, const int32_t* rowlist, const int32_t* seg, const void* Xold,
+// Colour-major copy of a CSR for the colour phases: permuted row p is natural
+// row rowlist[p]; its entries rpp[p]..rpp[p+1] keep their CSR order with
+// columns mapped to permuted indices (colpp) and values copied (valpp).
+struct PermCsr {
+    int n;
+    const int32_t* rowlist;  // n
+    const int32_t* seg;      // ncolors + 2
+    const int32_t* rpp;      // n + 1
+    const int32_t* colpp;    // nnz
+    const void* valpp;       // nnz values of the CSR's dtype
+};
+int perm_scan_blocks(int n);
+int launch_perm_setup(int dtype, const ad_csr* A, PermCsr& P, int32_t* inv, int32_t* bsum,
+                      hipStream_t s);
+int launch_gs_phase_perm(int dtype, int K, const PermCsr& P, int c, int ncolors, const void* Xold,
                          void* Xnew, void* Xnat, int write_perm, unsigned* status,
                          const LaunchCfg& cfg, hipStream_t s);
-int launch_perm_setup(int n, int64_t nnz, const int32_t* col, const int32_t* rowlist, int32_t* inv,
-                      int32_t* colp, hipStream_t s);
 int launch_start_perm(int dtype, int n, int K, const int32_t* rowlist, uint64_t seed,
                       const void* X0, void* Xp, hipStream_t s);
 int launch_unpermute(int dtype, int n, int K, const int32_t* rowlist, const void* Xp, void* X,

@@ -135,20 +135,18 @@ __global__ __launch_bounds__(kBlock) void color_count_kernel(int n, const int* _
     for (int q = threadIdx.x; q <= nc; q += kBlock) counts[(size_t)q * nblocks + blockIdx.x] = cnt[q];
 }
 
-// Exclusive scan of counts[0 .. m) in place (single workgroup of 1024
-// threads), plus seg[q] = scanned value at q * nblocks, seg[nc + 1] = n.
-__global__ __launch_bounds__(1024) void scan_counts_kernel(int* __restrict__ counts, int m,
-                                                           int nblocks, int nc, int n,
-                                                           int* __restrict__ seg) {
+// In-place exclusive scan of a[0 .. m) by one workgroup of 1024 threads
+// (contiguous chunks per thread, Hillis-Steele over the chunk sums).
+// Returns the total.
+__device__ int scan_1024(int* __restrict__ a, int m) {
     __shared__ int part[1024];
     const int t = threadIdx.x;
     const int chunk = (m + 1023) / 1024;
     const int b = t * chunk, e = min(m, b + chunk);
     int s = 0;
-    for (int q = b; q < e; ++q) s += counts[q];
+    for (int q = b; q < e; ++q) s += a[q];
     part[t] = s;
     __syncthreads();
-    // Hillis-Steele inclusive scan over the 1024 chunk sums
     for (int o = 1; o < 1024; o <<= 1) {
         int v = (t >= o) ? part[t - o] : 0;
         __syncthreads();
@@ -157,13 +155,23 @@ __global__ __launch_bounds__(1024) void scan_counts_kernel(int* __restrict__ cou
     }
     int run = (t > 0) ? part[t - 1] : 0;
     for (int q = b; q < e; ++q) {
-        int c = counts[q];
-        counts[q] = run;
+        int c = a[q];
+        a[q] = run;
         run += c;
     }
+    const int total = part[1023];
     __syncthreads();
-    for (int q = t; q <= nc; q += 1024) seg[q] = counts[(size_t)q * nblocks];
-    if (t == 0) seg[nc + 1] = n;
+    return total;
+}
+
+// Exclusive scan of the class-major count table, plus seg[q] = scanned
+// value at q * nblocks, seg[nc + 1] = n.
+__global__ __launch_bounds__(1024) void scan_counts_kernel(int* __restrict__ counts, int m,
+                                                           int nblocks, int nc, int n,
+                                                           int* __restrict__ seg) {
+    scan_1024(counts, m);
+    for (int q = threadIdx.x; q <= nc; q += 1024) seg[q] = counts[(size_t)q * nblocks];
+    if (threadIdx.x == 0) seg[nc + 1] = n;
 }
 
 __global__ __launch_bounds__(kBlock) void color_scatter_kernel(int n, const int* __restrict__ color,
@@ -236,35 +244,146 @@ __global__ __launch_bounds__(kBlock) void inverse_perm_kernel(int n, const int* 
     if (p < n) inv[rowlist[p]] = (int)p;
 }
 
-__global__ __launch_bounds__(kBlock) void permute_cols_kernel(int64_t nnz, const int* __restrict__ ci,
-                                                              const int* __restrict__ inv,
-                                                              int* __restrict__ colp) {
-    const int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (e < nnz) colp[e] = inv[ci[e]];
+// Colour-major CSR: permuted row p holds the entries of natural row
+// rowlist[p] in their CSR order, columns mapped to permuted indices, so a
+// phase reads its rows' entries as one contiguous range.  Row pointers are
+// an exclusive scan of the permuted row lengths in blocks of kScanRows rows
+// (4 consecutive rows per thread): block sums, one scan of the sums, then a
+// block-local scan.
+constexpr int kScanRows = 4 * kBlock;
+
+int perm_scan_blocks(int n) { return (n + kScanRows - 1) / kScanRows; }
+
+__device__ __forceinline__ void perm_lens(int n, const int* __restrict__ rp,
+                                          const int* __restrict__ rowlist, int p0, int (&len)[4]) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int p = p0 + q;
+        len[q] = 0;
+        if (p < n) {
+            const int i = rowlist[p];
+            len[q] = rp[i + 1] - rp[i];
+        }
+    }
 }
 
-// Xp[p] = hash start of natural row rowlist[p] (or X0[rowlist[p]] if given)
+__device__ __forceinline__ int wave_incl_scan(int v) {
+    const int lane = threadIdx.x & (kWave - 1);
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+        const int t = __shfl_up(v, o, kWave);
+        if (lane >= o) v += t;
+    }
+    return v;
+}
+
+__global__ __launch_bounds__(kBlock) void perm_len_sums_kernel(int n, const int* __restrict__ rp,
+                                                               const int* __restrict__ rowlist,
+                                                               int* __restrict__ bsum) {
+    __shared__ int wsum[kWavesPerBlock];
+    int len[4];
+    perm_lens(n, rp, rowlist, blockIdx.x * kScanRows + threadIdx.x * 4, len);
+    const int v = wave_incl_scan(len[0] + len[1] + len[2] + len[3]);
+    if ((threadIdx.x & (kWave - 1)) == kWave - 1) wsum[threadIdx.x / kWave] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int t = 0;
+        for (int w = 0; w < kWavesPerBlock; ++w) t += wsum[w];
+        bsum[blockIdx.x] = t;
+    }
+}
+
+__global__ __launch_bounds__(1024) void scan_block_sums_kernel(int* __restrict__ bsum, int m) {
+    scan_1024(bsum, m);
+}
+
+__global__ __launch_bounds__(kBlock) void perm_row_ptr_kernel(int n, const int* __restrict__ rp,
+                                                              const int* __restrict__ rowlist,
+                                                              const int* __restrict__ boff,
+                                                              int* __restrict__ rpp) {
+    __shared__ int wsum[kWavesPerBlock];
+    const int p0 = blockIdx.x * kScanRows + threadIdx.x * 4;
+    int len[4];
+    perm_lens(n, rp, rowlist, p0, len);
+    const int mine = len[0] + len[1] + len[2] + len[3];
+    const int incl = wave_incl_scan(mine);
+    const int wv = threadIdx.x / kWave;
+    if ((threadIdx.x & (kWave - 1)) == kWave - 1) wsum[wv] = incl;
+    __syncthreads();
+    int off = boff[blockIdx.x] + incl - mine;
+    for (int w = 0; w < wv; ++w) off += wsum[w];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int p = p0 + q;
+        if (p < n) rpp[p] = off;
+        off += len[q];
+        if (p == n - 1) rpp[n] = off;
+    }
+}
+
+// 8 lanes per permuted row copy its entries: colpp = inv[col], valpp = val.
+constexpr int kCopyLanes = 8;
+
 template <typename T>
-__global__ __launch_bounds__(kBlock) void start_perm_kernel(int n, int K, const int* __restrict__ rowlist,
+__global__ __launch_bounds__(kBlock) void permute_entries_kernel(
+    int n, const int* __restrict__ rp, const int* __restrict__ ci, const T* __restrict__ av,
+    const int* __restrict__ rowlist, const int* __restrict__ inv, const int* __restrict__ rpp,
+    int* __restrict__ colpp, T* __restrict__ valpp) {
+    const int64_t gid = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int64_t p = gid / kCopyLanes;
+    const int l = (int)(gid % kCopyLanes);
+    if (p >= n) return;
+    const int i = rowlist[p];
+    const int e0 = rp[i], e1 = rp[i + 1];
+    const int o = rpp[p] - e0;
+    for (int e = e0 + l; e < e1; e += kCopyLanes) {
+        colpp[o + e] = inv[ci[e]];
+        valpp[o + e] = av[e];
+    }
+}
+
+// Xp[p] = hash start of natural row rowlist[p] (or X0[rowlist[p]] if given);
+// E consecutive values per thread, stored as one 16-byte chunk.  K is a
+// power of two: row and column of a panel value come from shifts.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void start_perm_kernel(int64_t total, int kshift,
+                                                            const int* __restrict__ rowlist,
                                                             uint64_t seed, const T* __restrict__ X0,
                                                             T* __restrict__ Xp) {
-    const int64_t c = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (c >= (int64_t)n * K) return;
-    const int64_t p = c / K;
-    const int k = (int)(c - p * K);
-    const int64_t i = rowlist[p];
-    Xp[c] = X0 ? X0[i * K + k] : (T)uniform_pm1(splitmix64_at(seed, (uint64_t)(i * K + k)));
+    constexpr int E = 16 / sizeof(T);
+    const int64_t base = ((int64_t)blockIdx.x * kBlock + threadIdx.x) * E;
+    if (base >= total) return;
+    const int64_t kmask = ((int64_t)1 << kshift) - 1;
+    Frag<T, E> f;
+#pragma unroll
+    for (int q = 0; q < E; ++q) {
+        const int64_t c = base + q < total ? base + q : total - 1;
+        const int64_t src = ((int64_t)rowlist[c >> kshift] << kshift) | (c & kmask);
+        f.v[q] = X0 ? X0[src] : (T)uniform_pm1(splitmix64_at(seed, (uint64_t)src));
+    }
+    if (base + E <= total) {
+        store_frag<T, E>(Xp + base, f);
+    } else {
+        for (int q = 0; q < E && base + q < total; ++q) Xp[base + q] = f.v[q];
+    }
 }
 
 // X[rowlist[p]] = Xp[p]
 template <typename T>
-__global__ __launch_bounds__(kBlock) void unpermute_kernel(int n, int K, const int* __restrict__ rowlist,
-                                                           const T* __restrict__ Xp, T* __restrict__ X) {
+__global__ __launch_bounds__(kBlock) void unpermute_kernel(int64_t total, int kshift,
+                                                           const int* __restrict__ rowlist,
+                                                           const T* __restrict__ Xp,
+                                                           T* __restrict__ X) {
     const int64_t c = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (c >= (int64_t)n * K) return;
-    const int64_t p = c / K;
-    const int k = (int)(c - p * K);
-    X[(int64_t)rowlist[p] * K + k] = Xp[c];
+    if (c >= total) return;
+    const int64_t kmask = ((int64_t)1 << kshift) - 1;
+    X[((int64_t)rowlist[c >> kshift] << kshift) | (c & kmask)] = Xp[c];
+}
+
+static int log2_of(int K) {
+    int s = 0;
+    while ((1 << s) < K) ++s;
+    return s;
 }
 
 // One colour phase in the permuted layout.  Rows p in [seg[c], seg[c+1]):
@@ -274,7 +393,7 @@ __global__ __launch_bounds__(kBlock) void unpermute_kernel(int n, int K, const i
 // The phase of colour 0 also carries the held rows (invalid colour).
 template <typename T, int K, int LPR>
 __global__ __launch_bounds__(kBlock) void gs_phase_perm_kernel(
-    const int* __restrict__ rp, const int* __restrict__ colp, const T* __restrict__ av, int c,
+    const int* __restrict__ rpp, const int* __restrict__ colpp, const T* __restrict__ valpp, int c,
     int nc, const int* __restrict__ rowlist, const int* __restrict__ seg,
     const T* __restrict__ Xold, T* __restrict__ Xnew, T* __restrict__ Xnat, int write_perm,
     int iter, int xcd, unsigned* status) {
@@ -291,10 +410,9 @@ __global__ __launch_bounds__(kBlock) void gs_phase_perm_kernel(
         for (int it = 0; it < iter; ++it) {
             const int64_t p = b0 + tile * rows_per_tile + (int64_t)it * S::RPB + wv * S::RPW + g;
             if (p >= b1) break;
-            const int i = rowlist[p];
             T y[V], d;
             Frag<T, V> xi;
-            row_spmm<S, T, K>((int)p, rp[i], rp[i + 1], colp, av, l,
+            row_spmm<S, T, K>((int)p, rpp[p], rpp[p + 1], colpp, valpp, l,
                               [&](int jp) { return (jp < b0) ? (const T*)Xnew : Xold; }, y, d, xi);
             Frag<T, V> out;
             if (d == T(0)) {
@@ -305,7 +423,7 @@ __global__ __launch_bounds__(kBlock) void gs_phase_perm_kernel(
                 for (int q = 0; q < V; ++q) out.v[q] = xi.v[q] - y[q] / d;
             }
             if (write_perm) store_lane<T, V, C>(Xnew + (size_t)p * K + l * V, out);
-            if (Xnat) store_lane<T, V, C>(Xnat + (size_t)i * K + l * V, out);
+            if (Xnat) store_lane<T, V, C>(Xnat + (size_t)rowlist[p] * K + l * V, out);
         }
     }
     if (c == 0) {  // rows with an invalid colour are held fixed
@@ -320,53 +438,66 @@ __global__ __launch_bounds__(kBlock) void gs_phase_perm_kernel(
 }
 
 template <typename T, int K, int LPR>
-static void gsp_go(const ad_csr* A, const int32_t* colp, int c, int nc, const int32_t* rowlist,
-                   const int32_t* seg, const void* Xold, void* Xnew, void* Xnat, int write_perm,
-                   unsigned* st, const LaunchCfg& cfg, hipStream_t s) {
+static void gsp_go(const PermCsr& P, int c, int nc, const void* Xold, void* Xnew, void* Xnat,
+                   int write_perm, unsigned* st, const LaunchCfg& cfg, hipStream_t s) {
     using S = Shape<T, K, LPR>;
     const int64_t rpt = (int64_t)S::RPB * cfg.iter;
-    const int64_t ntiles = (A->n + rpt - 1) / rpt;
+    const int64_t ntiles = (P.n + rpt - 1) / rpt;
     const int grid = cfg.xcd_map ? grid_for_tiles(ntiles) : (int)ntiles;
     gs_phase_perm_kernel<T, K, LPR><<<dim3(grid), dim3(kBlock), 0, s>>>(
-        A->row_ptr, colp, (const T*)A->val, c, nc, rowlist, seg, (const T*)Xold, (T*)Xnew,
+        P.rpp, P.colpp, (const T*)P.valpp, c, nc, P.rowlist, P.seg, (const T*)Xold, (T*)Xnew,
         (T*)Xnat, write_perm, cfg.iter, cfg.xcd_map, st);
 }
 
 template <typename T>
-static int gsp_dispatch(int K, const ad_csr* A, const int32_t* colp, int c, int nc,
-                        const int32_t* rowlist, const int32_t* seg, const void* Xold, void* Xnew,
+static int gsp_dispatch(int K, const PermCsr& P, int c, int nc, const void* Xold, void* Xnew,
                         void* Xnat, int write_perm, unsigned* st, const LaunchCfg& cfg,
                         hipStream_t s) {
     return with_k<T>(K, [&](auto kc) {
         constexpr int KK = decltype(kc)::value;
         return with_lpr<T, KK>(cfg.lpr, [&](auto lc) {
             constexpr int L = decltype(lc)::value;
-            gsp_go<T, KK, L>(A, colp, c, nc, rowlist, seg, Xold, Xnew, Xnat, write_perm, st, cfg, s);
+            gsp_go<T, KK, L>(P, c, nc, Xold, Xnew, Xnat, write_perm, st, cfg, s);
         });
     });
 }
 
-int launch_gs_phase_perm(int dtype, int K, const ad_csr* A, const int32_t* colp, int c,
-                         int ncolors, const int32_t* rowlist, const int32_t* seg, const void* Xold,
+int launch_gs_phase_perm(int dtype, int K, const PermCsr& P, int c, int ncolors, const void* Xold,
                          void* Xnew, void* Xnat, int write_perm, unsigned* status,
                          const LaunchCfg& cfg, hipStream_t s) {
-    if (A->n == 0) return AD_OK;
+    if (P.n == 0) return AD_OK;
     const int rc = (dtype == AD_F32)
-                       ? gsp_dispatch<float>(K, A, colp, c, ncolors, rowlist, seg, Xold, Xnew, Xnat,
-                                             write_perm, status, cfg, s)
-                       : gsp_dispatch<double>(K, A, colp, c, ncolors, rowlist, seg, Xold, Xnew, Xnat,
-                                              write_perm, status, cfg, s);
+                       ? gsp_dispatch<float>(K, P, c, ncolors, Xold, Xnew, Xnat, write_perm,
+                                             status, cfg, s)
+                       : gsp_dispatch<double>(K, P, c, ncolors, Xold, Xnew, Xnat, write_perm,
+                                              status, cfg, s);
     if (rc) return rc;
     AD_HIP(hipGetLastError());
     return AD_OK;
 }
 
-int launch_perm_setup(int n, int64_t nnz, const int32_t* col, const int32_t* rowlist, int32_t* inv,
-                      int32_t* colp, hipStream_t s) {
-    inverse_perm_kernel<<<dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, s>>>(n, rowlist, inv);
-    if (nnz > 0)
-        permute_cols_kernel<<<dim3((unsigned)((nnz + kBlock - 1) / kBlock)), dim3(kBlock), 0, s>>>(
-            nnz, col, inv, colp);
+// inv, then the colour-major row pointers and entries of P (whose rowlist is
+// already partitioned); bsum holds perm_scan_blocks(n) ints.
+int launch_perm_setup(int dtype, const ad_csr* A, PermCsr& P, int32_t* inv, int32_t* bsum,
+                      hipStream_t s) {
+    const int n = A->n;
+    if (n == 0) return AD_OK;
+    const unsigned nb = (unsigned)perm_scan_blocks(n);
+    inverse_perm_kernel<<<dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, s>>>(
+        n, P.rowlist, inv);
+    perm_len_sums_kernel<<<dim3(nb), dim3(kBlock), 0, s>>>(n, A->row_ptr, P.rowlist, bsum);
+    scan_block_sums_kernel<<<dim3(1), dim3(1024), 0, s>>>(bsum, (int)nb);
+    perm_row_ptr_kernel<<<dim3(nb), dim3(kBlock), 0, s>>>(n, A->row_ptr, P.rowlist, bsum,
+                                                          (int32_t*)P.rpp);
+    const unsigned cb = (unsigned)(((int64_t)n * kCopyLanes + kBlock - 1) / kBlock);
+    if (dtype == AD_F32)
+        permute_entries_kernel<float><<<dim3(cb), dim3(kBlock), 0, s>>>(
+            n, A->row_ptr, A->col, (const float*)A->val, P.rowlist, inv, P.rpp,
+            (int32_t*)P.colpp, (float*)P.valpp);
+    else
+        permute_entries_kernel<double><<<dim3(cb), dim3(kBlock), 0, s>>>(
+            n, A->row_ptr, A->col, (const double*)A->val, P.rowlist, inv, P.rpp,
+            (int32_t*)P.colpp, (double*)P.valpp);
     AD_HIP(hipGetLastError());
     return AD_OK;
 }
@@ -374,11 +505,15 @@ int launch_perm_setup(int n, int64_t nnz, const int32_t* col, const int32_t* row
 int launch_start_perm(int dtype, int n, int K, const int32_t* rowlist, uint64_t seed,
                       const void* X0, void* Xp, hipStream_t s) {
     const int64_t m = (int64_t)n * K;
-    const unsigned b = (unsigned)((m + kBlock - 1) / kBlock);
+    if (m == 0) return AD_OK;
+    const int E = dtype == AD_F32 ? 4 : 2;
+    const unsigned b = (unsigned)(((m + E - 1) / E + kBlock - 1) / kBlock);
     if (dtype == AD_F32)
-        start_perm_kernel<float><<<dim3(b), dim3(kBlock), 0, s>>>(n, K, rowlist, seed, (const float*)X0, (float*)Xp);
+        start_perm_kernel<float><<<dim3(b), dim3(kBlock), 0, s>>>(m, log2_of(K), rowlist, seed,
+                                                                  (const float*)X0, (float*)Xp);
     else
-        start_perm_kernel<double><<<dim3(b), dim3(kBlock), 0, s>>>(n, K, rowlist, seed, (const double*)X0, (double*)Xp);
+        start_perm_kernel<double><<<dim3(b), dim3(kBlock), 0, s>>>(m, log2_of(K), rowlist, seed,
+                                                                   (const double*)X0, (double*)Xp);
     AD_HIP(hipGetLastError());
     return AD_OK;
 }
@@ -386,11 +521,14 @@ int launch_start_perm(int dtype, int n, int K, const int32_t* rowlist, uint64_t 
 int launch_unpermute(int dtype, int n, int K, const int32_t* rowlist, const void* Xp, void* X,
                      hipStream_t s) {
     const int64_t m = (int64_t)n * K;
+    if (m == 0) return AD_OK;
     const unsigned b = (unsigned)((m + kBlock - 1) / kBlock);
     if (dtype == AD_F32)
-        unpermute_kernel<float><<<dim3(b), dim3(kBlock), 0, s>>>(n, K, rowlist, (const float*)Xp, (float*)X);
+        unpermute_kernel<float><<<dim3(b), dim3(kBlock), 0, s>>>(m, log2_of(K), rowlist,
+                                                                 (const float*)Xp, (float*)X);
     else
-        unpermute_kernel<double><<<dim3(b), dim3(kBlock), 0, s>>>(n, K, rowlist, (const double*)Xp, (double*)X);
+        unpermute_kernel<double><<<dim3(b), dim3(kBlock), 0, s>>>(m, log2_of(K), rowlist,
+                                                                  (const double*)Xp, (double*)X);
     AD_HIP(hipGetLastError());
     return AD_OK;
 }
