@@ -45,6 +45,9 @@ def parse():
     ap.add_argument("--batched", action="store_true", help="run the batched leg (workload 4)")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the default launch shapes instead of the autotuner's")
+    ap.add_argument("--tune-cache", default=None,
+                    help="autotuner cache file (JSON lines); shapes found there are used without "
+                         "timing, new ones are appended (default: a fresh temporary file)")
     ap.add_argument("--batch-size", type=int, default=512)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one 1 GiB device-to-device copy (a kernel of known traffic "
@@ -234,12 +237,13 @@ def batched_leg(args, torch, ad, W):
     out = {"workload": "rgg-batch-%d (n log-uniform 2k-200k, mean degree U[4,29]), K=%d, %d Jacobi "
                        "sweeps, theta=%g" % (nm, K, S, th),
            "matrices": nm, "rows": rows, "nnz": ents, "edges": E}
-    cache = os.path.join(tempfile.mkdtemp(prefix="algdist_tune_"), "batch.jsonl")
+    cache = args.tune_cache or os.path.join(tempfile.mkdtemp(prefix="algdist_tune_"), "batch.jsonl")
     for tag, dt, s in (("f32", torch.float32, 4), ("f64", torch.float64, 8)):
         print("[bench] batched leg %s: autotune" % tag, file=sys.stderr, flush=True)
         dm = [ad.Csr.from_host(m, dtype=dt) for m in mats]
         ad.autotune_batched(dm, K, S, cache_json=cache)
-        shape = [json.loads(l) for l in open(cache) if '"dtype": %d' % ad._dtype_code(dt) in l][-1]
+        shape = [e for e in (json.loads(l) for l in open(cache))
+                 if e["kernel"] == "batched" and e["dtype"] == ad._dtype_code(dt)][-1]
         X = torch.empty((rows, K), dtype=dt, device="cuda")
         mu = torch.empty(ents, dtype=dt, device="cuda")
         st = torch.empty(ents, dtype=torch.uint8, device="cuda")
@@ -341,11 +345,13 @@ def main():
             # launch shapes picked by the library's autotuner on this matrix
             # (outside the timed region)
             print("[bench] autotune %s" % tag, file=sys.stderr, flush=True)
-            cache = os.path.join(tempfile.mkdtemp(prefix="algdist_tune_"), "shapes.jsonl")
+            cache = args.tune_cache or os.path.join(tempfile.mkdtemp(prefix="algdist_tune_"),
+                                                    "shapes.jsonl")
             ad.autotune(b["A"], wl.K, relax=wl.relax, color=b["color"], ncolors=wl.ncolors,
                         cf=b["cf"], caliber=wl.caliber, cache_json=cache)
+            code = ad._dtype_code(dtype)
             shapes = {e["kernel"]: {k: e[k] for k in ("lpr", "iter", "xcd")}
-                      for e in (json.loads(l) for l in open(cache))}
+                      for e in (json.loads(l) for l in open(cache)) if e["dtype"] == code}
         else:
             shapes = "defaults"
         print("[bench] timing %s leg: %d warmup + %d steps" % (tag, args.warmup, steps),

@@ -4,7 +4,8 @@
 // valid shape of each family is timed with HIP events on scratch buffers:
 //   lanes per row L (K / L panel entries per lane: the panel width a lane
 //   owns; 64 / L rows per wavefront), rows per lane group per tile
-//   (1, 2, 4), and the XCD-contiguous tile mapping on or off.
+//   (1, 2, 4), and the XCD-contiguous tile mapping on or off; for the
+//   distances also L = 0, the edge-parallel form (one lane per entry).
 // The fastest shape per family is stored in the handle (the same slot
 // algdist_set_launch writes) and, if a cache path is given, in a JSON file:
 // one object per line,
@@ -181,10 +182,14 @@ int autotune(ad_handle h, const ad_csr* A, int K, int relax, const int32_t* colo
         const int fam = fams[q];
         double best = 1e30;
         LaunchCfg bestc;
-        for (int L = 1; L <= kWave; L *= 2) {
-            if (!lpr_valid(dt, K, L)) continue;
+        // lanes per row 0 is the default form: for distances the edge-parallel
+        // kernel (one lane per entry), which ignores the row-step count
+        for (int L = 0; L <= kWave; L = L ? 2 * L : 1) {
+            if (L == 0 ? !(fam == KN_ALGDIST && algdist_uses_edge(dt, K, AD_TARGET_PLAIN, LaunchCfg()))
+                       : !lpr_valid(dt, K, L))
+                continue;
             for (int it : iters) {
-                if (fam == KN_LS && it != 1) continue;  // LS rows ignore the row-step count
+                if ((fam == KN_LS || L == 0) && it != 1) continue;  // LS rows ignore the row-step count
                 for (int xcd = 0; xcd <= 1; ++xcd) {
                     LaunchCfg c;
                     c.lpr = L;
@@ -292,8 +297,10 @@ int autotune_batched(ad_handle h, int nmat, const ad_csr* As, int K, int sweeps,
     const int iters[3] = {1, 2, 4};
     double best = 1e30;
     LaunchCfg bestc;
-    for (int L = 1; L <= kWave; L *= 2) {
-        if (!lpr_valid(dt, K, L)) continue;
+    // lanes per row 0: default relaxation shape with edge-parallel distances
+    for (int L = 0; L <= kWave; L = L ? 2 * L : 1) {
+        if (L == 0 ? !algdist_uses_edge(dt, K, AD_TARGET_PLAIN, LaunchCfg()) : !lpr_valid(dt, K, L))
+            continue;
         for (int it : iters)
             for (int xcd = 0; xcd <= 1; ++xcd) {
                 LaunchCfg c;

@@ -102,6 +102,28 @@ __global__ __launch_bounds__(kBlock) void batch_algdist_kernel(
     }
 }
 
+// Distances in the edge-parallel form: a second tile table with tiles of
+// kEdgeRows rows per wavefront.
+template <typename T, int K, bool WEIGHTED>
+__global__ __launch_bounds__(kBlock) void batch_algdist_edge_kernel(
+    const BatchMat* __restrict__ mats, const BatchTile* __restrict__ tiles, int64_t ntiles,
+    int xcd, const T* __restrict__ X, const double* __restrict__ w, T* __restrict__ mu,
+    double theta, uint8_t* __restrict__ strong, int* __restrict__ nstrong, unsigned* status) {
+    __shared__ EdgeLds<T> lds;
+    const int64_t t = batch_tile(ntiles, xcd);
+    if (t < 0) return;  // whole workgroup
+    const BatchTile tl = tiles[t];
+    const BatchMat m = mats[tl.m];
+    const int r0 = tl.r0 + (threadIdx.x / kWave) * kEdgeRows;
+    const int rl = r0 < tl.r1 ? min(kEdgeRows, tl.r1 - r0) : 0;
+    algdist_edge_rows<T, K, WEIGHTED, true>(r0, rl, m.rp, m.ci, X + m.row0 * K, w, mu + m.e0,
+                                            nullptr, theta, nullptr,
+                                            strong ? strong + m.e0 : nullptr,
+                                            nstrong ? nstrong + m.row0 : nullptr, lds, status);
+}
+
+constexpr int kEdgeTileRows = kEdgeRows * kWavesPerBlock;
+
 // ---------------------------------------------------------------- host side
 namespace {
 
@@ -138,13 +160,14 @@ void drop_graph(BatchPlan& p) {
 
 struct Seq {
     ad_handle h;
-    int dt, K, lpr, iter, xcd, sweeps;
-    int64_t rows, ntiles;
+    int dt, K, lpr, iter, xcd, sweeps, edge;
+    int64_t rows, ntiles, nedge;
     uint64_t seed;
     double omega, theta;
     const double* w;
     const BatchMat* mats;
     const BatchTile* tiles;
+    const BatchTile* etiles;  // distance tiles of the edge-parallel form
     void *X, *W, *mu;
     uint8_t* strong;
     int32_t* nstrong;
@@ -162,6 +185,20 @@ void seq_launch(const Seq& q, hipStream_t s) {
             q.mats, q.tiles, q.ntiles, q.iter, q.xcd, buf(k - 1), buf(k), (T)q.omega, q.status);
     }
     TimedScope ts(q.h, "batch_algdist", s);
+    if constexpr (K * (int)sizeof(T) <= kEdgeMaxRowBytes) {
+        if (q.edge) {
+            const int eg = q.xcd ? grid_for_tiles(q.nedge) : (int)q.nedge;
+            if (q.w)
+                batch_algdist_edge_kernel<T, K, true><<<dim3(eg), dim3(kBlock), 0, s>>>(
+                    q.mats, q.etiles, q.nedge, q.xcd, (const T*)q.X, q.w, (T*)q.mu, q.theta,
+                    q.strong, q.nstrong, q.status);
+            else
+                batch_algdist_edge_kernel<T, K, false><<<dim3(eg), dim3(kBlock), 0, s>>>(
+                    q.mats, q.etiles, q.nedge, q.xcd, (const T*)q.X, nullptr, (T*)q.mu, q.theta,
+                    q.strong, q.nstrong, q.status);
+            return;
+        }
+    }
     if (q.w)
         batch_algdist_kernel<T, K, LPR, true><<<dim3(grid), dim3(kBlock), 0, s>>>(
             q.mats, q.tiles, q.ntiles, q.iter, q.xcd, (const T*)q.X, q.w, (T*)q.mu, q.theta,
@@ -223,6 +260,7 @@ int launch_batched(ad_handle h, int nmat, const ad_csr* As, int K, uint64_t seed
     const int xcd = cfg.xcd_map ? 1 : 0;
     const int rpb = (kWave / lpr) * kWavesPerBlock;
     const int64_t tile_rows = (int64_t)rpb * iter;
+    const int edge = algdist_uses_edge(dt, K, AD_TARGET_PLAIN, cfg) ? 1 : 0;
 
     // key: everything the tables and the captured graph depend on
     std::vector<uint8_t> key;
@@ -234,26 +272,29 @@ int launch_batched(ad_handle h, int nmat, const ad_csr* As, int K, uint64_t seed
     put(As, sizeof(ad_csr) * (size_t)nmat);
     const void* ptrs[5] = {X, mu, strong, nstrong, w};
     put(ptrs, sizeof ptrs);
-    const int ints[5] = {K, sweeps, lpr, iter, xcd};
+    const int ints[6] = {K, sweeps, lpr, iter, xcd, edge};
     put(ints, sizeof ints);
     const double dbl[2] = {omega, theta};
     put(dbl, sizeof dbl);
     put(&seed, sizeof seed);
 
     std::vector<BatchMat> mats((size_t)nmat);
-    int64_t rows = 0, ents = 0, ntiles = 0;
+    int64_t rows = 0, ents = 0, ntiles = 0, nedge = 0;
     for (int m = 0; m < nmat; ++m) {
         mats[m] = BatchMat{As[m].row_ptr, As[m].col, As[m].val, rows, ents};
         rows += As[m].n;
         ents += As[m].nnz;
         ntiles += (As[m].n + tile_rows - 1) / tile_rows;
+        if (edge) nedge += (As[m].n + kEdgeTileRows - 1) / kEdgeTileRows;
     }
-    if (ntiles > ((int64_t)1 << 31) - 8) return AD_ESTRUCT;  // grid limit
+    if (ntiles > ((int64_t)1 << 31) - 8 || nedge > ((int64_t)1 << 31) - 8)
+        return AD_ESTRUCT;  // grid limit
 
     WsReq req;
     const size_t o_w = req.add((size_t)rows * K * vsz);
     const size_t o_mats = req.add(sizeof(BatchMat) * (size_t)nmat);
     const size_t o_tiles = req.add(sizeof(BatchTile) * (size_t)(ntiles > 0 ? ntiles : 1));
+    const size_t o_etiles = req.add(sizeof(BatchTile) * (size_t)(nedge > 0 ? nedge : 1));
     const bool same = key == bs->plan.key && bs->dev_bytes >= req.off;
     if (!same) {
         drop_graph(bs->plan);
@@ -273,13 +314,19 @@ int launch_batched(ad_handle h, int nmat, const ad_csr* As, int K, uint64_t seed
     char* ws = (char*)bs->dev;
     BatchMat* dmats = (BatchMat*)(ws + o_mats);
     BatchTile* dtiles = (BatchTile*)(ws + o_tiles);
+    BatchTile* detiles = (BatchTile*)(ws + o_etiles);
 
     if (!same) {
         std::vector<BatchTile> tiles;
-        tiles.reserve((size_t)ntiles);
-        for (int m = 0; m < nmat; ++m)
-            for (int64_t r = 0; r < As[m].n; r += tile_rows)
-                tiles.push_back(BatchTile{m, (int)r, (int)std::min<int64_t>(As[m].n, r + tile_rows)});
+        tiles.reserve((size_t)(ntiles + nedge));
+        auto cut = [&](int64_t rows_per_tile) {
+            for (int m = 0; m < nmat; ++m)
+                for (int64_t r = 0; r < As[m].n; r += rows_per_tile)
+                    tiles.push_back(
+                        BatchTile{m, (int)r, (int)std::min<int64_t>(As[m].n, r + rows_per_tile)});
+        };
+        cut(tile_rows);
+        if (edge) cut(kEdgeTileRows);  // tiles[ntiles ..) are the distance tiles
         const size_t mb = sizeof(BatchMat) * mats.size();
         const size_t tb = mb + sizeof(BatchTile) * tiles.size();
         if (bs->host_bytes < tb) {
@@ -295,15 +342,19 @@ int launch_batched(ad_handle h, int nmat, const ad_csr* As, int K, uint64_t seed
         memcpy(bs->host_stage, mats.data(), mb);
         memcpy((char*)bs->host_stage + mb, tiles.data(), sizeof(BatchTile) * tiles.size());
         AD_HIP(hipMemcpyAsync(dmats, bs->host_stage, mb, hipMemcpyHostToDevice, s));
-        AD_HIP(hipMemcpyAsync(dtiles, (char*)bs->host_stage + mb, sizeof(BatchTile) * tiles.size(),
+        AD_HIP(hipMemcpyAsync(dtiles, (char*)bs->host_stage + mb, sizeof(BatchTile) * (size_t)ntiles,
                               hipMemcpyHostToDevice, s));
+        if (nedge > 0)
+            AD_HIP(hipMemcpyAsync(detiles,
+                                  (char*)bs->host_stage + mb + sizeof(BatchTile) * (size_t)ntiles,
+                                  sizeof(BatchTile) * (size_t)nedge, hipMemcpyHostToDevice, s));
         bs->plan.key = key;
         bs->plan.ntiles = ntiles;
     }
 
-    const Seq q{h,     dt,    K,      lpr,      iter,   xcd,    sweeps,  rows,     ntiles,
-                seed,  omega, theta,  w,        dmats,  dtiles, X,       ws + o_w, mu,
-                strong, nstrong, h->status};
+    const Seq q{h,     dt,      K,        lpr,   iter,  xcd,    sweeps, edge,
+                rows,  ntiles,  nedge,    seed,  omega, theta,  w,      dmats,
+                dtiles, detiles, X,       ws + o_w, mu,  strong, nstrong, h->status};
     hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
     AD_HIP(hipStreamIsCapturing(s, &cs));
     if (direct || cs != hipStreamCaptureStatusNone) return run_seq(q, s);  // caller records it

@@ -10,7 +10,14 @@
 // many digits) is recomputed in FP64 from the same FP32 values.  The strength
 // mask needs the row minimum of mu, known only after the row: the lane that
 // stored mu_ij re-reads its own store (program order) in a second pass.
+//
+// For the plain target and panel rows of at most 128 bytes the default
+// launch is edge-parallel instead (one lane per stored entry, whole rows of
+// x_i and x_j in registers, contiguous mu stores, LDS row minima); a
+// positive lanes-per-row choice selects the row-group form above.
 #include <math.h>
+
+#include <type_traits>
 
 #include "device.h"
 #include "internal.h"
@@ -70,6 +77,67 @@ static void algdist_go(const ad_csr* A, const void* X, const double* w, int targ
             fmask, strong, nstrong, cfg.iter, cfg.xcd_map, st);
 }
 
+// Edge-parallel form (plain target): a workgroup takes kEdgeRows rows per
+// wavefront; see algdist_edge_rows.
+template <typename T, int K, bool WEIGHTED, bool LEAN>
+__global__ __launch_bounds__(kBlock) void algdist_edge_kernel(
+    int n, const int* __restrict__ rp, const int* __restrict__ ci, const T* __restrict__ X,
+    const double* __restrict__ w, T* __restrict__ mu, double* __restrict__ pout, double theta,
+    const uint8_t* __restrict__ fmask, uint8_t* __restrict__ strong, int* __restrict__ nstrong,
+    int xcd, unsigned* status) {
+    __shared__ EdgeLds<T> lds;
+    const int64_t rows_per_tile = (int64_t)kEdgeRows * kWavesPerBlock;
+    const int64_t ntiles = (n + rows_per_tile - 1) / rows_per_tile;
+    const int64_t tile = xcd ? xcd_tile(ntiles) : (int64_t)blockIdx.x;
+    if (tile < 0 || tile >= ntiles) return;  // whole workgroup
+    const int64_t r0 = tile * rows_per_tile + (int64_t)(threadIdx.x / kWave) * kEdgeRows;
+    const int rl = r0 < n ? (int)min<int64_t>(kEdgeRows, n - r0) : 0;
+    algdist_edge_rows<T, K, WEIGHTED, LEAN>((int)r0, rl, rp, ci, X, w, mu, pout, theta, fmask,
+                                            strong, nstrong, lds, status);
+}
+
+template <typename T, int K>
+static void algdist_edge_go(const ad_csr* A, const void* X, const double* w, void* mu, double* p,
+                            double theta, const uint8_t* fmask, uint8_t* strong, int32_t* nstrong,
+                            unsigned* st, const LaunchCfg& cfg, hipStream_t s) {
+    const int64_t rpt = (int64_t)kEdgeRows * kWavesPerBlock;
+    const int64_t ntiles = (A->n + rpt - 1) / rpt;
+    const int grid = cfg.xcd_map ? grid_for_tiles(ntiles) : (int)ntiles;
+    auto go = [&](auto weighted, auto lean) {
+        algdist_edge_kernel<T, K, decltype(weighted)::value, decltype(lean)::value>
+            <<<dim3(grid), dim3(kBlock), 0, s>>>(A->n, A->row_ptr, A->col, (const T*)X, w, (T*)mu,
+                                                 p, theta, fmask, strong, nstrong, cfg.xcd_map, st);
+    };
+    using Y = std::true_type;
+    using N = std::false_type;
+    const bool lean = !fmask && !p;
+    if (w)
+        lean ? go(Y(), Y()) : go(Y(), N());
+    else
+        lean ? go(N(), Y()) : go(N(), N());
+}
+
+template <typename T>
+static int algdist_edge_dispatch(int K, const ad_csr* A, const void* X, const double* w, void* mu,
+                                 double* p, double theta, const uint8_t* fmask, uint8_t* strong,
+                                 int32_t* nstrong, unsigned* st, const LaunchCfg& cfg,
+                                 hipStream_t s) {
+    return with_k<T>(K, [&](auto kc) {
+        constexpr int KK = decltype(kc)::value;
+        if constexpr (KK * (int)sizeof(T) <= kEdgeMaxRowBytes) {
+            algdist_edge_go<T, KK>(A, X, w, mu, p, theta, fmask, strong, nstrong, st, cfg, s);
+            return AD_OK;
+        } else {
+            return AD_EINVAL;
+        }
+    });
+}
+
+bool algdist_uses_edge(int dtype, int K, int target, const LaunchCfg& cfg) {
+    return cfg.lpr <= 0 && target == AD_TARGET_PLAIN &&
+           K * (dtype == AD_F32 ? 4 : 8) <= kEdgeMaxRowBytes;
+}
+
 template <typename T>
 static int algdist_dispatch(int K, const ad_csr* A, const void* X, const double* w, int target,
                             void* mu, double* p, double theta, const uint8_t* fmask,
@@ -88,6 +156,16 @@ int launch_algdist(int dtype, int K, const ad_csr* A, const void* X, const doubl
                    void* mu, double* p, double theta, const uint8_t* fmask, uint8_t* strong,
                    int32_t* nstrong, unsigned* status, const LaunchCfg& cfg, hipStream_t s) {
     if (A->n == 0) return AD_OK;
+    if (algdist_uses_edge(dtype, K, target, cfg)) {
+        const int rc = (dtype == AD_F32)
+                           ? algdist_edge_dispatch<float>(K, A, X, w, mu, p, theta, fmask, strong,
+                                                          nstrong, status, cfg, s)
+                           : algdist_edge_dispatch<double>(K, A, X, w, mu, p, theta, fmask, strong,
+                                                           nstrong, status, cfg, s);
+        if (rc) return rc;
+        AD_HIP(hipGetLastError());
+        return AD_OK;
+    }
     const int rc =
         (dtype == AD_F32)
             ? algdist_dispatch<float>(K, A, X, w, target, mu, p, theta, fmask, strong, nstrong,

@@ -154,6 +154,9 @@ int launch_unpermute(int dtype, int n, int K, const int32_t* rowlist, const void
                      hipStream_t s);
 
 // ---- distance.hip
+// true when algebraic_distance runs the edge-parallel kernel: default lanes
+// per row (cfg.lpr <= 0), plain target, panel rows of at most 128 bytes.
+bool algdist_uses_edge(int dtype, int K, int target, const LaunchCfg& cfg);
 int launch_algdist(int dtype, int K, const ad_csr* A, const void* X, const double* w, int target,
                    void* mu, double* p, double theta, const uint8_t* fmask, uint8_t* strong,
                    int32_t* nstrong, unsigned* status, const LaunchCfg& cfg, hipStream_t s);

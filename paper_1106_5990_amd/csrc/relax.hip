@@ -321,24 +321,43 @@ __global__ __launch_bounds__(kBlock) void perm_row_ptr_kernel(int n, const int* 
     }
 }
 
-// 8 lanes per permuted row copy its entries: colpp = inv[col], valpp = val.
-constexpr int kCopyLanes = 8;
+// Entry copy in natural order, one wavefront per kCopyRows natural rows:
+// the rows' natural and permuted entry starts go to LDS, then the wave
+// walks the rows' natural entry range kWave entries at a time (contiguous
+// loads; each row's entries land as one contiguous run, and rows that are
+// neighbours in a colour are neighbours in the copy); a lane finds the row
+// of its entry by binary search over the starts.  colpp = inv[col],
+// valpp = val.
+constexpr int kCopyRows = 64;
 
 template <typename T>
 __global__ __launch_bounds__(kBlock) void permute_entries_kernel(
     int n, const int* __restrict__ rp, const int* __restrict__ ci, const T* __restrict__ av,
-    const int* __restrict__ rowlist, const int* __restrict__ inv, const int* __restrict__ rpp,
-    int* __restrict__ colpp, T* __restrict__ valpp) {
-    const int64_t gid = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    const int64_t p = gid / kCopyLanes;
-    const int l = (int)(gid % kCopyLanes);
-    if (p >= n) return;
-    const int i = rowlist[p];
-    const int e0 = rp[i], e1 = rp[i + 1];
-    const int o = rpp[p] - e0;
-    for (int e = e0 + l; e < e1; e += kCopyLanes) {
-        colpp[o + e] = inv[ci[e]];
-        valpp[o + e] = av[e];
+    const int* __restrict__ inv, const int* __restrict__ rpp, int* __restrict__ colpp,
+    T* __restrict__ valpp) {
+    __shared__ int s_rp[kWavesPerBlock][kCopyRows + 1];  // natural starts, then the end
+    __shared__ int s_dst[kWavesPerBlock][kCopyRows];     // permuted starts
+    const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
+    const int64_t r0 = ((int64_t)blockIdx.x * kWavesPerBlock + wv) * kCopyRows;
+    const int rl = r0 < n ? (int)min<int64_t>(kCopyRows, n - r0) : 0;
+    if (lane < rl) {
+        s_rp[wv][lane] = rp[r0 + lane];
+        s_dst[wv][lane] = rpp[inv[r0 + lane]];
+    }
+    if (lane == 0 && rl > 0) s_rp[wv][rl] = rp[r0 + rl];
+    __syncthreads();
+    if (rl == 0) return;
+    const int b = s_rp[wv][0], e = s_rp[wv][rl];
+    for (int q = b + lane; q < e; q += kWave) {
+        int lo = 0, hi = rl - 1;  // last row whose start is <= q
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (s_rp[wv][mid] <= q) lo = mid;
+            else hi = mid - 1;
+        }
+        const int d = s_dst[wv][lo] + (q - s_rp[wv][lo]);
+        colpp[d] = inv[ci[q]];
+        valpp[d] = av[q];
     }
 }
 
@@ -489,15 +508,16 @@ int launch_perm_setup(int dtype, const ad_csr* A, PermCsr& P, int32_t* inv, int3
     scan_block_sums_kernel<<<dim3(1), dim3(1024), 0, s>>>(bsum, (int)nb);
     perm_row_ptr_kernel<<<dim3(nb), dim3(kBlock), 0, s>>>(n, A->row_ptr, P.rowlist, bsum,
                                                           (int32_t*)P.rpp);
-    const unsigned cb = (unsigned)(((int64_t)n * kCopyLanes + kBlock - 1) / kBlock);
+    const int64_t rows_per_block = (int64_t)kCopyRows * kWavesPerBlock;
+    const unsigned cb = (unsigned)((n + rows_per_block - 1) / rows_per_block);
     if (dtype == AD_F32)
         permute_entries_kernel<float><<<dim3(cb), dim3(kBlock), 0, s>>>(
-            n, A->row_ptr, A->col, (const float*)A->val, P.rowlist, inv, P.rpp,
-            (int32_t*)P.colpp, (float*)P.valpp);
+            n, A->row_ptr, A->col, (const float*)A->val, inv, P.rpp, (int32_t*)P.colpp,
+            (float*)P.valpp);
     else
         permute_entries_kernel<double><<<dim3(cb), dim3(kBlock), 0, s>>>(
-            n, A->row_ptr, A->col, (const double*)A->val, P.rowlist, inv, P.rpp,
-            (int32_t*)P.colpp, (double*)P.valpp);
+            n, A->row_ptr, A->col, (const double*)A->val, inv, P.rpp, (int32_t*)P.colpp,
+            (double*)P.valpp);
     AD_HIP(hipGetLastError());
     return AD_OK;
 }

@@ -4,6 +4,8 @@
 
 #include <math.h>
 
+#include <type_traits>
+
 #include "device.h"
 
 namespace ad {
@@ -235,6 +237,168 @@ __device__ __forceinline__ void algdist_row(int i, int l, const int* __restrict_
         cnt = group_sum<LPR>(cnt);
         if (l == 0 && nstrong) nstrong[i] = cnt;
     }
+}
+
+// ---------------------------------------------------------------- edge-parallel distances
+// Plain target only.  One wavefront takes up to kEdgeRows consecutive rows
+// [r0, r0 + rl) and walks their stored entries kWave at a time, one entry
+// per lane.  The lane gathers x_i and x_j whole (K values each; lanes of one
+// row read the same x_i addresses), so S_ab, S_bb, p and mu need no
+// cross-lane reduction, and mu is stored contiguously; the next chunk's
+// column indices are loaded one chunk ahead.  With the strength row wanted,
+// each mu is folded into its row's minimum in LDS (the bit patterns of
+// non-negative floats order like unsigned integers) and the first kEdgeKeep
+// chunks keep (j, mu) in LDS; a second walk writes the mask and, through LDS
+// counters, the counts.
+// All threads of the workgroup call it (it holds workgroup barriers); LDS
+// regions are per wavefront.
+// Per entry the arithmetic is that of algdist_row with one lane per row:
+// the sums over k run in index order in the panel type, p in FP32 via the
+// hardware reciprocal, the FP64 recompute below 1e-4 S_aa.
+constexpr int kEdgeRows = 64;
+
+// panel rows up to this many bytes use the edge-parallel kernel by default
+constexpr int kEdgeMaxRowBytes = 128;
+
+template <typename T>
+using OrdBits = typename std::conditional<sizeof(T) == 4, unsigned, unsigned long long>::type;
+
+__device__ __forceinline__ unsigned ord_bits(float m) { return __float_as_uint(m + 0.0f); }
+__device__ __forceinline__ unsigned long long ord_bits(double m) {
+    return (unsigned long long)__double_as_longlong(m + 0.0);
+}
+__device__ __forceinline__ float from_ord(unsigned b) { return __uint_as_float(b); }
+__device__ __forceinline__ double from_ord(unsigned long long b) {
+    return __longlong_as_double((long long)b);
+}
+
+// chunks of kWave entries whose (j, mu) stay in LDS for the strength walk
+constexpr int kEdgeKeep = 12;
+
+template <typename T>
+struct EdgeLds {
+    int rp[kWavesPerBlock][kEdgeRows + 1];
+    OrdBits<T> mn[kWavesPerBlock][kEdgeRows];
+    int cnt[kWavesPerBlock][kEdgeRows];
+    T m[kWavesPerBlock][kEdgeKeep][kWave];
+    int j[kWavesPerBlock][kEdgeKeep][kWave];
+};
+
+// last row of the wave's block whose first entry is <= q, searching [lo, rl)
+__device__ __forceinline__ int edge_row(const int* __restrict__ starts, int lo, int rl, int q) {
+    int hi = rl - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (starts[mid] <= q) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+template <typename T, int K, bool WEIGHTED, bool LEAN>
+__device__ __forceinline__ void algdist_edge_rows(
+    int r0, int rl, const int* __restrict__ rp, const int* __restrict__ ci,
+    const T* __restrict__ X, const double* __restrict__ w, T* __restrict__ mu,
+    double* __restrict__ pout, double theta, const uint8_t* __restrict__ fmask,
+    uint8_t* __restrict__ strong, int* __restrict__ nstrong, EdgeLds<T>& L, unsigned* status) {
+    constexpr int C = (K * (int)sizeof(T) <= 16) ? K : 16 / (int)sizeof(T);
+    const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
+    const bool fuse = strong != nullptr;
+    int* starts = L.rp[wv];
+    if (lane < rl) {
+        starts[lane] = rp[r0 + lane];
+        L.mn[wv][lane] = ord_bits((T)INFINITY);
+        L.cnt[wv][lane] = 0;
+    }
+    if (lane == 0 && rl > 0) starts[rl] = rp[r0 + rl];
+    __syncthreads();
+    const int b = rl > 0 ? starts[0] : 0, e = rl > 0 ? starts[rl] : 0;
+    bool bad = false;
+    int row = 0;
+    // the next chunk's column index is loaded one chunk ahead
+    int jn = (b + lane < e) ? ci[b + lane] : 0;
+    for (int q = b + lane, c = 0; q < e; q += kWave, ++c) {
+        row = edge_row(starts, row, rl, q);
+        const int i = r0 + row;
+        const int j = jn;
+        jn = (q + kWave < e) ? ci[q + kWave] : 0;
+        T m;
+        double pd;
+        if (j == i) {  // x_i against itself: p = 1 and mu = 0 exactly
+            m = T(0);
+            pd = 1.0;
+        } else {
+            const Frag<T, K> t = load_lane<T, K, C>(X + (size_t)i * K);
+            const Frag<T, K> x = load_lane<T, K, C>(X + (size_t)j * K);
+            T sab = T(0), sbb = T(0), saa = T(0);
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                const T wk = WEIGHTED ? (T)w[k] : T(1);
+                const T wtk = WEIGHTED ? wk * t.v[k] : t.v[k];
+                saa = fma(wtk, t.v[k], saa);
+                sab = fma(wtk, x.v[k], sab);
+                sbb = fma(WEIGHTED ? wk * x.v[k] : x.v[k], x.v[k], sbb);
+            }
+            const T p = (sbb > T(0)) ? ratio(sab, sbb) : T(0);
+            m = T(0);
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                const T r = fma(-p, x.v[k], t.v[k]);
+                m = fma(WEIGHTED ? (T)w[k] * r : r, r, m);
+            }
+            pd = (double)p;
+            if (Guard<T>::on && m < (T)1e-4 * saa) {
+                // FP64 recompute from the same FP32 inputs
+                double a2 = 0.0, b2 = 0.0;
+#pragma unroll
+                for (int k = 0; k < K; ++k) {
+                    const double wk = WEIGHTED ? w[k] : 1.0;
+                    const double xq = (double)x.v[k], tq = (double)t.v[k];
+                    a2 = fma(wk * tq, xq, a2);
+                    b2 = fma(wk * xq, xq, b2);
+                }
+                pd = (b2 > 0.0) ? a2 / b2 : 0.0;
+                double m2 = 0.0;
+#pragma unroll
+                for (int k = 0; k < K; ++k) {
+                    const double wk = WEIGHTED ? w[k] : 1.0;
+                    const double r = (double)t.v[k] - pd * (double)x.v[k];
+                    m2 = fma(wk * r, r, m2);
+                }
+                m = (T)m2;
+            }
+            bad |= !isfinite(m);
+        }
+        mu[q] = m;
+        if (!LEAN && pout) pout[q] = pd;
+        if (fuse) {
+            if (c < kEdgeKeep) {
+                L.m[wv][c][lane] = m;
+                L.j[wv][c][lane] = j;
+            }
+            if (j != i && (LEAN || !fmask || fmask[j])) atomicMin(&L.mn[wv][row], ord_bits(m));
+        }
+    }
+    if (bad) flag(status, AD_STAT_NONFINITE);
+    if (!fuse) return;
+    __syncthreads();
+    row = 0;
+    for (int q = b + lane, c = 0; q < e; q += kWave, ++c) {
+        row = edge_row(starts, row, rl, q);
+        const int i = r0 + row;
+        const bool kept = c < kEdgeKeep;
+        const int j = kept ? L.j[wv][c][lane] : ci[q];
+        int st = 0;
+        if ((LEAN || !fmask || (fmask[i] && fmask[j])) && j != i) {
+            const double md = (double)from_ord(L.mn[wv][row]);
+            const double me = (double)(kept ? L.m[wv][c][lane] : mu[q]);  // own store
+            st = (md > 0.0) ? (theta * me < md) : (me == 0.0);
+        }
+        strong[q] = (uint8_t)st;
+        if (st) atomicAdd(&L.cnt[wv][row], 1);
+    }
+    __syncthreads();
+    if (lane < rl && nstrong) nstrong[r0 + lane] = L.cnt[wv][lane];
 }
 
 }  // namespace ad

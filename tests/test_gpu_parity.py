@@ -233,6 +233,99 @@ def test_algdist_matches_oracle(dt, target, K, weighted):
     assert ad.status(clear=True) == 0
 
 
+def coo_csr(n, i, j, v, diag):
+    """CSR from off-diagonal pairs (both orientations given) plus a diagonal."""
+    i = np.concatenate([i, np.arange(n)])
+    j = np.concatenate([j, np.arange(n)])
+    v = np.concatenate([v, diag])
+    o = np.lexsort((j, i))
+    i, j, v = i[o], j[o], v[o]
+    rp = np.zeros(n + 1, np.int64)
+    np.cumsum(np.bincount(i, minlength=n), out=rp[1:])
+    return W.CSR(n, rp.astype(np.int32), j.astype(np.int32), v)
+
+
+def irregular(n, seed):
+    """Random geometric graph plus one hub row joined to a fifth of the nodes
+    (a row spanning several 64-entry chunks) and a few isolated nodes (rows
+    with only the diagonal)."""
+    B = W.rgg_laplacian(n, 25.0, seed)
+    rid = B.row_ids()
+    off = B.col != rid
+    i, j, v = rid[off], B.col[off], B.val[off]
+    rng = np.random.default_rng(seed)
+    hub = n // 3
+    nb = rng.choice(np.setdiff1d(np.arange(n), [hub]), n // 5, replace=False)
+    keep = (i != hub) & (j != hub)
+    iso = rng.choice(n, 5, replace=False)
+    keep &= ~np.isin(i, iso) & ~np.isin(j, iso)
+    w = -(0.1 + rng.random(len(nb)))
+    i = np.concatenate([i[keep], np.full(len(nb), hub), nb])
+    j = np.concatenate([j[keep], nb, np.full(len(nb), hub)])
+    v = np.concatenate([v[keep], w, w])
+    deg = np.zeros(n)
+    np.add.at(deg, i, -v)
+    return coo_csr(n, i, j, v, deg + 1e-3)
+
+
+@pytest.mark.parametrize("dt", ["f64", "f32"])
+@pytest.mark.parametrize("weighted", [False, True])
+def test_edge_parallel_distances_irregular_rows(dt, weighted):
+    """The edge-parallel kernel (default shape, plain target) and the
+    row-group kernel against the oracle on rows of very uneven length: mu,
+    p, the fused strength row with and without an F mask."""
+    say("edge-parallel distances %s weighted=%s" % (dt, weighted))
+    ad = lib()
+    dtype = DT[dt]
+    K = 16
+    A = irregular(3000, 17)
+    Ao = as_oracle(A, dtype)
+    Ad = dev_csr(A, dtype)
+    X = ad.setup_testvectors(Ad, K, seed=5, relax="jacobi", sweeps=3, omega=0.7)
+    x = to_np(X).astype(np.float64)
+    w = (0.5 + np.random.default_rng(3).random(K)) if weighted else None
+    wt = None if w is None else torch.as_tensor(w, device="cuda")
+    fm = (np.random.default_rng(4).random(A.n) < 0.6).astype(np.uint8)
+    fmt = torch.as_tensor(fm, device="cuda")
+    mu_ref, p_ref, bad = oracle.algdist(Ao, x, w, oracle.TARGET_PLAIN, want_p=True)
+    saa = saa_per_edge(Ao, x, w)
+    try:
+        for lpr in (0, 2):
+            ad.set_launch("algdist", dtype, K, lpr, 1, True)
+            mu, p = ad.algebraic_distance(Ad, X, w=wt, want_p=True)
+            check_mu(to_np(mu).astype(np.float64), mu_ref, saa, dtype, "lpr %d" % lpr)
+            pg = to_np(p)
+            assert np.all(np.abs(pg - p_ref) <= (1e-3 if dt == "f32" else 1e-10)
+                          * np.maximum(1, np.abs(p_ref))), lpr
+            for fmask, fmh in ((None, None), (fmt, fm)):
+                mu2, s, ns = ad.algebraic_distance(Ad, X, w=wt, fuse=True, theta=0.3, fmask=fmask)
+                assert torch.equal(mu2, mu), lpr
+                sr, nsr = oracle.strength(A, to_np(mu).astype(np.float64), 0.3, fmh)
+                assert np.array_equal(to_np(s), sr) and np.array_equal(to_np(ns), nsr), lpr
+    finally:
+        ad.set_launch("algdist", dtype, K, 0, 1, True)
+    assert ad.status(clear=True) == 0
+
+
+@pytest.mark.parametrize("n", [1, 63, 64, 65, 257])
+def test_edge_parallel_distances_small_and_ragged(n):
+    say("edge-parallel distances n=%d" % n)
+    ad = lib()
+    K = 8
+    i = np.arange(n - 1)
+    A = coo_csr(n, np.concatenate([i, i + 1]), np.concatenate([i + 1, i]),
+                -np.ones(2 * (n - 1)), np.full(n, 2.5))
+    for dtype in (torch.float32, torch.float64):
+        Ad = dev_csr(A, dtype)
+        X = ad.setup_testvectors(Ad, K, seed=n, relax="jacobi", sweeps=2, omega=0.6)
+        x = to_np(X).astype(np.float64)
+        mu, s, ns = ad.algebraic_distance(Ad, X, fuse=True, theta=0.25)
+        check_mu(to_np(mu).astype(np.float64), oracle.algdist(as_oracle(A, dtype), x),
+                 saa_per_edge(A, x), dtype)
+        sr, nsr = oracle.strength(A, to_np(mu).astype(np.float64), 0.25)
+        assert np.array_equal(to_np(s), sr) and np.array_equal(to_np(ns), nsr)
+
+
 @pytest.mark.parametrize("dt", ["f64", "f32"])
 def test_algdist_exact_zero_for_proportional_vectors(dt):
     say("algdist exact zeros %s" % dt)
@@ -473,7 +566,7 @@ def test_every_launch_shape_gives_the_same_results(dt, K):
     cf = torch.as_tensor(W.cf_red_is_coarse((N, N)), device="cuda")
     ref = None
     try:
-        for lpr in valid_lprs(dtype, K):
+        for lpr in [0] + valid_lprs(dtype, K):
             for it in (1, 3):
                 for xcd in (True, False):
                     for kern in ("jacobi", "gs_phase", "algdist"):
