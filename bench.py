@@ -45,6 +45,8 @@ def parse():
     ap.add_argument("--batched", action="store_true", help="run the batched leg (workload 4)")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the default launch shapes instead of the autotuner's")
+    ap.add_argument("--separate", action="store_true",
+                    help="distances and LS rows as two calls instead of the fused pass")
     ap.add_argument("--tune-cache", default=None,
                     help="autotuner cache file (JSON lines); shapes found there are used without "
                          "timing, new ones are appended (default: a fresh temporary file)")
@@ -79,10 +81,18 @@ def build_inputs(wl, dtype, torch, ad):
     return buf
 
 
-def make_step(wl, b, ad):
+def make_step(wl, b, ad, fused=True):
+    """One pass of the path: test vectors, then distances with the strength
+    row and the LS rows -- in one fused pass (distance_ls) or as the two
+    separate calls."""
     def step():
         ad.setup_testvectors(b["A"], wl.K, seed=wl.tv_seed, relax=wl.relax, sweeps=wl.sweeps,
                              omega=wl.omega, color=b["color"], ncolors=wl.ncolors, out=b["X"])
+        if fused:
+            ad.distance_ls(b["A"], b["X"], b["cf"], wl.caliber, theta=wl.theta, mu=b["mu"],
+                           strong=b["strong"], nstrong=b["ns"], P_col=b["Pc"], P_val=b["Pv"],
+                           ls_val=b["ls"], row_status=b["st"], ls_sum=b["lsum"], want_sum=True)
+            return
         ad.algebraic_distance(b["A"], b["X"], mu=b["mu"], fuse=True, theta=wl.theta,
                               strong=b["strong"], nstrong=b["ns"])
         ad.ls_interp(b["A"], b["X"], b["cf"], b["mu"], wl.caliber, P_col=b["Pc"], P_val=b["Pv"],
@@ -161,12 +171,16 @@ def kernel_bytes(wl, s):
     out["ls_interp"] = (n + (n + 1) * 4 + nnzF * (4 + s + 1) + panel
                         + n * wl.caliber * (4 + 8) + n * (8 + 4))
     out["strength"] = (n + 1) * 4 + nnz * (4 + s + 1) + n * 4
+    # fused pass: CSR structure, panel and C/F flags read once; mu, mask,
+    # counts and the LS rows written once
+    out["distance_ls"] = ((n + 1) * 4 + nnz * 4 + panel + n + nnz * s + nnz + n * 4
+                          + n * wl.caliber * (4 + 8) + n * (8 + 4))
     return out
 
 
-def step_bytes(wl, s, kb):
+def step_bytes(wl, s, kb, fused=True):
     sweeps = wl.sweeps
-    b = kb["tv_init"] + kb["algdist"] + kb["ls_interp"]
+    b = kb["tv_init"] + (kb["distance_ls"] if fused else kb["algdist"] + kb["ls_interp"])
     if wl.relax == "gs":
         b += kb["color_partition"] + sweeps * wl.ncolors * kb["gs_phase"]
     else:
@@ -176,7 +190,8 @@ def step_bytes(wl, s, kb):
 
 KERNEL_SYMBOL = {"gs_phase": "gs_phase_perm_kernel", "jacobi": "jacobi_kernel",
                  "algdist": "algdist_kernel", "ls_interp": "ls_interp_kernel",
-                 "tv_init": "start_perm_kernel", "batch_jacobi": "batch_jacobi_kernel",
+                 "tv_init": "start_perm_kernel", "distance_ls": "dist_ls_kernel",
+                 "batch_jacobi": "batch_jacobi_kernel",
                  "batch_algdist": "batch_algdist_kernel"}
 
 
@@ -340,7 +355,7 @@ def main():
         if tag == "f64" and args.no_fp64:
             continue
         b = build_inputs(wl, dtype, torch, ad)
-        step = make_step(wl, b, ad)
+        step = make_step(wl, b, ad, fused=not args.separate)
         if not args.no_autotune:
             # launch shapes picked by the library's autotuner on this matrix
             # (outside the timed region)
@@ -361,7 +376,7 @@ def main():
         s = 4 if dtype == torch.float32 else 8
         kb = kernel_bytes(wl, s)
         res[tag] = {"ms": ms, "wall_ms": wall_ms, "kernels": kern, "kb": kb, "shapes": shapes,
-                    "step_bytes": step_bytes(wl, s, kb), "status": bits, "steps": steps}
+                    "step_bytes": step_bytes(wl, s, kb, fused=not args.separate), "status": bits, "steps": steps}
         del b, step
         torch.cuda.empty_cache()
 

@@ -267,6 +267,22 @@ int ls_interp(ad_handle h, const ad_csr *A, int32_t K, const void *X, const doub
               int32_t *P_col, double *P_val, double *ls_val, int32_t *row_status,
               double *ls_sum, void *stream);
 
+/* The distances with the fused strength row (algebraic_distance with
+ * p = NULL) and the LS rows on them (ls_interp) in one pass over the rows:
+ * each row's entries, distances and panel rows are read once for both.
+ * Arguments as in those two calls (mu is written here and read by nothing
+ * else); strong / nstrong may be NULL (no strength row), fmask may be NULL.
+ * The row-group form with lanes_per_row L (algdist_set_launch("distance_ls",
+ * ...), default 16 bytes of panel per lane, or algdist_autotune) gives, for
+ * every row, bitwise the mu, mask and LS row of algebraic_distance and
+ * ls_interp run with the same L; ls_sum may differ from ls_interp's in the
+ * last bits (another order of the FP64 block partial sums).
+ * Uses handle workspace for the block partial sums when ls_sum is given. */
+int distance_ls(ad_handle h, const ad_csr *A, int32_t K, const void *X, const double *w,
+                int32_t target, void *mu, double theta, const uint8_t *fmask, uint8_t *strong,
+                int32_t *nstrong, const uint8_t *cf, int32_t caliber, int32_t *P_col,
+                double *P_val, double *ls_val, int32_t *row_status, double *ls_sum, void *stream);
+
 /* ------------------------------------------------------------------ */
 /* batched relaxation + distances                                      */
 /* ------------------------------------------------------------------ */

@@ -70,6 +70,8 @@ _SIGS = {
     "algebraic_distance": (_i32, [_P, _CSRP, _i32, _P, _P, _i32, _P, _P, _f64, _P, _P, _P, _P]),
     "strength_graph": (_i32, [_P, _CSRP, _P, _f64, _P, _P, _P, _P]),
     "ls_interp": (_i32, [_P, _CSRP, _i32, _P, _P, _P, _P, _i32, _i32, _P, _P, _P, _P, _P, _P]),
+    "distance_ls": (_i32, [_P, _CSRP, _i32, _P, _P, _i32, _P, _f64, _P, _P, _P, _P, _i32, _P, _P, _P,
+                           _P, _P, _P]),
     "relax_algdist_batched": (_i32, [_P, _i32, _CSRP, _i32, _u64, _i32, _f64, _P, _P, _P, _f64, _P,
                                      _P, _P]),
     "ls_interp_loss_backward": (_i32, [_P, _CSRP, _i32, _P, _i32, _i32, _f64, _P, _P, _P, _P, _i32,
@@ -293,6 +295,41 @@ def ls_interp(A: Csr, X: torch.Tensor, cf: torch.Tensor, mu: torch.Tensor, calib
     _check(rc, h, "ls_interp")
     out = (P_col, P_val, ls_val, row_status)
     return out + (ls_sum,) if want_sum else out
+
+
+def distance_ls(A: Csr, X: torch.Tensor, cf: torch.Tensor, caliber: int,
+                w: Optional[torch.Tensor] = None, target: str = "plain", theta: float = 0.25,
+                fuse: bool = True, fmask: Optional[torch.Tensor] = None,
+                mu: Optional[torch.Tensor] = None, strong: Optional[torch.Tensor] = None,
+                nstrong: Optional[torch.Tensor] = None, P_col: Optional[torch.Tensor] = None,
+                P_val: Optional[torch.Tensor] = None, ls_val: Optional[torch.Tensor] = None,
+                row_status: Optional[torch.Tensor] = None, ls_sum: Optional[torch.Tensor] = None,
+                want_sum: bool = False, stream=None):
+    """Distances (+ strength row when fuse) and LS rows in one pass
+    (distance_ls).  Returns (mu, strong, nstrong, P_col, P_val, ls_val,
+    row_status, ls_sum); strong/nstrong None when not fuse, ls_sum None when
+    not want_sum."""
+    h = handle(A.device.index)
+    n, dev = A.n, A.device
+    mu = mu if mu is not None else torch.empty(A.nnz, dtype=A.dtype, device=dev)
+    if fuse:
+        strong = strong if strong is not None else torch.empty(A.nnz, dtype=torch.uint8, device=dev)
+        nstrong = nstrong if nstrong is not None else torch.empty(n, dtype=torch.int32, device=dev)
+    else:
+        strong = nstrong = None
+    P_col = P_col if P_col is not None else torch.empty((n, caliber), dtype=torch.int32, device=dev)
+    P_val = P_val if P_val is not None else torch.empty((n, caliber), dtype=torch.float64, device=dev)
+    ls_val = ls_val if ls_val is not None else torch.empty(n, dtype=torch.float64, device=dev)
+    row_status = row_status if row_status is not None else torch.empty(n, dtype=torch.int32, device=dev)
+    if want_sum and ls_sum is None:
+        ls_sum = torch.empty(1, dtype=torch.float64, device=dev)
+    tg = {"plain": AD_TARGET_PLAIN, "residual": AD_TARGET_RESIDUAL}[target]
+    rc = _lib.distance_ls(h, A.ref(), X.shape[1], _ptr(X), _ptr(w), tg, _ptr(mu), float(theta),
+                          _ptr(fmask), _ptr(strong), _ptr(nstrong), _ptr(cf), caliber, _ptr(P_col),
+                          _ptr(P_val), _ptr(ls_val), _ptr(row_status),
+                          _ptr(ls_sum) if want_sum else None, _stream(stream))
+    _check(rc, h, "distance_ls")
+    return mu, strong, nstrong, P_col, P_val, ls_val, row_status, (ls_sum if want_sum else None)
 
 
 def relax_algdist_batched(mats, K: int, seed: int = 0, sweeps: int = 4, omega: float = 2.0 / 3.0,

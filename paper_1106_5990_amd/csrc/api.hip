@@ -227,6 +227,7 @@ int algdist_set_launch(ad_handle h, const char* kernel, int32_t dtype, int32_t K
     else if (!strcmp(kernel, "algdist")) kn = KN_ALGDIST;
     else if (!strcmp(kernel, "ls_interp")) kn = KN_LS;
     else if (!strcmp(kernel, "batched")) kn = KN_BATCHED;
+    else if (!strcmp(kernel, "distance_ls")) kn = KN_DLS;
     if (kn < 0) return fail(h, AD_EINVAL, "unknown kernel family '%s'", kernel);
     if (dtype != AD_F32 && dtype != AD_F64) return fail(h, AD_EDTYPE, "dtype %d", dtype);
     const int ks = k_slot(K);
@@ -489,6 +490,46 @@ int ls_interp(ad_handle h, const ad_csr* A, int32_t K, const void* X, const doub
     rc = launch_ls_interp(A->dtype, K, caliber, A, X, w, cf, mu, target, P_col, P_val, ls_val,
                           row_status, bs, ls_sum, h->status, cfg, (hipStream_t)stream);
     return rc ? fail(h, rc, "ls_interp launch") : AD_OK;
+}
+
+int distance_ls(ad_handle h, const ad_csr* A, int32_t K, const void* X, const double* w,
+                int32_t target, void* mu, double theta, const uint8_t* fmask, uint8_t* strong,
+                int32_t* nstrong, const uint8_t* cf, int32_t caliber, int32_t* P_col,
+                double* P_val, double* ls_val, int32_t* row_status, double* ls_sum, void* stream) {
+    if (!h) return AD_EINVAL;
+    h->err.clear();
+    int rc = check_csr(h, A);
+    if (rc) return rc;
+    if (!k_ok(K)) return fail(h, AD_EINVAL, "K = %d: must be 2, 4, 8, 16, 32 or 64", K);
+    if (target != AD_TARGET_PLAIN && target != AD_TARGET_RESIDUAL)
+        return fail(h, AD_EINVAL, "target = %d", target);
+    if (caliber < 1 || caliber > 8) return fail(h, AD_ECALIBER, "caliber = %d outside [1, 8]", caliber);
+    if (caliber > K)
+        return fail(h, AD_ECALIBER, "caliber = %d > K = %d: LS rows would not be unique", caliber, K);
+    if ((rc = check_panel(h, X, "X", A->n))) return rc;
+    if (A->nnz > 0 && !mu) return fail(h, AD_EINVAL, "mu is NULL");
+    if (strong && !(theta > 0.0 && theta < 1.0))
+        return fail(h, AD_EINVAL, "theta = %g outside (0, 1)", theta);
+    if (A->n > 0 && (!cf || !P_col || !P_val || !ls_val || !row_status))
+        return fail(h, AD_EINVAL, "null output or input array");
+    AD_HIP(hipSetDevice(h->device));
+    if (A->n == 0) {
+        if (ls_sum) AD_HIP(hipMemsetAsync(ls_sum, 0, sizeof(double), (hipStream_t)stream));
+        return AD_OK;
+    }
+    const LaunchCfg cfg = cfg_for(h, KN_DLS, A->dtype, K, A);
+    double* bs = nullptr;
+    if (ls_sum) {
+        const int nb = dist_ls_blocks(A->dtype, K, A->n, cfg);
+        if ((rc = ws_reserve(h, sizeof(double) * (size_t)nb)))
+            return fail(h, rc, "workspace for %d block sums", nb);
+        bs = (double*)h->ws;
+    }
+    TimedScope ts(h, "distance_ls", (hipStream_t)stream);
+    rc = launch_dist_ls(A->dtype, K, caliber, A, X, w, target, mu, theta, fmask, strong, nstrong,
+                        cf, P_col, P_val, ls_val, row_status, bs, ls_sum, h->status, cfg,
+                        (hipStream_t)stream);
+    return rc ? fail(h, rc, "distance_ls launch") : AD_OK;
 }
 
 int relax_algdist_batched(ad_handle h, int32_t nmat, const ad_csr* As, int32_t K, uint64_t seed,

@@ -24,7 +24,8 @@ namespace ad {
 
 namespace {
 
-const char* kFamilyName[KN_COUNT] = {"jacobi", "gs_phase", "algdist", "ls_interp", "batched"};
+const char* kFamilyName[KN_COUNT] = {"jacobi",    "gs_phase", "algdist",
+                                     "ls_interp", "batched",  "distance_ls"};
 
 struct Entry {
     std::string kernel;
@@ -108,9 +109,10 @@ int autotune(ad_handle h, const ad_csr* A, int K, int relax, const int32_t* colo
     const int ks = k_slot(K);
     const int bucket = nnz_bucket(A->nnz, A->n);
     std::vector<Entry> entries = read_cache(cache);
-    const int fams[3] = {relax == AD_JACOBI ? KN_JACOBI : KN_GS, KN_ALGDIST, KN_LS};
-    bool need[3] = {true, true, cf != nullptr && caliber >= 1 && caliber <= K && caliber <= 8};
-    for (int q = 0; q < 3; ++q)
+    const int fams[4] = {relax == AD_JACOBI ? KN_JACOBI : KN_GS, KN_ALGDIST, KN_LS, KN_DLS};
+    const bool with_ls = cf != nullptr && caliber >= 1 && caliber <= K && caliber <= 8;
+    bool need[4] = {true, true, with_ls, with_ls};
+    for (int q = 0; q < 4; ++q)
         for (const Entry& e : entries)
             if (need[q] && e.kernel == kFamilyName[fams[q]] && e.dtype == dt && e.K == K &&
                 e.bucket == bucket) {
@@ -122,7 +124,7 @@ int autotune(ad_handle h, const ad_csr* A, int K, int relax, const int32_t* colo
                 h->has_tuned[fams[q]][dt][ks][bucket] = true;
                 need[q] = false;
             }
-    if (!need[0] && !need[1] && !need[2]) return AD_OK;
+    if (!need[0] && !need[1] && !need[2] && !need[3]) return AD_OK;
 
     const size_t vs = dt == AD_F32 ? 4 : 8;
     const int n = A->n;
@@ -168,7 +170,7 @@ int autotune(ad_handle h, const ad_csr* A, int K, int relax, const int32_t* colo
     int32_t* Pc = nullptr;
     double *Pv = nullptr, *ls = nullptr, *bs = nullptr;
     int32_t* st = nullptr;
-    if (need[2]) {
+    if (with_ls) {
         Pc = (int32_t*)sc.get(sizeof(int32_t) * (size_t)n * caliber);
         Pv = (double*)sc.get(sizeof(double) * (size_t)n * caliber);
         ls = (double*)sc.get(sizeof(double) * (size_t)n);
@@ -177,7 +179,7 @@ int autotune(ad_handle h, const ad_csr* A, int K, int relax, const int32_t* colo
     }
 
     const int iters[3] = {1, 2, 4};
-    for (int q = 0; q < 3; ++q) {
+    for (int q = 0; q < 4; ++q) {
         if (!need[q]) continue;
         const int fam = fams[q];
         double best = 1e30;
@@ -189,7 +191,8 @@ int autotune(ad_handle h, const ad_csr* A, int K, int relax, const int32_t* colo
                        : !lpr_valid(dt, K, L))
                 continue;
             for (int it : iters) {
-                if ((fam == KN_LS || L == 0) && it != 1) continue;  // LS rows ignore the row-step count
+                // LS rows and the edge-parallel distances ignore the row-step count
+                if ((fam == KN_LS || L == 0) && it != 1) continue;
                 for (int xcd = 0; xcd <= 1; ++xcd) {
                     LaunchCfg c;
                     c.lpr = L;
@@ -214,6 +217,12 @@ int autotune(ad_handle h, const ad_csr* A, int K, int relax, const int32_t* colo
                         ms = time_ms(s, ea, eb, 3, [&] {
                             return launch_algdist(dt, K, A, X, nullptr, AD_TARGET_PLAIN, mu, nullptr,
                                                   0.25, nullptr, strong, ns, h->status, c, s);
+                        }, ok);
+                    } else if (fam == KN_DLS) {
+                        ms = time_ms(s, ea, eb, 3, [&] {
+                            return launch_dist_ls(dt, K, caliber, A, X, nullptr, AD_TARGET_PLAIN,
+                                                  mu, 0.25, nullptr, strong, ns, cf, Pc, Pv, ls,
+                                                  st, nullptr, nullptr, h->status, c, s);
                         }, ok);
                     } else {
                         // distances once, then LS rows on them

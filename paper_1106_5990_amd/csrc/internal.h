@@ -25,7 +25,15 @@ struct LaunchCfg {
     int iter = 1;     // row-block steps per workgroup (rows per lane group per tile)
     int xcd_map = 1;  // 1: XCD-contiguous tile mapping
 };
-enum KernelId { KN_JACOBI = 0, KN_GS = 1, KN_ALGDIST = 2, KN_LS = 3, KN_BATCHED = 4, KN_COUNT = 5 };
+enum KernelId {
+    KN_JACOBI = 0,
+    KN_GS = 1,
+    KN_ALGDIST = 2,
+    KN_LS = 3,
+    KN_BATCHED = 4,
+    KN_DLS = 5,  // fused distances + LS rows
+    KN_COUNT = 6
+};
 constexpr int kNumKSlots = 7;   // log2(K) for K = 2 .. 64
 constexpr int kNumBuckets = 4;  // stored entries per row: < 8, < 16, < 32, >= 32
 }  // namespace ad
@@ -171,6 +179,12 @@ int launch_ls_interp(int dtype, int K, int caliber, const ad_csr* A, const void*
                      double* block_sums, double* ls_sum, unsigned* status,
                      const LaunchCfg& cfg, hipStream_t s);
 int ls_interp_blocks(int dtype, int K, int n, const LaunchCfg& cfg);
+int launch_dist_ls(int dtype, int K, int caliber, const ad_csr* A, const void* X, const double* w,
+                   int target, void* mu, double theta, const uint8_t* fmask, uint8_t* strong,
+                   int32_t* nstrong, const uint8_t* cf, int32_t* P_col, double* P_val,
+                   double* ls_val, int32_t* row_status, double* block_sums, double* ls_sum,
+                   unsigned* status, const LaunchCfg& cfg, hipStream_t s);
+int dist_ls_blocks(int dtype, int K, int n, const LaunchCfg& cfg);
 
 // ---- autotune.hip
 int autotune(ad_handle h, const ad_csr* A, int K, int relax, const int32_t* color, int ncolors,

@@ -24,8 +24,12 @@
 //     on the register-resident values.
 #include <math.h>
 
+#include <type_traits>
+
 #include "device.h"
 #include "internal.h"
+#include "lsops.h"
+#include "rowops.h"
 
 namespace ad {
 
@@ -42,7 +46,6 @@ __device__ __forceinline__ double ls_row(int i, int l, const int* __restrict__ r
                                          int* __restrict__ rstat, unsigned* status) {
     using S = Shape<T, K, LPR>;
     constexpr int V = S::V, C = S::C;
-    constexpr int NG = CALT * (CALT + 1) / 2;
     const int e0 = rp[i], e1 = rp[i + 1];
     int st = 0;
 
@@ -73,28 +76,8 @@ __device__ __forceinline__ double ls_row(int i, int l, const int* __restrict__ r
         for (int u = 0; u < SE; ++u)
             if (jj[u] == i) d = (double)av[eb + u];
 #pragma unroll
-        for (int u = 0; u < SE; ++u) {
-            const T m = mm[u];
-            if (!cand[u] || m != m) continue;  // NaN distances are never chosen
-            int pos = 0;                       // insert after the equal ones (lower column)
-#pragma unroll
-            for (int q = 0; q < CALT; ++q)
-                if (q < nsel && smu[q] <= m) pos = q + 1;
-            if (pos >= cal) continue;
-#pragma unroll
-            for (int q = CALT - 1; q > 0; --q)
-                if (q > pos && q < cal) {
-                    smu[q] = smu[q - 1];
-                    scol[q] = scol[q - 1];
-                }
-#pragma unroll
-            for (int q = 0; q < CALT; ++q)
-                if (q == pos) {
-                    smu[q] = m;
-                    scol[q] = jj[u];
-                }
-            nsel = (nsel < cal) ? nsel + 1 : cal;
-        }
+        for (int u = 0; u < SE; ++u)
+            if (cand[u]) ls_insert<T, CALT>(smu, scol, nsel, cal, mm[u], jj[u]);
     }
 
     // target in FP64: x_i, or x_i - (A x)_i / a_ii (residual form)
@@ -123,129 +106,7 @@ __device__ __forceinline__ double ls_row(int i, int l, const int* __restrict__ r
             for (int q = 0; q < V; ++q) t[q] = t[q] - y[q] / d;
         }
     }
-
-    // gather the chosen neighbours once; normal equations in FP64
-    Frag<T, V> xs[CALT];
-#pragma unroll
-    for (int a = 0; a < CALT; ++a) {
-        if (a < nsel) {
-            xs[a] = load_lane<T, V, C>(X + (size_t)scol[a] * K + l * V);
-        } else {
-#pragma unroll
-            for (int q = 0; q < V; ++q) xs[a].v[q] = T(0);
-        }
-    }
-    double G[NG], hv[CALT], tt = 0.0;
-#pragma unroll
-    for (int q = 0; q < NG; ++q) G[q] = 0.0;
-#pragma unroll
-    for (int a = 0; a < CALT; ++a) hv[a] = 0.0;
-#pragma unroll
-    for (int q = 0; q < V; ++q) {
-        const double wt = wd[q] * t[q];
-        tt = fma(wt, t[q], tt);
-        int gi = 0;
-#pragma unroll
-        for (int a = 0; a < CALT; ++a) {
-            const double wx = wd[q] * (double)xs[a].v[q];
-            hv[a] = fma(wx, t[q], hv[a]);
-#pragma unroll
-            for (int b = 0; b <= a; ++b, ++gi) G[gi] = fma(wx, (double)xs[b].v[q], G[gi]);
-        }
-    }
-    if (nsel == 0) {
-        tt = group_sum<LPR>(tt);
-    } else {
-#pragma unroll
-        for (int q = 0; q < NG; ++q) G[q] = group_sum<LPR>(G[q]);
-#pragma unroll
-        for (int a = 0; a < CALT; ++a) hv[a] = group_sum<LPR>(hv[a]);
-    }
-
-    double val;
-    double coef[CALT];
-    bool keep[CALT];
-#pragma unroll
-    for (int q = 0; q < CALT; ++q) {
-        coef[q] = 0.0;
-        keep[q] = false;
-    }
-    if (nsel == 0) {
-        val = tt;
-        st = st ? st : 1;
-    } else {
-        // Cholesky (in place, packed lower) in increasing-mu order, drop rule
-#pragma unroll
-        for (int a = 0; a < CALT; ++a) {
-            if (a >= nsel) continue;
-            const int ra = a * (a + 1) / 2;
-            const double gaa = G[ra + a];
-#pragma unroll
-            for (int b = 0; b < a; ++b) {
-                const int rb = b * (b + 1) / 2;
-                double s = G[ra + b];
-#pragma unroll
-                for (int c = 0; c < b; ++c)
-                    if (keep[c]) s -= G[ra + c] * G[rb + c];
-                G[ra + b] = keep[b] ? s / G[rb + b] : 0.0;
-            }
-            double piv = gaa;
-#pragma unroll
-            for (int b = 0; b < a; ++b)
-                if (keep[b]) piv -= G[ra + b] * G[ra + b];
-            keep[a] = piv > 1e-12 * gaa;
-            G[ra + a] = keep[a] ? sqrt(piv) : 1.0;
-            if (!keep[a]) st = st ? st : 2;
-        }
-        double z[CALT];
-#pragma unroll
-        for (int a = 0; a < CALT; ++a) {
-            const int ra = a * (a + 1) / 2;
-            double s = hv[a];
-#pragma unroll
-            for (int b = 0; b < a; ++b)
-                if (keep[b]) s -= G[ra + b] * z[b];
-            z[a] = keep[a] ? s / G[ra + a] : 0.0;
-        }
-#pragma unroll
-        for (int a = CALT - 1; a >= 0; --a) {
-            double s = z[a];
-#pragma unroll
-            for (int b = a + 1; b < CALT; ++b)
-                if (keep[b]) s -= G[b * (b + 1) / 2 + a] * coef[b];
-            coef[a] = keep[a] ? s / G[a * (a + 1) / 2 + a] : 0.0;
-        }
-        // the functional at the minimiser, by its definition
-        double f = 0.0;
-#pragma unroll
-        for (int q = 0; q < V; ++q) {
-            double r = t[q];
-#pragma unroll
-            for (int a = 0; a < CALT; ++a)
-                if (keep[a]) r -= coef[a] * (double)xs[a].v[q];
-            f = fma(wd[q] * r, r, f);
-        }
-        val = group_sum<LPR>(f);
-    }
-    if (l == 0) {
-        int* pc = Pcol + (size_t)i * cal;
-        double* pv = Pval + (size_t)i * cal;
-        int o = 0;
-#pragma unroll
-        for (int a = 0; a < CALT; ++a)
-            if (keep[a]) {
-                pc[o] = scol[a];
-                pv[o] = coef[a];
-                ++o;
-            }
-        for (; o < cal; ++o) {
-            pc[o] = -1;
-            pv[o] = 0.0;
-        }
-        lsv[i] = val;
-        rstat[i] = st;
-    }
-    return val;
+    return ls_solve<T, K, LPR, CALT>(i, l, t, wd, X, scol, nsel, st, cal, Pcol, Pval, lsv, rstat);
 }
 
 template <typename T, int K, int LPR, int CALT>
@@ -277,18 +138,7 @@ __global__ __launch_bounds__(kBlock) void ls_interp_kernel(
             const int64_t row = w0 + r * kWave + lane;
             const bool valid = row < n;
             const bool isF = valid && cf[row] == 0;
-            if (valid && !isF) {  // a C point interpolates itself
-                int* pc = Pcol + (size_t)row * cal;
-                double* pv = Pval + (size_t)row * cal;
-                pc[0] = (int)row;
-                pv[0] = 1.0;
-                for (int q = 1; q < cal; ++q) {
-                    pc[q] = -1;
-                    pv[q] = 0.0;
-                }
-                lsv[row] = 0.0;
-                rstat[row] = 0;
-            }
+            if (valid && !isF) ls_c_row(row, cal, Pcol, Pval, lsv, rstat);
             const uint64_t m = __ballot(isF);
             if (isF) flist[wv][cnt + __popcll(m & lt)] = (int)row;
             cnt += __popcll(m);
@@ -387,6 +237,164 @@ static int ls_dispatch(int K, int caliber, const ad_csr* A, const void* X, const
                             st, cfg, s);
         });
     });
+}
+
+// ---------------------------------------------------------------- fused distances + LS rows
+// One pass per row group: the distances of the row (with the fused strength
+// row), the C-neighbour candidates picked from them as they are computed,
+// then the LS row on the FP64 target the distance pass formed.  The row's
+// CSR entries, distances and panel rows are read once for both results.
+template <typename T, int K, int LPR, int CALT, bool WEIGHTED>
+__global__ __launch_bounds__(kBlock) void dist_ls_kernel(
+    int n, const int* __restrict__ rp, const int* __restrict__ ci, const T* __restrict__ av,
+    const T* __restrict__ X, const double* __restrict__ w, int target, T* __restrict__ mu,
+    double theta, const uint8_t* __restrict__ fmask, uint8_t* __restrict__ strong,
+    int* __restrict__ nstrong, const uint8_t* __restrict__ cf, int cal, int* __restrict__ Pcol,
+    double* __restrict__ Pval, double* __restrict__ lsv, int* __restrict__ rstat,
+    double* __restrict__ block_sums, int iter, int xcd, unsigned* status) {
+    using S = Shape<T, K, LPR>;
+    constexpr int V = S::V;
+    __shared__ double wsum[kWavesPerBlock];
+    const int lane = threadIdx.x & (kWave - 1);
+    const int g = lane / LPR, l = lane % LPR;
+    const int wv = threadIdx.x / kWave;
+    const int64_t rows_per_tile = (int64_t)S::RPB * iter;
+    const int64_t ntiles = (n + rows_per_tile - 1) / rows_per_tile;
+    const int64_t tile = xcd ? xcd_tile(ntiles) : (int64_t)blockIdx.x;
+    double wd[V];
+    T wt[V];
+#pragma unroll
+    for (int q = 0; q < V; ++q) {
+        wd[q] = WEIGHTED ? w[l * V + q] : 1.0;
+        wt[q] = (T)wd[q];
+    }
+    const bool plain = target == AD_TARGET_PLAIN;
+    double fsum = 0.0;
+    if (tile >= 0 && tile < ntiles) {
+        for (int it = 0; it < iter; ++it) {
+            const int64_t i64 = tile * rows_per_tile + (int64_t)it * S::RPB + wv * S::RPW + g;
+            if (i64 >= n) break;
+            const int i = (int)i64;
+            const bool isF = cf[i] == 0;
+            T smu[CALT];
+            int scol[CALT];
+            int nsel = 0;
+#pragma unroll
+            for (int q = 0; q < CALT; ++q) {
+                smu[q] = T(0);
+                scol[q] = -1;
+            }
+            double t64[V], d;
+            algdist_row_sel<S, T, K, WEIGHTED>(
+                i, l, rp, ci, av, X, wd, wt, plain, mu, nullptr, theta, fmask, strong, nstrong,
+                status,
+                [&](int j, T m) {
+                    if (isF && cf[j] != 0) ls_insert<T, CALT>(smu, scol, nsel, cal, m, j);
+                },
+                t64, d);
+            if (isF) {
+                const int st = (!plain && d == 0.0) ? 3 : 0;
+                const double v = ls_solve<T, K, LPR, CALT>(i, l, t64, wd, X, scol, nsel, st, cal,
+                                                           Pcol, Pval, lsv, rstat);
+                if (l == 0) fsum += v;
+            } else if (l == 0) {
+                ls_c_row(i, cal, Pcol, Pval, lsv, rstat);
+            }
+        }
+    }
+    if (block_sums) {
+        // fixed-order reduction: xor butterfly in the wave, then waves in order
+#pragma unroll
+        for (int o = kWave / 2; o > 0; o >>= 1) fsum += __shfl_xor(fsum, o, kWave);
+        if (lane == 0) wsum[wv] = fsum;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double s = 0.0;
+            for (int q = 0; q < kWavesPerBlock; ++q) s += wsum[q];
+            block_sums[blockIdx.x] = s;
+        }
+    }
+}
+
+template <typename T, int K, int LPR>
+static int dist_ls_grid(int n, const LaunchCfg& cfg) {
+    using S = Shape<T, K, LPR>;
+    const int64_t rpt = (int64_t)S::RPB * cfg.iter;
+    const int64_t ntiles = (n + rpt - 1) / rpt;
+    return cfg.xcd_map ? grid_for_tiles(ntiles) : (int)(ntiles > 0 ? ntiles : 1);
+}
+
+int dist_ls_blocks(int dtype, int K, int n, const LaunchCfg& cfg) {
+    int grid = 1;
+    auto f = [&](auto tag) {
+        using T = decltype(tag);
+        with_k<T>(K, [&](auto kc) {
+            constexpr int KK = decltype(kc)::value;
+            return with_lpr<T, KK>(cfg.lpr > 0 ? cfg.lpr : ls_lpr_default<T>(KK), [&](auto lc) {
+                constexpr int L = decltype(lc)::value;
+                grid = dist_ls_grid<T, KK, L>(n, cfg);
+            });
+        });
+    };
+    if (dtype == AD_F32) f(float());
+    else f(double());
+    return grid;
+}
+
+template <typename T>
+static int dist_ls_dispatch(int K, int caliber, const ad_csr* A, const void* X, const double* w,
+                            int target, void* mu, double theta, const uint8_t* fmask,
+                            uint8_t* strong, int32_t* nstrong, const uint8_t* cf, int32_t* P_col,
+                            double* P_val, double* ls_val, int32_t* row_status, double* bs,
+                            unsigned* st, const LaunchCfg& cfg, hipStream_t s) {
+    return with_k<T>(K, [&](auto kc) {
+        constexpr int KK = decltype(kc)::value;
+        const int lpr = cfg.lpr > 0 ? cfg.lpr : ls_lpr_default<T>(KK);
+        return with_lpr<T, KK>(lpr, [&](auto lc) {
+            constexpr int L = decltype(lc)::value;
+            const int grid = dist_ls_grid<T, KK, L>(A->n, cfg);
+            auto go = [&](auto calt, auto weighted) {
+                dist_ls_kernel<T, KK, L, decltype(calt)::value, decltype(weighted)::value>
+                    <<<dim3(grid), dim3(kBlock), 0, s>>>(
+                        A->n, A->row_ptr, A->col, (const T*)A->val, (const T*)X, w, target,
+                        (T*)mu, theta, fmask, strong, nstrong, cf, caliber, P_col, P_val, ls_val,
+                        row_status, bs, cfg.iter, cfg.xcd_map, st);
+            };
+            using C4 = std::integral_constant<int, 4>;
+            using C8 = std::integral_constant<int, 8>;
+            using Y = std::true_type;
+            using N = std::false_type;
+            if (caliber <= 4) w ? go(C4(), Y()) : go(C4(), N());
+            else w ? go(C8(), Y()) : go(C8(), N());
+        });
+    });
+}
+
+int launch_dist_ls(int dtype, int K, int caliber, const ad_csr* A, const void* X, const double* w,
+                   int target, void* mu, double theta, const uint8_t* fmask, uint8_t* strong,
+                   int32_t* nstrong, const uint8_t* cf, int32_t* P_col, double* P_val,
+                   double* ls_val, int32_t* row_status, double* block_sums, double* ls_sum,
+                   unsigned* status, const LaunchCfg& cfg, hipStream_t s) {
+    if (A->n == 0) {
+        if (ls_sum) AD_HIP(hipMemsetAsync(ls_sum, 0, sizeof(double), s));
+        return AD_OK;
+    }
+    double* bs = ls_sum ? block_sums : nullptr;
+    const int rc = (dtype == AD_F32)
+                       ? dist_ls_dispatch<float>(K, caliber, A, X, w, target, mu, theta, fmask,
+                                                 strong, nstrong, cf, P_col, P_val, ls_val,
+                                                 row_status, bs, status, cfg, s)
+                       : dist_ls_dispatch<double>(K, caliber, A, X, w, target, mu, theta, fmask,
+                                                  strong, nstrong, cf, P_col, P_val, ls_val,
+                                                  row_status, bs, status, cfg, s);
+    if (rc) return rc;
+    AD_HIP(hipGetLastError());
+    if (ls_sum) {
+        const int nb = dist_ls_blocks(dtype, K, A->n, cfg);
+        sum_blocks_kernel<<<dim3(1), dim3(1024), 0, s>>>(block_sums, nb, ls_sum);
+        AD_HIP(hipGetLastError());
+    }
+    return AD_OK;
 }
 
 int launch_ls_interp(int dtype, int K, int caliber, const ad_csr* A, const void* X,

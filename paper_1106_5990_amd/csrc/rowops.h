@@ -93,15 +93,21 @@ __device__ __forceinline__ T ratio(T a, T b) {
     else return a / b;
 }
 
-template <typename S, typename T, int K, bool WEIGHTED>
-__device__ __forceinline__ void algdist_row(int i, int l, const int* __restrict__ rp,
-                                            const int* __restrict__ ci, const T* __restrict__ av,
-                                            const T* __restrict__ X, const double (&wd)[S::V],
-                                            const T (&wt)[S::V], bool plain, T* __restrict__ mu,
-                                            double* __restrict__ pout, double theta,
-                                            const uint8_t* __restrict__ fmask,
-                                            uint8_t* __restrict__ strong, int* __restrict__ nstrong,
-                                            unsigned* status) {
+// sel(j, mu_ij) is called for every off-diagonal entry in CSR order with
+// the group-uniform distance (the fused LS kernel picks its C-neighbours
+// there); tout receives the FP64 target and dout the diagonal value (0 when
+// absent; only looked for with the residual target).
+template <typename S, typename T, int K, bool WEIGHTED, typename Sel>
+__device__ __forceinline__ void algdist_row_sel(int i, int l, const int* __restrict__ rp,
+                                                const int* __restrict__ ci,
+                                                const T* __restrict__ av, const T* __restrict__ X,
+                                                const double (&wd)[S::V], const T (&wt)[S::V],
+                                                bool plain, T* __restrict__ mu,
+                                                double* __restrict__ pout, double theta,
+                                                const uint8_t* __restrict__ fmask,
+                                                uint8_t* __restrict__ strong,
+                                                int* __restrict__ nstrong, unsigned* status,
+                                                Sel&& sel, double (&tout)[S::V], double& dout) {
     constexpr int V = S::V, C = S::C, LPR = S::LPR;
     const bool fuse = strong != nullptr;
     const int e0 = rp[i], e1 = rp[i + 1];
@@ -135,6 +141,9 @@ __device__ __forceinline__ void algdist_row(int i, int l, const int* __restrict_
         } else if (l == 0) {
             flag(status, AD_STAT_ZERO_DIAG);
         }
+        dout = d;
+    } else {
+        dout = 0.0;
     }
     T wtt[V];
     T saa = T(0);
@@ -216,9 +225,12 @@ __device__ __forceinline__ void algdist_row(int i, int l, const int* __restrict_
                 if (pout) pout[e] = pd;
             }
             if (j != i && (!fmask || fmask[j])) mmin = (m < mmin) ? m : mmin;
+            if (j != i) sel(j, m);
         }
     }
     if (bad && l == 0) flag(status, AD_STAT_NONFINITE);
+#pragma unroll
+    for (int q = 0; q < V; ++q) tout[q] = t64[q];
 
     if (fuse) {
         // second pass: each lane re-reads the mu values it stored
@@ -237,6 +249,20 @@ __device__ __forceinline__ void algdist_row(int i, int l, const int* __restrict_
         cnt = group_sum<LPR>(cnt);
         if (l == 0 && nstrong) nstrong[i] = cnt;
     }
+}
+
+template <typename S, typename T, int K, bool WEIGHTED>
+__device__ __forceinline__ void algdist_row(int i, int l, const int* __restrict__ rp,
+                                            const int* __restrict__ ci, const T* __restrict__ av,
+                                            const T* __restrict__ X, const double (&wd)[S::V],
+                                            const T (&wt)[S::V], bool plain, T* __restrict__ mu,
+                                            double* __restrict__ pout, double theta,
+                                            const uint8_t* __restrict__ fmask,
+                                            uint8_t* __restrict__ strong, int* __restrict__ nstrong,
+                                            unsigned* status) {
+    double t64[S::V], d;
+    algdist_row_sel<S, T, K, WEIGHTED>(i, l, rp, ci, av, X, wd, wt, plain, mu, pout, theta, fmask,
+                                       strong, nstrong, status, [](int, T) {}, t64, d);
 }
 
 // ---------------------------------------------------------------- edge-parallel distances

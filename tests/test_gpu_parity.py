@@ -458,6 +458,114 @@ def test_ls_interp_duplicate_columns_and_zero_diagonal(dt):
             assert st[26] == 3 and ad.status(clear=True) & ad.STAT_ZERO_DIAG
 
 
+@pytest.mark.parametrize("dt", ["f64", "f32"])
+@pytest.mark.parametrize("target", ["plain", "residual"])
+@pytest.mark.parametrize("K,cal,weighted", [(16, 4, False), (8, 8, True), (32, 3, True)])
+def test_fused_distance_ls_equals_separate_calls(dt, target, K, cal, weighted):
+    """distance_ls against algebraic_distance + ls_interp with the same lanes
+    per row: mu, mask, counts and every LS row bitwise; ls_sum to 1e-12; and
+    against the oracle."""
+    say("distance_ls %s %s K=%d cal=%d w=%s" % (dt, target, K, cal, weighted))
+    ad = lib()
+    dtype = DT[dt]
+    N = 45
+    A = aniso(N)
+    Ao = as_oracle(A, dtype)
+    Ad = dev_csr(A, dtype)
+    color = torch.as_tensor(W.red_black((N, N)), device="cuda")
+    X = ad.setup_testvectors(Ad, K, seed=23, relax="gs", sweeps=3, color=color, ncolors=2)
+    x = to_np(X).astype(np.float64)
+    w = (0.5 + np.random.default_rng(K).random(K)) if weighted else None
+    wt = None if w is None else torch.as_tensor(w, device="cuda")
+    cf = (np.random.default_rng(5).random(A.n) < 0.4).astype(np.uint8)
+    cft = torch.as_tensor(cf, device="cuda")
+    fm = (np.random.default_rng(6).random(A.n) < 0.8).astype(np.uint8)
+    fmt = torch.as_tensor(fm, device="cuda")
+    tg = oracle.TARGET_PLAIN if target == "plain" else oracle.TARGET_RESIDUAL
+    T = x if target == "plain" else residual_target(Ao, x)
+    wv = np.ones(K) if w is None else w
+    try:
+        for lpr in [0] + valid_lprs(dtype, K):
+            for kern in ("distance_ls", "ls_interp"):
+                ad.set_launch(kern, dtype, K, lpr, 1, True)
+            # the separate distance call in the row-group form of the same shape
+            ad.set_launch("algdist", dtype, K, lpr if lpr else ls_default_lpr(dtype, K), 1, True)
+            for fmask in (None, fmt):
+                got = ad.distance_ls(Ad, X, cft, cal, w=wt, target=target, theta=0.25,
+                                     fmask=fmask, want_sum=True)
+                mu, s, ns = ad.algebraic_distance(Ad, X, w=wt, target=target, fuse=True, theta=0.25,
+                                                  fmask=fmask)
+                Pc, Pv, ls, st, tot = ad.ls_interp(Ad, X, cft, mu, cal, w=wt, target=target,
+                                                   want_sum=True)
+                assert torch.equal(got[0], mu) and torch.equal(got[1], s) and torch.equal(got[2], ns), lpr
+                for a, b in zip(got[3:7], (Pc, Pv, ls, st)):
+                    assert torch.equal(a, b), lpr
+                assert abs(float(got[7]) - float(tot)) <= 1e-12 * abs(float(tot)), lpr
+            mh = to_np(got[0]).astype(np.float64)
+            ref = oracle.ls_interp(Ao, x, w, cf, mh, cal, tg)
+            check_ls(tuple(to_np(t) for t in got[3:7]), ref, dtype, (T * T * wv).sum(1))
+            check_mu(mh, oracle.algdist(Ao, x, w, tg), saa_per_edge(Ao, T, w), dtype)
+    finally:
+        for kern in ("distance_ls", "ls_interp", "algdist"):
+            ad.set_launch(kern, dtype, K, 0, 1, True)
+    assert ad.status(clear=True) == 0
+
+
+def ls_default_lpr(dt, K):
+    """The LS rows' default lanes per row: 16 bytes of panel per lane."""
+    size = 4 if dt == torch.float32 else 8
+    for L in valid_lprs(dt, K):
+        if (K // L) * size <= 16:
+            return L
+    return valid_lprs(dt, K)[-1]
+
+
+@pytest.mark.parametrize("dt", ["f64", "f32"])
+def test_fused_distance_ls_degenerate_rows(dt):
+    """Duplicate and zero C-neighbour columns (status 2), a zero diagonal on
+    the residual target (status 3), rows without C-neighbours (status 1),
+    diagonal-only rows, through the fused call."""
+    say("distance_ls degenerate %s" % dt)
+    ad = lib()
+    dtype = DT[dt]
+    N, K, cal = 24, 8, 4
+    A = W.laplacian_2d_5pt(N)
+    val = A.val.copy()
+    cf = W.cf_red_is_coarse((N, N))
+    X = oracle.tv_init(A.n, K, 19)
+    X[2] = X[0]
+    X[25] = 0.0
+    r = 26
+    val[A.row_ptr[r]:A.row_ptr[r + 1]][A.col[A.row_ptr[r]:A.row_ptr[r + 1]] == r] = 0.0
+    A = W.CSR(A.n, A.row_ptr, A.col, val)
+    Ao = as_oracle(A, dtype)
+    Ad = dev_csr(A, dtype)
+    Xt = torch.as_tensor(X, dtype=dtype, device="cuda")
+    cft = torch.as_tensor(cf, device="cuda")
+    x = to_np(Xt).astype(np.float64)
+    for target, tg in (("plain", 0), ("residual", 1)):
+        ad.status(clear=True)
+        got = ad.distance_ls(Ad, Xt, cft, cal, target=target)
+        mh = to_np(got[0]).astype(np.float64)
+        ref = oracle.ls_interp(Ao, x, None, cf, mh, cal, tg)
+        T = x if tg == 0 else residual_target(Ao, x)
+        check_ls(tuple(to_np(t) for t in got[3:7]), ref, dtype, (T * T).sum(1))
+        st = to_np(got[6])
+        assert st[1] == 2
+        if tg == 1:
+            assert st[26] == 3 and ad.status(clear=True) & ad.STAT_ZERO_DIAG
+    # all rows F: every row has status 1 and ls_val = sum w t^2
+    cf0 = torch.zeros(A.n, dtype=torch.uint8, device="cuda")
+    got = ad.distance_ls(Ad, Xt, cf0, cal, want_sum=True)
+    assert np.all(to_np(got[6]) == 1)
+    assert np.allclose(to_np(got[5]), (x * x).sum(1), rtol=1e-12)
+    # empty matrix
+    E = W.CSR(0, np.zeros(1, np.int32), np.zeros(0, np.int32), np.zeros(0))
+    got = ad.distance_ls(dev_csr(E, dtype), torch.empty((0, K), dtype=dtype, device="cuda"),
+                         torch.empty(0, dtype=torch.uint8, device="cuda"), cal, want_sum=True)
+    assert float(got[7]) == 0.0
+
+
 def test_diagonal_only_rows():
     say("diagonal-only rows")
     ad = lib()
@@ -608,7 +716,7 @@ def test_autotune_installs_and_caches(tmp_path):
         ad.autotune(Ad, K, relax="gs", color=color, ncolors=2, cf=cf, caliber=4, cache_json=cache)
         lines = open(cache).read().splitlines()
         kinds = sorted(l.split('"')[3] for l in lines)
-        assert kinds == ["algdist", "gs_phase", "ls_interp"], lines
+        assert kinds == ["algdist", "distance_ls", "gs_phase", "ls_interp"], lines
         ad.autotune(Ad, K, relax="gs", color=color, ncolors=2, cf=cf, caliber=4, cache_json=cache)
         assert open(cache).read().splitlines() == lines  # served from the cache
         X = ad.setup_testvectors(Ad, K, seed=2, relax="gs", sweeps=3, color=color, ncolors=2)
