@@ -160,13 +160,20 @@ __device__ __forceinline__ void algdist_row_sel(int i, int l, const int* __restr
     bool bad = false;
     // U edges per step: their column and panel loads are issued together
     constexpr int U = (V >= 16) ? 2 : 4;
+    // the next step's column indices are loaded while this step's panel
+    // rows are in flight
+    int jn[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) jn[u] = (e0 + u < e1) ? ci[e0 + u] : i;
     for (int eb = e0; eb < e1; eb += U) {
         int jj[U];
         Frag<T, V> xs[U];
 #pragma unroll
-        for (int u = 0; u < U; ++u) jj[u] = (eb + u < e1) ? ci[eb + u] : i;
+        for (int u = 0; u < U; ++u) jj[u] = jn[u];
 #pragma unroll
         for (int u = 0; u < U; ++u) xs[u] = load_lane<T, V, C>(X + (size_t)jj[u] * K + l * V);
+#pragma unroll
+        for (int u = 0; u < U; ++u) jn[u] = (eb + U + u < e1) ? ci[eb + U + u] : i;
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int e = eb + u;
@@ -233,18 +240,35 @@ __device__ __forceinline__ void algdist_row_sel(int i, int l, const int* __restr
     for (int q = 0; q < V; ++q) tout[q] = t64[q];
 
     if (fuse) {
-        // second pass: each lane re-reads the mu values it stored
+        // second pass: each lane re-reads the mu values it stored, SB
+        // entries' loads in flight together
         int cnt = 0;
         const double md = (double)mmin;
-        for (int e = e0 + l; e < e1; e += LPR) {
-            const int j = ci[e];
-            int s = 0;
-            if (in_f && j != i && (!fmask || fmask[j])) {
-                const double me = (double)mu[e];
-                s = (md > 0.0) ? (theta * me < md) : (me == 0.0);
+        constexpr int SB = 8;
+        for (int eb = e0 + l; eb < e1; eb += SB * LPR) {
+            int jj[SB];
+            T mm[SB];
+            bool fj[SB];
+#pragma unroll
+            for (int u = 0; u < SB; ++u) {
+                const int e = eb + u * LPR;
+                jj[u] = (e < e1) ? ci[e] : i;
+                mm[u] = (e < e1) ? mu[e] : T(0);
             }
-            strong[e] = (uint8_t)s;
-            cnt += s;
+#pragma unroll
+            for (int u = 0; u < SB; ++u) fj[u] = !fmask || fmask[jj[u]];
+#pragma unroll
+            for (int u = 0; u < SB; ++u) {
+                const int e = eb + u * LPR;
+                if (e >= e1) break;
+                int s = 0;
+                if (in_f && jj[u] != i && fj[u]) {
+                    const double me = (double)mm[u];
+                    s = (md > 0.0) ? (theta * me < md) : (me == 0.0);
+                }
+                strong[e] = (uint8_t)s;
+                cnt += s;
+            }
         }
         cnt = group_sum<LPR>(cnt);
         if (l == 0 && nstrong) nstrong[i] = cnt;
