@@ -115,15 +115,22 @@ int algdist_timing(ad_handle h, int enable);
 const char *algdist_timing_report(ad_handle h);
 
 /* Launch shape of one kernel family, for a (dtype, K, stored-entries-per-row
- * bucket) key.  kernel: "jacobi", "gs_phase", "algdist", "ls_interp" or "batched".
+ * bucket) key.  kernel: "jacobi", "gs_phase", "algdist", "ls_interp",
+ * "distance_ls", "batched" (the batch's relaxation stage) or
+ * "batched_distance" (the batch's distance stage).  For "algdist" and
+ * "batched_distance", lanes_per_row 0 with the plain target and panel rows of
+ * at most 128 bytes selects the edge-parallel form (one lane per stored
+ * entry).
  * bucket: 0 (< 8 entries per row), 1 (< 16), 2 (< 32), 3 (>= 32), or -1 for
  * all four.  lanes_per_row: lanes sharing one panel row (0 = default; must
  * divide K with K / lanes_per_row entries per lane fitting 64 bytes and
  * being at least 8 bytes).  rows_per_lane: consecutive row steps per
  * workgroup tile (>= 1; ignored by ls_interp, which compacts the F rows of
  * fixed 128-row windows).
- * xcd_map: 1 maps contiguous row tiles to each XCD, 0 uses the plain block
- * order.  The kernels' results do not depend on the shape except for the
+ * xcd_map (0 .. 4096): how row tiles map to the 8 XCDs (workgroups are
+ * dispatched round-robin over them): 0 = plain block order (consecutive tiles
+ * on different XCDs), 1 = one contiguous range of tiles per XCD, c >= 2 =
+ * chunks of 8c consecutive tiles with c contiguous tiles per XCD in each.  The kernels' results do not depend on the shape except for the
  * order of the K-reductions inside algdist (all orders stay within the
  * parity bars).  Returns AD_EINVAL for a shape the kernel does not support. */
 int algdist_set_launch(ad_handle h, const char *kernel, int32_t dtype, int32_t K, int32_t bucket,
@@ -144,9 +151,12 @@ int algdist_autotune(ad_handle h, const ad_csr *A, int32_t K, int32_t relax, con
 
 /* Time every valid launch shape (lanes per row, row steps per tile, XCD
  * tile mapping) of relax_algdist_batched on this batch (As: host array of
- * nmat device CSRs of one dtype; `sweeps` Jacobi sweeps) and install the
- * fastest for the batch's dtype, K and stored-entries-per-row bucket.
- * cache_json as for algdist_autotune (kernel name "batched").  Allocates
+ * nmat device CSRs of one dtype; `sweeps` Jacobi sweeps): first the
+ * relaxation stage's shapes, then the distance stage's (including the
+ * edge-parallel form), each from its own launches' HIP-event times, and
+ * install the fastest of each for the batch's dtype, K and
+ * stored-entries-per-row bucket.  cache_json as for algdist_autotune (kernel
+ * names "batched" and "batched_distance").  Allocates
  * scratch outputs of the batch's size for the duration of the call and
  * synchronises the stream. */
 int algdist_autotune_batched(ad_handle h, int32_t nmat, const ad_csr *As, int32_t K,
@@ -307,8 +317,8 @@ int distance_ls(ad_handle h, const ad_csr *A, int32_t K, const void *X, const do
  * capturing `stream`, the launches are issued directly instead.  The batch
  * state (a second panel of (sum n) x K, the tables, the graph) is owned by
  * the handle and freed by algdist_destroy.  Calls that overlap on one
- * handle race.  Launch shape: algdist_set_launch("batched", ...) with
- * lanes_per_row, rows_per_lane (row steps per tile) and xcd_map, or
+ * handle race.  Launch shapes: algdist_set_launch("batched", ...) for the
+ * relaxation stage and ("batched_distance", ...) for the distance stage, or
  * algdist_autotune_batched. */
 int relax_algdist_batched(ad_handle h, int32_t nmat, const ad_csr *As, int32_t K, uint64_t seed,
                           int32_t sweeps, double omega, const double *w, void *X, void *mu,

@@ -183,9 +183,11 @@ def timing_report(device: Optional[int] = None) -> dict:
 
 
 def set_launch(kernel: str, dtype: torch.dtype, K: int, lanes_per_row: int = 0,
-               rows_per_lane: int = 1, xcd_map: bool = True, bucket: int = -1,
+               rows_per_lane: int = 1, xcd_map: int = 1, bucket: int = -1,
                device: Optional[int] = None) -> None:
-    """Force the launch shape of one kernel family (see algdist_set_launch)."""
+    """Force the launch shape of one kernel family (see algdist_set_launch);
+    xcd_map: 0 plain block order, 1 contiguous tiles per XCD, c >= 2 chunks of
+    8c tiles with c per XCD."""
     h = handle(device)
     rc = _lib.algdist_set_launch(h, kernel.encode(), _dtype_code(dtype), K, bucket, lanes_per_row,
                                  rows_per_lane, int(xcd_map))

@@ -228,6 +228,7 @@ int algdist_set_launch(ad_handle h, const char* kernel, int32_t dtype, int32_t K
     else if (!strcmp(kernel, "ls_interp")) kn = KN_LS;
     else if (!strcmp(kernel, "batched")) kn = KN_BATCHED;
     else if (!strcmp(kernel, "distance_ls")) kn = KN_DLS;
+    else if (!strcmp(kernel, "batched_distance")) kn = KN_BDIST;
     if (kn < 0) return fail(h, AD_EINVAL, "unknown kernel family '%s'", kernel);
     if (dtype != AD_F32 && dtype != AD_F64) return fail(h, AD_EDTYPE, "dtype %d", dtype);
     const int ks = k_slot(K);
@@ -239,7 +240,8 @@ int algdist_set_launch(ad_handle h, const char* kernel, int32_t dtype, int32_t K
     LaunchCfg c;
     c.lpr = lanes_per_row;
     c.iter = kn == KN_LS ? 1 : rows_per_lane;
-    c.xcd_map = xcd_map ? 1 : 0;
+    if (xcd_map < 0 || xcd_map > 4096) return fail(h, AD_EINVAL, "xcd_map %d", xcd_map);
+    c.xcd_map = xcd_map;
     for (int b = 0; b < kNumBuckets; ++b)
         if (bucket < 0 || bucket == b) {
             h->tuned[kn][dtype][ks][b] = c;
@@ -559,9 +561,11 @@ int relax_algdist_batched(ad_handle h, int32_t nmat, const ad_csr* As, int32_t K
     const int ks = k_slot(K), b = batch_bucket(nmat, As);
     const LaunchCfg cfg = h->has_tuned[KN_BATCHED][dt][ks][b] ? h->tuned[KN_BATCHED][dt][ks][b]
                                                                : LaunchCfg();
+    const LaunchCfg dcfg = h->has_tuned[KN_BDIST][dt][ks][b] ? h->tuned[KN_BDIST][dt][ks][b]
+                                                             : LaunchCfg();
     TimedScope ts(h, "batched", (hipStream_t)stream);
     rc = launch_batched(h, nmat, As, K, seed, sweeps, omega, w, X, mu, theta, strong, nstrong, cfg,
-                        h->timing, (hipStream_t)stream);
+                        dcfg, h->timing, (hipStream_t)stream);
     return rc ? fail(h, rc, "relax_algdist_batched launch") : AD_OK;
 }
 

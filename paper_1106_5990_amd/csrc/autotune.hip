@@ -24,8 +24,8 @@ namespace ad {
 
 namespace {
 
-const char* kFamilyName[KN_COUNT] = {"jacobi",    "gs_phase", "algdist",
-                                     "ls_interp", "batched",  "distance_ls"};
+const char* kFamilyName[KN_COUNT] = {"jacobi",  "gs_phase",    "algdist",         "ls_interp",
+                                     "batched", "distance_ls", "batched_distance"};
 
 struct Entry {
     std::string kernel;
@@ -67,6 +67,9 @@ void write_cache(const char* path, const std::vector<Entry>& v) {
     fclose(f);
     rename(tmp.c_str(), path);
 }
+
+// tile-to-XCD mappings tried (see map_tile)
+constexpr int kXcdModes[4] = {0, 1, 4, 16};
 
 bool lpr_valid(int dtype, int K, int L) {
     return dtype == AD_F32 ? lpr_ok<float>(K, L) : lpr_ok<double>(K, L);
@@ -193,7 +196,7 @@ int autotune(ad_handle h, const ad_csr* A, int K, int relax, const int32_t* colo
             for (int it : iters) {
                 // LS rows and the edge-parallel distances ignore the row-step count
                 if ((fam == KN_LS || L == 0) && it != 1) continue;
-                for (int xcd = 0; xcd <= 1; ++xcd) {
+                for (int xcd : kXcdModes) {
                     LaunchCfg c;
                     c.lpr = L;
                     c.iter = it;
@@ -259,27 +262,60 @@ int autotune(ad_handle h, const ad_csr* A, int K, int relax, const int32_t* colo
     return AD_OK;
 }
 
-// Batched sequence: every valid (lanes per row, row steps per tile, XCD
-// mapping) of the batch's dtype and K is timed on the batch itself (direct
-// launches into scratch outputs); the best is stored for the batch's
-// entries-per-row bucket.
+// Batched sequence: the relaxation shape and the distance shape are picked
+// separately.  Every valid relaxation shape (lanes per row, row steps per
+// tile, XCD mapping) is timed on the batch itself with the default distance
+// form, then every distance shape (the edge-parallel form or a row-group
+// shape) with the chosen relaxation shape; each candidate's stage time comes
+// from the library's per-launch HIP events (direct launches into scratch
+// outputs).  Both are stored for the batch's entries-per-row bucket.
+namespace {
+
+// total ms of the launches labelled `label` recorded while fn ran
+template <typename F>
+double stage_ms(ad_handle h, hipStream_t s, const char* label, F&& fn, bool& ok) {
+    const bool was = h->timing;
+    const size_t t0 = h->timed.size();
+    const int e0 = h->events_used;
+    h->timing = true;
+    ok = fn() == AD_OK;
+    (void)hipStreamSynchronize(s);
+    double ms = 0.0;
+    for (size_t q = t0; q < h->timed.size(); ++q) {
+        float x = 0.f;
+        if (strcmp(h->timed[q].label, label) == 0 &&
+            hipEventElapsedTime(&x, h->timed[q].a, h->timed[q].b) == hipSuccess)
+            ms += x;
+    }
+    h->timed.resize(t0);
+    h->events_used = e0;
+    h->timing = was;
+    return ok ? ms : 1e30;
+}
+
+}  // namespace
+
 int autotune_batched(ad_handle h, int nmat, const ad_csr* As, int K, int sweeps, const char* cache,
                      hipStream_t s) {
     const int dt = As[0].dtype;
     const int ks = k_slot(K);
     const int bucket = batch_bucket(nmat, As);
-    const char* fam = kFamilyName[KN_BATCHED];
+    const int fams[2] = {KN_BATCHED, KN_BDIST};
+    bool need[2] = {true, true};
     std::vector<Entry> entries = read_cache(cache);
-    for (const Entry& e : entries)
-        if (e.kernel == fam && e.dtype == dt && e.K == K && e.bucket == bucket) {
-            LaunchCfg c;
-            c.lpr = e.lpr;
-            c.iter = e.iter;
-            c.xcd_map = e.xcd;
-            h->tuned[KN_BATCHED][dt][ks][bucket] = c;
-            h->has_tuned[KN_BATCHED][dt][ks][bucket] = true;
-            return AD_OK;
-        }
+    for (int f = 0; f < 2; ++f)
+        for (const Entry& e : entries)
+            if (need[f] && e.kernel == kFamilyName[fams[f]] && e.dtype == dt && e.K == K &&
+                e.bucket == bucket) {
+                LaunchCfg c;
+                c.lpr = e.lpr;
+                c.iter = e.iter;
+                c.xcd_map = e.xcd;
+                h->tuned[fams[f]][dt][ks][bucket] = c;
+                h->has_tuned[fams[f]][dt][ks][bucket] = true;
+                need[f] = false;
+            }
+    if (!need[0] && !need[1]) return AD_OK;
     int64_t rows = 0, ents = 0;
     for (int m = 0; m < nmat; ++m) {
         rows += As[m].n;
@@ -293,45 +329,54 @@ int autotune_batched(ad_handle h, int nmat, const ad_csr* As, int K, int sweeps,
     uint8_t* strong = (uint8_t*)sc.get((size_t)ents);
     int32_t* ns = (int32_t*)sc.get(sizeof(int32_t) * (size_t)rows);
     if (!X || !mu || !strong || !ns) return AD_ENOMEM;
-    hipEvent_t ea, eb;
-    AD_HIP(hipEventCreate(&ea));
-    AD_HIP(hipEventCreate(&eb));
-    struct Ev {
-        hipEvent_t a, b;
-        ~Ev() {
-            (void)hipEventDestroy(a);
-            (void)hipEventDestroy(b);
-        }
-    } ev{ea, eb};
+    LaunchCfg rcfg = h->has_tuned[KN_BATCHED][dt][ks][bucket] ? h->tuned[KN_BATCHED][dt][ks][bucket]
+                                                              : LaunchCfg();
+    LaunchCfg dcfg = h->has_tuned[KN_BDIST][dt][ks][bucket] ? h->tuned[KN_BDIST][dt][ks][bucket]
+                                                            : LaunchCfg();
     const int iters[3] = {1, 2, 4};
-    double best = 1e30;
-    LaunchCfg bestc;
-    // lanes per row 0: default relaxation shape with edge-parallel distances
-    for (int L = 0; L <= kWave; L = L ? 2 * L : 1) {
-        if (L == 0 ? !algdist_uses_edge(dt, K, AD_TARGET_PLAIN, LaunchCfg()) : !lpr_valid(dt, K, L))
-            continue;
-        for (int it : iters)
-            for (int xcd = 0; xcd <= 1; ++xcd) {
-                LaunchCfg c;
-                c.lpr = L;
-                c.iter = it;
-                c.xcd_map = xcd;
-                bool ok = true;
-                const double ms = time_ms(s, ea, eb, 3, [&] {
-                    return launch_batched(h, nmat, As, K, 1, sweeps, 2.0 / 3.0, nullptr, X, mu, 0.25,
-                                          strong, ns, c, true, s);
-                }, ok);
-                if (ok && ms < best) {
-                    best = ms;
-                    bestc = c;
+    for (int f = 0; f < 2; ++f) {
+        if (!need[f]) continue;
+        const char* label = f == 0 ? "batch_jacobi" : "batch_algdist";
+        double best = 1e30;
+        LaunchCfg bestc;
+        for (int L = 0; L <= kWave; L = L ? 2 * L : 1) {
+            // relaxation: explicit shapes; distances: also 0, the edge-parallel form
+            if (L == 0 ? (f == 0 || !algdist_uses_edge(dt, K, AD_TARGET_PLAIN, LaunchCfg()))
+                       : !lpr_valid(dt, K, L))
+                continue;
+            for (int it : iters) {
+                if (L == 0 && it != 1) continue;
+                for (int xcd : kXcdModes) {
+                    LaunchCfg c;
+                    c.lpr = L;
+                    c.iter = it;
+                    c.xcd_map = xcd;
+                    const LaunchCfg& rc_ = f == 0 ? c : rcfg;
+                    const LaunchCfg& dc_ = f == 0 ? dcfg : c;
+                    auto run = [&] {
+                        return launch_batched(h, nmat, As, K, 1, sweeps, 2.0 / 3.0, nullptr, X, mu,
+                                              0.25, strong, ns, rc_, dc_, true, s);
+                    };
+                    bool ok = true;
+                    (void)stage_ms(h, s, label, run, ok);  // warm: tables, caches
+                    if (!ok) continue;
+                    double ms = 0.0;
+                    for (int r = 0; r < 3 && ok; ++r) ms += stage_ms(h, s, label, run, ok);
+                    if (ok && ms < best) {
+                        best = ms;
+                        bestc = c;
+                    }
                 }
             }
+        }
+        if (best >= 1e30) return AD_EDEVICE;
+        (f == 0 ? rcfg : dcfg) = bestc;
+        h->tuned[fams[f]][dt][ks][bucket] = bestc;
+        h->has_tuned[fams[f]][dt][ks][bucket] = true;
+        entries.push_back(Entry{kFamilyName[fams[f]], dt, K, bucket, bestc.lpr, bestc.iter,
+                                bestc.xcd_map, best / 3.0});
     }
     AD_HIP(hipStreamSynchronize(s));
-    if (best >= 1e30) return AD_EDEVICE;
-    h->tuned[KN_BATCHED][dt][ks][bucket] = bestc;
-    h->has_tuned[KN_BATCHED][dt][ks][bucket] = true;
-    entries.push_back(Entry{fam, dt, K, bucket, bestc.lpr, bestc.iter, bestc.xcd_map, best});
     write_cache(cache, entries);
     return AD_OK;
 }

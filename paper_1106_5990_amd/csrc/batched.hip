@@ -41,11 +41,7 @@ struct BatchTile {
 };
 
 // Tile index of this workgroup, or -1.
-__device__ __forceinline__ int64_t batch_tile(int64_t ntiles, int xcd) {
-    if (xcd) return xcd_tile(ntiles);
-    const int64_t t = blockIdx.x;
-    return t < ntiles ? t : -1;
-}
+__device__ __forceinline__ int64_t batch_tile(int64_t ntiles, int xcd) { return map_tile(ntiles, xcd); }
 
 template <typename T, int K, int LPR>
 __global__ __launch_bounds__(kBlock) void batch_jacobi_kernel(
@@ -122,7 +118,7 @@ __global__ __launch_bounds__(kBlock) void batch_algdist_edge_kernel(
                                             nstrong ? nstrong + m.row0 : nullptr, lds, status);
 }
 
-constexpr int kEdgeTileRows = kEdgeRows * kWavesPerBlock;
+constexpr int kEdgeTileRows = kEdgeRows * kWavesPerBlock;  // rows per distance tile (edge form)
 
 // ---------------------------------------------------------------- host side
 namespace {
@@ -160,14 +156,17 @@ void drop_graph(BatchPlan& p) {
 
 struct Seq {
     ad_handle h;
-    int dt, K, lpr, iter, xcd, sweeps, edge;
-    int64_t rows, ntiles, nedge;
+    int dt, K, sweeps;
+    int lpr, iter, xcd;     // relaxation shape
+    int dlpr, dxcd, edge;   // distance shape (edge: the edge-parallel form)
+    int64_t rows, ntiles, ndist;
     uint64_t seed;
     double omega, theta;
     const double* w;
     const BatchMat* mats;
-    const BatchTile* tiles;
-    const BatchTile* etiles;  // distance tiles of the edge-parallel form
+    const BatchTile* tiles;   // relaxation tiles
+    const BatchTile* dtiles;  // distance tiles
+    int diter;                // row steps per distance tile (row-group form)
     void *X, *W, *mu;
     uint8_t* strong;
     int32_t* nstrong;
@@ -175,47 +174,63 @@ struct Seq {
 };
 
 template <typename T, int K, int LPR>
-void seq_launch(const Seq& q, hipStream_t s) {
+void seq_relax(const Seq& q, hipStream_t s) {
     // iterate k lives in X when sweeps - k is even, so the last one ends in X
     auto buf = [&](int k) -> T* { return (T*)((((q.sweeps - k) & 1) == 0) ? q.X : q.W); };
-    const int grid = q.xcd ? grid_for_tiles(q.ntiles) : (int)q.ntiles;
+    const int grid = grid_for_tiles(q.ntiles, q.xcd);
     for (int k = 1; k <= q.sweeps; ++k) {
         TimedScope ts(q.h, "batch_jacobi", s);
         batch_jacobi_kernel<T, K, LPR><<<dim3(grid), dim3(kBlock), 0, s>>>(
             q.mats, q.tiles, q.ntiles, q.iter, q.xcd, buf(k - 1), buf(k), (T)q.omega, q.status);
     }
+}
+
+template <typename T, int K, int LPR>
+void seq_dist_rows(const Seq& q, hipStream_t s) {
     TimedScope ts(q.h, "batch_algdist", s);
-    if constexpr (K * (int)sizeof(T) <= kEdgeMaxRowBytes) {
-        if (q.edge) {
-            const int eg = q.xcd ? grid_for_tiles(q.nedge) : (int)q.nedge;
-            if (q.w)
-                batch_algdist_edge_kernel<T, K, true><<<dim3(eg), dim3(kBlock), 0, s>>>(
-                    q.mats, q.etiles, q.nedge, q.xcd, (const T*)q.X, q.w, (T*)q.mu, q.theta,
-                    q.strong, q.nstrong, q.status);
-            else
-                batch_algdist_edge_kernel<T, K, false><<<dim3(eg), dim3(kBlock), 0, s>>>(
-                    q.mats, q.etiles, q.nedge, q.xcd, (const T*)q.X, nullptr, (T*)q.mu, q.theta,
-                    q.strong, q.nstrong, q.status);
-            return;
-        }
-    }
+    const int grid = grid_for_tiles(q.ndist, q.dxcd);
     if (q.w)
         batch_algdist_kernel<T, K, LPR, true><<<dim3(grid), dim3(kBlock), 0, s>>>(
-            q.mats, q.tiles, q.ntiles, q.iter, q.xcd, (const T*)q.X, q.w, (T*)q.mu, q.theta,
+            q.mats, q.dtiles, q.ndist, q.diter, q.dxcd, (const T*)q.X, q.w, (T*)q.mu, q.theta,
             q.strong, q.nstrong, q.status);
     else
         batch_algdist_kernel<T, K, LPR, false><<<dim3(grid), dim3(kBlock), 0, s>>>(
-            q.mats, q.tiles, q.ntiles, q.iter, q.xcd, (const T*)q.X, nullptr, (T*)q.mu, q.theta,
-            q.strong, q.nstrong, q.status);
+            q.mats, q.dtiles, q.ndist, q.diter, q.dxcd, (const T*)q.X, nullptr, (T*)q.mu,
+            q.theta, q.strong, q.nstrong, q.status);
+}
+
+template <typename T, int K>
+void seq_dist_edge(const Seq& q, hipStream_t s) {
+    if constexpr (K * (int)sizeof(T) <= kEdgeMaxRowBytes) {
+        TimedScope ts(q.h, "batch_algdist", s);
+        const int grid = grid_for_tiles(q.ndist, q.dxcd);
+        if (q.w)
+            batch_algdist_edge_kernel<T, K, true><<<dim3(grid), dim3(kBlock), 0, s>>>(
+                q.mats, q.dtiles, q.ndist, q.dxcd, (const T*)q.X, q.w, (T*)q.mu, q.theta,
+                q.strong, q.nstrong, q.status);
+        else
+            batch_algdist_edge_kernel<T, K, false><<<dim3(grid), dim3(kBlock), 0, s>>>(
+                q.mats, q.dtiles, q.ndist, q.dxcd, (const T*)q.X, nullptr, (T*)q.mu, q.theta,
+                q.strong, q.nstrong, q.status);
+    }
 }
 
 template <typename T>
 int seq_dispatch(const Seq& q, hipStream_t s) {
-    return with_k<T>(q.K, [&](auto kc) {
+    return with_k<T>(q.K, [&](auto kc) -> int {
         constexpr int KK = decltype(kc)::value;
-        return with_lpr<T, KK>(q.lpr, [&](auto lc) {
+        const int rc = with_lpr<T, KK>(q.lpr, [&](auto lc) {
             constexpr int L = decltype(lc)::value;
-            seq_launch<T, KK, L>(q, s);
+            seq_relax<T, KK, L>(q, s);
+        });
+        if (rc) return rc;
+        if (q.edge) {
+            seq_dist_edge<T, KK>(q, s);
+            return (int)AD_OK;
+        }
+        return with_lpr<T, KK>(q.dlpr, [&](auto lc) {
+            constexpr int L = decltype(lc)::value;
+            seq_dist_rows<T, KK, L>(q, s);
         });
     });
 }
@@ -249,18 +264,24 @@ void batch_state_free(ad_handle h) {
 
 int launch_batched(ad_handle h, int nmat, const ad_csr* As, int K, uint64_t seed, int sweeps,
                    double omega, const double* w, void* X, void* mu, double theta,
-                   uint8_t* strong, int32_t* nstrong, const LaunchCfg& cfg, bool direct,
-                   hipStream_t s) {
+                   uint8_t* strong, int32_t* nstrong, const LaunchCfg& cfg, const LaunchCfg& dcfg,
+                   bool direct, hipStream_t s) {
     BatchState* bs = state_of(h);
     const int dt = As[0].dtype;
     const size_t vsz = dt == AD_F32 ? 4 : 8;
-    const int lpr = cfg.lpr > 0 ? cfg.lpr
-                                : (dt == AD_F32 ? lpr_default<float>(K) : lpr_default<double>(K));
+    auto resolve = [&](int l) {
+        return l > 0 ? l : (dt == AD_F32 ? lpr_default<float>(K) : lpr_default<double>(K));
+    };
+    const int lpr = resolve(cfg.lpr);
     const int iter = cfg.iter > 0 ? cfg.iter : 1;
-    const int xcd = cfg.xcd_map ? 1 : 0;
-    const int rpb = (kWave / lpr) * kWavesPerBlock;
-    const int64_t tile_rows = (int64_t)rpb * iter;
-    const int edge = algdist_uses_edge(dt, K, AD_TARGET_PLAIN, cfg) ? 1 : 0;
+    const int xcd = cfg.xcd_map;
+    const int64_t tile_rows = (int64_t)(kWave / lpr) * kWavesPerBlock * iter;
+    const int edge = algdist_uses_edge(dt, K, AD_TARGET_PLAIN, dcfg) ? 1 : 0;
+    const int dlpr = edge ? 0 : resolve(dcfg.lpr);
+    const int diter = edge ? 1 : (dcfg.iter > 0 ? dcfg.iter : 1);
+    const int dxcd = dcfg.xcd_map;
+    const int64_t dist_rows =
+        edge ? (int64_t)kEdgeTileRows : (int64_t)(kWave / dlpr) * kWavesPerBlock * diter;
 
     // key: everything the tables and the captured graph depend on
     std::vector<uint8_t> key;
@@ -272,29 +293,28 @@ int launch_batched(ad_handle h, int nmat, const ad_csr* As, int K, uint64_t seed
     put(As, sizeof(ad_csr) * (size_t)nmat);
     const void* ptrs[5] = {X, mu, strong, nstrong, w};
     put(ptrs, sizeof ptrs);
-    const int ints[6] = {K, sweeps, lpr, iter, xcd, edge};
+    const int ints[9] = {K, sweeps, lpr, iter, xcd, edge, dlpr, diter, dxcd};
     put(ints, sizeof ints);
     const double dbl[2] = {omega, theta};
     put(dbl, sizeof dbl);
     put(&seed, sizeof seed);
 
     std::vector<BatchMat> mats((size_t)nmat);
-    int64_t rows = 0, ents = 0, ntiles = 0, nedge = 0;
+    int64_t rows = 0, ents = 0, ntiles = 0, ndist = 0;
     for (int m = 0; m < nmat; ++m) {
         mats[m] = BatchMat{As[m].row_ptr, As[m].col, As[m].val, rows, ents};
         rows += As[m].n;
         ents += As[m].nnz;
         ntiles += (As[m].n + tile_rows - 1) / tile_rows;
-        if (edge) nedge += (As[m].n + kEdgeTileRows - 1) / kEdgeTileRows;
+        ndist += (As[m].n + dist_rows - 1) / dist_rows;
     }
-    if (ntiles > ((int64_t)1 << 31) - 8 || nedge > ((int64_t)1 << 31) - 8)
-        return AD_ESTRUCT;  // grid limit
+    if (ntiles > ((int64_t)1 << 30) || ndist > ((int64_t)1 << 30)) return AD_ESTRUCT;  // grid limit
 
     WsReq req;
     const size_t o_w = req.add((size_t)rows * K * vsz);
     const size_t o_mats = req.add(sizeof(BatchMat) * (size_t)nmat);
     const size_t o_tiles = req.add(sizeof(BatchTile) * (size_t)(ntiles > 0 ? ntiles : 1));
-    const size_t o_etiles = req.add(sizeof(BatchTile) * (size_t)(nedge > 0 ? nedge : 1));
+    const size_t o_dtiles = req.add(sizeof(BatchTile) * (size_t)(ndist > 0 ? ndist : 1));
     const bool same = key == bs->plan.key && bs->dev_bytes >= req.off;
     if (!same) {
         drop_graph(bs->plan);
@@ -314,11 +334,12 @@ int launch_batched(ad_handle h, int nmat, const ad_csr* As, int K, uint64_t seed
     char* ws = (char*)bs->dev;
     BatchMat* dmats = (BatchMat*)(ws + o_mats);
     BatchTile* dtiles = (BatchTile*)(ws + o_tiles);
-    BatchTile* detiles = (BatchTile*)(ws + o_etiles);
+    BatchTile* ddtiles = (BatchTile*)(ws + o_dtiles);
 
     if (!same) {
+        // relaxation tiles, then distance tiles, staged in one pinned buffer
         std::vector<BatchTile> tiles;
-        tiles.reserve((size_t)(ntiles + nedge));
+        tiles.reserve((size_t)(ntiles + ndist));
         auto cut = [&](int64_t rows_per_tile) {
             for (int m = 0; m < nmat; ++m)
                 for (int64_t r = 0; r < As[m].n; r += rows_per_tile)
@@ -326,7 +347,7 @@ int launch_batched(ad_handle h, int nmat, const ad_csr* As, int K, uint64_t seed
                         BatchTile{m, (int)r, (int)std::min<int64_t>(As[m].n, r + rows_per_tile)});
         };
         cut(tile_rows);
-        if (edge) cut(kEdgeTileRows);  // tiles[ntiles ..) are the distance tiles
+        cut(dist_rows);
         const size_t mb = sizeof(BatchMat) * mats.size();
         const size_t tb = mb + sizeof(BatchTile) * tiles.size();
         if (bs->host_bytes < tb) {
@@ -342,19 +363,45 @@ int launch_batched(ad_handle h, int nmat, const ad_csr* As, int K, uint64_t seed
         memcpy(bs->host_stage, mats.data(), mb);
         memcpy((char*)bs->host_stage + mb, tiles.data(), sizeof(BatchTile) * tiles.size());
         AD_HIP(hipMemcpyAsync(dmats, bs->host_stage, mb, hipMemcpyHostToDevice, s));
-        AD_HIP(hipMemcpyAsync(dtiles, (char*)bs->host_stage + mb, sizeof(BatchTile) * (size_t)ntiles,
-                              hipMemcpyHostToDevice, s));
-        if (nedge > 0)
-            AD_HIP(hipMemcpyAsync(detiles,
+        if (ntiles > 0)
+            AD_HIP(hipMemcpyAsync(dtiles, (char*)bs->host_stage + mb,
+                                  sizeof(BatchTile) * (size_t)ntiles, hipMemcpyHostToDevice, s));
+        if (ndist > 0)
+            AD_HIP(hipMemcpyAsync(ddtiles,
                                   (char*)bs->host_stage + mb + sizeof(BatchTile) * (size_t)ntiles,
-                                  sizeof(BatchTile) * (size_t)nedge, hipMemcpyHostToDevice, s));
+                                  sizeof(BatchTile) * (size_t)ndist, hipMemcpyHostToDevice, s));
         bs->plan.key = key;
         bs->plan.ntiles = ntiles;
     }
 
-    const Seq q{h,     dt,      K,        lpr,   iter,  xcd,    sweeps, edge,
-                rows,  ntiles,  nedge,    seed,  omega, theta,  w,      dmats,
-                dtiles, detiles, X,       ws + o_w, mu,  strong, nstrong, h->status};
+    Seq q;
+    q.h = h;
+    q.dt = dt;
+    q.K = K;
+    q.sweeps = sweeps;
+    q.lpr = lpr;
+    q.iter = iter;
+    q.xcd = xcd;
+    q.dlpr = dlpr;
+    q.dxcd = dxcd;
+    q.edge = edge;
+    q.rows = rows;
+    q.ntiles = ntiles;
+    q.ndist = ndist;
+    q.seed = seed;
+    q.omega = omega;
+    q.theta = theta;
+    q.w = w;
+    q.mats = dmats;
+    q.tiles = dtiles;
+    q.dtiles = ddtiles;
+    q.diter = diter;
+    q.X = X;
+    q.W = ws + o_w;
+    q.mu = mu;
+    q.strong = strong;
+    q.nstrong = nstrong;
+    q.status = h->status;
     hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
     AD_HIP(hipStreamIsCapturing(s, &cs));
     if (direct || cs != hipStreamCaptureStatusNone) return run_seq(q, s);  // caller records it

@@ -129,17 +129,30 @@ __device__ __forceinline__ U group_min(U x) {
     return x;
 }
 
-// XCD-aware tile assignment.  Workgroups are dispatched round-robin over the
-// 8 XCDs (blockIdx % 8), each XCD with its own L2.  Give XCD x the contiguous
-// tile range [x * per, (x + 1) * per) so that neighbouring rows -- whose
-// panel rows the gathers re-read -- stay in one L2.  Returns -1 for a
-// workgroup with no tile.  The grid must hold >= 8 * ceil(ntiles / 8) blocks.
-__device__ __forceinline__ int64_t xcd_tile(int64_t ntiles) {
-    const int64_t per = (ntiles + 7) / 8;
+// Tile assignment over the 8 XCDs (workgroups are dispatched round-robin:
+// block b runs on XCD b % 8, each XCD with its own L2).  mode:
+//   0      tile = block index: consecutive tiles on different XCDs;
+//   1      XCD x takes the contiguous tile range [x * per, (x + 1) * per);
+//   c >= 2 chunks of 8c consecutive tiles, XCD x taking tiles
+//          [x * c, (x + 1) * c) of each chunk: neighbouring tiles -- whose
+//          panel rows the gathers re-read -- share an L2 while all XCDs work
+//          on one region of memory at a time.
+// Returns -1 for a workgroup with no tile; the grid is grid_for_tiles(ntiles, mode).
+__device__ __forceinline__ int64_t map_tile(int64_t ntiles, int mode) {
     const int64_t b = blockIdx.x;
-    const int64_t q = b / 8;
-    if (q >= per) return -1;
-    const int64_t t = (b % 8) * per + q;
+    int64_t t;
+    if (mode <= 0) {
+        t = b;
+    } else if (mode == 1) {
+        const int64_t per = (ntiles + 7) / 8;
+        const int64_t q = b / 8;
+        if (q >= per) return -1;
+        t = (b % 8) * per + q;
+    } else {
+        const int64_t span = 8 * (int64_t)mode;
+        const int64_t r = b % span;
+        t = (b - r) + (r % 8) * mode + r / 8;
+    }
     return (t < ntiles) ? t : -1;
 }
 

@@ -39,7 +39,7 @@ __global__ __launch_bounds__(kBlock) void algdist_kernel(
     const int wv = threadIdx.x / kWave;
     const int64_t rows_per_tile = (int64_t)S::RPB * iter;
     const int64_t ntiles = (n + rows_per_tile - 1) / rows_per_tile;
-    const int64_t tile = xcd ? xcd_tile(ntiles) : (int64_t)blockIdx.x;
+    const int64_t tile = map_tile(ntiles, xcd);
     if (tile < 0 || tile >= ntiles) return;
 
     double wd[V];
@@ -66,7 +66,7 @@ static void algdist_go(const ad_csr* A, const void* X, const double* w, int targ
     using S = Shape<T, K, LPR>;
     const int64_t rpt = (int64_t)S::RPB * cfg.iter;
     const int64_t ntiles = (A->n + rpt - 1) / rpt;
-    const int grid = cfg.xcd_map ? grid_for_tiles(ntiles) : (int)ntiles;
+    const int grid = grid_for_tiles(ntiles, cfg.xcd_map);
     if (w)
         algdist_kernel<T, K, LPR, true><<<dim3(grid), dim3(kBlock), 0, s>>>(
             A->n, A->row_ptr, A->col, (const T*)A->val, (const T*)X, w, target, (T*)mu, p, theta,
@@ -88,7 +88,7 @@ __global__ __launch_bounds__(kBlock) void algdist_edge_kernel(
     __shared__ EdgeLds<T> lds;
     const int64_t rows_per_tile = (int64_t)kEdgeRows * kWavesPerBlock;
     const int64_t ntiles = (n + rows_per_tile - 1) / rows_per_tile;
-    const int64_t tile = xcd ? xcd_tile(ntiles) : (int64_t)blockIdx.x;
+    const int64_t tile = map_tile(ntiles, xcd);
     if (tile < 0 || tile >= ntiles) return;  // whole workgroup
     const int64_t r0 = tile * rows_per_tile + (int64_t)(threadIdx.x / kWave) * kEdgeRows;
     const int rl = r0 < n ? (int)min<int64_t>(kEdgeRows, n - r0) : 0;
@@ -102,7 +102,7 @@ static void algdist_edge_go(const ad_csr* A, const void* X, const double* w, voi
                             unsigned* st, const LaunchCfg& cfg, hipStream_t s) {
     const int64_t rpt = (int64_t)kEdgeRows * kWavesPerBlock;
     const int64_t ntiles = (A->n + rpt - 1) / rpt;
-    const int grid = cfg.xcd_map ? grid_for_tiles(ntiles) : (int)ntiles;
+    const int grid = grid_for_tiles(ntiles, cfg.xcd_map);
     auto go = [&](auto weighted, auto lean) {
         algdist_edge_kernel<T, K, decltype(weighted)::value, decltype(lean)::value>
             <<<dim3(grid), dim3(kBlock), 0, s>>>(A->n, A->row_ptr, A->col, (const T*)X, w, (T*)mu,

@@ -31,8 +31,9 @@ enum KernelId {
     KN_ALGDIST = 2,
     KN_LS = 3,
     KN_BATCHED = 4,
-    KN_DLS = 5,  // fused distances + LS rows
-    KN_COUNT = 6
+    KN_DLS = 5,    // fused distances + LS rows
+    KN_BDIST = 6,  // distance stage of the batched path
+    KN_COUNT = 7
 };
 constexpr int kNumKSlots = 7;   // log2(K) for K = 2 .. 64
 constexpr int kNumBuckets = 4;  // stored entries per row: < 8, < 16, < 32, >= 32
@@ -193,8 +194,8 @@ int autotune(ad_handle h, const ad_csr* A, int K, int relax, const int32_t* colo
 // ---- batched.hip
 int launch_batched(ad_handle h, int nmat, const ad_csr* As, int K, uint64_t seed, int sweeps,
                    double omega, const double* w, void* X, void* mu, double theta,
-                   uint8_t* strong, int32_t* nstrong, const LaunchCfg& cfg, bool direct,
-                   hipStream_t s);
+                   uint8_t* strong, int32_t* nstrong, const LaunchCfg& cfg,
+                   const LaunchCfg& dcfg, bool direct, hipStream_t s);
 void batch_state_free(ad_handle h);
 int autotune_batched(ad_handle h, int nmat, const ad_csr* As, int K, int sweeps, const char* cache,
                      hipStream_t s);
@@ -207,9 +208,11 @@ int launch_ls_loss_backward(ad_handle h, int K, const ad_csr* A, const void* ckp
                             const void* X_final, const double* dL, double* grad_val,
                             double* grad_omega, hipStream_t s);
 
-inline int grid_for_tiles(int64_t ntiles) {
-    int64_t per = (ntiles + 7) / 8;
-    return (int)(8 * (per > 0 ? per : 1));
+inline int grid_for_tiles(int64_t ntiles, int mode) {
+    if (ntiles < 1) ntiles = 1;
+    if (mode <= 0) return (int)ntiles;
+    const int64_t span = mode == 1 ? 8 : 8 * (int64_t)mode;
+    return (int)(span * ((ntiles + span - 1) / span));
 }
 
 }  // namespace ad

@@ -125,7 +125,7 @@ __global__ __launch_bounds__(kBlock) void ls_interp_kernel(
     const int g = lane / LPR, l = lane % LPR;
     const int64_t nwin = (n + kLsWindow - 1) / kLsWindow;
     const int64_t ntiles = (nwin + kWavesPerBlock - 1) / kWavesPerBlock;
-    const int64_t tile = xcd ? xcd_tile(ntiles) : (int64_t)blockIdx.x;
+    const int64_t tile = map_tile(ntiles, xcd);
     const int64_t win = (tile >= 0 && tile < ntiles) ? tile * kWavesPerBlock + wv : nwin;
     const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
 
@@ -195,7 +195,7 @@ int ls_interp_blocks(int dtype, int K, int n, const LaunchCfg& cfg) {
     (void)K;
     const int64_t nwin = ((int64_t)n + kLsWindow - 1) / kLsWindow;
     const int64_t ntiles = (nwin + kWavesPerBlock - 1) / kWavesPerBlock;
-    return cfg.xcd_map ? grid_for_tiles(ntiles) : (int)(ntiles > 0 ? ntiles : 1);
+    return grid_for_tiles(ntiles, cfg.xcd_map);
 }
 
 template <typename T, int K, int LPR>
@@ -260,7 +260,7 @@ __global__ __launch_bounds__(kBlock) void dist_ls_kernel(
     const int wv = threadIdx.x / kWave;
     const int64_t rows_per_tile = (int64_t)S::RPB * iter;
     const int64_t ntiles = (n + rows_per_tile - 1) / rows_per_tile;
-    const int64_t tile = xcd ? xcd_tile(ntiles) : (int64_t)blockIdx.x;
+    const int64_t tile = map_tile(ntiles, xcd);
     double wd[V];
     T wt[V];
 #pragma unroll
@@ -321,7 +321,7 @@ static int dist_ls_grid(int n, const LaunchCfg& cfg) {
     using S = Shape<T, K, LPR>;
     const int64_t rpt = (int64_t)S::RPB * cfg.iter;
     const int64_t ntiles = (n + rpt - 1) / rpt;
-    return cfg.xcd_map ? grid_for_tiles(ntiles) : (int)(ntiles > 0 ? ntiles : 1);
+    return grid_for_tiles(ntiles, cfg.xcd_map);
 }
 
 int dist_ls_blocks(int dtype, int K, int n, const LaunchCfg& cfg) {

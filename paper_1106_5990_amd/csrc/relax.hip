@@ -63,7 +63,7 @@ __global__ __launch_bounds__(kBlock) void jacobi_kernel(int n, const int* __rest
     const int wv = threadIdx.x / kWave;
     const int64_t rows_per_tile = (int64_t)S::RPB * iter;
     const int64_t ntiles = (n + rows_per_tile - 1) / rows_per_tile;
-    const int64_t tile = xcd ? xcd_tile(ntiles) : (int64_t)blockIdx.x;
+    const int64_t tile = map_tile(ntiles, xcd);
     if (tile < 0 || tile >= ntiles) return;
     for (int it = 0; it < iter; ++it) {
         const int64_t i64 = tile * rows_per_tile + (int64_t)it * S::RPB + wv * S::RPW + g;
@@ -78,7 +78,7 @@ static void jacobi_go(const ad_csr* A, const void* Xin, void* Xout, double omega
     using S = Shape<T, K, LPR>;
     const int64_t rpt = (int64_t)S::RPB * cfg.iter;
     const int64_t ntiles = (A->n + rpt - 1) / rpt;
-    const int grid = cfg.xcd_map ? grid_for_tiles(ntiles) : (int)ntiles;
+    const int grid = grid_for_tiles(ntiles, cfg.xcd_map);
     jacobi_kernel<T, K, LPR><<<dim3(grid), dim3(kBlock), 0, s>>>(
         A->n, A->row_ptr, A->col, (const T*)A->val, (const T*)Xin, (T*)Xout, (T)omega, cfg.iter,
         cfg.xcd_map, st);
@@ -424,7 +424,7 @@ __global__ __launch_bounds__(kBlock) void gs_phase_perm_kernel(
     const int b0 = seg[c], b1 = seg[c + 1];
     const int64_t rows_per_tile = (int64_t)S::RPB * iter;
     const int64_t ntiles = (b1 - b0 + rows_per_tile - 1) / rows_per_tile;
-    const int64_t tile = xcd ? xcd_tile(ntiles) : (int64_t)blockIdx.x;
+    const int64_t tile = map_tile(ntiles, xcd);
     if (tile >= 0 && tile < ntiles) {
         for (int it = 0; it < iter; ++it) {
             const int64_t p = b0 + tile * rows_per_tile + (int64_t)it * S::RPB + wv * S::RPW + g;
@@ -462,7 +462,7 @@ static void gsp_go(const PermCsr& P, int c, int nc, const void* Xold, void* Xnew
     using S = Shape<T, K, LPR>;
     const int64_t rpt = (int64_t)S::RPB * cfg.iter;
     const int64_t ntiles = (P.n + rpt - 1) / rpt;
-    const int grid = cfg.xcd_map ? grid_for_tiles(ntiles) : (int)ntiles;
+    const int grid = grid_for_tiles(ntiles, cfg.xcd_map);
     gs_phase_perm_kernel<T, K, LPR><<<dim3(grid), dim3(kBlock), 0, s>>>(
         P.rpp, P.colpp, (const T*)P.valpp, c, nc, P.rowlist, P.seg, (const T*)Xold, (T*)Xnew,
         (T*)Xnat, write_perm, cfg.iter, cfg.xcd_map, st);

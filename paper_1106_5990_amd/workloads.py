@@ -32,7 +32,7 @@ from typing import List, Optional, Sequence
 import numpy as np
 
 # Seeds: test-vector seed 1106 + i and coefficient/graph seed 5990 + i for
-# workload i = 1..5 (the five workloads listed in the design doc).
+# workload i = 1..5.
 TV_SEED_BASE = 1106
 COEF_SEED_BASE = 5990
 

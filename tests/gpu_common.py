@@ -1,6 +1,6 @@
 """Shared helpers of the GPU parity tests (imported only by `gpu` tests).
 
-Tolerances (all derived in DESIGN.md, "Parity bars"):
+Tolerances (each derived from the arithmetic of the step it bounds):
 * relaxation, FP64 end to end: |dx| <= 1e-12 max|x|;
 * relaxation, FP32, one sweep from identical FP32 inputs:
   |dx_ik| <= 2^-23 ((nnz_i + 2) sum_j |a_ij z_jk| / |a_ii| + |x_ik|);

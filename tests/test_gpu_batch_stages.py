@@ -71,7 +71,7 @@ def test_batch_replay_tiles_and_edge_members():
     dm = [ad.Csr.from_host(m, dtype=dt) for m in mats]
     ref = concat_reference(mats, dt, K, 7, 3, 0.6, 0.3)
     try:
-        for it, xcd in ((1, True), (3, True), (16, False), (2, False)):
+        for it, xcd in ((1, 1), (3, 1), (16, 0), (2, 0), (1, 4), (2, 16)):
             ad.set_launch("batched", dt, K, 0, it, xcd)
             for rep in range(3):  # the first call captures the graph, later ones replay it
                 got = ad.relax_algdist_batched(dm, K, seed=7, sweeps=3, omega=0.6, theta=0.3)
@@ -107,6 +107,7 @@ def test_batch_every_lane_shape_and_weights():
         say("batch stages lpr=%d" % lpr)
         try:
             ad.set_launch("batched", dt, K, lpr, 2, True)
+            ad.set_launch("batched_distance", dt, K, lpr, 3, 4)
             ad.set_launch("algdist", dt, K, lpr, 1, True)
             got = ad.relax_algdist_batched(dm, K, seed=5, sweeps=4, omega=2 / 3, theta=0.25)
             assert_same(got, concat_reference(mats, dt, K, 5, 4, 2 / 3, 0.25), "lpr %d" % lpr)
@@ -114,6 +115,7 @@ def test_batch_every_lane_shape_and_weights():
             assert_same(got, concat_reference(mats, dt, K, 5, 4, 2 / 3, 0.25, w), "lpr %d, w" % lpr)
         finally:
             ad.set_launch("batched", dt, K, 0, 1, True)
+            ad.set_launch("batched_distance", dt, K, 0, 1, True)
             ad.set_launch("algdist", dt, K, 0, 1, True)
     assert ad.status(clear=True) == 0
 
@@ -127,7 +129,8 @@ def test_batch_autotune_installs_a_shape(tmp_path):
     cache = str(tmp_path / "tune.jsonl")
     ad.autotune_batched(dm, K, 4, cache_json=cache)
     lines = open(cache).read().splitlines()
-    assert len(lines) == 1 and '"kernel": "batched"' in lines[0]
+    assert len(lines) == 2 and '"kernel": "batched"' in lines[0], lines
+    assert '"kernel": "batched_distance"' in lines[1], lines
     # a second handle state reads the cache instead of timing
     ad.autotune_batched(dm, K, 4, cache_json=cache)
     assert open(cache).read().splitlines() == lines
@@ -141,6 +144,7 @@ def test_batch_autotune_installs_a_shape(tmp_path):
              (x * x).sum(1)[ref[0].row_ids()], dt)
     assert ad.status(clear=True) == 0
     ad.set_launch("batched", dt, K, 0, 1, True)
+    ad.set_launch("batched_distance", dt, K, 0, 1, True)
 
 
 def test_batch_argument_errors():
