@@ -140,7 +140,7 @@ int algdist_set_launch(ad_handle h, const char *kernel, int32_t dtype, int32_t K
  * bucket): the relaxation family named by `relax` (color/ncolors as for
  * setup_testvectors), algebraic_distance, and ls_interp (only if cf != NULL
  * and 1 <= caliber <= min(K, 8)).  Every valid (lanes_per_row,
- * rows_per_lane in {1, 2, 4}, xcd_map) is timed with HIP events on scratch
+ * rows_per_lane in {1, 2, 4}, xcd_map in {0, 1, 4, 16, 64, 256}) is timed with HIP events on scratch
  * buffers allocated by this call; the fastest is installed as by
  * algdist_set_launch.  cache_json (host path, may be NULL): entries found
  * there for the key are installed without timing; new results are written

@@ -69,7 +69,7 @@ void write_cache(const char* path, const std::vector<Entry>& v) {
 }
 
 // tile-to-XCD mappings tried (see map_tile)
-constexpr int kXcdModes[4] = {0, 1, 4, 16};
+constexpr int kXcdModes[6] = {0, 1, 4, 16, 64, 256};
 
 bool lpr_valid(int dtype, int K, int L) {
     return dtype == AD_F32 ? lpr_ok<float>(K, L) : lpr_ok<double>(K, L);

@@ -93,6 +93,59 @@ def test_fullsize_fp32_steps(i):
     assert ad.status(clear=True) == 0
 
 
+@pytest.mark.parametrize("dt", [torch.float32, torch.float64])
+def test_fullsize_bench_configuration(dt):
+    """The step exactly as bench.py times it on workload 2: shapes from the
+    autotuner on this matrix, the colour-phase start and sweeps, then the
+    fused distances + strength + LS rows (distance_ls).  Last sweep and
+    distances on sampled rows, the strength graph on every row, the LS rows
+    on sampled rows, the F-row sum against the rows."""
+    ad = lib()
+    w = wl(2)
+    A = w.A
+    say("full-size bench configuration %s, workload %s" % (dt, w.name))
+    Av = A if dt == torch.float64 else W.CSR(A.n, A.row_ptr, A.col,
+                                             A.val.astype(np.float32).astype(np.float64))
+    Ad = dev_csr(A, dt)
+    color = torch.as_tensor(w.color, device="cuda")
+    cf = torch.as_tensor(w.cf, device="cuda")
+    try:
+        ad.autotune(Ad, w.K, relax=w.relax, color=color, ncolors=w.ncolors, cf=cf,
+                    caliber=w.caliber)
+        ad.status(clear=True)
+        Xp = to_np(run_setup(w, Ad, dt, w.sweeps - 1)).astype(np.float64)
+        X = run_setup(w, Ad, dt, w.sweeps)
+        x = to_np(X).astype(np.float64)
+        rows = sample_rows(A.n, seed=7)
+        want = oracle.color_gs_rows(Av, w.color, w.ncolors, Xp, x, rows)
+        err = np.abs(x[rows] - want)
+        if dt == torch.float32:
+            Z = np.where((w.color == 0)[:, None], x, Xp)
+            bound = np.maximum(row_abs_bound(Av, Z, Xp, 1.0, rows=rows),
+                               row_abs_bound(Av, Xp, Xp, 1.0, rows=rows))
+        else:
+            bound = 1e-13 * np.abs(Xp).max() + 0 * err
+        say("  last sweep: max err/bound %.3g" % np.max(err / bound))
+        assert np.all(err <= bound)
+        mu, strong, ns, Pc, Pv, ls, st, tot = ad.distance_ls(Ad, X, cf, w.caliber, theta=w.theta,
+                                                             want_sum=True)
+        mu_h = to_np(mu).astype(np.float64)
+        saa = (x[rows] ** 2).sum(1)
+        saa_e = np.repeat(saa, np.diff(A.row_ptr.astype(np.int64))[rows])
+        check_mu(packed(A, mu_h, rows), oracle.algdist(Av, x, rows=rows), saa_e, dt, "sampled")
+        s_ref, ns_ref = oracle.strength(A, mu_h, w.theta)
+        assert np.array_equal(to_np(strong), s_ref) and np.array_equal(to_np(ns), ns_ref)
+        ref = oracle.ls_interp(Av, x, None, w.cf, mu_h, w.caliber, rows=rows)
+        got = tuple(to_np(t)[rows] for t in (Pc, Pv, ls, st))
+        check_ls(got, ref, dt, saa)
+        lsn = to_np(ls)
+        assert abs(float(tot) - lsn[w.cf == 0].sum()) <= 1e-12 * lsn.sum()
+        assert ad.status(clear=True) == 0
+    finally:
+        for kern in ("gs_phase", "algdist", "ls_interp", "distance_ls"):
+            ad.set_launch(kern, dt, w.K, 0, 1, 1)
+
+
 @pytest.mark.parametrize("i", [2, 3])
 def test_fullsize_fp64_whole_path(i):
     ad = lib()
