@@ -327,8 +327,8 @@ static int gs_sweeps(ad_handle h, const ad_csr* A, int K, uint64_t seed, const v
     PermCsr pc{n, rowlist, seg, (int32_t*)(ws + o_rpp), (int32_t*)(ws + o_colp), ws + o_valp};
     {
         TimedScope ts(h, "color_partition", s);
-        rc = launch_color_partition(n, color, ncolors, rowlist, seg, (int32_t*)(ws + o_cnt), nblk,
-                                    h->status, s);
+        rc = launch_color_partition(n, color, ncolors, rowlist, (int32_t*)(ws + o_inv), seg,
+                                    (int32_t*)(ws + o_cnt), nblk, h->status, s);
         if (!rc) rc = launch_perm_setup(dt, A, pc, (int32_t*)(ws + o_inv), (int32_t*)(ws + o_bs), s);
         if (rc) return fail(h, rc, "colour partition launch");
     }

@@ -165,7 +165,8 @@ int autotune(ad_handle h, const ad_csr* A, int K, int relax, const int32_t* colo
         int32_t* cnt = (int32_t*)sc.get(sizeof(int32_t) * (size_t)(ncolors + 1) * nblk);
         int32_t* bsum = (int32_t*)sc.get(sizeof(int32_t) * (size_t)perm_scan_blocks(n));
         if (!rowlist || !inv || !rpp || !colp || !valp || !seg || !cnt || !bsum) return AD_ENOMEM;
-        if ((rc = launch_color_partition(n, color, ncolors, rowlist, seg, cnt, nblk, h->status, s)))
+        if ((rc = launch_color_partition(n, color, ncolors, rowlist, inv, seg, cnt, nblk, h->status,
+                                         s)))
             return rc;
         pc = PermCsr{n, rowlist, seg, rpp, colp, valp};
         if ((rc = launch_perm_setup(dt, A, pc, inv, bsum, s))) return rc;

@@ -133,12 +133,13 @@ int launch_tv_init(int dtype, int64_t row0, int64_t nrows, int K, uint64_t seed,
                    hipStream_t s);
 int launch_jacobi(int dtype, int K, const ad_csr* A, const void* Xin, void* Xout, double omega,
                   unsigned* status, const LaunchCfg& cfg, hipStream_t s);
-// Builds the colour-sorted row list: rowlist[n] and seg[ncolors + 2]
+// Builds the colour-sorted row list: rowlist[n], its inverse inv[n] (may be
+// NULL) and seg[ncolors + 2]
 // (seg[c]..seg[c+1] are the rows of colour c; seg[ncolors]..seg[ncolors+1]
 // the rows with an invalid colour).  counts: (ncolors+1) * nblocks ints.
 int launch_color_partition(int n, const int32_t* color, int ncolors, int32_t* rowlist,
-                           int32_t* seg, int32_t* counts, int nblocks, unsigned* status,
-                           hipStream_t s);
+                           int32_t* inv, int32_t* seg, int32_t* counts, int nblocks,
+                           unsigned* status, hipStream_t s);
 int color_partition_blocks(int n);
 // Colour-major copy of a CSR for the colour phases: permuted row p is natural
 // row rowlist[p]; its entries rpp[p]..rpp[p+1] keep their CSR order with

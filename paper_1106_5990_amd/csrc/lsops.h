@@ -122,9 +122,13 @@ __device__ __forceinline__ double ls_solve(int i, int l, const double (&t)[K / L
         val = tt;
         st = st ? st : 1;
     } else {
-        // Cholesky (in place, packed lower) in increasing-mu order, drop rule
+        // Cholesky (in place, packed lower) in increasing-mu order, drop
+        // rule; the reciprocal of each kept pivot is formed once and the
+        // factor and both triangular solves multiply by it
+        double rd[CALT];
 #pragma unroll
         for (int a = 0; a < CALT; ++a) {
+            rd[a] = 0.0;
             if (a >= nsel) continue;
             const int ra = a * (a + 1) / 2;
             const double gaa = G[ra + a];
@@ -135,15 +139,21 @@ __device__ __forceinline__ double ls_solve(int i, int l, const double (&t)[K / L
 #pragma unroll
                 for (int c = 0; c < b; ++c)
                     if (keep[c]) s -= G[ra + c] * G[rb + c];
-                G[ra + b] = keep[b] ? s / G[rb + b] : 0.0;
+                G[ra + b] = keep[b] ? s * rd[b] : 0.0;
             }
             double piv = gaa;
 #pragma unroll
             for (int b = 0; b < a; ++b)
                 if (keep[b]) piv -= G[ra + b] * G[ra + b];
             keep[a] = piv > 1e-12 * gaa;
-            G[ra + a] = keep[a] ? sqrt(piv) : 1.0;
-            if (!keep[a]) st = st ? st : 2;
+            if (keep[a]) {
+                const double l = sqrt(piv);
+                G[ra + a] = l;
+                rd[a] = 1.0 / l;
+            } else {
+                G[ra + a] = 1.0;
+                st = st ? st : 2;
+            }
         }
         double z[CALT];
 #pragma unroll
@@ -153,7 +163,7 @@ __device__ __forceinline__ double ls_solve(int i, int l, const double (&t)[K / L
 #pragma unroll
             for (int b = 0; b < a; ++b)
                 if (keep[b]) s -= G[ra + b] * z[b];
-            z[a] = keep[a] ? s / G[ra + a] : 0.0;
+            z[a] = keep[a] ? s * rd[a] : 0.0;
         }
 #pragma unroll
         for (int a = CALT - 1; a >= 0; --a) {
@@ -161,7 +171,7 @@ __device__ __forceinline__ double ls_solve(int i, int l, const double (&t)[K / L
 #pragma unroll
             for (int b = a + 1; b < CALT; ++b)
                 if (keep[b]) s -= G[b * (b + 1) / 2 + a] * coef[b];
-            coef[a] = keep[a] ? s / G[a * (a + 1) / 2 + a] : 0.0;
+            coef[a] = keep[a] ? s * rd[a] : 0.0;
         }
         // the functional at the minimiser, by its definition
         double f = 0.0;

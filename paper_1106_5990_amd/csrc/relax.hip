@@ -179,6 +179,7 @@ __global__ __launch_bounds__(kBlock) void color_scatter_kernel(int n, const int*
                                                                const int* __restrict__ offsets,
                                                                int nblocks,
                                                                int* __restrict__ rowlist,
+                                                               int* __restrict__ inv,
                                                                unsigned* status) {
     __shared__ int base[kMaxColors + 1];
     __shared__ int wcnt[kWavesPerBlock][kMaxColors + 1];
@@ -203,6 +204,7 @@ __global__ __launch_bounds__(kBlock) void color_scatter_kernel(int n, const int*
             int pos = base[c] + rank;
             for (int w = 0; w < wv; ++w) pos += wcnt[w][c];
             rowlist[pos] = r;
+            if (inv) inv[r] = pos;
         }
         __syncthreads();
         for (int q = threadIdx.x; q <= nc; q += kBlock) {
@@ -216,8 +218,8 @@ __global__ __launch_bounds__(kBlock) void color_scatter_kernel(int n, const int*
 }
 
 int launch_color_partition(int n, const int32_t* color, int ncolors, int32_t* rowlist,
-                           int32_t* seg, int32_t* counts, int nblocks, unsigned* status,
-                           hipStream_t s) {
+                           int32_t* inv, int32_t* seg, int32_t* counts, int nblocks,
+                           unsigned* status, hipStream_t s) {
     if (n == 0) {
         AD_HIP(hipMemsetAsync(seg, 0, sizeof(int32_t) * (ncolors + 2), s));
         return AD_OK;
@@ -226,7 +228,7 @@ int launch_color_partition(int n, const int32_t* color, int ncolors, int32_t* ro
     scan_counts_kernel<<<dim3(1), dim3(1024), 0, s>>>(counts, (ncolors + 1) * nblocks, nblocks,
                                                       ncolors, n, seg);
     color_scatter_kernel<<<dim3(nblocks), dim3(kBlock), 0, s>>>(n, color, ncolors, counts,
-                                                                nblocks, rowlist, status);
+                                                                nblocks, rowlist, inv, status);
     AD_HIP(hipGetLastError());
     return AD_OK;
 }
@@ -237,12 +239,6 @@ int launch_color_partition(int n, const int32_t* color, int ncolors, int32_t* ro
 // cache line a phase touches holds rows it needs.  A neighbour's permuted
 // index jp is read from colp[e] = inv[col[e]]; "smaller colour" is jp <
 // seg[c] because the segments are in colour order.
-
-__global__ __launch_bounds__(kBlock) void inverse_perm_kernel(int n, const int* __restrict__ rowlist,
-                                                              int* __restrict__ inv) {
-    const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (p < n) inv[rowlist[p]] = (int)p;
-}
 
 // Colour-major CSR: permuted row p holds the entries of natural row
 // rowlist[p] in their CSR order, columns mapped to permuted indices, so a
@@ -362,28 +358,41 @@ __global__ __launch_bounds__(kBlock) void permute_entries_kernel(
 }
 
 // Xp[p] = hash start of natural row rowlist[p] (or X0[rowlist[p]] if given);
-// E consecutive values per thread, stored as one 16-byte chunk.  K is a
-// power of two: row and column of a panel value come from shifts.
+// each thread writes kStartChunks consecutive 16-byte chunks (the row-list
+// loads of a thread are independent and in flight together).  K is a power
+// of two: row and column of a panel value come from shifts.
+constexpr int kStartChunks = 4;
+
 template <typename T>
 __global__ __launch_bounds__(kBlock) void start_perm_kernel(int64_t total, int kshift,
                                                             const int* __restrict__ rowlist,
                                                             uint64_t seed, const T* __restrict__ X0,
                                                             T* __restrict__ Xp) {
     constexpr int E = 16 / sizeof(T);
-    const int64_t base = ((int64_t)blockIdx.x * kBlock + threadIdx.x) * E;
+    constexpr int N = E * kStartChunks;
+    const int64_t base = ((int64_t)blockIdx.x * kBlock + threadIdx.x) * N;
     if (base >= total) return;
     const int64_t kmask = ((int64_t)1 << kshift) - 1;
-    Frag<T, E> f;
+    int64_t src[N];
 #pragma unroll
-    for (int q = 0; q < E; ++q) {
+    for (int q = 0; q < N; ++q) {
         const int64_t c = base + q < total ? base + q : total - 1;
-        const int64_t src = ((int64_t)rowlist[c >> kshift] << kshift) | (c & kmask);
-        f.v[q] = X0 ? X0[src] : (T)uniform_pm1(splitmix64_at(seed, (uint64_t)src));
+        src[q] = ((int64_t)rowlist[c >> kshift] << kshift) | (c & kmask);
     }
-    if (base + E <= total) {
-        store_frag<T, E>(Xp + base, f);
-    } else {
-        for (int q = 0; q < E && base + q < total; ++q) Xp[base + q] = f.v[q];
+#pragma unroll
+    for (int h = 0; h < kStartChunks; ++h) {
+        Frag<T, E> f;
+#pragma unroll
+        for (int q = 0; q < E; ++q) {
+            const int64_t s = src[h * E + q];
+            f.v[q] = X0 ? X0[s] : (T)uniform_pm1(splitmix64_at(seed, (uint64_t)s));
+        }
+        const int64_t o = base + h * E;
+        if (o + E <= total) {
+            store_frag<T, E>(Xp + o, f);
+        } else {
+            for (int q = 0; q < E && o + q < total; ++q) Xp[o + q] = f.v[q];
+        }
     }
 }
 
@@ -495,15 +504,13 @@ int launch_gs_phase_perm(int dtype, int K, const PermCsr& P, int c, int ncolors,
     return AD_OK;
 }
 
-// inv, then the colour-major row pointers and entries of P (whose rowlist is
-// already partitioned); bsum holds perm_scan_blocks(n) ints.
+// The colour-major row pointers and entries of P (whose rowlist and inverse
+// inv the partition wrote); bsum holds perm_scan_blocks(n) ints.
 int launch_perm_setup(int dtype, const ad_csr* A, PermCsr& P, int32_t* inv, int32_t* bsum,
                       hipStream_t s) {
     const int n = A->n;
     if (n == 0) return AD_OK;
     const unsigned nb = (unsigned)perm_scan_blocks(n);
-    inverse_perm_kernel<<<dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, s>>>(
-        n, P.rowlist, inv);
     perm_len_sums_kernel<<<dim3(nb), dim3(kBlock), 0, s>>>(n, A->row_ptr, P.rowlist, bsum);
     scan_block_sums_kernel<<<dim3(1), dim3(1024), 0, s>>>(bsum, (int)nb);
     perm_row_ptr_kernel<<<dim3(nb), dim3(kBlock), 0, s>>>(n, A->row_ptr, P.rowlist, bsum,
@@ -526,8 +533,8 @@ int launch_start_perm(int dtype, int n, int K, const int32_t* rowlist, uint64_t 
                       const void* X0, void* Xp, hipStream_t s) {
     const int64_t m = (int64_t)n * K;
     if (m == 0) return AD_OK;
-    const int E = dtype == AD_F32 ? 4 : 2;
-    const unsigned b = (unsigned)(((m + E - 1) / E + kBlock - 1) / kBlock);
+    const int N = (dtype == AD_F32 ? 4 : 2) * kStartChunks;
+    const unsigned b = (unsigned)(((m + N - 1) / N + kBlock - 1) / kBlock);
     if (dtype == AD_F32)
         start_perm_kernel<float><<<dim3(b), dim3(kBlock), 0, s>>>(m, log2_of(K), rowlist, seed,
                                                                   (const float*)X0, (float*)Xp);
