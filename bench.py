@@ -51,6 +51,8 @@ def parse():
                     help="autotuner cache file (JSON lines); shapes found there are used without "
                          "timing, new ones are appended (default: a fresh temporary file)")
     ap.add_argument("--batch-size", type=int, default=512)
+    ap.add_argument("--adjoint", action="store_true",
+                    help="also time the LS-loss forward and adjoint (workload 5)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one 1 GiB device-to-device copy (a kernel of known traffic "
                          "for scaling hardware byte counters)")
@@ -311,6 +313,43 @@ def batched_leg(args, torch, ad, W, mats):
     return out
 
 
+def adjoint_leg(args, torch, ad, W):
+    """Workload 5: L(values, omega) through LSInterpLoss (FP64, checkpoints
+    every 2 sweeps) and its gradient with respect to every stored value and
+    omega; forward and forward + backward timed separately."""
+    wl = W.workload(5)
+    A = wl.A
+    dev = "cuda"
+    rp = torch.as_tensor(A.row_ptr, device=dev)
+    col = torch.as_tensor(A.col, device=dev)
+    cf = torch.as_tensor(wl.cf, device=dev)
+    vals = torch.as_tensor(A.val, dtype=torch.float64, device=dev).requires_grad_(True)
+    om = torch.tensor(wl.omega, dtype=torch.float64, device=dev, requires_grad=True)
+
+    def fwd():
+        return ad.LSInterpLoss.apply(vals, om, rp, col, wl.K, wl.tv_seed, wl.sweeps, cf,
+                                     wl.caliber, 2)
+
+    def both():
+        return torch.autograd.grad(fwd(), (vals, om))
+    out = {"workload": wl.name, "K": wl.K, "sweeps": wl.sweeps, "edges": A.n_edges}
+    for tag, fn in (("forward", fwd), ("forward_backward", both)):
+        for _ in range(args.warmup):
+            fn()
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(args.steps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        out[tag + "_ms"] = round(e0.elapsed_time(e1) / args.steps, 4)
+    out["backward_over_forward"] = round(out["forward_backward_ms"] / out["forward_ms"] - 1.0, 3)
+    out["device_status_bits"] = ad.status(clear=True)
+    return out
+
+
 def cpu_baseline(idx, side):
     """The oracle, as it stands, on a bounded sample of the same workload:
     the same operator family and parameters on a smaller grid."""
@@ -446,6 +485,9 @@ def main():
     if args.batched:
         print("[bench] batched leg (workload 4)", file=sys.stderr, flush=True)
         out["batched"] = batched_leg(args, torch, ad, W, batch)
+    if args.adjoint:
+        print("[bench] adjoint leg (workload 5)", file=sys.stderr, flush=True)
+        out["adjoint"] = adjoint_leg(args, torch, ad, W)
     if not args.no_cpu_baseline:
         side = args.cpu_sample or args.size or {1: 32, 2: 2048, 3: 160}[idx]
         print("[bench] cpu baseline: oracle on a side-%d sample" % side, file=sys.stderr, flush=True)

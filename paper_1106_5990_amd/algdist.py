@@ -386,8 +386,9 @@ class LSInterpLoss(torch.autograd.Function):
     apply(values, omega, row_ptr, col, K, seed, sweeps, cf, caliber,
           ckpt_every=2, w=None, X0=None) -> 0-dim FP64 tensor.
     values: FP64 CSR values (requires_grad); omega: 0-dim or 1-element FP64
-    tensor (requires_grad).  Forward: setup_testvectors (checkpointed),
-    algebraic_distance (which picks C_i), ls_interp with its F-row sum.
+    tensor (requires_grad).  Forward: setup_testvectors (checkpointed), then
+    the distances (which pick C_i) and the LS rows with their F-row sum in one
+    pass (distance_ls).
     Backward: ls_interp_loss_backward.
     """
 
@@ -400,8 +401,8 @@ class LSInterpLoss(torch.autograd.Function):
         ck = torch.empty((nck, A.n, K), dtype=torch.float64, device=A.device)
         X = setup_testvectors(A, K, seed=seed, X0=X0, relax="jacobi", sweeps=sweeps, omega=om,
                               ckpt=ck, ckpt_every=ckpt_every)
-        mu = algebraic_distance(A, X, w=w)
-        Pc, Pv, ls, st, tot = ls_interp(A, X, cf, mu, caliber, w=w, want_sum=True)
+        _, _, _, Pc, Pv, ls, st, tot = distance_ls(A, X, cf, caliber, w=w, fuse=False,
+                                                   want_sum=True)
         ctx.save_for_backward(values, ck, X, Pc, Pv, cf)
         ctx.meta = (row_ptr, col, K, sweeps, ckpt_every, om, w, omega.shape)
         return tot.reshape(())

@@ -31,7 +31,7 @@ def gpu_loss_and_grad(A, K, seed, sweeps, omega, cf, cal, w=None, ce=2):
     wt = None if w is None else torch.as_tensor(w, device="cuda")
     L = ad.LSInterpLoss.apply(vals, om, rp, col, K, seed, sweeps, cft, cal, ce, wt)
     gv, go = torch.autograd.grad(L, (vals, om))
-    return float(L), to_np(gv), float(go)
+    return float(L.detach()), to_np(gv), float(go)
 
 
 @pytest.mark.parametrize("weighted", [False, True])
