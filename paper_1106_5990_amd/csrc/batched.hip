@@ -58,10 +58,21 @@ __global__ __launch_bounds__(kBlock) void batch_jacobi_kernel(
     const int wv = threadIdx.x / kWave;
     const T* xi = Xin + m.row0 * K;
     T* xo = Xout + m.row0 * K;
+    __shared__ CsrStage<T> stg;
     for (int it = 0; it < iter; ++it) {
-        const int i = tl.r0 + it * S::RPB + wv * S::RPW + g;
-        if (i >= tl.r1) break;
-        jacobi_row<S, T, K>(i, l, m.rp, m.ci, (const T*)m.av, xi, xo, omega, status);
+        const int iw = tl.r0 + it * S::RPB + wv * S::RPW;
+        if (iw >= tl.r1) break;  // whole wavefront
+        const int64_t s0 = m.rp[iw];
+        const int ie = (iw + S::RPW < tl.r1) ? iw + S::RPW : tl.r1;
+        const int64_t sc = m.rp[ie] - s0;
+        const int cnt = sc < kStageCap ? (int)sc : kStageCap;
+        wave_lds_sync();
+        stage_csr(stg, wv, lane, s0, cnt, m.ci, (const T*)m.av);
+        wave_lds_sync();
+        const int i = iw + g;
+        if (i >= tl.r1) continue;
+        jacobi_row_staged<S, T, K>(i, l, m.rp, m.ci, (const T*)m.av, stg, wv, s0, cnt, xi, xo,
+                                   omega, status);
     }
 }
 

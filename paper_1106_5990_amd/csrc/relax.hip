@@ -65,10 +65,21 @@ __global__ __launch_bounds__(kBlock) void jacobi_kernel(int n, const int* __rest
     const int64_t ntiles = (n + rows_per_tile - 1) / rows_per_tile;
     const int64_t tile = map_tile(ntiles, xcd);
     if (tile < 0 || tile >= ntiles) return;
+    __shared__ CsrStage<T> stg;
     for (int it = 0; it < iter; ++it) {
-        const int64_t i64 = tile * rows_per_tile + (int64_t)it * S::RPB + wv * S::RPW + g;
-        if (i64 >= n) break;
-        jacobi_row<S, T, K>((int)i64, l, rp, ci, av, Xin, Xout, omega, status);
+        const int64_t iw = tile * rows_per_tile + (int64_t)it * S::RPB + wv * S::RPW;
+        if (iw >= n) break;  // whole wavefront
+        const int64_t s0 = rp[iw];
+        const int64_t ie = (iw + S::RPW < n) ? iw + S::RPW : (int64_t)n;
+        const int64_t sc = rp[ie] - s0;
+        const int cnt = sc < kStageCap ? (int)sc : kStageCap;
+        wave_lds_sync();
+        stage_csr(stg, wv, lane, s0, cnt, ci, av);
+        wave_lds_sync();
+        const int64_t i64 = iw + g;
+        if (i64 >= n) continue;
+        jacobi_row_staged<S, T, K>((int)i64, l, rp, ci, av, stg, wv, s0, cnt, Xin, Xout, omega,
+                                   status);
     }
 }
 
@@ -434,14 +445,25 @@ __global__ __launch_bounds__(kBlock) void gs_phase_perm_kernel(
     const int64_t rows_per_tile = (int64_t)S::RPB * iter;
     const int64_t ntiles = (b1 - b0 + rows_per_tile - 1) / rows_per_tile;
     const int64_t tile = map_tile(ntiles, xcd);
+    __shared__ CsrStage<T> stg;
     if (tile >= 0 && tile < ntiles) {
         for (int it = 0; it < iter; ++it) {
-            const int64_t p = b0 + tile * rows_per_tile + (int64_t)it * S::RPB + wv * S::RPW + g;
-            if (p >= b1) break;
+            const int64_t pw = b0 + tile * rows_per_tile + (int64_t)it * S::RPB + wv * S::RPW;
+            if (pw >= b1) break;  // whole wavefront
+            const int64_t s0 = rpp[pw];
+            const int64_t pe = (pw + S::RPW < b1) ? pw + S::RPW : (int64_t)b1;
+            const int64_t sc = rpp[pe] - s0;
+            const int cnt = sc < kStageCap ? (int)sc : kStageCap;
+            wave_lds_sync();
+            stage_csr(stg, wv, lane, s0, cnt, colpp, valpp);
+            wave_lds_sync();
+            const int64_t p = pw + g;
+            if (p >= b1) continue;
             T y[V], d;
             Frag<T, V> xi;
-            row_spmm<S, T, K>((int)p, rpp[p], rpp[p + 1], colpp, valpp, l,
-                              [&](int jp) { return (jp < b0) ? (const T*)Xnew : Xold; }, y, d, xi);
+            row_spmm_staged<S, T, K>(
+                (int)p, rpp[p], rpp[p + 1], stg, wv, s0, cnt, colpp, valpp, l,
+                [&](int jp) { return (jp < b0) ? (const T*)Xnew : Xold; }, y, d, xi);
             Frag<T, V> out;
             if (d == T(0)) {
                 out = load_lane<T, V, C>(Xold + (size_t)p * K + l * V);

@@ -13,11 +13,12 @@ namespace ad {
 // ---------------------------------------------------------------- row SpMM core
 // y = sum_e a_e x_{col e} over the row's entries, in CSR order (FMA per term);
 // also returns the diagonal value and the row's own fragment.
-// pick(j) chooses which panel a neighbour is read from.
-template <typename S, typename T, int K, typename Pick>
-__device__ __forceinline__ void row_spmm(int i, int e0, int e1, const int* __restrict__ ci,
-                                         const T* __restrict__ av, int l, Pick pick,
-                                         T (&y)[S::V], T& d, Frag<T, S::V>& xi) {
+// ci_of(e) / av_of(e) give entry e's column and value (from global memory or
+// from a wavefront's LDS copy); pick(j) chooses which panel a neighbour is
+// read from.
+template <typename S, typename T, int K, typename CiF, typename AvF, typename Pick>
+__device__ __forceinline__ void row_spmm_acc(int i, int e0, int e1, CiF ci_of, AvF av_of, int l,
+                                             Pick pick, T (&y)[S::V], T& d, Frag<T, S::V>& xi) {
     constexpr int V = S::V, C = S::C;
     constexpr int U = (V >= 16) ? 2 : 4;  // independent gathers in flight per step
 #pragma unroll
@@ -30,8 +31,8 @@ __device__ __forceinline__ void row_spmm(int i, int e0, int e1, const int* __res
         Frag<T, V> x[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            j[u] = ci[e + u];
-            a[u] = av[e + u];
+            j[u] = ci_of(e + u);
+            a[u] = av_of(e + u);
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) x[u] = load_lane<T, V, C>(pick(j[u]) + (size_t)j[u] * K + l * V);
@@ -46,8 +47,8 @@ __device__ __forceinline__ void row_spmm(int i, int e0, int e1, const int* __res
         }
     }
     for (; e < e1; ++e) {
-        const int j = ci[e];
-        const T a = av[e];
+        const int j = ci_of(e);
+        const T a = av_of(e);
         Frag<T, V> x = load_lane<T, V, C>(pick(j) + (size_t)j * K + l * V);
 #pragma unroll
         for (int q = 0; q < V; ++q) y[q] = fma(a, x.v[q], y[q]);
@@ -55,6 +56,66 @@ __device__ __forceinline__ void row_spmm(int i, int e0, int e1, const int* __res
             d = a;
             xi = x;
         }
+    }
+}
+
+template <typename S, typename T, int K, typename Pick>
+__device__ __forceinline__ void row_spmm(int i, int e0, int e1, const int* __restrict__ ci,
+                                         const T* __restrict__ av, int l, Pick pick,
+                                         T (&y)[S::V], T& d, Frag<T, S::V>& xi) {
+    row_spmm_acc<S, T, K>(
+        i, e0, e1, [&](int e) { return ci[e]; }, [&](int e) { return av[e]; }, l, pick, y, d, xi);
+}
+
+// ---------------------------------------------------------------- CSR staging
+// The rows a wavefront works on are consecutive, so their entries form one
+// contiguous range.  The wave copies that range (up to kStageCap entries)
+// into its own LDS region with coalesced loads, and its row groups then read
+// columns and values from LDS: the per-lane entry loads -- the same entry
+// fetched by every lane of a row group -- leave the vector-memory address
+// path to the panel gathers.  A row whose entries run past the staged range
+// reads them from global memory.
+constexpr int kStageCap = 512;  // entries per wavefront
+
+template <typename T>
+struct CsrStage {
+    int ci[kWavesPerBlock][kStageCap];
+    T av[kWavesPerBlock][kStageCap];
+};
+
+// orders this wavefront's LDS writes before its later LDS reads
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Copies entries [s0, s0 + cnt), cnt <= kStageCap, of (ci, av) into the
+// wave's region (entry g at index g - s0), one entry per lane per load.
+template <typename T>
+__device__ __forceinline__ void stage_csr(CsrStage<T>& L, int wv, int lane, int64_t s0, int cnt,
+                                          const int* __restrict__ ci, const T* __restrict__ av) {
+    for (int q = lane; q < cnt; q += kWave) {
+        L.ci[wv][q] = ci[s0 + q];
+        L.av[wv][q] = av[s0 + q];
+    }
+}
+
+// row_spmm with the row's entries from the wave's staged copy when they lie
+// inside it (s0: first staged entry, cnt: staged count), else from global.
+template <typename S, typename T, int K, typename Pick>
+__device__ __forceinline__ void row_spmm_staged(int i, int e0, int e1, const CsrStage<T>& L,
+                                                int wv, int64_t s0, int cnt,
+                                                const int* __restrict__ ci,
+                                                const T* __restrict__ av, int l, Pick pick,
+                                                T (&y)[S::V], T& d, Frag<T, S::V>& xi) {
+    if ((int64_t)e1 - s0 <= cnt) {
+        const int o = -(int)s0;  // LDS index of entry e is e + o
+        row_spmm_acc<S, T, K>(
+            i, e0, e1, [&](int e) { return L.ci[wv][e + o]; }, [&](int e) { return L.av[wv][e + o]; },
+            l, pick, y, d, xi);
+    } else {
+        row_spmm<S, T, K>(i, e0, e1, ci, av, l, pick, y, d, xi);
     }
 }
 
@@ -68,6 +129,30 @@ __device__ __forceinline__ void jacobi_row(int i, int l, const int* __restrict__
     T y[V], d;
     Frag<T, V> xi;
     row_spmm<S, T, K>(i, rp[i], rp[i + 1], ci, av, l, [&](int) { return Xin; }, y, d, xi);
+    Frag<T, V> out;
+    if (d == T(0)) {
+        out = load_lane<T, V, C>(Xin + (size_t)i * K + l * V);
+        if (l == 0) flag(status, AD_STAT_ZERO_DIAG);
+    } else {
+#pragma unroll
+        for (int q = 0; q < V; ++q) out.v[q] = xi.v[q] - omega * y[q] / d;
+    }
+    store_lane<T, V, C>(Xout + (size_t)i * K + l * V, out);
+}
+
+// jacobi_row with the row's entries from the wave's staged copy
+template <typename S, typename T, int K>
+__device__ __forceinline__ void jacobi_row_staged(int i, int l, const int* __restrict__ rp,
+                                                  const int* __restrict__ ci,
+                                                  const T* __restrict__ av, const CsrStage<T>& L,
+                                                  int wv, int64_t s0, int cnt,
+                                                  const T* __restrict__ Xin, T* __restrict__ Xout,
+                                                  T omega, unsigned* status) {
+    constexpr int V = S::V, C = S::C;
+    T y[V], d;
+    Frag<T, V> xi;
+    row_spmm_staged<S, T, K>(i, rp[i], rp[i + 1], L, wv, s0, cnt, ci, av, l,
+                             [&](int) { return Xin; }, y, d, xi);
     Frag<T, V> out;
     if (d == T(0)) {
         out = load_lane<T, V, C>(Xin + (size_t)i * K + l * V);
