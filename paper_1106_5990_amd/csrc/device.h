@@ -111,22 +111,88 @@ __device__ __forceinline__ void store_lane(T* __restrict__ p, const Frag<T, V>& 
     }
 }
 
-// Sum over the LPR lanes of a row group (groups are aligned lane ranges).
+// v itself, as a value the compiler cannot see through: conversions of it
+// are formed where they are used instead of being hoisted and kept live.
+template <typename T>
+__device__ __forceinline__ T opaque(T v) {
+    asm volatile("" : "+v"(v));
+    return v;
+}
+
+// An FP64 value as the FP32 path carries it: its FP32 rounding plus the
+// FP32 rounding of the remainder (48 significant bits, relative error at
+// most 2^-48); the value itself on the FP64 path.
+template <typename T>
+__device__ __forceinline__ double carried(double x) {
+    if constexpr (sizeof(T) == 8) {
+        return x;
+    } else {
+        const T hi = (T)x;
+        return (double)hi + (double)(T)(x - (double)hi);
+    }
+}
+
+// The value of partner lane i ^ m(O) for a butterfly level of offset O.
+// Inside a 16-lane row the exchange is a DPP move (no LDS round trip):
+// O = 1, 2 swap lanes within a quad (m = 1, 2), O = 4 mirrors each 8-lane
+// half (m = 7), O = 8 mirrors the row (m = 15); larger offsets use the
+// cross-lane permute (m = O).  The masks of any run O = LPR/2, ..., 1 span
+// the group's lane indices, so the butterfly reaches every lane, and at each
+// level a lane and its partner add the same two values: every lane of the
+// group ends with the bitwise identical result.
+template <int O>
+__device__ __forceinline__ int lane_swap_i32(int x) {
+    if constexpr (O == 1) return __builtin_amdgcn_mov_dpp(x, 0xB1, 0xF, 0xF, true);  // [1,0,3,2]
+    else if constexpr (O == 2) return __builtin_amdgcn_mov_dpp(x, 0x4E, 0xF, 0xF, true);  // [2,3,0,1]
+    else if constexpr (O == 4) return __builtin_amdgcn_mov_dpp(x, 0x141, 0xF, 0xF, true);  // half mirror
+    else if constexpr (O == 8) return __builtin_amdgcn_mov_dpp(x, 0x140, 0xF, 0xF, true);  // mirror
+    else return __shfl_xor(x, O, kWave);
+}
+
+template <int O, typename U>
+__device__ __forceinline__ U lane_swap(U x) {
+    static_assert(sizeof(U) == 4 || sizeof(U) == 8, "32- or 64-bit values");
+    if constexpr (sizeof(U) == 4) {
+        return __builtin_bit_cast(U, lane_swap_i32<O>(__builtin_bit_cast(int, x)));
+    } else {
+        const int64_t b = __builtin_bit_cast(int64_t, x);
+        const int lo = lane_swap_i32<O>((int)(uint32_t)b);
+        const int hi = lane_swap_i32<O>((int)(b >> 32));
+        return __builtin_bit_cast(U, (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo));
+    }
+}
+
+template <int O, int LPR, typename U>
+__device__ __forceinline__ U group_sum_from(U x) {
+    if constexpr (O == 0) {
+        return x;
+    } else {
+        x += lane_swap<O>(x);
+        return group_sum_from<O / 2, LPR>(x);
+    }
+}
+
+// Sum over the LPR lanes of a row group (groups are aligned lane ranges;
+// every lane of the group must be active).
 template <int LPR, typename U>
 __device__ __forceinline__ U group_sum(U x) {
-#pragma unroll
-    for (int o = LPR / 2; o > 0; o >>= 1) x += __shfl_xor(x, o, kWave);
-    return x;
+    return group_sum_from<LPR / 2, LPR>(x);
+}
+
+template <int O, typename U>
+__device__ __forceinline__ U group_min_from(U x) {
+    if constexpr (O == 0) {
+        return x;
+    } else {
+        const U y = lane_swap<O>(x);
+        x = (y < x) ? y : x;
+        return group_min_from<O / 2>(x);
+    }
 }
 
 template <int LPR, typename U>
 __device__ __forceinline__ U group_min(U x) {
-#pragma unroll
-    for (int o = LPR / 2; o > 0; o >>= 1) {
-        U y = __shfl_xor(x, o, kWave);
-        x = (y < x) ? y : x;
-    }
-    return x;
+    return group_min_from<LPR / 2>(x);
 }
 
 // Tile assignment over the 8 XCDs (workgroups are dispatched round-robin:

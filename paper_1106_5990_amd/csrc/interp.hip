@@ -80,7 +80,8 @@ __device__ __forceinline__ double ls_row(int i, int l, const int* __restrict__ r
             if (cand[u]) ls_insert<T, CALT>(smu, scol, nsel, cal, mm[u], jj[u]);
     }
 
-    // target in FP64: x_i, or x_i - (A x)_i / a_ii (residual form)
+    // target in FP64: x_i, or x_i - (A x)_i / a_ii (residual form, carried
+    // as the distance pass carries it, so that both give the same rows)
     double t[V];
     {
         Frag<T, V> f = load_lane<T, V, C>(X + (size_t)i * K + l * V);
@@ -103,7 +104,7 @@ __device__ __forceinline__ double ls_row(int i, int l, const int* __restrict__ r
                 for (int q = 0; q < V; ++q) y[q] = fma(a, (double)xj.v[q], y[q]);
             }
 #pragma unroll
-            for (int q = 0; q < V; ++q) t[q] = t[q] - y[q] / d;
+            for (int q = 0; q < V; ++q) t[q] = carried<T>(t[q] - y[q] / d);
         }
     }
     return ls_solve<T, K, LPR, CALT>(i, l, t, wd, X, scol, nsel, st, cal, Pcol, Pval, lsv, rstat);

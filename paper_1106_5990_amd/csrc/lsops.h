@@ -180,7 +180,7 @@ __device__ __forceinline__ double ls_solve(int i, int l, const double (&t)[K / L
             double r = t[q];
 #pragma unroll
             for (int a = 0; a < CALT; ++a)
-                if (keep[a]) r -= coef[a] * (double)xs[a].v[q];
+                if (keep[a]) r -= coef[a] * (double)opaque(xs[a].v[q]);
             f = fma(wd[q] * r, r, f);
         }
         val = group_sum<LPR>(f);

@@ -164,6 +164,14 @@ __device__ __forceinline__ void jacobi_row_staged(int i, int l, const int* __res
     store_lane<T, V, C>(Xout + (size_t)i * K + l * V, out);
 }
 
+// The FP64 target entry carried as hi + lo (both panel type; lo is zero for
+// FP64 panels, whose hi is the FP64 value itself).
+template <typename T>
+__device__ __forceinline__ double target64(T hi, T lo) {
+    if constexpr (sizeof(T) == 8) return (double)opaque(hi);
+    else return (double)opaque(hi) + (double)opaque(lo);
+}
+
 template <typename T> struct Guard { static constexpr bool on = false; };
 template <> struct Guard<float> { static constexpr bool on = true; };
 
@@ -199,11 +207,16 @@ __device__ __forceinline__ void algdist_row_sel(int i, int l, const int* __restr
 
     // target t_i; the residual form is built in FP64 (products of two
     // panel-type values are exact there), then rounded to the panel type
-    // for the main pass; the FP64 copy feeds the guard-band recompute.
+    // for the main pass.  The FP64 target that feeds the guard-band
+    // recompute and tout is carried as t + tlo, tlo the panel-type rounding
+    // of the remainder (zero for the plain target and for FP64 panels):
+    // exact where tlo is zero, within 2^-48 relative otherwise.  It is
+    // re-formed at each use so that no FP64 copy stays live through the
+    // entry loop.
     Frag<T, V> t = load_lane<T, V, C>(X + (size_t)i * K + l * V);
-    double t64[V];
+    T tlo[V];
 #pragma unroll
-    for (int q = 0; q < V; ++q) t64[q] = (double)t.v[q];
+    for (int q = 0; q < V; ++q) tlo[q] = T(0);
     if (!plain) {
         double y[V];
 #pragma unroll
@@ -220,8 +233,9 @@ __device__ __forceinline__ void algdist_row_sel(int i, int l, const int* __restr
         if (d != 0.0) {
 #pragma unroll
             for (int q = 0; q < V; ++q) {
-                t64[q] = t64[q] - y[q] / d;
-                t.v[q] = (T)t64[q];
+                const double t64 = (double)t.v[q] - y[q] / d;
+                t.v[q] = (T)t64;
+                if constexpr (sizeof(T) == 4) tlo[q] = (T)(t64 - (double)t.v[q]);
             }
         } else if (l == 0) {
             flag(status, AD_STAT_ZERO_DIAG);
@@ -296,7 +310,7 @@ __device__ __forceinline__ void algdist_row_sel(int i, int l, const int* __restr
                 double a2 = 0.0, b2 = 0.0;
 #pragma unroll
                 for (int q = 0; q < V; ++q) {
-                    const double xq = (double)xj.v[q], tq = t64[q];
+                    const double xq = (double)xj.v[q], tq = target64(t.v[q], tlo[q]);
                     a2 = fma(wd[q] * tq, xq, a2);
                     b2 = fma(wd[q] * xq, xq, b2);
                 }
@@ -306,7 +320,7 @@ __device__ __forceinline__ void algdist_row_sel(int i, int l, const int* __restr
                 double m2 = 0.0;
 #pragma unroll
                 for (int q = 0; q < V; ++q) {
-                    const double r = t64[q] - pd * (double)xj.v[q];
+                    const double r = target64(t.v[q], tlo[q]) - pd * (double)xj.v[q];
                     m2 = fma(wd[q] * r, r, m2);
                 }
                 m = (T)group_sum<LPR>(m2);
@@ -322,7 +336,7 @@ __device__ __forceinline__ void algdist_row_sel(int i, int l, const int* __restr
     }
     if (bad && l == 0) flag(status, AD_STAT_NONFINITE);
 #pragma unroll
-    for (int q = 0; q < V; ++q) tout[q] = t64[q];
+    for (int q = 0; q < V; ++q) tout[q] = (double)t.v[q] + (double)tlo[q];
 
     if (fuse) {
         // second pass: each lane re-reads the mu values it stored, SB
