@@ -102,10 +102,13 @@ __global__ __launch_bounds__(kBlock) void batch_algdist_kernel(
     uint8_t* sm = strong ? strong + m.e0 : nullptr;
     int* nsm = nstrong ? nstrong + m.row0 : nullptr;
     for (int it = 0; it < iter; ++it) {
-        const int i = tl.r0 + it * S::RPB + wv * S::RPW + g;
-        if (i >= tl.r1) break;
-        algdist_row<S, T, K, WEIGHTED>(i, l, m.rp, m.ci, (const T*)m.av, xm, wd, wt, true, mum,
-                                       nullptr, theta, nullptr, sm, nsm, status);
+        const int iw = tl.r0 + it * S::RPB + wv * S::RPW;
+        if (iw >= tl.r1) break;  // whole wavefront
+        const bool ghost = iw + g >= tl.r1;
+        if (ghost && CoopGather<T, V, LPR>::G == 1) break;  // ghosts only serve group loads
+        algdist_row<S, T, K, WEIGHTED>(ghost ? tl.r1 - 1 : iw + g, ghost, l, m.rp, m.ci,
+                                       (const T*)m.av, xm, wd, wt, true, mum, nullptr, theta,
+                                       nullptr, sm, nsm, status);
     }
 }
 

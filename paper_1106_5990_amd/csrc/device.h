@@ -195,6 +195,31 @@ __device__ __forceinline__ U group_min(U x) {
     return group_min_from<LPR / 2>(x);
 }
 
+template <int O, typename U>
+__device__ __forceinline__ U group_max_from(U x) {
+    if constexpr (O == 0) {
+        return x;
+    } else {
+        const U y = lane_swap<O>(x);
+        x = (y > x) ? y : x;
+        return group_max_from<O / 2>(x);
+    }
+}
+
+template <int G, typename U>
+__device__ __forceinline__ U group_max(U x) {
+    return group_max_from<G / 2>(x);
+}
+
+// The 32-bit value of lane k of this lane's aligned group of G (2 or 4)
+// lanes (DPP quad permute).
+template <int G, int k>
+__device__ __forceinline__ int group_bcast(int x) {
+    static_assert((G == 2 || G == 4) && k < G, "groups of 2 or 4 lanes");
+    constexpr int ctrl = (G == 4) ? k * 0x55 : (k | (k << 2) | ((2 + k) << 4) | ((2 + k) << 6));
+    return __builtin_amdgcn_mov_dpp(x, ctrl, 0xF, 0xF, true);
+}
+
 // Tile assignment over the 8 XCDs (workgroups are dispatched round-robin:
 // block b runs on XCD b % 8, each XCD with its own L2).  mode:
 //   0      tile = block index: consecutive tiles on different XCDs;
@@ -229,11 +254,23 @@ __device__ __forceinline__ void flag(unsigned* status, unsigned bit) {
 // splitmix64 (Steele, Lea, Flood 2014): state += 0x9e3779b97f4a7c15, then
 // the xor-shift-multiply finaliser.  Output number c + 1 of the generator
 // seeded with s is finalise(s + (c + 1) * gamma).
-__device__ __forceinline__ uint64_t splitmix64_at(uint64_t seed, uint64_t c) {
-    uint64_t z = seed + (c + 1ull) * 0x9e3779b97f4a7c15ull;
+constexpr uint64_t kSplitmixGamma = 0x9e3779b97f4a7c15ull;
+
+// The output mix applied to the state z.
+__device__ __forceinline__ uint64_t splitmix64_mix(uint64_t z) {
     z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
     z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
     return z ^ (z >> 31);
+}
+
+// State before output c; consecutive outputs step it by kSplitmixGamma, so
+// a run of them costs one multiply for the first and an add for each next.
+__device__ __forceinline__ uint64_t splitmix64_state(uint64_t seed, uint64_t c) {
+    return seed + (c + 1ull) * kSplitmixGamma;
+}
+
+__device__ __forceinline__ uint64_t splitmix64_at(uint64_t seed, uint64_t c) {
+    return splitmix64_mix(splitmix64_state(seed, c));
 }
 
 __device__ __forceinline__ double uniform_pm1(uint64_t z) {

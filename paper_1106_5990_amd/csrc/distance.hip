@@ -52,10 +52,13 @@ __global__ __launch_bounds__(kBlock) void algdist_kernel(
     const bool plain = target == AD_TARGET_PLAIN;
 
     for (int it = 0; it < iter; ++it) {
-        const int64_t i64 = tile * rows_per_tile + (int64_t)it * S::RPB + wv * S::RPW + g;
-        if (i64 >= n) break;
-        algdist_row<S, T, K, WEIGHTED>((int)i64, l, rp, ci, av, X, wd, wt, plain, mu, pout, theta,
-                                       fmask, strong, nstrong, status);
+        const int64_t iw = tile * rows_per_tile + (int64_t)it * S::RPB + wv * S::RPW;
+        if (iw >= n) break;  // whole wavefront
+        const int64_t i64 = iw + g;
+        const bool ghost = i64 >= n;
+        if (ghost && CoopGather<T, V, LPR>::G == 1) break;  // ghosts only serve group loads
+        algdist_row<S, T, K, WEIGHTED>(ghost ? n - 1 : (int)i64, ghost, l, rp, ci, av, X, wd, wt,
+                                       plain, mu, pout, theta, fmask, strong, nstrong, status);
     }
 }
 

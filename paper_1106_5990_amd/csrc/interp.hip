@@ -273,10 +273,13 @@ __global__ __launch_bounds__(kBlock) void dist_ls_kernel(
     double fsum = 0.0;
     if (tile >= 0 && tile < ntiles) {
         for (int it = 0; it < iter; ++it) {
-            const int64_t i64 = tile * rows_per_tile + (int64_t)it * S::RPB + wv * S::RPW + g;
-            if (i64 >= n) break;
-            const int i = (int)i64;
-            const bool isF = cf[i] == 0;
+            const int64_t iw = tile * rows_per_tile + (int64_t)it * S::RPB + wv * S::RPW;
+            if (iw >= n) break;  // whole wavefront
+            const int64_t i64 = iw + g;
+            const bool ghost = i64 >= n;
+            if (ghost && CoopGather<T, V, LPR>::G == 1) break;  // ghosts only serve group loads
+            const int i = ghost ? n - 1 : (int)i64;
+            const bool isF = !ghost && cf[i] == 0;
             T smu[CALT];
             int scol[CALT];
             int nsel = 0;
@@ -287,8 +290,8 @@ __global__ __launch_bounds__(kBlock) void dist_ls_kernel(
             }
             double t64[V], d;
             algdist_row_sel<S, T, K, WEIGHTED>(
-                i, l, rp, ci, av, X, wd, wt, plain, mu, nullptr, theta, fmask, strong, nstrong,
-                status,
+                i, ghost, l, rp, ci, av, X, wd, wt, plain, mu, nullptr, theta, fmask, strong,
+                nstrong, status,
                 [&](int j, T m) {
                     if (isF && cf[j] != 0) ls_insert<T, CALT>(smu, scol, nsel, cal, m, j);
                 },
@@ -298,7 +301,7 @@ __global__ __launch_bounds__(kBlock) void dist_ls_kernel(
                 const double v = ls_solve<T, K, LPR, CALT>(i, l, t64, wd, X, scol, nsel, st, cal,
                                                            Pcol, Pval, lsv, rstat);
                 if (l == 0) fsum += v;
-            } else if (l == 0) {
+            } else if (l == 0 && !ghost) {
                 ls_c_row(i, cal, Pcol, Pval, lsv, rstat);
             }
         }

@@ -21,9 +21,9 @@ __global__ __launch_bounds__(kBlock) void tv_init_kernel(int64_t total, int64_t 
     const int64_t base = ((int64_t)blockIdx.x * kBlock + threadIdx.x) * E;
     if (base >= total) return;
     Frag<T, E> f;
+    uint64_t z = splitmix64_state(seed, (uint64_t)(c0 + base));
 #pragma unroll
-    for (int q = 0; q < E; ++q)
-        f.v[q] = (T)uniform_pm1(splitmix64_at(seed, (uint64_t)(c0 + base + q)));
+    for (int q = 0; q < E; ++q, z += kSplitmixGamma) f.v[q] = (T)uniform_pm1(splitmix64_mix(z));
     if (base + E <= total) {
         store_frag<T, E>(X + base, f);
     } else {
@@ -336,6 +336,7 @@ __global__ __launch_bounds__(kBlock) void perm_row_ptr_kernel(int n, const int* 
 // of its entry by binary search over the starts.  colpp = inv[col],
 // valpp = val.
 constexpr int kCopyRows = 64;
+constexpr int kPermUnroll = 4;
 
 template <typename T>
 __global__ __launch_bounds__(kBlock) void permute_entries_kernel(
@@ -355,24 +356,48 @@ __global__ __launch_bounds__(kBlock) void permute_entries_kernel(
     __syncthreads();
     if (rl == 0) return;
     const int b = s_rp[wv][0], e = s_rp[wv][rl];
-    for (int q = b + lane; q < e; q += kWave) {
-        int lo = 0, hi = rl - 1;  // last row whose start is <= q
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (s_rp[wv][mid] <= q) lo = mid;
-            else hi = mid - 1;
+    // kPermUnroll chunks per pass: their loads, searches and inv gathers are
+    // independent and in flight together
+    for (int q0 = b + lane; q0 < e; q0 += kWave * kPermUnroll) {
+        int cc[kPermUnroll], dd[kPermUnroll], jj[kPermUnroll];
+        T vv[kPermUnroll];
+#pragma unroll
+        for (int u = 0; u < kPermUnroll; ++u) {
+            const int q = q0 + u * kWave;
+            cc[u] = (q < e) ? ci[q] : 0;
+            vv[u] = (q < e) ? av[q] : T(0);
         }
-        const int d = s_dst[wv][lo] + (q - s_rp[wv][lo]);
-        colpp[d] = inv[ci[q]];
-        valpp[d] = av[q];
+#pragma unroll
+        for (int u = 0; u < kPermUnroll; ++u) {
+            const int q = q0 + u * kWave;
+            int lo = 0;  // last row whose start is <= q
+#pragma unroll
+            for (int st = kCopyRows / 2; st > 0; st >>= 1) {
+                const int mid = lo + st;
+                if (mid < rl && s_rp[wv][mid] <= q) lo = mid;
+            }
+            dd[u] = s_dst[wv][lo] + (q - s_rp[wv][lo]);
+        }
+#pragma unroll
+        for (int u = 0; u < kPermUnroll; ++u) jj[u] = (q0 + u * kWave < e) ? inv[cc[u]] : 0;
+#pragma unroll
+        for (int u = 0; u < kPermUnroll; ++u)
+            if (q0 + u * kWave < e) {
+                colpp[dd[u]] = jj[u];
+                valpp[dd[u]] = vv[u];
+            }
     }
 }
 
-// Xp[p] = hash start of natural row rowlist[p] (or X0[rowlist[p]] if given);
-// each thread writes kStartChunks consecutive 16-byte chunks (the row-list
-// loads of a thread are independent and in flight together).  K is a power
-// of two: row and column of a panel value come from shifts.
+// Xp[p] = hash start of natural row rowlist[p] (or X0[rowlist[p]] if given).
+// A thread writes kStartChunks 16-byte chunks, chunk h of every thread of
+// the block at consecutive addresses, so each store instruction of a wave
+// fills whole cache lines; the row-list loads of a thread are issued
+// together.  K is a power of two: row and column of a panel value come from
+// shifts.
 constexpr int kStartChunks = 4;
+template <typename T>
+constexpr int kStartLog2E = (sizeof(T) == 4) ? 2 : 1;  // log2 of the values per chunk
 
 template <typename T>
 __global__ __launch_bounds__(kBlock) void start_perm_kernel(int64_t total, int kshift,
@@ -380,29 +405,44 @@ __global__ __launch_bounds__(kBlock) void start_perm_kernel(int64_t total, int k
                                                             uint64_t seed, const T* __restrict__ X0,
                                                             T* __restrict__ Xp) {
     constexpr int E = 16 / sizeof(T);
-    constexpr int N = E * kStartChunks;
-    const int64_t base = ((int64_t)blockIdx.x * kBlock + threadIdx.x) * N;
-    if (base >= total) return;
     const int64_t kmask = ((int64_t)1 << kshift) - 1;
-    int64_t src[N];
+    // a chunk's values lie in one panel row when K >= E (a launch-wide
+    // condition): its source run is contiguous and the hash state is formed
+    // once and stepped by one counter
+    const bool one_row = kshift >= kStartLog2E<T>;
+    int64_t o[kStartChunks], s0[kStartChunks];
 #pragma unroll
-    for (int q = 0; q < N; ++q) {
-        const int64_t c = base + q < total ? base + q : total - 1;
-        src[q] = ((int64_t)rowlist[c >> kshift] << kshift) | (c & kmask);
+    for (int h = 0; h < kStartChunks; ++h) {
+        o[h] = (((int64_t)blockIdx.x * kStartChunks + h) * kBlock + threadIdx.x) * E;
+        const int64_t c = o[h] < total ? o[h] : total - 1;
+        s0[h] = ((int64_t)rowlist[c >> kshift] << kshift) | (c & kmask);
     }
 #pragma unroll
     for (int h = 0; h < kStartChunks; ++h) {
+        if (o[h] >= total) break;
         Frag<T, E> f;
+        if (one_row) {
+            if (X0) {
 #pragma unroll
-        for (int q = 0; q < E; ++q) {
-            const int64_t s = src[h * E + q];
-            f.v[q] = X0 ? X0[s] : (T)uniform_pm1(splitmix64_at(seed, (uint64_t)s));
-        }
-        const int64_t o = base + h * E;
-        if (o + E <= total) {
-            store_frag<T, E>(Xp + o, f);
+                for (int q = 0; q < E; ++q) f.v[q] = X0[s0[h] + q];
+            } else {
+                uint64_t z = splitmix64_state(seed, (uint64_t)s0[h]);
+#pragma unroll
+                for (int q = 0; q < E; ++q, z += kSplitmixGamma)
+                    f.v[q] = (T)uniform_pm1(splitmix64_mix(z));
+            }
         } else {
-            for (int q = 0; q < E && o + q < total; ++q) Xp[o + q] = f.v[q];
+#pragma unroll
+            for (int q = 0; q < E; ++q) {
+                const int64_t c = o[h] + q < total ? o[h] + q : total - 1;
+                const int64_t sq = ((int64_t)rowlist[c >> kshift] << kshift) | (c & kmask);
+                f.v[q] = X0 ? X0[sq] : (T)uniform_pm1(splitmix64_at(seed, (uint64_t)sq));
+            }
+        }
+        if (o[h] + E <= total) {
+            store_frag<T, E>(Xp + o[h], f);
+        } else {
+            for (int q = 0; q < E && o[h] + q < total; ++q) Xp[o[h] + q] = f.v[q];
         }
     }
 }
@@ -555,8 +595,8 @@ int launch_start_perm(int dtype, int n, int K, const int32_t* rowlist, uint64_t 
                       const void* X0, void* Xp, hipStream_t s) {
     const int64_t m = (int64_t)n * K;
     if (m == 0) return AD_OK;
-    const int N = (dtype == AD_F32 ? 4 : 2) * kStartChunks;
-    const unsigned b = (unsigned)(((m + N - 1) / N + kBlock - 1) / kBlock);
+    const int64_t per_block = (int64_t)(dtype == AD_F32 ? 4 : 2) * kStartChunks * kBlock;
+    const unsigned b = (unsigned)((m + per_block - 1) / per_block);
     if (dtype == AD_F32)
         start_perm_kernel<float><<<dim3(b), dim3(kBlock), 0, s>>>(m, log2_of(K), rowlist, seed,
                                                                   (const float*)X0, (float*)Xp);

@@ -172,6 +172,70 @@ __device__ __forceinline__ double target64(T hi, T lo) {
     else return (double)opaque(hi) + (double)opaque(lo);
 }
 
+// Cooperative panel gather for one lane per row (LPR = 1) when a panel row
+// is 32 or 64 bytes: G = 2 or 4 adjacent lanes (rows) load each of their G
+// neighbour rows together -- lane s of the group reads the 16-byte piece s
+// of every one of them, so each load instruction touches one cache line per
+// lane group instead of one per lane -- and the pieces are handed to their
+// owners through LDS.  G = 1: every lane loads its own rows.
+template <typename T, int V, int LPR>
+struct CoopGather {
+    static constexpr int B = V * (int)sizeof(T);
+    static constexpr int G = (LPR == 1 && (B == 32 || B == 64)) ? B / 16 : 1;
+};
+
+template <int G, int U, int k>
+__device__ __forceinline__ void coop_bcast_cols(const int (&jj)[U], int (&jk)[U]) {
+#pragma unroll
+    for (int u = 0; u < U; ++u) jk[u] = group_bcast<G, k>(jj[u]);
+}
+
+// Every lane of the aligned group of G lanes must be active.  LDS slot of
+// piece p of the row of lane r: p * 64 + (r ^ p) (16-byte units), which keeps
+// both the stores (fixed k) and the loads (fixed p) free of bank conflicts.
+template <typename T, int K, int V, int U, int G>
+__device__ __forceinline__ void coop_gather(const T* __restrict__ X, const int (&jj)[U],
+                                            Frag<T, V> (&xs)[U]) {
+    typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
+    constexpr int CP = 16 / (int)sizeof(T);  // panel entries per piece
+    static_assert(G * CP == V, "a lane's row is G pieces");
+    __shared__ u32x4 buf[kWavesPerBlock][U][G * kWave];
+    const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
+    const int s = lane & (G - 1), base = lane & ~(G - 1);
+    u32x4 pc[U][G];
+    int jk[U];
+    coop_bcast_cols<G, U, 0>(jj, jk);
+#pragma unroll
+    for (int u = 0; u < U; ++u) pc[u][0] = *(const u32x4*)(X + (size_t)jk[u] * K + s * CP);
+    coop_bcast_cols<G, U, 1>(jj, jk);
+#pragma unroll
+    for (int u = 0; u < U; ++u) pc[u][1] = *(const u32x4*)(X + (size_t)jk[u] * K + s * CP);
+    if constexpr (G == 4) {
+        coop_bcast_cols<G, U, 2>(jj, jk);
+#pragma unroll
+        for (int u = 0; u < U; ++u) pc[u][2] = *(const u32x4*)(X + (size_t)jk[u] * K + s * CP);
+        coop_bcast_cols<G, U, 3>(jj, jk);
+#pragma unroll
+        for (int u = 0; u < U; ++u) pc[u][3] = *(const u32x4*)(X + (size_t)jk[u] * K + s * CP);
+    }
+    wave_lds_sync();  // the previous step's reads of the slots are done
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+        for (int k = 0; k < G; ++k) buf[wv][u][s * kWave + ((base + k) ^ s)] = pc[u][k];
+    wave_lds_sync();
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+        for (int p = 0; p < G; ++p) {
+            const u32x4 w = buf[wv][u][p * kWave + (lane ^ p)];
+            typedef T tvec __attribute__((ext_vector_type(CP)));
+            const tvec v = __builtin_bit_cast(tvec, w);
+#pragma unroll
+            for (int q = 0; q < CP; ++q) xs[u].v[p * CP + q] = v[q];
+        }
+}
+
 template <typename T> struct Guard { static constexpr bool on = false; };
 template <> struct Guard<float> { static constexpr bool on = true; };
 
@@ -189,9 +253,12 @@ __device__ __forceinline__ T ratio(T a, T b) {
 // sel(j, mu_ij) is called for every off-diagonal entry in CSR order with
 // the group-uniform distance (the fused LS kernel picks its C-neighbours
 // there); tout receives the FP64 target and dout the diagonal value (0 when
-// absent; only looked for with the residual target).
+// absent; only looked for with the residual target).  A ghost row (a lane
+// past the end of the rows, i clamped to a valid row) has no entries and
+// writes nothing, but takes its part in the cooperative panel loads.
 template <typename S, typename T, int K, bool WEIGHTED, typename Sel>
-__device__ __forceinline__ void algdist_row_sel(int i, int l, const int* __restrict__ rp,
+__device__ __forceinline__ void algdist_row_sel(int i, bool ghost, int l,
+                                                const int* __restrict__ rp,
                                                 const int* __restrict__ ci,
                                                 const T* __restrict__ av, const T* __restrict__ X,
                                                 const double (&wd)[S::V], const T (&wt)[S::V],
@@ -203,7 +270,7 @@ __device__ __forceinline__ void algdist_row_sel(int i, int l, const int* __restr
                                                 Sel&& sel, double (&tout)[S::V], double& dout) {
     constexpr int V = S::V, C = S::C, LPR = S::LPR;
     const bool fuse = strong != nullptr;
-    const int e0 = rp[i], e1 = rp[i + 1];
+    const int e0 = rp[i], e1 = ghost ? e0 : rp[i + 1];
 
     // target t_i; the residual form is built in FP64 (products of two
     // panel-type values are exact there), then rounded to the panel type
@@ -237,7 +304,7 @@ __device__ __forceinline__ void algdist_row_sel(int i, int l, const int* __restr
                 t.v[q] = (T)t64;
                 if constexpr (sizeof(T) == 4) tlo[q] = (T)(t64 - (double)t.v[q]);
             }
-        } else if (l == 0) {
+        } else if (l == 0 && !ghost) {
             flag(status, AD_STAT_ZERO_DIAG);
         }
         dout = d;
@@ -258,19 +325,27 @@ __device__ __forceinline__ void algdist_row_sel(int i, int l, const int* __restr
     T mmin = (T)INFINITY;
     bool bad = false;
     // U edges per step: their column and panel loads are issued together
-    constexpr int U = (V >= 16) ? 2 : 4;
+    constexpr int G = CoopGather<T, V, LPR>::G;
+    constexpr int U = (G > 1) ? 8 / G : (V >= 16) ? 2 : 4;
     // the next step's column indices are loaded while this step's panel
     // rows are in flight
     int jn[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) jn[u] = (e0 + u < e1) ? ci[e0 + u] : i;
-    for (int eb = e0; eb < e1; eb += U) {
+    // with the cooperative gather the G rows of a lane group step together
+    int nsteps = 0;
+    if constexpr (G > 1) nsteps = group_max<G>((e1 - e0 + U - 1) / U);
+    for (int eb = e0, st = 0; (G > 1) ? (st < nsteps) : (eb < e1); eb += U, ++st) {
         int jj[U];
         Frag<T, V> xs[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) jj[u] = jn[u];
+        if constexpr (G > 1) {
+            coop_gather<T, K, V, U, G>(X, jj, xs);
+        } else {
 #pragma unroll
-        for (int u = 0; u < U; ++u) xs[u] = load_lane<T, V, C>(X + (size_t)jj[u] * K + l * V);
+            for (int u = 0; u < U; ++u) xs[u] = load_lane<T, V, C>(X + (size_t)jj[u] * K + l * V);
+        }
 #pragma unroll
         for (int u = 0; u < U; ++u) jn[u] = (eb + U + u < e1) ? ci[eb + U + u] : i;
 #pragma unroll
@@ -370,12 +445,12 @@ __device__ __forceinline__ void algdist_row_sel(int i, int l, const int* __restr
             }
         }
         cnt = group_sum<LPR>(cnt);
-        if (l == 0 && nstrong) nstrong[i] = cnt;
+        if (l == 0 && nstrong && !ghost) nstrong[i] = cnt;
     }
 }
 
 template <typename S, typename T, int K, bool WEIGHTED>
-__device__ __forceinline__ void algdist_row(int i, int l, const int* __restrict__ rp,
+__device__ __forceinline__ void algdist_row(int i, bool ghost, int l, const int* __restrict__ rp,
                                             const int* __restrict__ ci, const T* __restrict__ av,
                                             const T* __restrict__ X, const double (&wd)[S::V],
                                             const T (&wt)[S::V], bool plain, T* __restrict__ mu,
@@ -384,8 +459,8 @@ __device__ __forceinline__ void algdist_row(int i, int l, const int* __restrict_
                                             uint8_t* __restrict__ strong, int* __restrict__ nstrong,
                                             unsigned* status) {
     double t64[S::V], d;
-    algdist_row_sel<S, T, K, WEIGHTED>(i, l, rp, ci, av, X, wd, wt, plain, mu, pout, theta, fmask,
-                                       strong, nstrong, status, [](int, T) {}, t64, d);
+    algdist_row_sel<S, T, K, WEIGHTED>(i, ghost, l, rp, ci, av, X, wd, wt, plain, mu, pout, theta,
+                                       fmask, strong, nstrong, status, [](int, T) {}, t64, d);
 }
 
 // ---------------------------------------------------------------- edge-parallel distances
