@@ -316,8 +316,7 @@ static int gs_sweeps(ad_handle h, const ad_csr* A, int K, uint64_t seed, const v
     const size_t o_colp = req.add(sizeof(int32_t) * (size_t)A->nnz);
     const size_t o_valp = req.add(dsize(dt) * (size_t)A->nnz);
     const size_t o_seg = req.add(sizeof(int32_t) * (ncolors + 2));
-    const size_t o_cnt = req.add(sizeof(int32_t) * (size_t)(ncolors + 1) * nblk);
-    const size_t o_bs = req.add(sizeof(int32_t) * (size_t)perm_scan_blocks(n));
+    const size_t o_cnt = req.add(sizeof(int32_t) * 2 * (size_t)(ncolors + 1) * nblk);
     int rc;
     if ((rc = ws_reserve(h, req.off))) return fail(h, rc, "workspace of %zu bytes", req.off);
     char* ws = (char*)h->ws;
@@ -327,9 +326,10 @@ static int gs_sweeps(ad_handle h, const ad_csr* A, int K, uint64_t seed, const v
     PermCsr pc{n, rowlist, seg, (int32_t*)(ws + o_rpp), (int32_t*)(ws + o_colp), ws + o_valp};
     {
         TimedScope ts(h, "color_partition", s);
-        rc = launch_color_partition(n, color, ncolors, rowlist, (int32_t*)(ws + o_inv), seg,
-                                    (int32_t*)(ws + o_cnt), nblk, h->status, s);
-        if (!rc) rc = launch_perm_setup(dt, A, pc, (int32_t*)(ws + o_inv), (int32_t*)(ws + o_bs), s);
+        rc = launch_color_partition(n, color, ncolors, A->row_ptr, rowlist, (int32_t*)(ws + o_inv),
+                                    seg, (int32_t*)(ws + o_cnt), nblk, (int32_t*)(ws + o_rpp),
+                                    h->status, s);
+        if (!rc) rc = launch_perm_setup(dt, A, pc, (int32_t*)(ws + o_inv), s);
         if (rc) return fail(h, rc, "colour partition launch");
     }
     {

@@ -162,14 +162,13 @@ int autotune(ad_handle h, const ad_csr* A, int K, int relax, const int32_t* colo
         int32_t* colp = (int32_t*)sc.get(sizeof(int32_t) * (size_t)A->nnz);
         void* valp = sc.get(vs * (size_t)A->nnz);
         int32_t* seg = (int32_t*)sc.get(sizeof(int32_t) * (ncolors + 2));
-        int32_t* cnt = (int32_t*)sc.get(sizeof(int32_t) * (size_t)(ncolors + 1) * nblk);
-        int32_t* bsum = (int32_t*)sc.get(sizeof(int32_t) * (size_t)perm_scan_blocks(n));
-        if (!rowlist || !inv || !rpp || !colp || !valp || !seg || !cnt || !bsum) return AD_ENOMEM;
-        if ((rc = launch_color_partition(n, color, ncolors, rowlist, inv, seg, cnt, nblk, h->status,
-                                         s)))
+        int32_t* cnt = (int32_t*)sc.get(sizeof(int32_t) * 2 * (size_t)(ncolors + 1) * nblk);
+        if (!rowlist || !inv || !rpp || !colp || !valp || !seg || !cnt) return AD_ENOMEM;
+        if ((rc = launch_color_partition(n, color, ncolors, A->row_ptr, rowlist, inv, seg, cnt,
+                                         nblk, rpp, h->status, s)))
             return rc;
         pc = PermCsr{n, rowlist, seg, rpp, colp, valp};
-        if ((rc = launch_perm_setup(dt, A, pc, inv, bsum, s))) return rc;
+        if ((rc = launch_perm_setup(dt, A, pc, inv, s))) return rc;
     }
     int32_t* Pc = nullptr;
     double *Pv = nullptr, *ls = nullptr, *bs = nullptr;

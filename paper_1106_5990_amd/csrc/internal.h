@@ -136,10 +136,12 @@ int launch_jacobi(int dtype, int K, const ad_csr* A, const void* Xin, void* Xout
 // Builds the colour-sorted row list: rowlist[n], its inverse inv[n] (may be
 // NULL) and seg[ncolors + 2]
 // (seg[c]..seg[c+1] are the rows of colour c; seg[ncolors]..seg[ncolors+1]
-// the rows with an invalid colour).  counts: (ncolors+1) * nblocks ints.
-int launch_color_partition(int n, const int32_t* color, int ncolors, int32_t* rowlist,
-                           int32_t* inv, int32_t* seg, int32_t* counts, int nblocks,
-                           unsigned* status, hipStream_t s);
+// the rows with an invalid colour).  With rpp (n + 1 ints, may be NULL) it
+// also writes the row pointers of the colour-major copy of the CSR whose
+// row pointers are rp.  counts: 2 * (ncolors+1) * nblocks ints.
+int launch_color_partition(int n, const int32_t* color, int ncolors, const int32_t* rp,
+                           int32_t* rowlist, int32_t* inv, int32_t* seg, int32_t* counts,
+                           int nblocks, int32_t* rpp, unsigned* status, hipStream_t s);
 int color_partition_blocks(int n);
 // Colour-major copy of a CSR for the colour phases: permuted row p is natural
 // row rowlist[p]; its entries rpp[p]..rpp[p+1] keep their CSR order with
@@ -152,9 +154,7 @@ struct PermCsr {
     const int32_t* colpp;    // nnz
     const void* valpp;       // nnz values of the CSR's dtype
 };
-int perm_scan_blocks(int n);
-int launch_perm_setup(int dtype, const ad_csr* A, PermCsr& P, int32_t* inv, int32_t* bsum,
-                      hipStream_t s);
+int launch_perm_setup(int dtype, const ad_csr* A, PermCsr& P, int32_t* inv, hipStream_t s);
 int launch_gs_phase_perm(int dtype, int K, const PermCsr& P, int c, int ncolors, const void* Xold,
                          void* Xnew, void* Xnat, int write_perm, unsigned* status,
                          const LaunchCfg& cfg, hipStream_t s);

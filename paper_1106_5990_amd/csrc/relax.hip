@@ -120,8 +120,12 @@ int launch_jacobi(int dtype, int K, const ad_csr* A, const void* Xin, void* Xout
 // ---------------------------------------------------------------- colour partition
 // Stable partition of the rows by colour: rows of colour 0 first (in index
 // order), then colour 1, ..., then rows with an invalid colour.  Three
-// launches: per-block class counts, one exclusive scan of the class-major
-// count table, per-block scatter with wave ballots for stable ranks.
+// launches: per-block class counts (and class sums of the row lengths), one
+// exclusive scan of the class-major tables, per-block scatter with wave
+// ballots for stable ranks.  With the row lengths the scatter also writes
+// the colour-major row pointers: the entries before a permuted row are
+// those of the lower classes plus those of the same class's earlier rows,
+// which is the same class-major scan over the lengths.
 constexpr int kPartRows = 1024;  // rows per partition block (4 per thread)
 constexpr int kMaxColors = 64;
 
@@ -129,149 +133,6 @@ int color_partition_blocks(int n) { return (n + kPartRows - 1) / kPartRows; }
 
 __device__ __forceinline__ int color_class(int c, int nc) {
     return ((unsigned)c < (unsigned)nc) ? c : nc;
-}
-
-__global__ __launch_bounds__(kBlock) void color_count_kernel(int n, const int* __restrict__ color,
-                                                             int nc, int* __restrict__ counts,
-                                                             int nblocks) {
-    __shared__ int cnt[kMaxColors + 1];
-    for (int q = threadIdx.x; q <= nc; q += kBlock) cnt[q] = 0;
-    __syncthreads();
-    const int base = blockIdx.x * kPartRows;
-    for (int k = 0; k < kPartRows / kBlock; ++k) {
-        const int r = base + k * kBlock + threadIdx.x;
-        if (r < n) atomicAdd(&cnt[color_class(color[r], nc)], 1);
-    }
-    __syncthreads();
-    for (int q = threadIdx.x; q <= nc; q += kBlock) counts[(size_t)q * nblocks + blockIdx.x] = cnt[q];
-}
-
-// In-place exclusive scan of a[0 .. m) by one workgroup of 1024 threads
-// (contiguous chunks per thread, Hillis-Steele over the chunk sums).
-// Returns the total.
-__device__ int scan_1024(int* __restrict__ a, int m) {
-    __shared__ int part[1024];
-    const int t = threadIdx.x;
-    const int chunk = (m + 1023) / 1024;
-    const int b = t * chunk, e = min(m, b + chunk);
-    int s = 0;
-    for (int q = b; q < e; ++q) s += a[q];
-    part[t] = s;
-    __syncthreads();
-    for (int o = 1; o < 1024; o <<= 1) {
-        int v = (t >= o) ? part[t - o] : 0;
-        __syncthreads();
-        part[t] += v;
-        __syncthreads();
-    }
-    int run = (t > 0) ? part[t - 1] : 0;
-    for (int q = b; q < e; ++q) {
-        int c = a[q];
-        a[q] = run;
-        run += c;
-    }
-    const int total = part[1023];
-    __syncthreads();
-    return total;
-}
-
-// Exclusive scan of the class-major count table, plus seg[q] = scanned
-// value at q * nblocks, seg[nc + 1] = n.
-__global__ __launch_bounds__(1024) void scan_counts_kernel(int* __restrict__ counts, int m,
-                                                           int nblocks, int nc, int n,
-                                                           int* __restrict__ seg) {
-    scan_1024(counts, m);
-    for (int q = threadIdx.x; q <= nc; q += 1024) seg[q] = counts[(size_t)q * nblocks];
-    if (threadIdx.x == 0) seg[nc + 1] = n;
-}
-
-__global__ __launch_bounds__(kBlock) void color_scatter_kernel(int n, const int* __restrict__ color,
-                                                               int nc,
-                                                               const int* __restrict__ offsets,
-                                                               int nblocks,
-                                                               int* __restrict__ rowlist,
-                                                               int* __restrict__ inv,
-                                                               unsigned* status) {
-    __shared__ int base[kMaxColors + 1];
-    __shared__ int wcnt[kWavesPerBlock][kMaxColors + 1];
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    for (int q = threadIdx.x; q <= nc; q += kBlock) base[q] = offsets[(size_t)q * nblocks + blockIdx.x];
-    __syncthreads();
-    const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-    bool bad = false;
-    for (int k = 0; k < kPartRows / kBlock; ++k) {
-        const int r = blockIdx.x * kPartRows + k * kBlock + threadIdx.x;
-        const bool valid = r < n;
-        const int c = valid ? color_class(color[r], nc) : -1;
-        bad |= (valid && c == nc);
-        int rank = 0;
-        for (int q = 0; q <= nc; ++q) {
-            const uint64_t m = __ballot(c == q);
-            if (lane == 0) wcnt[wv][q] = __popcll(m);
-            if (c == q) rank = __popcll(m & lt);
-        }
-        __syncthreads();
-        if (valid) {
-            int pos = base[c] + rank;
-            for (int w = 0; w < wv; ++w) pos += wcnt[w][c];
-            rowlist[pos] = r;
-            if (inv) inv[r] = pos;
-        }
-        __syncthreads();
-        for (int q = threadIdx.x; q <= nc; q += kBlock) {
-            int add = 0;
-            for (int w = 0; w < kWavesPerBlock; ++w) add += wcnt[w][q];
-            base[q] += add;
-        }
-        __syncthreads();
-    }
-    if (bad) flag(status, AD_STAT_BAD_COLOR);
-}
-
-int launch_color_partition(int n, const int32_t* color, int ncolors, int32_t* rowlist,
-                           int32_t* inv, int32_t* seg, int32_t* counts, int nblocks,
-                           unsigned* status, hipStream_t s) {
-    if (n == 0) {
-        AD_HIP(hipMemsetAsync(seg, 0, sizeof(int32_t) * (ncolors + 2), s));
-        return AD_OK;
-    }
-    color_count_kernel<<<dim3(nblocks), dim3(kBlock), 0, s>>>(n, color, ncolors, counts, nblocks);
-    scan_counts_kernel<<<dim3(1), dim3(1024), 0, s>>>(counts, (ncolors + 1) * nblocks, nblocks,
-                                                      ncolors, n, seg);
-    color_scatter_kernel<<<dim3(nblocks), dim3(kBlock), 0, s>>>(n, color, ncolors, counts,
-                                                                nblocks, rowlist, inv, status);
-    AD_HIP(hipGetLastError());
-    return AD_OK;
-}
-
-// ---------------------------------------------------------------- colour-major layout
-// The colour phases run on panels stored colour-major: permuted row p holds
-// natural row rowlist[p], so the rows of one colour are contiguous and every
-// cache line a phase touches holds rows it needs.  A neighbour's permuted
-// index jp is read from colp[e] = inv[col[e]]; "smaller colour" is jp <
-// seg[c] because the segments are in colour order.
-
-// Colour-major CSR: permuted row p holds the entries of natural row
-// rowlist[p] in their CSR order, columns mapped to permuted indices, so a
-// phase reads its rows' entries as one contiguous range.  Row pointers are
-// an exclusive scan of the permuted row lengths in blocks of kScanRows rows
-// (4 consecutive rows per thread): block sums, one scan of the sums, then a
-// block-local scan.
-constexpr int kScanRows = 4 * kBlock;
-
-int perm_scan_blocks(int n) { return (n + kScanRows - 1) / kScanRows; }
-
-__device__ __forceinline__ void perm_lens(int n, const int* __restrict__ rp,
-                                          const int* __restrict__ rowlist, int p0, int (&len)[4]) {
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        const int p = p0 + q;
-        len[q] = 0;
-        if (p < n) {
-            const int i = rowlist[p];
-            len[q] = rp[i + 1] - rp[i];
-        }
-    }
 }
 
 __device__ __forceinline__ int wave_incl_scan(int v) {
@@ -284,49 +145,175 @@ __device__ __forceinline__ int wave_incl_scan(int v) {
     return v;
 }
 
-__global__ __launch_bounds__(kBlock) void perm_len_sums_kernel(int n, const int* __restrict__ rp,
-                                                               const int* __restrict__ rowlist,
-                                                               int* __restrict__ bsum) {
-    __shared__ int wsum[kWavesPerBlock];
-    int len[4];
-    perm_lens(n, rp, rowlist, blockIdx.x * kScanRows + threadIdx.x * 4, len);
-    const int v = wave_incl_scan(len[0] + len[1] + len[2] + len[3]);
-    if ((threadIdx.x & (kWave - 1)) == kWave - 1) wsum[threadIdx.x / kWave] = v;
+// counts[q * nblocks + b]: rows of class q in block b; with rp, lens at
+// counts + (nc + 1) * nblocks: their total row length.
+__global__ __launch_bounds__(kBlock) void color_count_kernel(int n, const int* __restrict__ color,
+                                                             int nc, const int* __restrict__ rp,
+                                                             int* __restrict__ counts,
+                                                             int nblocks) {
+    __shared__ int cnt[kMaxColors + 1];
+    __shared__ int len[kMaxColors + 1];
+    for (int q = threadIdx.x; q <= nc; q += kBlock) {
+        cnt[q] = 0;
+        len[q] = 0;
+    }
     __syncthreads();
-    if (threadIdx.x == 0) {
-        int t = 0;
-        for (int w = 0; w < kWavesPerBlock; ++w) t += wsum[w];
-        bsum[blockIdx.x] = t;
+    const int base = blockIdx.x * kPartRows;
+    for (int k = 0; k < kPartRows / kBlock; ++k) {
+        const int r = base + k * kBlock + threadIdx.x;
+        if (r < n) {
+            const int c = color_class(color[r], nc);
+            atomicAdd(&cnt[c], 1);
+            if (rp) atomicAdd(&len[c], rp[r + 1] - rp[r]);
+        }
+    }
+    __syncthreads();
+    int* lens = counts + (size_t)(nc + 1) * nblocks;
+    for (int q = threadIdx.x; q <= nc; q += kBlock) {
+        counts[(size_t)q * nblocks + blockIdx.x] = cnt[q];
+        if (rp) lens[(size_t)q * nblocks + blockIdx.x] = len[q];
     }
 }
 
-__global__ __launch_bounds__(1024) void scan_block_sums_kernel(int* __restrict__ bsum, int m) {
-    scan_1024(bsum, m);
+// In-place exclusive scan of a[0 .. m) by one workgroup of 1024 threads, in
+// tiles of 1024 (coalesced loads, the next tile's load issued before this
+// tile's scan).  Returns the total.
+__device__ int scan_tiles_1024(int* __restrict__ a, int m) {
+    __shared__ int wtot[1024 / kWave];
+    __shared__ int carry_s;
+    const int t = threadIdx.x, lane = t & (kWave - 1), wv = t / kWave;
+    int carry = 0;
+    int v = (t < m) ? a[t] : 0;
+    for (int b = 0; b < m; b += 1024) {
+        const int vn = (b + 1024 + t < m) ? a[b + 1024 + t] : 0;
+        const int incl = wave_incl_scan(v);
+        if (lane == kWave - 1) wtot[wv] = incl;
+        __syncthreads();
+        int before = 0, tile = 0;
+        for (int w = 0; w < 1024 / kWave; ++w) {
+            const int x = wtot[w];
+            before += (w < wv) ? x : 0;
+            tile += x;
+        }
+        if (b + t < m) a[b + t] = carry + before + incl - v;
+        carry += tile;
+        __syncthreads();
+        v = vn;
+    }
+    if (t == 0) carry_s = carry;
+    __syncthreads();
+    return carry_s;
 }
 
-__global__ __launch_bounds__(kBlock) void perm_row_ptr_kernel(int n, const int* __restrict__ rp,
-                                                              const int* __restrict__ rowlist,
-                                                              const int* __restrict__ boff,
-                                                              int* __restrict__ rpp) {
-    __shared__ int wsum[kWavesPerBlock];
-    const int p0 = blockIdx.x * kScanRows + threadIdx.x * 4;
-    int len[4];
-    perm_lens(n, rp, rowlist, p0, len);
-    const int mine = len[0] + len[1] + len[2] + len[3];
-    const int incl = wave_incl_scan(mine);
-    const int wv = threadIdx.x / kWave;
-    if ((threadIdx.x & (kWave - 1)) == kWave - 1) wsum[wv] = incl;
-    __syncthreads();
-    int off = boff[blockIdx.x] + incl - mine;
-    for (int w = 0; w < wv; ++w) off += wsum[w];
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        const int p = p0 + q;
-        if (p < n) rpp[p] = off;
-        off += len[q];
-        if (p == n - 1) rpp[n] = off;
+// Exclusive scans of the class-major tables; seg[q] = scanned count at
+// q * nblocks, seg[nc + 1] = n, and with the lengths rpp[n] = their total.
+__global__ __launch_bounds__(1024) void scan_counts_kernel(int* __restrict__ counts, int m,
+                                                           int nblocks, int nc, int n,
+                                                           int* __restrict__ seg, int with_lens,
+                                                           int* __restrict__ rpp) {
+    scan_tiles_1024(counts, m);
+    if (with_lens) {
+        const int tot = scan_tiles_1024(counts + m, m);
+        if (threadIdx.x == 0) rpp[n] = tot;
     }
+    for (int q = threadIdx.x; q <= nc; q += 1024) seg[q] = counts[(size_t)q * nblocks];
+    if (threadIdx.x == 0) seg[nc + 1] = n;
 }
+
+__global__ __launch_bounds__(kBlock) void color_scatter_kernel(
+    int n, const int* __restrict__ color, int nc, const int* __restrict__ rp,
+    const int* __restrict__ offsets, int nblocks, int* __restrict__ rowlist,
+    int* __restrict__ inv, int* __restrict__ rpp, unsigned* status) {
+    __shared__ int base[kMaxColors + 1];
+    __shared__ int lbase[kMaxColors + 1];
+    __shared__ int wcnt[kWavesPerBlock][kMaxColors + 1];
+    __shared__ int wlen[kWavesPerBlock][kMaxColors + 1];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const bool with_rp = rpp != nullptr;
+    const int* loff = offsets + (size_t)(nc + 1) * nblocks;
+    for (int q = threadIdx.x; q <= nc; q += kBlock) {
+        base[q] = offsets[(size_t)q * nblocks + blockIdx.x];
+        lbase[q] = with_rp ? loff[(size_t)q * nblocks + blockIdx.x] : 0;
+    }
+    __syncthreads();
+    const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    bool bad = false;
+    for (int k = 0; k < kPartRows / kBlock; ++k) {
+        const int r = blockIdx.x * kPartRows + k * kBlock + threadIdx.x;
+        const bool valid = r < n;
+        const int c = valid ? color_class(color[r], nc) : -1;
+        const int len = (valid && with_rp) ? rp[r + 1] - rp[r] : 0;
+        bad |= (valid && c == nc);
+        int rank = 0, lpre = 0;
+        for (int q = 0; q <= nc; ++q) {
+            const uint64_t m = __ballot(c == q);
+            if (lane == 0) wcnt[wv][q] = __popcll(m);
+            if (c == q) rank = __popcll(m & lt);
+            if (with_rp) {
+                int tot = 0;
+                if (m) {  // wave-uniform: the class is present in this wave
+                    const int x = (c == q) ? len : 0;
+                    const int incl = wave_incl_scan(x);
+                    if (c == q) lpre = incl - x;
+                    tot = __shfl(incl, kWave - 1, kWave);
+                }
+                if (lane == 0) wlen[wv][q] = tot;
+            }
+        }
+        __syncthreads();
+        if (valid) {
+            int pos = base[c] + rank;
+            int off = lbase[c] + lpre;
+            for (int w = 0; w < wv; ++w) {
+                pos += wcnt[w][c];
+                off += with_rp ? wlen[w][c] : 0;
+            }
+            rowlist[pos] = r;
+            if (inv) inv[r] = pos;
+            if (with_rp) rpp[pos] = off;
+        }
+        __syncthreads();
+        for (int q = threadIdx.x; q <= nc; q += kBlock) {
+            int add = 0, ladd = 0;
+            for (int w = 0; w < kWavesPerBlock; ++w) {
+                add += wcnt[w][q];
+                ladd += with_rp ? wlen[w][q] : 0;
+            }
+            base[q] += add;
+            lbase[q] += ladd;
+        }
+        __syncthreads();
+    }
+    if (bad) flag(status, AD_STAT_BAD_COLOR);
+}
+
+int launch_color_partition(int n, const int32_t* color, int ncolors, const int32_t* rp,
+                           int32_t* rowlist, int32_t* inv, int32_t* seg, int32_t* counts,
+                           int nblocks, int32_t* rpp, unsigned* status, hipStream_t s) {
+    if (n == 0) {
+        AD_HIP(hipMemsetAsync(seg, 0, sizeof(int32_t) * (ncolors + 2), s));
+        if (rpp) AD_HIP(hipMemsetAsync(rpp, 0, sizeof(int32_t), s));
+        return AD_OK;
+    }
+    const int* rpu = rpp ? rp : nullptr;
+    color_count_kernel<<<dim3(nblocks), dim3(kBlock), 0, s>>>(n, color, ncolors, rpu, counts,
+                                                              nblocks);
+    scan_counts_kernel<<<dim3(1), dim3(1024), 0, s>>>(counts, (ncolors + 1) * nblocks, nblocks,
+                                                      ncolors, n, seg, rpp ? 1 : 0, rpp);
+    color_scatter_kernel<<<dim3(nblocks), dim3(kBlock), 0, s>>>(
+        n, color, ncolors, rpu, counts, nblocks, rowlist, inv, rpp, status);
+    AD_HIP(hipGetLastError());
+    return AD_OK;
+}
+
+// ---------------------------------------------------------------- colour-major layout
+// The colour phases run on panels stored colour-major: permuted row p holds
+// natural row rowlist[p], so the rows of one colour are contiguous and every
+// cache line a phase touches holds rows it needs.  A neighbour's permuted
+// index jp is read from colp[e] = inv[col[e]]; "smaller colour" is jp <
+// seg[c] because the segments are in colour order.  Permuted row p holds the
+// entries of natural row rowlist[p] in their CSR order (row pointers from
+// the partition), columns mapped to permuted indices.
 
 // Entry copy in natural order, one wavefront per kCopyRows natural rows:
 // the rows' natural and permuted entry starts go to LDS, then the wave
@@ -566,17 +553,11 @@ int launch_gs_phase_perm(int dtype, int K, const PermCsr& P, int c, int ncolors,
     return AD_OK;
 }
 
-// The colour-major row pointers and entries of P (whose rowlist and inverse
-// inv the partition wrote); bsum holds perm_scan_blocks(n) ints.
-int launch_perm_setup(int dtype, const ad_csr* A, PermCsr& P, int32_t* inv, int32_t* bsum,
-                      hipStream_t s) {
+// The colour-major entries of P (whose rowlist, row pointers and inverse inv
+// the partition wrote).
+int launch_perm_setup(int dtype, const ad_csr* A, PermCsr& P, int32_t* inv, hipStream_t s) {
     const int n = A->n;
     if (n == 0) return AD_OK;
-    const unsigned nb = (unsigned)perm_scan_blocks(n);
-    perm_len_sums_kernel<<<dim3(nb), dim3(kBlock), 0, s>>>(n, A->row_ptr, P.rowlist, bsum);
-    scan_block_sums_kernel<<<dim3(1), dim3(1024), 0, s>>>(bsum, (int)nb);
-    perm_row_ptr_kernel<<<dim3(nb), dim3(kBlock), 0, s>>>(n, A->row_ptr, P.rowlist, bsum,
-                                                          (int32_t*)P.rpp);
     const int64_t rows_per_block = (int64_t)kCopyRows * kWavesPerBlock;
     const unsigned cb = (unsigned)((n + rows_per_block - 1) / rows_per_block);
     if (dtype == AD_F32)
