@@ -132,6 +132,19 @@ __device__ __forceinline__ double carried(double x) {
     }
 }
 
+// 1/sqrt(x) for x > 0 in FP64: the hardware estimate refined by two Newton
+// steps y <- y + y (1/2 - (x/2) y^2) (each doubles the correct bits), within
+// a few ulps of the correctly rounded value; tiny x (where the estimate
+// may flush) takes the division.
+__device__ __forceinline__ double rsqrt_fp64(double x) {
+    if (x < 0x1p-1000) return 1.0 / sqrt(x);
+    double y = __builtin_amdgcn_rsq(x);
+    const double hx = 0.5 * x;
+    y = fma(y, fma(-hx * y, y, 0.5), y);
+    y = fma(y, fma(-hx * y, y, 0.5), y);
+    return y;
+}
+
 // The value of partner lane i ^ m(O) for a butterfly level of offset O.
 // Inside a 16-lane row the exchange is a DPP move (no LDS round trip):
 // O = 1, 2 swap lanes within a quad (m = 1, 2), O = 4 mirrors each 8-lane

@@ -174,21 +174,25 @@ __global__ __launch_bounds__(kBlock) void ls_interp_kernel(
 }
 
 // Sum of m block partials by one workgroup of 1024 threads in a fixed order:
-// contiguous per-thread runs, then an in-LDS pairwise tree.
+// thread t adds partials t, t + 1024, ... (coalesced loads, several in
+// flight), then an xor butterfly in each wavefront and the wavefront sums
+// in order.
 __global__ __launch_bounds__(1024) void sum_blocks_kernel(const double* __restrict__ part, int m,
                                                           double* __restrict__ out) {
-    __shared__ double acc[1024];
+    __shared__ double wsum[1024 / kWave];
     const int t = threadIdx.x;
-    const int per = (m + 1023) / 1024;
     double s = 0.0;
-    for (int q = t * per; q < min(m, (t + 1) * per); ++q) s += part[q];
-    acc[t] = s;
+#pragma unroll 8
+    for (int q = t; q < m; q += 1024) s += part[q];
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) s += __shfl_xor(s, o, kWave);
+    if ((t & (kWave - 1)) == 0) wsum[t / kWave] = s;
     __syncthreads();
-    for (int o = 512; o > 0; o >>= 1) {
-        if (t < o) acc[t] += acc[t + o];
-        __syncthreads();
+    if (t == 0) {
+        double tot = 0.0;
+        for (int w = 0; w < 1024 / kWave; ++w) tot += wsum[w];
+        *out = tot;
     }
-    if (t == 0) *out = acc[0];
 }
 
 int ls_interp_blocks(int dtype, int K, int n, const LaunchCfg& cfg) {

@@ -123,8 +123,8 @@ __device__ __forceinline__ double ls_solve(int i, int l, const double (&t)[K / L
         st = st ? st : 1;
     } else {
         // Cholesky (in place, packed lower) in increasing-mu order, drop
-        // rule; the reciprocal of each kept pivot is formed once and the
-        // factor and both triangular solves multiply by it
+        // rule; the reciprocal of each kept pivot (1/sqrt of the pivot) is
+        // formed once and the factor and both triangular solves multiply by it
         double rd[CALT];
 #pragma unroll
         for (int a = 0; a < CALT; ++a) {
@@ -147,9 +147,9 @@ __device__ __forceinline__ double ls_solve(int i, int l, const double (&t)[K / L
                 if (keep[b]) piv -= G[ra + b] * G[ra + b];
             keep[a] = piv > 1e-12 * gaa;
             if (keep[a]) {
-                const double l = sqrt(piv);
-                G[ra + a] = l;
-                rd[a] = 1.0 / l;
+                const double r = rsqrt_fp64(piv);
+                G[ra + a] = piv * r;
+                rd[a] = r;
             } else {
                 G[ra + a] = 1.0;
                 st = st ? st : 2;

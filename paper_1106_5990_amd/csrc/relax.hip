@@ -121,12 +121,14 @@ int launch_jacobi(int dtype, int K, const ad_csr* A, const void* Xin, void* Xout
 // Stable partition of the rows by colour: rows of colour 0 first (in index
 // order), then colour 1, ..., then rows with an invalid colour.  Three
 // launches: per-block class counts (and class sums of the row lengths), one
-// exclusive scan of the class-major tables, per-block scatter with wave
-// ballots for stable ranks.  With the row lengths the scatter also writes
-// the colour-major row pointers: the entries before a permuted row are
-// those of the lower classes plus those of the same class's earlier rows,
-// which is the same class-major scan over the lengths.
-constexpr int kPartRows = 1024;  // rows per partition block (4 per thread)
+// exclusive scan of the class-major tables, per-block scatter.  With the
+// row lengths the scatter also writes the colour-major row pointers: the
+// entries before a permuted row are those of the lower classes plus those
+// of the same class's earlier rows, which is the same class-major scan over
+// the lengths.  A thread holds kPartR consecutive rows of its block; the
+// block works class by class over the classes present in it.
+constexpr int kPartR = 8;                       // consecutive rows per thread
+constexpr int kPartRows = kPartR * kBlock;      // rows per partition block
 constexpr int kMaxColors = 64;
 
 int color_partition_blocks(int n) { return (n + kPartRows - 1) / kPartRows; }
@@ -135,14 +137,60 @@ __device__ __forceinline__ int color_class(int c, int nc) {
     return ((unsigned)c < (unsigned)nc) ? c : nc;
 }
 
-__device__ __forceinline__ int wave_incl_scan(int v) {
+template <typename U>
+__device__ __forceinline__ U wave_incl_scan(U v) {
     const int lane = threadIdx.x & (kWave - 1);
 #pragma unroll
     for (int o = 1; o < kWave; o <<= 1) {
-        const int t = __shfl_up(v, o, kWave);
+        const U t = __shfl_up(v, o, kWave);
         if (lane >= o) v += t;
     }
     return v;
+}
+
+// The thread's rows: class (-1 past the end) and, with rp, length.
+__device__ __forceinline__ void part_rows(int n, const int* __restrict__ color, int nc,
+                                          const int* __restrict__ rp, int (&c)[kPartR],
+                                          int (&len)[kPartR]) {
+    const int r0 = blockIdx.x * kPartRows + threadIdx.x * kPartR;
+    int b[kPartR + 1];
+#pragma unroll
+    for (int k = 0; k < kPartR; ++k) c[k] = (r0 + k < n) ? color_class(color[r0 + k], nc) : -1;
+#pragma unroll
+    for (int k = 0; k <= kPartR; ++k) b[k] = (rp && r0 + k <= n) ? rp[r0 + k] : 0;
+#pragma unroll
+    for (int k = 0; k < kPartR; ++k) len[k] = (c[k] >= 0) ? b[k + 1] - b[k] : 0;
+}
+
+// Marks the classes present in the block (present[0 .. nc] zeroed by the
+// caller and synchronised).
+__device__ __forceinline__ void part_mark(const int (&c)[kPartR], int* present) {
+#pragma unroll
+    for (int k = 0; k < kPartR; ++k)
+        if (c[k] >= 0) present[c[k]] = 1;
+}
+
+// Exclusive scan over the workgroup of a packed (count | length << 32)
+// value; returns the thread's exclusive prefix and sets tot to the total.
+__device__ __forceinline__ uint64_t block_excl_scan(uint64_t v, uint64_t* wtot, uint64_t& tot) {
+    const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
+    const uint64_t incl = wave_incl_scan(v);
+    if (lane == kWave - 1) wtot[wv] = incl;
+    __syncthreads();
+    uint64_t off = incl - v;
+    tot = 0;
+#pragma unroll
+    for (int w = 0; w < kWavesPerBlock; ++w) {
+        const uint64_t x = wtot[w];
+        off += (w < wv) ? x : 0;
+        tot += x;
+    }
+    __syncthreads();
+    return off;
+}
+
+__device__ __forceinline__ uint64_t pack_cl(int cnt, int len) {
+    return (uint64_t)(uint32_t)cnt | ((uint64_t)(uint32_t)len << 32);
 }
 
 // counts[q * nblocks + b]: rows of class q in block b; with rp, lens at
@@ -151,140 +199,149 @@ __global__ __launch_bounds__(kBlock) void color_count_kernel(int n, const int* _
                                                              int nc, const int* __restrict__ rp,
                                                              int* __restrict__ counts,
                                                              int nblocks) {
-    __shared__ int cnt[kMaxColors + 1];
-    __shared__ int len[kMaxColors + 1];
-    for (int q = threadIdx.x; q <= nc; q += kBlock) {
-        cnt[q] = 0;
-        len[q] = 0;
-    }
+    __shared__ int present[kMaxColors + 1];
+    __shared__ uint64_t wtot[kWavesPerBlock];
+    for (int q = threadIdx.x; q <= nc; q += kBlock) present[q] = 0;
+    int c[kPartR], len[kPartR];
+    part_rows(n, color, nc, rp, c, len);
     __syncthreads();
-    const int base = blockIdx.x * kPartRows;
-    for (int k = 0; k < kPartRows / kBlock; ++k) {
-        const int r = base + k * kBlock + threadIdx.x;
-        if (r < n) {
-            const int c = color_class(color[r], nc);
-            atomicAdd(&cnt[c], 1);
-            if (rp) atomicAdd(&len[c], rp[r + 1] - rp[r]);
-        }
-    }
+    part_mark(c, present);
     __syncthreads();
     int* lens = counts + (size_t)(nc + 1) * nblocks;
-    for (int q = threadIdx.x; q <= nc; q += kBlock) {
-        counts[(size_t)q * nblocks + blockIdx.x] = cnt[q];
-        if (rp) lens[(size_t)q * nblocks + blockIdx.x] = len[q];
-    }
-}
-
-// In-place exclusive scan of a[0 .. m) by one workgroup of 1024 threads, in
-// tiles of 1024 (coalesced loads, the next tile's load issued before this
-// tile's scan).  Returns the total.
-__device__ int scan_tiles_1024(int* __restrict__ a, int m) {
-    __shared__ int wtot[1024 / kWave];
-    __shared__ int carry_s;
-    const int t = threadIdx.x, lane = t & (kWave - 1), wv = t / kWave;
-    int carry = 0;
-    int v = (t < m) ? a[t] : 0;
-    for (int b = 0; b < m; b += 1024) {
-        const int vn = (b + 1024 + t < m) ? a[b + 1024 + t] : 0;
-        const int incl = wave_incl_scan(v);
-        if (lane == kWave - 1) wtot[wv] = incl;
-        __syncthreads();
-        int before = 0, tile = 0;
-        for (int w = 0; w < 1024 / kWave; ++w) {
-            const int x = wtot[w];
-            before += (w < wv) ? x : 0;
-            tile += x;
+    for (int q = 0; q <= nc; ++q) {
+        if (!present[q]) {  // block-uniform
+            if (threadIdx.x == 0) {
+                counts[(size_t)q * nblocks + blockIdx.x] = 0;
+                if (rp) lens[(size_t)q * nblocks + blockIdx.x] = 0;
+            }
+            continue;
         }
-        if (b + t < m) a[b + t] = carry + before + incl - v;
-        carry += tile;
-        __syncthreads();
-        v = vn;
+        int tc = 0, tl = 0;
+#pragma unroll
+        for (int k = 0; k < kPartR; ++k)
+            if (c[k] == q) {
+                ++tc;
+                tl += len[k];
+            }
+        uint64_t tot;
+        (void)block_excl_scan(pack_cl(tc, tl), wtot, tot);
+        if (threadIdx.x == 0) {
+            counts[(size_t)q * nblocks + blockIdx.x] = (int)(uint32_t)tot;
+            if (rp) lens[(size_t)q * nblocks + blockIdx.x] = (int)(tot >> 32);
+        }
     }
-    if (t == 0) carry_s = carry;
-    __syncthreads();
-    return carry_s;
 }
 
-// Exclusive scans of the class-major tables; seg[q] = scanned count at
-// q * nblocks, seg[nc + 1] = n, and with the lengths rpp[n] = their total.
+// Exclusive scans of the class-major tables counts[0 .. m) and (with lens)
+// counts[m .. 2m) by one workgroup of 1024 threads, both in one pass: a
+// thread's contiguous run (loads of kScanRun values in flight together,
+// kept in registers) is summed, the run sums (count in the low, length in
+// the high 32 bits of one 64-bit value: neither field can carry, both
+// totals being below 2^31) are scanned across the workgroup, and the run is
+// rewritten.  seg[q] = scanned count at q * nblocks, seg[nc + 1] = n, and
+// with the lengths rpp[n] = their total.
+constexpr int kScanRun = 8;
+
 __global__ __launch_bounds__(1024) void scan_counts_kernel(int* __restrict__ counts, int m,
                                                            int nblocks, int nc, int n,
                                                            int* __restrict__ seg, int with_lens,
                                                            int* __restrict__ rpp) {
-    scan_tiles_1024(counts, m);
-    if (with_lens) {
-        const int tot = scan_tiles_1024(counts + m, m);
-        if (threadIdx.x == 0) rpp[n] = tot;
+    __shared__ uint64_t wtot[1024 / kWave];
+    const int t = threadIdx.x, lane = t & (kWave - 1), wv = t / kWave;
+    int* lens = counts + m;
+    uint64_t carry = 0;
+    // rounds of 1024 * kScanRun entries; thread t takes a contiguous run
+    for (int r0 = 0; r0 < m; r0 += 1024 * kScanRun) {
+        const int b = r0 + t * kScanRun;
+        int vc[kScanRun], vl[kScanRun];
+#pragma unroll
+        for (int k = 0; k < kScanRun; ++k) {
+            vc[k] = (b + k < m) ? counts[b + k] : 0;
+            vl[k] = (with_lens && b + k < m) ? lens[b + k] : 0;
+        }
+        uint64_t run = 0;
+#pragma unroll
+        for (int k = 0; k < kScanRun; ++k) run += pack_cl(vc[k], vl[k]);
+        const uint64_t incl = wave_incl_scan(run);
+        if (lane == kWave - 1) wtot[wv] = incl;
+        __syncthreads();
+        uint64_t off = carry + incl - run, tot = 0;
+        for (int w = 0; w < 1024 / kWave; ++w) {
+            const uint64_t x = wtot[w];
+            off += (w < wv) ? x : 0;
+            tot += x;
+        }
+        int oc = (int)(uint32_t)off, ol = (int)(off >> 32);
+#pragma unroll
+        for (int k = 0; k < kScanRun; ++k)
+            if (b + k < m) {
+                counts[b + k] = oc;
+                oc += vc[k];
+                if (with_lens) {
+                    lens[b + k] = ol;
+                    ol += vl[k];
+                }
+            }
+        carry += tot;
+        __syncthreads();
     }
-    for (int q = threadIdx.x; q <= nc; q += 1024) seg[q] = counts[(size_t)q * nblocks];
-    if (threadIdx.x == 0) seg[nc + 1] = n;
+    if (with_lens && t == 0) rpp[n] = (int)(carry >> 32);
+    for (int q = t; q <= nc; q += 1024) seg[q] = counts[(size_t)q * nblocks];
+    if (t == 0) seg[nc + 1] = n;
 }
 
+// Stable positions and (with rp) entry offsets: per class present in the
+// block, one workgroup scan of the threads' (count, length) gives each
+// thread's start, and its rows of that class follow in order.  A position
+// outside [0, n) is dropped and flagged instead of written.
 __global__ __launch_bounds__(kBlock) void color_scatter_kernel(
     int n, const int* __restrict__ color, int nc, const int* __restrict__ rp,
     const int* __restrict__ offsets, int nblocks, int* __restrict__ rowlist,
     int* __restrict__ inv, int* __restrict__ rpp, unsigned* status) {
-    __shared__ int base[kMaxColors + 1];
-    __shared__ int lbase[kMaxColors + 1];
-    __shared__ int wcnt[kWavesPerBlock][kMaxColors + 1];
-    __shared__ int wlen[kWavesPerBlock][kMaxColors + 1];
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    __shared__ int present[kMaxColors + 1];
+    __shared__ uint64_t wtot[kWavesPerBlock];
     const bool with_rp = rpp != nullptr;
-    const int* loff = offsets + (size_t)(nc + 1) * nblocks;
-    for (int q = threadIdx.x; q <= nc; q += kBlock) {
-        base[q] = offsets[(size_t)q * nblocks + blockIdx.x];
-        lbase[q] = with_rp ? loff[(size_t)q * nblocks + blockIdx.x] : 0;
-    }
+    for (int q = threadIdx.x; q <= nc; q += kBlock) present[q] = 0;
+    int c[kPartR], len[kPartR];
+    part_rows(n, color, nc, with_rp ? rp : nullptr, c, len);
     __syncthreads();
-    const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-    bool bad = false;
-    for (int k = 0; k < kPartRows / kBlock; ++k) {
-        const int r = blockIdx.x * kPartRows + k * kBlock + threadIdx.x;
-        const bool valid = r < n;
-        const int c = valid ? color_class(color[r], nc) : -1;
-        const int len = (valid && with_rp) ? rp[r + 1] - rp[r] : 0;
-        bad |= (valid && c == nc);
-        int rank = 0, lpre = 0;
-        for (int q = 0; q <= nc; ++q) {
-            const uint64_t m = __ballot(c == q);
-            if (lane == 0) wcnt[wv][q] = __popcll(m);
-            if (c == q) rank = __popcll(m & lt);
-            if (with_rp) {
-                int tot = 0;
-                if (m) {  // wave-uniform: the class is present in this wave
-                    const int x = (c == q) ? len : 0;
-                    const int incl = wave_incl_scan(x);
-                    if (c == q) lpre = incl - x;
-                    tot = __shfl(incl, kWave - 1, kWave);
+    part_mark(c, present);
+    __syncthreads();
+    const int* loff = offsets + (size_t)(nc + 1) * nblocks;
+    const int r0 = blockIdx.x * kPartRows + threadIdx.x * kPartR;
+    bool bad = false, oob = false;
+#pragma unroll
+    for (int k = 0; k < kPartR; ++k) bad |= (c[k] == nc);
+    for (int q = 0; q <= nc; ++q) {
+        if (!present[q]) continue;  // block-uniform
+        int tc = 0, tl = 0;
+#pragma unroll
+        for (int k = 0; k < kPartR; ++k)
+            if (c[k] == q) {
+                ++tc;
+                tl += len[k];
+            }
+        uint64_t tot;
+        const uint64_t ex = block_excl_scan(pack_cl(tc, tl), wtot, tot);
+        int pos = offsets[(size_t)q * nblocks + blockIdx.x] + (int)(uint32_t)ex;
+        int off = with_rp ? loff[(size_t)q * nblocks + blockIdx.x] + (int)(ex >> 32) : 0;
+#pragma unroll
+        for (int k = 0; k < kPartR; ++k)
+            if (c[k] == q) {
+                if (pos >= 0 && pos < n) {
+                    rowlist[pos] = r0 + k;
+                    if (inv) inv[r0 + k] = pos;
+                    if (with_rp) rpp[pos] = off;
+                } else {
+                    oob = true;
                 }
-                if (lane == 0) wlen[wv][q] = tot;
+                ++pos;
+                off += len[k];
             }
-        }
-        __syncthreads();
-        if (valid) {
-            int pos = base[c] + rank;
-            int off = lbase[c] + lpre;
-            for (int w = 0; w < wv; ++w) {
-                pos += wcnt[w][c];
-                off += with_rp ? wlen[w][c] : 0;
-            }
-            rowlist[pos] = r;
-            if (inv) inv[r] = pos;
-            if (with_rp) rpp[pos] = off;
-        }
-        __syncthreads();
-        for (int q = threadIdx.x; q <= nc; q += kBlock) {
-            int add = 0, ladd = 0;
-            for (int w = 0; w < kWavesPerBlock; ++w) {
-                add += wcnt[w][q];
-                ladd += with_rp ? wlen[w][q] : 0;
-            }
-            base[q] += add;
-            lbase[q] += ladd;
-        }
-        __syncthreads();
     }
-    if (bad) flag(status, AD_STAT_BAD_COLOR);
+    // an out-of-range position can only come from colours that changed
+    // between the count and scatter launches
+    if (bad || oob) flag(status, AD_STAT_BAD_COLOR);
 }
 
 int launch_color_partition(int n, const int32_t* color, int ncolors, const int32_t* rp,
