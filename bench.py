@@ -162,10 +162,12 @@ def kernel_bytes(wl, s):
             nc_, nnzc = int(rows.sum()), int(deg[rows].sum())
             per.append(nc_ * 4 + nnzc * (4 + s) + panel + nc_ * K * s + nc_ * 4 / wl.sweeps)
         out["gs_phase"] = float(np.mean(per))
-        # colour counts, scatter of the row list, inverse permutation,
-        # permuted row lengths (sums, then pointers) and the entry copy
-        # (columns through the inverse, values)
-        out["color_partition"] = n * 4 * 14 + nnz * (8 + 2 * s)
+        # colours and row pointers read by the count and scatter kernels,
+        # row list, inverse permutation and colour-major row pointers
+        # written, the entry copy's row starts, inverse and permuted starts,
+        # the inverse table once, and the entries (columns, values) read and
+        # written once
+        out["color_partition"] = n * 4 * 11 + nnz * (8 + 2 * s)
         out["tv_init"] = panel + n * 4
     out["algdist"] = (n + 1) * 4 + nnz * 4 + panel + nnz * s + nnz + n * 4
     F = wl.cf == 0
