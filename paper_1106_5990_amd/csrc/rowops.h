@@ -504,6 +504,7 @@ struct EdgeLds {
     int rp[kWavesPerBlock][kEdgeRows + 1];
     OrdBits<T> mn[kWavesPerBlock][kEdgeRows];
     int cnt[kWavesPerBlock][kEdgeRows];
+    T aa[kWavesPerBlock][kEdgeRows];  // S_aa of each row, formed once per row
     T m[kWavesPerBlock][kEdgeKeep][kWave];
     int j[kWavesPerBlock][kEdgeKeep][kWave];
 };
@@ -533,6 +534,15 @@ __device__ __forceinline__ void algdist_edge_rows(
         starts[lane] = rp[r0 + lane];
         L.mn[wv][lane] = ord_bits((T)INFINITY);
         L.cnt[wv][lane] = 0;
+        // S_aa of the row, in the order the per-entry loop would form it
+        const Frag<T, K> t = load_lane<T, K, C>(X + (size_t)(r0 + lane) * K);
+        T saa = T(0);
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const T wtk = WEIGHTED ? (T)w[k] * t.v[k] : t.v[k];
+            saa = fma(wtk, t.v[k], saa);
+        }
+        L.aa[wv][lane] = saa;
     }
     if (lane == 0 && rl > 0) starts[rl] = rp[r0 + rl];
     __syncthreads();
@@ -554,12 +564,12 @@ __device__ __forceinline__ void algdist_edge_rows(
         } else {
             const Frag<T, K> t = load_lane<T, K, C>(X + (size_t)i * K);
             const Frag<T, K> x = load_lane<T, K, C>(X + (size_t)j * K);
-            T sab = T(0), sbb = T(0), saa = T(0);
+            T sab = T(0), sbb = T(0);
+            const T saa = L.aa[wv][row];
 #pragma unroll
             for (int k = 0; k < K; ++k) {
                 const T wk = WEIGHTED ? (T)w[k] : T(1);
                 const T wtk = WEIGHTED ? wk * t.v[k] : t.v[k];
-                saa = fma(wtk, t.v[k], saa);
                 sab = fma(wtk, x.v[k], sab);
                 sbb = fma(WEIGHTED ? wk * x.v[k] : x.v[k], x.v[k], sbb);
             }

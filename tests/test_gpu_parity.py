@@ -106,6 +106,30 @@ def test_colour_gs_fp64_matches_oracle(ncol, K):
     assert ad.status(clear=True) == 0
 
 
+@pytest.mark.parametrize("ncol,used,N", [(64, 64, 101), (5, 2, 73), (7, 7, 9)])
+def test_colour_gs_random_colouring_partition(ncol, used, N):
+    """Random colours (up to the maximum of 64, some classes absent, a few
+    invalid) over several partition blocks with a ragged tail: the colour
+    phases against the oracle."""
+    say("gs f64 random colours ncolors=%d used=%d n=%d" % (ncol, used, N * N))
+    ad = lib()
+    K = 8
+    A = aniso(N)
+    rng = np.random.default_rng(ncol * 1000 + used)
+    pal = np.sort(rng.choice(ncol, used, replace=False)).astype(np.int32)
+    color = pal[rng.integers(0, used, A.n)].astype(np.int32)
+    bad = rng.choice(A.n, max(1, A.n // 500), replace=False)
+    color[bad] = np.where(np.arange(bad.size) % 2 == 0, -3, ncol + 1)
+    ad.status(clear=True)
+    X = ad.setup_testvectors(dev_csr(A, torch.float64), K, seed=31, relax="gs", sweeps=2,
+                             color=torch.as_tensor(color, device="cuda"), ncolors=ncol)
+    want, held = oracle.color_gs(A, oracle.tv_init(A.n, K, 31), color, ncol, 2)
+    assert held == bad.size
+    got = to_np(X)
+    assert np.max(np.abs(got - want)) <= 1e-12 * np.max(np.abs(want))
+    assert ad.status(clear=True) & ad.STAT_BAD_COLOR  # the invalid colours are reported
+
+
 def test_colour_gs_fp32_one_sweep_bound():
     say("gs f32 one sweep")
     ad = lib()
