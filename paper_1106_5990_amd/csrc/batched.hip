@@ -62,12 +62,12 @@ __global__ __launch_bounds__(kBlock) void batch_jacobi_kernel(
     for (int it = 0; it < iter; ++it) {
         const int iw = tl.r0 + it * S::RPB + wv * S::RPW;
         if (iw >= tl.r1) break;  // whole wavefront
-        const int64_t s0 = m.rp[iw];
         const int ie = (iw + S::RPW < tl.r1) ? iw + S::RPW : tl.r1;
-        const int64_t sc = m.rp[ie] - s0;
-        const int cnt = sc < kStageCap ? (int)sc : kStageCap;
+        int64_t s0;
+        int cnt;
         wave_lds_sync();
-        stage_csr(stg, wv, lane, s0, cnt, m.ci, (const T*)m.av);
+        stage_csr(stg, wv, lane, (int64_t)m.rp[iw], (int64_t)m.rp[ie], m.ci, (const T*)m.av, s0,
+                  cnt);
         wave_lds_sync();
         const int i = iw + g;
         if (i >= tl.r1) continue;

@@ -69,16 +69,15 @@ __global__ __launch_bounds__(kBlock) void jacobi_kernel(int n, const int* __rest
     for (int it = 0; it < iter; ++it) {
         const int64_t iw = tile * rows_per_tile + (int64_t)it * S::RPB + wv * S::RPW;
         if (iw >= n) break;  // whole wavefront
-        const int64_t s0 = rp[iw];
         const int64_t ie = (iw + S::RPW < n) ? iw + S::RPW : (int64_t)n;
-        const int64_t sc = rp[ie] - s0;
-        const int cnt = sc < kStageCap ? (int)sc : kStageCap;
+        int64_t a0;
+        int cnt;
         wave_lds_sync();
-        stage_csr(stg, wv, lane, s0, cnt, ci, av);
+        stage_csr(stg, wv, lane, (int64_t)rp[iw], (int64_t)rp[ie], ci, av, a0, cnt);
         wave_lds_sync();
         const int64_t i64 = iw + g;
         if (i64 >= n) continue;
-        jacobi_row_staged<S, T, K>((int)i64, l, rp, ci, av, stg, wv, s0, cnt, Xin, Xout, omega,
+        jacobi_row_staged<S, T, K>((int)i64, l, rp, ci, av, stg, wv, a0, cnt, Xin, Xout, omega,
                                    status);
     }
 }
@@ -534,12 +533,11 @@ __global__ __launch_bounds__(kBlock) void gs_phase_perm_kernel(
         for (int it = 0; it < iter; ++it) {
             const int64_t pw = b0 + tile * rows_per_tile + (int64_t)it * S::RPB + wv * S::RPW;
             if (pw >= b1) break;  // whole wavefront
-            const int64_t s0 = rpp[pw];
             const int64_t pe = (pw + S::RPW < b1) ? pw + S::RPW : (int64_t)b1;
-            const int64_t sc = rpp[pe] - s0;
-            const int cnt = sc < kStageCap ? (int)sc : kStageCap;
+            int64_t s0;
+            int cnt;
             wave_lds_sync();
-            stage_csr(stg, wv, lane, s0, cnt, colpp, valpp);
+            stage_csr(stg, wv, lane, (int64_t)rpp[pw], (int64_t)rpp[pe], colpp, valpp, s0, cnt);
             wave_lds_sync();
             const int64_t p = pw + g;
             if (p >= b1) continue;

@@ -78,7 +78,7 @@ __device__ __forceinline__ void row_spmm(int i, int e0, int e1, const int* __res
 constexpr int kStageCap = 512;  // entries per wavefront
 
 template <typename T>
-struct CsrStage {
+struct alignas(16) CsrStage {
     int ci[kWavesPerBlock][kStageCap];
     T av[kWavesPerBlock][kStageCap];
 };
@@ -90,14 +90,36 @@ __device__ __forceinline__ void wave_lds_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Copies entries [s0, s0 + cnt), cnt <= kStageCap, of (ci, av) into the
-// wave's region (entry g at index g - s0), one entry per lane per load.
+// Copies the wave's entries [s0, s1) of (ci, av) into its region: entries
+// [a0, a0 + cnt) with entry g at index g - a0, cnt <= kStageCap.  When both
+// arrays are 16-byte aligned, a0 is s0 rounded down to a multiple of 4 and
+// whole 4-entry chunks move as 16-byte loads and stores (the tail entry by
+// entry); otherwise a0 = s0 and every entry is its own load.
 template <typename T>
-__device__ __forceinline__ void stage_csr(CsrStage<T>& L, int wv, int lane, int64_t s0, int cnt,
-                                          const int* __restrict__ ci, const T* __restrict__ av) {
-    for (int q = lane; q < cnt; q += kWave) {
-        L.ci[wv][q] = ci[s0 + q];
-        L.av[wv][q] = av[s0 + q];
+__device__ __forceinline__ void stage_csr(CsrStage<T>& L, int wv, int lane, int64_t s0,
+                                          int64_t s1, const int* __restrict__ ci,
+                                          const T* __restrict__ av, int64_t& a0, int& cnt) {
+    const bool vec = (((uintptr_t)ci | (uintptr_t)av) & 15) == 0;  // launch-wide
+    a0 = vec ? (s0 & ~(int64_t)3) : s0;
+    const int64_t sc = s1 - a0;
+    cnt = sc < kStageCap ? (int)sc : kStageCap;
+    int q0 = 0;
+    if (vec) {
+        typedef int i4 __attribute__((ext_vector_type(4)));
+        constexpr int E = 16 / (int)sizeof(T);
+        typedef T tv __attribute__((ext_vector_type(E)));
+        const int nch = cnt / 4;
+        for (int c = lane; c < nch; c += kWave) {
+            *(i4*)&L.ci[wv][4 * c] = *(const i4*)(ci + a0 + 4 * c);
+#pragma unroll
+            for (int h = 0; h < 4 / E; ++h)
+                *(tv*)&L.av[wv][4 * c + h * E] = *(const tv*)(av + a0 + 4 * c + h * E);
+        }
+        q0 = 4 * nch;
+    }
+    for (int q = q0 + lane; q < cnt; q += kWave) {
+        L.ci[wv][q] = ci[a0 + q];
+        L.av[wv][q] = av[a0 + q];
     }
 }
 
