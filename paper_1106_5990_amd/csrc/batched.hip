@@ -76,7 +76,7 @@ __global__ __launch_bounds__(kBlock) void batch_jacobi_kernel(
     }
 }
 
-template <typename T, int K, int LPR, bool WEIGHTED>
+template <typename T, int K, int LPR, bool WEIGHTED, int UN>
 __global__ __launch_bounds__(kBlock) void batch_algdist_kernel(
     const BatchMat* __restrict__ mats, const BatchTile* __restrict__ tiles, int64_t ntiles,
     int iter, int xcd, const T* __restrict__ X, const double* __restrict__ w, T* __restrict__ mu,
@@ -106,7 +106,7 @@ __global__ __launch_bounds__(kBlock) void batch_algdist_kernel(
         if (iw >= tl.r1) break;  // whole wavefront
         const bool ghost = iw + g >= tl.r1;
         if (ghost && CoopGather<T, V, LPR>::G == 1) break;  // ghosts only serve group loads
-        algdist_row<S, T, K, WEIGHTED>(ghost ? tl.r1 - 1 : iw + g, ghost, l, m.rp, m.ci,
+        algdist_row<S, T, K, WEIGHTED, UN>(ghost ? tl.r1 - 1 : iw + g, ghost, l, m.rp, m.ci,
                                        (const T*)m.av, xm, wd, wt, true, mum, nullptr, theta,
                                        nullptr, sm, nsm, status);
     }
@@ -181,6 +181,7 @@ struct Seq {
     const BatchTile* tiles;   // relaxation tiles
     const BatchTile* dtiles;  // distance tiles
     int diter;                // row steps per distance tile (row-group form)
+    bool long_rows;           // at least 16 stored entries per row on average
     void *X, *W, *mu;
     uint8_t* strong;
     int32_t* nstrong;
@@ -203,14 +204,17 @@ template <typename T, int K, int LPR>
 void seq_dist_rows(const Seq& q, hipStream_t s) {
     TimedScope ts(q.h, "batch_algdist", s);
     const int grid = grid_for_tiles(q.ndist, q.dxcd);
-    if (q.w)
-        batch_algdist_kernel<T, K, LPR, true><<<dim3(grid), dim3(kBlock), 0, s>>>(
-            q.mats, q.dtiles, q.ndist, q.diter, q.dxcd, (const T*)q.X, q.w, (T*)q.mu, q.theta,
-            q.strong, q.nstrong, q.status);
-    else
-        batch_algdist_kernel<T, K, LPR, false><<<dim3(grid), dim3(kBlock), 0, s>>>(
-            q.mats, q.dtiles, q.ndist, q.diter, q.dxcd, (const T*)q.X, nullptr, (T*)q.mu,
-            q.theta, q.strong, q.nstrong, q.status);
+    dist_unroll<T, K, LPR>(q.long_rows, [&](auto uc) {
+        constexpr int UN = decltype(uc)::value;
+        if (q.w)
+            batch_algdist_kernel<T, K, LPR, true, UN><<<dim3(grid), dim3(kBlock), 0, s>>>(
+                q.mats, q.dtiles, q.ndist, q.diter, q.dxcd, (const T*)q.X, q.w, (T*)q.mu, q.theta,
+                q.strong, q.nstrong, q.status);
+        else
+            batch_algdist_kernel<T, K, LPR, false, UN><<<dim3(grid), dim3(kBlock), 0, s>>>(
+                q.mats, q.dtiles, q.ndist, q.diter, q.dxcd, (const T*)q.X, nullptr, (T*)q.mu,
+                q.theta, q.strong, q.nstrong, q.status);
+    });
 }
 
 template <typename T, int K>
@@ -402,6 +406,7 @@ int launch_batched(ad_handle h, int nmat, const ad_csr* As, int K, uint64_t seed
     q.rows = rows;
     q.ntiles = ntiles;
     q.ndist = ndist;
+    q.long_rows = batch_bucket(nmat, As) >= 2;
     q.seed = seed;
     q.omega = omega;
     q.theta = theta;

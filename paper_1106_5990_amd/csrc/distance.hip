@@ -25,7 +25,7 @@
 
 namespace ad {
 
-template <typename T, int K, int LPR, bool WEIGHTED>
+template <typename T, int K, int LPR, bool WEIGHTED, int UN>
 __global__ __launch_bounds__(kBlock) void algdist_kernel(
     int n, const int* __restrict__ rp, const int* __restrict__ ci, const T* __restrict__ av,
     const T* __restrict__ X, const double* __restrict__ w, int target, T* __restrict__ mu,
@@ -57,8 +57,9 @@ __global__ __launch_bounds__(kBlock) void algdist_kernel(
         const int64_t i64 = iw + g;
         const bool ghost = i64 >= n;
         if (ghost && CoopGather<T, V, LPR>::G == 1) break;  // ghosts only serve group loads
-        algdist_row<S, T, K, WEIGHTED>(ghost ? n - 1 : (int)i64, ghost, l, rp, ci, av, X, wd, wt,
-                                       plain, mu, pout, theta, fmask, strong, nstrong, status);
+        algdist_row<S, T, K, WEIGHTED, UN>(ghost ? n - 1 : (int)i64, ghost, l, rp, ci, av, X, wd,
+                                           wt, plain, mu, pout, theta, fmask, strong, nstrong,
+                                           status);
     }
 }
 
@@ -70,14 +71,17 @@ static void algdist_go(const ad_csr* A, const void* X, const double* w, int targ
     const int64_t rpt = (int64_t)S::RPB * cfg.iter;
     const int64_t ntiles = (A->n + rpt - 1) / rpt;
     const int grid = grid_for_tiles(ntiles, cfg.xcd_map);
-    if (w)
-        algdist_kernel<T, K, LPR, true><<<dim3(grid), dim3(kBlock), 0, s>>>(
-            A->n, A->row_ptr, A->col, (const T*)A->val, (const T*)X, w, target, (T*)mu, p, theta,
-            fmask, strong, nstrong, cfg.iter, cfg.xcd_map, st);
-    else
-        algdist_kernel<T, K, LPR, false><<<dim3(grid), dim3(kBlock), 0, s>>>(
-            A->n, A->row_ptr, A->col, (const T*)A->val, (const T*)X, w, target, (T*)mu, p, theta,
-            fmask, strong, nstrong, cfg.iter, cfg.xcd_map, st);
+    dist_unroll<T, K, LPR>(nnz_bucket(A->nnz, A->n) >= 2, [&](auto uc) {
+        constexpr int UN = decltype(uc)::value;
+        if (w)
+            algdist_kernel<T, K, LPR, true, UN><<<dim3(grid), dim3(kBlock), 0, s>>>(
+                A->n, A->row_ptr, A->col, (const T*)A->val, (const T*)X, w, target, (T*)mu, p,
+                theta, fmask, strong, nstrong, cfg.iter, cfg.xcd_map, st);
+        else
+            algdist_kernel<T, K, LPR, false, UN><<<dim3(grid), dim3(kBlock), 0, s>>>(
+                A->n, A->row_ptr, A->col, (const T*)A->val, (const T*)X, w, target, (T*)mu, p,
+                theta, fmask, strong, nstrong, cfg.iter, cfg.xcd_map, st);
+    });
 }
 
 // Edge-parallel form (plain target): a workgroup takes kEdgeRows rows per

@@ -249,7 +249,7 @@ static int ls_dispatch(int K, int caliber, const ad_csr* A, const void* X, const
 // row), the C-neighbour candidates picked from them as they are computed,
 // then the LS row on the FP64 target the distance pass formed.  The row's
 // CSR entries, distances and panel rows are read once for both results.
-template <typename T, int K, int LPR, int CALT, bool WEIGHTED>
+template <typename T, int K, int LPR, int CALT, bool WEIGHTED, int UN>
 __global__ __launch_bounds__(kBlock) void dist_ls_kernel(
     int n, const int* __restrict__ rp, const int* __restrict__ ci, const T* __restrict__ av,
     const T* __restrict__ X, const double* __restrict__ w, int target, T* __restrict__ mu,
@@ -293,7 +293,7 @@ __global__ __launch_bounds__(kBlock) void dist_ls_kernel(
                 scol[q] = -1;
             }
             double t64[V], d;
-            algdist_row_sel<S, T, K, WEIGHTED>(
+            algdist_row_sel<S, T, K, WEIGHTED, UN>(
                 i, ghost, l, rp, ci, av, X, wd, wt, plain, mu, nullptr, theta, fmask, strong,
                 nstrong, status,
                 [&](int j, T m) {
@@ -361,12 +361,15 @@ static int dist_ls_dispatch(int K, int caliber, const ad_csr* A, const void* X, 
         return with_lpr<T, KK>(lpr, [&](auto lc) {
             constexpr int L = decltype(lc)::value;
             const int grid = dist_ls_grid<T, KK, L>(A->n, cfg);
+            const bool long_rows = nnz_bucket(A->nnz, A->n) >= 2;
             auto go = [&](auto calt, auto weighted) {
-                dist_ls_kernel<T, KK, L, decltype(calt)::value, decltype(weighted)::value>
-                    <<<dim3(grid), dim3(kBlock), 0, s>>>(
+                dist_unroll<T, KK, L>(long_rows, [&](auto uc) {
+                    dist_ls_kernel<T, KK, L, decltype(calt)::value, decltype(weighted)::value,
+                                   decltype(uc)::value><<<dim3(grid), dim3(kBlock), 0, s>>>(
                         A->n, A->row_ptr, A->col, (const T*)A->val, (const T*)X, w, target,
                         (T*)mu, theta, fmask, strong, nstrong, cf, caliber, P_col, P_val, ls_val,
                         row_status, bs, cfg.iter, cfg.xcd_map, st);
+                });
             };
             using C4 = std::integral_constant<int, 4>;
             using C8 = std::integral_constant<int, 8>;

@@ -258,6 +258,24 @@ __device__ __forceinline__ void coop_gather(const T* __restrict__ X, const int (
         }
 }
 
+// Entries per step of the row-group distance loop when a lane holds under
+// 64 bytes of a panel row and loads its rows itself: 3 for matrices of fewer
+// than 16 stored entries per row on average, 4 for longer rows (measured: 3
+// fills the steps of 9-entry stencil rows exactly, 2 leaves more latency
+// exposed and 5 or more cost occupancy; rows of about 17 entries ran best
+// with 4).  f(std::integral_constant<int, UN>) is called with the choice;
+// shapes where it does not matter get 3 only.
+template <typename T, int K, int LPR, typename F>
+void dist_unroll(bool long_rows, F&& f) {
+    constexpr int V = K / LPR;
+    if constexpr (V < 16 && CoopGather<T, V, LPR>::G == 1) {
+        if (long_rows) f(std::integral_constant<int, 4>{});
+        else f(std::integral_constant<int, 3>{});
+    } else {
+        f(std::integral_constant<int, 3>{});
+    }
+}
+
 template <typename T> struct Guard { static constexpr bool on = false; };
 template <> struct Guard<float> { static constexpr bool on = true; };
 
@@ -278,7 +296,7 @@ __device__ __forceinline__ T ratio(T a, T b) {
 // absent; only looked for with the residual target).  A ghost row (a lane
 // past the end of the rows, i clamped to a valid row) has no entries and
 // writes nothing, but takes its part in the cooperative panel loads.
-template <typename S, typename T, int K, bool WEIGHTED, typename Sel>
+template <typename S, typename T, int K, bool WEIGHTED, int UN, typename Sel>
 __device__ __forceinline__ void algdist_row_sel(int i, bool ghost, int l,
                                                 const int* __restrict__ rp,
                                                 const int* __restrict__ ci,
@@ -347,8 +365,9 @@ __device__ __forceinline__ void algdist_row_sel(int i, bool ghost, int l,
     T mmin = (T)INFINITY;
     bool bad = false;
     // U edges per step: their column and panel loads are issued together
+    // (UN, see dist_unroll, for lanes holding under 64 bytes of a row)
     constexpr int G = CoopGather<T, V, LPR>::G;
-    constexpr int U = (G > 1) ? 8 / G : (V >= 16) ? 2 : 4;
+    constexpr int U = (G > 1) ? 8 / G : (V >= 16) ? 2 : UN;
     // the next step's column indices are loaded while this step's panel
     // rows are in flight
     int jn[U];
@@ -471,7 +490,7 @@ __device__ __forceinline__ void algdist_row_sel(int i, bool ghost, int l,
     }
 }
 
-template <typename S, typename T, int K, bool WEIGHTED>
+template <typename S, typename T, int K, bool WEIGHTED, int UN>
 __device__ __forceinline__ void algdist_row(int i, bool ghost, int l, const int* __restrict__ rp,
                                             const int* __restrict__ ci, const T* __restrict__ av,
                                             const T* __restrict__ X, const double (&wd)[S::V],
@@ -481,8 +500,9 @@ __device__ __forceinline__ void algdist_row(int i, bool ghost, int l, const int*
                                             uint8_t* __restrict__ strong, int* __restrict__ nstrong,
                                             unsigned* status) {
     double t64[S::V], d;
-    algdist_row_sel<S, T, K, WEIGHTED>(i, ghost, l, rp, ci, av, X, wd, wt, plain, mu, pout, theta,
-                                       fmask, strong, nstrong, status, [](int, T) {}, t64, d);
+    algdist_row_sel<S, T, K, WEIGHTED, UN>(i, ghost, l, rp, ci, av, X, wd, wt, plain, mu, pout,
+                                           theta, fmask, strong, nstrong, status, [](int, T) {},
+                                           t64, d);
 }
 
 // ---------------------------------------------------------------- edge-parallel distances
