@@ -521,7 +521,7 @@ __device__ __forceinline__ void algdist_row(int i, bool ghost, int l, const int*
 // Per entry the arithmetic is that of algdist_row with one lane per row:
 // the sums over k run in index order in the panel type, p in FP32 via the
 // hardware reciprocal, the FP64 recompute below 1e-4 S_aa.
-constexpr int kEdgeRows = 64;
+constexpr int kEdgeRows = 32;  // measured: 2-3% faster than 64 on graph rows of ~17 entries
 
 // panel rows up to this many bytes use the edge-parallel kernel by default
 constexpr int kEdgeMaxRowBytes = 128;
