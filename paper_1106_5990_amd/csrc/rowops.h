@@ -20,7 +20,10 @@ template <typename S, typename T, int K, typename CiF, typename AvF, typename Pi
 __device__ __forceinline__ void row_spmm_acc(int i, int e0, int e1, CiF ci_of, AvF av_of, int l,
                                              Pick pick, T (&y)[S::V], T& d, Frag<T, S::V>& xi) {
     constexpr int V = S::V, C = S::C;
-    constexpr int U = (V >= 16) ? 2 : 4;  // independent gathers in flight per step
+    // independent gathers in flight per step (measured: 3 beat 4 by 7% on
+    // the colour phases and Jacobi sweeps of stencil rows and matched it on
+    // graph rows of about 17 entries; 6 and 8 were slower)
+    constexpr int U = (V >= 16) ? 2 : 3;
 #pragma unroll
     for (int q = 0; q < V; ++q) y[q] = T(0);
     d = T(0);
