@@ -126,7 +126,7 @@ int launch_jacobi(int dtype, int K, const ad_csr* A, const void* Xin, void* Xout
 // of the same class's earlier rows, which is the same class-major scan over
 // the lengths.  A thread holds kPartR consecutive rows of its block; the
 // block works class by class over the classes present in it.
-constexpr int kPartR = 8;                       // consecutive rows per thread
+constexpr int kPartR = 4;                       // consecutive rows per thread
 constexpr int kPartRows = kPartR * kBlock;      // rows per partition block
 constexpr int kMaxColors = 64;
 
@@ -438,7 +438,7 @@ __global__ __launch_bounds__(kBlock) void permute_entries_kernel(
 // fills whole cache lines; the row-list loads of a thread are issued
 // together.  K is a power of two: row and column of a panel value come from
 // shifts.
-constexpr int kStartChunks = 4;
+constexpr int kStartChunks = 8;
 template <typename T>
 constexpr int kStartLog2E = (sizeof(T) == 4) ? 2 : 1;  // log2 of the values per chunk
 
