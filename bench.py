@@ -42,7 +42,9 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=None, help="grid side of the oracle sample")
     ap.add_argument("--graph", action="store_true", help="replay the step as a captured HIP graph")
-    ap.add_argument("--batched", action="store_true", help="run the batched leg (workload 4)")
+    ap.add_argument("--batched", action="store_true",
+                    help="run the batched leg (workload 4; the default unless --size is given)")
+    ap.add_argument("--no-batched", action="store_true", help="skip the batched leg")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the default launch shapes instead of the autotuner's")
     ap.add_argument("--separate", action="store_true",
@@ -52,11 +54,17 @@ def parse():
                          "timing, new ones are appended (default: a fresh temporary file)")
     ap.add_argument("--batch-size", type=int, default=512)
     ap.add_argument("--adjoint", action="store_true",
-                    help="also time the LS-loss forward and adjoint (workload 5)")
+                    help="also time the LS-loss forward and adjoint (workload 5; the default "
+                         "unless --size is given)")
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint leg")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one 1 GiB device-to-device copy (a kernel of known traffic "
                          "for scaling hardware byte counters)")
-    return ap.parse_args()
+    a = ap.parse_args()
+    # the batched and adjoint legs run by default on the full-size workloads
+    a.batched = not a.no_batched and (a.batched or a.size is None)
+    a.adjoint = not a.no_adjoint and (a.adjoint or a.size is None)
+    return a
 
 
 WORKLOAD_INDEX = {"laplace2d": 1, "aniso2d": 2, "varcoef3d": 3}
