@@ -53,6 +53,9 @@ def parse():
                     help="autotuner cache file (JSON lines); shapes found there are used without "
                          "timing, new ones are appended (default: a fresh temporary file)")
     ap.add_argument("--batch-size", type=int, default=512)
+    ap.add_argument("--batch-workers", type=int, default=None,
+                    help="processes building the batch (default: up to 16; 1 builds it in this "
+                         "process, as a run under a profiler must)")
     ap.add_argument("--adjoint", action="store_true",
                     help="also time the LS-loss forward and adjoint (workload 5; the default "
                          "unless --size is given)")
@@ -219,10 +222,11 @@ def source_hash():
     return h.hexdigest()[:16]
 
 
-def counter_traffic(workload_tag, label):
+def counter_traffic(workload_tag, label, ctype="float"):
     """HBM bytes per launch of `label` from the committed rocprofv3 counter
     summary of this workload (FETCH_SIZE x its copy-calibration factor +
-    WRITE_SIZE x its factor), or None if absent or taken on other sources."""
+    WRITE_SIZE x its factor), or None if absent or taken on other sources.
+    Only rows of the kernel instantiated for element type `ctype` count."""
     here = os.path.dirname(os.path.abspath(__file__))
     path = os.path.join(here, "profiles", "hbm_counters_%s.txt" % workload_tag)
     if not os.path.exists(path):
@@ -242,11 +246,21 @@ def counter_traffic(workload_tag, label):
     sym = KERNEL_SYMBOL.get(label)
     tot, cnt = 0.0, 0
     for r in rows:
-        if sym and r[0].split("<")[0].endswith(sym):
+        base, _, targs = r[0].partition("<")
+        if sym and base.split("::")[-1] == sym and targs.startswith(ctype):
             d = int(r[1])
             tot += d * (float(r[2]) * meta["fs"] + float(r[3]) * meta["ws"]) * 1024.0
             cnt += d
     return tot / cnt if cnt else None
+
+
+def btraffic(tag, label):
+    """HBM bytes per launch of a batch kernel from the committed counter
+    summary of the 512-matrix batch (FP32 only), or None."""
+    if tag != "f32":
+        return None
+    tr = counter_traffic("rgg-batch-fp32", label)
+    return None if tr is None else int(tr)
 
 
 def batched_leg(args, torch, ad, W, mats):
@@ -315,7 +329,9 @@ def batched_leg(args, torch, ad, W, mats):
                     "roofline": {"bound": "hbm", "kernel": "batch_jacobi",
                                  "achieved": kern["batch_jacobi"]["GB/s"], "peak": HBM_PEAK_GBS,
                                  "unit": "GB/s",
-                                 "frac": round(kern["batch_jacobi"]["GB/s"] / HBM_PEAK_GBS, 4)},
+                                 "frac": round(kern["batch_jacobi"]["GB/s"] / HBM_PEAK_GBS, 4),
+                                 "traffic": btraffic(tag, "batch_jacobi"),
+                                 "algorithmic_bytes_per_launch": int(by["batch_jacobi"])},
                     "device_status_bits": ad.status(clear=True)}
         del dm, X, mu, st, ns
         torch.cuda.empty_cache()
@@ -394,7 +410,12 @@ def main():
         # the batch members are built in worker processes before anything
         # touches the GPU
         print("[bench] building the batch", file=sys.stderr, flush=True)
-        batch = W.batch_workload(args.batch_size, workers=min(16, os.cpu_count() or 1))
+        workers = args.batch_workers or min(16, os.cpu_count() or 1)
+
+        def progress(k):
+            if k % 128 == 0:
+                print("[bench]   %d members built" % k, file=sys.stderr, flush=True)
+        batch = W.batch_workload(args.batch_size, workers=workers, progress=progress)
     import torch
     from paper_1106_5990_amd import algdist as ad
 

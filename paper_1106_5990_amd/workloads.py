@@ -265,13 +265,20 @@ def _rgg_member(args):
     return rgg_laplacian(n, d, seed)
 
 
-def rgg_batch(nmat: int, seed_base: int, nmin=2_000, nmax=200_000, workers: int = 1) -> List[CSR]:
+def rgg_batch(nmat: int, seed_base: int, nmin=2_000, nmax=200_000, workers: int = 1,
+              progress=None) -> List[CSR]:
     """Matrix m uses seed (seed_base, m); `workers` > 1 builds members in
-    parallel processes (same result)."""
+    parallel processes (same result).  Built in-process (workers <= 1),
+    progress(k) is called after each member."""
     ns, ds = rgg_batch_sizes(nmat, seed_base, nmin, nmax)
     jobs = [(int(ns[m]), float(ds[m]), (seed_base, m)) for m in range(nmat)]
     if workers <= 1:
-        return [_rgg_member(j) for j in jobs]
+        out = []
+        for j in jobs:
+            out.append(_rgg_member(j))
+            if progress:
+                progress(len(out))
+        return out
     import multiprocessing as mp
     with mp.get_context("fork").Pool(workers) as pool:
         return pool.map(_rgg_member, jobs, chunksize=1)
@@ -353,10 +360,11 @@ def workload(i: int, dtype: str = "f64", size: Optional[int] = None) -> Workload
     raise ValueError("workload %d is a batch; use batch_workload()" % i)
 
 
-def batch_workload(nmat: int = 512, nmin: int = 2_000, nmax: int = 200_000, workers: int = 1):
+def batch_workload(nmat: int = 512, nmin: int = 2_000, nmax: int = 200_000, workers: int = 1,
+                   progress=None):
     """Workload 4: a batch of RGG Laplacians (n log-uniform in [nmin, nmax]),
     K = 16, 4 Jacobi sweeps with omega = 2/3, theta = 0.25."""
-    return rgg_batch(nmat, COEF_SEED_BASE + 4, nmin, nmax, workers)
+    return rgg_batch(nmat, COEF_SEED_BASE + 4, nmin, nmax, workers, progress)
 
 
 BATCH_K, BATCH_SWEEPS, BATCH_OMEGA, BATCH_THETA = 16, 4, 2.0 / 3.0, 0.25
