@@ -42,6 +42,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=None, help="grid side of the oracle sample")
     ap.add_argument("--graph", action="store_true", help="replay the step as a captured HIP graph")
+    ap.add_argument("--no-graph-replay", action="store_true",
+                    help="skip the extra graph-replay timing of the FP32 step")
     ap.add_argument("--batched", action="store_true",
                     help="run the batched leg (workload 4; the default unless --size is given)")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched leg")
@@ -454,9 +456,17 @@ def main():
               file=sys.stderr, flush=True)
         ms, wall_ms, kern = timed(step, steps, args.warmup, torch, ad, graph=args.graph)
         bits = ad.status(clear=True)
+        gms = None
+        if tag == "f32" and not args.graph and not args.no_graph_replay:
+            # the same step captured once and replayed (no per-kernel events)
+            print("[bench] timing %s leg as a graph replay: %d steps" % (tag, steps),
+                  file=sys.stderr, flush=True)
+            gms, _, _ = timed(step, steps, 1, torch, ad, graph=True)
+            bits |= ad.status(clear=True)
         s = 4 if dtype == torch.float32 else 8
         kb = kernel_bytes(wl, s)
         res[tag] = {"ms": ms, "wall_ms": wall_ms, "kernels": kern, "kb": kb, "shapes": shapes,
+                    "graph_ms": gms,
                     "step_bytes": step_bytes(wl, s, kb, fused=not args.separate), "status": bits, "steps": steps}
         del b, step
         torch.cuda.empty_cache()
@@ -513,6 +523,9 @@ def main():
         "kernels": kstats,
         "wall_ms_per_step": round(main_leg["wall_ms"], 4),
         "device_status_bits": main_leg["status"],
+        "graph_replay": None if main_leg["graph_ms"] is None else {
+            "value": round(E / (main_leg["graph_ms"] * 1e-3), 1),
+            "ms_per_step": round(main_leg["graph_ms"], 4)},
     }
     if "f64" in res:
         r = res["f64"]

@@ -655,6 +655,53 @@ def test_run_to_run_bitwise_identical():
         assert torch.equal(a, b)
 
 
+def test_step_graph_replay_matches_eager():
+    """The whole step (start, colour-phase sweeps, fused distances + strength +
+    LS rows with the F-row sum) captured once and replayed: every replay,
+    with eager steps on other start vectors between the replays, equals the
+    eager result bitwise."""
+    say("graph replay of the whole step")
+    ad = lib()
+    N, K = 97, 16
+    A = aniso(N)
+    Ad = dev_csr(A, torch.float32)
+    color = torch.as_tensor(W.red_black((N, N)), device="cuda")
+    cf = torch.as_tensor(W.cf_red_is_coarse((N, N)), device="cuda")
+    X = torch.empty((A.n, K), dtype=torch.float32, device="cuda")
+    ad.setup_testvectors(Ad, K, seed=1, relax="gs", sweeps=5, color=color, ncolors=2, out=X)
+    out = ad.distance_ls(Ad, X, cf, 4, theta=0.25, want_sum=True)
+
+    def step(seed):
+        ad.setup_testvectors(Ad, K, seed=seed, relax="gs", sweeps=5, color=color, ncolors=2,
+                             out=X)
+        ad.distance_ls(Ad, X, cf, 4, theta=0.25, mu=out[0], strong=out[1], nstrong=out[2],
+                       P_col=out[3], P_val=out[4], ls_val=out[5], row_status=out[6],
+                       ls_sum=out[7], want_sum=True)
+
+    bufs = [X] + list(out)
+    step(1)
+    torch.cuda.synchronize()
+    ref = [b.clone() for b in bufs]
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        step(1)
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        step(1)
+    for r in range(3):
+        step(7 + r)
+        torch.cuda.synchronize()
+        assert not torch.equal(X, ref[0])
+        g.replay()
+        torch.cuda.synchronize()
+        for a, b in zip(bufs, ref):
+            assert torch.equal(a, b), "replay %d" % r
+    assert ad.status(clear=True) == 0
+
+
 def test_host_argument_errors():
     say("argument errors")
     ad = lib()
