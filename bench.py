@@ -224,11 +224,20 @@ def source_hash():
     return h.hexdigest()[:16]
 
 
-def counter_traffic(workload_tag, label, ctype="float"):
+# launch-shape family (autotuner cache name) of each timed label
+SHAPE_FAMILY = {"gs_phase": "gs_phase", "jacobi": "jacobi", "algdist": "algdist",
+                "ls_interp": "ls_interp", "distance_ls": "distance_ls",
+                "batch_jacobi": "batched", "batch_algdist": "batched_distance"}
+
+
+def counter_traffic(workload_tag, label, ctype="float", shapes=None):
     """HBM bytes per launch of `label` from the committed rocprofv3 counter
     summary of this workload (FETCH_SIZE x its copy-calibration factor +
     WRITE_SIZE x its factor), or None if absent or taken on other sources.
-    Only rows of the kernel instantiated for element type `ctype` count."""
+    Only rows of the kernel instantiated for element type `ctype` count.
+    When the summary records the launch shape it was taken with for the
+    label's family and `shapes` (this run's) does not give the same one, the
+    counters do not describe this run's launches: None."""
     here = os.path.dirname(os.path.abspath(__file__))
     path = os.path.join(here, "profiles", "hbm_counters_%s.txt" % workload_tag)
     if not os.path.exists(path):
@@ -238,6 +247,8 @@ def counter_traffic(workload_tag, label, ctype="float"):
         line = line.strip()
         if line.startswith("# source-hash:"):
             meta["hash"] = line.split(":", 1)[1].strip()
+        elif line.startswith("# shapes:"):
+            meta["shapes"] = json.loads(line.split(":", 1)[1])
         elif line.startswith("# scale:"):
             f, w = line.split(":", 1)[1].split()
             meta["fs"], meta["ws"] = float(f), float(w)
@@ -245,6 +256,10 @@ def counter_traffic(workload_tag, label, ctype="float"):
             rows.append([c.strip() for c in line.split("|")])
     if meta.get("hash") != source_hash() or "fs" not in meta:
         return None
+    fam = SHAPE_FAMILY.get(label)
+    if fam in meta.get("shapes", {}):
+        if not isinstance(shapes, dict) or shapes.get(fam) != meta["shapes"][fam]:
+            return None
     sym = KERNEL_SYMBOL.get(label)
     tot, cnt = 0.0, 0
     for r in rows:
@@ -256,12 +271,12 @@ def counter_traffic(workload_tag, label, ctype="float"):
     return tot / cnt if cnt else None
 
 
-def btraffic(tag, label):
+def btraffic(tag, label, shapes):
     """HBM bytes per launch of a batch kernel from the committed counter
-    summary of the 512-matrix batch (FP32 only), or None."""
+    summary of the 512-matrix batch (FP32 only, same launch shape), or None."""
     if tag != "f32":
         return None
-    tr = counter_traffic("rgg-batch-fp32", label)
+    tr = counter_traffic("rgg-batch-fp32", label, shapes=shapes)
     return None if tr is None else int(tr)
 
 
@@ -332,7 +347,7 @@ def batched_leg(args, torch, ad, W, mats):
                                  "achieved": kern["batch_jacobi"]["GB/s"], "peak": HBM_PEAK_GBS,
                                  "unit": "GB/s",
                                  "frac": round(kern["batch_jacobi"]["GB/s"] / HBM_PEAK_GBS, 4),
-                                 "traffic": btraffic(tag, "batch_jacobi"),
+                                 "traffic": btraffic(tag, "batch_jacobi", shape),
                                  "algorithmic_bytes_per_launch": int(by["batch_jacobi"])},
                     "device_status_bits": ad.status(clear=True)}
         del dm, X, mu, st, ns
@@ -493,7 +508,8 @@ def main():
         cnt, tot = kern[dom]
         avg = tot / cnt
         ach = main_leg["kb"][dom] / (avg * 1e-3) / 1e9
-        tr = counter_traffic("%s-fp32" % args.workload, dom) if args.size is None else None
+        tr = (counter_traffic("%s-fp32" % args.workload, dom, shapes=main_leg["shapes"])
+              if args.size is None else None)
         roof = {"bound": "hbm", "kernel": dom, "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
                 "traffic": None if tr is None else int(tr),

@@ -233,7 +233,8 @@ __global__ __launch_bounds__(kBlock) void color_count_kernel(int n, const int* _
 
 // Exclusive scans of the class-major tables counts[0 .. m) and (with lens)
 // counts[m .. 2m) by one workgroup of 1024 threads, both in one pass: a
-// thread's contiguous run (loads of kScanRun values in flight together,
+// thread's contiguous run (loads of kScanRun values in flight together, as
+// 16-byte loads when both tables are 16-byte aligned and the run is whole;
 // kept in registers) is summed, the run sums (count in the low, length in
 // the high 32 bits of one 64-bit value: neither field can carry, both
 // totals being below 2^31) are scanned across the workgroup, and the run is
@@ -248,15 +249,31 @@ __global__ __launch_bounds__(1024) void scan_counts_kernel(int* __restrict__ cou
     __shared__ uint64_t wtot[1024 / kWave];
     const int t = threadIdx.x, lane = t & (kWave - 1), wv = t / kWave;
     int* lens = counts + m;
+    const bool vec_ok = (((uintptr_t)counts | (uintptr_t)lens) & 15) == 0;
     uint64_t carry = 0;
     // rounds of 1024 * kScanRun entries; thread t takes a contiguous run
     for (int r0 = 0; r0 < m; r0 += 1024 * kScanRun) {
         const int b = r0 + t * kScanRun;
         int vc[kScanRun], vl[kScanRun];
+        if (vec_ok && b + kScanRun <= m) {
+            typedef int int4v __attribute__((ext_vector_type(4)));
 #pragma unroll
-        for (int k = 0; k < kScanRun; ++k) {
-            vc[k] = (b + k < m) ? counts[b + k] : 0;
-            vl[k] = (with_lens && b + k < m) ? lens[b + k] : 0;
+            for (int k = 0; k < kScanRun; k += 4) {
+                const int4v c4 = *reinterpret_cast<const int4v*>(counts + b + k);
+                const int4v l4 = with_lens ? *reinterpret_cast<const int4v*>(lens + b + k)
+                                           : int4v{0, 0, 0, 0};
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    vc[k + q] = c4[q];
+                    vl[k + q] = l4[q];
+                }
+            }
+        } else {
+#pragma unroll
+            for (int k = 0; k < kScanRun; ++k) {
+                vc[k] = (b + k < m) ? counts[b + k] : 0;
+                vl[k] = (with_lens && b + k < m) ? lens[b + k] : 0;
+            }
         }
         uint64_t run = 0;
 #pragma unroll

@@ -1,6 +1,7 @@
 """Host-side logic of bench.py, without a GPU: the one-GPU guard, the
 algorithmic byte model, and the counter-summary reader (used only when its
 source hash matches the current kernel sources)."""
+import json
 import os
 import subprocess
 import sys
@@ -70,3 +71,12 @@ def test_counter_summary_is_used_only_for_matching_sources(tmp_path, monkeypatch
     assert got == pytest.approx(want)
     assert bench.counter_traffic("x-fp32", "distance_ls") == pytest.approx((7 * 2 + 9) * 1024)
     assert bench.counter_traffic("missing", "gs_phase") is None
+    # a summary taken with another launch shape of the kernel is not used
+    shp = {"gs_phase": {"lpr": 4, "iter": 2, "xcd": 0}}
+    path.write_text("\n".join(["# source-hash: abc", "# shapes: " + json.dumps(shp)] + body) + "\n")
+    assert bench.counter_traffic("x-fp32", "gs_phase", shapes=shp) == pytest.approx(want)
+    other = {"gs_phase": {"lpr": 4, "iter": 4, "xcd": 16}}
+    assert bench.counter_traffic("x-fp32", "gs_phase", shapes=other) is None
+    assert bench.counter_traffic("x-fp32", "gs_phase", shapes="defaults") is None
+    # families the summary does not record are not checked
+    assert bench.counter_traffic("x-fp32", "distance_ls", shapes=other) == pytest.approx((7 * 2 + 9) * 1024)
