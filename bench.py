@@ -3,8 +3,9 @@
 
 One step = the whole path over one synthetic operator resident in HBM:
   test-vector start + relaxation (setup_testvectors)
-  -> per-edge distances with the fused strength graph (algebraic_distance)
-  -> LS interpolation rows with their F-row sum (ls_interp).
+  -> per-edge distances with the fused strength row and the LS
+     interpolation rows with their F-row sum (distance_ls; --separate runs
+     algebraic_distance + ls_interp instead).
 The metric is edges/s: off-diagonal CSR entries (the directed pairs on which
 distances are computed) per second of step time.
 
@@ -12,15 +13,35 @@ Default workload: the rotated anisotropic diffusion operator (alpha = pi/6,
 eps = 1e-3) with the central 9-point stencil on a 2048 x 2048 grid, K = 16
 test vectors, 5 red-black colour-phase Gauss-Seidel sweeps, theta = 0.25,
 caliber 4 from the red C/F split; FP32 relaxation and distances with FP64
-interpolation solves.  The plain FP64 path on the same workload is timed
-beside it, and the CPU oracle on a bounded sample of the same workload on the
-host cores.  Prints ONE JSON line.
+interpolation solves.
+
+Timing: the step is captured once in a HIP graph and replayed; every replay
+is bracketed by its own events and followed (outside the events) by a 1 GiB
+scratch write, so that no replay starts with the panels of the previous one
+in the 256 MB Infinity Cache.  `value` is edges / median replay time.  A
+second, eager pass with the library's per-launch HIP events (on the stream
+the kernels run on, the same scratch write between steps) gives per-kernel
+times and the roofline of the dominant kernel.
+
+Byte model (roofline.frac, step_hbm_frac): every operand read or written
+once per sweep or pass -- one CSR stream and one panel read + one panel
+write per relaxation sweep (a colour phase of c colours is 1/c sweep); the
+distance pass reads the CSR structure and the panel once and writes mu and
+the mask; the LS rows read each F row's columns and distances, its panel
+row, and write the row.  The start panel is not charged.  The bytes the
+colour-major layout actually moves (each phase reads the whole old panel)
+are reported beside it as the layout model.
+
+Also reported: the plain FP64 path on the same workload, the 3D log-normal
+7-point workload (160^3, K = 32, 4 Jacobi sweeps; FP32 and FP64), the
+per-result error of the FP32 chain against the FP64 chain on both workloads,
+the 512-matrix batch, the adjoint, and the CPU oracle on the host cores.
+Prints ONE JSON line.
 
   python bench.py [--steps K] [--warmup W] [--workload aniso2d|varcoef3d|laplace2d]
 """
 import argparse
 import json
-import math
 import os
 import sys
 import tempfile
@@ -29,9 +50,10 @@ import time
 import numpy as np
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
+FLUSH_BYTES = 1 << 30  # scratch written between timed repetitions
 
 
-def parse():
+def parse(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
@@ -41,9 +63,13 @@ def parse():
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 leg")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=None, help="grid side of the oracle sample")
-    ap.add_argument("--graph", action="store_true", help="replay the step as a captured HIP graph")
-    ap.add_argument("--no-graph-replay", action="store_true",
-                    help="skip the extra graph-replay timing of the FP32 step")
+    ap.add_argument("--cpu-threads", type=int, default=None,
+                    help="threads of the all-cores oracle variant (default: the host cores this "
+                         "process may use, at most 16)")
+    ap.add_argument("--no-second", action="store_true",
+                    help="skip the second workload's legs (varcoef3d when the main one is aniso2d)")
+    ap.add_argument("--no-precision", action="store_true",
+                    help="skip the FP32-chain vs FP64-chain error statement")
     ap.add_argument("--batched", action="store_true",
                     help="run the batched leg (workload 4; the default unless --size is given)")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched leg")
@@ -51,6 +77,8 @@ def parse():
                     help="keep the default launch shapes instead of the autotuner's")
     ap.add_argument("--separate", action="store_true",
                     help="distances and LS rows as two calls instead of the fused pass")
+    ap.add_argument("--eager-only", action="store_true",
+                    help="time eager steps only (no graph capture; for profiler runs)")
     ap.add_argument("--tune-cache", default=None,
                     help="autotuner cache file (JSON lines); shapes found there are used without "
                          "timing, new ones are appended (default: a fresh temporary file)")
@@ -65,7 +93,7 @@ def parse():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one 1 GiB device-to-device copy (a kernel of known traffic "
                          "for scaling hardware byte counters)")
-    a = ap.parse_args()
+    a = ap.parse_args(argv)
     # the batched and adjoint legs run by default on the full-size workloads
     a.batched = not a.no_batched and (a.batched or a.size is None)
     a.adjoint = not a.no_adjoint and (a.adjoint or a.size is None)
@@ -73,89 +101,45 @@ def parse():
 
 
 WORKLOAD_INDEX = {"laplace2d": 1, "aniso2d": 2, "varcoef3d": 3}
+SECOND = {"aniso2d": "varcoef3d"}
 
 
-def build_inputs(wl, dtype, torch, ad):
-    A = ad.Csr.from_host(wl.A, dtype=dtype)
-    dev = A.device
-    n, nnz, K = wl.A.n, wl.A.nnz, wl.K
-    buf = {
-        "A": A,
-        "X": torch.empty((n, K), dtype=dtype, device=dev),
-        "mu": torch.empty(nnz, dtype=dtype, device=dev),
-        "strong": torch.empty(nnz, dtype=torch.uint8, device=dev),
-        "ns": torch.empty(n, dtype=torch.int32, device=dev),
-        "cf": torch.as_tensor(wl.cf, device=dev),
-        "Pc": torch.empty((n, wl.caliber), dtype=torch.int32, device=dev),
-        "Pv": torch.empty((n, wl.caliber), dtype=torch.float64, device=dev),
-        "ls": torch.empty(n, dtype=torch.float64, device=dev),
-        "st": torch.empty(n, dtype=torch.int32, device=dev),
-        "lsum": torch.empty(1, dtype=torch.float64, device=dev),
-        "color": None if wl.color is None else torch.as_tensor(wl.color, device=dev),
-    }
-    return buf
+def log(msg):
+    print("[bench] " + msg, file=sys.stderr, flush=True)
 
 
-def make_step(wl, b, ad, fused=True):
-    """One pass of the path: test vectors, then distances with the strength
-    row and the LS rows -- in one fused pass (distance_ls) or as the two
-    separate calls."""
-    def step():
-        ad.setup_testvectors(b["A"], wl.K, seed=wl.tv_seed, relax=wl.relax, sweeps=wl.sweeps,
-                             omega=wl.omega, color=b["color"], ncolors=wl.ncolors, out=b["X"])
-        if fused:
-            ad.distance_ls(b["A"], b["X"], b["cf"], wl.caliber, theta=wl.theta, mu=b["mu"],
-                           strong=b["strong"], nstrong=b["ns"], P_col=b["Pc"], P_val=b["Pv"],
-                           ls_val=b["ls"], row_status=b["st"], ls_sum=b["lsum"], want_sum=True)
-            return
-        ad.algebraic_distance(b["A"], b["X"], mu=b["mu"], fuse=True, theta=wl.theta,
-                              strong=b["strong"], nstrong=b["ns"])
-        ad.ls_interp(b["A"], b["X"], b["cf"], b["mu"], wl.caliber, P_col=b["Pc"], P_val=b["Pv"],
-                     ls_val=b["ls"], row_status=b["st"], ls_sum=b["lsum"], want_sum=True)
-    return step
+# ------------------------------------------------------------------ byte models
+def model_bytes(wl, s):
+    """Algorithmic HBM bytes of one step by the model of the module
+    docstring (s = bytes per panel / matrix value): per relaxation sweep,
+    per distance pass, per LS pass, and the step total."""
+    A = wl.A
+    n, nnz, K = A.n, A.nnz, wl.K
+    deg = np.diff(A.row_ptr.astype(np.int64))
+    F = wl.cf == 0
+    sweep = (n + 1) * 4 + nnz * (4 + s) + 2 * n * K * s
+    dist = (n + 1) * 4 + nnz * 4 + n * K * s + nnz * s + nnz
+    ls = int(deg[F].sum()) * (4 + s) + int(F.sum()) * (K * s + wl.caliber * 12 + 8)
+    return {"sweep": sweep, "distance": dist, "ls": ls, "step": wl.sweeps * sweep + dist + ls}
 
 
-def timed(step, steps, warmup, torch, ad, graph=False):
-    """Run warmup steps, then time `steps` steps bracketed by synchronisation;
-    per-kernel HIP events (the library's timing record) run over the same
-    timed region."""
-    for _ in range(warmup):
-        step()
-    torch.cuda.synchronize()
-    g = None
-    if graph:
-        s = torch.cuda.Stream()
-        s.wait_stream(torch.cuda.current_stream())
-        with torch.cuda.stream(s):
-            step()
-        torch.cuda.current_stream().wait_stream(s)
-        torch.cuda.synchronize()
-        g = torch.cuda.CUDAGraph()
-        with torch.cuda.graph(g):
-            step()
-        g.replay()
-        torch.cuda.synchronize()
-    run = g.replay if g is not None else step
-    ad.timing(not graph)
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    e0.record()
-    for _ in range(steps):
-        run()
-    e1.record()
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    kernels = ad.timing_report() if not graph else {}
-    ad.timing(False)
-    return e0.elapsed_time(e1) / steps, wall / steps * 1e3, kernels
+def kernel_model_bytes(wl, s):
+    """Model bytes per launch of each timed kernel label (None: not in the
+    model, e.g. the start panel and the colour setup)."""
+    m = model_bytes(wl, s)
+    out = {"jacobi": m["sweep"], "algdist": m["distance"], "ls_interp": m["ls"],
+           "distance_ls": m["distance"] + m["ls"], "tv_init": None, "color_partition": None,
+           "strength": None}
+    if wl.color is not None:
+        out["gs_phase"] = m["sweep"] / wl.ncolors
+    return out
 
 
 def kernel_bytes(wl, s):
-    """Algorithmic HBM bytes per launch of each kernel (s = panel bytes per
-    value).  Every operand is read or written once; neighbour re-reads of the
-    panel are taken to hit in cache."""
+    """Bytes per launch of each kernel as the implementation's data layout
+    moves them (the layout model): every operand read or written once,
+    neighbour re-reads of the panel taken to hit in cache; a colour phase
+    reads every panel row (new rows of earlier colours, old otherwise)."""
     A = wl.A
     n, nnz, K = A.n, A.nnz, wl.K
     rp = A.row_ptr.astype(np.int64)
@@ -196,6 +180,7 @@ def kernel_bytes(wl, s):
 
 
 def step_bytes(wl, s, kb, fused=True):
+    """Step bytes by the layout model (kb = kernel_bytes)."""
     sweeps = wl.sweeps
     b = kb["tv_init"] + (kb["distance_ls"] if fused else kb["algdist"] + kb["ls_interp"])
     if wl.relax == "gs":
@@ -205,6 +190,7 @@ def step_bytes(wl, s, kb, fused=True):
     return b
 
 
+# ------------------------------------------------------------------ counters
 KERNEL_SYMBOL = {"gs_phase": "gs_phase_perm_kernel", "jacobi": "jacobi_kernel",
                  "algdist": "algdist_kernel", "ls_interp": "ls_interp_kernel",
                  "tv_init": "start_perm_kernel", "distance_ls": "dist_ls_kernel",
@@ -271,20 +257,253 @@ def counter_traffic(workload_tag, label, ctype="float", shapes=None):
     return tot / cnt if cnt else None
 
 
-def btraffic(tag, label, shapes):
-    """HBM bytes per launch of a batch kernel from the committed counter
-    summary of the 512-matrix batch (FP32 only, same launch shape), or None."""
-    if tag != "f32":
+# ------------------------------------------------------------------ timing
+class Flusher:
+    """A 1 GiB device buffer rewritten between timed repetitions (on the
+    current stream, outside the events)."""
+
+    def __init__(self, torch):
+        self.buf = torch.empty(FLUSH_BYTES // 4, dtype=torch.float32, device="cuda")
+        self.k = 0
+
+    def __call__(self):
+        self.k += 1
+        self.buf.fill_(float(self.k))
+
+
+def capture_graph(run, torch):
+    """`run` captured once in a CUDA/HIP graph (after one run on a side
+    stream, as graph capture wants)."""
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        run()
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        run()
+    torch.cuda.synchronize()
+    return g
+
+
+def rep_times(run, reps, flush, torch):
+    """Per-repetition milliseconds of `run`, each bracketed by events, with
+    the scratch write after it (outside the events)."""
+    evs = []
+    for _ in range(reps):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        run()
+        e1.record()
+        flush()
+        evs.append((e0, e1))
+    torch.cuda.synchronize()
+    return [a.elapsed_time(b) for a, b in evs]
+
+
+def time_step(step, steps, warmup, flush, torch, ad, graph=True):
+    """Median replay time of the captured step (graph=False: of eager
+    steps), then an eager pass with per-kernel HIP events."""
+    for _ in range(warmup):
+        step()
+        flush()
+    torch.cuda.synchronize()
+    if graph:
+        g = capture_graph(step, torch)
+        for _ in range(warmup):
+            g.replay()
+            flush()
+        ms = rep_times(g.replay, steps, flush, torch)
+    else:
+        ms = rep_times(step, steps, flush, torch)
+    ad.timing(True)
+    eager = rep_times(step, steps, flush, torch)
+    kernels = ad.timing_report()
+    ad.timing(False)
+    return {"median_ms": float(np.median(ms)), "min_ms": float(np.min(ms)),
+            "max_ms": float(np.max(ms)), "eager_median_ms": float(np.median(eager)),
+            "kernels": kernels, "graph": graph}
+
+
+# ------------------------------------------------------------------ one workload
+def build_inputs(wl, dtype, torch, ad):
+    A = ad.Csr.from_host(wl.A, dtype=dtype)
+    dev = A.device
+    n, nnz, K = wl.A.n, wl.A.nnz, wl.K
+    return {
+        "A": A,
+        "X": torch.empty((n, K), dtype=dtype, device=dev),
+        "mu": torch.empty(nnz, dtype=dtype, device=dev),
+        "strong": torch.empty(nnz, dtype=torch.uint8, device=dev),
+        "ns": torch.empty(n, dtype=torch.int32, device=dev),
+        "cf": torch.as_tensor(wl.cf, device=dev),
+        "Pc": torch.empty((n, wl.caliber), dtype=torch.int32, device=dev),
+        "Pv": torch.empty((n, wl.caliber), dtype=torch.float64, device=dev),
+        "ls": torch.empty(n, dtype=torch.float64, device=dev),
+        "st": torch.empty(n, dtype=torch.int32, device=dev),
+        "lsum": torch.empty(1, dtype=torch.float64, device=dev),
+        "color": None if wl.color is None else torch.as_tensor(wl.color, device=dev),
+    }
+
+
+def make_step(wl, b, ad, fused=True):
+    """One pass of the path: test vectors, then distances with the strength
+    row and the LS rows -- in one fused pass (distance_ls) or as the two
+    separate calls."""
+    def step():
+        ad.setup_testvectors(b["A"], wl.K, seed=wl.tv_seed, relax=wl.relax, sweeps=wl.sweeps,
+                             omega=wl.omega, color=b["color"], ncolors=wl.ncolors, out=b["X"])
+        if fused:
+            ad.distance_ls(b["A"], b["X"], b["cf"], wl.caliber, theta=wl.theta, mu=b["mu"],
+                           strong=b["strong"], nstrong=b["ns"], P_col=b["Pc"], P_val=b["Pv"],
+                           ls_val=b["ls"], row_status=b["st"], ls_sum=b["lsum"], want_sum=True)
+            return
+        ad.algebraic_distance(b["A"], b["X"], mu=b["mu"], fuse=True, theta=wl.theta,
+                              strong=b["strong"], nstrong=b["ns"])
+        ad.ls_interp(b["A"], b["X"], b["cf"], b["mu"], wl.caliber, P_col=b["Pc"], P_val=b["Pv"],
+                     ls_val=b["ls"], row_status=b["st"], ls_sum=b["lsum"], want_sum=True)
+    return step
+
+
+def kernel_stats(wl, s, kernels, steps):
+    """Per-kernel average launch time with its model and layout rates."""
+    mb, lb = kernel_model_bytes(wl, s), kernel_bytes(wl, s)
+    out = {}
+    for lab, (cnt, tot) in kernels.items():
+        avg = tot / cnt
+        m, l_ = mb.get(lab), lb.get(lab)
+        out[lab] = {"launches_per_step": cnt / steps, "avg_ms": round(avg, 5),
+                    "model_GB/s": None if m is None else round(m / (avg * 1e-3) / 1e9, 1),
+                    "layout_GB/s": None if l_ is None else round(l_ / (avg * 1e-3) / 1e9, 1)}
+    return out
+
+
+def roofline_of(wl, s, kernels, counter_tag, shapes):
+    """Roofline of the kernel with the largest total time: model bytes per
+    launch / its average launch time, against the HBM peak."""
+    if not kernels:
         return None
-    tr = counter_traffic("rgg-batch-fp32", label, shapes=shapes)
-    return None if tr is None else int(tr)
+    dom = max(kernels, key=lambda k: kernels[k][1])
+    cnt, tot = kernels[dom]
+    avg = tot / cnt
+    mb = kernel_model_bytes(wl, s).get(dom)
+    lb = kernel_bytes(wl, s).get(dom)
+    tr = counter_traffic(counter_tag, dom, shapes=shapes) if counter_tag else None
+    ach = None if mb is None else mb / (avg * 1e-3) / 1e9
+    return {"bound": "hbm", "kernel": dom,
+            "achieved": None if ach is None else round(ach, 1), "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": None if ach is None else round(ach / HBM_PEAK_GBS, 4),
+            "traffic": None if tr is None else int(tr),
+            "algorithmic_bytes_per_launch": None if mb is None else int(mb),
+            "avg_launch_ms": round(avg, 5),
+            "layout_bytes_per_launch": None if lb is None else int(lb),
+            "layout_frac": None if lb is None else round(lb / (avg * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
 
 
-def batched_leg(args, torch, ad, W, mats):
+def run_leg(args, wl, tag, dtype, torch, ad, flush, keep=False):
+    """Time one (workload, dtype) leg; keep=True also returns host copies of
+    the step's outputs (for the precision statement)."""
+    b = build_inputs(wl, dtype, torch, ad)
+    step = make_step(wl, b, ad, fused=not args.separate)
+    if not args.no_autotune:
+        log("%s %s: autotune" % (wl.name, tag))
+        cache = args.tune_cache or os.path.join(tempfile.mkdtemp(prefix="algdist_tune_"),
+                                                "shapes.jsonl")
+        ad.autotune(b["A"], wl.K, relax=wl.relax, color=b["color"], ncolors=wl.ncolors,
+                    cf=b["cf"], caliber=wl.caliber, cache_json=cache)
+        code = ad._dtype_code(dtype)
+        shapes = {e["kernel"]: {k: e[k] for k in ("lpr", "iter", "xcd")}
+                  for e in (json.loads(l) for l in open(cache)) if e["dtype"] == code}
+    else:
+        shapes = "defaults"
+    steps = args.steps if tag == "f32" else max(3, args.steps // 2)
+    log("%s %s: %d warmup + %d timed steps%s" % (wl.name, tag, args.warmup, steps,
+                                                "" if args.eager_only else " (graph replays)"))
+    t = time_step(step, steps, args.warmup, flush, torch, ad, graph=not args.eager_only)
+    bits = ad.status(clear=True)
+    s = 4 if dtype == torch.float32 else 8
+    E = wl.A.n_edges
+    mb = model_bytes(wl, s)
+    lay = step_bytes(wl, s, kernel_bytes(wl, s), fused=not args.separate)
+    ms = t["median_ms"]
+    ctag = ("%s-fp32" % wl.name.split("-")[0]) if (s == 4 and args.size is None) else None
+    out = {"value": round(E / (ms * 1e-3), 1), "ms_per_step": round(ms, 4),
+           "ms_min_max": [round(t["min_ms"], 4), round(t["max_ms"], 4)],
+           "eager_ms_per_step": round(t["eager_median_ms"], 4), "steps": steps,
+           "timing": "median of %d %s, 1 GiB scratch write between them" % (
+               steps, "graph replays" if t["graph"] else "eager steps"),
+           "step_model_bytes": int(mb["step"]),
+           "step_hbm_frac": round(mb["step"] / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+           "step_layout_bytes": int(lay),
+           "step_layout_frac": round(lay / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+           "kernels": kernel_stats(wl, s, t["kernels"], steps),
+           "roofline": roofline_of(wl, s, t["kernels"], ctag, shapes),
+           "launch_shapes": shapes, "device_status_bits": bits}
+    host = None
+    if keep:
+        torch.cuda.synchronize()
+        host = {k: b[k].cpu().numpy() for k in ("mu", "strong", "Pc", "Pv", "ls", "st")}
+    del b, step
+    torch.cuda.empty_cache()
+    return out, host
+
+
+# ------------------------------------------------------------------ precision
+def precision_statement(wl, r32, r64):
+    """Per-result error of the FP32 chain (FP32 relaxation and distances,
+    FP64 LS solves) against the all-FP64 chain on the same workload."""
+    A = wl.A
+    rid = A.row_ids()
+    off = A.col != rid
+    m32 = r32["mu"].astype(np.float64)
+    m64 = r64["mu"]
+    rel = np.abs(m32 - m64)[off] / np.maximum(m64[off], 1e-300)
+    out = {"mu_rel_err": {"max": float(rel.max()), "p99": float(np.quantile(rel, 0.99)),
+                          "median": float(np.median(rel)),
+                          "above_1e-4": int((rel > 1e-4).sum()), "edges": int(rel.size)}}
+    # strong-mask flips by the FP64 chain's threshold margin |theta mu / m_i - 1|
+    mmin = np.full(A.n, np.inf)
+    np.minimum.at(mmin, rid[off], m64[off])
+    with np.errstate(divide="ignore", invalid="ignore"):
+        margin = np.abs(wl.theta * m64 / mmin[rid] - 1.0)
+    margin[~off] = np.inf
+    flips = (r32["strong"] != r64["strong"])
+    bands = {"<=1e-6": int((flips & (margin <= 1e-6)).sum()),
+             "1e-6..1e-5": int((flips & (margin > 1e-6) & (margin <= 1e-5)).sum()),
+             "1e-5..1e-4": int((flips & (margin > 1e-5) & (margin <= 1e-4)).sum()),
+             ">1e-4": int((flips & (margin > 1e-4)).sum())}
+    # a flip needs the threshold inside the combined error of mu_ij and m_i
+    err = np.abs(m32 - m64) / np.maximum(m64, 1e-300)
+    row_err = np.zeros(A.n)
+    np.maximum.at(row_err, rid[off], err[off])
+    allowed = margin <= 2.0 * (err + row_err[rid]) + 1e-6
+    out["mask"] = {"flips": int(flips.sum()), "flips_by_margin": bands,
+                   "flips_outside_twice_measured_error": int((flips & ~allowed).sum()),
+                   "edges": int(off.sum())}
+    # LS rows: weights and functional on F rows whose C_i agree
+    F = wl.cf == 0
+    same = F & np.all(r32["Pc"] == r64["Pc"], axis=1) & (r32["st"] == r64["st"])
+    pe = (np.abs(r32["Pv"] - r64["Pv"]) / np.maximum(1.0, np.abs(r64["Pv"])))[same]
+    le = (np.abs(r32["ls"] - r64["ls"]) / np.maximum(np.abs(r64["ls"]), 1e-300))[same]
+    out["P_val_scaled_err"] = {"max": float(pe.max()) if pe.size else 0.0,
+                               "p99": float(np.quantile(pe, 0.99)) if pe.size else 0.0,
+                               "above_1e-6": int((pe > 1e-6).sum()),
+                               "rows_same_C": int(same.sum()),
+                               "rows_C_differ": int((F & ~same).sum()), "F_rows": int(F.sum())}
+    out["ls_val_rel_err"] = {"max": float(le.max()) if le.size else 0.0,
+                             "p99": float(np.quantile(le, 0.99)) if le.size else 0.0}
+    return out
+
+
+# ------------------------------------------------------------------ batch, adjoint
+def batched_leg(args, torch, ad, W, mats, flush):
     """Workload 4: the RGG batch through relax_algdist_batched.  The launch
     shape is picked by the batch autotuner (outside the timed region); the
-    timed region replays the captured stage graph; a separate pass with
-    per-kernel timing gives the sweep kernel's rate for the roofline."""
+    timed repetitions replay the captured stage graph (median, 1 GiB write
+    between them); a separate pass with per-kernel timing gives the sweep
+    kernel's rate for the roofline."""
     K, S, om, th = W.BATCH_K, W.BATCH_SWEEPS, W.BATCH_OMEGA, W.BATCH_THETA
     E = sum(m.n_edges for m in mats)
     rows = sum(m.n for m in mats)
@@ -295,7 +514,7 @@ def batched_leg(args, torch, ad, W, mats):
            "matrices": nm, "rows": rows, "nnz": ents, "edges": E}
     cache = args.tune_cache or os.path.join(tempfile.mkdtemp(prefix="algdist_tune_"), "batch.jsonl")
     for tag, dt, s in (("f32", torch.float32, 4), ("f64", torch.float64, 8)):
-        print("[bench] batched leg %s: autotune" % tag, file=sys.stderr, flush=True)
+        log("batched leg %s: autotune" % tag)
         dm = [ad.Csr.from_host(m, dtype=dt) for m in mats]
         ad.autotune_batched(dm, K, S, cache_json=cache)
         tuned = [json.loads(l) for l in open(cache)]
@@ -312,17 +531,11 @@ def batched_leg(args, torch, ad, W, mats):
                                      X=X, mu=mu, strong=st, nstrong=ns)
         for _ in range(args.warmup):
             run()
+            flush()
         torch.cuda.synchronize()
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
         steps = max(3, args.steps // 2)
-        print("[bench] batched leg %s: %d steps" % (tag, steps), file=sys.stderr, flush=True)
-        e0.record()
-        for _ in range(steps):
-            run()
-        e1.record()
-        torch.cuda.synchronize()
-        ms = e0.elapsed_time(e1) / steps
+        log("batched leg %s: %d steps" % (tag, steps))
+        ms = float(np.median(rep_times(run, steps, flush, torch)))
         ad.timing(True)
         run()
         torch.cuda.synchronize()
@@ -330,25 +543,33 @@ def batched_leg(args, torch, ad, W, mats):
         ad.timing(False)
         rp = (rows + nm) * 4
         panel = rows * K * s
-        by = {"batch_tv_init": panel,
+        # model bytes per launch (module docstring); the start panel is not
+        # in the model
+        by = {"batch_tv_init": None,
               "batch_jacobi": rp + ents * (4 + s) + 2 * panel,
-              "batch_algdist": rp + ents * 4 + panel + ents * (s + 1) + rows * 4}
+              "batch_algdist": rp + ents * 4 + panel + ents * (s + 1)}
         kern = {}
         for lab, b in by.items():
             cnt, tot = rep[lab]
             kern[lab] = {"launches": cnt, "avg_ms": round(tot / cnt, 5),
-                         "GB/s": round(b / (tot / cnt * 1e-3) / 1e9, 1)}
-        step_bytes = by["batch_tv_init"] + S * by["batch_jacobi"] + by["batch_algdist"]
+                         "model_GB/s": None if b is None else round(b / (tot / cnt * 1e-3) / 1e9, 1)}
+        step_model = S * by["batch_jacobi"] + by["batch_algdist"]
+        jt = rep["batch_jacobi"][1] / rep["batch_jacobi"][0]
         out[tag] = {"value": round(E / (ms * 1e-3), 1), "ms_per_step": round(ms, 4),
+                    "timing": "median of %d graph replays, 1 GiB scratch write between them" % steps,
                     "shapes": shape,
-                    "step_hbm_frac": round(step_bytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                    "step_model_bytes": int(step_model),
+                    "step_hbm_frac": round(step_model / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
                     "kernels": kern,
                     "roofline": {"bound": "hbm", "kernel": "batch_jacobi",
-                                 "achieved": kern["batch_jacobi"]["GB/s"], "peak": HBM_PEAK_GBS,
-                                 "unit": "GB/s",
-                                 "frac": round(kern["batch_jacobi"]["GB/s"] / HBM_PEAK_GBS, 4),
-                                 "traffic": btraffic(tag, "batch_jacobi", shape),
-                                 "algorithmic_bytes_per_launch": int(by["batch_jacobi"])},
+                                 "achieved": kern["batch_jacobi"]["model_GB/s"],
+                                 "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                 "frac": round(kern["batch_jacobi"]["model_GB/s"] / HBM_PEAK_GBS, 4),
+                                 "traffic": (None if tag != "f32" else
+                                             counter_traffic("rgg-batch-fp32", "batch_jacobi",
+                                                             shapes=shape)),
+                                 "algorithmic_bytes_per_launch": int(by["batch_jacobi"]),
+                                 "avg_launch_ms": round(jt, 5)},
                     "device_status_bits": ad.status(clear=True)}
         del dm, X, mu, st, ns
         torch.cuda.empty_cache()
@@ -393,34 +614,119 @@ def adjoint_leg(args, torch, ad, W):
     return out
 
 
-def cpu_baseline(idx, side, min_seconds=10.0, max_passes=8):
-    """The oracle, as it stands, on a bounded sample of the same workload
-    (the same operator family and parameters, on a smaller grid when `side`
-    is given): whole-path passes are repeated until at least `min_seconds`
-    of CPU work has been timed (at most `max_passes`)."""
-    import oracle
-    from paper_1106_5990_amd import workloads as W
-    wl = W.workload(idx, "f64", size=side)
+# ------------------------------------------------------------------ CPU baseline
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def host_threads():
+    try:
+        return len(os.sched_getaffinity(0))
+    except AttributeError:
+        return os.cpu_count() or 1
+
+
+def oracle_pass(oracle, wl, threads):
+    """One whole-path pass of the oracle; returns (X, mu, strong, LS rows).
+    threads > 1: the same oracle functions on disjoint row blocks in
+    parallel threads (its C calls release the interpreter lock), phase by
+    phase and sweep by sweep -- every row is computed by the same code, so
+    the results are identical."""
     A = wl.A
-    passes, dt = 0, 0.0
-    while passes < max_passes and (passes == 0 or dt < min_seconds):
-        t0 = time.perf_counter()
+    if threads <= 1:
         X0 = oracle.tv_init(A.n, wl.K, wl.tv_seed)
         if wl.relax == "gs":
             X, _ = oracle.color_gs(A, X0, wl.color, wl.ncolors, wl.sweeps)
         else:
             X, _ = oracle.jacobi(A, X0, wl.omega, wl.sweeps)
         mu = oracle.algdist(A, X)
-        oracle.strength(A, mu, wl.theta)
-        oracle.ls_interp(A, X, None, wl.cf, mu, wl.caliber)
-        dt += time.perf_counter() - t0
-        passes += 1
-        print("[bench]   cpu baseline pass %d: %.1f s" % (passes, dt), file=sys.stderr, flush=True)
-    return {"value": passes * A.n_edges / dt, "unit": "edges/s", "cores": 1, "kind": "oracle",
+        strong, _ = oracle.strength(A, mu, wl.theta)
+        P = oracle.ls_interp(A, X, None, wl.cf, mu, wl.caliber)
+        return X, mu, strong, P
+    from concurrent.futures import ThreadPoolExecutor
+
+    def blocks(rows):
+        return [b for b in np.array_split(rows, threads) if len(b)]
+    with ThreadPoolExecutor(threads) as ex:
+        allrows = np.arange(A.n, dtype=np.int32)
+        X0 = np.empty((A.n, wl.K))
+        rb = blocks(allrows)
+
+        def init(b):
+            X0[b[0]:b[-1] + 1] = oracle.tv_init(len(b), wl.K, wl.tv_seed, row0=int(b[0]))
+        list(ex.map(init, rb))
+        X = X0
+        for _ in range(wl.sweeps):
+            Xn = np.empty_like(X)
+            if wl.relax == "gs":
+                for c in range(wl.ncolors):
+                    cb = blocks(np.nonzero(wl.color == c)[0].astype(np.int32))
+
+                    def phase(b, X=X, Xn=Xn):
+                        Xn[b] = oracle.color_gs_rows(A, wl.color, wl.ncolors, X, Xn, b)
+                    list(ex.map(phase, cb))
+            else:
+                def sweep(b, X=X, Xn=Xn):
+                    Xn[b] = oracle.jacobi_rows(A, X, wl.omega, b)
+                list(ex.map(sweep, rb))
+            X = Xn
+        rp = A.row_ptr.astype(np.int64)
+        mu = np.empty(A.nnz)
+
+        def dist(b):
+            mu[rp[b[0]]:rp[b[-1] + 1]] = oracle.algdist(A, X, rows=b)
+        list(ex.map(dist, rb))
+        strong, _ = oracle.strength(A, mu, wl.theta)
+
+        def ls(b):
+            return oracle.ls_interp(A, X, None, wl.cf, mu, wl.caliber, rows=b)
+        parts = list(ex.map(ls, rb))
+        P = tuple(np.concatenate([q[k] for q in parts]) for k in range(4))
+        return X, mu, strong, P
+
+
+def cpu_baseline(idx, side, threads, min_seconds=10.0, max_passes=8):
+    """The oracle, as it stands, on a bounded sample of the same workload
+    (the same operator family and parameters, on a smaller grid when `side`
+    is given): whole-path passes are repeated until at least `min_seconds`
+    of CPU time has been timed (at most `max_passes`), single-threaded and
+    on `threads` host threads."""
+    import oracle
+    from paper_1106_5990_amd import workloads as W
+    wl = W.workload(idx, "f64", size=side)
+    A = wl.A
+    res = {}
+    for tag, th, tmin in (("single", 1, min_seconds), ("all_cores", threads, min_seconds / 2)):
+        passes, dt = 0, 0.0
+        while passes < max_passes and (passes == 0 or dt < tmin):
+            t0 = time.perf_counter()
+            oracle_pass(oracle, wl, th)
+            dt += time.perf_counter() - t0
+            passes += 1
+            log("  cpu baseline (%s, %d threads) pass %d: %.1f s" % (tag, th, passes, dt))
+        res[tag] = {"value": passes * A.n_edges / dt, "threads": th, "passes": passes,
+                    "seconds": round(dt, 2)}
+    single = res["single"]
+    return {"value": single["value"], "unit": "edges/s", "cores": 1, "kind": "oracle",
             "sample": "%s (%d rows, %d edges), %d whole-path passes, single-threaded C oracle, "
-                      "%.1f s" % (wl.name, A.n, A.n_edges, passes, dt)}
+                      "%.1f s" % (wl.name, A.n, A.n_edges, single["passes"], single["seconds"]),
+            "all_cores": {"value": res["all_cores"]["value"], "unit": "edges/s",
+                          "cores": res["all_cores"]["threads"],
+                          "sample": "same workload, %d passes, the oracle's row functions on %d "
+                                    "row blocks in %d threads, %.1f s"
+                                    % (res["all_cores"]["passes"], threads, threads,
+                                       res["all_cores"]["seconds"])},
+            "host": {"nproc": os.cpu_count(), "usable_cores": host_threads(),
+                     "cpu_model": cpu_model()}}
 
 
+# ------------------------------------------------------------------ main
 def main():
     args = parse()
     if args.gpus != 1:
@@ -432,59 +738,37 @@ def main():
     if args.batched:
         # the batch members are built in worker processes before anything
         # touches the GPU
-        print("[bench] building the batch", file=sys.stderr, flush=True)
+        log("building the batch")
         workers = args.batch_workers or min(16, os.cpu_count() or 1)
 
         def progress(k):
             if k % 128 == 0:
-                print("[bench]   %d members built" % k, file=sys.stderr, flush=True)
+                log("  %d members built" % k)
         batch = W.batch_workload(args.batch_size, workers=workers, progress=progress)
     import torch
     from paper_1106_5990_amd import algdist as ad
 
-    idx = WORKLOAD_INDEX[args.workload]
-    print("[bench] building %s" % args.workload, file=sys.stderr, flush=True)
-    wl = W.workload(idx, "f32", size=args.size)
-    E = wl.A.n_edges
-
-    res = {}
-    for tag, dtype, steps in (("f32", torch.float32, args.steps),
-                              ("f64", torch.float64, max(3, args.steps // 2))):
-        if tag == "f64" and args.no_fp64:
-            continue
-        b = build_inputs(wl, dtype, torch, ad)
-        step = make_step(wl, b, ad, fused=not args.separate)
-        if not args.no_autotune:
-            # launch shapes picked by the library's autotuner on this matrix
-            # (outside the timed region)
-            print("[bench] autotune %s" % tag, file=sys.stderr, flush=True)
-            cache = args.tune_cache or os.path.join(tempfile.mkdtemp(prefix="algdist_tune_"),
-                                                    "shapes.jsonl")
-            ad.autotune(b["A"], wl.K, relax=wl.relax, color=b["color"], ncolors=wl.ncolors,
-                        cf=b["cf"], caliber=wl.caliber, cache_json=cache)
-            code = ad._dtype_code(dtype)
-            shapes = {e["kernel"]: {k: e[k] for k in ("lpr", "iter", "xcd")}
-                      for e in (json.loads(l) for l in open(cache)) if e["dtype"] == code}
-        else:
-            shapes = "defaults"
-        print("[bench] timing %s leg: %d warmup + %d steps" % (tag, args.warmup, steps),
-              file=sys.stderr, flush=True)
-        ms, wall_ms, kern = timed(step, steps, args.warmup, torch, ad, graph=args.graph)
-        bits = ad.status(clear=True)
-        gms = None
-        if tag == "f32" and not args.graph and not args.no_graph_replay:
-            # the same step captured once and replayed (no per-kernel events)
-            print("[bench] timing %s leg as a graph replay: %d steps" % (tag, steps),
-                  file=sys.stderr, flush=True)
-            gms, _, _ = timed(step, steps, 1, torch, ad, graph=True)
-            bits |= ad.status(clear=True)
-        s = 4 if dtype == torch.float32 else 8
-        kb = kernel_bytes(wl, s)
-        res[tag] = {"ms": ms, "wall_ms": wall_ms, "kernels": kern, "kb": kb, "shapes": shapes,
-                    "graph_ms": gms,
-                    "step_bytes": step_bytes(wl, s, kb, fused=not args.separate), "status": bits, "steps": steps}
-        del b, step
-        torch.cuda.empty_cache()
+    flush = Flusher(torch)
+    legs = {}
+    names = [args.workload]
+    if args.size is None and not args.no_second and args.workload in SECOND:
+        names.append(SECOND[args.workload])
+    for name in names:
+        idx = WORKLOAD_INDEX[name]
+        log("building %s" % name)
+        wl = W.workload(idx, "f32", size=args.size)
+        keep = not args.no_precision and not args.no_fp64
+        r = {"wl": wl}
+        r["f32"], h32 = run_leg(args, wl, "f32", torch.float32, torch, ad, flush, keep)
+        if not args.no_fp64:
+            r["f64"], h64 = run_leg(args, wl, "f64", torch.float64, torch, ad, flush, keep)
+            r["f64"]["speedup_f32_over_f64"] = round(r["f64"]["ms_per_step"]
+                                                     / r["f32"]["ms_per_step"], 3)
+            if keep:
+                log("%s: FP32 chain vs FP64 chain" % name)
+                r["precision"] = precision_statement(wl, h32, h64)
+            del h32, h64
+        legs[name] = r
 
     if args.copy_calibration:
         src = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
@@ -492,72 +776,67 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    main_leg = res["f32"]
-    kern = main_leg["kernels"]
-    ms = main_leg["ms"]
-    value = E / (ms * 1e-3)
-    roof = None
-    kstats = {}
-    for lab, (cnt, tot) in kern.items():
-        avg = tot / cnt
-        by = main_leg["kb"].get(lab)
-        kstats[lab] = {"launches_per_step": cnt / main_leg["steps"], "avg_ms": round(avg, 5),
-                       "GB/s": None if by is None else round(by / (avg * 1e-3) / 1e9, 1)}
-    if kern:
-        dom = max(kern, key=lambda k: kern[k][1])
-        cnt, tot = kern[dom]
-        avg = tot / cnt
-        ach = main_leg["kb"][dom] / (avg * 1e-3) / 1e9
-        tr = (counter_traffic("%s-fp32" % args.workload, dom, shapes=main_leg["shapes"])
-              if args.size is None else None)
-        roof = {"bound": "hbm", "kernel": dom, "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
-                "traffic": None if tr is None else int(tr),
-                "algorithmic_bytes_per_launch": int(main_leg["kb"][dom]),
-                "avg_launch_ms": round(avg, 5)}
+
+    main_leg = legs[args.workload]
+    wl = main_leg["wl"]
+    m = main_leg["f32"]
+    E = wl.A.n_edges
+
+    def config_of(w):
+        return {"workload": w.name, "n": w.A.n, "nnz": w.A.nnz, "edges": w.A.n_edges, "K": w.K,
+                "relax": "%d %s sweeps" % (w.sweeps, "red-black colour-phase GS" if w.relax == "gs"
+                                           else "Jacobi omega=%.3g" % w.omega),
+                "theta": w.theta, "caliber": w.caliber,
+                "precision": "FP32 relaxation and distances, FP64 interpolation solves"}
+    cfg = config_of(wl)
+    cfg["launch_shapes"] = m["launch_shapes"]
     out = {
         "metric": "edges/s (relax+algdist+ls_interp)",
-        "value": round(value, 1),
+        "value": m["value"],
         "unit": "edges/s",
         "n_gpus": 1,
-        "steps": main_leg["steps"],
+        "steps": m["steps"],
         "warmup": args.warmup,
-        "ms_per_step": round(ms, 4),
+        "ms_per_step": m["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": wl.name, "n": wl.A.n, "nnz": wl.A.nnz, "edges": E, "K": wl.K,
-                   "relax": "%d %s sweeps" % (wl.sweeps, "red-black colour-phase GS" if wl.relax == "gs"
-                                              else "Jacobi omega=%.3g" % wl.omega),
-                   "theta": wl.theta, "caliber": wl.caliber,
-                   "precision": "FP32 relaxation and distances, FP64 interpolation solves",
-                   "graph": bool(args.graph), "launch_shapes": main_leg["shapes"]},
-        "roofline": roof,
-        "step_hbm_frac": round(main_leg["step_bytes"] / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
-        "kernels": kstats,
-        "wall_ms_per_step": round(main_leg["wall_ms"], 4),
-        "device_status_bits": main_leg["status"],
-        "graph_replay": None if main_leg["graph_ms"] is None else {
-            "value": round(E / (main_leg["graph_ms"] * 1e-3), 1),
-            "ms_per_step": round(main_leg["graph_ms"], 4)},
+        "config": cfg,
+        "roofline": m["roofline"],
+        "step_hbm_frac": m["step_hbm_frac"],
+        "step_layout_frac": m["step_layout_frac"],
+        "timing": m["timing"],
+        "eager_ms_per_step": m["eager_ms_per_step"],
+        "ms_min_max": m["ms_min_max"],
+        "kernels": m["kernels"],
+        "device_status_bits": m["device_status_bits"],
     }
-    if "f64" in res:
-        r = res["f64"]
-        out["fp64_plain"] = {"value": round(E / (r["ms"] * 1e-3), 1), "ms_per_step": round(r["ms"], 4),
-                             "step_hbm_frac": round(r["step_bytes"] / (r["ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
-                             "speedup_f32_over_f64": round(r["ms"] / ms, 3)}
+    if "f64" in main_leg:
+        out["fp64_plain"] = main_leg["f64"]
+    if "precision" in main_leg:
+        out["precision"] = {wl.name: main_leg["precision"]}
+    for name in names[1:]:
+        r = legs[name]
+        sec = {"config": config_of(r["wl"]), "f32": r["f32"]}
+        if "f64" in r:
+            sec["fp64_plain"] = r["f64"]
+        out[name] = sec
+        if "precision" in r:
+            out.setdefault("precision", {})[r["wl"].name] = r["precision"]
     if args.batched:
-        print("[bench] batched leg (workload 4)", file=sys.stderr, flush=True)
-        out["batched"] = batched_leg(args, torch, ad, W, batch)
+        log("batched leg (workload 4)")
+        out["batched"] = batched_leg(args, torch, ad, W, batch, flush)
     if args.adjoint:
-        print("[bench] adjoint leg (workload 5)", file=sys.stderr, flush=True)
+        log("adjoint leg (workload 5)")
         out["adjoint"] = adjoint_leg(args, torch, ad, W)
     if not args.no_cpu_baseline:
+        idx = WORKLOAD_INDEX[args.workload]
         side = args.cpu_sample or args.size or {1: 32, 2: 2048, 3: 160}[idx]
-        print("[bench] cpu baseline: oracle on a side-%d sample" % side, file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(idx, side)
+        threads = args.cpu_threads or min(16, host_threads())
+        log("cpu baseline: oracle on a side-%d sample" % side)
+        out["cpu_baseline"] = cpu_baseline(idx, side, threads)
     print(json.dumps(out), flush=True)
 
 

@@ -32,6 +32,15 @@
  *   dtype.  Device pointers to panels must be 16-byte aligned.
  * - K must be one of 2, 4, 8, 16, 32, 64.
  * - Calls on one handle must not overlap in time across host threads.
+ * - Graph capture: a call may be made while `stream` is capturing (its
+ *   launches are then recorded into the caller's graph).  Workspace and
+ *   batch tables do not move under such a graph: a call that would have to
+ *   grow the workspace, or upload batch tables for a new argument set,
+ *   during capture returns AD_EUNSUPPORTED (make the same call once
+ *   uncaptured first); buffers a captured graph refers to are kept alive
+ *   until algdist_destroy, even when a later uncaptured call needs larger
+ *   ones.  Replays and other calls on the handle share its workspace as
+ *   scratch, so they must not overlap in time either.
  */
 #ifndef ALGDIST_H
 #define ALGDIST_H
@@ -66,8 +75,8 @@ typedef enum {
 #define AD_STAT_CSR_ROWPTR  0x08u /* csr_validate: row_ptr not nondecreasing or row_ptr[n] != nnz */
 #define AD_STAT_CSR_COLS    0x10u /* csr_validate: column out of range or not strictly increasing */
 #define AD_STAT_CSR_NODIAG  0x20u /* csr_validate: a row has no diagonal entry */
-#define AD_STAT_TIMEOUT     0x40u /* batched path: a bounded inter-workgroup wait gave up */
-#define AD_STAT_ASYMMETRIC  0x80u /* backward: the sparsity pattern is not structurally symmetric */
+#define AD_STAT_RESERVED_40 0x40u /* reserved (never set) */
+#define AD_STAT_RESERVED_80 0x80u /* reserved (never set) */
 
 typedef struct ad_handle_s *ad_handle;
 
@@ -172,9 +181,9 @@ int csr_validate(ad_handle h, const ad_csr *A, void *stream);
 /* 1. test vectors                                                     */
 /* ------------------------------------------------------------------ */
 
-/* Produce K test vectors by relaxing the homogeneous system A x = 0 from
- * K starts (Sec. 3: "relaxing the homogeneous system Ax = 0 with a
- * different starting vector"; Sec. 5.2 uses Gauss-Seidel).
+/* Produce K test vectors by relaxation of the homogeneous system A x = 0,
+ * each from its own start (Sec. 3, test vectors; Sec. 5.2 relaxes them by
+ * Gauss-Seidel).
  *
  * Start: X0 (device, n x K, may be NULL).  When NULL, entry (i, k) is
  * 2u - 1 with u the top 53 bits of output number i*K + k + 1 of splitmix64
@@ -293,12 +302,15 @@ int distance_ls(ad_handle h, const ad_csr *A, int32_t K, const void *X, const do
                 int32_t *nstrong, const uint8_t *cf, int32_t caliber, int32_t *P_col,
                 double *P_val, double *ls_val, int32_t *row_status, double *ls_sum, void *stream);
 
+
 /* ------------------------------------------------------------------ */
 /* batched relaxation + distances                                      */
 /* ------------------------------------------------------------------ */
 
 /* For each of nmat matrices As[m] (host array of device CSRs, one dtype):
- * the test-vector start, `sweeps` damped-Jacobi sweeps with omega, and the
+ * the test-vector start, `sweeps` damped-Jacobi sweeps with omega
+ * (relax = AD_JACOBI; AD_MULTICOLOR_GS returns AD_EUNSUPPORTED: a batch
+ * carries no colouring), and the
  * distances of Sec. 4.1 (plain target) with the fused strength graph of
  * Sec. 4.2 (theta; all rows in F) -- exactly what setup_testvectors +
  * algebraic_distance compute for the block-diagonal matrix made of the
@@ -321,8 +333,8 @@ int distance_ls(ad_handle h, const ad_csr *A, int32_t K, const void *X, const do
  * relaxation stage and ("batched_distance", ...) for the distance stage, or
  * algdist_autotune_batched. */
 int relax_algdist_batched(ad_handle h, int32_t nmat, const ad_csr *As, int32_t K, uint64_t seed,
-                          int32_t sweeps, double omega, const double *w, void *X, void *mu,
-                          double theta, uint8_t *strong, int32_t *nstrong, void *stream);
+                          int32_t relax, int32_t sweeps, double omega, const double *w, void *X,
+                          void *mu, double theta, uint8_t *strong, int32_t *nstrong, void *stream);
 
 /* ------------------------------------------------------------------ */
 /* adjoint of the LS interpolation loss                                */
@@ -338,9 +350,9 @@ int relax_algdist_batched(ad_handle h, int32_t nmat, const ad_csr *As, int32_t K
  * dL/da_ii += omega <y_i, (A x^s)_i> / a_ii, dL/domega -= <y, A x^s>,
  * g <- g - omega A^T y, from the seed g = dL/dx^S.
  *
- * FP64 only (A->dtype == AD_F64).  The sparsity pattern must be
- * structurally symmetric (entry (i, j) stored iff (j, i) is); otherwise
- * AD_STAT_ASYMMETRIC is set and the result is undefined.
+ * FP64 only (A->dtype == AD_F64).  Any sparsity pattern: the products with
+ * A^T and P^T gather through a column-major index of the pattern that the
+ * call builds in the handle's workspace.  1 <= caliber <= min(8, K).
  * Inputs (device): ckpt, the iterates x^0, x^c, x^2c, ... written by
  * setup_testvectors with ckpt_every = c (others are recomputed forward);
  * X_final = x^S; w (K, may be NULL); cf; P_col / P_val (n x caliber) from

@@ -37,8 +37,6 @@ STAT_NONFINITE = 0x04
 STAT_CSR_ROWPTR = 0x08
 STAT_CSR_COLS = 0x10
 STAT_CSR_NODIAG = 0x20
-STAT_TIMEOUT = 0x40
-STAT_ASYMMETRIC = 0x80
 
 STATUS_NAMES = {0: "AD_OK", 1: "AD_EINVAL", 2: "AD_EDTYPE", 3: "AD_ECALIBER", 4: "AD_ESTRUCT",
                 5: "AD_EDEVICE", 6: "AD_ENOMEM", 7: "AD_EUNSUPPORTED"}
@@ -72,8 +70,8 @@ _SIGS = {
     "ls_interp": (_i32, [_P, _CSRP, _i32, _P, _P, _P, _P, _i32, _i32, _P, _P, _P, _P, _P, _P]),
     "distance_ls": (_i32, [_P, _CSRP, _i32, _P, _P, _i32, _P, _f64, _P, _P, _P, _P, _i32, _P, _P, _P,
                            _P, _P, _P]),
-    "relax_algdist_batched": (_i32, [_P, _i32, _CSRP, _i32, _u64, _i32, _f64, _P, _P, _P, _f64, _P,
-                                     _P, _P]),
+    "relax_algdist_batched": (_i32, [_P, _i32, _CSRP, _i32, _u64, _i32, _i32, _f64, _P, _P, _P,
+                                     _f64, _P, _P, _P]),
     "ls_interp_loss_backward": (_i32, [_P, _CSRP, _i32, _P, _i32, _i32, _f64, _P, _P, _P, _P, _i32,
                                        _P, _P, _P, _P, _P]),
 }
@@ -336,6 +334,7 @@ def distance_ls(A: Csr, X: torch.Tensor, cf: torch.Tensor, caliber: int,
 
 def relax_algdist_batched(mats, K: int, seed: int = 0, sweeps: int = 4, omega: float = 2.0 / 3.0,
                           w: Optional[torch.Tensor] = None, theta: float = 0.25, fuse: bool = True,
+                          relax: str = "jacobi",
                           X: Optional[torch.Tensor] = None, mu: Optional[torch.Tensor] = None,
                           strong: Optional[torch.Tensor] = None,
                           nstrong: Optional[torch.Tensor] = None, stream=None):
@@ -354,8 +353,9 @@ def relax_algdist_batched(mats, K: int, seed: int = 0, sweeps: int = 4, omega: f
         strong = strong if strong is not None else torch.empty(ents, dtype=torch.uint8, device=dev)
         nstrong = nstrong if nstrong is not None else torch.empty(rows, dtype=torch.int32, device=dev)
     arr = (ad_csr * len(mats))(*[m._s for m in mats])
-    rc = _lib.relax_algdist_batched(h, len(mats), arr, K, seed & (2 ** 64 - 1), sweeps, float(omega),
-                                    _ptr(w), _ptr(X), _ptr(mu), float(theta),
+    rk = {"jacobi": AD_JACOBI, "gs": AD_MULTICOLOR_GS}[relax]
+    rc = _lib.relax_algdist_batched(h, len(mats), arr, K, seed & (2 ** 64 - 1), rk, sweeps,
+                                    float(omega), _ptr(w), _ptr(X), _ptr(mu), float(theta),
                                     _ptr(strong) if fuse else None, _ptr(nstrong) if fuse else None,
                                     _stream(stream))
     _check(rc, h, "relax_algdist_batched")

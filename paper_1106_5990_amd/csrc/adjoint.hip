@@ -12,8 +12,11 @@
 //   sweep  s = S-1 .. 0:  y = D^{-1} g;
 //          dL/da_ij -= omega <y_i, x_j^s>;  dL/da_ii += omega <y_i, (A x^s)_i> / a_ii;
 //          dL/domega -= <y, A x^s>;  g <- g - omega A^T y.
-// The transpose products are gathers: the pattern must be structurally
-// symmetric, and tp[e] is the position of entry (j, i) for entry e = (i, j).
+// The transpose products are gathers over a column-major (CSC) index of the
+// pattern built here: column j's entries (q, j) sorted by row q, each with
+// its position in the CSR, so any pattern works; for a structurally
+// symmetric one, column i lists the rows of row i's columns in the same
+// order, and the sums are those of a gather through row i.
 // Iterates that are not checkpointed are recomputed forward from the last
 // checkpoint.  Every reduction has a fixed order (no atomics on values).
 #include <math.h>
@@ -23,13 +26,26 @@
 
 namespace ad {
 
-// tp[e] = position of (col[e], i) in row col[e]; -1 (and a status bit) if absent.
-__global__ __launch_bounds__(kBlock) void transpose_perm_kernel(int n, const int* __restrict__ rp,
-                                                                const int* __restrict__ ci,
-                                                                int* __restrict__ tp,
-                                                                double* __restrict__ diag,
-                                                                const double* __restrict__ av,
-                                                                unsigned* status) {
+// ---------------------------------------------------------------- CSC index
+// cnt[j] = entries in column j (cnt zeroed by the caller).
+__global__ __launch_bounds__(kBlock) void col_count_kernel(int64_t nnz, const int* __restrict__ ci,
+                                                           int* __restrict__ cnt) {
+    const int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (e < nnz) atomicAdd(&cnt[ci[e]], 1);
+}
+
+// Row i's entries go to their columns' segments in arrival order (cur
+// zeroed by the caller); the per-column sort below fixes the order.  Also
+// writes the diagonal.
+__global__ __launch_bounds__(kBlock) void col_fill_kernel(int n, const int* __restrict__ rp,
+                                                          const int* __restrict__ ci,
+                                                          const double* __restrict__ av,
+                                                          const int64_t* __restrict__ cp,
+                                                          int* __restrict__ cur,
+                                                          int* __restrict__ trow,
+                                                          int* __restrict__ tent,
+                                                          double* __restrict__ diag,
+                                                          unsigned* status) {
     const int64_t i64 = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (i64 >= n) return;
     const int i = (int)i64;
@@ -37,22 +53,33 @@ __global__ __launch_bounds__(kBlock) void transpose_perm_kernel(int n, const int
     for (int e = rp[i]; e < rp[i + 1]; ++e) {
         const int j = ci[e];
         if (j == i) d = av[e];
-        int lo = rp[j], hi = rp[j + 1] - 1, f = -1;
-        while (lo <= hi) {
-            const int mid = (lo + hi) >> 1;
-            const int c = ci[mid];
-            if (c == i) {
-                f = mid;
-                break;
-            }
-            if (c < i) lo = mid + 1;
-            else hi = mid - 1;
-        }
-        tp[e] = f;
-        if (f < 0) flag(status, AD_STAT_ASYMMETRIC);
+        const int64_t f = cp[j] + atomicAdd(&cur[j], 1);
+        trow[f] = i;
+        tent[f] = e;
     }
     diag[i] = d;
     if (d == 0.0) flag(status, AD_STAT_ZERO_DIAG);
+}
+
+// Sorts each column's (row, entry) pairs by row (insertion sort: columns
+// hold a handful of entries), one column per thread.
+__global__ __launch_bounds__(kBlock) void col_sort_kernel(int n, const int64_t* __restrict__ cp,
+                                                          int* __restrict__ trow,
+                                                          int* __restrict__ tent) {
+    const int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (j >= n) return;
+    const int64_t a = cp[j], b = cp[j + 1];
+    for (int64_t f = a + 1; f < b; ++f) {
+        const int r = trow[f], t = tent[f];
+        int64_t g = f - 1;
+        while (g >= a && trow[g] > r) {
+            trow[g + 1] = trow[g];
+            tent[g + 1] = tent[g];
+            --g;
+        }
+        trow[g + 1] = r;
+        tent[g + 1] = t;
+    }
 }
 
 // R_i = 2 dL w .* rho_i for F rows (rho = x_i - sum_q P_val[i,q] x_{P_col[i,q]}), 0 for C rows.
@@ -92,10 +119,11 @@ __global__ __launch_bounds__(kBlock) void ls_residual_kernel(int n, const double
     store_lane<double, V, C>(R + (size_t)i * K + l * V, r);
 }
 
-// g_j = R_j - sum over neighbours q of j that interpolate from j of p_qj R_q.
+// g_j = R_j - sum over the rows q that interpolate from j of p_qj R_q (every
+// such q stores (q, j), so they are found in column j).
 template <int K, int LPR>
-__global__ __launch_bounds__(kBlock) void ls_seed_kernel(int n, const int* __restrict__ rp,
-                                                         const int* __restrict__ ci,
+__global__ __launch_bounds__(kBlock) void ls_seed_kernel(int n, const int64_t* __restrict__ cp,
+                                                         const int* __restrict__ trow,
                                                          const uint8_t* __restrict__ cf,
                                                          const int* __restrict__ Pcol,
                                                          const double* __restrict__ Pval, int cal,
@@ -109,8 +137,8 @@ __global__ __launch_bounds__(kBlock) void ls_seed_kernel(int n, const int* __res
     if (j64 >= n) return;
     const int j = (int)j64;
     Frag<double, V> acc = load_lane<double, V, C>(R + (size_t)j * K + l * V);
-    for (int e = rp[j]; e < rp[j + 1]; ++e) {
-        const int q = ci[e];
+    for (int64_t f = cp[j]; f < cp[j + 1]; ++f) {
+        const int q = trow[f];  // (q, j) is stored
         if (q == j || cf[q]) continue;
         double p = 0.0;
         bool hit = false;
@@ -146,13 +174,14 @@ __global__ __launch_bounds__(kBlock) void dinv_kernel(int n, const double* __res
 }
 
 // One backward sweep for row i:
-//   z_i = (A x^s)_i, (A^T y)_i = sum_e a[tp[e]] y_{col e},
+//   z_i = (A x^s)_i, (A^T y)_i = sum over column i's entries (r, i) of a_ri y_r,
 //   gval[e] -= omega <y_i, x_col e>,  gval[diag] += omega <y_i, z_i> / a_ii,
 //   Gout_i = Gin_i - omega (A^T y)_i,  block partial of -<y_i, z_i>.
 template <int K, int LPR>
 __global__ __launch_bounds__(kBlock) void adjoint_sweep_kernel(
     int n, const int* __restrict__ rp, const int* __restrict__ ci, const double* __restrict__ av,
-    const int* __restrict__ tp, const double* __restrict__ diag, const double* __restrict__ Xs,
+    const int64_t* __restrict__ cp, const int* __restrict__ trow, const int* __restrict__ tent,
+    const double* __restrict__ diag, const double* __restrict__ Xs,
     const double* __restrict__ Y, const double* __restrict__ Gin, double* __restrict__ Gout,
     double omega, double* __restrict__ gval, double* __restrict__ wpart) {
     using S = Shape<double, K, LPR>;
@@ -177,20 +206,23 @@ __global__ __launch_bounds__(kBlock) void adjoint_sweep_kernel(
         for (int e = e0; e < e1; ++e) {
             const int j = ci[e];
             const double a = av[e];
-            const int t = tp[e];
-            const double at = (t >= 0) ? av[t] : 0.0;
             const Frag<double, V> xj = load_lane<double, V, C>(Xs + (size_t)j * K + l * V);
-            const Frag<double, V> yj = load_lane<double, V, C>(Y + (size_t)j * K + l * V);
             double dot = 0.0;
 #pragma unroll
             for (int q = 0; q < V; ++q) {
                 z[q] = fma(a, xj.v[q], z[q]);
-                aty[q] = fma(at, yj.v[q], aty[q]);
                 dot = fma(yi.v[q], xj.v[q], dot);
             }
             dot = group_sum<LPR>(dot);
             if (j == i) ediag = e;
             if (l == 0) gval[e] -= omega * dot;
+        }
+        for (int64_t f = cp[i]; f < cp[i + 1]; ++f) {
+            const int r = trow[f];
+            const double at = av[tent[f]];
+            const Frag<double, V> yr = load_lane<double, V, C>(Y + (size_t)r * K + l * V);
+#pragma unroll
+            for (int q = 0; q < V; ++q) aty[q] = fma(at, yr.v[q], aty[q]);
         }
         double yz = 0.0;
 #pragma unroll
@@ -215,11 +247,6 @@ __global__ __launch_bounds__(kBlock) void adjoint_sweep_kernel(
         for (int q = 0; q < kWavesPerBlock; ++q) s += part[q];
         wpart[blockIdx.x] = s;
     }
-}
-
-__global__ __launch_bounds__(kBlock) void fill_kernel(double* __restrict__ p, int64_t m, double v) {
-    const int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (q < m) p[q] = v;
 }
 
 // Fixed-order sum of m partials into *out (one workgroup of 1024 threads).
@@ -255,17 +282,25 @@ static int adjoint_go(ad_handle h, const ad_csr* A, const void* ckpt, int ce, in
     const int extra = ce - 1;  // recomputed iterates inside one checkpoint segment
 
     WsReq req;
-    const size_t o_tp = req.add(sizeof(int) * (size_t)nnz);
+    const size_t o_cnt = req.add(sizeof(int) * (size_t)n);
+    const size_t o_cp = req.add(sizeof(int64_t) * ((size_t)n + 1));
+    const size_t o_sc = req.add((size_t)scan_workspace_bytes(n));
+    const size_t o_tr = req.add(sizeof(int) * (size_t)nnz);
+    const size_t o_te = req.add(sizeof(int) * (size_t)nnz);
     const size_t o_dg = req.add(sizeof(double) * (size_t)n);
     const size_t o_g0 = req.add(panel);
     const size_t o_g1 = req.add(panel);
     const size_t o_y = req.add(panel);
     const size_t o_xr = req.add(panel * (size_t)(extra > 0 ? extra : 0));
     const size_t o_wp = req.add(sizeof(double) * (size_t)rblocks * (sweeps > 0 ? sweeps : 1));
-    int rc = ws_reserve(h, req.off);
+    int rc = ws_reserve(h, req.off, s);
     if (rc) return rc;
     char* ws = (char*)h->ws;
-    int* tp = (int*)(ws + o_tp);
+    int* cnt = (int*)(ws + o_cnt);
+    int64_t* cp = (int64_t*)(ws + o_cp);
+    int64_t* sc = (int64_t*)(ws + o_sc);
+    int* trow = (int*)(ws + o_tr);
+    int* tent = (int*)(ws + o_te);
     double* diag = (double*)(ws + o_dg);
     double* G[2] = {(double*)(ws + o_g0), (double*)(ws + o_g1)};
     double* Y = (double*)(ws + o_y);
@@ -273,14 +308,22 @@ static int adjoint_go(ad_handle h, const ad_csr* A, const void* ckpt, int ce, in
     double* wp = (double*)(ws + o_wp);
     const double* av = (const double*)A->val;
 
-    transpose_perm_kernel<<<dim3(nblk_n), dim3(kBlock), 0, s>>>(n, A->row_ptr, A->col, tp, diag, av,
-                                                                h->status);
-    fill_kernel<<<dim3(nblk_e > 0 ? nblk_e : 1), dim3(kBlock), 0, s>>>(grad_val, nnz, 0.0);
+    // column-major index of the pattern
+    if ((rc = launch_fill_i32(cnt, n, 0, s))) return rc;
+    col_count_kernel<<<dim3(nblk_e > 0 ? nblk_e : 1), dim3(kBlock), 0, s>>>(nnz, A->col, cnt);
+    AD_HIP(hipGetLastError());
+    if ((rc = launch_excl_scan(cnt, n, cp, sc, s))) return rc;
+    if ((rc = launch_fill_i32(cnt, n, 0, s))) return rc;
+    col_fill_kernel<<<dim3(nblk_n), dim3(kBlock), 0, s>>>(n, A->row_ptr, A->col, av, cp, cnt, trow,
+                                                          tent, diag, h->status);
+    col_sort_kernel<<<dim3(nblk_n), dim3(kBlock), 0, s>>>(n, cp, trow, tent);
+    AD_HIP(hipGetLastError());
+    if ((rc = launch_fill_f64(grad_val, nnz, 0.0, s))) return rc;
     // seed: R into Y (as scratch), then g into G[0]
     ls_residual_kernel<K, LPR><<<dim3(rblocks), dim3(kBlock), 0, s>>>(
         n, (const double*)X_final, w, cf, P_col, P_val, cal, dL, Y);
-    ls_seed_kernel<K, LPR><<<dim3(rblocks), dim3(kBlock), 0, s>>>(n, A->row_ptr, A->col, cf, P_col,
-                                                                   P_val, cal, Y, G[0]);
+    ls_seed_kernel<K, LPR><<<dim3(rblocks), dim3(kBlock), 0, s>>>(n, cp, trow, cf, P_col, P_val,
+                                                                   cal, Y, G[0]);
     AD_HIP(hipGetLastError());
     int cur = 0;
     const int nseg = (sweeps + ce - 1) / ce;
@@ -299,7 +342,8 @@ static int adjoint_go(ad_handle h, const ad_csr* A, const void* ckpt, int ce, in
             const double* xs = (st == s0) ? xck : Xr + (size_t)(st - s0 - 1) * n * K;
             dinv_kernel<K, LPR><<<dim3(rblocks), dim3(kBlock), 0, s>>>(n, diag, G[cur], Y);
             adjoint_sweep_kernel<K, LPR><<<dim3(rblocks), dim3(kBlock), 0, s>>>(
-                n, A->row_ptr, A->col, av, tp, diag, xs, Y, G[cur], G[cur ^ 1], omega, grad_val,
+                n, A->row_ptr, A->col, av, cp, trow, tent, diag, xs, Y, G[cur], G[cur ^ 1], omega,
+                grad_val,
                 wp + (size_t)st * rblocks);
             AD_HIP(hipGetLastError());
             cur ^= 1;

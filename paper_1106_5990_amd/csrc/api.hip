@@ -29,6 +29,14 @@ bool k_ok(int K) { return K == 2 || K == 4 || K == 8 || K == 16 || K == 32 || K 
 size_t dsize(int dtype) { return dtype == AD_F32 ? 4 : 8; }
 bool aligned16(const void* p) { return ((uintptr_t)p & 15u) == 0; }
 
+// the reason appended to a failed workspace reservation
+const char* ws_why(int rc) {
+    return rc == AD_EUNSUPPORTED
+               ? ": the workspace would have to grow while the stream is capturing; make the "
+                 "same call once uncaptured first"
+               : "";
+}
+
 // Common CSR argument checks (host side: sizes and pointers only).
 int check_csr(ad_handle h, const ad_csr* A) {
     if (!A) return fail(h, AD_EINVAL, "A is NULL");
@@ -103,11 +111,29 @@ LaunchCfg cfg_for(ad_handle h, int kernel, int dtype, int K, const ad_csr* A) {
     return LaunchCfg();
 }
 
-int ws_reserve(ad_handle h, size_t bytes) {
-    if (bytes <= h->ws_bytes) return AD_OK;
-    // earlier calls may still use the old buffer
-    AD_HIP(hipDeviceSynchronize());
-    if (h->ws) AD_HIP(hipFree(h->ws));
+bool stream_capturing(hipStream_t s) {
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(s, &cs) != hipSuccess) return false;
+    return cs != hipStreamCaptureStatusNone;
+}
+
+int ws_reserve(ad_handle h, size_t bytes, hipStream_t s) {
+    const bool cap = stream_capturing(s);
+    if (bytes <= h->ws_bytes) {
+        if (cap) h->ws_pinned = true;  // the caller's graph now refers to this buffer
+        return AD_OK;
+    }
+    // a buffer cannot move under a graph being captured
+    if (cap) return AD_EUNSUPPORTED;
+    if (h->ws_pinned) {
+        // a captured graph may still replay on the old buffer: keep it
+        if (h->ws) h->retired.push_back(h->ws);
+        h->ws_pinned = false;
+    } else {
+        // earlier calls may still use the old buffer
+        AD_HIP(hipDeviceSynchronize());
+        if (h->ws) AD_HIP(hipFree(h->ws));
+    }
     h->ws = nullptr;
     h->ws_bytes = 0;
     size_t want = bytes + bytes / 4;
@@ -155,6 +181,7 @@ int algdist_destroy(ad_handle h) {
     (void)hipSetDevice(h->device);
     (void)hipDeviceSynchronize();
     if (h->ws) (void)hipFree(h->ws);
+    for (void* p : h->retired) (void)hipFree(p);
     if (h->status) (void)hipFree(h->status);
     for (hipEvent_t e : h->event_pool) (void)hipEventDestroy(e);
     batch_state_free(h);
@@ -318,7 +345,8 @@ static int gs_sweeps(ad_handle h, const ad_csr* A, int K, uint64_t seed, const v
     const size_t o_seg = req.add(sizeof(int32_t) * (ncolors + 2));
     const size_t o_cnt = req.add(sizeof(int32_t) * 2 * (size_t)(ncolors + 1) * nblk);
     int rc;
-    if ((rc = ws_reserve(h, req.off))) return fail(h, rc, "workspace of %zu bytes", req.off);
+    if ((rc = ws_reserve(h, req.off, s)))
+        return fail(h, rc, "workspace of %zu bytes%s", req.off, ws_why(rc));
     char* ws = (char*)h->ws;
     void* P[2] = {ws + o_pa, ws + o_pb};
     int32_t* rowlist = (int32_t*)(ws + o_rl);
@@ -393,7 +421,8 @@ int setup_testvectors(ad_handle h, const ad_csr* A, int32_t K, uint64_t seed, co
     // Jacobi (or no sweep).  Workspace: one extra panel for the ping-pong.
     WsReq req;
     const size_t o_pp = req.add(panel);
-    if ((rc = ws_reserve(h, req.off))) return fail(h, rc, "workspace of %zu bytes", req.off);
+    if ((rc = ws_reserve(h, req.off, s)))
+        return fail(h, rc, "workspace of %zu bytes%s", req.off, ws_why(rc));
     void* W = (char*)h->ws + o_pp;
 
     // Buffer of iterate q (0..sweeps): x^sweeps lands in X; a checkpointed
@@ -484,8 +513,8 @@ int ls_interp(ad_handle h, const ad_csr* A, int32_t K, const void* X, const doub
     double* bs = nullptr;
     if (ls_sum && A->n > 0) {
         const int nb = ls_interp_blocks(A->dtype, K, A->n, cfg);
-        if ((rc = ws_reserve(h, sizeof(double) * (size_t)nb)))
-            return fail(h, rc, "workspace for %d block sums", nb);
+        if ((rc = ws_reserve(h, sizeof(double) * (size_t)nb, (hipStream_t)stream)))
+            return fail(h, rc, "workspace for %d block sums%s", nb, ws_why(rc));
         bs = (double*)h->ws;
     }
     TimedScope ts(h, "ls_interp", (hipStream_t)stream);
@@ -494,10 +523,15 @@ int ls_interp(ad_handle h, const ad_csr* A, int32_t K, const void* X, const doub
     return rc ? fail(h, rc, "ls_interp launch") : AD_OK;
 }
 
-int distance_ls(ad_handle h, const ad_csr* A, int32_t K, const void* X, const double* w,
-                int32_t target, void* mu, double theta, const uint8_t* fmask, uint8_t* strong,
-                int32_t* nstrong, const uint8_t* cf, int32_t caliber, int32_t* P_col,
-                double* P_val, double* ls_val, int32_t* row_status, double* ls_sum, void* stream) {
+}  // extern "C"
+
+// distance_ls: the block partial sums of ls_sum live in the handle's
+// workspace (grown on demand).
+static int distance_ls_impl(ad_handle h, const ad_csr* A, int32_t K, const void* X,
+                            const double* w, int32_t target, void* mu, double theta,
+                            const uint8_t* fmask, uint8_t* strong, int32_t* nstrong,
+                            const uint8_t* cf, int32_t caliber, int32_t* P_col, double* P_val,
+                            double* ls_val, int32_t* row_status, double* ls_sum, void* stream) {
     if (!h) return AD_EINVAL;
     h->err.clear();
     int rc = check_csr(h, A);
@@ -515,16 +549,14 @@ int distance_ls(ad_handle h, const ad_csr* A, int32_t K, const void* X, const do
     if (A->n > 0 && (!cf || !P_col || !P_val || !ls_val || !row_status))
         return fail(h, AD_EINVAL, "null output or input array");
     AD_HIP(hipSetDevice(h->device));
-    if (A->n == 0) {
-        if (ls_sum) AD_HIP(hipMemsetAsync(ls_sum, 0, sizeof(double), (hipStream_t)stream));
-        return AD_OK;
-    }
+    if (A->n == 0) return ls_sum ? launch_fill_f64(ls_sum, 1, 0.0, (hipStream_t)stream) : AD_OK;
     const LaunchCfg cfg = cfg_for(h, KN_DLS, A->dtype, K, A);
     double* bs = nullptr;
     if (ls_sum) {
         const int nb = dist_ls_blocks(A->dtype, K, A->n, cfg);
-        if ((rc = ws_reserve(h, sizeof(double) * (size_t)nb)))
-            return fail(h, rc, "workspace for %d block sums", nb);
+        const size_t need = sizeof(double) * (size_t)nb;
+        if ((rc = ws_reserve(h, need, (hipStream_t)stream)))
+            return fail(h, rc, "workspace for %d block sums%s", nb, ws_why(rc));
         bs = (double*)h->ws;
     }
     TimedScope ts(h, "distance_ls", (hipStream_t)stream);
@@ -534,12 +566,27 @@ int distance_ls(ad_handle h, const ad_csr* A, int32_t K, const void* X, const do
     return rc ? fail(h, rc, "distance_ls launch") : AD_OK;
 }
 
+extern "C" {
+
+int distance_ls(ad_handle h, const ad_csr* A, int32_t K, const void* X, const double* w,
+                int32_t target, void* mu, double theta, const uint8_t* fmask, uint8_t* strong,
+                int32_t* nstrong, const uint8_t* cf, int32_t caliber, int32_t* P_col,
+                double* P_val, double* ls_val, int32_t* row_status, double* ls_sum, void* stream) {
+    return distance_ls_impl(h, A, K, X, w, target, mu, theta, fmask, strong, nstrong, cf, caliber,
+                            P_col, P_val, ls_val, row_status, ls_sum, stream);
+}
+
 int relax_algdist_batched(ad_handle h, int32_t nmat, const ad_csr* As, int32_t K, uint64_t seed,
-                          int32_t sweeps, double omega, const double* w, void* X, void* mu,
-                          double theta, uint8_t* strong, int32_t* nstrong, void* stream) {
+                          int32_t relax, int32_t sweeps, double omega, const double* w, void* X,
+                          void* mu, double theta, uint8_t* strong, int32_t* nstrong,
+                          void* stream) {
     if (!h) return AD_EINVAL;
     h->err.clear();
     if (nmat < 1 || !As) return fail(h, AD_EINVAL, "nmat = %d or As is NULL", nmat);
+    if (relax == AD_MULTICOLOR_GS)
+        return fail(h, AD_EUNSUPPORTED,
+                    "the batched path relaxes by damped Jacobi only (a batch carries no colouring)");
+    if (relax != AD_JACOBI) return fail(h, AD_EINVAL, "relax = %d", relax);
     int rc;
     int64_t rows = 0, ents = 0;
     for (int m = 0; m < nmat; ++m) {
@@ -583,16 +630,15 @@ int ls_interp_loss_backward(ad_handle h, const ad_csr* A, int32_t K, const void*
     if (sweeps < 0) return fail(h, AD_EINVAL, "sweeps = %d < 0", sweeps);
     if (ckpt_every < 1) return fail(h, AD_EINVAL, "ckpt_every = %d < 1", ckpt_every);
     if (caliber < 1 || caliber > 8) return fail(h, AD_ECALIBER, "caliber = %d outside [1, 8]", caliber);
+    if (caliber > K)
+        return fail(h, AD_ECALIBER, "caliber = %d > K = %d: LS rows would not be unique", caliber, K);
     if (!grad_omega || !dL) return fail(h, AD_EINVAL, "grad_omega or dL is NULL");
     if (A->n > 0 && (!ckpt || !X_final || !cf || !P_col || !P_val || !grad_val))
         return fail(h, AD_EINVAL, "null input or output array");
     if ((rc = check_panel(h, ckpt, "ckpt", A->n)) || (rc = check_panel(h, X_final, "X_final", A->n)))
         return rc;
     AD_HIP(hipSetDevice(h->device));
-    if (A->n == 0) {
-        AD_HIP(hipMemsetAsync(grad_omega, 0, sizeof(double), (hipStream_t)stream));
-        return AD_OK;
-    }
+    if (A->n == 0) return launch_fill_f64(grad_omega, 1, 0.0, (hipStream_t)stream);
     TimedScope ts(h, "ls_loss_backward", (hipStream_t)stream);
     rc = launch_ls_loss_backward(h, K, A, ckpt, ckpt_every, sweeps, omega, w, cf, P_col, P_val,
                                  caliber, X_final, dL, grad_val, grad_omega, (hipStream_t)stream);

@@ -4,8 +4,10 @@
 // valid shape of each family is timed with HIP events on scratch buffers:
 //   lanes per row L (K / L panel entries per lane: the panel width a lane
 //   owns; 64 / L rows per wavefront), rows per lane group per tile
-//   (1, 2, 4), and the XCD-contiguous tile mapping on or off; for the
-//   distances also L = 0, the edge-parallel form (one lane per entry).
+//   (1, 2, 4), and the tile-to-XCD mapping (0: plain block order; 1: one
+//   contiguous tile range per XCD; c in {4, 16, 64, 256}: chunks of 8c
+//   tiles, c contiguous tiles per XCD in each); for the distances also
+//   L = 0, the edge-parallel form (one lane per entry).
 // The fastest shape per family is stored in the handle (the same slot
 // algdist_set_launch writes) and, if a cache path is given, in a JSON file:
 // one object per line,

@@ -154,6 +154,9 @@ struct BatchState {
     void* host_stage = nullptr;  // pinned staging for the tables
     size_t host_bytes = 0;
     hipStream_t cap = nullptr;   // private stream used only for graph capture
+    // true once a call ran inside a caller's stream capture: that graph refers
+    // to `dev`, which is then never rewritten for another argument set
+    bool pinned = false;
 };
 
 BatchState* state_of(ad_handle h) {
@@ -334,9 +337,20 @@ int launch_batched(ad_handle h, int nmat, const ad_csr* As, int K, uint64_t seed
     const size_t o_tiles = req.add(sizeof(BatchTile) * (size_t)(ntiles > 0 ? ntiles : 1));
     const size_t o_dtiles = req.add(sizeof(BatchTile) * (size_t)(ndist > 0 ? ndist : 1));
     const bool same = key == bs->plan.key && bs->dev_bytes >= req.off;
+    const bool capturing = stream_capturing(s);
     if (!same) {
+        // the tables are uploaded from the host: not inside a caller's capture
+        if (capturing) return AD_EUNSUPPORTED;
         drop_graph(bs->plan);
         bs->plan.key.clear();
+        if (bs->pinned) {
+            // a caller's captured graph refers to the current buffer: keep it
+            // alive and give this argument set a buffer of its own
+            if (bs->dev) h->retired.push_back(bs->dev);
+            bs->dev = nullptr;
+            bs->dev_bytes = 0;
+            bs->pinned = false;
+        }
         if (bs->dev_bytes < req.off) {
             AD_HIP(hipDeviceSynchronize());  // earlier launches may still use the old buffer
             if (bs->dev) AD_HIP(hipFree(bs->dev));
@@ -421,9 +435,11 @@ int launch_batched(ad_handle h, int nmat, const ad_csr* As, int K, uint64_t seed
     q.strong = strong;
     q.nstrong = nstrong;
     q.status = h->status;
-    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
-    AD_HIP(hipStreamIsCapturing(s, &cs));
-    if (direct || cs != hipStreamCaptureStatusNone) return run_seq(q, s);  // caller records it
+    if (capturing) {
+        bs->pinned = true;  // the caller's graph now refers to the tables and panel
+        return run_seq(q, s);
+    }
+    if (direct) return run_seq(q, s);
     if (!bs->plan.exec) {
         if (!bs->cap) AD_HIP(hipStreamCreateWithFlags(&bs->cap, hipStreamNonBlocking));
         AD_HIP(hipStreamBeginCapture(bs->cap, hipStreamCaptureModeThreadLocal));

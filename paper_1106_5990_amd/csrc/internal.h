@@ -44,6 +44,11 @@ struct ad_handle_s {
     unsigned* status = nullptr;  // sticky device status word
     void* ws = nullptr;          // workspace (grown on demand)
     size_t ws_bytes = 0;
+    // true once a call has run while its stream was capturing: a caller's
+    // graph may then refer to the current workspace, which is kept alive
+    // (moved to `retired`) instead of being freed when it must grow
+    bool ws_pinned = false;
+    std::vector<void*> retired;  // device buffers freed by algdist_destroy
     std::string err;
     int cu_count = 256;
     // per-kernel timing (algdist_timing / algdist_timing_report)
@@ -112,7 +117,13 @@ struct WsReq {
         return o;
     }
 };
-int ws_reserve(ad_handle h, size_t bytes);
+// Grows the workspace to at least `bytes`.  While `s` is capturing, growth
+// is refused (AD_EUNSUPPORTED: a captured graph must not see its buffers
+// move), and the current buffer is marked as referenced by a graph; a buffer
+// so marked is retired, not freed, when a later uncaptured call grows it.
+int ws_reserve(ad_handle h, size_t bytes, hipStream_t s);
+// true when `s` is capturing into a graph
+bool stream_capturing(hipStream_t s);
 
 // Records HIP events around the launches made in its lifetime when the
 // handle's timing is on (no-op otherwise).
@@ -127,6 +138,14 @@ class TimedScope {
     hipStream_t s_;
     hipEvent_t a_ = nullptr;
 };
+
+// ---- util.hip
+int launch_fill_f64(double* p, int64_t m, double v, hipStream_t s);
+int launch_fill_i32(int32_t* p, int64_t m, int32_t v, hipStream_t s);
+// out[0] = 0, out[q + 1] = cnt[0] + ... + cnt[q] (q < m); tmp holds
+// scan_workspace_bytes(m) bytes
+int64_t scan_workspace_bytes(int64_t m);
+int launch_excl_scan(const int32_t* cnt, int64_t m, int64_t* out, int64_t* tmp, hipStream_t s);
 
 // ---- relax.hip
 int launch_tv_init(int dtype, int64_t row0, int64_t nrows, int K, uint64_t seed, void* X,

@@ -387,8 +387,7 @@ int launch_dist_ls(int dtype, int K, int caliber, const ad_csr* A, const void* X
                    double* ls_val, int32_t* row_status, double* block_sums, double* ls_sum,
                    unsigned* status, const LaunchCfg& cfg, hipStream_t s) {
     if (A->n == 0) {
-        if (ls_sum) AD_HIP(hipMemsetAsync(ls_sum, 0, sizeof(double), s));
-        return AD_OK;
+        return ls_sum ? launch_fill_f64(ls_sum, 1, 0.0, s) : AD_OK;
     }
     double* bs = ls_sum ? block_sums : nullptr;
     const int rc = (dtype == AD_F32)
@@ -414,8 +413,7 @@ int launch_ls_interp(int dtype, int K, int caliber, const ad_csr* A, const void*
                      double* block_sums, double* ls_sum, unsigned* status,
                      const LaunchCfg& cfg, hipStream_t s) {
     if (A->n == 0) {
-        if (ls_sum) AD_HIP(hipMemsetAsync(ls_sum, 0, sizeof(double), s));
-        return AD_OK;
+        return ls_sum ? launch_fill_f64(ls_sum, 1, 0.0, s) : AD_OK;
     }
     double* bs = ls_sum ? block_sums : nullptr;
     const int rc = (dtype == AD_F32)

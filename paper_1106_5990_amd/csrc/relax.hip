@@ -364,9 +364,9 @@ int launch_color_partition(int n, const int32_t* color, int ncolors, const int32
                            int32_t* rowlist, int32_t* inv, int32_t* seg, int32_t* counts,
                            int nblocks, int32_t* rpp, unsigned* status, hipStream_t s) {
     if (n == 0) {
-        AD_HIP(hipMemsetAsync(seg, 0, sizeof(int32_t) * (ncolors + 2), s));
-        if (rpp) AD_HIP(hipMemsetAsync(rpp, 0, sizeof(int32_t), s));
-        return AD_OK;
+        int rc = launch_fill_i32(seg, ncolors + 2, 0, s);
+        if (!rc && rpp) rc = launch_fill_i32(rpp, 1, 0, s);
+        return rc;
     }
     const int* rpu = rpp ? rp : nullptr;
     color_count_kernel<<<dim3(nblocks), dim3(kBlock), 0, s>>>(n, color, ncolors, rpu, counts,

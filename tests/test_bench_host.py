@@ -80,3 +80,69 @@ def test_counter_summary_is_used_only_for_matching_sources(tmp_path, monkeypatch
     assert bench.counter_traffic("x-fp32", "gs_phase", shapes="defaults") is None
     # families the summary does not record are not checked
     assert bench.counter_traffic("x-fp32", "distance_ls", shapes=other) == pytest.approx((7 * 2 + 9) * 1024)
+
+
+def test_model_bytes_reproduce_the_planned_table():
+    """The step byte model on the full-size anisotropic (9-point, 2048^2,
+    K = 16, 5 sweeps) and 3D log-normal (160^3, K = 32, 4 sweeps) workloads:
+    5.30 / 9.37 GB and 6.46 / 12.07 GB (FP32 / FP64); a colour phase is half
+    a sweep."""
+    w2 = W.workload(2)
+    m32, m64 = bench.model_bytes(w2, 4), bench.model_bytes(w2, 8)
+    assert m32["step"] / 1e9 == pytest.approx(5.30, abs=0.006)
+    assert m64["step"] / 1e9 == pytest.approx(9.37, abs=0.006)
+    assert m32["sweep"] / 1e6 == pytest.approx(855.4, abs=0.1)
+    assert bench.kernel_model_bytes(w2, 4)["gs_phase"] == pytest.approx(m32["sweep"] / 2)
+    w3 = W.workload(3)
+    assert bench.model_bytes(w3, 4)["step"] / 1e9 == pytest.approx(6.46, abs=0.006)
+    assert bench.model_bytes(w3, 8)["step"] / 1e9 == pytest.approx(12.07, abs=0.006)
+
+
+@pytest.mark.parametrize("idx", [2, 3])
+def test_threaded_oracle_pass_equals_the_single_threaded_one(idx):
+    """The all-cores CPU baseline runs the oracle's row functions on row
+    blocks in threads: bitwise the single-threaded pass."""
+    import oracle
+    wl = W.workload(idx, "f64", size=24 if idx == 2 else 10)
+    a = bench.oracle_pass(oracle, wl, 1)
+    b = bench.oracle_pass(oracle, wl, 4)
+    for x, y in zip(a[:3], b[:3]):
+        assert np.array_equal(x, y)
+    for x, y in zip(a[3], b[3]):
+        assert np.array_equal(x, y)
+
+
+def test_precision_statement_counts_flips_by_band():
+    """Host arithmetic of the FP32-vs-FP64 statement on a planted case."""
+    wl = W.workload(1)
+    A = wl.A
+    rng = np.random.default_rng(0)
+    mu64 = rng.random(A.nnz) + 0.5
+    rid = A.row_ids()
+    mu64[A.col == rid] = 0.0
+    import oracle
+    s64, _ = oracle.strength(A, mu64, wl.theta)
+    mu32 = mu64 * (1 + 1e-7)
+    s32 = s64.copy()
+    n, cal = A.n, wl.caliber
+    Pc = np.tile(np.arange(cal, dtype=np.int32), (n, 1))
+    Pv = rng.random((n, cal))
+    ls = rng.random(n)
+    st = np.zeros(n, np.int32)
+    r64 = {"mu": mu64, "strong": s64, "Pc": Pc, "Pv": Pv, "ls": ls, "st": st}
+    Pv32 = Pv + 1e-8
+    Pc32 = Pc.copy()
+    Pc32[3] = -1  # one row whose C_i differ
+    r32 = {"mu": mu32.astype(np.float32), "strong": s32, "Pc": Pc32, "Pv": Pv32, "ls": ls, "st": st}
+    # flip one strong edge: it lies far from the threshold
+    e = int(np.nonzero(s64)[0][0])
+    r32["strong"] = s32.copy()
+    r32["strong"][e] ^= 1
+    out = bench.precision_statement(wl, r32, r64)
+    assert out["mask"]["flips"] == 1
+    assert out["mask"]["flips_outside_twice_measured_error"] == 1
+    assert sum(out["mask"]["flips_by_margin"].values()) == 1
+    F = wl.cf == 0
+    assert out["P_val_scaled_err"]["rows_C_differ"] == int(F[3])
+    assert out["P_val_scaled_err"]["max"] == pytest.approx(1e-8, rel=1e-3)
+    assert out["mu_rel_err"]["max"] < 2e-7
