@@ -189,3 +189,110 @@ def ls_loss_grad(A, X0, sweeps: int, omega: float, w, cf, caliber: int):
     L = lib().oracle_ls_loss_grad(n, _p(rp), _p(ci), _p(va), X0.shape[1], _p(X0), int(sweeps),
                                   float(omega), _p(w), _p(cf), int(caliber), _p(g), C.byref(gw))
     return float(L), g, float(gw.value)
+
+
+# ---------------------------------------------------------------- long range
+def _sig_longrange(L):
+    P = C.c_void_p
+    i32, i64, f64 = C.c_int, C.c_int64, C.c_double
+    for name, res, args in (
+            ("oracle_power_counts", i64, [i32, P, P, i32, P]),
+            ("oracle_power_fill", None, [i32, P, P, i32, P, P]),
+            ("oracle_algdist_graph", i32, [i32, P, P, P, P, P, i32, P, P, i32, i32, P, P, P]),
+            ("oracle_ls_fit_sets", None, [i32, P, P, P, i32, P, P, i32, i32, i32, P, P, P, P, P]),
+            ("oracle_ls_search", None, [i32, P, P, P, P, P, i32, P, P, P, i32, f64, i32, i32, P,
+                                        P, P, P, P, P, P])):
+        fn = getattr(L, name)
+        fn.restype = res
+        fn.argtypes = args
+    return L
+
+
+class Pattern:
+    """A sparsity pattern in CSR form (row_ptr, col), no values."""
+
+    def __init__(self, n, row_ptr, col):
+        self.n = int(n)
+        self.row_ptr = np.ascontiguousarray(row_ptr, dtype=np.int32)
+        self.col = np.ascontiguousarray(col, dtype=np.int32)
+
+    @property
+    def nnz(self):
+        return int(self.row_ptr[-1])
+
+    def row_ids(self):
+        return np.repeat(np.arange(self.n, dtype=np.int64), np.diff(self.row_ptr))
+
+
+def power_pattern(A, d: int) -> Pattern:
+    """Structural pattern of A^d (eq. graph): per row, the vertices within
+    graph distance d, sorted."""
+    L = _sig_longrange(lib())
+    n, rp, ci, _ = _csr(A)
+    cnt = np.empty(n, dtype=np.int32)
+    L.oracle_power_counts(n, _p(rp), _p(ci), int(d), _p(cnt))
+    rpd = np.concatenate([[0], np.cumsum(cnt, dtype=np.int64)])
+    assert rpd[-1] < 2 ** 31
+    rpd = rpd.astype(np.int32)
+    cid = np.empty(int(rpd[-1]), dtype=np.int32)
+    L.oracle_power_fill(n, _p(rp), _p(ci), int(d), _p(rpd), _p(cid))
+    return Pattern(n, rpd, cid)
+
+
+def algdist_graph(A, G, X, w=None, target: int = TARGET_PLAIN, rows=None, want_p: bool = False):
+    """mu (and p) per entry of the pattern G (e.g. power_pattern(A, d)), the
+    targets formed from A; packed in row order over the selected rows."""
+    L = _sig_longrange(lib())
+    n, rp, ci, va = _csr(A)
+    X = _f64(X)
+    w = None if w is None else _f64(w)
+    r = _rows(rows)
+    m = packed_len(G, rows)
+    mu = np.empty(m)
+    p = np.empty(m) if want_p else None
+    L.oracle_algdist_graph(n, _p(rp), _p(ci), _p(va), _p(G.row_ptr), _p(G.col), X.shape[1], _p(X),
+                           _p(w), int(target), 0 if r is None else len(r), _p(r), _p(mu), _p(p))
+    return (mu, p) if want_p else mu
+
+
+def ls_fit_sets(A, X, w, sets, rows, target: int = TARGET_PLAIN):
+    """LS fit of each row of `rows` by its given set (row r of `sets`, -1
+    padded): (P_val, ls_val, rankdef)."""
+    L = _sig_longrange(lib())
+    n, rp, ci, va = _csr(A)
+    X = _f64(X)
+    w = None if w is None else _f64(w)
+    sets = np.ascontiguousarray(sets, dtype=np.int32)
+    r = _rows(rows)
+    cal = sets.shape[1]
+    Pv = np.empty((len(r), cal))
+    ls = np.empty(len(r))
+    rd = np.empty(len(r), dtype=np.int32)
+    L.oracle_ls_fit_sets(n, _p(rp), _p(ci), _p(va), X.shape[1], _p(X), _p(w), int(target), cal,
+                         len(r), _p(r), _p(sets), _p(Pv), _p(ls), _p(rd))
+    return Pv, ls, rd
+
+
+def ls_search(A, G, X, w, cf, caliber: int, gamma: float = 1.5, target: int = TARGET_PLAIN,
+              rows=None):
+    """Interpolatory sets by search over the C-points of G's rows (Sec. 4.3):
+    (P_col, P_val, ls_val, status, best, ncand); best[r] = (S, best_1/S, ...,
+    best_caliber/S)."""
+    L = _sig_longrange(lib())
+    n, rp, ci, va = _csr(A)
+    X = _f64(X)
+    w = None if w is None else _f64(w)
+    cf = np.ascontiguousarray(cf, dtype=np.uint8)
+    r = _rows(rows)
+    m = n if r is None else len(r)
+    Pc = np.empty((m, caliber), dtype=np.int32)
+    Pv = np.empty((m, caliber))
+    ls = np.empty(m)
+    st = np.empty(m, dtype=np.int32)
+    best = np.empty((m, caliber + 1))
+    nc = np.empty(m, dtype=np.int32)
+    L.oracle_ls_search(n, _p(rp), _p(ci), _p(va), _p(G.row_ptr), _p(G.col), X.shape[1], _p(X),
+                       _p(w), _p(cf), int(caliber), float(gamma), int(target),
+                       0 if r is None else len(r), _p(r), _p(Pc), _p(Pv), _p(ls), _p(st),
+                       _p(best), _p(nc))
+    return Pc, Pv, ls, st, best, nc

@@ -603,3 +603,336 @@ double oracle_ls_loss_grad(int n, const int *rp, const int *ci, const double *a,
     free(Pc); free(Pv); free(ls); free(st);
     return L;
 }
+
+/* ====================================================================== */
+/* Long-range connectivity and the search over interpolatory sets          */
+/* ====================================================================== */
+
+/* ---------------------------------------------------------------------- */
+/* Pattern of A^d (Sec. 4.1, eq. graph).  Read structurally: j is in row i */
+/* of A^d iff a walk of exactly d steps joins i to j in the graph of A;    */
+/* with every diagonal stored this is every j within graph distance d of   */
+/* i.  A^d itself is never formed (the remark closing Sec. 4.2): the rows  */
+/* come from a breadth-first search of depth d over the graph of A.        */
+/* ---------------------------------------------------------------------- */
+
+/* Vertices within distance d of i, unsorted, into list; returns the count.
+ * mark[] must hold values != i on entry for every vertex. */
+static int reach(const int *rp, const int *ci, int d, int i, int *mark, int *list)
+{
+    int head = 0, tail = 0, lev, e;
+    list[tail++] = i;
+    mark[i] = i;
+    for (lev = 0; lev < d; ++lev) {
+        int end = tail;
+        for (; head < end; ++head) {
+            int u = list[head];
+            for (e = rp[u]; e < rp[u + 1]; ++e) {
+                int j = ci[e];
+                if (mark[j] != i) {
+                    mark[j] = i;
+                    list[tail++] = j;
+                }
+            }
+        }
+    }
+    return tail;
+}
+
+static int cmp_int(const void *a, const void *b)
+{
+    int x = *(const int *)a, y = *(const int *)b;
+    return (x > y) - (x < y);
+}
+
+/* cnt[i] = number of entries of row i of A^d.  Returns their sum. */
+int64_t oracle_power_counts(int n, const int *rp, const int *ci, int d, int *cnt)
+{
+    int *mark = (int *)malloc(sizeof(int) * (size_t)(n > 0 ? n : 1));
+    int *list = (int *)malloc(sizeof(int) * (size_t)(n > 0 ? n : 1));
+    int64_t total = 0;
+    int i;
+    for (i = 0; i < n; ++i) mark[i] = -1;
+    for (i = 0; i < n; ++i) {
+        cnt[i] = reach(rp, ci, d, i, mark, list);
+        total += cnt[i];
+    }
+    free(mark);
+    free(list);
+    return total;
+}
+
+/* Columns of A^d, sorted per row, at the row pointers rpd (from the counts). */
+void oracle_power_fill(int n, const int *rp, const int *ci, int d, const int *rpd, int *cid)
+{
+    int *mark = (int *)malloc(sizeof(int) * (size_t)(n > 0 ? n : 1));
+    int *list = (int *)malloc(sizeof(int) * (size_t)(n > 0 ? n : 1));
+    int i, m;
+    for (i = 0; i < n; ++i) mark[i] = -1;
+    for (i = 0; i < n; ++i) {
+        m = reach(rp, ci, d, i, mark, list);
+        qsort(list, (size_t)m, sizeof(int), cmp_int);
+        memcpy(cid + rpd[i], list, sizeof(int) * (size_t)m);
+    }
+    free(mark);
+    free(list);
+}
+
+/* ---------------------------------------------------------------------- */
+/* Algebraic distance on a graph G other than that of A (Sec. 4.1,         */
+/* eq:measure with j ranging over V_i of eq. graph, e.g. G = A^d): for     */
+/* every entry (i, j) of G the one-point problem of oracle_algdist, the    */
+/* target of row i formed from A (plain, or with A's residual).  mu (and   */
+/* p) per entry of G, packed over the selected rows.                       */
+/* ---------------------------------------------------------------------- */
+int oracle_algdist_graph(int n, const int *rp, const int *ci, const double *a, const int *rpg,
+                         const int *cig, int K, const double *X, const double *w, int target,
+                         int nrows, const int *rows, double *mu, double *p)
+{
+    double *t = (double *)malloc(sizeof(double) * K);
+    double *sc = (double *)malloc(sizeof(double) * K);
+    int64_t out = 0;
+    int r, e, k, bad = 0;
+    int cnt = rows ? nrows : n;
+    for (r = 0; r < cnt; ++r) {
+        int i = rows ? rows[r] : r;
+        bad += fit_target(rp, ci, a, K, X, i, target, t, sc);
+        for (e = rpg[i]; e < rpg[i + 1]; ++e, ++out) {
+            const double *xj = X + (int64_t)cig[e] * K;
+            double sab = 0.0, sbb = 0.0, pij, m = 0.0;
+            for (k = 0; k < K; ++k) {
+                sab += weight(w, k) * t[k] * xj[k];
+                sbb += weight(w, k) * xj[k] * xj[k];
+            }
+            pij = (sbb > 0.0) ? sab / sbb : 0.0;
+            for (k = 0; k < K; ++k) {
+                double res = t[k] - pij * xj[k];
+                m += weight(w, k) * res * res;
+            }
+            mu[out] = m;
+            if (p) p[out] = pij;
+        }
+    }
+    free(t);
+    free(sc);
+    return bad;
+}
+
+/* ---------------------------------------------------------------------- */
+/* Least-squares fit of target t by the panel rows cols[0..m) (Sec. 3.1,   */
+/* eq:LSfuncrowi / eq:modls for a given set W): Householder QR of the      */
+/* sqrt(w)-scaled K x m system.  Returns 1 (and nothing else) when a       */
+/* column is numerically dependent on the ones before it (the part of it   */
+/* the earlier reflections leave, squared, <= 1e-12 of its squared norm),  */
+/* else 0 with coef[0..m) the minimiser and *val the functional at it,     */
+/* evaluated by its definition.  M: K*m scratch, b, v: K scratch.          */
+/* ---------------------------------------------------------------------- */
+static int qr_fit(int K, const double *X, const double *w, const double *t, const int *cols,
+                  int m, double *coef, double *val, double *M, double *b, double *v)
+{
+    double R[ORACLE_MAX_CAL][ORACLE_MAX_CAL];
+    int s, q, k;
+    for (s = 0; s < m; ++s)
+        for (k = 0; k < K; ++k) M[s * K + k] = sqrt(weight(w, k)) * X[(int64_t)cols[s] * K + k];
+    for (k = 0; k < K; ++k) b[k] = sqrt(weight(w, k)) * t[k];
+    for (s = 0; s < m; ++s) {
+        double *col = M + s * K;
+        double full = 0.0, tail = 0.0, alpha, vnorm2, dot;
+        for (k = 0; k < K; ++k) full += col[k] * col[k];
+        for (k = s; k < K; ++k) tail += col[k] * col[k];
+        if (s >= K || tail <= 1e-12 * full) return 1;
+        alpha = (col[s] > 0.0) ? -sqrt(tail) : sqrt(tail);
+        for (k = 0; k < K; ++k) v[k] = 0.0;
+        for (k = s; k < K; ++k) v[k] = col[k];
+        v[s] -= alpha;
+        vnorm2 = 0.0;
+        for (k = s; k < K; ++k) vnorm2 += v[k] * v[k];
+        for (q = s; q < m; ++q) {
+            double *cq = M + q * K;
+            dot = 0.0;
+            for (k = s; k < K; ++k) dot += v[k] * cq[k];
+            for (k = s; k < K; ++k) cq[k] -= 2.0 * dot / vnorm2 * v[k];
+        }
+        dot = 0.0;
+        for (k = s; k < K; ++k) dot += v[k] * b[k];
+        for (k = s; k < K; ++k) b[k] -= 2.0 * dot / vnorm2 * v[k];
+        for (q = 0; q <= s; ++q) R[q][s] = col[q];
+    }
+    for (s = m - 1; s >= 0; --s) {
+        double acc = b[s];
+        for (q = s + 1; q < m; ++q) acc -= R[s][q] * coef[q];
+        coef[s] = acc / R[s][s];
+    }
+    *val = 0.0;
+    for (k = 0; k < K; ++k) {
+        double res = t[k];
+        for (s = 0; s < m; ++s) res -= coef[s] * X[(int64_t)cols[s] * K + k];
+        *val += weight(w, k) * res * res;
+    }
+    return 0;
+}
+
+/* LS rows for given interpolatory sets: sets (row-major nrows x caliber,
+ * -1 padded, the set of rows[r] in row r) are fitted by qr_fit; P_val and
+ * ls_val receive the minimiser and the functional, rankdef[r] = 1 (and
+ * zeros) for a numerically dependent set.  Target as in oracle_algdist. */
+void oracle_ls_fit_sets(int n, const int *rp, const int *ci, const double *a, int K,
+                        const double *X, const double *w, int target, int caliber, int nrows,
+                        const int *rows, const int *sets, double *P_val, double *ls_val,
+                        int *rankdef)
+{
+    double *t = (double *)malloc(sizeof(double) * K);
+    double *sc = (double *)malloc(sizeof(double) * K);
+    double *M = (double *)malloc(sizeof(double) * K * ORACLE_MAX_CAL);
+    double *b = (double *)malloc(sizeof(double) * K);
+    double *v = (double *)malloc(sizeof(double) * K);
+    int r, s, k;
+    (void)n;
+    for (r = 0; r < nrows; ++r) {
+        int i = rows[r], m = 0;
+        const int *set = sets + (int64_t)r * caliber;
+        double coef[ORACLE_MAX_CAL], val = 0.0;
+        fit_target(rp, ci, a, K, X, i, target, t, sc);
+        while (m < caliber && set[m] >= 0) ++m;
+        for (s = 0; s < caliber; ++s) P_val[(int64_t)r * caliber + s] = 0.0;
+        rankdef[r] = 0;
+        if (m == 0) {
+            for (k = 0; k < K; ++k) val += weight(w, k) * t[k] * t[k];
+            ls_val[r] = val;
+            continue;
+        }
+        if (qr_fit(K, X, w, t, set, m, coef, &val, M, b, v)) {
+            rankdef[r] = 1;
+            ls_val[r] = 0.0;
+            continue;
+        }
+        for (s = 0; s < m; ++s) P_val[(int64_t)r * caliber + s] = coef[s];
+        ls_val[r] = val;
+    }
+    free(t); free(sc); free(M); free(b); free(v);
+}
+
+/* ---------------------------------------------------------------------- */
+/* Interpolatory sets by search (Sec. 4.3).  For an F row i the candidates */
+/* are N_i = C-points of row i of the graph G (eq:nbhd with G the pattern  */
+/* of A^{d_LS}), i excluded, in increasing column order.  Every W within   */
+/* N_i with 1 <= |W| <= caliber is fitted (qr_fit; a numerically dependent */
+/* W is skipped: its span is that of a smaller set already visited), and   */
+/* for each size m the least functional best_m is kept (ties: the first W  */
+/* in lexicographic order of candidate positions).  Values are normalised  */
+/* by the functional of the empty set, S = sum_k w_k t_k^2 (the reading of */
+/* the penalty's exponent as acting on a relative value).  The size is     */
+/* then chosen by the penalty rule read as a scan in increasing size: the  */
+/* incumbent starts at size 1 and is replaced by the best set of size m    */
+/* when best_m / S < (incumbent / S)^(gamma (m - incumbent size)).  With   */
+/* S = 0 every fit is exact and size 1 is kept.                            */
+/*                                                                         */
+/* Outputs per selected row (row-major nrows x caliber): P_col (the chosen */
+/* W, increasing columns, -1 padded; C rows: i itself), P_val, ls_val (the */
+/* functional at the minimiser, not normalised), status (0 ok, 1 no        */
+/* candidate or every W dependent, 3 residual target with zero diagonal),  */
+/* best (nrows x (caliber + 1), may be NULL): S, then best_m / S for m =   */
+/* 1..caliber (-1 where no W of that size was fitted), ncand (may be NULL):*/
+/* |N_i|.                                                                  */
+/* ---------------------------------------------------------------------- */
+void oracle_ls_search(int n, const int *rp, const int *ci, const double *a, const int *rpg,
+                      const int *cig, int K, const double *X, const double *w,
+                      const unsigned char *cf, int caliber, double gamma, int target, int nrows,
+                      const int *rows, int *P_col, double *P_val, double *ls_val, int *status,
+                      double *best, int *ncand)
+{
+    int cnt = rows ? nrows : n;
+    double *t = (double *)malloc(sizeof(double) * K);
+    double *sc = (double *)malloc(sizeof(double) * K);
+    double *M = (double *)malloc(sizeof(double) * K * ORACLE_MAX_CAL);
+    double *b = (double *)malloc(sizeof(double) * K);
+    double *v = (double *)malloc(sizeof(double) * K);
+    int *cand = (int *)malloc(sizeof(int) * (size_t)(n > 0 ? n : 1));
+    int r, s, k, e;
+    for (r = 0; r < cnt; ++r) {
+        int i = rows ? rows[r] : r;
+        int *pc = P_col + (int64_t)r * caliber;
+        double *pv = P_val + (int64_t)r * caliber;
+        double *bo = best ? best + (int64_t)r * (caliber + 1) : NULL;
+        int nc = 0, st = 0, m, inc_m = 0;
+        double S = 0.0, bestv[ORACLE_MAX_CAL + 1];
+        int bestset[ORACLE_MAX_CAL + 1][ORACLE_MAX_CAL];
+        double inc_v = 0.0;
+
+        for (s = 0; s < caliber; ++s) { pc[s] = -1; pv[s] = 0.0; }
+        if (cf[i]) {
+            pc[0] = i;
+            pv[0] = 1.0;
+            ls_val[r] = 0.0;
+            status[r] = 0;
+            if (bo) for (s = 0; s <= caliber; ++s) bo[s] = -1.0;
+            if (ncand) ncand[r] = 0;
+            continue;
+        }
+        if (fit_target(rp, ci, a, K, X, i, target, t, sc)) st = 3;
+        for (k = 0; k < K; ++k) S += weight(w, k) * t[k] * t[k];
+        for (e = rpg[i]; e < rpg[i + 1]; ++e)
+            if (cig[e] != i && cf[cig[e]]) cand[nc++] = cig[e];
+        if (ncand) ncand[r] = nc;
+
+        /* every subset of each size, positions idx[0] < ... < idx[m-1] */
+        for (m = 1; m <= caliber; ++m) {
+            int idx[ORACLE_MAX_CAL], cols[ORACLE_MAX_CAL], q;
+            bestv[m] = -1.0;
+            if (m > nc) continue;
+            for (q = 0; q < m; ++q) idx[q] = q;
+            for (;;) {
+                double coef[ORACLE_MAX_CAL], val;
+                for (q = 0; q < m; ++q) cols[q] = cand[idx[q]];
+                if (!qr_fit(K, X, w, t, cols, m, coef, &val, M, b, v) &&
+                    (bestv[m] < 0.0 || val < bestv[m])) {
+                    bestv[m] = val;
+                    for (q = 0; q < m; ++q) bestset[m][q] = cols[q];
+                }
+                /* next combination in lexicographic order */
+                q = m - 1;
+                while (q >= 0 && idx[q] == nc - m + q) --q;
+                if (q < 0) break;
+                ++idx[q];
+                for (++q; q < m; ++q) idx[q] = idx[q - 1] + 1;
+            }
+        }
+        if (bo) {
+            bo[0] = S;
+            for (m = 1; m <= caliber; ++m)
+                bo[m] = (bestv[m] < 0.0) ? -1.0 : (S > 0.0 ? bestv[m] / S : 0.0);
+        }
+        /* penalty rule, sizes in increasing order */
+        for (m = 1; m <= caliber; ++m) {
+            double rel, inc_rel;
+            if (bestv[m] < 0.0) continue;
+            if (inc_m == 0) {
+                inc_m = m;
+                inc_v = bestv[m];
+                continue;
+            }
+            rel = S > 0.0 ? bestv[m] / S : 0.0;
+            inc_rel = S > 0.0 ? inc_v / S : 0.0;
+            if (rel < pow(inc_rel, gamma * (double)(m - inc_m))) {
+                inc_m = m;
+                inc_v = bestv[m];
+            }
+        }
+        if (inc_m == 0) {
+            ls_val[r] = S;
+            status[r] = st ? st : 1;
+            continue;
+        }
+        {
+            double coef[ORACLE_MAX_CAL], val;
+            qr_fit(K, X, w, t, bestset[inc_m], inc_m, coef, &val, M, b, v);
+            for (s = 0; s < inc_m; ++s) {
+                pc[s] = bestset[inc_m][s];
+                pv[s] = coef[s];
+            }
+            ls_val[r] = val;
+            status[r] = st;
+        }
+    }
+    free(t); free(sc); free(M); free(b); free(v); free(cand);
+}
