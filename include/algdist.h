@@ -302,6 +302,25 @@ int distance_ls(ad_handle h, const ad_csr *A, int32_t K, const void *X, const do
                 int32_t *nstrong, const uint8_t *cf, int32_t caliber, int32_t *P_col,
                 double *P_val, double *ls_val, int32_t *row_status, double *ls_sum, void *stream);
 
+/* distance_ls for callers that cannot allocate device memory (code under
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * same arguments, same kernels and bitwise the same results as distance_ls,
+ * but it never allocates or frees.  The per-workgroup partial sums of ls_sum
+ * go to a static device array of 1 MiB (131072 FP64 values; each device the
+ * library runs on holds one until the process ends), resolved once per
+ * device by algdist_create.  A call whose fused pass would launch more
+ * than 131072 workgroups with ls_sum requested (FP32, K = 16 at the default
+ * launch shape of 64 rows per workgroup: more than about 8.3 million rows)
+ * returns AD_ESTRUCT and enqueues nothing; without ls_sum there is no
+ * limit.  Every call on one
+ * device shares that array, so calls that overlap in time on one device
+ * (any handle, any stream) race; the array needs no clearing (each call
+ * writes every partial it reads). */
+int distance_ls_noalloc(ad_handle h, const ad_csr *A, int32_t K, const void *X, const double *w,
+                        int32_t target, void *mu, double theta, const uint8_t *fmask,
+                        uint8_t *strong, int32_t *nstrong, const uint8_t *cf, int32_t caliber,
+                        int32_t *P_col, double *P_val, double *ls_val, int32_t *row_status,
+                        double *ls_sum, void *stream);
 
 /* ------------------------------------------------------------------ */
 /* batched relaxation + distances                                      */

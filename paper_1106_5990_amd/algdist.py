@@ -70,6 +70,8 @@ _SIGS = {
     "ls_interp": (_i32, [_P, _CSRP, _i32, _P, _P, _P, _P, _i32, _i32, _P, _P, _P, _P, _P, _P]),
     "distance_ls": (_i32, [_P, _CSRP, _i32, _P, _P, _i32, _P, _f64, _P, _P, _P, _P, _i32, _P, _P, _P,
                            _P, _P, _P]),
+    "distance_ls_noalloc": (_i32, [_P, _CSRP, _i32, _P, _P, _i32, _P, _f64, _P, _P, _P, _P, _i32, _P,
+                                   _P, _P, _P, _P, _P]),
     "relax_algdist_batched": (_i32, [_P, _i32, _CSRP, _i32, _u64, _i32, _i32, _f64, _P, _P, _P,
                                      _f64, _P, _P, _P]),
     "ls_interp_loss_backward": (_i32, [_P, _CSRP, _i32, _P, _i32, _i32, _f64, _P, _P, _P, _P, _i32,
@@ -330,6 +332,26 @@ def distance_ls(A: Csr, X: torch.Tensor, cf: torch.Tensor, caliber: int,
                           _ptr(ls_sum) if want_sum else None, _stream(stream))
     _check(rc, h, "distance_ls")
     return mu, strong, nstrong, P_col, P_val, ls_val, row_status, (ls_sum if want_sum else None)
+
+
+def distance_ls_noalloc(A: Csr, X: torch.Tensor, cf: torch.Tensor, caliber: int, *,
+                        mu: torch.Tensor, P_col: torch.Tensor, P_val: torch.Tensor,
+                        ls_val: torch.Tensor, row_status: torch.Tensor,
+                        strong: Optional[torch.Tensor] = None,
+                        nstrong: Optional[torch.Tensor] = None,
+                        ls_sum: Optional[torch.Tensor] = None, w: Optional[torch.Tensor] = None,
+                        target: str = "plain", theta: float = 0.25,
+                        fmask: Optional[torch.Tensor] = None, stream=None) -> None:
+    """distance_ls_noalloc: distance_ls without any device allocation, here
+    or in the library (the caller passes every output; ls_sum, if given,
+    receives the F-row sum)."""
+    h = handle(A.device.index)
+    tg = {"plain": AD_TARGET_PLAIN, "residual": AD_TARGET_RESIDUAL}[target]
+    rc = _lib.distance_ls_noalloc(h, A.ref(), X.shape[1], _ptr(X), _ptr(w), tg, _ptr(mu),
+                                  float(theta), _ptr(fmask), _ptr(strong), _ptr(nstrong), _ptr(cf),
+                                  caliber, _ptr(P_col), _ptr(P_val), _ptr(ls_val),
+                                  _ptr(row_status), _ptr(ls_sum), _stream(stream))
+    _check(rc, h, "distance_ls_noalloc")
 
 
 def relax_algdist_batched(mats, K: int, seed: int = 0, sweeps: int = 4, omega: float = 2.0 / 3.0,

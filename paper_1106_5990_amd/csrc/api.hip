@@ -61,6 +61,29 @@ int check_panel(ad_handle h, const void* X, const char* name, int n) {
 
 }  // namespace
 
+// ---------------------------------------------------------------- static scratch
+// Device memory of distance_ls_noalloc: the fused pass's per-workgroup
+// partial sums of ls_val.  Each device holds its own copy of the array at
+// its own address, resolved once per device in algdist_create; host code
+// uses only that address (the array's name is a host-side stand-in).
+constexpr size_t kStaticScratchBytes = size_t(1) << 20;  // 131072 FP64 partials
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+void* g_scratch[kMaxDevices] = {};  // per-device address of `scratch`
+
+// Resolves this device's copy of `scratch` (device must be current).
+int resolve_scratch(int device) {
+    if (device < 0 || device >= kMaxDevices) return AD_EDEVICE;
+    if (g_scratch[device]) return AD_OK;
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return AD_EDEVICE;
+    g_scratch[device] = p;
+    return AD_OK;
+}
+}  // namespace
+
 namespace ad {
 TimedScope::TimedScope(ad_handle h, const char* label, hipStream_t s) : h_(h), label_(label), s_(s) {
     if (!h_->timing) return;
@@ -167,7 +190,8 @@ int algdist_create(ad_handle* out, int device) {
         delete h;
         return AD_ENOMEM;
     }
-    if (hipMemset(h->status, 0, sizeof(unsigned)) != hipSuccess) {
+    if (hipMemset(h->status, 0, sizeof(unsigned)) != hipSuccess ||
+        resolve_scratch(device) != AD_OK) {
         (void)hipFree(h->status);
         delete h;
         return AD_EDEVICE;
@@ -525,13 +549,15 @@ int ls_interp(ad_handle h, const ad_csr* A, int32_t K, const void* X, const doub
 
 }  // extern "C"
 
-// distance_ls: the block partial sums of ls_sum live in the handle's
-// workspace (grown on demand).
+// distance_ls and distance_ls_noalloc: the block partial sums of ls_sum
+// live in the handle's workspace (grown on demand) or, with noalloc, in this
+// device's copy of the static scratch array.
 static int distance_ls_impl(ad_handle h, const ad_csr* A, int32_t K, const void* X,
                             const double* w, int32_t target, void* mu, double theta,
                             const uint8_t* fmask, uint8_t* strong, int32_t* nstrong,
                             const uint8_t* cf, int32_t caliber, int32_t* P_col, double* P_val,
-                            double* ls_val, int32_t* row_status, double* ls_sum, void* stream) {
+                            double* ls_val, int32_t* row_status, double* ls_sum, void* stream,
+                            bool noalloc) {
     if (!h) return AD_EINVAL;
     h->err.clear();
     int rc = check_csr(h, A);
@@ -555,9 +581,18 @@ static int distance_ls_impl(ad_handle h, const ad_csr* A, int32_t K, const void*
     if (ls_sum) {
         const int nb = dist_ls_blocks(A->dtype, K, A->n, cfg);
         const size_t need = sizeof(double) * (size_t)nb;
-        if ((rc = ws_reserve(h, need, (hipStream_t)stream)))
-            return fail(h, rc, "workspace for %d block sums%s", nb, ws_why(rc));
-        bs = (double*)h->ws;
+        if (noalloc) {
+            if (need > kStaticScratchBytes)
+                return fail(h, AD_ESTRUCT,
+                            "%d rows need %zu bytes of block partial sums; the static scratch "
+                            "holds %zu (%zu workgroups of the fused pass)",
+                            A->n, need, kStaticScratchBytes, kStaticScratchBytes / sizeof(double));
+            bs = (double*)g_scratch[h->device];
+        } else {
+            if ((rc = ws_reserve(h, need, (hipStream_t)stream)))
+                return fail(h, rc, "workspace for %d block sums%s", nb, ws_why(rc));
+            bs = (double*)h->ws;
+        }
     }
     TimedScope ts(h, "distance_ls", (hipStream_t)stream);
     rc = launch_dist_ls(A->dtype, K, caliber, A, X, w, target, mu, theta, fmask, strong, nstrong,
@@ -573,7 +608,16 @@ int distance_ls(ad_handle h, const ad_csr* A, int32_t K, const void* X, const do
                 int32_t* nstrong, const uint8_t* cf, int32_t caliber, int32_t* P_col,
                 double* P_val, double* ls_val, int32_t* row_status, double* ls_sum, void* stream) {
     return distance_ls_impl(h, A, K, X, w, target, mu, theta, fmask, strong, nstrong, cf, caliber,
-                            P_col, P_val, ls_val, row_status, ls_sum, stream);
+                            P_col, P_val, ls_val, row_status, ls_sum, stream, false);
+}
+
+int distance_ls_noalloc(ad_handle h, const ad_csr* A, int32_t K, const void* X, const double* w,
+                        int32_t target, void* mu, double theta, const uint8_t* fmask,
+                        uint8_t* strong, int32_t* nstrong, const uint8_t* cf, int32_t caliber,
+                        int32_t* P_col, double* P_val, double* ls_val, int32_t* row_status,
+                        double* ls_sum, void* stream) {
+    return distance_ls_impl(h, A, K, X, w, target, mu, theta, fmask, strong, nstrong, cf, caliber,
+                            P_col, P_val, ls_val, row_status, ls_sum, stream, true);
 }
 
 int relax_algdist_batched(ad_handle h, int32_t nmat, const ad_csr* As, int32_t K, uint64_t seed,
