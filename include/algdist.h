@@ -75,8 +75,8 @@ typedef enum {
 #define AD_STAT_CSR_ROWPTR  0x08u /* csr_validate: row_ptr not nondecreasing or row_ptr[n] != nnz */
 #define AD_STAT_CSR_COLS    0x10u /* csr_validate: column out of range or not strictly increasing */
 #define AD_STAT_CSR_NODIAG  0x20u /* csr_validate: a row has no diagonal entry */
-#define AD_STAT_RESERVED_40 0x40u /* reserved (never set) */
-#define AD_STAT_RESERVED_80 0x80u /* reserved (never set) */
+#define AD_STAT_SEARCH_CAP  0x40u /* ls_interp_search: an F row had more than 64 candidates (row left empty, status 4) */
+#define AD_STAT_PATTERN     0x80u /* power_graph_cols: row_ptr_d does not fit A^d's row lengths (rows cut) */
 
 typedef struct ad_handle_s *ad_handle;
 
@@ -321,6 +321,70 @@ int distance_ls_noalloc(ad_handle h, const ad_csr *A, int32_t K, const void *X, 
                         uint8_t *strong, int32_t *nstrong, const uint8_t *cf, int32_t caliber,
                         int32_t *P_col, double *P_val, double *ls_val, int32_t *row_status,
                         double *ls_sum, void *stream);
+
+/* ------------------------------------------------------------------ */
+/* long-range connectivity and the search over interpolatory sets      */
+/* ------------------------------------------------------------------ */
+
+/* Pattern of A^d, d >= 1 (Sec. 4.1, eq. graph: V_i = {j : (A^d)_ij != 0};
+ * the closing remark of Sec. 4.2: A^d is never formed, its graph is rebuilt
+ * from the graph of A).  Read structurally: row i holds every j joined to i
+ * by a walk of exactly d steps -- with every diagonal stored, every j within
+ * graph distance d -- in increasing order; cancellation in A^d's values is
+ * ignored.  Only A's structure is read (A->val may be NULL).
+ *
+ * power_graph_rows writes the row pointers row_ptr_d (device, n + 1 int32)
+ * and the entry count *nnz_d (host); it synchronises `stream`, so it cannot
+ * be captured.  Returns AD_EUNSUPPORTED when a row would have more than
+ * 1024 entries or the count would pass INT32_MAX (row_ptr_d is then
+ * undefined).  power_graph_cols then writes the sorted columns col_d
+ * (device, *nnz_d int32) for those row pointers, asynchronously.  The pair
+ * (row_ptr_d, col_d) is the pattern argument of algebraic_distance_graph
+ * and ls_interp_search. */
+int power_graph_rows(ad_handle h, const ad_csr *A, int32_t d, int32_t *row_ptr_d,
+                     int64_t *nnz_d, void *stream);
+int power_graph_cols(ad_handle h, const ad_csr *A, int32_t d, const int32_t *row_ptr_d,
+                     int32_t *col_d, void *stream);
+
+/* algebraic_distance over the entries of another pattern G of the same n
+ * rows -- typically that of A^d from power_graph_* (Sec. 4.1: mu_ij for all
+ * j in V_i of G_d; Sec. 4.2 builds the strength graph M^d on it).  The target
+ * t_i is formed from A (plain x_i, or x_i - (A x)_i / a_ii), the one-point
+ * fit runs against every x_j, j in row i of G.  G: row_ptr_g (n + 1 int32),
+ * col_g (nnz_g int32, sorted per row; the diagonal is not required).  mu, p,
+ * strong (nnz_g) are per entry of G; nstrong per row; theta, fmask, w as
+ * in algebraic_distance (the strength graph is that of Sec. 4.2 on G). */
+int algebraic_distance_graph(ad_handle h, const ad_csr *A, int64_t nnz_g,
+                             const int32_t *row_ptr_g, const int32_t *col_g, int32_t K,
+                             const void *X, const double *w, int32_t target, void *mu, double *p,
+                             double theta, const uint8_t *fmask, uint8_t *strong,
+                             int32_t *nstrong, void *stream);
+
+/* Interpolatory sets by search (Sec. 4.3).  For each F row i (cf[i] == 0)
+ * the candidates are N_i = the C-points (cf != 0) of row i of the pattern G
+ * (eq:nbhd with G the pattern of A^{d_LS}), i excluded.  Every set W within
+ * N_i with 1 <= |W| <= caliber is fitted (the LS functional of Sec. 3.1,
+ * eq:LSfuncrowi or eq:modls per target, weights w); a set whose Gram
+ * matrix has a Cholesky pivot <= 1e-12 of its diagonal is numerically
+ * dependent and skipped.  For each size m the set of least functional
+ * best_m is kept (ties: the first in lexicographic order of candidate
+ * positions).  The size follows the penalty rule of Sec. 4.3 read as a scan
+ * in increasing size against the incumbent, on values relative to the
+ * empty set's S = sum_k w_k t_k^2: the incumbent starts at the smallest size
+ * with a fitted set and is replaced by size m when
+ *     best_m / S < (incumbent / S)^(gamma (m - incumbent size)).
+ * The paper's gamma is 1.5.  Outputs as in ls_interp: P_col (the chosen W in
+ * increasing column order, -1 padded; C rows: i), P_val (FP64 minimiser),
+ * ls_val (functional at it, by definition), row_status: 0 ok, 1 no
+ * candidate (or all dependent; ls_val = S), 3 residual target with a zero
+ * diagonal (plain target used), 4 more than 64 candidates (row left empty;
+ * AD_STAT_SEARCH_CAP set).  1 <= caliber <= min(4, K).  Work per F row grows
+ * as |N_i|^caliber; G's rows may hold up to 1024 entries. */
+int ls_interp_search(ad_handle h, const ad_csr *A, int64_t nnz_g, const int32_t *row_ptr_g,
+                     const int32_t *col_g, int32_t K, const void *X, const double *w,
+                     const uint8_t *cf, int32_t caliber, double gamma, int32_t target,
+                     int32_t *P_col, double *P_val, double *ls_val, int32_t *row_status,
+                     void *stream);
 
 /* ------------------------------------------------------------------ */
 /* batched relaxation + distances                                      */

@@ -37,6 +37,8 @@ STAT_NONFINITE = 0x04
 STAT_CSR_ROWPTR = 0x08
 STAT_CSR_COLS = 0x10
 STAT_CSR_NODIAG = 0x20
+STAT_SEARCH_CAP = 0x40
+STAT_PATTERN = 0x80
 
 STATUS_NAMES = {0: "AD_OK", 1: "AD_EINVAL", 2: "AD_EDTYPE", 3: "AD_ECALIBER", 4: "AD_ESTRUCT",
                 5: "AD_EDEVICE", 6: "AD_ENOMEM", 7: "AD_EUNSUPPORTED"}
@@ -72,6 +74,12 @@ _SIGS = {
                            _P, _P, _P]),
     "distance_ls_noalloc": (_i32, [_P, _CSRP, _i32, _P, _P, _i32, _P, _f64, _P, _P, _P, _P, _i32, _P,
                                    _P, _P, _P, _P, _P]),
+    "power_graph_rows": (_i32, [_P, _CSRP, _i32, _P, C.POINTER(C.c_int64), _P]),
+    "power_graph_cols": (_i32, [_P, _CSRP, _i32, _P, _P, _P]),
+    "algebraic_distance_graph": (_i32, [_P, _CSRP, _i64, _P, _P, _i32, _P, _P, _i32, _P, _P, _f64,
+                                        _P, _P, _P, _P]),
+    "ls_interp_search": (_i32, [_P, _CSRP, _i64, _P, _P, _i32, _P, _P, _P, _i32, _f64, _i32, _P, _P,
+                                _P, _P, _P]),
     "relax_algdist_batched": (_i32, [_P, _i32, _CSRP, _i32, _u64, _i32, _i32, _f64, _P, _P, _P,
                                      _f64, _P, _P, _P]),
     "ls_interp_loss_backward": (_i32, [_P, _CSRP, _i32, _P, _i32, _i32, _f64, _P, _P, _P, _P, _i32,
@@ -352,6 +360,80 @@ def distance_ls_noalloc(A: Csr, X: torch.Tensor, cf: torch.Tensor, caliber: int,
                                   caliber, _ptr(P_col), _ptr(P_val), _ptr(ls_val),
                                   _ptr(row_status), _ptr(ls_sum), _stream(stream))
     _check(rc, h, "distance_ls_noalloc")
+
+
+
+class Pattern:
+    """A device sparsity pattern of n rows (int32 row_ptr[n+1], int32 col)."""
+
+    def __init__(self, row_ptr: torch.Tensor, col: torch.Tensor):
+        self.row_ptr, self.col = row_ptr, col
+        self.n = row_ptr.numel() - 1
+        self.nnz = col.numel()
+
+
+def power_graph(A: Csr, d: int, stream=None) -> Pattern:
+    """Pattern of A^d (power_graph_rows, which synchronises, then
+    power_graph_cols)."""
+    h = handle(A.device.index)
+    rp = torch.empty(A.n + 1, dtype=torch.int32, device=A.device)
+    nnz = C.c_int64(0)
+    _check(_lib.power_graph_rows(h, A.ref(), int(d), _ptr(rp), C.byref(nnz), _stream(stream)), h,
+           "power_graph_rows")
+    col = torch.empty(int(nnz.value), dtype=torch.int32, device=A.device)
+    _check(_lib.power_graph_cols(h, A.ref(), int(d), _ptr(rp), _ptr(col), _stream(stream)), h,
+           "power_graph_cols")
+    return Pattern(rp, col)
+
+
+def algebraic_distance_graph(A: Csr, G: Pattern, X: torch.Tensor, w: Optional[torch.Tensor] = None,
+                             target: str = "plain", mu: Optional[torch.Tensor] = None,
+                             p: Optional[torch.Tensor] = None, want_p: bool = False,
+                             theta: float = 0.0, fmask: Optional[torch.Tensor] = None,
+                             strong: Optional[torch.Tensor] = None,
+                             nstrong: Optional[torch.Tensor] = None, fuse: bool = False,
+                             stream=None):
+    """Distances over G's entries (targets from A).  Returns mu, or (mu,
+    strong, nstrong) when fuse=True, plus p if want_p."""
+    h = handle(A.device.index)
+    K = X.shape[1]
+    mu = mu if mu is not None else torch.empty(G.nnz, dtype=A.dtype, device=A.device)
+    if want_p and p is None:
+        p = torch.empty(G.nnz, dtype=torch.float64, device=A.device)
+    if fuse:
+        strong = strong if strong is not None else torch.empty(G.nnz, dtype=torch.uint8, device=A.device)
+        nstrong = nstrong if nstrong is not None else torch.empty(A.n, dtype=torch.int32, device=A.device)
+    tg = {"plain": AD_TARGET_PLAIN, "residual": AD_TARGET_RESIDUAL}[target]
+    rc = _lib.algebraic_distance_graph(h, A.ref(), G.nnz, _ptr(G.row_ptr), _ptr(G.col), K, _ptr(X),
+                                       _ptr(w), tg, _ptr(mu), _ptr(p), float(theta), _ptr(fmask),
+                                       _ptr(strong) if fuse else None,
+                                       _ptr(nstrong) if fuse else None, _stream(stream))
+    _check(rc, h, "algebraic_distance_graph")
+    res = (mu, strong, nstrong) if fuse else (mu,)
+    if want_p:
+        res = res + (p,)
+    return res if len(res) > 1 else res[0]
+
+
+def ls_interp_search(A: Csr, G: Pattern, X: torch.Tensor, cf: torch.Tensor, caliber: int,
+                     gamma: float = 1.5, w: Optional[torch.Tensor] = None, target: str = "plain",
+                     P_col: Optional[torch.Tensor] = None, P_val: Optional[torch.Tensor] = None,
+                     ls_val: Optional[torch.Tensor] = None,
+                     row_status: Optional[torch.Tensor] = None, stream=None):
+    """Interpolatory sets by search over the C-points of G's rows:
+    (P_col, P_val, ls_val, row_status)."""
+    h = handle(A.device.index)
+    n, dev = A.n, A.device
+    P_col = P_col if P_col is not None else torch.empty((n, caliber), dtype=torch.int32, device=dev)
+    P_val = P_val if P_val is not None else torch.empty((n, caliber), dtype=torch.float64, device=dev)
+    ls_val = ls_val if ls_val is not None else torch.empty(n, dtype=torch.float64, device=dev)
+    row_status = row_status if row_status is not None else torch.empty(n, dtype=torch.int32, device=dev)
+    tg = {"plain": AD_TARGET_PLAIN, "residual": AD_TARGET_RESIDUAL}[target]
+    rc = _lib.ls_interp_search(h, A.ref(), G.nnz, _ptr(G.row_ptr), _ptr(G.col), X.shape[1], _ptr(X),
+                               _ptr(w), _ptr(cf), caliber, float(gamma), tg, _ptr(P_col),
+                               _ptr(P_val), _ptr(ls_val), _ptr(row_status), _stream(stream))
+    _check(rc, h, "ls_interp_search")
+    return P_col, P_val, ls_val, row_status
 
 
 def relax_algdist_batched(mats, K: int, seed: int = 0, sweeps: int = 4, omega: float = 2.0 / 3.0,

@@ -620,6 +620,123 @@ int distance_ls_noalloc(ad_handle h, const ad_csr* A, int32_t K, const void* X, 
                             P_col, P_val, ls_val, row_status, ls_sum, stream, true);
 }
 
+// Structure-only checks of A (values unused).
+static int check_structure(ad_handle h, const ad_csr* A) {
+    if (!A) return fail(h, AD_EINVAL, "A is NULL");
+    if (A->n < 0) return fail(h, AD_EINVAL, "n = %d < 0", A->n);
+    if (A->nnz < 0 || A->nnz > 0x7fffffffLL)
+        return fail(h, AD_ESTRUCT, "nnz = %lld outside [0, 2^31)", (long long)A->nnz);
+    if (A->n > 0 && (!A->row_ptr || (A->nnz > 0 && !A->col)))
+        return fail(h, AD_EINVAL, "null CSR array");
+    return AD_OK;
+}
+
+static int check_pattern(ad_handle h, int n, int64_t nnz_g, const int32_t* rpg,
+                         const int32_t* cig) {
+    if (nnz_g < 0 || nnz_g > 0x7fffffffLL)
+        return fail(h, AD_ESTRUCT, "nnz_g = %lld outside [0, 2^31)", (long long)nnz_g);
+    if (n > 0 && (!rpg || (nnz_g > 0 && !cig))) return fail(h, AD_EINVAL, "null pattern array");
+    return AD_OK;
+}
+
+int power_graph_rows(ad_handle h, const ad_csr* A, int32_t d, int32_t* row_ptr_d, int64_t* nnz_d,
+                     void* stream) {
+    if (!h) return AD_EINVAL;
+    h->err.clear();
+    int rc = check_structure(h, A);
+    if (rc) return rc;
+    if (d < 1) return fail(h, AD_EINVAL, "d = %d < 1", d);
+    if (!row_ptr_d || !nnz_d) return fail(h, AD_EINVAL, "row_ptr_d or nnz_d is NULL");
+    hipStream_t s = (hipStream_t)stream;
+    AD_HIP(hipSetDevice(h->device));
+    if (stream_capturing(s))
+        return fail(h, AD_EUNSUPPORTED, "power_graph_rows synchronises the stream: not capturable");
+    const size_t need = pow_rows_workspace(A->n);
+    if ((rc = ws_reserve(h, need, s))) return fail(h, rc, "workspace of %zu bytes", need);
+    int64_t tot = 0;
+    int bad = 0;
+    {
+        TimedScope ts(h, "power_graph", s);
+        rc = launch_pow_rows(A->n, d, A->row_ptr, A->col, row_ptr_d, h->ws, &tot, &bad, s);
+    }
+    if (rc) return fail(h, rc, "power_graph_rows launch");
+    if (bad & 1) return fail(h, AD_EUNSUPPORTED, "a row of A^%d has more than 1024 entries", d);
+    if (bad & 2) return fail(h, AD_EUNSUPPORTED, "A^%d has more than 2^31 - 1 entries", d);
+    *nnz_d = tot;
+    return AD_OK;
+}
+
+int power_graph_cols(ad_handle h, const ad_csr* A, int32_t d, const int32_t* row_ptr_d,
+                     int32_t* col_d, void* stream) {
+    if (!h) return AD_EINVAL;
+    h->err.clear();
+    int rc = check_structure(h, A);
+    if (rc) return rc;
+    if (d < 1) return fail(h, AD_EINVAL, "d = %d < 1", d);
+    if (A->n > 0 && (!row_ptr_d || !col_d)) return fail(h, AD_EINVAL, "row_ptr_d or col_d is NULL");
+    AD_HIP(hipSetDevice(h->device));
+    TimedScope ts(h, "power_graph", (hipStream_t)stream);
+    rc = launch_pow_cols(A->n, d, A->row_ptr, A->col, row_ptr_d, col_d, h->status,
+                         (hipStream_t)stream);
+    return rc ? fail(h, rc, "power_graph_cols launch") : AD_OK;
+}
+
+int algebraic_distance_graph(ad_handle h, const ad_csr* A, int64_t nnz_g, const int32_t* row_ptr_g,
+                             const int32_t* col_g, int32_t K, const void* X, const double* w,
+                             int32_t target, void* mu, double* p, double theta,
+                             const uint8_t* fmask, uint8_t* strong, int32_t* nstrong,
+                             void* stream) {
+    if (!h) return AD_EINVAL;
+    h->err.clear();
+    int rc = check_csr(h, A);
+    if (rc) return rc;
+    if ((rc = check_pattern(h, A->n, nnz_g, row_ptr_g, col_g))) return rc;
+    if (!k_ok(K)) return fail(h, AD_EINVAL, "K = %d: must be 2, 4, 8, 16, 32 or 64", K);
+    if (target != AD_TARGET_PLAIN && target != AD_TARGET_RESIDUAL)
+        return fail(h, AD_EINVAL, "target = %d", target);
+    if ((rc = check_panel(h, X, "X", A->n))) return rc;
+    if (nnz_g > 0 && !mu) return fail(h, AD_EINVAL, "mu is NULL");
+    if (strong && !(theta > 0.0 && theta < 1.0))
+        return fail(h, AD_EINVAL, "theta = %g outside (0, 1)", theta);
+    if (A->n == 0) return AD_OK;
+    AD_HIP(hipSetDevice(h->device));
+    const ad_csr G{A->n, nnz_g, row_ptr_g, col_g, A->val, A->dtype};
+    const LaunchCfg cfg = cfg_for(h, KN_ALGDIST, A->dtype, K, &G);
+    TimedScope ts(h, "algdist_graph", (hipStream_t)stream);
+    rc = launch_algdist(A->dtype, K, &G, X, w, target, mu, p, theta, fmask, strong, nstrong,
+                        h->status, cfg, (hipStream_t)stream, A);
+    return rc ? fail(h, rc, "algebraic_distance_graph launch") : AD_OK;
+}
+
+int ls_interp_search(ad_handle h, const ad_csr* A, int64_t nnz_g, const int32_t* row_ptr_g,
+                     const int32_t* col_g, int32_t K, const void* X, const double* w,
+                     const uint8_t* cf, int32_t caliber, double gamma, int32_t target,
+                     int32_t* P_col, double* P_val, double* ls_val, int32_t* row_status,
+                     void* stream) {
+    if (!h) return AD_EINVAL;
+    h->err.clear();
+    int rc = check_csr(h, A);
+    if (rc) return rc;
+    if ((rc = check_pattern(h, A->n, nnz_g, row_ptr_g, col_g))) return rc;
+    if (!k_ok(K)) return fail(h, AD_EINVAL, "K = %d: must be 2, 4, 8, 16, 32 or 64", K);
+    if (caliber < 1 || caliber > 4)
+        return fail(h, AD_ECALIBER, "caliber = %d outside [1, 4] for the set search", caliber);
+    if (caliber > K)
+        return fail(h, AD_ECALIBER, "caliber = %d > K = %d: LS rows would not be unique", caliber, K);
+    if (!(gamma >= 0.0) || !(gamma < 1e6)) return fail(h, AD_EINVAL, "gamma = %g", gamma);
+    if (target != AD_TARGET_PLAIN && target != AD_TARGET_RESIDUAL)
+        return fail(h, AD_EINVAL, "target = %d", target);
+    if ((rc = check_panel(h, X, "X", A->n))) return rc;
+    if (A->n > 0 && (!cf || !P_col || !P_val || !ls_val || !row_status))
+        return fail(h, AD_EINVAL, "null output or input array");
+    if (A->n == 0) return AD_OK;
+    AD_HIP(hipSetDevice(h->device));
+    TimedScope ts(h, "ls_search", (hipStream_t)stream);
+    rc = launch_ls_search(A->dtype, K, A, row_ptr_g, col_g, X, w, cf, caliber, gamma, target,
+                          P_col, P_val, ls_val, row_status, h->status, (hipStream_t)stream);
+    return rc ? fail(h, rc, "ls_interp_search launch") : AD_OK;
+}
+
 int relax_algdist_batched(ad_handle h, int32_t nmat, const ad_csr* As, int32_t K, uint64_t seed,
                           int32_t relax, int32_t sweeps, double omega, const double* w, void* X,
                           void* mu, double theta, uint8_t* strong, int32_t* nstrong,

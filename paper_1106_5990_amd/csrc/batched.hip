@@ -107,7 +107,8 @@ __global__ __launch_bounds__(kBlock) void batch_algdist_kernel(
         const bool ghost = iw + g >= tl.r1;
         if (ghost && CoopGather<T, V, LPR>::G == 1) break;  // ghosts only serve group loads
         algdist_row<S, T, K, WEIGHTED, UN>(ghost ? tl.r1 - 1 : iw + g, ghost, l, m.rp, m.ci,
-                                       (const T*)m.av, xm, wd, wt, true, mum, nullptr, theta,
+                                       m.rp, m.ci, (const T*)m.av, xm, wd, wt, true, mum, nullptr,
+                                       theta,
                                        nullptr, sm, nsm, status);
     }
 }

@@ -27,7 +27,8 @@ namespace ad {
 
 template <typename T, int K, int LPR, bool WEIGHTED, int UN>
 __global__ __launch_bounds__(kBlock) void algdist_kernel(
-    int n, const int* __restrict__ rp, const int* __restrict__ ci, const T* __restrict__ av,
+    int n, const int* __restrict__ rp, const int* __restrict__ ci, const int* __restrict__ rpt,
+    const int* __restrict__ cit, const T* __restrict__ av,
     const T* __restrict__ X, const double* __restrict__ w, int target, T* __restrict__ mu,
     double* __restrict__ pout, double theta, const uint8_t* __restrict__ fmask,
     uint8_t* __restrict__ strong, int* __restrict__ nstrong, int iter, int xcd,
@@ -57,14 +58,14 @@ __global__ __launch_bounds__(kBlock) void algdist_kernel(
         const int64_t i64 = iw + g;
         const bool ghost = i64 >= n;
         if (ghost && CoopGather<T, V, LPR>::G == 1) break;  // ghosts only serve group loads
-        algdist_row<S, T, K, WEIGHTED, UN>(ghost ? n - 1 : (int)i64, ghost, l, rp, ci, av, X, wd,
+        algdist_row<S, T, K, WEIGHTED, UN>(ghost ? n - 1 : (int)i64, ghost, l, rp, ci, rpt, cit, av, X, wd,
                                            wt, plain, mu, pout, theta, fmask, strong, nstrong,
                                            status);
     }
 }
 
 template <typename T, int K, int LPR>
-static void algdist_go(const ad_csr* A, const void* X, const double* w, int target, void* mu,
+static void algdist_go(const ad_csr* A, const ad_csr* At, const void* X, const double* w, int target, void* mu,
                        double* p, double theta, const uint8_t* fmask, uint8_t* strong,
                        int32_t* nstrong, unsigned* st, const LaunchCfg& cfg, hipStream_t s) {
     using S = Shape<T, K, LPR>;
@@ -75,11 +76,13 @@ static void algdist_go(const ad_csr* A, const void* X, const double* w, int targ
         constexpr int UN = decltype(uc)::value;
         if (w)
             algdist_kernel<T, K, LPR, true, UN><<<dim3(grid), dim3(kBlock), 0, s>>>(
-                A->n, A->row_ptr, A->col, (const T*)A->val, (const T*)X, w, target, (T*)mu, p,
+                A->n, A->row_ptr, A->col, At->row_ptr, At->col, (const T*)At->val, (const T*)X, w,
+                target, (T*)mu, p,
                 theta, fmask, strong, nstrong, cfg.iter, cfg.xcd_map, st);
         else
             algdist_kernel<T, K, LPR, false, UN><<<dim3(grid), dim3(kBlock), 0, s>>>(
-                A->n, A->row_ptr, A->col, (const T*)A->val, (const T*)X, w, target, (T*)mu, p,
+                A->n, A->row_ptr, A->col, At->row_ptr, At->col, (const T*)At->val, (const T*)X, w,
+                target, (T*)mu, p,
                 theta, fmask, strong, nstrong, cfg.iter, cfg.xcd_map, st);
     });
 }
@@ -146,7 +149,7 @@ bool algdist_uses_edge(int dtype, int K, int target, const LaunchCfg& cfg) {
 }
 
 template <typename T>
-static int algdist_dispatch(int K, const ad_csr* A, const void* X, const double* w, int target,
+static int algdist_dispatch(int K, const ad_csr* A, const ad_csr* At, const void* X, const double* w, int target,
                             void* mu, double* p, double theta, const uint8_t* fmask,
                             uint8_t* strong, int32_t* nstrong, unsigned* st, const LaunchCfg& cfg,
                             hipStream_t s) {
@@ -154,15 +157,17 @@ static int algdist_dispatch(int K, const ad_csr* A, const void* X, const double*
         constexpr int KK = decltype(kc)::value;
         return with_lpr<T, KK>(cfg.lpr, [&](auto lc) {
             constexpr int L = decltype(lc)::value;
-            algdist_go<T, KK, L>(A, X, w, target, mu, p, theta, fmask, strong, nstrong, st, cfg, s);
+            algdist_go<T, KK, L>(A, At, X, w, target, mu, p, theta, fmask, strong, nstrong, st, cfg, s);
         });
     });
 }
 
 int launch_algdist(int dtype, int K, const ad_csr* A, const void* X, const double* w, int target,
                    void* mu, double* p, double theta, const uint8_t* fmask, uint8_t* strong,
-                   int32_t* nstrong, unsigned* status, const LaunchCfg& cfg, hipStream_t s) {
+                   int32_t* nstrong, unsigned* status, const LaunchCfg& cfg, hipStream_t s,
+                   const ad_csr* At) {
     if (A->n == 0) return AD_OK;
+    if (!At) At = A;
     if (algdist_uses_edge(dtype, K, target, cfg)) {
         const int rc = (dtype == AD_F32)
                            ? algdist_edge_dispatch<float>(K, A, X, w, mu, p, theta, fmask, strong,
@@ -175,9 +180,9 @@ int launch_algdist(int dtype, int K, const ad_csr* A, const void* X, const doubl
     }
     const int rc =
         (dtype == AD_F32)
-            ? algdist_dispatch<float>(K, A, X, w, target, mu, p, theta, fmask, strong, nstrong,
+            ? algdist_dispatch<float>(K, A, At, X, w, target, mu, p, theta, fmask, strong, nstrong,
                                       status, cfg, s)
-            : algdist_dispatch<double>(K, A, X, w, target, mu, p, theta, fmask, strong, nstrong,
+            : algdist_dispatch<double>(K, A, At, X, w, target, mu, p, theta, fmask, strong, nstrong,
                                        status, cfg, s);
     if (rc) return rc;
     AD_HIP(hipGetLastError());

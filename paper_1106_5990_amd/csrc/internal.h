@@ -186,9 +186,12 @@ int launch_unpermute(int dtype, int n, int K, const int32_t* rowlist, const void
 // true when algebraic_distance runs the edge-parallel kernel: default lanes
 // per row (cfg.lpr <= 0), plain target, panel rows of at most 128 bytes.
 bool algdist_uses_edge(int dtype, int K, int target, const LaunchCfg& cfg);
+// Distances over the entries of A; the residual target is formed from At
+// (NULL: A itself; another matrix when A is only a pattern, e.g. of A^d).
 int launch_algdist(int dtype, int K, const ad_csr* A, const void* X, const double* w, int target,
                    void* mu, double* p, double theta, const uint8_t* fmask, uint8_t* strong,
-                   int32_t* nstrong, unsigned* status, const LaunchCfg& cfg, hipStream_t s);
+                   int32_t* nstrong, unsigned* status, const LaunchCfg& cfg, hipStream_t s,
+                   const ad_csr* At = nullptr);
 int launch_strength(int dtype, const ad_csr* A, const void* mu, double theta,
                     const uint8_t* fmask, uint8_t* strong, int32_t* nstrong, hipStream_t s);
 int launch_csr_validate(const ad_csr* A, unsigned* status, hipStream_t s);
@@ -206,6 +209,21 @@ int launch_dist_ls(int dtype, int K, int caliber, const ad_csr* A, const void* X
                    double* ls_val, int32_t* row_status, double* block_sums, double* ls_sum,
                    unsigned* status, const LaunchCfg& cfg, hipStream_t s);
 int dist_ls_blocks(int dtype, int K, int n, const LaunchCfg& cfg);
+
+// ---- longrange.hip
+// Row pointers of the pattern of A^d into rpd (n + 1 ints) from the
+// structure of A; *host_tot receives the entry count and *host_bad a
+// nonzero value (1: a row over the per-row cap, 2: past int32) -- both after
+// synchronising s.  ws: pow_rows_workspace(n) bytes.
+size_t pow_rows_workspace(int n);
+int launch_pow_rows(int n, int d, const int* rp, const int* ci, int* rpd, void* ws,
+                    int64_t* host_tot, int* host_bad, hipStream_t s);
+int launch_pow_cols(int n, int d, const int* rp, const int* ci, const int* rpd, int* cid,
+                    unsigned* status, hipStream_t s);
+int launch_ls_search(int dtype, int K, const ad_csr* A, const int* rpg, const int* cig,
+                     const void* X, const double* w, const uint8_t* cf, int caliber, double gamma,
+                     int target, int32_t* P_col, double* P_val, double* ls_val,
+                     int32_t* row_status, unsigned* status, hipStream_t s);
 
 // ---- autotune.hip
 int autotune(ad_handle h, const ad_csr* A, int K, int relax, const int32_t* color, int ncolors,

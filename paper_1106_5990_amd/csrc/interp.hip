@@ -294,7 +294,7 @@ __global__ __launch_bounds__(kBlock) void dist_ls_kernel(
             }
             double t64[V], d;
             algdist_row_sel<S, T, K, WEIGHTED, UN>(
-                i, ghost, l, rp, ci, av, X, wd, wt, plain, mu, nullptr, theta, fmask, strong,
+                i, ghost, l, rp, ci, rp, ci, av, X, wd, wt, plain, mu, nullptr, theta, fmask, strong,
                 nstrong, status,
                 [&](int j, T m) {
                     if (isF && cf[j] != 0) ls_insert<T, CALT>(smu, scol, nsel, cal, m, j);

@@ -1,0 +1,542 @@
+// longrange.hip -- long-range connectivity and the search over interpolatory
+// sets (Sec. 4.1 eq. graph, the closing remark of Sec. 4.2, Sec. 4.3).
+//
+// Pattern of A^d.  Row i of A^d holds (structurally) every j within graph
+// distance d of i; A^d itself is never formed.  One wavefront per row runs
+// a breadth-first search of depth d over the graph of A: the set found so
+// far lives in an LDS hash table (open addressing, compare-and-swap
+// inserts), and each newly inserted vertex is appended to an LDS list, so
+// the list holds the levels one after the other and the current frontier
+// is its last range.  The count pass writes |row|; the fill pass repeats
+// the search and writes the list sorted (bitonic sort in LDS).
+//
+// Interpolatory-set search.  One wavefront per F row: the row's candidates
+// (the C-points of its row of the pattern, i excluded, in column order) and
+// their panel rows are staged in LDS as FP64, with the target and the FP64
+// Gram matrix G_ab = <x_a, x_b>_w and h_a = <x_a, t>_w of all candidates.
+// Every set W of each size m <= caliber is then a small Cholesky on
+// entries of G: LS_W = S - |L^{-1} h_W|^2 with S = <t, t>_w (a set with a
+// pivot <= 1e-12 of its Gram diagonal is numerically dependent and
+// skipped).  Lanes take consecutive blocks of the sets in lexicographic
+// order (the first unranked, the rest by successor); the least (value,
+// rank) over the wave is that size's best.  The size is chosen by the
+// penalty rule in increasing size against the incumbent, on values
+// relative to S; the chosen set's weights come from its Cholesky solve and
+// its functional is evaluated by definition.
+#include <math.h>
+
+#include "device.h"
+#include "internal.h"
+
+namespace ad {
+
+// ---------------------------------------------------------------- pattern of A^d
+constexpr int kPowCap = 1024;   // entries per row of A^d
+constexpr int kPowHash = 2048;  // LDS hash slots per wavefront (load factor <= 1/2 + 1/32)
+constexpr int kPowWaves = 2;    // wavefronts (rows) per workgroup
+
+struct PowLds {
+    int hash[kPowWaves][kPowHash];
+    int list[kPowWaves][kPowCap];
+    int n[kPowWaves];
+};
+
+__device__ __forceinline__ void wave_sync_lds() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Breadth-first search of depth d from row i into L.list[wv][0 .. n);
+// returns n, or -1 when the row of A^d has more than kPowCap entries.
+__device__ int pow_row(int i, int d, const int* __restrict__ rp, const int* __restrict__ ci,
+                       PowLds& L, int wv, int lane) {
+    int* hash = L.hash[wv];
+    int* list = L.list[wv];
+    for (int q = lane; q < kPowHash; q += kWave) hash[q] = -1;
+    if (lane == 0) {
+        L.n[wv] = 1;
+        list[0] = i;
+    }
+    wave_sync_lds();
+    if (lane == 0) hash[((unsigned)i * 2654435761u) & (kPowHash - 1)] = i;
+    wave_sync_lds();
+    int lo = 0, hi = 1;
+    bool over = false;
+    for (int lev = 0; lev < d && lo < hi; ++lev) {
+        for (int q = lo + lane; q < hi; q += kWave) {
+            const int u = list[q];
+            for (int e = rp[u]; e < rp[u + 1]; ++e) {
+                const int j = ci[e];
+                unsigned slot = ((unsigned)j * 2654435761u) & (kPowHash - 1);
+                for (int probe = 0; probe < kPowHash; ++probe) {
+                    const int prev = atomicCAS(&hash[slot], -1, j);
+                    if (prev == j) break;  // already in the set
+                    if (prev == -1) {      // new: append to the next level
+                        const int pos = atomicAdd(&L.n[wv], 1);
+                        if (pos < kPowCap) list[pos] = j;
+                        break;
+                    }
+                    slot = (slot + 1) & (kPowHash - 1);
+                }
+                // stop inserting once the cap is passed (the table keeps
+                // at most kPowCap + one insert per lane)
+                if (__atomic_load_n(&L.n[wv], __ATOMIC_RELAXED) > kPowCap) {
+                    over = true;
+                    break;
+                }
+            }
+            if (over) break;
+        }
+        wave_sync_lds();
+        lo = hi;
+        hi = L.n[wv];
+        if (__any(over) || hi > kPowCap) return -1;
+    }
+    return hi;
+}
+
+__global__ __launch_bounds__(kWave* kPowWaves) void pow_count_kernel(int n, int d,
+                                                                     const int* __restrict__ rp,
+                                                                     const int* __restrict__ ci,
+                                                                     int* __restrict__ cnt) {
+    __shared__ PowLds L;
+    const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
+    const int64_t i = (int64_t)blockIdx.x * kPowWaves + wv;
+    if (i >= n) return;  // whole wavefront
+    const int c = pow_row((int)i, d, rp, ci, L, wv, lane);
+    if (lane == 0) cnt[i] = c;
+}
+
+__global__ __launch_bounds__(kWave* kPowWaves) void pow_fill_kernel(
+    int n, int d, const int* __restrict__ rp, const int* __restrict__ ci,
+    const int* __restrict__ rpd, int* __restrict__ cid, unsigned* status) {
+    __shared__ PowLds L;
+    const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
+    const int64_t i = (int64_t)blockIdx.x * kPowWaves + wv;
+    if (i >= n) return;  // whole wavefront
+    const int c = pow_row((int)i, d, rp, ci, L, wv, lane);
+    if (c < 0) return;  // the count pass refused such a matrix
+    int* a = L.list[wv];
+    int m = 1;
+    while (m < c) m <<= 1;
+    for (int q = c + lane; q < m; q += kWave) a[q] = 0x7fffffff;
+    wave_sync_lds();
+    // bitonic sort of a[0 .. m), m a power of two <= kPowCap
+    for (int k = 2; k <= m; k <<= 1) {
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            for (int q = lane; q < m; q += kWave) {
+                const int p = q ^ j;
+                if (p > q) {
+                    const int x = a[q], y = a[p];
+                    const bool up = (q & k) == 0;
+                    if ((x > y) == up) {
+                        a[q] = y;
+                        a[p] = x;
+                    }
+                }
+            }
+            wave_sync_lds();
+        }
+    }
+    // row pointers that do not match this row's length (not those of the
+    // same A and d) are flagged, and no entry is written outside the row
+    const int room = rpd[i + 1] - rpd[i];
+    if (room != c && lane == 0) flag(status, AD_STAT_PATTERN);
+    const int cw = room < c ? room : c;
+    int* out = cid + rpd[i];
+    for (int q = lane; q < cw; q += kWave) out[q] = a[q];
+}
+
+// rpd[0] = 0, rpd[i + 1] = rpd[i] + cnt[i] (int32), total into *tot; a
+// negative count (a row over the cap) or a total past int32 sets *bad.
+__global__ __launch_bounds__(kBlock) void pow_rows_kernel(int n, const int* __restrict__ cnt,
+                                                          const int64_t* __restrict__ pre,
+                                                          int* __restrict__ rpd,
+                                                          int64_t* __restrict__ tot,
+                                                          int* __restrict__ bad) {
+    const int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (q > n) return;
+    const int64_t v = pre[q];
+    if (q < n && cnt[q] < 0) atomicOr(bad, 1);
+    if (v > 0x7fffffffLL) atomicOr(bad, 2);
+    rpd[q] = (int)v;
+    if (q == n) *tot = v;
+}
+
+size_t pow_rows_workspace(int n) {
+    return sizeof(int) * ((size_t)n + 1) + sizeof(int64_t) * ((size_t)n + 2) +
+           (size_t)scan_workspace_bytes(n) + 1024;
+}
+
+int launch_pow_rows(int n, int d, const int* rp, const int* ci, int* rpd, void* ws,
+                    int64_t* host_tot, int* host_bad, hipStream_t s) {
+    WsReq req;
+    const size_t o_cnt = req.add(sizeof(int) * ((size_t)n + 1));
+    const size_t o_pre = req.add(sizeof(int64_t) * ((size_t)n + 1));
+    const size_t o_sc = req.add((size_t)scan_workspace_bytes(n));
+    const size_t o_tot = req.add(sizeof(int64_t) + sizeof(int));
+    char* w = (char*)ws;
+    int* cnt = (int*)(w + o_cnt);
+    int64_t* pre = (int64_t*)(w + o_pre);
+    int64_t* tot = (int64_t*)(w + o_tot);
+    int* bad = (int*)(w + o_tot + sizeof(int64_t));
+    int rc;
+    if ((rc = launch_fill_i32(bad, 1, 0, s))) return rc;
+    if (n > 0) {
+        const unsigned nb = (unsigned)(((int64_t)n + kPowWaves - 1) / kPowWaves);
+        pow_count_kernel<<<dim3(nb), dim3(kWave * kPowWaves), 0, s>>>(n, d, rp, ci, cnt);
+        AD_HIP(hipGetLastError());
+    }
+    if ((rc = launch_excl_scan(cnt, n, pre, (int64_t*)(w + o_sc), s))) return rc;
+    const unsigned nb = (unsigned)(((int64_t)n + 1 + kBlock - 1) / kBlock);
+    pow_rows_kernel<<<dim3(nb), dim3(kBlock), 0, s>>>(n, cnt, pre, rpd, tot, bad);
+    AD_HIP(hipGetLastError());
+    AD_HIP(hipMemcpyAsync(host_tot, tot, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    AD_HIP(hipMemcpyAsync(host_bad, bad, sizeof(int), hipMemcpyDeviceToHost, s));
+    AD_HIP(hipStreamSynchronize(s));
+    return AD_OK;
+}
+
+int launch_pow_cols(int n, int d, const int* rp, const int* ci, const int* rpd, int* cid,
+                    unsigned* status, hipStream_t s) {
+    if (n == 0) return AD_OK;
+    const unsigned nb = (unsigned)(((int64_t)n + kPowWaves - 1) / kPowWaves);
+    pow_fill_kernel<<<dim3(nb), dim3(kWave * kPowWaves), 0, s>>>(n, d, rp, ci, rpd, cid,
+                                                                   status);
+    AD_HIP(hipGetLastError());
+    return AD_OK;
+}
+
+// ---------------------------------------------------------------- set search
+constexpr int kSearchCand = 64;  // candidates per row (one per lane)
+constexpr int kSearchCal = 4;    // largest set size
+constexpr int kSearchGram = kSearchCand * (kSearchCand + 1) / 2;
+
+template <int K>
+struct SearchLds {
+    double x[kSearchCand][K + 1];  // candidate panel rows (padded against bank conflicts)
+    double t[K];
+    double w[K];
+    double g[kSearchGram];  // packed lower triangle, (a, b) at a (a + 1) / 2 + b, b <= a
+    double h[kSearchCand];
+    int cand[kSearchCand];
+    double red[kWave];
+    int redr[kWave];
+    int ncand;
+};
+
+__device__ __forceinline__ int64_t binom_small(int a, int b) {
+    if (b < 0 || a < b) return 0;
+    switch (b) {
+        case 0: return 1;
+        case 1: return a;
+        case 2: return (int64_t)a * (a - 1) / 2;
+        case 3: return (int64_t)a * (a - 1) * (a - 2) / 6;
+        default: return (int64_t)a * (a - 1) * (a - 2) * (a - 3) / 24;
+    }
+}
+
+// The combination of rank r (lexicographic order) of m out of nc.
+__device__ __forceinline__ void unrank(int64_t r, int nc, int m, int (&idx)[kSearchCal]) {
+    int c = 0;
+#pragma unroll
+    for (int q = 0; q < kSearchCal; ++q) {
+        if (q >= m) break;
+        for (;;) {
+            const int64_t cnt = binom_small(nc - c - 1, m - q - 1);
+            if (r < cnt) break;
+            r -= cnt;
+            ++c;
+        }
+        idx[q] = c++;
+    }
+}
+
+// The successor of idx in lexicographic order (false after the last).
+__device__ __forceinline__ bool next_comb(int nc, int m, int (&idx)[kSearchCal]) {
+    int q = m - 1;
+    while (q >= 0 && idx[q] == nc - m + q) --q;
+    if (q < 0) return false;
+    ++idx[q];
+#pragma unroll
+    for (int p = 1; p < kSearchCal; ++p)
+        if (p > q && p < m) idx[p] = idx[p - 1] + 1;
+    return true;
+}
+
+__device__ __forceinline__ double gram_at(const double* g, int a, int b) {
+    return (a >= b) ? g[a * (a + 1) / 2 + b] : g[b * (b + 1) / 2 + a];
+}
+
+// Cholesky of G_W (W = candidates idx[0..m)) with the dependence rule;
+// returns false for a dependent set, else the functional S - |L^{-1} h|^2
+// in *val (clamped at 0) and, when coef != nullptr, the minimiser.
+__device__ bool subset_fit(const double* g, const double* h, double S, int m,
+                           const int (&idx)[kSearchCal], double* val, double* coef) {
+    double L[kSearchCal][kSearchCal];
+    double z[kSearchCal];
+#pragma unroll
+    for (int a = 0; a < kSearchCal; ++a) {
+        if (a >= m) break;
+        const double gaa = gram_at(g, idx[a], idx[a]);
+#pragma unroll
+        for (int b = 0; b < kSearchCal; ++b) {
+            if (b >= a) break;
+            double s = gram_at(g, idx[a], idx[b]);
+#pragma unroll
+            for (int c = 0; c < kSearchCal; ++c) {
+                if (c >= b) break;
+                s -= L[a][c] * L[b][c];
+            }
+            L[a][b] = s / L[b][b];
+        }
+        double piv = gaa;
+#pragma unroll
+        for (int b = 0; b < kSearchCal; ++b) {
+            if (b >= a) break;
+            piv -= L[a][b] * L[a][b];
+        }
+        if (!(piv > 1e-12 * gaa)) return false;
+        L[a][a] = sqrt(piv);
+    }
+    double zz = 0.0;
+#pragma unroll
+    for (int a = 0; a < kSearchCal; ++a) {
+        if (a >= m) break;
+        double s = h[idx[a]];
+#pragma unroll
+        for (int b = 0; b < kSearchCal; ++b) {
+            if (b >= a) break;
+            s -= L[a][b] * z[b];
+        }
+        z[a] = s / L[a][a];
+        zz += z[a] * z[a];
+    }
+    const double v = S - zz;
+    *val = v > 0.0 ? v : 0.0;
+    if (coef) {
+#pragma unroll
+        for (int a = kSearchCal - 1; a >= 0; --a) {
+            if (a >= m) continue;
+            double s = z[a];
+#pragma unroll
+            for (int b = 0; b < kSearchCal; ++b)
+                if (b > a && b < m) s -= L[b][a] * coef[b];
+            coef[a] = s / L[a][a];
+        }
+    }
+    return true;
+}
+
+template <typename T, int K>
+__global__ __launch_bounds__(kWave) void ls_search_kernel(
+    int n, const int* __restrict__ rp, const int* __restrict__ ci, const T* __restrict__ av,
+    const int* __restrict__ rpg, const int* __restrict__ cig, const T* __restrict__ X,
+    const double* __restrict__ w, const uint8_t* __restrict__ cf, int cal, double gamma,
+    int target, int* __restrict__ Pcol, double* __restrict__ Pval, double* __restrict__ lsv,
+    int* __restrict__ rstat, unsigned* status) {
+    __shared__ SearchLds<K> L;
+    const int lane = threadIdx.x;
+    const int64_t i64 = blockIdx.x;
+    if (i64 >= n) return;
+    const int i = (int)i64;
+    int* pc = Pcol + (size_t)i * cal;
+    double* pv = Pval + (size_t)i * cal;
+    if (cf[i]) {  // a C point interpolates itself
+        if (lane < cal) {
+            pc[lane] = lane == 0 ? i : -1;
+            pv[lane] = lane == 0 ? 1.0 : 0.0;
+        }
+        if (lane == 0) {
+            lsv[i] = 0.0;
+            rstat[i] = 0;
+        }
+        return;
+    }
+    int st = 0;
+    // target (FP64): lane k holds t_k
+    if (lane < K) {
+        const double wk = w ? w[lane] : 1.0;
+        double t = (double)X[(size_t)i * K + lane];
+        if (target == AD_TARGET_RESIDUAL) {
+            double y = 0.0, d = 0.0;
+            for (int e = rp[i]; e < rp[i + 1]; ++e) {
+                const int j = ci[e];
+                const double a = (double)av[e];
+                y = fma(a, (double)X[(size_t)j * K + lane], y);
+                if (j == i) d = a;
+            }
+            if (d != 0.0) t = t - y / d;
+            else st = 3;
+        }
+        L.t[lane] = t;
+        L.w[lane] = wk;
+    }
+    st = __shfl(st, 0, kWave);
+    if (st == 3 && lane == 0) flag(status, AD_STAT_ZERO_DIAG);
+    // candidates: C points of row i of the pattern, i excluded, in column order
+    const int g0 = rpg[i], g1 = rpg[i + 1];
+    int nc = 0;
+    bool over = false;
+    for (int e0 = g0; e0 < g1; e0 += kWave) {
+        const int e = e0 + lane;
+        const int j = e < g1 ? cig[e] : -1;
+        const bool isc = j >= 0 && j != i && cf[j] != 0;
+        const uint64_t bal = __ballot(isc);
+        const int pos = nc + __popcll(bal & ((lane == 0) ? 0ull : (~0ull >> (64 - lane))));
+        if (isc && pos < kSearchCand) L.cand[pos] = j;
+        nc += __popcll(bal);
+    }
+    if (nc > kSearchCand) {
+        over = true;
+        nc = kSearchCand;
+    }
+    __syncthreads();
+    // candidate rows (FP64) and the target's functional S = <t, t>_w
+    for (int q = lane; q < nc * K; q += kWave) {
+        const int a = q / K, k = q % K;
+        L.x[a][k] = (double)X[(size_t)L.cand[a] * K + k];
+    }
+    __syncthreads();
+    double S = 0.0;
+    for (int k = 0; k < K; ++k) S = fma(L.w[k] * L.t[k], L.t[k], S);
+    // h_a and the Gram matrix of the candidates
+    if (lane < nc) {
+        double s = 0.0;
+        for (int k = 0; k < K; ++k) s = fma(L.w[k] * L.x[lane][k], L.t[k], s);
+        L.h[lane] = s;
+    }
+    const int npair = nc * (nc + 1) / 2;
+    for (int p = lane; p < npair; p += kWave) {
+        int a = (int)((sqrt(8.0 * p + 1.0) - 1.0) * 0.5);
+        while (a * (a + 1) / 2 > p) --a;
+        while ((a + 1) * (a + 2) / 2 <= p) ++a;
+        const int b = p - a * (a + 1) / 2;
+        double s = 0.0;
+        for (int k = 0; k < K; ++k) s = fma(L.w[k] * L.x[a][k], L.x[b][k], s);
+        L.g[p] = s;
+    }
+    __syncthreads();
+
+    // best set of each size, then the penalty rule against the incumbent
+    int inc_m = 0;
+    int inc_idx[kSearchCal] = {0, 0, 0, 0};
+    double inc_v = 0.0;
+    // a row past the candidate cap is left empty (status 4)
+    const int mmax = over ? 0 : (cal < nc ? cal : nc);
+    for (int m = 1; m <= mmax; ++m) {
+        const int64_t total = binom_small(nc, m);
+        const int64_t per = (total + kWave - 1) / kWave;
+        const int64_t r0 = (int64_t)lane * per, r1 = (r0 + per < total) ? r0 + per : total;
+        double bv = INFINITY;
+        int64_t br = total;
+        if (r0 < r1) {
+            int idx[kSearchCal];
+            unrank(r0, nc, m, idx);
+            for (int64_t r = r0; r < r1; ++r) {
+                double v;
+                if (subset_fit(L.g, L.h, S, m, idx, &v, nullptr) && v < bv) {
+                    bv = v;
+                    br = r;
+                }
+                next_comb(nc, m, idx);
+            }
+        }
+        // least (value, rank) over the wave: lanes hold increasing rank blocks
+#pragma unroll
+        for (int o = kWave / 2; o > 0; o >>= 1) {
+            const double ov = __shfl_xor(bv, o, kWave);
+            const int64_t orr = __shfl_xor(br, o, kWave);
+            if (ov < bv || (ov == bv && orr < br)) {
+                bv = ov;
+                br = orr;
+            }
+        }
+        if (br >= total) continue;  // every set of this size was dependent
+        int idx[kSearchCal];
+        unrank(br, nc, m, idx);
+        bool take = inc_m == 0;
+        if (!take) {
+            const double rel = S > 0.0 ? bv / S : 0.0;
+            const double inc_rel = S > 0.0 ? inc_v / S : 0.0;
+            take = rel < pow(inc_rel, gamma * (double)(m - inc_m));
+        }
+        if (take) {
+            inc_m = m;
+            inc_v = bv;
+#pragma unroll
+            for (int q = 0; q < kSearchCal; ++q) inc_idx[q] = idx[q];
+        }
+    }
+
+    // the chosen set: weights by its Cholesky solve, functional by definition
+    double coef[kSearchCal] = {0.0, 0.0, 0.0, 0.0};
+    double val;
+    if (inc_m > 0) {
+        subset_fit(L.g, L.h, S, inc_m, inc_idx, &val, coef);
+        double r = 0.0;
+        if (lane < K) {
+            r = L.t[lane];
+#pragma unroll
+            for (int a = 0; a < kSearchCal; ++a)
+                if (a < inc_m) r -= coef[a] * L.x[inc_idx[a]][lane];
+            r = L.w[lane] * r * r;
+        }
+#pragma unroll
+        for (int o = kWave / 2; o > 0; o >>= 1) r += __shfl_xor(r, o, kWave);
+        val = r;
+    } else {
+        val = S;
+    }
+    int mycol = -1;
+    double mycoef = 0.0;
+#pragma unroll
+    for (int a = 0; a < kSearchCal; ++a)
+        if (lane == a && a < inc_m) {
+            mycol = L.cand[inc_idx[a]];
+            mycoef = coef[a];
+        }
+    if (lane < cal) {
+        pc[lane] = mycol;
+        pv[lane] = mycoef;
+    }
+    if (lane == 0) {
+        lsv[i] = val;
+        rstat[i] = over ? 4 : (inc_m == 0 ? (st ? st : 1) : st);
+        if (over) flag(status, AD_STAT_SEARCH_CAP);
+    }
+}
+
+template <typename T>
+static int ls_search_dispatch(int K, const ad_csr* A, const int* rpg, const int* cig,
+                              const void* X, const double* w, const uint8_t* cf, int cal,
+                              double gamma, int target, int* Pcol, double* Pval, double* lsv,
+                              int* rstat, unsigned* status, hipStream_t s) {
+    return with_k<T>(K, [&](auto kc) {
+        constexpr int KK = decltype(kc)::value;
+        ls_search_kernel<T, KK><<<dim3((unsigned)A->n), dim3(kWave), 0, s>>>(
+            A->n, A->row_ptr, A->col, (const T*)A->val, rpg, cig, (const T*)X, w, cf, cal, gamma,
+            target, Pcol, Pval, lsv, rstat, status);
+        return (int)AD_OK;
+    });
+}
+
+int launch_ls_search(int dtype, int K, const ad_csr* A, const int* rpg, const int* cig,
+                     const void* X, const double* w, const uint8_t* cf, int caliber, double gamma,
+                     int target, int32_t* P_col, double* P_val, double* ls_val,
+                     int32_t* row_status, unsigned* status, hipStream_t s) {
+    if (A->n == 0) return AD_OK;
+    const int rc = (dtype == AD_F32)
+                       ? ls_search_dispatch<float>(K, A, rpg, cig, X, w, cf, caliber, gamma,
+                                                   target, P_col, P_val, ls_val, row_status,
+                                                   status, s)
+                       : ls_search_dispatch<double>(K, A, rpg, cig, X, w, cf, caliber, gamma,
+                                                    target, P_col, P_val, ls_val, row_status,
+                                                    status, s);
+    if (rc) return rc;
+    AD_HIP(hipGetLastError());
+    return AD_OK;
+}
+
+}  // namespace ad

@@ -299,10 +299,15 @@ __device__ __forceinline__ T ratio(T a, T b) {
 // absent; only looked for with the residual target).  A ghost row (a lane
 // past the end of the rows, i clamped to a valid row) has no entries and
 // writes nothing, but takes its part in the cooperative panel loads.
+// The distances run over the entries of (rp, ci); the residual target is
+// formed from the rows of (rpt, cit, av) -- the matrix itself, also when
+// (rp, ci) is another pattern such as that of A^d.
 template <typename S, typename T, int K, bool WEIGHTED, int UN, typename Sel>
 __device__ __forceinline__ void algdist_row_sel(int i, bool ghost, int l,
                                                 const int* __restrict__ rp,
                                                 const int* __restrict__ ci,
+                                                const int* __restrict__ rpt,
+                                                const int* __restrict__ cit,
                                                 const T* __restrict__ av, const T* __restrict__ X,
                                                 const double (&wd)[S::V], const T (&wt)[S::V],
                                                 bool plain, T* __restrict__ mu,
@@ -332,8 +337,9 @@ __device__ __forceinline__ void algdist_row_sel(int i, bool ghost, int l,
 #pragma unroll
         for (int q = 0; q < V; ++q) y[q] = 0.0;
         double d = 0.0;
-        for (int e = e0; e < e1; ++e) {
-            const int j = ci[e];
+        const int f0 = rpt[i], f1 = ghost ? f0 : rpt[i + 1];
+        for (int e = f0; e < f1; ++e) {
+            const int j = cit[e];
             const double a = (double)av[e];
             Frag<T, V> xj = load_lane<T, V, C>(X + (size_t)j * K + l * V);
 #pragma unroll
@@ -495,7 +501,8 @@ __device__ __forceinline__ void algdist_row_sel(int i, bool ghost, int l,
 
 template <typename S, typename T, int K, bool WEIGHTED, int UN>
 __device__ __forceinline__ void algdist_row(int i, bool ghost, int l, const int* __restrict__ rp,
-                                            const int* __restrict__ ci, const T* __restrict__ av,
+                                            const int* __restrict__ ci, const int* __restrict__ rpt,
+                                            const int* __restrict__ cit, const T* __restrict__ av,
                                             const T* __restrict__ X, const double (&wd)[S::V],
                                             const T (&wt)[S::V], bool plain, T* __restrict__ mu,
                                             double* __restrict__ pout, double theta,
@@ -503,7 +510,7 @@ __device__ __forceinline__ void algdist_row(int i, bool ghost, int l, const int*
                                             uint8_t* __restrict__ strong, int* __restrict__ nstrong,
                                             unsigned* status) {
     double t64[S::V], d;
-    algdist_row_sel<S, T, K, WEIGHTED, UN>(i, ghost, l, rp, ci, av, X, wd, wt, plain, mu, pout,
+    algdist_row_sel<S, T, K, WEIGHTED, UN>(i, ghost, l, rp, ci, rpt, cit, av, X, wd, wt, plain, mu, pout,
                                            theta, fmask, strong, nstrong, status, [](int, T) {},
                                            t64, d);
 }

@@ -1,0 +1,271 @@
+"""The long-range calls on the GPU against the oracle: the pattern of A^d
+(bit-exact), distances and the strength graph on it (the per-step bars of
+the short-range distances), and the search over interpolatory sets
+(identical sets and statuses wherever the oracle's decision is not within
+rounding of a tie; where it is, the GPU's set is checked to be a valid
+choice; weights and functional to the LS bars)."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1106_5990_amd import workloads as W
+from gpu_common import check_mu, dev_csr, lib, say, to_np
+
+pytestmark = pytest.mark.gpu
+
+
+def _csr_from_dense(D):
+    D = np.asarray(D, dtype=np.float64)
+    n = D.shape[0]
+    mask = D != 0
+    mask[np.arange(n), np.arange(n)] = True
+    rows, cols = np.nonzero(mask)
+    rp = np.zeros(n + 1, dtype=np.int32)
+    np.cumsum(np.bincount(rows, minlength=n), out=rp[1:])
+    return W.CSR(n, rp, cols.astype(np.int32), D[rows, cols])
+
+
+def _asym(n, seed, density):
+    rng = np.random.default_rng(seed)
+    D = np.where(rng.random((n, n)) < density, -rng.random((n, n)), 0.0)
+    return _csr_from_dense(D + np.diag(4.0 + rng.random(n)))
+
+
+def _matrices():
+    return {"lap5": W.laplacian_2d_5pt(33), "aniso9": W.rotated_anisotropic_9pt(30, 1e-3, 0.4),
+            "rgg": W.rgg_laplacian(2000, 8.0, 11), "asym": _asym(300, 4, 0.01),
+            "lap3d": W.lognormal_3d_7pt(12, 1.0, 3), "one": W.laplacian_2d_5pt(1)}
+
+
+@pytest.mark.parametrize("d", [1, 2, 3, 4])
+def test_power_graph_is_the_oracle_pattern(d):
+    ad = lib()
+    for name, A in _matrices().items():
+        say("pattern of A^%d, %s (n = %d)" % (d, name, A.n))
+        Ad = dev_csr(A, torch.float64)
+        G = ad.power_graph(Ad, d)
+        R = oracle.power_pattern(A, d)
+        assert np.array_equal(to_np(G.row_ptr), R.row_ptr), name
+        assert np.array_equal(to_np(G.col), R.col), name
+    assert ad.status(clear=True) == 0
+
+
+def test_power_graph_limits():
+    """Rows of A^d past 1024 entries are refused; an empty matrix gives an
+    empty pattern; d < 1 is an argument error."""
+    ad = lib()
+    A = _asym(2000, 8, 0.05)  # about 100 entries per row: A^2 rows pass 1024
+    assert oracle.power_pattern(A, 2).row_ptr[1] > 1024
+    Ad = dev_csr(A, torch.float64)
+    with pytest.raises(ad.AlgdistError, match="AD_EUNSUPPORTED"):
+        ad.power_graph(Ad, 2)
+    with pytest.raises(ad.AlgdistError, match="AD_EINVAL"):
+        ad.power_graph(Ad, 0)
+    E = ad.Csr(torch.zeros(1, dtype=torch.int32, device="cuda"),
+               torch.zeros(0, dtype=torch.int32, device="cuda"),
+               torch.zeros(0, dtype=torch.float64, device="cuda"))
+    G = ad.power_graph(E, 2)
+    assert G.nnz == 0 and to_np(G.row_ptr).tolist() == [0]
+    assert ad.status(clear=True) == 0
+
+
+def _graph_csr(G, n):
+    rp, col = to_np(G.row_ptr), to_np(G.col)
+    return W.CSR(n, rp, col, np.zeros(len(col)))
+
+
+def _saa_graph(Gc, T, w=None):
+    w = np.ones(T.shape[1]) if w is None else np.asarray(w)
+    return ((T * T * w).sum(1))[Gc.row_ids()]
+
+
+@pytest.mark.parametrize("dt", [torch.float64, torch.float32])
+@pytest.mark.parametrize("target", ["plain", "residual"])
+@pytest.mark.parametrize("weighted", [False, True])
+@pytest.mark.parametrize("lpr", [0, 4])
+def test_distances_on_the_pattern_of_a_power(dt, target, weighted, lpr):
+    """mu on A^2's pattern (and A^3's) against the oracle given the same
+    panel: FP64 1e-10, FP32 1e-4 relative (with the S_aa floors); the
+    strength graph on that pattern bit-exact given mu."""
+    ad = lib()
+    N, K = 37, 16
+    A = W.rotated_anisotropic_9pt(N, 1e-3, math.atan(0.5))
+    if dt == torch.float32:
+        A = W.CSR(A.n, A.row_ptr, A.col, A.val.astype(np.float32).astype(np.float64))
+    Ad = dev_csr(A, dt)
+    color = torch.as_tensor(W.red_black((N, N)), device="cuda")
+    X = ad.setup_testvectors(Ad, K, seed=9, relax="gs", sweeps=3, color=color, ncolors=2)
+    x = to_np(X).astype(np.float64)
+    w = (0.5 + np.random.default_rng(2).random(K)) if weighted else None
+    wt = None if w is None else torch.as_tensor(w, device="cuda")
+    ad.set_launch("algdist", dt, K, lanes_per_row=lpr)
+    try:
+        for d in (2, 3):
+            say("distances on A^%d: %s %s weighted=%s lpr=%d" % (d, dt, target, weighted, lpr))
+            G = ad.power_graph(Ad, d)
+            Gc = _graph_csr(G, A.n)
+            mu, strong, ns = ad.algebraic_distance_graph(Ad, G, X, w=wt, target=target, fuse=True,
+                                                         theta=0.25)
+            tg = oracle.TARGET_PLAIN if target == "plain" else oracle.TARGET_RESIDUAL
+            ref = oracle.algdist_graph(A, oracle.Pattern(A.n, Gc.row_ptr, Gc.col), x, w, tg)
+            if target == "plain":
+                T = x
+            else:
+                import scipy.sparse as sp
+                S_ = sp.csr_matrix((A.val, A.col, A.row_ptr), shape=(A.n, A.n))
+                T = x - (S_ @ x) / S_.diagonal()[:, None]
+            mu_h = to_np(mu).astype(np.float64)
+            check_mu(mu_h, ref, _saa_graph(Gc, T, w), dt, "A^%d" % d)
+            s_ref, ns_ref = oracle.strength(Gc, mu_h, 0.25)
+            assert np.array_equal(to_np(strong), s_ref) and np.array_equal(to_np(ns), ns_ref)
+    finally:
+        ad.set_launch("algdist", dt, K, lanes_per_row=0)
+    assert ad.status(clear=True) == 0
+
+
+def _scan_sizes(best_rel, gamma, tol=1e-6):
+    """The penalty scan on given relative best values; returns (size,
+    near) where near says some comparison was within tol of its threshold."""
+    inc_m, inc_v, near = 0, None, False
+    for m in range(1, len(best_rel)):
+        v = best_rel[m]
+        if v < 0:
+            continue
+        if inc_m == 0:
+            inc_m, inc_v = m, v
+            continue
+        thr = inc_v ** (gamma * (m - inc_m))
+        if thr > 0 and abs(v / thr - 1.0) < tol:
+            near = True
+        if v < thr:
+            inc_m, inc_v = m, v
+    return inc_m, near
+
+
+def check_search(A, G, x, w, cf, cal, gamma, target, got, dt):
+    """GPU search results `got` against the oracle (see the module doc)."""
+    Gp = oracle.Pattern(A.n, to_np(G.row_ptr), to_np(G.col))
+    tg = oracle.TARGET_PLAIN if target == "plain" else oracle.TARGET_RESIDUAL
+    Rc, Rv, Rl, Rs, best, nc = oracle.ls_search(A, Gp, x, w, cf, cal, gamma, tg)
+    Pc, Pv, ls, st = (to_np(t) for t in got)
+    assert np.array_equal(st, Rs), "status differ at %s" % np.nonzero(st != Rs)[0][:5]
+    same = np.all(Pc == Rc, axis=1)
+    diff_rows = np.nonzero(~same)[0]
+    say("  rows %d, F rows %d, sets differ in %d rows" % (A.n, int((cf == 0).sum()), len(diff_rows)))
+    S = best[:, 0]
+    for i in diff_rows:
+        assert cf[i] == 0
+        mine = [c for c in Pc[i] if c >= 0]
+        m_g = len(mine)
+        assert m_g >= 1
+        pv, lv, rd = oracle.ls_fit_sets(A, x, w, np.array([list(Pc[i])]), [i], tg)
+        assert rd[0] == 0
+        rel = lv[0] / S[i] if S[i] > 0 else 0.0
+        # a (near-)best set of its size ...
+        assert rel <= best[i, m_g] * (1 + 1e-7) + 1e-13, (i, rel, best[i, m_g])
+        # ... and a size the penalty scan reaches within rounding
+        m_o, near = _scan_sizes(list(best[i]), gamma)
+        assert m_g == m_o or near, (i, m_g, m_o)
+    assert len(diff_rows) <= max(2, 0.002 * A.n)
+    ok = same & (cf == 0)
+    perr = np.abs(Pv - Rv)[ok] / np.maximum(1.0, np.abs(Rv[ok]))
+    assert np.all(perr <= 1e-6), perr.max()
+    lerr = np.abs(ls - Rl)[ok]
+    assert np.all(lerr <= 1e-6 * np.abs(Rl[ok]) + 1e-12 * S[ok]), lerr.max()
+    c = cf != 0
+    assert np.all(Pc[c, 0] == np.nonzero(c)[0]) and np.all(Pv[c, 0] == 1.0)
+
+
+@pytest.mark.parametrize("dt", [torch.float64, torch.float32])
+@pytest.mark.parametrize("target", ["plain", "residual"])
+@pytest.mark.parametrize("d, cal", [(1, 4), (2, 2), (2, 3), (2, 4), (3, 2)])
+def test_search_matches_the_oracle(dt, target, d, cal):
+    ad = lib()
+    N, K = 23, 16
+    A = W.rotated_anisotropic_9pt(N, 1e-3, math.pi / 6)
+    if dt == torch.float32:
+        A = W.CSR(A.n, A.row_ptr, A.col, A.val.astype(np.float32).astype(np.float64))
+    Ad = dev_csr(A, dt)
+    color = torch.as_tensor(W.red_black((N, N)), device="cuda")
+    X = ad.setup_testvectors(Ad, K, seed=4, relax="gs", sweeps=4, color=color, ncolors=2)
+    x = to_np(X).astype(np.float64)
+    cf = W.cf_red_is_coarse((N, N))
+    G = ad.power_graph(Ad, d)
+    say("search: %s %s d=%d caliber=%d" % (dt, target, d, cal))
+    got = ad.ls_interp_search(Ad, G, X, torch.as_tensor(cf, device="cuda"), cal, 1.5,
+                              target=target)
+    check_search(A, G, x, None, cf, cal, 1.5, target, got, dt)
+    assert ad.status(clear=True) == 0
+
+
+@pytest.mark.parametrize("gamma", [1.0, 1.5, 3.0])
+def test_search_weights_gamma_and_graph_rows(gamma):
+    """Weighted functional, other gammas, a random graph with a random C/F
+    split and rows of uneven candidate counts."""
+    ad = lib()
+    A = W.rgg_laplacian(900, 6.0, 21)
+    K = 8
+    Ad = dev_csr(A, torch.float64)
+    X = ad.setup_testvectors(Ad, K, seed=3, relax="jacobi", sweeps=3, omega=0.7)
+    x = to_np(X)
+    rng = np.random.default_rng(7)
+    cf = (rng.random(A.n) < 0.4).astype(np.uint8)
+    w = 0.5 + rng.random(K)
+    G = ad.power_graph(Ad, 2)
+    got = ad.ls_interp_search(Ad, G, X, torch.as_tensor(cf, device="cuda"), 3, gamma,
+                              w=torch.as_tensor(w, device="cuda"))
+    check_search(A, G, x, w, cf, 3, gamma, "plain", got, torch.float64)
+    assert ad.status(clear=True) == 0
+
+
+def test_search_follows_the_knight_move_anisotropy():
+    """tan(alpha) = 1/2 on a 64^2 grid, test vectors by 40 colour-phase GS
+    sweeps on the GPU, C = red, search depth 2: most interior F points pick
+    their two C-neighbours at +-(2, 1), and the rows match the oracle."""
+    ad = lib()
+    N, K = 64, 8
+    A = W.rotated_anisotropic_9pt(N, 1e-3, math.atan(0.5))
+    Ad = dev_csr(A, torch.float64)
+    color = torch.as_tensor(W.red_black((N, N)), device="cuda")
+    X = ad.setup_testvectors(Ad, K, seed=11, relax="gs", sweeps=40, color=color, ncolors=2)
+    cf = W.cf_red_is_coarse((N, N))
+    G = ad.power_graph(Ad, 2)
+    got = ad.ls_interp_search(Ad, G, X, torch.as_tensor(cf, device="cuda"), 2, 1.5)
+    check_search(A, G, to_np(X), None, cf, 2, 1.5, "plain", got, torch.float64)
+    Pc = to_np(got[0])
+    iy, ix = np.divmod(np.arange(A.n), N)
+    inner = (ix > 2) & (ix < N - 3) & (iy > 2) & (iy < N - 3) & (cf == 0)
+    rows = np.nonzero(inner)[0]
+    hit = sum(sorted(int(c) - int(i) for c in Pc[i] if c >= 0) == [-(N + 2), N + 2] for i in rows)
+    say("  knight-move sets: %d of %d interior F rows" % (hit, len(rows)))
+    assert hit >= 0.8 * len(rows)
+    assert ad.status(clear=True) == 0
+
+
+def test_search_candidate_cap_and_errors():
+    """An F row with more than 64 candidates gets status 4, an empty row and
+    the sticky bit; caliber 5 and caliber > K are refused."""
+    ad = lib()
+    N, K = 21, 8
+    A = W.rotated_anisotropic_9pt(N, 1e-3, 0.3)
+    Ad = dev_csr(A, torch.float64)
+    X = ad.setup_testvectors(Ad, K, seed=1, relax="jacobi", sweeps=1, omega=0.7)
+    cf = np.ones(A.n, dtype=np.uint8)
+    c = (N // 2) * N + N // 2
+    cf[c] = 0
+    G = ad.power_graph(Ad, 4)  # 81 entries, 80 of them C
+    Pc, Pv, ls, st = ad.ls_interp_search(Ad, G, X, torch.as_tensor(cf, device="cuda"), 2)
+    assert to_np(st)[c] == 4 and np.all(to_np(Pc)[c] == -1)
+    x = to_np(X)
+    assert to_np(ls)[c] == pytest.approx(float((x[c] * x[c]).sum()), rel=1e-12)
+    assert ad.status(clear=True) & ad.STAT_SEARCH_CAP
+    cft = torch.as_tensor(cf, device="cuda")
+    with pytest.raises(ad.AlgdistError, match="AD_ECALIBER"):
+        ad.ls_interp_search(Ad, G, X, cft, 5)
+    X2 = ad.setup_testvectors(Ad, 2, seed=1)
+    with pytest.raises(ad.AlgdistError, match="AD_ECALIBER"):
+        ad.ls_interp_search(Ad, G, X2, cft, 3)
+    assert ad.status(clear=True) == 0
