@@ -90,6 +90,10 @@ def parse(argv=None):
                     help="also time the LS-loss forward and adjoint (workload 5; the default "
                          "unless --size is given)")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint leg")
+    ap.add_argument("--longrange", action="store_true",
+                    help="time the long-range leg (pattern of A^2, distances on it, set search; "
+                         "the default unless --size is given)")
+    ap.add_argument("--no-longrange", action="store_true", help="skip the long-range leg")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one 1 GiB device-to-device copy (a kernel of known traffic "
                          "for scaling hardware byte counters)")
@@ -97,6 +101,7 @@ def parse(argv=None):
     # the batched and adjoint legs run by default on the full-size workloads
     a.batched = not a.no_batched and (a.batched or a.size is None)
     a.adjoint = not a.no_adjoint and (a.adjoint or a.size is None)
+    a.longrange = not a.no_longrange and (a.longrange or a.size is None)
     return a
 
 
@@ -614,6 +619,63 @@ def adjoint_leg(args, torch, ad, W):
     return out
 
 
+def longrange_leg(args, torch, ad, W, flush):
+    """Long-range distances and the interpolatory-set search on the full
+    anisotropic workload (FP32 panel from the step's relaxation): the
+    pattern of A^2, distances with the strength graph on it, and the search
+    over sets of its C-points (depth 2, caliber 4, gamma = 1.5); each call
+    timed as the median of its repetitions with the scratch write between
+    them."""
+    wl = W.workload(2, "f32", size=args.size)
+    A = ad.Csr.from_host(wl.A, dtype=torch.float32)
+    color = torch.as_tensor(wl.color, device="cuda")
+    cf = torch.as_tensor(wl.cf, device="cuda")
+    X = ad.setup_testvectors(A, wl.K, seed=wl.tv_seed, relax="gs", sweeps=wl.sweeps, color=color,
+                             ncolors=wl.ncolors)
+    n = wl.A.n
+    G = ad.power_graph(A, 2)
+    mu = torch.empty(G.nnz, dtype=torch.float32, device="cuda")
+    st = torch.empty(G.nnz, dtype=torch.uint8, device="cuda")
+    ns = torch.empty(n, dtype=torch.int32, device="cuda")
+    out = [torch.empty((n, 4), dtype=torch.int32, device="cuda"),
+           torch.empty((n, 4), dtype=torch.float64, device="cuda"),
+           torch.empty(n, dtype=torch.float64, device="cuda"),
+           torch.empty(n, dtype=torch.int32, device="cuda")]
+    calls = {
+        "power_graph": lambda: ad.power_graph(A, 2),
+        "algdist_graph": lambda: ad.algebraic_distance_graph(A, G, X, mu=mu, fuse=True,
+                                                            theta=wl.theta, strong=st, nstrong=ns),
+        "ls_search": lambda: ad.ls_interp_search(A, G, X, cf, 4, 1.5, P_col=out[0],
+                                                 P_val=out[1], ls_val=out[2], row_status=out[3]),
+    }
+    res = {"workload": wl.name + ", pattern of A^2, search depth 2, caliber 4, gamma 1.5",
+           "rows": n, "pattern_entries": G.nnz,
+           "pattern_edges": G.nnz - n}
+    reps = max(3, args.steps // 4)
+    for name, fn in calls.items():
+        fn()
+        torch.cuda.synchronize()
+        log("long-range leg: %s, %d repetitions" % (name, reps))
+        res[name + "_ms"] = round(float(np.median(rep_times(fn, reps, flush, torch))), 4)
+    s = 4
+    dist_bytes = (n + 1) * 4 + G.nnz * 4 + n * wl.K * s + G.nnz * s + G.nnz
+    ms = res["algdist_graph_ms"]
+    res["algdist_graph_edges_per_s"] = round((G.nnz - n) / (ms * 1e-3), 1)
+    res["algdist_graph_roofline"] = {
+        "bound": "hbm", "achieved": round(dist_bytes / (ms * 1e-3) / 1e9, 1), "peak": HBM_PEAK_GBS,
+        "unit": "GB/s", "frac": round(dist_bytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+        "algorithmic_bytes_per_launch": int(dist_bytes)}
+    Fr = int((wl.cf == 0).sum())
+    rs = out[3].cpu().numpy()
+    res["ls_search_F_rows_per_s"] = round(Fr / (res["ls_search_ms"] * 1e-3), 1)
+    res["ls_search_sets_per_F_row"] = 12 + 66 + 220 + 495  # C(12, 1..4): 12 candidates per row
+    res["ls_search_status_counts"] = {str(k): int((rs == k).sum()) for k in np.unique(rs)}
+    res["device_status_bits"] = ad.status(clear=True)
+    del A, X, G, mu, st, ns, out
+    torch.cuda.empty_cache()
+    return res
+
+
 # ------------------------------------------------------------------ CPU baseline
 def cpu_model():
     try:
@@ -831,6 +893,9 @@ def main():
     if args.adjoint:
         log("adjoint leg (workload 5)")
         out["adjoint"] = adjoint_leg(args, torch, ad, W)
+    if args.longrange:
+        log("long-range leg")
+        out["longrange"] = longrange_leg(args, torch, ad, W, flush)
     if not args.no_cpu_baseline:
         idx = WORKLOAD_INDEX[args.workload]
         side = args.cpu_sample or args.size or {1: 32, 2: 2048, 3: 160}[idx]

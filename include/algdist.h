@@ -145,6 +145,7 @@ const char *algdist_timing_report(ad_handle h);
 int algdist_set_launch(ad_handle h, const char *kernel, int32_t dtype, int32_t K, int32_t bucket,
                        int32_t lanes_per_row, int32_t rows_per_lane, int32_t xcd_map);
 
+
 /* Autotune the launch shapes of this matrix's key (dtype, K, entries-per-row
  * bucket): the relaxation family named by `relax` (color/ncolors as for
  * setup_testvectors), algebraic_distance, and ls_interp (only if cf != NULL

@@ -107,7 +107,8 @@ __device__ __forceinline__ double ls_row(int i, int l, const int* __restrict__ r
             for (int q = 0; q < V; ++q) t[q] = carried<T>(t[q] - y[q] / d);
         }
     }
-    return ls_solve<T, K, LPR, CALT>(i, l, t, wd, X, scol, nsel, st, cal, Pcol, Pval, lsv, rstat);
+    return ls_solve<T, K, LPR, CALT>(i, l, t, wd, GlobalRows<T, K>{X}, scol, nsel, st, cal, Pcol,
+                                     Pval, lsv, rstat);
 }
 
 template <typename T, int K, int LPR, int CALT>
@@ -275,13 +276,16 @@ __global__ __launch_bounds__(kBlock) void dist_ls_kernel(
     }
     const bool plain = target == AD_TARGET_PLAIN;
     double fsum = 0.0;
-    if (tile >= 0 && tile < ntiles) {
+    // the tile's rows, reading panel rows from `src`
+    auto rows = [&](const auto& src) {
+        using Src = typename std::decay<decltype(src)>::type;
+        constexpr int G = Src::kCoop ? CoopGather<T, V, LPR>::G : 1;
         for (int it = 0; it < iter; ++it) {
             const int64_t iw = tile * rows_per_tile + (int64_t)it * S::RPB + wv * S::RPW;
             if (iw >= n) break;  // whole wavefront
             const int64_t i64 = iw + g;
             const bool ghost = i64 >= n;
-            if (ghost && CoopGather<T, V, LPR>::G == 1) break;  // ghosts only serve group loads
+            if (ghost && G == 1) break;  // ghosts only serve group loads
             const int i = ghost ? n - 1 : (int)i64;
             const bool isF = !ghost && cf[i] == 0;
             T smu[CALT];
@@ -294,22 +298,23 @@ __global__ __launch_bounds__(kBlock) void dist_ls_kernel(
             }
             double t64[V], d;
             algdist_row_sel<S, T, K, WEIGHTED, UN>(
-                i, ghost, l, rp, ci, rp, ci, av, X, wd, wt, plain, mu, nullptr, theta, fmask, strong,
-                nstrong, status,
+                i, ghost, l, rp, ci, rp, ci, av, src, wd, wt, plain, mu, nullptr, theta, fmask,
+                strong, nstrong, status,
                 [&](int j, T m) {
                     if (isF && cf[j] != 0) ls_insert<T, CALT>(smu, scol, nsel, cal, m, j);
                 },
                 t64, d);
             if (isF) {
                 const int st = (!plain && d == 0.0) ? 3 : 0;
-                const double v = ls_solve<T, K, LPR, CALT>(i, l, t64, wd, X, scol, nsel, st, cal,
+                const double v = ls_solve<T, K, LPR, CALT>(i, l, t64, wd, src, scol, nsel, st, cal,
                                                            Pcol, Pval, lsv, rstat);
                 if (l == 0) fsum += v;
             } else if (l == 0 && !ghost) {
                 ls_c_row(i, cal, Pcol, Pval, lsv, rstat);
             }
         }
-    }
+    };
+    if (tile >= 0 && tile < ntiles) rows(GlobalRows<T, K>{X});
     if (block_sums) {
         // fixed-order reduction: xor butterfly in the wave, then waves in order
 #pragma unroll

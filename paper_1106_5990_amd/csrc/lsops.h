@@ -64,9 +64,9 @@ __device__ __forceinline__ void ls_c_row(int64_t i, int cal, int* __restrict__ P
 // evaluates the functional at the minimiser from its definition, and writes
 // the row (lane 0).  st: status so far (3 = zero diagonal on the residual
 // target); returns the functional value.
-template <typename T, int K, int LPR, int CALT>
+template <typename T, int K, int LPR, int CALT, typename Src>
 __device__ __forceinline__ double ls_solve(int i, int l, const double (&t)[K / LPR],
-                                           const double (&wd)[K / LPR], const T* __restrict__ X,
+                                           const double (&wd)[K / LPR], const Src& src,
                                            const int (&scol)[CALT], int nsel, int st, int cal,
                                            int* __restrict__ Pcol, double* __restrict__ Pval,
                                            double* __restrict__ lsv, int* __restrict__ rstat) {
@@ -77,7 +77,7 @@ __device__ __forceinline__ double ls_solve(int i, int l, const double (&t)[K / L
 #pragma unroll
     for (int a = 0; a < CALT; ++a) {
         if (a < nsel) {
-            xs[a] = load_lane<T, V, C>(X + (size_t)scol[a] * K + l * V);
+            xs[a] = load_lane<T, V, C>(src.row(scol[a]) + l * V);
         } else {
 #pragma unroll
             for (int q = 0; q < V; ++q) xs[a].v[q] = T(0);

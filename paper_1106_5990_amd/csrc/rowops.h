@@ -279,6 +279,16 @@ void dist_unroll(bool long_rows, F&& f) {
     }
 }
 
+// ---------------------------------------------------------------- panel row source
+// Where the distance and LS row bodies read panel rows from: the panel in
+// global memory (gathers through the caches).
+template <typename T, int K>
+struct GlobalRows {
+    const T* __restrict__ X;
+    static constexpr bool kCoop = true;  // the cooperative gather may be used
+    __device__ __forceinline__ const T* row(int j) const { return X + (size_t)j * K; }
+};
+
 template <typename T> struct Guard { static constexpr bool on = false; };
 template <> struct Guard<float> { static constexpr bool on = true; };
 
@@ -302,13 +312,13 @@ __device__ __forceinline__ T ratio(T a, T b) {
 // The distances run over the entries of (rp, ci); the residual target is
 // formed from the rows of (rpt, cit, av) -- the matrix itself, also when
 // (rp, ci) is another pattern such as that of A^d.
-template <typename S, typename T, int K, bool WEIGHTED, int UN, typename Sel>
+template <typename S, typename T, int K, bool WEIGHTED, int UN, typename Src, typename Sel>
 __device__ __forceinline__ void algdist_row_sel(int i, bool ghost, int l,
                                                 const int* __restrict__ rp,
                                                 const int* __restrict__ ci,
                                                 const int* __restrict__ rpt,
                                                 const int* __restrict__ cit,
-                                                const T* __restrict__ av, const T* __restrict__ X,
+                                                const T* __restrict__ av, const Src& src,
                                                 const double (&wd)[S::V], const T (&wt)[S::V],
                                                 bool plain, T* __restrict__ mu,
                                                 double* __restrict__ pout, double theta,
@@ -328,7 +338,7 @@ __device__ __forceinline__ void algdist_row_sel(int i, bool ghost, int l,
     // exact where tlo is zero, within 2^-48 relative otherwise.  It is
     // re-formed at each use so that no FP64 copy stays live through the
     // entry loop.
-    Frag<T, V> t = load_lane<T, V, C>(X + (size_t)i * K + l * V);
+    Frag<T, V> t = load_lane<T, V, C>(src.row(i) + l * V);
     T tlo[V];
 #pragma unroll
     for (int q = 0; q < V; ++q) tlo[q] = T(0);
@@ -341,7 +351,7 @@ __device__ __forceinline__ void algdist_row_sel(int i, bool ghost, int l,
         for (int e = f0; e < f1; ++e) {
             const int j = cit[e];
             const double a = (double)av[e];
-            Frag<T, V> xj = load_lane<T, V, C>(X + (size_t)j * K + l * V);
+            Frag<T, V> xj = load_lane<T, V, C>(src.row(j) + l * V);
 #pragma unroll
             for (int q = 0; q < V; ++q) y[q] = fma(a, (double)xj.v[q], y[q]);
             if (j == i) d = a;
@@ -375,7 +385,7 @@ __device__ __forceinline__ void algdist_row_sel(int i, bool ghost, int l,
     bool bad = false;
     // U edges per step: their column and panel loads are issued together
     // (UN, see dist_unroll, for lanes holding under 64 bytes of a row)
-    constexpr int G = CoopGather<T, V, LPR>::G;
+    constexpr int G = Src::kCoop ? CoopGather<T, V, LPR>::G : 1;
     constexpr int U = (G > 1) ? 8 / G : (V >= 16) ? 2 : UN;
     // the next step's column indices are loaded while this step's panel
     // rows are in flight
@@ -391,10 +401,10 @@ __device__ __forceinline__ void algdist_row_sel(int i, bool ghost, int l,
 #pragma unroll
         for (int u = 0; u < U; ++u) jj[u] = jn[u];
         if constexpr (G > 1) {
-            coop_gather<T, K, V, U, G>(X, jj, xs);
+            coop_gather<T, K, V, U, G>(src.X, jj, xs);
         } else {
 #pragma unroll
-            for (int u = 0; u < U; ++u) xs[u] = load_lane<T, V, C>(X + (size_t)jj[u] * K + l * V);
+            for (int u = 0; u < U; ++u) xs[u] = load_lane<T, V, C>(src.row(jj[u]) + l * V);
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) jn[u] = (eb + U + u < e1) ? ci[eb + U + u] : i;
@@ -510,7 +520,7 @@ __device__ __forceinline__ void algdist_row(int i, bool ghost, int l, const int*
                                             uint8_t* __restrict__ strong, int* __restrict__ nstrong,
                                             unsigned* status) {
     double t64[S::V], d;
-    algdist_row_sel<S, T, K, WEIGHTED, UN>(i, ghost, l, rp, ci, rpt, cit, av, X, wd, wt, plain, mu, pout,
+    algdist_row_sel<S, T, K, WEIGHTED, UN>(i, ghost, l, rp, ci, rpt, cit, av, GlobalRows<T, K>{X}, wd, wt, plain, mu, pout,
                                            theta, fmask, strong, nstrong, status, [](int, T) {},
                                            t64, d);
 }
