@@ -296,3 +296,69 @@ def ls_search(A, G, X, w, cf, caliber: int, gamma: float = 1.5, target: int = TA
                        0 if r is None else len(r), _p(r), _p(Pc), _p(Pv), _p(ls), _p(st),
                        _p(best), _p(nc))
     return Pc, Pv, ls, st, best, nc
+
+
+def _sig_cr(L):
+    P = C.c_void_p
+    i32, u64, f64 = C.c_int, C.c_uint64, C.c_double
+    for name, res, args in (
+            ("oracle_cr_rate", f64, [i32, P, P, P, P, i32, P, i32, P]),
+            ("oracle_cr_candidates", None, [i32, P, P, f64, P]),
+            ("oracle_independent_set", i32, [i32, P, P, P, P, u64, P]),
+            ("oracle_cr_coarsen", i32, [i32, P, P, P, P, i32, P, f64, i32, f64, i32, u64, P, P,
+                                        P])):
+        fn = getattr(L, name)
+        fn.restype = res
+        fn.argtypes = args
+    return L
+
+
+def cr_rate(A, color, ncolors: int, cf, nu: int):
+    """nu F-relaxation sweeps (eq:frelax) from the constant start, C held at
+    zero: (rho_f of eq:meas1, u^nu)."""
+    L = _sig_cr(lib())
+    n, rp, ci, va = _csr(A)
+    col = np.ascontiguousarray(color, dtype=np.int32)
+    cf = np.ascontiguousarray(cf, dtype=np.uint8)
+    u = np.empty(n)
+    r = L.oracle_cr_rate(n, _p(rp), _p(ci), _p(va), _p(col), int(ncolors), _p(cf), int(nu), _p(u))
+    return float(r), u
+
+
+def cr_candidates(cf, u, tol: float):
+    """F points with |u_i| / max_F |u| > tol."""
+    L = _sig_cr(lib())
+    cf = np.ascontiguousarray(cf, dtype=np.uint8)
+    u = _f64(u)
+    z = np.empty(len(cf), dtype=np.uint8)
+    L.oracle_cr_candidates(len(cf), _p(cf), _p(u), float(tol), _p(z))
+    return z
+
+
+def independent_set(A, strong, z, seed: int):
+    """Greedy maximal independent set of the candidates z on the symmetric
+    closure of the strong graph, in decreasing (|S_i^T|, hash, index)."""
+    L = _sig_cr(lib())
+    n, rp, ci, _ = _csr(A)
+    strong = np.ascontiguousarray(strong, dtype=np.uint8)
+    z = np.ascontiguousarray(z, dtype=np.uint8)
+    sel = np.empty(n, dtype=np.uint8)
+    L.oracle_independent_set(n, _p(rp), _p(ci), _p(strong), _p(z), seed & (2**64 - 1), _p(sel))
+    return sel
+
+
+def cr_coarsen(A, color, ncolors: int, mu, theta: float, nu: int = 5, delta: float = 0.7,
+               max_stages: int = 20, seed: int = 0, cf0=None):
+    """Algorithm 1 of Sec. 4.2: (cf, rho per stage, |C| per stage)."""
+    L = _sig_cr(lib())
+    n, rp, ci, va = _csr(A)
+    col = np.ascontiguousarray(color, dtype=np.int32)
+    mu = _f64(mu)
+    cf = (np.zeros(n, dtype=np.uint8) if cf0 is None
+          else np.ascontiguousarray(cf0, dtype=np.uint8).copy())
+    rho = np.zeros(max_stages + 1)
+    nc = np.zeros(max_stages + 1, dtype=np.int64)
+    s = L.oracle_cr_coarsen(n, _p(rp), _p(ci), _p(va), _p(col), int(ncolors), _p(mu),
+                            float(theta), int(nu), float(delta), int(max_stages),
+                            seed & (2**64 - 1), _p(cf), _p(rho), _p(nc))
+    return cf, rho[:s + 1], nc[:s + 1]

@@ -936,3 +936,168 @@ void oracle_ls_search(int n, const int *rp, const int *ci, const double *a, cons
     }
     free(t); free(sc); free(M); free(b); free(v); free(cand);
 }
+
+/* ---------------------------------------------------------------------- */
+/* Compatible relaxation (Sec. 3.2) and the coarsening loop of Sec. 4.2    */
+/* (Algorithm 1).                                                          */
+/*                                                                         */
+/* F-relaxation (eq:frelax): relaxation applied to the F variables of the  */
+/* homogeneous system, the C variables held at zero, so that each sweep is */
+/* u_f <- (I - M_ff^{-1} A_ff) u_f.  M is the colour-phase Gauss-Seidel    */
+/* splitting of oracle_color_gs (C rows take no colour and stay fixed).    */
+/* The start is the constant 1 on F (Algorithm 1 starts every CR run from  */
+/* a constant vector), 0 on C.                                             */
+/*                                                                         */
+/* Rate estimate (eq:meas1): rho_f = (||u_f^nu||_2 / ||u_f^0||_2)^(1/nu).  */
+/* Candidate measure (remark after Algorithm 1): sigma_i = |u_i^nu| /      */
+/* ||u^nu||_inf, and the candidates are the F points with sigma_i > tol,   */
+/* tol = 1 - rho_f (Sec. 5.2).                                             */
+/* ---------------------------------------------------------------------- */
+
+/* nu F-relaxation sweeps from the constant start; u (n) receives u^nu.
+ * Returns rho_f (0 when F is empty). */
+double oracle_cr_rate(int n, const int *rp, const int *ci, const double *a, const int *color,
+                      int ncolors, const unsigned char *cf, int nu, double *u)
+{
+    int *fcol = (int *)malloc(sizeof(int) * (size_t)(n ? n : 1));
+    double n0 = 0.0, n1 = 0.0;
+    int i;
+    for (i = 0; i < n; ++i) {
+        fcol[i] = cf[i] ? -1 : color[i];
+        u[i] = cf[i] ? 0.0 : 1.0;
+        n0 += u[i] * u[i];
+    }
+    oracle_color_gs(n, rp, ci, a, 1, fcol, ncolors, nu, u);
+    for (i = 0; i < n; ++i)
+        if (!cf[i]) n1 += u[i] * u[i];
+    free(fcol);
+    if (n0 == 0.0 || nu <= 0) return 0.0;
+    return pow(sqrt(n1) / sqrt(n0), 1.0 / (double)nu);
+}
+
+/* z[i] = 1 for the F points with sigma_i = |u_i| / max_F |u| > tol. */
+void oracle_cr_candidates(int n, const unsigned char *cf, const double *u, double tol,
+                          unsigned char *z)
+{
+    double m = 0.0;
+    int i;
+    for (i = 0; i < n; ++i)
+        if (!cf[i] && fabs(u[i]) > m) m = fabs(u[i]);
+    for (i = 0; i < n; ++i)
+        z[i] = (unsigned char)(!cf[i] && m > 0.0 && fabs(u[i]) / m > tol);
+}
+
+/* ---------------------------------------------------------------------- */
+/* Independent set of the candidates on the strength graph (Algorithm 1,   */
+/* "independent set of Z based on M^d").  Two candidates are neighbours    */
+/* when either is strongly connected to the other (strong[e] for entry e   */
+/* = (i, j) of the pattern).  Following the weighting of the classical     */
+/* colouring (Sec. 2), a point's weight is the number of points strongly   */
+/* depending on it, lambda_i = |S_i^T|; the set is the greedy maximal one  */
+/* taken in decreasing (lambda_i, h_i, i), h_i the (i+1)-th output of      */
+/* splitmix64 seeded with `seed`.  sel[i] = 1 for the chosen points.       */
+/* ---------------------------------------------------------------------- */
+static const int *g_lam;
+static const uint64_t *g_h;
+
+static int cmp_priority_desc(const void *pa, const void *pb)
+{
+    int a = *(const int *)pa, b = *(const int *)pb;
+    if (g_lam[a] != g_lam[b]) return g_lam[a] > g_lam[b] ? -1 : 1;
+    if (g_h[a] != g_h[b]) return g_h[a] > g_h[b] ? -1 : 1;
+    return a > b ? -1 : (a < b ? 1 : 0);
+}
+
+int oracle_independent_set(int n, const int *rp, const int *ci, const unsigned char *strong,
+                           const unsigned char *z, uint64_t seed, unsigned char *sel)
+{
+    int *lam = (int *)calloc((size_t)(n ? n : 1), sizeof(int));
+    uint64_t *h = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)(n ? n : 1));
+    int *order = (int *)malloc(sizeof(int) * (size_t)(n ? n : 1));
+    /* transpose of the strong graph: tp[j] .. tp[j+1] lists the rows i with
+     * a strong entry (i, j) */
+    int *tp = (int *)calloc((size_t)n + 1, sizeof(int));
+    int *trow, *fill;
+    uint64_t st = seed;
+    int i, e, m = 0, count = 0;
+    for (i = 0; i < n; ++i) h[i] = splitmix64_next(&st);
+    for (i = 0; i < n; ++i)
+        for (e = rp[i]; e < rp[i + 1]; ++e)
+            if (strong[e]) {
+                ++lam[ci[e]];
+                ++tp[ci[e] + 1];
+            }
+    for (i = 0; i < n; ++i) tp[i + 1] += tp[i];
+    trow = (int *)malloc(sizeof(int) * (size_t)(tp[n] ? tp[n] : 1));
+    fill = (int *)calloc((size_t)(n ? n : 1), sizeof(int));
+    for (i = 0; i < n; ++i)
+        for (e = rp[i]; e < rp[i + 1]; ++e)
+            if (strong[e]) trow[tp[ci[e]] + fill[ci[e]]++] = i;
+    for (i = 0; i < n; ++i) {
+        sel[i] = 0;
+        if (z[i]) order[m++] = i;
+    }
+    g_lam = lam;
+    g_h = h;
+    qsort(order, (size_t)m, sizeof(int), cmp_priority_desc);
+    for (i = 0; i < m; ++i) {
+        int v = order[i], blocked = 0, q;
+        for (e = rp[v]; e < rp[v + 1] && !blocked; ++e)
+            if (strong[e] && ci[e] != v && sel[ci[e]]) blocked = 1;
+        for (q = tp[v]; q < tp[v + 1] && !blocked; ++q)
+            if (trow[q] != v && sel[trow[q]]) blocked = 1;
+        if (!blocked) {
+            sel[v] = 1;
+            ++count;
+        }
+    }
+    free(lam); free(h); free(order); free(tp); free(trow); free(fill);
+    return count;
+}
+
+/* Algorithm 1 (Sec. 4.2): start from C_0 (cf[i] = 1 marks C), run nu CR
+ * sweeps, and while rho_f > delta: candidates Z (sigma_i > 1 - rho_f), the
+ * strength graph restricted to F (oracle_strength with the F mask, on the
+ * distances mu of the pattern), C grown by the independent set of Z, and
+ * CR again.  Stops also when Z is empty or after max_stages growth steps.
+ * rho[s] and ncoarse[s] record rho_f and |C| after s growth steps
+ * (arrays of max_stages + 1).  Returns the number of growth steps. */
+int oracle_cr_coarsen(int n, const int *rp, const int *ci, const double *a, const int *color,
+                      int ncolors, const double *mu, double theta, int nu, double delta,
+                      int max_stages, uint64_t seed, unsigned char *cf, double *rho,
+                      int64_t *ncoarse)
+{
+    double *u = (double *)malloc(sizeof(double) * (size_t)(n ? n : 1));
+    unsigned char *z = (unsigned char *)malloc((size_t)(n ? n : 1));
+    unsigned char *fm = (unsigned char *)malloc((size_t)(n ? n : 1));
+    unsigned char *sel = (unsigned char *)malloc((size_t)(n ? n : 1));
+    int64_t nnz = n ? rp[n] : 0;
+    unsigned char *strong = (unsigned char *)malloc((size_t)(nnz ? nnz : 1));
+    int stage = 0, i;
+    int64_t nc = 0;
+    double r;
+    for (i = 0; i < n; ++i) nc += cf[i] != 0;
+    r = oracle_cr_rate(n, rp, ci, a, color, ncolors, cf, nu, u);
+    rho[0] = r;
+    ncoarse[0] = nc;
+    while (r > delta && stage < max_stages) {
+        int any = 0;
+        oracle_cr_candidates(n, cf, u, 1.0 - r, z);
+        for (i = 0; i < n; ++i) any |= z[i];
+        if (!any) break;
+        for (i = 0; i < n; ++i) fm[i] = (unsigned char)!cf[i];
+        oracle_strength(n, rp, ci, mu, theta, fm, strong, NULL);
+        oracle_independent_set(n, rp, ci, strong, z, seed + (uint64_t)stage, sel);
+        for (i = 0; i < n; ++i)
+            if (sel[i]) {
+                cf[i] = 1;
+                ++nc;
+            }
+        ++stage;
+        r = oracle_cr_rate(n, rp, ci, a, color, ncolors, cf, nu, u);
+        rho[stage] = r;
+        ncoarse[stage] = nc;
+    }
+    free(u); free(z); free(fm); free(sel); free(strong);
+    return stage;
+}
