@@ -94,6 +94,10 @@ def parse(argv=None):
                     help="time the long-range leg (pattern of A^2, distances on it, set search; "
                          "the default unless --size is given)")
     ap.add_argument("--no-longrange", action="store_true", help="skip the long-range leg")
+    ap.add_argument("--cr", action="store_true",
+                    help="time the compatible-relaxation coarsening leg (the default unless "
+                         "--size is given)")
+    ap.add_argument("--no-cr", action="store_true", help="skip the coarsening leg")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one 1 GiB device-to-device copy (a kernel of known traffic "
                          "for scaling hardware byte counters)")
@@ -102,6 +106,7 @@ def parse(argv=None):
     a.batched = not a.no_batched and (a.batched or a.size is None)
     a.adjoint = not a.no_adjoint and (a.adjoint or a.size is None)
     a.longrange = not a.no_longrange and (a.longrange or a.size is None)
+    a.cr = not a.no_cr and (a.cr or a.size is None)
     return a
 
 
@@ -676,6 +681,56 @@ def longrange_leg(args, torch, ad, W, flush):
     return res
 
 
+def cr_leg(args, torch, ad, W, flush):
+    """Compatible-relaxation coarsening (Algorithm 1: nu = 5, delta = 0.7,
+    theta = 0.25) on the full anisotropic workload, FP32 operator, distances
+    from the step's test vectors; each call is synchronous and timed on the
+    host clock around it (median of its repetitions, the scratch write
+    between them); the per-label times come from one eager run with the
+    library's HIP events."""
+    wl = W.workload(2, "f32", size=args.size)
+    A = ad.Csr.from_host(wl.A, dtype=torch.float32)
+    color = torch.as_tensor(wl.color, device="cuda")
+    X = ad.setup_testvectors(A, wl.K, seed=wl.tv_seed, relax="gs", sweeps=wl.sweeps, color=color,
+                             ncolors=wl.ncolors)
+    mu = ad.algebraic_distance(A, X)
+    n = wl.A.n
+    cf = torch.zeros(n, dtype=torch.uint8, device="cuda")
+
+    def call():
+        cf.zero_()
+        return ad.cr_coarsening(A, color, wl.ncolors, mu, wl.theta, nu=5, delta=0.7, max_stages=20,
+                                seed=1, cf=cf)
+
+    _, rho, nc = call()
+    torch.cuda.synchronize()
+    reps = max(3, args.steps // 4)
+    log("coarsening leg: %d repetitions" % reps)
+    times = []
+    for _ in range(reps):
+        flush()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        call()
+        torch.cuda.synchronize()
+        times.append((time.perf_counter() - t0) * 1e3)
+    ad.timing(True)
+    call()
+    rep = ad.timing_report()
+    ad.timing(False)
+    res = {"workload": wl.name + ", CR coarsening from C_0 = empty (nu 5, delta 0.7, theta 0.25)",
+           "rows": n, "ms": round(float(np.median(times)), 3),
+           "ms_min_max": [round(min(times), 3), round(max(times), 3)],
+           "stages": len(rho) - 1, "rho_f": [round(r, 5) for r in rho],
+           "coarse_points": [int(c) for c in nc],
+           "coarse_fraction": round(nc[-1] / n, 4),
+           "kernels_ms": {k: [v[0], round(v[1], 4)] for k, v in rep.items()},
+           "device_status_bits": ad.status(clear=True)}
+    del A, X, mu, cf
+    torch.cuda.empty_cache()
+    return res
+
+
 # ------------------------------------------------------------------ CPU baseline
 def cpu_model():
     try:
@@ -896,6 +951,9 @@ def main():
     if args.longrange:
         log("long-range leg")
         out["longrange"] = longrange_leg(args, torch, ad, W, flush)
+    if args.cr:
+        log("coarsening leg")
+        out["cr_coarsening"] = cr_leg(args, torch, ad, W, flush)
     if not args.no_cpu_baseline:
         idx = WORKLOAD_INDEX[args.workload]
         side = args.cpu_sample or args.size or {1: 32, 2: 2048, 3: 160}[idx]

@@ -451,6 +451,59 @@ int ls_interp_loss_backward(ad_handle h, const ad_csr *A, int32_t K, const void 
                             int32_t caliber, const void *X_final, const double *dL,
                             double *grad_val, double *grad_omega, void *stream);
 
+/* ------------------------------------------------------------------ */
+/* Compatible-relaxation coarsening (Sec. 3.2; Sec. 4.2, Algorithm 1).  */
+/* These calls are synchronous (the host decides between stages and     */
+/* rounds), allocate their own device buffers, and must not be made     */
+/* while `stream` is capturing.                                         */
+/* ------------------------------------------------------------------ */
+
+/* One CR run (eq:frelax, eq:meas1): nu >= 1 sweeps of F-relaxation of the
+ * homogeneous system from the constant start (1 on F, 0 on C; cf[i] != 0
+ * marks C), the relaxation being the colour-phase Gauss-Seidel of
+ * setup_testvectors restricted to F (C rows take no colour and stay at 0).
+ * color/ncolors as for setup_testvectors (rows with an invalid colour are
+ * held as well).
+ * Outputs: u (device, n values of A's dtype, may be NULL) = u^nu; *rho (host)
+ * = (||u_f^nu||_2 / ||u_f^0||_2)^(1/nu), 0 when F is empty; norms (host, 3
+ * doubles, may be NULL) = |F|, sum over F of (u_i^nu)^2, max over F of
+ * |u_i^nu|, all accumulated in FP64. */
+int cr_rate(ad_handle h, const ad_csr *A, const int32_t *color, int32_t ncolors,
+            const uint8_t *cf, int32_t nu, void *u, double *rho, double *norms, void *stream);
+
+/* Candidate set of Algorithm 1 with the measure of the remark after it:
+ * z[i] = 1 (device, n bytes) for the F points (cf[i] == 0) with
+ * |u_i| / max over F of |u| > tol, compared in FP64; u (device, n values of
+ * type dtype). */
+int cr_candidates(ad_handle h, int32_t n, int32_t dtype, const uint8_t *cf, const void *u,
+                  double tol, uint8_t *z, void *stream);
+
+/* Independent set of the candidates z (device, n bytes) on the strength
+ * graph (Algorithm 1): strong (device, nnz bytes) marks entry (i, j) of A's
+ * pattern; candidates i and j are neighbours when strong(i, j) or
+ * strong(j, i).  The set is the greedy maximal one in decreasing
+ * (lambda_i, h_i, i), lambda_i = |S_i^T| (strong entries in column i, the
+ * weight of the classical colouring of Sec. 2), h_i the (i+1)-th output of
+ * splitmix64 seeded with `seed`; it is found by parallel rounds of local
+ * maxima, which give exactly that set.  sel (device, n bytes) receives 0/1;
+ * *count (host, may be NULL) its size.  Only A's pattern is used. */
+int independent_set(ad_handle h, const ad_csr *A, const uint8_t *strong, const uint8_t *z,
+                    uint64_t seed, uint8_t *sel, int64_t *count, void *stream);
+
+/* Algorithm 1: from C_0 (cf, device n bytes, in/out; cf[i] != 0 marks C),
+ * run cr_rate; while rho_f > delta: candidates with tol = 1 - rho_f, the
+ * strength graph (strength_graph on mu with the F mask, i.e. restricted to
+ * F), C grown by the independent set of the candidates with seed
+ * seed + stage, and cr_rate again.  Stops also when a stage adds nothing or
+ * after max_stages stages.  Outputs (host): rho[s], ncoarse[s] = rho_f and
+ * |C| after s stages (arrays of max_stages + 1), *nstages = stages run.
+ * mu: nnz distances of A's dtype (algebraic_distance on the test vectors).
+ * The paper's parameters are nu = 5, delta = 0.7 (Sec. 5.2). */
+int cr_coarsening(ad_handle h, const ad_csr *A, const int32_t *color, int32_t ncolors,
+                  const void *mu, double theta, int32_t nu, double delta, int32_t max_stages,
+                  uint64_t seed, uint8_t *cf, double *rho, int64_t *ncoarse, int32_t *nstages,
+                  void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -84,6 +84,11 @@ _SIGS = {
                                      _f64, _P, _P, _P]),
     "ls_interp_loss_backward": (_i32, [_P, _CSRP, _i32, _P, _i32, _i32, _f64, _P, _P, _P, _P, _i32,
                                        _P, _P, _P, _P, _P]),
+    "cr_rate": (_i32, [_P, _CSRP, _P, _i32, _P, _i32, _P, C.POINTER(C.c_double), _P, _P]),
+    "cr_candidates": (_i32, [_P, _i32, _i32, _P, _P, _f64, _P, _P]),
+    "independent_set": (_i32, [_P, _CSRP, _P, _P, _u64, _P, C.POINTER(C.c_int64), _P]),
+    "cr_coarsening": (_i32, [_P, _CSRP, _P, _i32, _P, _f64, _i32, _f64, _i32, _u64, _P, _P, _P,
+                             C.POINTER(C.c_int32), _P]),
 }
 for _name, (_res, _args) in _SIGS.items():
     _fn = getattr(_lib, _name)
@@ -519,3 +524,54 @@ class LSInterpLoss(torch.autograd.Function):
         dL = gL.detach().reshape(1).to(torch.float64).contiguous()
         gv, go = ls_interp_loss_backward(A, K, ck, ce, sweeps, om, cf, Pc, Pv, X, dL, w=w)
         return gv, go.reshape(oshape), None, None, None, None, None, None, None, None, None, None
+
+
+# ------------------------------------------------------------------ compatible relaxation
+def cr_rate(A: Csr, color: torch.Tensor, ncolors: int, cf: torch.Tensor, nu: int = 5,
+            u: Optional[torch.Tensor] = None, stream=None):
+    """One CR run (cr_rate): (rho_f, u^nu, (|F|, sum u^2, max |u|))."""
+    h = handle(A.device.index)
+    u = u if u is not None else torch.empty(A.n, dtype=A.dtype, device=A.device)
+    rho = C.c_double(0.0)
+    norms = (C.c_double * 3)()
+    _check(_lib.cr_rate(h, A.ref(), _ptr(color), int(ncolors), _ptr(cf), int(nu), _ptr(u),
+                        C.byref(rho), norms, _stream(stream)), h, "cr_rate")
+    return rho.value, u, tuple(norms)
+
+
+def cr_candidates(cf: torch.Tensor, u: torch.Tensor, tol: float,
+                  z: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+    """F points with |u_i| / max_F |u| > tol (cr_candidates)."""
+    h = handle(u.device.index)
+    z = z if z is not None else torch.empty(u.numel(), dtype=torch.uint8, device=u.device)
+    _check(_lib.cr_candidates(h, u.numel(), _dtype_code(u.dtype), _ptr(cf), _ptr(u), float(tol),
+                              _ptr(z), _stream(stream)), h, "cr_candidates")
+    return z
+
+
+def independent_set(A: Csr, strong: torch.Tensor, z: torch.Tensor, seed: int,
+                    sel: Optional[torch.Tensor] = None, stream=None):
+    """Greedy maximal independent set of z on the strong graph: (sel, count)."""
+    h = handle(A.device.index)
+    sel = sel if sel is not None else torch.empty(A.n, dtype=torch.uint8, device=A.device)
+    cnt = C.c_int64(0)
+    _check(_lib.independent_set(h, A.ref(), _ptr(strong), _ptr(z), seed & (2 ** 64 - 1), _ptr(sel),
+                                C.byref(cnt), _stream(stream)), h, "independent_set")
+    return sel, cnt.value
+
+
+def cr_coarsening(A: Csr, color: torch.Tensor, ncolors: int, mu: torch.Tensor, theta: float = 0.25,
+                  nu: int = 5, delta: float = 0.7, max_stages: int = 20, seed: int = 0,
+                  cf: Optional[torch.Tensor] = None, stream=None):
+    """Algorithm 1 (cr_coarsening): (cf, rho per stage, |C| per stage); cf
+    is updated in place when given (its entries are C_0)."""
+    h = handle(A.device.index)
+    cf = cf if cf is not None else torch.zeros(A.n, dtype=torch.uint8, device=A.device)
+    rho = (C.c_double * (max_stages + 1))()
+    nc = (C.c_int64 * (max_stages + 1))()
+    ns = C.c_int32(0)
+    _check(_lib.cr_coarsening(h, A.ref(), _ptr(color), int(ncolors), _ptr(mu), float(theta), int(nu),
+                              float(delta), int(max_stages), seed & (2 ** 64 - 1), _ptr(cf), rho, nc,
+                              C.byref(ns), _stream(stream)), h, "cr_coarsening")
+    k = ns.value + 1
+    return cf, list(rho)[:k], list(nc)[:k]

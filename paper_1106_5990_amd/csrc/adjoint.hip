@@ -36,7 +36,7 @@ __global__ __launch_bounds__(kBlock) void col_count_kernel(int64_t nnz, const in
 
 // Row i's entries go to their columns' segments in arrival order (cur
 // zeroed by the caller); the per-column sort below fixes the order.  Also
-// writes the diagonal.
+// writes the diagonal (when diag is not null).
 __global__ __launch_bounds__(kBlock) void col_fill_kernel(int n, const int* __restrict__ rp,
                                                           const int* __restrict__ ci,
                                                           const double* __restrict__ av,
@@ -52,13 +52,15 @@ __global__ __launch_bounds__(kBlock) void col_fill_kernel(int n, const int* __re
     double d = 0.0;
     for (int e = rp[i]; e < rp[i + 1]; ++e) {
         const int j = ci[e];
-        if (j == i) d = av[e];
+        if (diag && j == i) d = av[e];
         const int64_t f = cp[j] + atomicAdd(&cur[j], 1);
         trow[f] = i;
         tent[f] = e;
     }
-    diag[i] = d;
-    if (d == 0.0) flag(status, AD_STAT_ZERO_DIAG);
+    if (diag) {
+        diag[i] = d;
+        if (d == 0.0) flag(status, AD_STAT_ZERO_DIAG);
+    }
 }
 
 // Sorts each column's (row, entry) pairs by row (insertion sort: columns
@@ -266,6 +268,28 @@ __global__ __launch_bounds__(1024) void sum_partials_kernel(const double* __rest
     if (t == 0) *out = acc[0];
 }
 
+// The column-major index: cp[n+1] (column starts), trow/tent[nnz] (row and
+// CSR position of each entry of a column, by increasing row); diag (if not
+// null) the diagonal of the values av.  cnt: n ints, sc: the scan's
+// workspace.
+int launch_csc_index(int n, int64_t nnz, const int* rp, const int* ci, const double* av, int* cnt,
+                     int64_t* cp, int64_t* sc, int* trow, int* tent, double* diag,
+                     unsigned* status, hipStream_t s) {
+    const int nblk_e = (int)((nnz + kBlock - 1) / kBlock);
+    const int nblk_n = (int)(((int64_t)n + kBlock - 1) / kBlock);
+    int rc;
+    if ((rc = launch_fill_i32(cnt, n, 0, s))) return rc;
+    col_count_kernel<<<dim3(nblk_e > 0 ? nblk_e : 1), dim3(kBlock), 0, s>>>(nnz, ci, cnt);
+    AD_HIP(hipGetLastError());
+    if ((rc = launch_excl_scan(cnt, n, cp, sc, s))) return rc;
+    if ((rc = launch_fill_i32(cnt, n, 0, s))) return rc;
+    col_fill_kernel<<<dim3(nblk_n), dim3(kBlock), 0, s>>>(n, rp, ci, av, cp, cnt, trow, tent, diag,
+                                                          status);
+    col_sort_kernel<<<dim3(nblk_n), dim3(kBlock), 0, s>>>(n, cp, trow, tent);
+    AD_HIP(hipGetLastError());
+    return AD_OK;
+}
+
 template <int K>
 static int adjoint_go(ad_handle h, const ad_csr* A, const void* ckpt, int ce, int sweeps,
                       double omega, const double* w, const uint8_t* cf, const int32_t* P_col,
@@ -277,8 +301,6 @@ static int adjoint_go(ad_handle h, const ad_csr* A, const void* ckpt, int ce, in
     const int64_t nnz = A->nnz;
     const size_t panel = (size_t)n * K * sizeof(double);
     const int rblocks = (int)(((int64_t)n + Sh::RPB - 1) / Sh::RPB);
-    const int nblk_e = (int)((nnz + kBlock - 1) / kBlock);
-    const int nblk_n = (int)(((int64_t)n + kBlock - 1) / kBlock);
     const int extra = ce - 1;  // recomputed iterates inside one checkpoint segment
 
     WsReq req;
@@ -309,15 +331,9 @@ static int adjoint_go(ad_handle h, const ad_csr* A, const void* ckpt, int ce, in
     const double* av = (const double*)A->val;
 
     // column-major index of the pattern
-    if ((rc = launch_fill_i32(cnt, n, 0, s))) return rc;
-    col_count_kernel<<<dim3(nblk_e > 0 ? nblk_e : 1), dim3(kBlock), 0, s>>>(nnz, A->col, cnt);
-    AD_HIP(hipGetLastError());
-    if ((rc = launch_excl_scan(cnt, n, cp, sc, s))) return rc;
-    if ((rc = launch_fill_i32(cnt, n, 0, s))) return rc;
-    col_fill_kernel<<<dim3(nblk_n), dim3(kBlock), 0, s>>>(n, A->row_ptr, A->col, av, cp, cnt, trow,
-                                                          tent, diag, h->status);
-    col_sort_kernel<<<dim3(nblk_n), dim3(kBlock), 0, s>>>(n, cp, trow, tent);
-    AD_HIP(hipGetLastError());
+    if ((rc = launch_csc_index(n, nnz, A->row_ptr, A->col, av, cnt, cp, sc, trow, tent, diag,
+                               h->status, s)))
+        return rc;
     if ((rc = launch_fill_f64(grad_val, nnz, 0.0, s))) return rc;
     // seed: R into Y (as scratch), then g into G[0]
     ls_residual_kernel<K, LPR><<<dim3(rblocks), dim3(kBlock), 0, s>>>(

@@ -345,15 +345,20 @@ int csr_validate(ad_handle h, const ad_csr* A, void* stream) {
     return launch_csr_validate(A, h->status, (hipStream_t)stream);
 }
 
+}  // extern "C"
+
+namespace ad {
+
 // Colour-phase Gauss-Seidel sweeps in the colour-major layout: stable
 // colour partition (rowlist: permuted row -> natural row, seg), a
 // colour-major copy of the CSR (rows of one colour contiguous, permuted
 // columns), the start written in permuted order, ping-pong of two permuted
 // panels, and the last sweep writing each row straight to its natural
 // position in X.  Checkpoints are un-permuted.
-static int gs_sweeps(ad_handle h, const ad_csr* A, int K, uint64_t seed, const void* X0,
-                     int sweeps, const int32_t* color, int ncolors, void* X, void* ckpt,
-                     int ckpt_every, hipStream_t s) {
+int gs_sweeps(ad_handle h, const ad_csr* A, int K, uint64_t seed, const void* X0, int sweeps,
+              const int32_t* color, int ncolors, void* X, void* ckpt, int ckpt_every,
+              hipStream_t s, unsigned* color_status) {
+    if (!color_status) color_status = h->status;
     const int dt = A->dtype;
     const int n = A->n;
     const size_t panel = (size_t)n * K * dsize(dt);
@@ -380,7 +385,7 @@ static int gs_sweeps(ad_handle h, const ad_csr* A, int K, uint64_t seed, const v
         TimedScope ts(h, "color_partition", s);
         rc = launch_color_partition(n, color, ncolors, A->row_ptr, rowlist, (int32_t*)(ws + o_inv),
                                     seg, (int32_t*)(ws + o_cnt), nblk, (int32_t*)(ws + o_rpp),
-                                    h->status, s);
+                                    color_status, s);
         if (!rc) rc = launch_perm_setup(dt, A, pc, (int32_t*)(ws + o_inv), s);
         if (rc) return fail(h, rc, "colour partition launch");
     }
@@ -409,6 +414,10 @@ static int gs_sweeps(ad_handle h, const ad_csr* A, int K, uint64_t seed, const v
     }
     return AD_OK;
 }
+
+}  // namespace ad
+
+extern "C" {
 
 int setup_testvectors(ad_handle h, const ad_csr* A, int32_t K, uint64_t seed, const void* X0,
                       int32_t relax, int32_t sweeps, double omega, const int32_t* color,
@@ -804,6 +813,248 @@ int ls_interp_loss_backward(ad_handle h, const ad_csr* A, int32_t K, const void*
     rc = launch_ls_loss_backward(h, K, A, ckpt, ckpt_every, sweeps, omega, w, cf, P_col, P_val,
                                  caliber, X_final, dL, grad_val, grad_omega, (hipStream_t)stream);
     return rc ? fail(h, rc, "ls_interp_loss_backward launch") : AD_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------- compatible relaxation
+namespace {
+
+// Device buffers of one synchronous call, freed on every return path.
+struct DevBufs {
+    std::vector<void*> p;
+    ~DevBufs() {
+        for (void* q : p) (void)hipFree(q);
+    }
+    template <typename T>
+    T* get(size_t count) {
+        void* q = nullptr;
+        if (hipMalloc(&q, count ? count * sizeof(T) : 16) != hipSuccess) return nullptr;
+        p.push_back(q);
+        return (T*)q;
+    }
+};
+
+// One CR run: nu F-relaxation sweeps from the constant start on the F rows
+// of cf; U (n x 2, column 0 the CR vector) receives u^nu and norms (device,
+// 3 doubles) |F|, sum_F u^2, max_F |u|.  rho (host) = eq:meas1's estimate.
+int cr_run(ad_handle h, const ad_csr* A, const int32_t* color, int ncolors, const uint8_t* cf,
+           int nu, int* fcol, void* U0, void* U, double* part, double* norms, unsigned* cstat,
+           double* rho, double* hnorms, hipStream_t s) {
+    const int n = A->n;
+    int rc = launch_cr_start(A->dtype, n, color, cf, fcol, U0, s);
+    if (rc) return rc;
+    {
+        TimedScope ts(h, "cr_relax", s);
+        if ((rc = gs_sweeps(h, A, 2, 0, U0, nu, fcol, ncolors, U, nullptr, 0, s, cstat))) return rc;
+    }
+    {
+        TimedScope ts(h, "cr_norms", s);
+        if ((rc = launch_cr_norms(A->dtype, n, cf, U, part, norms, s))) return rc;
+    }
+    AD_HIP(hipMemcpyAsync(hnorms, norms, 3 * sizeof(double), hipMemcpyDeviceToHost, s));
+    AD_HIP(hipStreamSynchronize(s));
+    *rho = (hnorms[0] > 0.0) ? pow(sqrt(hnorms[1]) / sqrt(hnorms[0]), 1.0 / (double)nu) : 0.0;
+    return AD_OK;
+}
+
+int check_cr_args(ad_handle h, const ad_csr* A, const int32_t* color, int32_t ncolors,
+                  const uint8_t* cf, int32_t nu) {
+    int rc = check_csr(h, A);
+    if (rc) return rc;
+    if (ncolors < 1 || ncolors > 64) return fail(h, AD_EINVAL, "ncolors = %d outside [1, 64]", ncolors);
+    if (A->n > 0 && (!color || !cf)) return fail(h, AD_EINVAL, "color or cf is NULL");
+    if (nu < 1) return fail(h, AD_EINVAL, "nu = %d < 1", nu);
+    return AD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int cr_rate(ad_handle h, const ad_csr* A, const int32_t* color, int32_t ncolors, const uint8_t* cf,
+            int32_t nu, void* u, double* rho, double* norms, void* stream) {
+    if (!h) return AD_EINVAL;
+    h->err.clear();
+    int rc = check_cr_args(h, A, color, ncolors, cf, nu);
+    if (rc) return rc;
+    if (!rho) return fail(h, AD_EINVAL, "rho is NULL");
+    double hn[3] = {0.0, 0.0, 0.0};
+    *rho = 0.0;
+    if (A->n == 0) {
+        if (norms) memcpy(norms, hn, sizeof hn);
+        return AD_OK;
+    }
+    AD_HIP(hipSetDevice(h->device));
+    hipStream_t s = (hipStream_t)stream;
+    const int n = A->n;
+    const size_t vs = dsize(A->dtype);
+    DevBufs b;
+    int* fcol = b.get<int>(n);
+    char* U0 = b.get<char>((size_t)n * 2 * vs);
+    char* U = b.get<char>((size_t)n * 2 * vs);
+    double* part = b.get<double>(3 * (size_t)cr_norm_blocks(n));
+    double* nd = b.get<double>(3);
+    unsigned* cstat = b.get<unsigned>(1);
+    if (!fcol || !U0 || !U || !part || !nd || !cstat) return fail(h, AD_ENOMEM, "cr_rate buffers");
+    if ((rc = cr_run(h, A, color, ncolors, cf, nu, fcol, U0, U, part, nd, cstat, rho, hn, s)))
+        return fail(h, rc, "cr_rate");
+    if (u) {
+        // column 0 of the n x 2 panel
+        AD_HIP(hipMemcpy2DAsync(u, vs, U, 2 * vs, vs, (size_t)n, hipMemcpyDeviceToDevice, s));
+        AD_HIP(hipStreamSynchronize(s));
+    }
+    if (norms) memcpy(norms, hn, sizeof hn);
+    return AD_OK;
+}
+
+int cr_candidates(ad_handle h, int32_t n, int32_t dtype, const uint8_t* cf, const void* u,
+                  double tol, uint8_t* z, void* stream) {
+    if (!h) return AD_EINVAL;
+    h->err.clear();
+    if (n < 0) return fail(h, AD_EINVAL, "n = %d", n);
+    if (dtype != AD_F32 && dtype != AD_F64) return fail(h, AD_EDTYPE, "dtype %d", dtype);
+    if (n > 0 && (!cf || !u || !z)) return fail(h, AD_EINVAL, "cf, u or z is NULL");
+    if (n == 0) return AD_OK;
+    AD_HIP(hipSetDevice(h->device));
+    hipStream_t s = (hipStream_t)stream;
+    DevBufs b;
+    double* part = b.get<double>(3 * (size_t)cr_norm_blocks(n));
+    double* nd = b.get<double>(3);
+    char* U2 = b.get<char>((size_t)n * 2 * dsize(dtype));
+    if (!part || !nd || !U2) return fail(h, AD_ENOMEM, "cr_candidates buffers");
+    // the norm pass reads column 0 of an n x 2 panel
+    const size_t vs = dsize(dtype);
+    AD_HIP(hipMemcpy2DAsync(U2, 2 * vs, u, vs, vs, (size_t)n, hipMemcpyDeviceToDevice, s));
+    int rc = launch_cr_norms(dtype, n, cf, U2, part, nd, s);
+    if (!rc) rc = launch_cr_candidates(dtype, n, cf, u, 1, nd, tol, z, s);
+    if (rc) return fail(h, rc, "cr_candidates launch");
+    AD_HIP(hipStreamSynchronize(s));
+    return AD_OK;
+}
+
+int independent_set(ad_handle h, const ad_csr* A, const uint8_t* strong, const uint8_t* z,
+                    uint64_t seed, uint8_t* sel, int64_t* count, void* stream) {
+    if (!h) return AD_EINVAL;
+    h->err.clear();
+    int rc = check_structure(h, A);
+    if (rc) return rc;
+    if (A->n > 0 && (!z || !sel || (A->nnz > 0 && !strong)))
+        return fail(h, AD_EINVAL, "strong, z or sel is NULL");
+    int64_t cnt = 0;
+    if (A->n > 0) {
+        AD_HIP(hipSetDevice(h->device));
+        hipStream_t s = (hipStream_t)stream;
+        const int n = A->n;
+        const int64_t nnz = A->nnz;
+        DevBufs b;
+        int* cnt_c = b.get<int>(n);
+        int64_t* cp = b.get<int64_t>((size_t)n + 1);
+        int64_t* sc = (int64_t*)b.get<char>((size_t)scan_workspace_bytes(n));
+        int* trow = b.get<int>((size_t)nnz);
+        int* tent = b.get<int>((size_t)nnz);
+        int* lam = b.get<int>(n);
+        uint64_t* hh = b.get<uint64_t>(n);
+        int8_t* state = b.get<int8_t>(n);
+        int* left = b.get<int>(1);
+        if (!cnt_c || !cp || !sc || !trow || !tent || !lam || !hh || !state || !left)
+            return fail(h, AD_ENOMEM, "independent_set buffers");
+        TimedScope ts(h, "independent_set", s);
+        if ((rc = launch_csc_index(n, nnz, A->row_ptr, A->col, nullptr, cnt_c, cp, sc, trow, tent,
+                                   nullptr, h->status, s)) ||
+            (rc = run_independent_set(n, A->row_ptr, A->col, strong, cp, trow, tent, z, seed, lam,
+                                      hh, state, left, sel, nullptr, &cnt, s)))
+            return fail(h, rc, "independent_set");
+    }
+    if (count) *count = cnt;
+    return AD_OK;
+}
+
+int cr_coarsening(ad_handle h, const ad_csr* A, const int32_t* color, int32_t ncolors,
+                  const void* mu, double theta, int32_t nu, double delta, int32_t max_stages,
+                  uint64_t seed, uint8_t* cf, double* rho, int64_t* ncoarse, int32_t* nstages,
+                  void* stream) {
+    if (!h) return AD_EINVAL;
+    h->err.clear();
+    int rc = check_cr_args(h, A, color, ncolors, cf, nu);
+    if (rc) return rc;
+    if (!(theta > 0.0 && theta < 1.0)) return fail(h, AD_EINVAL, "theta = %g outside (0, 1)", theta);
+    if (!(delta >= 0.0)) return fail(h, AD_EINVAL, "delta = %g", delta);
+    if (max_stages < 0) return fail(h, AD_EINVAL, "max_stages = %d", max_stages);
+    if (!rho || !ncoarse || !nstages) return fail(h, AD_EINVAL, "rho, ncoarse or nstages is NULL");
+    if (A->nnz > 0 && !mu) return fail(h, AD_EINVAL, "mu is NULL");
+    *nstages = 0;
+    if (A->n == 0) {
+        rho[0] = 0.0;
+        ncoarse[0] = 0;
+        return AD_OK;
+    }
+    AD_HIP(hipSetDevice(h->device));
+    hipStream_t s = (hipStream_t)stream;
+    const int n = A->n;
+    const int64_t nnz = A->nnz;
+    const size_t vs = dsize(A->dtype);
+    DevBufs b;
+    int* fcol = b.get<int>(n);
+    char* U0 = b.get<char>((size_t)n * 2 * vs);
+    char* U = b.get<char>((size_t)n * 2 * vs);
+    double* part = b.get<double>(3 * (size_t)cr_norm_blocks(n));
+    double* nd = b.get<double>(3);
+    unsigned* cstat = b.get<unsigned>(1);
+    uint8_t* z = b.get<uint8_t>(n);
+    uint8_t* fm = b.get<uint8_t>(n);
+    uint8_t* strong = b.get<uint8_t>((size_t)nnz);
+    int* cnt_c = b.get<int>(n);
+    int64_t* cp = b.get<int64_t>((size_t)n + 1);
+    int64_t* sc = (int64_t*)b.get<char>((size_t)scan_workspace_bytes(n));
+    int* trow = b.get<int>((size_t)nnz);
+    int* tent = b.get<int>((size_t)nnz);
+    int* lam = b.get<int>(n);
+    uint64_t* hh = b.get<uint64_t>(n);
+    int8_t* state = b.get<int8_t>(n);
+    int* left = b.get<int>(1);
+    if (!fcol || !U0 || !U || !part || !nd || !cstat || !z || !fm || !strong || !cnt_c || !cp ||
+        !sc || !trow || !tent || !lam || !hh || !state || !left)
+        return fail(h, AD_ENOMEM, "cr_coarsening buffers");
+    {
+        TimedScope ts(h, "cr_index", s);
+        if ((rc = launch_csc_index(n, nnz, A->row_ptr, A->col, nullptr, cnt_c, cp, sc, trow, tent,
+                                   nullptr, h->status, s)))
+            return fail(h, rc, "cr_coarsening: column index");
+    }
+    double r = 0.0, hn[3];
+    if ((rc = cr_run(h, A, color, ncolors, cf, nu, fcol, U0, U, part, nd, cstat, &r, hn, s)))
+        return fail(h, rc, "cr_coarsening: CR run");
+    int64_t nc = n - (int64_t)hn[0];
+    rho[0] = r;
+    ncoarse[0] = nc;
+    int stage = 0;
+    while (r > delta && stage < max_stages) {
+        {
+            TimedScope ts(h, "cr_select", s);
+            if ((rc = launch_cr_candidates(A->dtype, n, cf, U, 2, nd, 1.0 - r, z, s)) ||
+                (rc = launch_cr_fmask(n, cf, fm, s)) ||
+                (rc = launch_strength(A->dtype, A, mu, theta, fm, strong, nullptr, s)))
+                return fail(h, rc, "cr_coarsening: candidates / strength");
+        }
+        int64_t added = 0;
+        {
+            TimedScope ts(h, "independent_set", s);
+            if ((rc = run_independent_set(n, A->row_ptr, A->col, strong, cp, trow, tent, z,
+                                          seed + (uint64_t)stage, lam, hh, state, left, nullptr,
+                                          cf, &added, s)))
+                return fail(h, rc, "cr_coarsening: independent set");
+        }
+        if (added == 0) break;  // no candidate: nothing can grow C
+        ++stage;
+        if ((rc = cr_run(h, A, color, ncolors, cf, nu, fcol, U0, U, part, nd, cstat, &r, hn, s)))
+            return fail(h, rc, "cr_coarsening: CR run");
+        nc += added;
+        rho[stage] = r;
+        ncoarse[stage] = nc;
+    }
+    *nstages = stage;
+    return AD_OK;
 }
 
 }  // extern "C"

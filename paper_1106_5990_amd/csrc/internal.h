@@ -239,7 +239,31 @@ int autotune_batched(ad_handle h, int nmat, const ad_csr* As, int K, int sweeps,
                      hipStream_t s);
 int batch_bucket(int nmat, const ad_csr* As);
 
+// ---- api.hip
+// Colour-phase sweeps of setup_testvectors (arguments checked by the caller);
+// color_status (null: the handle's) receives the partition's bad-colour flag.
+int gs_sweeps(ad_handle h, const ad_csr* A, int K, uint64_t seed, const void* X0, int sweeps,
+              const int32_t* color, int ncolors, void* X, void* ckpt, int ckpt_every,
+              hipStream_t s, unsigned* color_status = nullptr);
+
+// ---- coarsen.hip
+int cr_norm_blocks(int n);
+int launch_cr_start(int dtype, int n, const int* color, const uint8_t* cf, int* fcol, void* U0,
+                    hipStream_t s);
+int launch_cr_fmask(int n, const uint8_t* cf, uint8_t* fm, hipStream_t s);
+int launch_cr_norms(int dtype, int n, const uint8_t* cf, const void* U, double* part,
+                    double* norms, hipStream_t s);
+int launch_cr_candidates(int dtype, int n, const uint8_t* cf, const void* U, int stride,
+                         const double* norms, double tol, uint8_t* z, hipStream_t s);
+int run_independent_set(int n, const int* rp, const int* ci, const uint8_t* strong,
+                        const int64_t* cp, const int* trow, const int* tent, const uint8_t* z,
+                        uint64_t seed, int* lam, uint64_t* hh, int8_t* state, int* left,
+                        uint8_t* sel, uint8_t* cf, int64_t* count, hipStream_t s);
+
 // ---- adjoint.hip
+int launch_csc_index(int n, int64_t nnz, const int* rp, const int* ci, const double* av, int* cnt,
+                     int64_t* cp, int64_t* sc, int* trow, int* tent, double* diag,
+                     unsigned* status, hipStream_t s);
 int launch_ls_loss_backward(ad_handle h, int K, const ad_csr* A, const void* ckpt, int ce,
                             int sweeps, double omega, const double* w, const uint8_t* cf,
                             const int32_t* P_col, const double* P_val, int cal,
