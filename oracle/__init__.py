@@ -362,3 +362,58 @@ def cr_coarsen(A, color, ncolors: int, mu, theta: float, nu: int = 5, delta: flo
                             float(theta), int(nu), float(delta), int(max_stages),
                             seed & (2**64 - 1), _p(cf), _p(rho), _p(nc))
     return cf, rho[:s + 1], nc[:s + 1]
+
+
+def _sig_gs_grad(L):
+    P = C.c_void_p
+    i32, f64 = C.c_int, C.c_double
+    for name, res, args in (
+            ("oracle_ls_loss_gs", f64, [i32, P, P, P, i32, P, i32, P, i32, P, P, i32]),
+            ("oracle_ls_grad_w", None, [i32, P, P, P, i32, P, P, P, i32, P]),
+            ("oracle_ls_loss_grad_gs", f64, [i32, P, P, P, i32, P, i32, P, i32, P, P, i32, P, P])):
+        fn = getattr(L, name)
+        fn.restype = res
+        fn.argtypes = args
+    return L
+
+
+def ls_loss_gs(A, X0, sweeps: int, color, ncolors: int, w, cf, caliber: int, val=None) -> float:
+    """L = sum over F of ls_val after colour-phase Gauss-Seidel sweeps."""
+    L = _sig_gs_grad(lib())
+    n, rp, ci, va = _csr(A)
+    if val is not None:
+        va = _f64(val)
+    X0 = _f64(X0)
+    col = np.ascontiguousarray(color, dtype=np.int32)
+    w = None if w is None else _f64(w)
+    cf = np.ascontiguousarray(cf, dtype=np.uint8)
+    return float(L.oracle_ls_loss_gs(n, _p(rp), _p(ci), _p(va), X0.shape[1], _p(X0), int(sweeps),
+                                     _p(col), int(ncolors), _p(w), _p(cf), int(caliber)))
+
+
+def ls_grad_w(A, X, w, cf, caliber: int):
+    """dL/dw_k at the final panel X."""
+    L = _sig_gs_grad(lib())
+    n, rp, ci, va = _csr(A)
+    X = _f64(X)
+    w = None if w is None else _f64(w)
+    cf = np.ascontiguousarray(cf, dtype=np.uint8)
+    gw = np.empty(X.shape[1])
+    L.oracle_ls_grad_w(n, _p(rp), _p(ci), _p(va), X.shape[1], _p(X), _p(w), _p(cf), int(caliber),
+                       _p(gw))
+    return gw
+
+
+def ls_loss_grad_gs(A, X0, sweeps: int, color, ncolors: int, w, cf, caliber: int):
+    """(L, dL/dvals, dL/dw) through colour-phase Gauss-Seidel sweeps."""
+    L = _sig_gs_grad(lib())
+    n, rp, ci, va = _csr(A)
+    X0 = _f64(X0)
+    col = np.ascontiguousarray(color, dtype=np.int32)
+    w = None if w is None else _f64(w)
+    cf = np.ascontiguousarray(cf, dtype=np.uint8)
+    gv = np.empty(len(ci))
+    gw = np.empty(X0.shape[1])
+    Lv = L.oracle_ls_loss_grad_gs(n, _p(rp), _p(ci), _p(va), X0.shape[1], _p(X0), int(sweeps),
+                                  _p(col), int(ncolors), _p(w), _p(cf), int(caliber), _p(gv), _p(gw))
+    return float(Lv), gv, gw

@@ -604,6 +604,177 @@ double oracle_ls_loss_grad(int n, const int *rp, const int *ci, const double *a,
     return L;
 }
 
+/* ---------------------------------------------------------------------- */
+/* The same loss with the test vectors relaxed by colour-phase Gauss-      */
+/* Seidel (Sec. 3 test vectors, relaxed by Gauss-Seidel as in Sec. 5.2),   */
+/* and its gradient with respect to the stored values of A and to the LS   */
+/* weights w_k (eq:LSfuncrowi).                                            */
+/*                                                                         */
+/* One colour phase of oracle_color_gs is the linear map                   */
+/*     v' = v - E_c D^{-1} A v,                                            */
+/* E_c selecting the rows of colour c (rows with an invalid colour or a    */
+/* zero diagonal are never selected): every value a phase reads is the     */
+/* state before it.  Its adjoint is g = g' - A^T y with y = D^{-1} E_c g', */
+/* and the phase contributes -y_i v_j to dL/da_ij (i of colour c) and      */
+/* y_i (A v)_i / a_ii to dL/da_ii through D^{-1}.  A sweep's adjoint runs  */
+/* its phases in reverse colour order.                                     */
+/*                                                                         */
+/* w_k enters L directly and through the fitted p; p minimises each row's  */
+/* functional, so dL/dw_k = sum over F rows of (x_i^k - sum_j p_ij x_j^k)^2 */
+/* at the final panel.                                                     */
+/* ---------------------------------------------------------------------- */
+static void gs_phase(int n, const int *rp, const int *ci, const double *a, int K,
+                     const int *color, int ncolors, int c, const double *v, double *out)
+{
+    int i, e, k;
+    memcpy(out, v, sizeof(double) * (size_t)n * K);
+    for (i = 0; i < n; ++i) {
+        double d;
+        if (color[i] != c || c < 0 || c >= ncolors) continue;
+        d = diag_of(rp, ci, a, i);
+        if (d == 0.0) continue;
+        for (k = 0; k < K; ++k) {
+            double y = 0.0;
+            for (e = rp[i]; e < rp[i + 1]; ++e) y += a[e] * v[(int64_t)ci[e] * K + k];
+            out[(int64_t)i * K + k] = v[(int64_t)i * K + k] - y / d;
+        }
+    }
+}
+
+double oracle_ls_loss_gs(int n, const int *rp, const int *ci, const double *a, int K,
+                         const double *X0, int sweeps, const int *color, int ncolors,
+                         const double *w, const unsigned char *cf, int caliber)
+{
+    size_t nk = (size_t)n * K;
+    double *X = (double *)malloc(sizeof(double) * nk);
+    int *Pc = (int *)malloc(sizeof(int) * (size_t)n * caliber);
+    double *Pv = (double *)malloc(sizeof(double) * (size_t)n * caliber);
+    double *ls = (double *)malloc(sizeof(double) * n);
+    int *st = (int *)malloc(sizeof(int) * n);
+    double L = 0.0;
+    int i;
+    memcpy(X, X0, sizeof(double) * nk);
+    oracle_color_gs(n, rp, ci, a, K, color, ncolors, sweeps, X);
+    ls_rows_for(n, rp, ci, a, K, X, w, cf, caliber, Pc, Pv, ls, st);
+    for (i = 0; i < n; ++i)
+        if (!cf[i]) L += ls[i];
+    free(X); free(Pc); free(Pv); free(ls); free(st);
+    return L;
+}
+
+/* dL/dw_k at the final panel X (p refitted there). */
+void oracle_ls_grad_w(int n, const int *rp, const int *ci, const double *a, int K,
+                      const double *X, const double *w, const unsigned char *cf, int caliber,
+                      double *grad_w)
+{
+    int *Pc = (int *)malloc(sizeof(int) * (size_t)n * caliber);
+    double *Pv = (double *)malloc(sizeof(double) * (size_t)n * caliber);
+    double *ls = (double *)malloc(sizeof(double) * n);
+    int *st = (int *)malloc(sizeof(int) * n);
+    int i, k, q;
+    ls_rows_for(n, rp, ci, a, K, X, w, cf, caliber, Pc, Pv, ls, st);
+    for (k = 0; k < K; ++k) grad_w[k] = 0.0;
+    for (i = 0; i < n; ++i) {
+        if (cf[i]) continue;
+        for (k = 0; k < K; ++k) {
+            double res = X[(int64_t)i * K + k];
+            for (q = 0; q < caliber; ++q) {
+                int j = Pc[(int64_t)i * caliber + q];
+                if (j >= 0) res -= Pv[(int64_t)i * caliber + q] * X[(int64_t)j * K + k];
+            }
+            grad_w[k] += res * res;
+        }
+    }
+    free(Pc); free(Pv); free(ls); free(st);
+}
+
+double oracle_ls_loss_grad_gs(int n, const int *rp, const int *ci, const double *a, int K,
+                              const double *X0, int sweeps, const int *color, int ncolors,
+                              const double *w, const unsigned char *cf, int caliber,
+                              double *grad_val, double *grad_w)
+{
+    size_t nk = (size_t)n * K;
+    int64_t nnz = rp[n];
+    int nst = sweeps * ncolors + 1;   /* the state before every phase, and the last */
+    double **v = (double **)malloc(sizeof(double *) * (size_t)nst);
+    double *g = (double *)malloc(sizeof(double) * nk);
+    double *gn = (double *)malloc(sizeof(double) * nk);
+    double *yv = (double *)malloc(sizeof(double) * nk);
+    double *z = (double *)malloc(sizeof(double) * K);
+    int *Pc = (int *)malloc(sizeof(int) * (size_t)n * caliber);
+    double *Pv = (double *)malloc(sizeof(double) * (size_t)n * caliber);
+    double *ls = (double *)malloc(sizeof(double) * n);
+    int *st = (int *)malloc(sizeof(int) * n);
+    double L = 0.0;
+    int s, c, i, k, e, q, t;
+    int64_t ee;
+
+    for (t = 0; t < nst; ++t) v[t] = (double *)malloc(sizeof(double) * nk);
+    memcpy(v[0], X0, sizeof(double) * nk);
+    for (s = 0; s < sweeps; ++s)
+        for (c = 0; c < ncolors; ++c) {
+            t = s * ncolors + c;
+            gs_phase(n, rp, ci, a, K, color, ncolors, c, v[t], v[t + 1]);
+        }
+    {
+        const double *x = v[nst - 1];
+        ls_rows_for(n, rp, ci, a, K, x, w, cf, caliber, Pc, Pv, ls, st);
+        for (ee = 0; ee < (int64_t)nk; ++ee) g[ee] = 0.0;
+        for (k = 0; k < K; ++k) grad_w[k] = 0.0;
+        for (i = 0; i < n; ++i) {
+            if (cf[i]) continue;
+            L += ls[i];
+            for (k = 0; k < K; ++k) {
+                double res = x[(int64_t)i * K + k];
+                for (q = 0; q < caliber; ++q)
+                    if (Pc[(int64_t)i * caliber + q] >= 0)
+                        res -= Pv[(int64_t)i * caliber + q] * x[(int64_t)Pc[(int64_t)i * caliber + q] * K + k];
+                grad_w[k] += res * res;
+                g[(int64_t)i * K + k] += 2.0 * weight(w, k) * res;
+                for (q = 0; q < caliber; ++q) {
+                    int j = Pc[(int64_t)i * caliber + q];
+                    if (j >= 0)
+                        g[(int64_t)j * K + k] -= 2.0 * weight(w, k) * res * Pv[(int64_t)i * caliber + q];
+                }
+            }
+        }
+    }
+    for (e = 0; e < nnz; ++e) grad_val[e] = 0.0;
+    for (t = nst - 2; t >= 0; --t) {
+        const double *x = v[t];      /* state before the phase */
+        c = t % ncolors;
+        for (i = 0; i < n; ++i) {
+            double d = diag_of(rp, ci, a, i);
+            int on = color[i] == c && d != 0.0;
+            for (k = 0; k < K; ++k) yv[(int64_t)i * K + k] = on ? g[(int64_t)i * K + k] / d : 0.0;
+        }
+        memcpy(gn, g, sizeof(double) * nk);
+        for (i = 0; i < n; ++i) {
+            double d = diag_of(rp, ci, a, i);
+            if (color[i] != c || d == 0.0) continue;
+            row_apply(rp, ci, a, K, x, i, z);
+            for (e = rp[i]; e < rp[i + 1]; ++e) {
+                int j = ci[e];
+                double acc = 0.0;
+                for (k = 0; k < K; ++k) acc += yv[(int64_t)i * K + k] * x[(int64_t)j * K + k];
+                grad_val[e] -= acc;
+                if (j == i) {
+                    double acc2 = 0.0;
+                    for (k = 0; k < K; ++k) acc2 += yv[(int64_t)i * K + k] * z[k];
+                    grad_val[e] += acc2 / d;
+                }
+                for (k = 0; k < K; ++k) gn[(int64_t)j * K + k] -= a[e] * yv[(int64_t)i * K + k];
+            }
+        }
+        memcpy(g, gn, sizeof(double) * nk);
+    }
+
+    for (t = 0; t < nst; ++t) free(v[t]);
+    free(v); free(g); free(gn); free(yv); free(z);
+    free(Pc); free(Pv); free(ls); free(st);
+    return L;
+}
+
 /* ====================================================================== */
 /* Long-range connectivity and the search over interpolatory sets          */
 /* ====================================================================== */
