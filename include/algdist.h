@@ -451,6 +451,28 @@ int ls_interp_loss_backward(ad_handle h, const ad_csr *A, int32_t K, const void 
                             int32_t caliber, const void *X_final, const double *dL,
                             double *grad_val, double *grad_omega, void *stream);
 
+/* The gradient of the same loss for test vectors relaxed by either rule of
+ * setup_testvectors, and with respect to the LS weights as well.
+ * relax = AD_JACOBI: as ls_interp_loss_backward (grad_omega may be NULL).
+ * relax = AD_MULTICOLOR_GS (color/ncolors as for setup_testvectors, omega
+ * ignored; grad_omega, if given, receives 0): one colour phase is the map
+ * v' = v - E_c D^{-1} A v (E_c: the rows of colour c), its adjoint is
+ * g = g' - A^T y with y = D^{-1} E_c g', and it adds -<y_i, v_j> to
+ * dL/da_ij and <y_i, (A v)_i> / a_ii to dL/da_ii; a sweep's phases are
+ * undone in reverse colour order, their states recomputed from the sweep's
+ * iterate.  grad_w (device, K FP64, may be NULL) receives dL/dw_k = dL *
+ * sum over F rows of (x_i^k - sum_j p_ij x_j^k)^2 at X_final (p minimises
+ * each row's functional, so its own variation does not enter; Sec. 3.1
+ * eq:LSfuncrowi).  Other arguments as for ls_interp_loss_backward; ckpt
+ * comes from setup_testvectors with the same relax and colouring.  Uses
+ * handle workspace of about (4 + c + ncolors) n K doubles + nnz ints. */
+int ls_interp_loss_grad(ad_handle h, const ad_csr *A, int32_t K, int32_t relax,
+                        const int32_t *color, int32_t ncolors, const void *ckpt,
+                        int32_t ckpt_every, int32_t sweeps, double omega, const double *w,
+                        const uint8_t *cf, const int32_t *P_col, const double *P_val,
+                        int32_t caliber, const void *X_final, const double *dL, double *grad_val,
+                        double *grad_omega, double *grad_w, void *stream);
+
 /* ------------------------------------------------------------------ */
 /* Compatible-relaxation coarsening (Sec. 3.2; Sec. 4.2, Algorithm 1).  */
 /* These calls are synchronous (the host decides between stages and     */

@@ -84,6 +84,8 @@ _SIGS = {
                                      _f64, _P, _P, _P]),
     "ls_interp_loss_backward": (_i32, [_P, _CSRP, _i32, _P, _i32, _i32, _f64, _P, _P, _P, _P, _i32,
                                        _P, _P, _P, _P, _P]),
+    "ls_interp_loss_grad": (_i32, [_P, _CSRP, _i32, _i32, _P, _i32, _P, _i32, _i32, _f64, _P, _P,
+                                   _P, _P, _i32, _P, _P, _P, _P, _P, _P]),
     "cr_rate": (_i32, [_P, _CSRP, _P, _i32, _P, _i32, _P, C.POINTER(C.c_double), _P, _P]),
     "cr_candidates": (_i32, [_P, _i32, _i32, _P, _P, _f64, _P, _P]),
     "independent_set": (_i32, [_P, _CSRP, _P, _P, _u64, _P, C.POINTER(C.c_int64), _P]),
@@ -524,6 +526,61 @@ class LSInterpLoss(torch.autograd.Function):
         dL = gL.detach().reshape(1).to(torch.float64).contiguous()
         gv, go = ls_interp_loss_backward(A, K, ck, ce, sweeps, om, cf, Pc, Pv, X, dL, w=w)
         return gv, go.reshape(oshape), None, None, None, None, None, None, None, None, None, None
+
+
+def ls_interp_loss_grad(A: Csr, K: int, ckpt: torch.Tensor, ckpt_every: int, sweeps: int,
+                        cf: torch.Tensor, P_col: torch.Tensor, P_val: torch.Tensor,
+                        X_final: torch.Tensor, dL: torch.Tensor, relax: str = "gs",
+                        color: Optional[torch.Tensor] = None, ncolors: int = 0,
+                        omega: float = 1.0, w: Optional[torch.Tensor] = None, stream=None):
+    """(dL/dvalues, dL/domega, dL/dw) of the LS loss (ls_interp_loss_grad)."""
+    h = handle(A.device.index)
+    gv = torch.empty(A.nnz, dtype=torch.float64, device=A.device)
+    go = torch.empty(1, dtype=torch.float64, device=A.device)
+    gw = torch.empty(K, dtype=torch.float64, device=A.device)
+    rk = {"jacobi": AD_JACOBI, "gs": AD_MULTICOLOR_GS}[relax]
+    rc = _lib.ls_interp_loss_grad(h, A.ref(), K, rk, _ptr(color), int(ncolors), _ptr(ckpt),
+                                  int(ckpt_every), int(sweeps), float(omega), _ptr(w), _ptr(cf),
+                                  _ptr(P_col), _ptr(P_val), P_col.shape[1], _ptr(X_final), _ptr(dL),
+                                  _ptr(gv), _ptr(go), _ptr(gw), _stream(stream))
+    _check(rc, h, "ls_interp_loss_grad")
+    return gv, go, gw
+
+
+class LSInterpLossGS(torch.autograd.Function):
+    """L(values, w) = sum over F rows of the LS interpolation functional
+    after `sweeps` colour-phase Gauss-Seidel sweeps of K test vectors (plain
+    target), differentiable in the CSR values and the LS weights w.
+
+    apply(values, w, row_ptr, col, K, seed, sweeps, color, ncolors, cf, caliber,
+          ckpt_every=1, X0=None) -> 0-dim FP64 tensor.
+    Forward: setup_testvectors (checkpointed), then distance_ls.  Backward:
+    ls_interp_loss_grad."""
+
+    @staticmethod
+    def forward(ctx, values, w, row_ptr, col, K, seed, sweeps, color, ncolors, cf, caliber,
+                ckpt_every=1, X0=None):
+        A = Csr(row_ptr, col, values.detach().contiguous())
+        wd = w.detach().contiguous()
+        nck = max(1, -(-sweeps // ckpt_every))
+        ck = torch.empty((nck, A.n, K), dtype=torch.float64, device=A.device)
+        X = setup_testvectors(A, K, seed=seed, X0=X0, relax="gs", sweeps=sweeps, color=color,
+                              ncolors=ncolors, ckpt=ck, ckpt_every=ckpt_every)
+        _, _, _, Pc, Pv, ls, st, tot = distance_ls(A, X, cf, caliber, w=wd, fuse=False,
+                                                   want_sum=True)
+        ctx.save_for_backward(values, wd, ck, X, Pc, Pv, cf, color)
+        ctx.meta = (row_ptr, col, K, sweeps, ckpt_every, ncolors)
+        return tot.reshape(())
+
+    @staticmethod
+    def backward(ctx, gL):
+        values, wd, ck, X, Pc, Pv, cf, color = ctx.saved_tensors
+        row_ptr, col, K, sweeps, ce, ncolors = ctx.meta
+        A = Csr(row_ptr, col, values.detach().contiguous())
+        dL = gL.detach().reshape(1).to(torch.float64).contiguous()
+        gv, _, gw = ls_interp_loss_grad(A, K, ck, ce, sweeps, cf, Pc, Pv, X, dL, relax="gs",
+                                        color=color, ncolors=ncolors, w=wd)
+        return (gv, gw) + (None,) * 11
 
 
 # ------------------------------------------------------------------ compatible relaxation

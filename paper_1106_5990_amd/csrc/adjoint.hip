@@ -23,6 +23,7 @@
 
 #include "device.h"
 #include "internal.h"
+#include "rowops.h"
 
 namespace ad {
 
@@ -175,17 +176,145 @@ __global__ __launch_bounds__(kBlock) void dinv_kernel(int n, const double* __res
     store_lane<double, V, C>(Y + (size_t)i64 * K + l * V, v);
 }
 
+// y = D^{-1} E_c g: rows of colour c with a nonzero diagonal, 0 elsewhere
+// (the adjoint of one colour phase).
+template <int K, int LPR>
+__global__ __launch_bounds__(kBlock) void dinv_colour_kernel(int n, const double* __restrict__ diag,
+                                                             const int* __restrict__ color, int c,
+                                                             const double* __restrict__ G,
+                                                             double* __restrict__ Y) {
+    using S = Shape<double, K, LPR>;
+    constexpr int V = S::V, C = S::C;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int g = lane / LPR, l = lane % LPR;
+    const int64_t i64 = ((int64_t)blockIdx.x * kWavesPerBlock + threadIdx.x / kWave) * S::RPW + g;
+    if (i64 >= n) return;
+    const double d = diag[i64];
+    const bool on = color[i64] == c && d != 0.0;
+    Frag<double, V> v = load_lane<double, V, C>(G + (size_t)i64 * K + l * V);
+#pragma unroll
+    for (int q = 0; q < V; ++q) v.v[q] = on ? v.v[q] / d : 0.0;
+    store_lane<double, V, C>(Y + (size_t)i64 * K + l * V, v);
+}
+
+// One colour phase in natural row order (the recomputation of the forward
+// sweeps): rows of colour c become x_i - (A x)_i / a_ii (held when a_ii = 0),
+// every other row is copied.  The row arithmetic is the colour-major phase
+// kernel's (same entry order, same operations), so the iterates it
+// recomputes are those the forward pass checkpointed.
+template <int K, int LPR>
+__global__ __launch_bounds__(kBlock) void gs_phase_nat_kernel(int n, const int* __restrict__ rp,
+                                                              const int* __restrict__ ci,
+                                                              const double* __restrict__ av,
+                                                              const int* __restrict__ color, int c,
+                                                              const double* __restrict__ Xin,
+                                                              double* __restrict__ Xout,
+                                                              unsigned* status) {
+    using S = Shape<double, K, LPR>;
+    constexpr int V = S::V, C = S::C;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int g = lane / LPR, l = lane % LPR;
+    const int64_t i64 = ((int64_t)blockIdx.x * kWavesPerBlock + threadIdx.x / kWave) * S::RPW + g;
+    if (i64 >= n) return;
+    const int i = (int)i64;
+    if (color[i] == c) {
+        double y[V], d;
+        Frag<double, V> xi;
+        row_spmm<S, double, K>(i, rp[i], rp[i + 1], ci, av, l, [&](int) { return Xin; }, y, d, xi);
+        Frag<double, V> out;
+        if (d == 0.0) {
+            out = load_lane<double, V, C>(Xin + (size_t)i * K + l * V);
+        } else {
+#pragma unroll
+            for (int q = 0; q < V; ++q) out.v[q] = xi.v[q] - y[q] / d;
+        }
+        store_lane<double, V, C>(Xout + (size_t)i * K + l * V, out);
+    } else {
+        store_lane<double, V, C>(Xout + (size_t)i * K + l * V,
+                                 load_lane<double, V, C>(Xin + (size_t)i * K + l * V));
+    }
+}
+
+// dL/dw_k partials: part[b * K + k] = sum over block b's F rows of rho_ik^2,
+// rho_i = x_i - sum_q P_val[i,q] x_{P_col[i,q]}.  Fixed order: a lane's
+// entries, then the row groups of a wave (xor butterfly over lanes with the
+// same entries), then the waves in order.
+template <int K, int LPR>
+__global__ __launch_bounds__(kBlock) void gradw_partials_kernel(
+    int n, const double* __restrict__ X, const uint8_t* __restrict__ cf,
+    const int* __restrict__ Pcol, const double* __restrict__ Pval, int cal,
+    double* __restrict__ part) {
+    using S = Shape<double, K, LPR>;
+    constexpr int V = S::V, C = S::C;
+    __shared__ double acc[kWavesPerBlock][K];
+    const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
+    const int g = lane / LPR, l = lane % LPR;
+    const int64_t i64 = ((int64_t)blockIdx.x * kWavesPerBlock + wv) * S::RPW + g;
+    double sq[V];
+#pragma unroll
+    for (int q = 0; q < V; ++q) sq[q] = 0.0;
+    if (i64 < n && !cf[i64]) {
+        const int i = (int)i64;
+        Frag<double, V> r = load_lane<double, V, C>(X + (size_t)i * K + l * V);
+        for (int q = 0; q < cal; ++q) {
+            const int j = Pcol[(size_t)i * cal + q];
+            if (j < 0) continue;
+            const double p = Pval[(size_t)i * cal + q];
+            const Frag<double, V> xj = load_lane<double, V, C>(X + (size_t)j * K + l * V);
+#pragma unroll
+            for (int v = 0; v < V; ++v) r.v[v] -= p * xj.v[v];
+        }
+#pragma unroll
+        for (int v = 0; v < V; ++v) sq[v] = r.v[v] * r.v[v];
+    }
+#pragma unroll
+    for (int o = kWave / 2; o >= LPR; o >>= 1)
+#pragma unroll
+        for (int v = 0; v < V; ++v) sq[v] += __shfl_xor(sq[v], o, kWave);
+    if (g == 0)
+#pragma unroll
+        for (int v = 0; v < V; ++v) acc[wv][l * V + v] = sq[v];
+    __syncthreads();
+    for (int k = threadIdx.x; k < K; k += kBlock) {
+        double t = 0.0;
+        for (int q = 0; q < kWavesPerBlock; ++q) t += acc[q][k];
+        part[(size_t)blockIdx.x * K + k] = t;
+    }
+}
+
+// out[k] = scale * sum_b part[b * K + k], one workgroup per k, fixed order.
+__global__ __launch_bounds__(1024) void sum_columns_kernel(const double* __restrict__ part,
+                                                           int64_t m, int K,
+                                                           const double* __restrict__ scale,
+                                                           double* __restrict__ out) {
+    __shared__ double acc[1024];
+    const int t = threadIdx.x, k = blockIdx.x;
+    const int64_t per = (m + 1023) / 1024;
+    double s = 0.0;
+    for (int64_t q = t * per; q < m && q < (t + 1) * per; ++q) s += part[q * K + k];
+    acc[t] = s;
+    __syncthreads();
+    for (int o = 512; o > 0; o >>= 1) {
+        if (t < o) acc[t] += acc[t + o];
+        __syncthreads();
+    }
+    if (t == 0) out[k] = *scale * acc[0];
+}
+
 // One backward sweep for row i:
 //   z_i = (A x^s)_i, (A^T y)_i = sum over column i's entries (r, i) of a_ri y_r,
 //   gval[e] -= omega <y_i, x_col e>,  gval[diag] += omega <y_i, z_i> / a_ii,
 //   Gout_i = Gin_i - omega (A^T y)_i,  block partial of -<y_i, z_i>.
+// With color (a colour phase's adjoint, y zero off colour c) the row part is
+// skipped for rows of another colour (its terms are zero).
 template <int K, int LPR>
 __global__ __launch_bounds__(kBlock) void adjoint_sweep_kernel(
     int n, const int* __restrict__ rp, const int* __restrict__ ci, const double* __restrict__ av,
     const int64_t* __restrict__ cp, const int* __restrict__ trow, const int* __restrict__ tent,
     const double* __restrict__ diag, const double* __restrict__ Xs,
     const double* __restrict__ Y, const double* __restrict__ Gin, double* __restrict__ Gout,
-    double omega, double* __restrict__ gval, double* __restrict__ wpart) {
+    double omega, double* __restrict__ gval, double* __restrict__ wpart,
+    const int* __restrict__ color, int c) {
     using S = Shape<double, K, LPR>;
     constexpr int V = S::V, C = S::C;
     __shared__ double part[kWavesPerBlock];
@@ -205,7 +334,8 @@ __global__ __launch_bounds__(kBlock) void adjoint_sweep_kernel(
             aty[q] = 0.0;
         }
         int ediag = -1;
-        for (int e = e0; e < e1; ++e) {
+        const bool rows_part = !color || color[i] == c;
+        for (int e = rows_part ? e0 : e1; e < e1; ++e) {
             const int j = ci[e];
             const double a = av[e];
             const Frag<double, V> xj = load_lane<double, V, C>(Xs + (size_t)j * K + l * V);
@@ -231,7 +361,7 @@ __global__ __launch_bounds__(kBlock) void adjoint_sweep_kernel(
         for (int q = 0; q < V; ++q) yz = fma(yi.v[q], z[q], yz);
         yz = group_sum<LPR>(yz);
         const double d = diag[i];
-        if (l == 0) {
+        if (l == 0 && rows_part) {
             if (ediag >= 0 && d != 0.0) gval[ediag] += omega * yz / d;
             wsum = -yz;
         }
@@ -290,11 +420,17 @@ int launch_csc_index(int n, int64_t nnz, const int* rp, const int* ci, const dou
     return AD_OK;
 }
 
+// Backward pass.  relax AD_JACOBI: damped-Jacobi sweeps (grad_omega).
+// relax AD_MULTICOLOR_GS: colour-phase sweeps; each sweep's phase states are
+// recomputed from its iterate and the phases' adjoints run in reverse colour
+// order (omega is 1 and grad_omega, if given, is set to 0).  grad_w (may be
+// null) receives dL/dw_k.
 template <int K>
-static int adjoint_go(ad_handle h, const ad_csr* A, const void* ckpt, int ce, int sweeps,
-                      double omega, const double* w, const uint8_t* cf, const int32_t* P_col,
-                      const double* P_val, int cal, const void* X_final, const double* dL,
-                      double* grad_val, double* grad_omega, hipStream_t s) {
+static int adjoint_go(ad_handle h, const ad_csr* A, int relax, const int32_t* color, int ncolors,
+                      const void* ckpt, int ce, int sweeps, double omega, const double* w,
+                      const uint8_t* cf, const int32_t* P_col, const double* P_val, int cal,
+                      const void* X_final, const double* dL, double* grad_val,
+                      double* grad_omega, double* grad_w, hipStream_t s) {
     constexpr int LPR = lpr_default<double>(K);
     using Sh = Shape<double, K, LPR>;
     const int n = A->n;
@@ -302,6 +438,8 @@ static int adjoint_go(ad_handle h, const ad_csr* A, const void* ckpt, int ce, in
     const size_t panel = (size_t)n * K * sizeof(double);
     const int rblocks = (int)(((int64_t)n + Sh::RPB - 1) / Sh::RPB);
     const int extra = ce - 1;  // recomputed iterates inside one checkpoint segment
+    const bool gs = relax == AD_MULTICOLOR_GS;
+    const int nph = gs ? ncolors : 0;  // phase states of one sweep (the first is its iterate)
 
     WsReq req;
     const size_t o_cnt = req.add(sizeof(int) * (size_t)n);
@@ -315,6 +453,8 @@ static int adjoint_go(ad_handle h, const ad_csr* A, const void* ckpt, int ce, in
     const size_t o_y = req.add(panel);
     const size_t o_xr = req.add(panel * (size_t)(extra > 0 ? extra : 0));
     const size_t o_wp = req.add(sizeof(double) * (size_t)rblocks * (sweeps > 0 ? sweeps : 1));
+    const size_t o_ph = req.add(panel * (size_t)(nph > 1 ? nph : 0));
+    const size_t o_gw = req.add(grad_w ? sizeof(double) * (size_t)rblocks * K : 0);
     int rc = ws_reserve(h, req.off, s);
     if (rc) return rc;
     char* ws = (char*)h->ws;
@@ -328,7 +468,27 @@ static int adjoint_go(ad_handle h, const ad_csr* A, const void* ckpt, int ce, in
     double* Y = (double*)(ws + o_y);
     double* Xr = (double*)(ws + o_xr);
     double* wp = (double*)(ws + o_wp);
+    double* Ph = (double*)(ws + o_ph);
+    double* gwp = (double*)(ws + o_gw);
     const double* av = (const double*)A->val;
+    const size_t pe = (size_t)n * K;  // entries of one panel
+    // one full sweep from xin to xout (GS: its phases through the phase
+    // state buffers, which are free while iterates are recomputed)
+    auto sweep = [&](const double* xin, double* xout) -> int {
+        if (!gs) {
+            LaunchCfg cfg;
+            return launch_jacobi(AD_F64, K, A, xin, xout, omega, h->status, cfg, s);
+        }
+        const double* src = xin;
+        for (int c = 0; c < ncolors; ++c) {
+            double* dst = (c == ncolors - 1) ? xout : Ph + (size_t)(c % 2) * pe;
+            gs_phase_nat_kernel<K, LPR><<<dim3(rblocks), dim3(kBlock), 0, s>>>(
+                n, A->row_ptr, A->col, av, color, c, src, dst, h->status);
+            src = dst;
+        }
+        AD_HIP(hipGetLastError());
+        return AD_OK;
+    };
 
     // column-major index of the pattern
     if ((rc = launch_csc_index(n, nnz, A->row_ptr, A->col, av, cnt, cp, sc, trow, tent, diag,
@@ -341,6 +501,12 @@ static int adjoint_go(ad_handle h, const ad_csr* A, const void* ckpt, int ce, in
     ls_seed_kernel<K, LPR><<<dim3(rblocks), dim3(kBlock), 0, s>>>(n, cp, trow, cf, P_col, P_val,
                                                                    cal, Y, G[0]);
     AD_HIP(hipGetLastError());
+    if (grad_w) {
+        gradw_partials_kernel<K, LPR><<<dim3(rblocks), dim3(kBlock), 0, s>>>(
+            n, (const double*)X_final, cf, P_col, P_val, cal, gwp);
+        sum_columns_kernel<<<dim3(K), dim3(1024), 0, s>>>(gwp, rblocks, K, dL, grad_w);
+        AD_HIP(hipGetLastError());
+    }
     int cur = 0;
     const int nseg = (sweeps + ce - 1) / ce;
     for (int q = nseg - 1; q >= 0; --q) {
@@ -348,40 +514,64 @@ static int adjoint_go(ad_handle h, const ad_csr* A, const void* ckpt, int ce, in
         const int s1 = (s0 + ce < sweeps) ? s0 + ce : sweeps;  // segment sweeps s0 .. s1-1
         const double* xck = (const double*)((const char*)ckpt + (size_t)q * panel);
         // recompute x^{s0+1} .. x^{s1-1}
-        LaunchCfg cfg;
         for (int r = 1; r < s1 - s0; ++r) {
-            const void* src = (r == 1) ? (const void*)xck : (const void*)(Xr + (size_t)(r - 2) * n * K);
-            rc = launch_jacobi(AD_F64, K, A, src, Xr + (size_t)(r - 1) * n * K, omega, h->status, cfg, s);
-            if (rc) return rc;
+            const double* src = (r == 1) ? xck : Xr + (size_t)(r - 2) * pe;
+            if ((rc = sweep(src, Xr + (size_t)(r - 1) * pe))) return rc;
         }
         for (int st = s1 - 1; st >= s0; --st) {
-            const double* xs = (st == s0) ? xck : Xr + (size_t)(st - s0 - 1) * n * K;
-            dinv_kernel<K, LPR><<<dim3(rblocks), dim3(kBlock), 0, s>>>(n, diag, G[cur], Y);
-            adjoint_sweep_kernel<K, LPR><<<dim3(rblocks), dim3(kBlock), 0, s>>>(
-                n, A->row_ptr, A->col, av, cp, trow, tent, diag, xs, Y, G[cur], G[cur ^ 1], omega,
-                grad_val,
-                wp + (size_t)st * rblocks);
+            const double* xs = (st == s0) ? xck : Xr + (size_t)(st - s0 - 1) * pe;
+            if (!gs) {
+                dinv_kernel<K, LPR><<<dim3(rblocks), dim3(kBlock), 0, s>>>(n, diag, G[cur], Y);
+                adjoint_sweep_kernel<K, LPR><<<dim3(rblocks), dim3(kBlock), 0, s>>>(
+                    n, A->row_ptr, A->col, av, cp, trow, tent, diag, xs, Y, G[cur], G[cur ^ 1],
+                    omega, grad_val, wp + (size_t)st * rblocks, nullptr, 0);
+                AD_HIP(hipGetLastError());
+                cur ^= 1;
+                continue;
+            }
+            // phase states: state c is the panel before phase c (state 0 = x^st)
+            for (int c = 1; c < ncolors; ++c) {
+                const double* src = (c == 1) ? xs : Ph + (size_t)(c - 2) * pe;
+                gs_phase_nat_kernel<K, LPR><<<dim3(rblocks), dim3(kBlock), 0, s>>>(
+                    n, A->row_ptr, A->col, av, color, c - 1, src, Ph + (size_t)(c - 1) * pe,
+                    h->status);
+            }
+            for (int c = ncolors - 1; c >= 0; --c) {
+                const double* v = (c == 0) ? xs : Ph + (size_t)(c - 1) * pe;
+                dinv_colour_kernel<K, LPR><<<dim3(rblocks), dim3(kBlock), 0, s>>>(n, diag, color, c,
+                                                                                 G[cur], Y);
+                adjoint_sweep_kernel<K, LPR><<<dim3(rblocks), dim3(kBlock), 0, s>>>(
+                    n, A->row_ptr, A->col, av, cp, trow, tent, diag, v, Y, G[cur], G[cur ^ 1],
+                    1.0, grad_val, wp, color, c);
+                cur ^= 1;
+            }
             AD_HIP(hipGetLastError());
-            cur ^= 1;
         }
     }
-    sum_partials_kernel<<<dim3(1), dim3(1024), 0, s>>>(wp, (int64_t)rblocks * sweeps, grad_omega);
-    AD_HIP(hipGetLastError());
+    if (grad_omega) {
+        if (gs) {
+            if ((rc = launch_fill_f64(grad_omega, 1, 0.0, s))) return rc;
+        } else {
+            sum_partials_kernel<<<dim3(1), dim3(1024), 0, s>>>(wp, (int64_t)rblocks * sweeps,
+                                                               grad_omega);
+            AD_HIP(hipGetLastError());
+        }
+    }
     return AD_OK;
 }
 
-int launch_ls_loss_backward(ad_handle h, int K, const ad_csr* A, const void* ckpt, int ce,
-                            int sweeps, double omega, const double* w, const uint8_t* cf,
-                            const int32_t* P_col, const double* P_val, int cal,
-                            const void* X_final, const double* dL, double* grad_val,
-                            double* grad_omega, hipStream_t s) {
+int launch_ls_loss_backward(ad_handle h, int K, const ad_csr* A, int relax, const int32_t* color,
+                            int ncolors, const void* ckpt, int ce, int sweeps, double omega,
+                            const double* w, const uint8_t* cf, const int32_t* P_col,
+                            const double* P_val, int cal, const void* X_final, const double* dL,
+                            double* grad_val, double* grad_omega, double* grad_w, hipStream_t s) {
     switch (K) {
-        case 2: return adjoint_go<2>(h, A, ckpt, ce, sweeps, omega, w, cf, P_col, P_val, cal, X_final, dL, grad_val, grad_omega, s);
-        case 4: return adjoint_go<4>(h, A, ckpt, ce, sweeps, omega, w, cf, P_col, P_val, cal, X_final, dL, grad_val, grad_omega, s);
-        case 8: return adjoint_go<8>(h, A, ckpt, ce, sweeps, omega, w, cf, P_col, P_val, cal, X_final, dL, grad_val, grad_omega, s);
-        case 16: return adjoint_go<16>(h, A, ckpt, ce, sweeps, omega, w, cf, P_col, P_val, cal, X_final, dL, grad_val, grad_omega, s);
-        case 32: return adjoint_go<32>(h, A, ckpt, ce, sweeps, omega, w, cf, P_col, P_val, cal, X_final, dL, grad_val, grad_omega, s);
-        case 64: return adjoint_go<64>(h, A, ckpt, ce, sweeps, omega, w, cf, P_col, P_val, cal, X_final, dL, grad_val, grad_omega, s);
+        case 2: return adjoint_go<2>(h, A, relax, color, ncolors, ckpt, ce, sweeps, omega, w, cf, P_col, P_val, cal, X_final, dL, grad_val, grad_omega, grad_w, s);
+        case 4: return adjoint_go<4>(h, A, relax, color, ncolors, ckpt, ce, sweeps, omega, w, cf, P_col, P_val, cal, X_final, dL, grad_val, grad_omega, grad_w, s);
+        case 8: return adjoint_go<8>(h, A, relax, color, ncolors, ckpt, ce, sweeps, omega, w, cf, P_col, P_val, cal, X_final, dL, grad_val, grad_omega, grad_w, s);
+        case 16: return adjoint_go<16>(h, A, relax, color, ncolors, ckpt, ce, sweeps, omega, w, cf, P_col, P_val, cal, X_final, dL, grad_val, grad_omega, grad_w, s);
+        case 32: return adjoint_go<32>(h, A, relax, color, ncolors, ckpt, ce, sweeps, omega, w, cf, P_col, P_val, cal, X_final, dL, grad_val, grad_omega, grad_w, s);
+        case 64: return adjoint_go<64>(h, A, relax, color, ncolors, ckpt, ce, sweeps, omega, w, cf, P_col, P_val, cal, X_final, dL, grad_val, grad_omega, grad_w, s);
         default: return AD_EINVAL;
     }
 }

@@ -786,33 +786,70 @@ int relax_algdist_batched(ad_handle h, int32_t nmat, const ad_csr* As, int32_t K
     return rc ? fail(h, rc, "relax_algdist_batched launch") : AD_OK;
 }
 
-int ls_interp_loss_backward(ad_handle h, const ad_csr* A, int32_t K, const void* ckpt,
-                            int32_t ckpt_every, int32_t sweeps, double omega, const double* w,
-                            const uint8_t* cf, const int32_t* P_col, const double* P_val,
-                            int32_t caliber, const void* X_final, const double* dL,
-                            double* grad_val, double* grad_omega, void* stream) {
+static int loss_grad_impl(ad_handle h, const ad_csr* A, int32_t K, int32_t relax,
+                          const int32_t* color, int32_t ncolors, const void* ckpt,
+                          int32_t ckpt_every, int32_t sweeps, double omega, const double* w,
+                          const uint8_t* cf, const int32_t* P_col, const double* P_val,
+                          int32_t caliber, const void* X_final, const double* dL,
+                          double* grad_val, double* grad_omega, double* grad_w, void* stream,
+                          const char* name) {
     if (!h) return AD_EINVAL;
     h->err.clear();
     int rc = check_csr(h, A);
     if (rc) return rc;
     if (A->dtype != AD_F64) return fail(h, AD_EDTYPE, "the backward pass is FP64 only");
     if (!k_ok(K)) return fail(h, AD_EINVAL, "K = %d: must be 2, 4, 8, 16, 32 or 64", K);
+    if (relax != AD_JACOBI && relax != AD_MULTICOLOR_GS)
+        return fail(h, AD_EINVAL, "relax = %d is neither AD_JACOBI nor AD_MULTICOLOR_GS", relax);
+    if (relax == AD_MULTICOLOR_GS && (ncolors < 1 || ncolors > 64 || (A->n > 0 && !color)))
+        return fail(h, AD_EINVAL, "colours: ncolors = %d, color %p", ncolors, (const void*)color);
     if (sweeps < 0) return fail(h, AD_EINVAL, "sweeps = %d < 0", sweeps);
     if (ckpt_every < 1) return fail(h, AD_EINVAL, "ckpt_every = %d < 1", ckpt_every);
     if (caliber < 1 || caliber > 8) return fail(h, AD_ECALIBER, "caliber = %d outside [1, 8]", caliber);
     if (caliber > K)
         return fail(h, AD_ECALIBER, "caliber = %d > K = %d: LS rows would not be unique", caliber, K);
-    if (!grad_omega || !dL) return fail(h, AD_EINVAL, "grad_omega or dL is NULL");
+    if (!dL) return fail(h, AD_EINVAL, "dL is NULL");
     if (A->n > 0 && (!ckpt || !X_final || !cf || !P_col || !P_val || !grad_val))
         return fail(h, AD_EINVAL, "null input or output array");
     if ((rc = check_panel(h, ckpt, "ckpt", A->n)) || (rc = check_panel(h, X_final, "X_final", A->n)))
         return rc;
     AD_HIP(hipSetDevice(h->device));
-    if (A->n == 0) return launch_fill_f64(grad_omega, 1, 0.0, (hipStream_t)stream);
-    TimedScope ts(h, "ls_loss_backward", (hipStream_t)stream);
-    rc = launch_ls_loss_backward(h, K, A, ckpt, ckpt_every, sweeps, omega, w, cf, P_col, P_val,
-                                 caliber, X_final, dL, grad_val, grad_omega, (hipStream_t)stream);
-    return rc ? fail(h, rc, "ls_interp_loss_backward launch") : AD_OK;
+    hipStream_t s = (hipStream_t)stream;
+    if (A->n == 0) {
+        if (grad_omega && (rc = launch_fill_f64(grad_omega, 1, 0.0, s))) return rc;
+        if (grad_w && (rc = launch_fill_f64(grad_w, K, 0.0, s))) return rc;
+        return AD_OK;
+    }
+    TimedScope ts(h, "ls_loss_backward", s);
+    rc = launch_ls_loss_backward(h, K, A, relax, color, ncolors, ckpt, ckpt_every, sweeps, omega, w,
+                                 cf, P_col, P_val, caliber, X_final, dL, grad_val, grad_omega,
+                                 grad_w, s);
+    return rc ? fail(h, rc, "%s launch", name) : AD_OK;
+}
+
+int ls_interp_loss_backward(ad_handle h, const ad_csr* A, int32_t K, const void* ckpt,
+                            int32_t ckpt_every, int32_t sweeps, double omega, const double* w,
+                            const uint8_t* cf, const int32_t* P_col, const double* P_val,
+                            int32_t caliber, const void* X_final, const double* dL,
+                            double* grad_val, double* grad_omega, void* stream) {
+    if (h && !grad_omega) {
+        h->err.clear();
+        return fail(h, AD_EINVAL, "grad_omega is NULL");
+    }
+    return loss_grad_impl(h, A, K, AD_JACOBI, nullptr, 0, ckpt, ckpt_every, sweeps, omega, w, cf,
+                          P_col, P_val, caliber, X_final, dL, grad_val, grad_omega, nullptr, stream,
+                          "ls_interp_loss_backward");
+}
+
+int ls_interp_loss_grad(ad_handle h, const ad_csr* A, int32_t K, int32_t relax,
+                        const int32_t* color, int32_t ncolors, const void* ckpt,
+                        int32_t ckpt_every, int32_t sweeps, double omega, const double* w,
+                        const uint8_t* cf, const int32_t* P_col, const double* P_val,
+                        int32_t caliber, const void* X_final, const double* dL, double* grad_val,
+                        double* grad_omega, double* grad_w, void* stream) {
+    return loss_grad_impl(h, A, K, relax, color, ncolors, ckpt, ckpt_every, sweeps, omega, w, cf,
+                          P_col, P_val, caliber, X_final, dL, grad_val, grad_omega, grad_w, stream,
+                          "ls_interp_loss_grad");
 }
 
 }  // extern "C"

@@ -264,11 +264,11 @@ int run_independent_set(int n, const int* rp, const int* ci, const uint8_t* stro
 int launch_csc_index(int n, int64_t nnz, const int* rp, const int* ci, const double* av, int* cnt,
                      int64_t* cp, int64_t* sc, int* trow, int* tent, double* diag,
                      unsigned* status, hipStream_t s);
-int launch_ls_loss_backward(ad_handle h, int K, const ad_csr* A, const void* ckpt, int ce,
-                            int sweeps, double omega, const double* w, const uint8_t* cf,
-                            const int32_t* P_col, const double* P_val, int cal,
-                            const void* X_final, const double* dL, double* grad_val,
-                            double* grad_omega, hipStream_t s);
+int launch_ls_loss_backward(ad_handle h, int K, const ad_csr* A, int relax, const int32_t* color,
+                            int ncolors, const void* ckpt, int ce, int sweeps, double omega,
+                            const double* w, const uint8_t* cf, const int32_t* P_col,
+                            const double* P_val, int cal, const void* X_final, const double* dL,
+                            double* grad_val, double* grad_omega, double* grad_w, hipStream_t s);
 
 inline int grid_for_tiles(int64_t ntiles, int mode) {
     if (ntiles < 1) ntiles = 1;
