@@ -417,3 +417,71 @@ def ls_loss_grad_gs(A, X0, sweeps: int, color, ncolors: int, w, cf, caliber: int
     Lv = L.oracle_ls_loss_grad_gs(n, _p(rp), _p(ci), _p(va), X0.shape[1], _p(X0), int(sweeps),
                                   _p(col), int(ncolors), _p(w), _p(cf), int(caliber), _p(gv), _p(gw))
     return float(Lv), gv, gw
+
+
+def _sig_galerkin(L):
+    P = C.c_void_p
+    i32 = C.c_int
+    for name, res, args in (
+            ("oracle_galerkin_counts", i32, [i32, P, P, i32, P, P, P, P]),
+            ("oracle_galerkin_fill", None, [i32, P, P, P, i32, P, P, P, P, P, P]),
+            ("oracle_two_grid", i32, [i32, P, P, P, P, i32, i32, P, P, P, P, P, P, i32, P, i32, i32,
+                                      i32, P, P])):
+        fn = getattr(L, name)
+        fn.restype = res
+        fn.argtypes = args
+    return L
+
+
+class CoarseCSR:
+    """A coarse operator: nc rows, CSR with sorted columns, FP64 values."""
+
+    def __init__(self, nc, row_ptr, col, val):
+        self.n = int(nc)
+        self.row_ptr = row_ptr
+        self.col = col
+        self.val = val
+
+    @property
+    def nnz(self):
+        return int(self.row_ptr[-1])
+
+
+def galerkin(A, P_col, P_val, cf) -> CoarseCSR:
+    """A_c = P^T A P (Sec. 5.2), coarse points numbered in fine order."""
+    L = _sig_galerkin(lib())
+    n, rp, ci, va = _csr(A)
+    Pc = np.ascontiguousarray(P_col, dtype=np.int32)
+    Pv = _f64(P_val)
+    cf = np.ascontiguousarray(cf, dtype=np.uint8)
+    cal = Pc.shape[1]
+    cnt = np.empty(max(1, int(cf.astype(bool).sum())), dtype=np.int32)
+    nc = L.oracle_galerkin_counts(n, _p(rp), _p(ci), cal, _p(Pc), _p(Pv), _p(cf), _p(cnt))
+    rpc = np.concatenate([[0], np.cumsum(cnt[:nc], dtype=np.int64)]).astype(np.int32)
+    colc = np.empty(max(1, int(rpc[-1])), dtype=np.int32)
+    valc = np.empty(max(1, int(rpc[-1])))
+    L.oracle_galerkin_fill(n, _p(rp), _p(ci), _p(va), cal, _p(Pc), _p(Pv), _p(cf), _p(rpc), _p(colc),
+                           _p(valc))
+    m = int(rpc[-1])
+    return CoarseCSR(nc, rpc, colc[:m], valc[:m])
+
+
+def two_grid(A, color, ncolors: int, P_col, P_val, cf, Ac: CoarseCSR, E0, iters: int = 100,
+             pre: int = 2, post: int = 2):
+    """Two-grid rate per column of E0 (Sec. 5.2): (rho[K], status, hist),
+    hist[t, k] = ||e^t||_A."""
+    L = _sig_galerkin(lib())
+    n, rp, ci, va = _csr(A)
+    col = np.ascontiguousarray(color, dtype=np.int32)
+    Pc = np.ascontiguousarray(P_col, dtype=np.int32)
+    Pv = _f64(P_val)
+    cf = np.ascontiguousarray(cf, dtype=np.uint8)
+    E0 = _f64(E0)
+    K = E0.shape[1]
+    rho = np.empty(K)
+    hist = np.zeros((iters + 1, K))
+    bad = L.oracle_two_grid(n, _p(rp), _p(ci), _p(va), _p(col), int(ncolors), Pc.shape[1], _p(Pc),
+                            _p(Pv), _p(cf), _p(np.ascontiguousarray(Ac.row_ptr, dtype=np.int32)),
+                            _p(np.ascontiguousarray(Ac.col, dtype=np.int32)), _p(_f64(Ac.val)), K,
+                            _p(E0), int(iters), int(pre), int(post), _p(rho), _p(hist))
+    return rho, int(bad), hist

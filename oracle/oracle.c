@@ -1272,3 +1272,252 @@ int oracle_cr_coarsen(int n, const int *rp, const int *ci, const double *a, cons
     free(u); free(z); free(fm); free(sel); free(strong);
     return stage;
 }
+
+/* ====================================================================== */
+/* Galerkin coarse operator and the two-grid method of Sec. 5.2            */
+/* ====================================================================== */
+
+/* ---------------------------------------------------------------------- */
+/* Interpolation as a matrix.  Row i of P (n x nc) holds P_val[i][q] in    */
+/* column cidx(P_col[i][q]) for P_col[i][q] >= 0, where cidx numbers the C */
+/* points (cf != 0) in increasing fine index.  A_c = P^T A P (the Galerkin */
+/* operator of the two-grid method, Sec. 5.2), formed row by row: coarse   */
+/* row I accumulates p_iI * a_ij * p_jJ into column J, over the fine rows  */
+/* i with p_iI != 0 in increasing i, row i's entries in CSR order and row  */
+/* j's weights in their stored order; each product is formed as            */
+/* (p_iI * a_ij) * p_jJ and added in that order.                           */
+/* ---------------------------------------------------------------------- */
+static int *coarse_index(int n, const unsigned char *cf, int *nc)
+{
+    int *cidx = (int *)malloc(sizeof(int) * (size_t)(n ? n : 1));
+    int i, c = 0;
+    for (i = 0; i < n; ++i) cidx[i] = cf[i] ? c++ : -1;
+    *nc = c;
+    return cidx;
+}
+
+/* P^T as lists: pt[I] .. pt[I+1] index (prow, pval) pairs, by increasing i */
+static void p_transpose(int n, int caliber, const int *Pc, const double *Pv, const int *cidx,
+                        int nc, int **pt_out, int **prow_out, double **pval_out)
+{
+    int *pt = (int *)calloc((size_t)nc + 1, sizeof(int));
+    int *fill = (int *)calloc((size_t)(nc ? nc : 1), sizeof(int));
+    int i, q, m;
+    int *prow;
+    double *pval;
+    for (i = 0; i < n; ++i)
+        for (q = 0; q < caliber; ++q)
+            if (Pc[(int64_t)i * caliber + q] >= 0) ++pt[cidx[Pc[(int64_t)i * caliber + q]] + 1];
+    for (m = 0; m < nc; ++m) pt[m + 1] += pt[m];
+    prow = (int *)malloc(sizeof(int) * (size_t)(pt[nc] ? pt[nc] : 1));
+    pval = (double *)malloc(sizeof(double) * (size_t)(pt[nc] ? pt[nc] : 1));
+    for (i = 0; i < n; ++i)
+        for (q = 0; q < caliber; ++q) {
+            int c = Pc[(int64_t)i * caliber + q];
+            if (c < 0) continue;
+            c = cidx[c];
+            prow[pt[c] + fill[c]] = i;
+            pval[pt[c] + fill[c]] = Pv[(int64_t)i * caliber + q];
+            ++fill[c];
+        }
+    free(fill);
+    *pt_out = pt;
+    *prow_out = prow;
+    *pval_out = pval;
+}
+
+static int cmp_int_asc(const void *a, const void *b)
+{
+    int x = *(const int *)a, y = *(const int *)b;
+    return (x > y) - (x < y);
+}
+
+/* cnt[I] = stored entries of coarse row I (every J reached by a product,
+ * also if the products cancel).  Returns nc. */
+int oracle_galerkin_counts(int n, const int *rp, const int *ci, int caliber, const int *Pc,
+                           const double *Pv, const unsigned char *cf, int *cnt)
+{
+    int nc, I, t, e, q, m;
+    int *cidx = coarse_index(n, cf, &nc);
+    int *pt, *prow, *mark, *list;
+    double *pval;
+    p_transpose(n, caliber, Pc, Pv, cidx, nc, &pt, &prow, &pval);
+    mark = (int *)malloc(sizeof(int) * (size_t)(nc ? nc : 1));
+    list = (int *)malloc(sizeof(int) * (size_t)(nc ? nc : 1));
+    for (I = 0; I < nc; ++I) mark[I] = -1;
+    for (I = 0; I < nc; ++I) {
+        m = 0;
+        for (t = pt[I]; t < pt[I + 1]; ++t) {
+            int i = prow[t];
+            for (e = rp[i]; e < rp[i + 1]; ++e) {
+                int j = ci[e];
+                for (q = 0; q < caliber; ++q) {
+                    int c = Pc[(int64_t)j * caliber + q];
+                    if (c < 0) continue;
+                    c = cidx[c];
+                    if (mark[c] != I) {
+                        mark[c] = I;
+                        list[m++] = c;
+                    }
+                }
+            }
+        }
+        cnt[I] = m;
+    }
+    free(cidx); free(pt); free(prow); free(pval); free(mark); free(list);
+    return nc;
+}
+
+void oracle_galerkin_fill(int n, const int *rp, const int *ci, const double *a, int caliber,
+                          const int *Pc, const double *Pv, const unsigned char *cf, const int *rpc,
+                          int *colc, double *valc)
+{
+    int nc, I, t, e, q, m, r;
+    int *cidx = coarse_index(n, cf, &nc);
+    int *pt, *prow, *mark, *list;
+    double *pval, *acc;
+    p_transpose(n, caliber, Pc, Pv, cidx, nc, &pt, &prow, &pval);
+    mark = (int *)malloc(sizeof(int) * (size_t)(nc ? nc : 1));
+    list = (int *)malloc(sizeof(int) * (size_t)(nc ? nc : 1));
+    acc = (double *)malloc(sizeof(double) * (size_t)(nc ? nc : 1));
+    for (I = 0; I < nc; ++I) mark[I] = -1;
+    for (I = 0; I < nc; ++I) {
+        m = 0;
+        for (t = pt[I]; t < pt[I + 1]; ++t) {
+            int i = prow[t];
+            double piI = pval[t];
+            for (e = rp[i]; e < rp[i + 1]; ++e) {
+                int j = ci[e];
+                double pa = piI * a[e];
+                for (q = 0; q < caliber; ++q) {
+                    int c = Pc[(int64_t)j * caliber + q];
+                    double prod;
+                    if (c < 0) continue;
+                    c = cidx[c];
+                    prod = pa * Pv[(int64_t)j * caliber + q];
+                    if (mark[c] != I) {
+                        mark[c] = I;
+                        list[m++] = c;
+                        acc[c] = prod;
+                    } else {
+                        acc[c] = acc[c] + prod;
+                    }
+                }
+            }
+        }
+        qsort(list, (size_t)m, sizeof(int), cmp_int_asc);
+        for (r = 0; r < m; ++r) {
+            colc[rpc[I] + r] = list[r];
+            valc[rpc[I] + r] = acc[list[r]];
+        }
+    }
+    free(cidx); free(pt); free(prow); free(pval); free(mark); free(list); free(acc);
+}
+
+/* ---------------------------------------------------------------------- */
+/* Two-grid method of Sec. 5.2 on the homogeneous system A e = 0: `pre`    */
+/* colour-phase Gauss-Seidel sweeps, the coarse-grid correction            */
+/* e <- e - P A_c^{-1} P^T A e with the coarse system solved directly      */
+/* (dense Cholesky factorisation of A_c), `post` sweeps; `iters` cycles    */
+/* from the K columns of E0.  rho[k] = ||e^iters||_A / ||e^(iters-1)||_A   */
+/* for column k; hist (may be NULL, (iters + 1) x K) receives ||e^t||_A.   */
+/* Returns 0, or 1 if A_c has a non-positive pivot.                        */
+/* ---------------------------------------------------------------------- */
+static double a_norm(int n, const int *rp, const int *ci, const double *a, int K,
+                     const double *E, int k)
+{
+    double s = 0.0;
+    int i, e;
+    for (i = 0; i < n; ++i) {
+        double y = 0.0;
+        for (e = rp[i]; e < rp[i + 1]; ++e) y += a[e] * E[(int64_t)ci[e] * K + k];
+        s += E[(int64_t)i * K + k] * y;
+    }
+    return sqrt(s > 0.0 ? s : 0.0);
+}
+
+int oracle_two_grid(int n, const int *rp, const int *ci, const double *a, const int *color,
+                    int ncolors, int caliber, const int *Pc, const double *Pv,
+                    const unsigned char *cf, const int *rpc, const int *colc, const double *valc,
+                    int K, const double *E0, int iters, int pre, int post, double *rho,
+                    double *hist)
+{
+    int nc, i, j, k, e, q, it, I;
+    int *cidx = coarse_index(n, cf, &nc);
+    double *L = (double *)calloc((size_t)nc * (nc ? nc : 1), sizeof(double));
+    double *E = (double *)malloc(sizeof(double) * (size_t)n * K);
+    double *r = (double *)malloc(sizeof(double) * (size_t)n);
+    double *rc = (double *)malloc(sizeof(double) * (size_t)(nc ? nc : 1));
+    double *prev = (double *)malloc(sizeof(double) * K);
+    int bad = 0;
+    memcpy(E, E0, sizeof(double) * (size_t)n * K);
+    /* dense A_c, then its Cholesky factor in the lower triangle */
+    for (I = 0; I < nc; ++I)
+        for (e = rpc[I]; e < rpc[I + 1]; ++e) L[(int64_t)I * nc + colc[e]] = valc[e];
+    for (j = 0; j < nc && !bad; ++j) {
+        double d = L[(int64_t)j * nc + j];
+        for (q = 0; q < j; ++q) d -= L[(int64_t)j * nc + q] * L[(int64_t)j * nc + q];
+        if (!(d > 0.0)) {
+            bad = 1;
+            break;
+        }
+        d = sqrt(d);
+        L[(int64_t)j * nc + j] = d;
+        for (i = j + 1; i < nc; ++i) {
+            double s = L[(int64_t)i * nc + j];
+            for (q = 0; q < j; ++q) s -= L[(int64_t)i * nc + q] * L[(int64_t)j * nc + q];
+            L[(int64_t)i * nc + j] = s / d;
+        }
+    }
+    for (k = 0; k < K; ++k) {
+        rho[k] = 0.0;
+        prev[k] = 0.0;
+        if (hist) hist[k] = a_norm(n, rp, ci, a, K, E, k);
+    }
+    for (it = 0; it < iters && !bad; ++it) {
+        oracle_color_gs(n, rp, ci, a, K, color, ncolors, pre, E);
+        for (k = 0; k < K; ++k) {
+            /* r = -A e (b = 0), r_c = P^T r */
+            for (i = 0; i < n; ++i) {
+                double y = 0.0;
+                for (e = rp[i]; e < rp[i + 1]; ++e) y += a[e] * E[(int64_t)ci[e] * K + k];
+                r[i] = -y;
+            }
+            for (I = 0; I < nc; ++I) rc[I] = 0.0;
+            for (i = 0; i < n; ++i)
+                for (q = 0; q < caliber; ++q) {
+                    int c = Pc[(int64_t)i * caliber + q];
+                    if (c >= 0) rc[cidx[c]] += Pv[(int64_t)i * caliber + q] * r[i];
+                }
+            /* A_c e_c = r_c: L y = r_c, then L^T e_c = y */
+            for (I = 0; I < nc; ++I) {
+                double s = rc[I];
+                for (q = 0; q < I; ++q) s -= L[(int64_t)I * nc + q] * rc[q];
+                rc[I] = s / L[(int64_t)I * nc + I];
+            }
+            for (I = nc - 1; I >= 0; --I) {
+                double s = rc[I];
+                for (q = I + 1; q < nc; ++q) s -= L[(int64_t)q * nc + I] * rc[q];
+                rc[I] = s / L[(int64_t)I * nc + I];
+            }
+            /* e += P e_c */
+            for (i = 0; i < n; ++i) {
+                double s = 0.0;
+                for (q = 0; q < caliber; ++q) {
+                    int c = Pc[(int64_t)i * caliber + q];
+                    if (c >= 0) s += Pv[(int64_t)i * caliber + q] * rc[cidx[c]];
+                }
+                E[(int64_t)i * K + k] += s;
+            }
+        }
+        oracle_color_gs(n, rp, ci, a, K, color, ncolors, post, E);
+        for (k = 0; k < K; ++k) {
+            double an = a_norm(n, rp, ci, a, K, E, k);
+            if (it == iters - 1) rho[k] = prev[k] > 0.0 ? an / prev[k] : 0.0;
+            prev[k] = an;
+            if (hist) hist[(int64_t)(it + 1) * K + k] = an;
+        }
+    }
+    free(cidx); free(L); free(E); free(r); free(rc); free(prev);
+    return bad;
+}
