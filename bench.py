@@ -98,6 +98,11 @@ def parse(argv=None):
                     help="time the compatible-relaxation coarsening leg (the default unless "
                          "--size is given)")
     ap.add_argument("--no-cr", action="store_true", help="skip the coarsening leg")
+    ap.add_argument("--quality", action="store_true",
+                    help="run the two-grid quality leg (the whole setup, Galerkin operator and "
+                         "two-grid rate at the paper's grid sizes; the default unless --size is "
+                         "given)")
+    ap.add_argument("--no-quality", action="store_true", help="skip the two-grid quality leg")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one 1 GiB device-to-device copy (a kernel of known traffic "
                          "for scaling hardware byte counters)")
@@ -107,6 +112,7 @@ def parse(argv=None):
     a.adjoint = not a.no_adjoint and (a.adjoint or a.size is None)
     a.longrange = not a.no_longrange and (a.longrange or a.size is None)
     a.cr = not a.no_cr and (a.cr or a.size is None)
+    a.quality = not a.no_quality and (a.quality or a.size is None)
     return a
 
 
@@ -731,6 +737,74 @@ def cr_leg(args, torch, ad, W, flush):
     return res
 
 
+def quality_leg(args, torch, ad, W, flush):
+    """The whole two-level setup on the GPU and the two-grid quality of
+    Sec. 5.2: K = 8 test vectors with 40 colour-phase sweeps, distances,
+    CR coarsening (theta 0.5, nu 5, delta 0.7), LS interpolation (caliber
+    4), A_c = P^T A P and the two-grid rate (100 cycles, 2 + 2 sweeps, four
+    random starts), on the 7-point rotated anisotropy and the 9-point one at
+    the paper's sizes; and the Galerkin product on the full 2048^2 operator
+    with the CR coarse grid and LS rows of the step's test vectors."""
+    import math
+    res = {"cases": []}
+    for name, gen, N in (("fd7 eps 1e-2 alpha pi/4", lambda N: W.rotated_anisotropic_7pt(N, 1e-2, math.pi / 4), 64),
+                         ("fd7 eps 1e-2 alpha pi/4", lambda N: W.rotated_anisotropic_7pt(N, 1e-2, math.pi / 4), 128),
+                         ("9pt eps 1e-3 alpha pi/6", lambda N: W.rotated_anisotropic_9pt(N, 1e-3, math.pi / 6), 128)):
+        Ah = gen(N)
+        A = ad.Csr.from_host(Ah, dtype=torch.float64)
+        color = torch.as_tensor(W.red_black((N, N)), device="cuda")
+        t0 = time.perf_counter()
+        X = ad.setup_testvectors(A, 8, seed=3, relax="gs", sweeps=40, color=color, ncolors=2)
+        mu = ad.algebraic_distance(A, X)
+        cf, rho_cr, nc_cr = ad.cr_coarsening(A, color, 2, mu, 0.5, seed=1)
+        Pc, Pv, ls, st = ad.ls_interp(A, X, cf, mu, 4)
+        Ac = ad.galerkin(A, Pc, Pv, cf)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        E0 = torch.rand((A.n, 4), dtype=torch.float64, device="cuda", generator=torch.Generator(
+            device="cuda").manual_seed(5)) * 2 - 1
+        rho, hist = ad.two_grid_rate(A, color, 2, Pc, Pv, cf, Ac, E0, iters=100)
+        t2 = time.perf_counter()
+        res["cases"].append({
+            "operator": "%s, %d^2" % (name, N), "rows": A.n, "coarse": Ac.n,
+            "cr_stages": len(rho_cr) - 1, "rho_f": [round(r, 4) for r in rho_cr],
+            "two_grid_rho": [round(float(r), 4) for r in rho],
+            "gamma_o": round((A.nnz + Ac.nnz) / A.nnz, 3), "gamma_g": round(Ac.n / A.n, 3),
+            "setup_ms": round((t1 - t0) * 1e3, 1), "two_grid_100_cycles_ms": round((t2 - t1) * 1e3, 1)})
+        log("two-grid %s %d^2: rho %s" % (name, N, np.round(rho, 4)))
+        del A, X, mu, cf, Pc, Pv, Ac, E0
+    # the Galerkin product at full size
+    wl = W.workload(2, "f32", size=args.size)
+    A = ad.Csr.from_host(wl.A, dtype=torch.float32)
+    color = torch.as_tensor(wl.color, device="cuda")
+    X = ad.setup_testvectors(A, wl.K, seed=wl.tv_seed, relax="gs", sweeps=wl.sweeps, color=color,
+                             ncolors=wl.ncolors)
+    mu = ad.algebraic_distance(A, X)
+    cf, _, _ = ad.cr_coarsening(A, color, 2, mu, wl.theta, seed=1)
+    Pc, Pv, ls, st = ad.ls_interp(A, X, cf, mu, wl.caliber)
+    Ac = ad.galerkin(A, Pc, Pv, cf)
+    torch.cuda.synchronize()
+    times = []
+    for _ in range(3):
+        flush()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ad.galerkin(A, Pc, Pv, cf)
+        torch.cuda.synchronize()
+        times.append((time.perf_counter() - t0) * 1e3)
+    ms = float(np.median(times))
+    res["galerkin_full"] = {"workload": wl.name + ", CR coarse grid, LS rows caliber 4",
+                            "rows": wl.A.n, "coarse_rows": Ac.n, "coarse_nnz": Ac.nnz,
+                            "gamma_o": round((wl.A.nnz + Ac.nnz) / wl.A.nnz, 3),
+                            "ms": round(ms, 3), "coarse_rows_per_s": round(Ac.n / (ms * 1e-3), 1),
+                            "timing": "host clock around the two synchronous calls (rows, cols), "
+                                      "median of 3"}
+    res["device_status_bits"] = ad.status(clear=True)
+    del A, X, mu, cf, Pc, Pv, Ac
+    torch.cuda.empty_cache()
+    return res
+
+
 # ------------------------------------------------------------------ CPU baseline
 def cpu_model():
     try:
@@ -954,6 +1028,9 @@ def main():
     if args.cr:
         log("coarsening leg")
         out["cr_coarsening"] = cr_leg(args, torch, ad, W, flush)
+    if args.quality:
+        log("two-grid quality leg")
+        out["two_grid"] = quality_leg(args, torch, ad, W, flush)
     if not args.no_cpu_baseline:
         idx = WORKLOAD_INDEX[args.workload]
         side = args.cpu_sample or args.size or {1: 32, 2: 2048, 3: 160}[idx]

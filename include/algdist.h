@@ -77,6 +77,7 @@ typedef enum {
 #define AD_STAT_CSR_NODIAG  0x20u /* csr_validate: a row has no diagonal entry */
 #define AD_STAT_SEARCH_CAP  0x40u /* ls_interp_search: an F row had more than 64 candidates (row left empty, status 4) */
 #define AD_STAT_PATTERN     0x80u /* power_graph_cols: row_ptr_d does not fit A^d's row lengths (rows cut) */
+#define AD_STAT_BAD_INTERP  0x100u /* galerkin_*: an interpolation column names a point that is not coarse (ignored) */
 
 typedef struct ad_handle_s *ad_handle;
 
@@ -525,6 +526,52 @@ int cr_coarsening(ad_handle h, const ad_csr *A, const int32_t *color, int32_t nc
                   const void *mu, double theta, int32_t nu, double delta, int32_t max_stages,
                   uint64_t seed, uint8_t *cf, double *rho, int64_t *ncoarse, int32_t *nstages,
                   void *stream);
+
+/* ------------------------------------------------------------------ */
+/* Galerkin coarse operator and the two-grid method (Sec. 5.2).          */
+/* Synchronous; the calls allocate their own device buffers.            */
+/* ------------------------------------------------------------------ */
+
+/* Interpolation P (n x nc) in the layout ls_interp / ls_interp_search
+ * write: P_col (device, n x caliber int32, fine indices of C points, -1
+ * padded; a C row names itself), P_val (device, n x caliber FP64).  The C
+ * points (cf[i] != 0) are numbered in increasing fine index.  A column
+ * naming a non-C point or an index outside [0, n) is ignored and sets
+ * AD_STAT_BAD_INTERP.
+ *
+ * A_c = P^T A P.  Coarse row I accumulates (p_iI * a_ij) * p_jJ over the
+ * fine rows i of column I of P in increasing i (then stored slot), row i's
+ * entries in CSR order and row j's slots in order, each product and sum
+ * rounded separately: the coefficients are those of that plain loop,
+ * bit for bit.  Every column reached by a product is stored (also when the
+ * products cancel), sorted ascending.
+ *
+ * galerkin_rows: *nc (host) = number of C points; row_ptr_c (device, room
+ * for n + 1 int32) receives nc + 1 row pointers; *nnz_c (host) the number
+ * of entries.  AD_EUNSUPPORTED when a coarse row has more than 64
+ * contributing fine rows or more than 2048 products, or nnz_c > 2^31 - 1.
+ * galerkin_cols then writes col_c (nnz_c int32) and val_c (nnz_c FP64). */
+int galerkin_rows(ad_handle h, const ad_csr *A, int32_t caliber, const int32_t *P_col,
+                  const double *P_val, const uint8_t *cf, int32_t *nc, int32_t *row_ptr_c,
+                  int64_t *nnz_c, void *stream);
+int galerkin_cols(ad_handle h, const ad_csr *A, int32_t caliber, const int32_t *P_col,
+                  const double *P_val, const uint8_t *cf, int32_t nc, const int32_t *row_ptr_c,
+                  int32_t *col_c, double *val_c, void *stream);
+
+/* The two-grid method of Sec. 5.2 on the homogeneous system A e = 0, for
+ * the K columns of E0 (device, n x K FP64, e.g. random starts) at once:
+ * per cycle `pre` colour-phase Gauss-Seidel sweeps (setup_testvectors'
+ * rule; color/ncolors as there), e <- e - P A_c^{-1} P^T A e with A_c
+ * (nc rows, from galerkin_*) factored once by dense Cholesky (the direct
+ * coarse solve; nc <= 8192), `post` sweeps.  hist (host, may be NULL,
+ * (iters + 1) x K) receives ||e^t||_A; rho (host, K) = ||e^iters||_A /
+ * ||e^(iters-1)||_A.  FP64 only.  AD_ESTRUCT if A_c is not positive
+ * definite.  The paper's settings: iters = 100, pre = post = 2. */
+int two_grid_rate(ad_handle h, const ad_csr *A, const int32_t *color, int32_t ncolors,
+                  int32_t caliber, const int32_t *P_col, const double *P_val, const uint8_t *cf,
+                  int32_t nc, const int32_t *row_ptr_c, const int32_t *col_c, const double *val_c,
+                  int32_t K, const void *E0, int32_t iters, int32_t pre, int32_t post,
+                  double *hist, double *rho, void *stream);
 
 #ifdef __cplusplus
 }

@@ -39,6 +39,7 @@ STAT_CSR_COLS = 0x10
 STAT_CSR_NODIAG = 0x20
 STAT_SEARCH_CAP = 0x40
 STAT_PATTERN = 0x80
+STAT_BAD_INTERP = 0x100
 
 STATUS_NAMES = {0: "AD_OK", 1: "AD_EINVAL", 2: "AD_EDTYPE", 3: "AD_ECALIBER", 4: "AD_ESTRUCT",
                 5: "AD_EDEVICE", 6: "AD_ENOMEM", 7: "AD_EUNSUPPORTED"}
@@ -86,6 +87,11 @@ _SIGS = {
                                        _P, _P, _P, _P, _P]),
     "ls_interp_loss_grad": (_i32, [_P, _CSRP, _i32, _i32, _P, _i32, _P, _i32, _i32, _f64, _P, _P,
                                    _P, _P, _i32, _P, _P, _P, _P, _P, _P]),
+    "galerkin_rows": (_i32, [_P, _CSRP, _i32, _P, _P, _P, C.POINTER(C.c_int32), _P,
+                             C.POINTER(C.c_int64), _P]),
+    "galerkin_cols": (_i32, [_P, _CSRP, _i32, _P, _P, _P, _i32, _P, _P, _P, _P]),
+    "two_grid_rate": (_i32, [_P, _CSRP, _P, _i32, _i32, _P, _P, _P, _i32, _P, _P, _P, _i32, _P,
+                             _i32, _i32, _i32, _P, _P, _P]),
     "cr_rate": (_i32, [_P, _CSRP, _P, _i32, _P, _i32, _P, C.POINTER(C.c_double), _P, _P]),
     "cr_candidates": (_i32, [_P, _i32, _i32, _P, _P, _f64, _P, _P]),
     "independent_set": (_i32, [_P, _CSRP, _P, _P, _u64, _P, C.POINTER(C.c_int64), _P]),
@@ -632,3 +638,53 @@ def cr_coarsening(A: Csr, color: torch.Tensor, ncolors: int, mu: torch.Tensor, t
                               C.byref(ns), _stream(stream)), h, "cr_coarsening")
     k = ns.value + 1
     return cf, list(rho)[:k], list(nc)[:k]
+
+
+# ------------------------------------------------------------------ Galerkin operator, two-grid
+class CoarseOperator:
+    """A_c = P^T A P on the device: nc rows, CSR (row_ptr, col), FP64 val."""
+
+    def __init__(self, nc, row_ptr, col, val):
+        self.n = int(nc)
+        self.row_ptr = row_ptr
+        self.col = col
+        self.val = val
+
+    @property
+    def nnz(self):
+        return int(self.col.numel())
+
+
+def galerkin(A: Csr, P_col: torch.Tensor, P_val: torch.Tensor, cf: torch.Tensor,
+             stream=None) -> CoarseOperator:
+    """A_c = P^T A P (galerkin_rows, then galerkin_cols)."""
+    h = handle(A.device.index)
+    cal = P_col.shape[1]
+    rp = torch.empty(A.n + 1, dtype=torch.int32, device=A.device)
+    nc = C.c_int32(0)
+    nnz = C.c_int64(0)
+    _check(_lib.galerkin_rows(h, A.ref(), cal, _ptr(P_col), _ptr(P_val), _ptr(cf), C.byref(nc),
+                              _ptr(rp), C.byref(nnz), _stream(stream)), h, "galerkin_rows")
+    rp = rp[:nc.value + 1].clone()
+    col = torch.empty(int(nnz.value), dtype=torch.int32, device=A.device)
+    val = torch.empty(int(nnz.value), dtype=torch.float64, device=A.device)
+    _check(_lib.galerkin_cols(h, A.ref(), cal, _ptr(P_col), _ptr(P_val), _ptr(cf), nc.value,
+                              _ptr(rp), _ptr(col), _ptr(val), _stream(stream)), h, "galerkin_cols")
+    return CoarseOperator(nc.value, rp, col, val)
+
+
+def two_grid_rate(A: Csr, color: torch.Tensor, ncolors: int, P_col: torch.Tensor,
+                  P_val: torch.Tensor, cf: torch.Tensor, Ac: CoarseOperator, E0: torch.Tensor,
+                  iters: int = 100, pre: int = 2, post: int = 2, stream=None):
+    """Two-grid rate per column of E0 (two_grid_rate): (rho[K], hist[iters+1, K])."""
+    import numpy as _np
+    h = handle(A.device.index)
+    K = E0.shape[1]
+    rho = _np.empty(K)
+    hist = _np.empty((iters + 1, K))
+    _check(_lib.two_grid_rate(h, A.ref(), _ptr(color), int(ncolors), P_col.shape[1], _ptr(P_col),
+                              _ptr(P_val), _ptr(cf), Ac.n, _ptr(Ac.row_ptr), _ptr(Ac.col),
+                              _ptr(Ac.val), K, _ptr(E0), int(iters), int(pre), int(post),
+                              hist.ctypes.data_as(C.c_void_p), rho.ctypes.data_as(C.c_void_p),
+                              _stream(stream)), h, "two_grid_rate")
+    return rho, hist

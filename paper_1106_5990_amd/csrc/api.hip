@@ -1095,3 +1095,184 @@ int cr_coarsening(ad_handle h, const ad_csr* A, const int32_t* color, int32_t nc
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------- Galerkin operator, two-grid
+namespace {
+
+int check_interp(ad_handle h, const ad_csr* A, int32_t caliber, const int32_t* P_col,
+                 const double* P_val, const uint8_t* cf) {
+    int rc = check_csr(h, A);
+    if (rc) return rc;
+    if (caliber < 1 || caliber > 64) return fail(h, AD_ECALIBER, "caliber = %d outside [1, 64]", caliber);
+    if (A->n > 0 && (!P_col || !P_val || !cf)) return fail(h, AD_EINVAL, "P_col, P_val or cf is NULL");
+    if ((int64_t)A->n * caliber > INT32_MAX)
+        return fail(h, AD_EUNSUPPORTED, "n * caliber beyond int32");
+    return AD_OK;
+}
+
+struct GalerkinCtx {
+    DevBufs b;
+    GalerkinIn g;
+    GalerkinWork w;
+    bool ok = false;
+    GalerkinCtx(const ad_csr* A, int32_t caliber, const int32_t* P_col, const double* P_val,
+                const uint8_t* cf) {
+        const int n = A->n;
+        g = GalerkinIn{n, A->row_ptr, A->col, A->val, A->dtype, caliber, P_col, P_val, cf};
+        w.flags = b.get<int>(n);
+        w.scan = b.get<int64_t>((size_t)n + 1);
+        w.scan_tmp = (int64_t*)b.get<char>((size_t)scan_workspace_bytes(n));
+        w.cidx = b.get<int>(n);
+        w.cnt = b.get<int>(n);
+        w.pt = b.get<int64_t>((size_t)n + 1);
+        w.ptkey = b.get<int64_t>((size_t)n * caliber);
+        w.maxslots = b.get<int>(1);
+        ok = w.flags && w.scan && w.scan_tmp && w.cidx && w.cnt && w.pt && w.ptkey && w.maxslots;
+    }
+};
+
+}  // namespace
+
+extern "C" {
+
+int galerkin_rows(ad_handle h, const ad_csr* A, int32_t caliber, const int32_t* P_col,
+                  const double* P_val, const uint8_t* cf, int32_t* nc, int32_t* row_ptr_c,
+                  int64_t* nnz_c, void* stream) {
+    if (!h) return AD_EINVAL;
+    h->err.clear();
+    int rc = check_interp(h, A, caliber, P_col, P_val, cf);
+    if (rc) return rc;
+    if (!nc || !nnz_c || !row_ptr_c) return fail(h, AD_EINVAL, "nc, row_ptr_c or nnz_c is NULL");
+    *nc = 0;
+    *nnz_c = 0;
+    AD_HIP(hipSetDevice(h->device));
+    hipStream_t s = (hipStream_t)stream;
+    if (A->n == 0) return launch_fill_i32(row_ptr_c, 1, 0, s);
+    GalerkinCtx c(A, caliber, P_col, P_val, cf);
+    if (!c.ok) return fail(h, AD_ENOMEM, "galerkin_rows buffers");
+    int ncl = 0;
+    TimedScope ts(h, "galerkin", s);
+    if ((rc = galerkin_prepare(c.g, c.w, &ncl, s)) ||
+        (rc = galerkin_transpose(c.g, c.w, ncl, h->status, s)))
+        return fail(h, rc, "galerkin_rows: coarse numbering / transpose");
+    rc = galerkin_rows_run(c.g, c.w, ncl, row_ptr_c, nnz_c, s);
+    if (rc == AD_EUNSUPPORTED)
+        return fail(h, rc, "galerkin_rows: a coarse row has more than 64 contributing fine rows or "
+                           "2048 products, or the operator has more than 2^31 entries");
+    if (rc) return fail(h, rc, "galerkin_rows");
+    *nc = ncl;
+    return AD_OK;
+}
+
+int galerkin_cols(ad_handle h, const ad_csr* A, int32_t caliber, const int32_t* P_col,
+                  const double* P_val, const uint8_t* cf, int32_t nc, const int32_t* row_ptr_c,
+                  int32_t* col_c, double* val_c, void* stream) {
+    if (!h) return AD_EINVAL;
+    h->err.clear();
+    int rc = check_interp(h, A, caliber, P_col, P_val, cf);
+    if (rc) return rc;
+    if (nc < 0 || nc > A->n) return fail(h, AD_EINVAL, "nc = %d", nc);
+    if (nc > 0 && (!row_ptr_c || !col_c || !val_c))
+        return fail(h, AD_EINVAL, "row_ptr_c, col_c or val_c is NULL");
+    if (nc == 0) return AD_OK;
+    AD_HIP(hipSetDevice(h->device));
+    hipStream_t s = (hipStream_t)stream;
+    GalerkinCtx c(A, caliber, P_col, P_val, cf);
+    if (!c.ok) return fail(h, AD_ENOMEM, "galerkin_cols buffers");
+    int ncl = 0;
+    TimedScope ts(h, "galerkin", s);
+    if ((rc = galerkin_prepare(c.g, c.w, &ncl, s)) ||
+        (rc = galerkin_transpose(c.g, c.w, ncl, h->status, s)))
+        return fail(h, rc, "galerkin_cols: coarse numbering / transpose");
+    if (ncl != nc) return fail(h, AD_EINVAL, "nc = %d but cf marks %d coarse points", nc, ncl);
+    if ((rc = galerkin_cols_run(c.g, c.w, nc, row_ptr_c, col_c, val_c, s)))
+        return fail(h, rc, "galerkin_cols");
+    AD_HIP(hipStreamSynchronize(s));
+    return AD_OK;
+}
+
+int two_grid_rate(ad_handle h, const ad_csr* A, const int32_t* color, int32_t ncolors,
+                  int32_t caliber, const int32_t* P_col, const double* P_val, const uint8_t* cf,
+                  int32_t nc, const int32_t* row_ptr_c, const int32_t* col_c, const double* val_c,
+                  int32_t K, const void* E0, int32_t iters, int32_t pre, int32_t post,
+                  double* hist, double* rho, void* stream) {
+    if (!h) return AD_EINVAL;
+    h->err.clear();
+    int rc = check_interp(h, A, caliber, P_col, P_val, cf);
+    if (rc) return rc;
+    if (A->dtype != AD_F64) return fail(h, AD_EDTYPE, "the two-grid method runs in FP64");
+    if (!k_ok(K)) return fail(h, AD_EINVAL, "K = %d: must be 2, 4, 8, 16, 32 or 64", K);
+    if (ncolors < 1 || ncolors > 64 || (A->n > 0 && !color))
+        return fail(h, AD_EINVAL, "colours: ncolors = %d, color %p", ncolors, (const void*)color);
+    if (iters < 1 || pre < 0 || post < 0)
+        return fail(h, AD_EINVAL, "iters = %d, pre = %d, post = %d", iters, pre, post);
+    if (!rho) return fail(h, AD_EINVAL, "rho is NULL");
+    if (nc < 1 || nc > kCoarseSolveMax || nc > A->n)
+        return fail(h, AD_EUNSUPPORTED, "nc = %d outside [1, %d] (dense coarse solve)", nc,
+                    kCoarseSolveMax);
+    if (!row_ptr_c || !col_c || !val_c) return fail(h, AD_EINVAL, "coarse operator is NULL");
+    if ((rc = check_panel(h, E0, "E0", A->n))) return rc;
+    AD_HIP(hipSetDevice(h->device));
+    hipStream_t s = (hipStream_t)stream;
+    const int n = A->n;
+    const size_t panel = (size_t)n * K;
+    GalerkinCtx c(A, caliber, P_col, P_val, cf);
+    double* E[2] = {c.b.get<double>(panel), c.b.get<double>(panel)};
+    double* R = c.b.get<double>(panel);
+    double* Rc = c.b.get<double>((size_t)nc * K);
+    double* L = c.b.get<double>((size_t)nc * nc);
+    double* Li = c.b.get<double>((size_t)nc * nc);
+    double* LiT = c.b.get<double>((size_t)nc * nc);
+    int* bad = c.b.get<int>(1);
+    const int nb = two_grid_blocks(n, K);
+    double* part = c.b.get<double>((size_t)nb * K);
+    double* hd = c.b.get<double>((size_t)(iters + 1) * K);
+    if (!c.ok || !E[0] || !E[1] || !R || !Rc || !L || !Li || !LiT || !bad || !part || !hd)
+        return fail(h, AD_ENOMEM, "two_grid_rate buffers");
+    int ncl = 0;
+    if ((rc = galerkin_prepare(c.g, c.w, &ncl, s)) ||
+        (rc = galerkin_transpose(c.g, c.w, ncl, h->status, s)))
+        return fail(h, rc, "two_grid_rate: coarse numbering / transpose");
+    if (ncl != nc) return fail(h, AD_EINVAL, "nc = %d but cf marks %d coarse points", nc, ncl);
+    {
+        TimedScope ts(h, "coarse_factor", s);
+        if ((rc = coarse_factor(nc, row_ptr_c, col_c, val_c, L, Li, LiT, bad, s)))
+            return fail(h, rc, "two_grid_rate: coarse factorisation");
+    }
+    int hbad = 0;
+    AD_HIP(hipMemcpyAsync(&hbad, bad, sizeof hbad, hipMemcpyDeviceToHost, s));
+    AD_HIP(hipStreamSynchronize(s));
+    if (hbad) return fail(h, AD_ESTRUCT, "two_grid_rate: the coarse operator is not positive definite");
+    AD_HIP(hipMemcpyAsync(E[0], E0, panel * sizeof(double), hipMemcpyDeviceToDevice, s));
+    int cur = 0;
+    if ((rc = a_norms_sq(c.g, K, E[0], part, hd, s))) return fail(h, rc, "two_grid_rate: norms");
+    for (int it = 0; it < iters; ++it) {
+        TimedScope ts(h, "two_grid_cycle", s);
+        if (pre > 0) {
+            if ((rc = gs_sweeps(h, A, K, 0, E[cur], pre, color, ncolors, E[cur ^ 1], nullptr, 0, s)))
+                return fail(h, rc, "two_grid_rate: pre-smoothing");
+            cur ^= 1;
+        }
+        if ((rc = coarse_correction(c.g, c.w, nc, K, Li, LiT, E[cur], R, Rc, s)))
+            return fail(h, rc, "two_grid_rate: coarse-grid correction");
+        if (post > 0) {
+            if ((rc = gs_sweeps(h, A, K, 0, E[cur], post, color, ncolors, E[cur ^ 1], nullptr, 0, s)))
+                return fail(h, rc, "two_grid_rate: post-smoothing");
+            cur ^= 1;
+        }
+        if ((rc = a_norms_sq(c.g, K, E[cur], part, hd + (size_t)(it + 1) * K, s)))
+            return fail(h, rc, "two_grid_rate: norms");
+    }
+    std::vector<double> hh((size_t)(iters + 1) * K);
+    AD_HIP(hipMemcpyAsync(hh.data(), hd, hh.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+    AD_HIP(hipStreamSynchronize(s));
+    for (double& v : hh) v = sqrt(v > 0.0 ? v : 0.0);
+    for (int k = 0; k < K; ++k) {
+        const double a = hh[(size_t)iters * K + k], b = hh[(size_t)(iters - 1) * K + k];
+        rho[k] = b > 0.0 ? a / b : 0.0;
+    }
+    if (hist) memcpy(hist, hh.data(), hh.size() * sizeof(double));
+    return AD_OK;
+}
+
+}  // extern "C"

@@ -146,6 +146,7 @@ int launch_fill_i32(int32_t* p, int64_t m, int32_t v, hipStream_t s);
 // scan_workspace_bytes(m) bytes
 int64_t scan_workspace_bytes(int64_t m);
 int launch_excl_scan(const int32_t* cnt, int64_t m, int64_t* out, int64_t* tmp, hipStream_t s);
+int launch_narrow_i64(const int64_t* a, int64_t m, int32_t* b, hipStream_t s);
 
 // ---- relax.hip
 int launch_tv_init(int dtype, int64_t row0, int64_t nrows, int K, uint64_t seed, void* X,
@@ -259,6 +260,44 @@ int run_independent_set(int n, const int* rp, const int* ci, const uint8_t* stro
                         const int64_t* cp, const int* trow, const int* tent, const uint8_t* z,
                         uint64_t seed, int* lam, uint64_t* hh, int8_t* state, int* left,
                         uint8_t* sel, uint8_t* cf, int64_t* count, hipStream_t s);
+
+// ---- galerkin.hip
+struct GalerkinIn {
+    int n;
+    const int* rp;
+    const int* ci;
+    const void* av;
+    int dtype;
+    int cal;
+    const int* Pc;     // n x cal fine column indices, -1 padded
+    const double* Pv;  // n x cal weights
+    const uint8_t* cf;
+};
+struct GalerkinWork {
+    int* flags;         // n
+    int64_t* scan;      // n + 1 (also the coarse row counts' scan)
+    int64_t* scan_tmp;  // scan_workspace_bytes(n)
+    int* cidx;          // n
+    int* cnt;           // n
+    int64_t* pt;        // n + 1
+    int64_t* ptkey;     // n * cal
+    int* maxslots;      // 1
+};
+int galerkin_prepare(const GalerkinIn& g, GalerkinWork& w, int* nc_out, hipStream_t s);
+int galerkin_transpose(const GalerkinIn& g, GalerkinWork& w, int nc, unsigned* status,
+                       hipStream_t s);
+int galerkin_rows_run(const GalerkinIn& g, GalerkinWork& w, int nc, int* rpc, int64_t* nnz_c,
+                      hipStream_t s);
+int galerkin_cols_run(const GalerkinIn& g, GalerkinWork& w, int nc, const int* rpc, int* colc,
+                      double* valc, hipStream_t s);
+int coarse_factor(int nc, const int* rpc, const int* colc, const double* valc, double* L,
+                  double* Li, double* LiT, int* bad, hipStream_t s);
+int coarse_correction(const GalerkinIn& g, const GalerkinWork& w, int nc, int K, const double* Li,
+                      const double* LiT, double* E, double* R, double* Rc, hipStream_t s);
+int a_norms_sq(const GalerkinIn& g, int K, const double* E, double* part, double* out,
+               hipStream_t s);
+int two_grid_blocks(int n, int K);
+constexpr int kCoarseSolveMax = 8192;
 
 // ---- adjoint.hip
 int launch_csc_index(int n, int64_t nnz, const int* rp, const int* ci, const double* av, int* cnt,

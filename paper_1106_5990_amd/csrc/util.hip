@@ -122,6 +122,20 @@ int64_t scan_workspace_bytes(int64_t m) {
     return (nb > 0 ? nb : 1) * (int64_t)sizeof(int64_t);
 }
 
+__global__ __launch_bounds__(kBlock) void narrow_i64_kernel(const int64_t* __restrict__ a,
+                                                            int64_t m, int32_t* __restrict__ b) {
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i < m) b[i] = (int32_t)a[i];
+}
+
+// b[0..m) = a[0..m) (values known to fit int32)
+int launch_narrow_i64(const int64_t* a, int64_t m, int32_t* b, hipStream_t s) {
+    if (m <= 0) return AD_OK;
+    narrow_i64_kernel<<<dim3((unsigned)((m + kBlock - 1) / kBlock)), dim3(kBlock), 0, s>>>(a, m, b);
+    AD_HIP(hipGetLastError());
+    return AD_OK;
+}
+
 int launch_excl_scan(const int32_t* cnt, int64_t m, int64_t* out, int64_t* tmp, hipStream_t s) {
     if (m <= 0) {
         fill_i64_kernel<<<dim3(1), dim3(kBlock), 0, s>>>(out, 1, 0);
