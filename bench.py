@@ -15,6 +15,11 @@ test vectors, 5 red-black colour-phase Gauss-Seidel sweeps, theta = 0.25,
 caliber 4 from the red C/F split; FP32 relaxation and distances with FP64
 interpolation solves.
 
+Launch shapes: the autotuner runs before the timed region, starting from a
+private copy of the committed bench_shapes.jsonl (shapes tuned on MI355X,
+the ones the counter summaries under profiles/ were taken with); keys it
+lacks are tuned; --retune tunes everything afresh.
+
 Timing: the step is captured once in a HIP graph and replayed; every replay
 is bracketed by its own events and followed (outside the events) by a 1 GiB
 scratch write, so that no replay starts with the panels of the previous one
@@ -82,6 +87,9 @@ def parse(argv=None):
     ap.add_argument("--tune-cache", default=None,
                     help="autotuner cache file (JSON lines); shapes found there are used without "
                          "timing, new ones are appended (default: a fresh temporary file)")
+    ap.add_argument("--retune", action="store_true",
+                    help="autotune afresh instead of starting from the committed shapes "
+                         "(bench_shapes.jsonl, tuned on MI355X; keys it lacks are tuned)")
     ap.add_argument("--batch-size", type=int, default=512)
     ap.add_argument("--batch-workers", type=int, default=None,
                     help="processes building the batch (default: up to 16; 1 builds it in this "
@@ -118,6 +126,23 @@ def parse(argv=None):
 
 WORKLOAD_INDEX = {"laplace2d": 1, "aniso2d": 2, "varcoef3d": 3}
 SECOND = {"aniso2d": "varcoef3d"}
+
+
+BENCH_SHAPES = os.path.join(os.path.dirname(os.path.abspath(__file__)), "bench_shapes.jsonl")
+
+
+def tune_cache_path(args, name):
+    """The autotuner cache for this run: --tune-cache if given, else a
+    private copy of the committed shapes (so the launch shapes, and with them
+    the counter summaries under profiles/, are the ones measured there), or
+    an empty file with --retune.  The committed file is never written."""
+    if args.tune_cache:
+        return args.tune_cache
+    import shutil
+    path = os.path.join(tempfile.mkdtemp(prefix="algdist_tune_"), name)
+    if not args.retune and os.path.exists(BENCH_SHAPES):
+        shutil.copyfile(BENCH_SHAPES, path)
+    return path
 
 
 def log(msg):
@@ -425,8 +450,7 @@ def run_leg(args, wl, tag, dtype, torch, ad, flush, keep=False):
     step = make_step(wl, b, ad, fused=not args.separate)
     if not args.no_autotune:
         log("%s %s: autotune" % (wl.name, tag))
-        cache = args.tune_cache or os.path.join(tempfile.mkdtemp(prefix="algdist_tune_"),
-                                                "shapes.jsonl")
+        cache = tune_cache_path(args, "shapes.jsonl")
         ad.autotune(b["A"], wl.K, relax=wl.relax, color=b["color"], ncolors=wl.ncolors,
                     cf=b["cf"], caliber=wl.caliber, cache_json=cache)
         code = ad._dtype_code(dtype)
@@ -528,7 +552,7 @@ def batched_leg(args, torch, ad, W, mats, flush):
     out = {"workload": "rgg-batch-%d (n log-uniform 2k-200k, mean degree U[4,29]), K=%d, %d Jacobi "
                        "sweeps, theta=%g" % (nm, K, S, th),
            "matrices": nm, "rows": rows, "nnz": ents, "edges": E}
-    cache = args.tune_cache or os.path.join(tempfile.mkdtemp(prefix="algdist_tune_"), "batch.jsonl")
+    cache = tune_cache_path(args, "batch.jsonl")
     for tag, dt, s in (("f32", torch.float32, 4), ("f64", torch.float64, 8)):
         log("batched leg %s: autotune" % tag)
         dm = [ad.Csr.from_host(m, dtype=dt) for m in mats]
