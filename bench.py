@@ -145,6 +145,13 @@ def tune_cache_path(args, name):
     return path
 
 
+def nnz_bucket(nnz, n):
+    """The autotuner's key bucket: stored entries per row < 8, < 16, < 32,
+    or more."""
+    r = nnz / n if n > 0 else 0.0
+    return 0 if r < 8 else 1 if r < 16 else 2 if r < 32 else 3
+
+
 def log(msg):
     print("[bench] " + msg, file=sys.stderr, flush=True)
 
@@ -454,8 +461,10 @@ def run_leg(args, wl, tag, dtype, torch, ad, flush, keep=False):
         ad.autotune(b["A"], wl.K, relax=wl.relax, color=b["color"], ncolors=wl.ncolors,
                     cf=b["cf"], caliber=wl.caliber, cache_json=cache)
         code = ad._dtype_code(dtype)
+        bucket = nnz_bucket(wl.A.nnz, wl.A.n)
         shapes = {e["kernel"]: {k: e[k] for k in ("lpr", "iter", "xcd")}
-                  for e in (json.loads(l) for l in open(cache)) if e["dtype"] == code}
+                  for e in (json.loads(l) for l in open(cache))
+                  if e["dtype"] == code and e["K"] == wl.K and e["bucket"] == bucket}
     else:
         shapes = "defaults"
     steps = args.steps if tag == "f32" else max(3, args.steps // 2)
@@ -558,9 +567,11 @@ def batched_leg(args, torch, ad, W, mats, flush):
         dm = [ad.Csr.from_host(m, dtype=dt) for m in mats]
         ad.autotune_batched(dm, K, S, cache_json=cache)
         tuned = [json.loads(l) for l in open(cache)]
+        bb = nnz_bucket(ents, rows)
         shape = {fam: {k: e[k] for k in ("lpr", "iter", "xcd")}
                  for fam in ("batched", "batched_distance")
-                 for e in tuned if e["kernel"] == fam and e["dtype"] == ad._dtype_code(dt)}
+                 for e in tuned if e["kernel"] == fam and e["dtype"] == ad._dtype_code(dt)
+                 and e["K"] == K and e["bucket"] == bb}
         X = torch.empty((rows, K), dtype=dt, device="cuda")
         mu = torch.empty(ents, dtype=dt, device="cuda")
         st = torch.empty(ents, dtype=torch.uint8, device="cuda")
