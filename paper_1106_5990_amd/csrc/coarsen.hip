@@ -225,15 +225,22 @@ __global__ __launch_bounds__(kBlock) void mis_drop_kernel(
     if (threadIdx.x == 0 && cnt) atomicAdd(left, cnt);
 }
 
-// sel[i] = chosen; cf[i] |= chosen (cf may be null).
+// sel[i] = chosen; cf[i] |= chosen (cf may be null); *chosen += the count.
 __global__ __launch_bounds__(kBlock) void mis_apply_kernel(int n, const int8_t* __restrict__ state,
                                                            uint8_t* __restrict__ sel,
-                                                           uint8_t* __restrict__ cf) {
+                                                           uint8_t* __restrict__ cf, int* chosen) {
+    __shared__ int cnt;
+    if (threadIdx.x == 0) cnt = 0;
+    __syncthreads();
     const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (i >= n) return;
-    const bool c = state[i] == 2;
-    if (sel) sel[i] = (uint8_t)c;
-    if (cf && c) cf[i] = 1;
+    if (i < n) {
+        const bool c = state[i] == 2;
+        if (sel) sel[i] = (uint8_t)c;
+        if (cf && c) cf[i] = 1;
+        if (c) atomicAdd(&cnt, 1);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0 && cnt) atomicAdd(chosen, cnt);
 }
 
 // fm[i] = 1 on F (cf[i] == 0)
@@ -306,29 +313,33 @@ int run_independent_set(int n, const int* rp, const int* ci, const uint8_t* stro
     const unsigned nb = blocks_for(n, kBlock);
     mis_init_kernel<<<dim3(nb), dim3(kBlock), 0, s>>>(n, cp, tent, strong, z, seed, lam, hh, state);
     AD_HIP(hipGetLastError());
-    // every round chooses the highest undecided candidate, so n rounds bound the loop
-    for (int64_t round = 0; round <= n; ++round) {
-        int rc = launch_fill_i32(left, 1, 0, s);
-        if (rc) return rc;
-        mis_select_kernel<<<dim3(nb), dim3(kBlock), 0, s>>>(n, rp, ci, strong, cp, trow, tent, lam,
-                                                            hh, state);
-        mis_drop_kernel<<<dim3(nb), dim3(kBlock), 0, s>>>(n, rp, ci, strong, cp, trow, tent, state,
-                                                          left);
+    // every round chooses the highest undecided candidate, so n rounds bound
+    // the loop; the host looks at the count of undecided points after every
+    // kMisRounds rounds (rounds after the last one find nothing to do)
+    constexpr int kMisRounds = 4;
+    for (int64_t round = 0; round <= n; round += kMisRounds) {
+        for (int r = 0; r < kMisRounds; ++r) {
+            int rc = launch_fill_i32(left, 1, 0, s);
+            if (rc) return rc;
+            mis_select_kernel<<<dim3(nb), dim3(kBlock), 0, s>>>(n, rp, ci, strong, cp, trow, tent,
+                                                                lam, hh, state);
+            mis_drop_kernel<<<dim3(nb), dim3(kBlock), 0, s>>>(n, rp, ci, strong, cp, trow, tent,
+                                                              state, left);
+        }
         AD_HIP(hipGetLastError());
         int h_left = 0;
         AD_HIP(hipMemcpyAsync(&h_left, left, sizeof h_left, hipMemcpyDeviceToHost, s));
         AD_HIP(hipStreamSynchronize(s));
         if (h_left == 0) break;
     }
-    mis_apply_kernel<<<dim3(nb), dim3(kBlock), 0, s>>>(n, state, sel, cf);
+    int rc = launch_fill_i32(left, 1, 0, s);
+    if (rc) return rc;
+    mis_apply_kernel<<<dim3(nb), dim3(kBlock), 0, s>>>(n, state, sel, cf, left);
     AD_HIP(hipGetLastError());
-    // the set's size: count the chosen states on the host side of a copy
-    std::vector<int8_t> st((size_t)n);
-    AD_HIP(hipMemcpyAsync(st.data(), state, (size_t)n, hipMemcpyDeviceToHost, s));
+    int chosen = 0;
+    AD_HIP(hipMemcpyAsync(&chosen, left, sizeof chosen, hipMemcpyDeviceToHost, s));
     AD_HIP(hipStreamSynchronize(s));
-    int64_t c = 0;
-    for (int8_t v : st) c += v == 2;
-    *count = c;
+    *count = chosen;
     return AD_OK;
 }
 
