@@ -3,12 +3,13 @@
 //
 // Pattern of A^d.  Row i of A^d holds (structurally) every j within graph
 // distance d of i; A^d itself is never formed.  One wavefront per row runs
-// a breadth-first search of depth d over the graph of A: the set found so
-// far lives in an LDS hash table (open addressing, compare-and-swap
-// inserts), and each newly inserted vertex is appended to an LDS list, so
-// the list holds the levels one after the other and the current frontier
-// is its last range.  The count pass writes |row|; the fill pass repeats
-// the search and writes the list sorted (bitonic sort in LDS).
+// a breadth-first search of depth d over the graph of A, a level at a
+// time: the frontier's rows of A are walked with every lane taking its own
+// entries, inserted into an LDS hash set (open addressing,
+// compare-and-swap), new vertices appended to a list that holds the levels
+// in order.  A wavefront handles several rows, clearing only the slots a
+// row took.  The count pass writes |row|; the fill pass repeats the search
+// and writes the list sorted (bitonic sort in LDS).
 //
 // Interpolatory-set search.  One wavefront per F row: the row's candidates
 // (the C-points of its row of the pattern, i excluded, in column order) and
@@ -33,11 +34,14 @@ namespace ad {
 // ---------------------------------------------------------------- pattern of A^d
 constexpr int kPowCap = 1024;   // entries per row of A^d
 constexpr int kPowHash = 2048;  // LDS hash slots per wavefront (load factor <= 1/2 + 1/32)
-constexpr int kPowWaves = 2;    // wavefronts (rows) per workgroup
+constexpr int kPowWaves = 4;    // wavefronts per workgroup
+constexpr int kPowRows = 8;     // rows per wavefront (the hash is cleared once per wavefront)
 
 struct PowLds {
     int hash[kPowWaves][kPowHash];
-    int list[kPowWaves][kPowCap];
+    int list[kPowWaves][kPowCap];  // the vertices in the order found
+    short slot[kPowWaves][kPowCap];  // the hash slot each one took
+    int off[kPowWaves][kPowCap];   // expansion offsets of the frontier
     int n[kPowWaves];
 };
 
@@ -47,53 +51,104 @@ __device__ __forceinline__ void wave_sync_lds() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Breadth-first search of depth d from row i into L.list[wv][0 .. n);
-// returns n, or -1 when the row of A^d has more than kPowCap entries.
+// exclusive wave prefix of v over the lanes; *total receives the sum
+__device__ __forceinline__ int wave_excl(int v, int lane, int* total) {
+    int x = v;
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+        const int y = __shfl_up(x, o, kWave);
+        if (lane >= o) x += y;
+    }
+    *total = __shfl(x, kWave - 1, kWave);
+    return x - v;
+}
+
+// Inserts j; appends it to the list when new.  false when the list is full.
+__device__ __forceinline__ bool pow_insert(int j, PowLds& L, int wv) {
+    int* hash = L.hash[wv];
+    unsigned slot = ((unsigned)j * 2654435761u) & (kPowHash - 1);
+    for (int probe = 0; probe < kPowHash; ++probe) {
+        const int prev = atomicCAS(&hash[slot], -1, j);
+        if (prev == j) return true;  // already in the set
+        if (prev == -1) {            // new
+            const int pos = atomicAdd(&L.n[wv], 1);
+            if (pos >= kPowCap) return false;
+            L.list[wv][pos] = j;
+            L.slot[wv][pos] = (short)slot;
+            return true;
+        }
+        slot = (slot + 1) & (kPowHash - 1);
+    }
+    return false;
+}
+
+// Breadth-first search of depth d from row i, a level at a time: the
+// frontier's rows of A are walked with every lane taking its own entries
+// (all of a level's loads in flight together) and inserting them into the
+// wavefront's LDS hash set, new vertices appended to the list, so the list
+// holds the levels one after the other.  Returns |row of A^d| (the list),
+// or -1 past kPowCap.  The caller clears the used slots afterwards.
 __device__ int pow_row(int i, int d, const int* __restrict__ rp, const int* __restrict__ ci,
                        PowLds& L, int wv, int lane) {
-    int* hash = L.hash[wv];
     int* list = L.list[wv];
-    for (int q = lane; q < kPowHash; q += kWave) hash[q] = -1;
+    int* off = L.off[wv];
     if (lane == 0) {
-        L.n[wv] = 1;
-        list[0] = i;
+        L.n[wv] = 0;
     }
     wave_sync_lds();
-    if (lane == 0) hash[((unsigned)i * 2654435761u) & (kPowHash - 1)] = i;
+    if (lane == 0) pow_insert(i, L, wv);
     wave_sync_lds();
     int lo = 0, hi = 1;
     bool over = false;
-    for (int lev = 0; lev < d && lo < hi; ++lev) {
-        for (int q = lo + lane; q < hi; q += kWave) {
-            const int u = list[q];
-            for (int e = rp[u]; e < rp[u + 1]; ++e) {
-                const int j = ci[e];
-                unsigned slot = ((unsigned)j * 2654435761u) & (kPowHash - 1);
-                for (int probe = 0; probe < kPowHash; ++probe) {
-                    const int prev = atomicCAS(&hash[slot], -1, j);
-                    if (prev == j) break;  // already in the set
-                    if (prev == -1) {      // new: append to the next level
-                        const int pos = atomicAdd(&L.n[wv], 1);
-                        if (pos < kPowCap) list[pos] = j;
-                        break;
-                    }
-                    slot = (slot + 1) & (kPowHash - 1);
-                }
-                // stop inserting once the cap is passed (the table keeps
-                // at most kPowCap + one insert per lane)
-                if (__atomic_load_n(&L.n[wv], __ATOMIC_RELAXED) > kPowCap) {
-                    over = true;
-                    break;
-                }
+    for (int lev = 0; lev < d && lo < hi && !over; ++lev) {
+        const int nf = hi - lo;
+        int total = 0;
+        for (int c0 = 0; c0 < nf; c0 += kWave) {
+            const int q = c0 + lane;
+            const int deg = q < nf ? rp[list[lo + q] + 1] - rp[list[lo + q]] : 0;
+            int sum;
+            const int ex = wave_excl(deg, lane, &sum);
+            if (q < nf) off[q] = total + ex;
+            total += sum;
+        }
+        wave_sync_lds();
+        for (int k = lane; k < total; k += kWave) {
+            int a = 0, b = nf;  // last frontier entry with off <= k
+            while (b - a > 1) {
+                const int mid = (a + b) >> 1;
+                if (off[mid] <= k) a = mid;
+                else b = mid;
             }
-            if (over) break;
+            const int u = list[lo + a];
+            if (!pow_insert(ci[rp[u] + (k - off[a])], L, wv) ||
+                __atomic_load_n(&L.n[wv], __ATOMIC_RELAXED) > kPowCap) {
+                over = true;
+                break;
+            }
         }
         wave_sync_lds();
         lo = hi;
         hi = L.n[wv];
-        if (__any(over) || hi > kPowCap) return -1;
+        over = __any(over) || hi > kPowCap;
     }
-    return hi;
+    return over ? -1 : hi;
+}
+
+// back to an empty hash: the slots the row's vertices took, or every slot
+// after an overflow (whose last inserts are not in the list)
+__device__ __forceinline__ void pow_clear(PowLds& L, int wv, int lane) {
+    const int m = L.n[wv];
+    if (m > kPowCap) {
+        for (int q = lane; q < kPowHash; q += kWave) L.hash[wv][q] = -1;
+    } else {
+        for (int q = lane; q < m; q += kWave) L.hash[wv][L.slot[wv][q]] = -1;
+    }
+    wave_sync_lds();
+}
+
+__device__ __forceinline__ void pow_init(PowLds& L, int wv, int lane) {
+    for (int q = lane; q < kPowHash; q += kWave) L.hash[wv][q] = -1;
+    wave_sync_lds();
 }
 
 __global__ __launch_bounds__(kWave* kPowWaves) void pow_count_kernel(int n, int d,
@@ -102,10 +157,14 @@ __global__ __launch_bounds__(kWave* kPowWaves) void pow_count_kernel(int n, int 
                                                                      int* __restrict__ cnt) {
     __shared__ PowLds L;
     const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
-    const int64_t i = (int64_t)blockIdx.x * kPowWaves + wv;
-    if (i >= n) return;  // whole wavefront
-    const int c = pow_row((int)i, d, rp, ci, L, wv, lane);
-    if (lane == 0) cnt[i] = c;
+    const int64_t i0 = ((int64_t)blockIdx.x * kPowWaves + wv) * kPowRows;
+    if (i0 >= n) return;  // whole wavefront
+    pow_init(L, wv, lane);
+    for (int64_t i = i0; i < i0 + kPowRows && i < n; ++i) {
+        const int c = pow_row((int)i, d, rp, ci, L, wv, lane);
+        if (lane == 0) cnt[i] = c;
+        pow_clear(L, wv, lane);
+    }
 }
 
 __global__ __launch_bounds__(kWave* kPowWaves) void pow_fill_kernel(
@@ -113,39 +172,44 @@ __global__ __launch_bounds__(kWave* kPowWaves) void pow_fill_kernel(
     const int* __restrict__ rpd, int* __restrict__ cid, unsigned* status) {
     __shared__ PowLds L;
     const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
-    const int64_t i = (int64_t)blockIdx.x * kPowWaves + wv;
-    if (i >= n) return;  // whole wavefront
-    const int c = pow_row((int)i, d, rp, ci, L, wv, lane);
-    if (c < 0) return;  // the count pass refused such a matrix
-    int* a = L.list[wv];
-    int m = 1;
-    while (m < c) m <<= 1;
-    for (int q = c + lane; q < m; q += kWave) a[q] = 0x7fffffff;
-    wave_sync_lds();
-    // bitonic sort of a[0 .. m), m a power of two <= kPowCap
-    for (int k = 2; k <= m; k <<= 1) {
-        for (int j = k >> 1; j > 0; j >>= 1) {
-            for (int q = lane; q < m; q += kWave) {
-                const int p = q ^ j;
-                if (p > q) {
-                    const int x = a[q], y = a[p];
-                    const bool up = (q & k) == 0;
-                    if ((x > y) == up) {
-                        a[q] = y;
-                        a[p] = x;
+    const int64_t i0 = ((int64_t)blockIdx.x * kPowWaves + wv) * kPowRows;
+    if (i0 >= n) return;  // whole wavefront
+    pow_init(L, wv, lane);
+    for (int64_t i = i0; i < i0 + kPowRows && i < n; ++i) {
+        const int c = pow_row((int)i, d, rp, ci, L, wv, lane);
+        pow_clear(L, wv, lane);
+        if (c < 0) continue;  // the count pass refused such a matrix
+        int* a = L.list[wv];
+        int m = 1;
+        while (m < c) m <<= 1;
+        for (int q = c + lane; q < m; q += kWave) a[q] = 0x7fffffff;
+        wave_sync_lds();
+        // bitonic sort of a[0 .. m), m a power of two <= kPowCap
+        for (int k = 2; k <= m; k <<= 1) {
+            for (int j = k >> 1; j > 0; j >>= 1) {
+                for (int q = lane; q < m; q += kWave) {
+                    const int p = q ^ j;
+                    if (p > q) {
+                        const int x = a[q], y = a[p];
+                        const bool up = (q & k) == 0;
+                        if ((x > y) == up) {
+                            a[q] = y;
+                            a[p] = x;
+                        }
                     }
                 }
+                wave_sync_lds();
             }
-            wave_sync_lds();
         }
+        // row pointers that do not match this row's length (not those of the
+        // same A and d) are flagged, and no entry is written outside the row
+        const int room = rpd[i + 1] - rpd[i];
+        if (room != c && lane == 0) flag(status, AD_STAT_PATTERN);
+        const int cw = room < c ? room : c;
+        int* out = cid + rpd[i];
+        for (int q = lane; q < cw; q += kWave) out[q] = a[q];
+        wave_sync_lds();
     }
-    // row pointers that do not match this row's length (not those of the
-    // same A and d) are flagged, and no entry is written outside the row
-    const int room = rpd[i + 1] - rpd[i];
-    if (room != c && lane == 0) flag(status, AD_STAT_PATTERN);
-    const int cw = room < c ? room : c;
-    int* out = cid + rpd[i];
-    for (int q = lane; q < cw; q += kWave) out[q] = a[q];
 }
 
 // rpd[0] = 0, rpd[i + 1] = rpd[i] + cnt[i] (int32), total into *tot; a
@@ -184,7 +248,8 @@ int launch_pow_rows(int n, int d, const int* rp, const int* ci, int* rpd, void* 
     int rc;
     if ((rc = launch_fill_i32(bad, 1, 0, s))) return rc;
     if (n > 0) {
-        const unsigned nb = (unsigned)(((int64_t)n + kPowWaves - 1) / kPowWaves);
+        const int64_t per = (int64_t)kPowWaves * kPowRows;
+        const unsigned nb = (unsigned)(((int64_t)n + per - 1) / per);
         pow_count_kernel<<<dim3(nb), dim3(kWave * kPowWaves), 0, s>>>(n, d, rp, ci, cnt);
         AD_HIP(hipGetLastError());
     }
@@ -201,7 +266,8 @@ int launch_pow_rows(int n, int d, const int* rp, const int* ci, int* rpd, void* 
 int launch_pow_cols(int n, int d, const int* rp, const int* ci, const int* rpd, int* cid,
                     unsigned* status, hipStream_t s) {
     if (n == 0) return AD_OK;
-    const unsigned nb = (unsigned)(((int64_t)n + kPowWaves - 1) / kPowWaves);
+    const int64_t per = (int64_t)kPowWaves * kPowRows;
+    const unsigned nb = (unsigned)(((int64_t)n + per - 1) / per);
     pow_fill_kernel<<<dim3(nb), dim3(kWave * kPowWaves), 0, s>>>(n, d, rp, ci, rpd, cid,
                                                                    status);
     AD_HIP(hipGetLastError());
