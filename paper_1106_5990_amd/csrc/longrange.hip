@@ -275,42 +275,51 @@ int launch_pow_cols(int n, int d, const int* rp, const int* ci, const int* rpd, 
 }
 
 // ---------------------------------------------------------------- set search
-constexpr int kSearchCand = 64;  // candidates per row (one per lane)
+// A wavefront searches one F row at a time: the target and the candidates'
+// panel rows go to the wavefront's LDS slice, the lanes form h and the
+// packed Gram matrix, then every lane fits a contiguous block of subsets of
+// each size in lexicographic order.  Consecutive subsets of a block share
+// their leading positions, so the Cholesky rows of those positions are kept
+// and only the rows from the first changed position on are refactored (the
+// same operations in the same order as a full factorization of each set).
+// A first pass with room for kSearchFast candidates handles every row and
+// marks the F rows with more (row status -1); a second pass with room for
+// kSearchCand takes only the marked rows.
+constexpr int kSearchCand = 64;  // candidates per row (the cap of the search)
+constexpr int kSearchFast = 32;  // candidates per row in the first pass
 constexpr int kSearchCal = 4;    // largest set size
-constexpr int kSearchGram = kSearchCand * (kSearchCand + 1) / 2;
+constexpr int kSearchMarked = -1;  // row status between the two passes
 
-template <int K>
+template <typename T, int K, int NCAP>
 struct SearchLds {
-    double x[kSearchCand][K + 1];  // candidate panel rows (padded against bank conflicts)
+    double g[NCAP * (NCAP + 1) / 2];  // packed lower triangle, (a, b) at a (a + 1) / 2 + b, b <= a
+    double h[NCAP];
     double t[K];
     double w[K];
-    double g[kSearchGram];  // packed lower triangle, (a, b) at a (a + 1) / 2 + b, b <= a
-    double h[kSearchCand];
-    int cand[kSearchCand];
-    double red[kWave];
-    int redr[kWave];
-    int ncand;
+    T x[NCAP][K + 1];  // candidate panel rows (padded against bank conflicts)
+    int cand[NCAP];
 };
 
-__device__ __forceinline__ int64_t binom_small(int a, int b) {
+// C(a, b) for b <= 4 and a <= kSearchCand (at most C(64, 4) = 635376)
+__device__ __forceinline__ int binom_small(int a, int b) {
     if (b < 0 || a < b) return 0;
     switch (b) {
         case 0: return 1;
         case 1: return a;
-        case 2: return (int64_t)a * (a - 1) / 2;
-        case 3: return (int64_t)a * (a - 1) * (a - 2) / 6;
-        default: return (int64_t)a * (a - 1) * (a - 2) * (a - 3) / 24;
+        case 2: return a * (a - 1) / 2;
+        case 3: return a * (a - 1) * (a - 2) / 6;
+        default: return a * (a - 1) / 2 * ((a - 2) * (a - 3) / 2) / 6;
     }
 }
 
 // The combination of rank r (lexicographic order) of m out of nc.
-__device__ __forceinline__ void unrank(int64_t r, int nc, int m, int (&idx)[kSearchCal]) {
+__device__ __forceinline__ void unrank(int r, int nc, int m, int (&idx)[kSearchCal]) {
     int c = 0;
 #pragma unroll
     for (int q = 0; q < kSearchCal; ++q) {
         if (q >= m) break;
         for (;;) {
-            const int64_t cnt = binom_small(nc - c - 1, m - q - 1);
+            const int cnt = binom_small(nc - c - 1, m - q - 1);
             if (r < cnt) break;
             r -= cnt;
             ++c;
@@ -319,94 +328,163 @@ __device__ __forceinline__ void unrank(int64_t r, int nc, int m, int (&idx)[kSea
     }
 }
 
-// The successor of idx in lexicographic order (false after the last).
-__device__ __forceinline__ bool next_comb(int nc, int m, int (&idx)[kSearchCal]) {
-    int q = m - 1;
-    while (q >= 0 && idx[q] == nc - m + q) --q;
-    if (q < 0) return false;
-    ++idx[q];
+// The successor of idx in lexicographic order; returns the first position
+// that changed (-1 after the last combination).
+__device__ __forceinline__ int next_comb(int nc, int m, int (&idx)[kSearchCal]) {
+    // the last position below its largest value (constant register indices)
+    int q = -1;
 #pragma unroll
-    for (int p = 1; p < kSearchCal; ++p)
-        if (p > q && p < m) idx[p] = idx[p - 1] + 1;
-    return true;
+    for (int p = 0; p < kSearchCal; ++p)
+        if (p < m && idx[p] != nc - m + p) q = p;
+    if (q < 0) return -1;
+#pragma unroll
+    for (int p = 0; p < kSearchCal; ++p) {
+        if (p == q) ++idx[p];
+        else if (p > q && p < m) idx[p] = idx[p > 0 ? p - 1 : 0] + 1;
+    }
+    return q;
 }
 
-__device__ __forceinline__ double gram_at(const double* g, int a, int b) {
-    return (a >= b) ? g[a * (a + 1) / 2 + b] : g[b * (b + 1) / 2 + a];
+// G_W entry of positions (a, b), a >= b: the positions of a set are in
+// increasing candidate order, so idx[a] >= idx[b] and the entry sits in row
+// idx[a] of the packed triangle.
+__device__ __forceinline__ double gram_ab(const double* g, int ia, int ib) {
+    return g[(((unsigned)ia * (unsigned)(ia + 1)) >> 1) + (unsigned)ib];
 }
 
-// Cholesky of G_W (W = candidates idx[0..m)) with the dependence rule;
-// returns false for a dependent set, else the functional S - |L^{-1} h|^2
-// in *val (clamped at 0) and, when coef != nullptr, the minimiser.
-__device__ bool subset_fit(const double* g, const double* h, double S, int m,
-                           const int (&idx)[kSearchCal], double* val, double* coef) {
+// Cholesky factor of G_W for the leading positions of W: the off-diagonal
+// rows of L, the reciprocals of its diagonal, z = L^{-1} h_W and the running
+// sums of z^2.
+struct SetFit {
     double L[kSearchCal][kSearchCal];
+    double inv[kSearchCal];
     double z[kSearchCal];
+    double zz[kSearchCal];
+};
+
+// Rows [from, upto) of the factor of G_W (W = candidates idx[...]), rows
+// below `from` already in F.  Returns the first position whose pivot fails
+// the dependence rule (<= 1e-12 of its Gram diagonal), or upto.
+__device__ __forceinline__ int fit_rows(const double* g, const double* h, int from, int upto,
+                                        const int (&idx)[kSearchCal], SetFit& F) {
 #pragma unroll
     for (int a = 0; a < kSearchCal; ++a) {
-        if (a >= m) break;
-        const double gaa = gram_at(g, idx[a], idx[a]);
+        if (a < from) continue;
+        if (a >= upto) break;
+        const double gaa = gram_ab(g, idx[a], idx[a]);
 #pragma unroll
         for (int b = 0; b < kSearchCal; ++b) {
             if (b >= a) break;
-            double s = gram_at(g, idx[a], idx[b]);
+            double s = gram_ab(g, idx[a], idx[b]);
 #pragma unroll
             for (int c = 0; c < kSearchCal; ++c) {
                 if (c >= b) break;
-                s -= L[a][c] * L[b][c];
+                s -= F.L[a][c] * F.L[b][c];
             }
-            L[a][b] = s / L[b][b];
+            F.L[a][b] = s * F.inv[b];
         }
         double piv = gaa;
 #pragma unroll
         for (int b = 0; b < kSearchCal; ++b) {
             if (b >= a) break;
-            piv -= L[a][b] * L[a][b];
+            piv -= F.L[a][b] * F.L[a][b];
         }
-        if (!(piv > 1e-12 * gaa)) return false;
-        L[a][a] = sqrt(piv);
-    }
-    double zz = 0.0;
-#pragma unroll
-    for (int a = 0; a < kSearchCal; ++a) {
-        if (a >= m) break;
+        if (!(piv > 1e-12 * gaa)) return a;
+        F.inv[a] = 1.0 / sqrt(piv);
         double s = h[idx[a]];
 #pragma unroll
         for (int b = 0; b < kSearchCal; ++b) {
             if (b >= a) break;
-            s -= L[a][b] * z[b];
+            s -= F.L[a][b] * F.z[b];
         }
-        z[a] = s / L[a][a];
-        zz += z[a] * z[a];
+        F.z[a] = s * F.inv[a];
+        F.zz[a] = (a == 0 ? 0.0 : F.zz[a > 0 ? a - 1 : 0]) + F.z[a] * F.z[a];
     }
-    const double v = S - zz;
+    return upto;
+}
+
+// The functional of the set whose leading M - 1 positions are factored in
+// F: with the last row l = L_{M-1, <M-1} and pivot p, the set's z^T z is
+// the leading sum plus (h - l . z)^2 / p, so no square root is taken.
+// false when the last pivot fails the dependence rule.
+template <int M>
+__device__ __forceinline__ bool last_value(const double* g, const double* h, double S,
+                                           const int (&idx)[kSearchCal], const SetFit& F,
+                                           double* val) {
+    constexpr int A = M - 1;
+    const double gaa = gram_ab(g, idx[A], idx[A]);
+    double l[kSearchCal];
+#pragma unroll
+    for (int b = 0; b < A; ++b) {
+        double s = gram_ab(g, idx[A], idx[b]);
+#pragma unroll
+        for (int c = 0; c < b; ++c) s -= l[c] * F.L[b][c];
+        l[b] = s * F.inv[b];
+    }
+    double piv = gaa;
+#pragma unroll
+    for (int b = 0; b < A; ++b) piv -= l[b] * l[b];
+    if (!(piv > 1e-12 * gaa)) return false;
+    double t = h[idx[A]];
+#pragma unroll
+    for (int b = 0; b < A; ++b) t -= l[b] * F.z[b];
+    const double v = S - ((A > 0 ? F.zz[A > 0 ? A - 1 : 0] : 0.0) + t * t / piv);
     *val = v > 0.0 ? v : 0.0;
-    if (coef) {
-#pragma unroll
-        for (int a = kSearchCal - 1; a >= 0; --a) {
-            if (a >= m) continue;
-            double s = z[a];
-#pragma unroll
-            for (int b = 0; b < kSearchCal; ++b)
-                if (b > a && b < m) s -= L[b][a] * coef[b];
-            coef[a] = s / L[a][a];
-        }
-    }
     return true;
 }
 
-template <typename T, int K>
-__global__ __launch_bounds__(kWave) void ls_search_kernel(
-    int n, const int* __restrict__ rp, const int* __restrict__ ci, const T* __restrict__ av,
-    const int* __restrict__ rpg, const int* __restrict__ cig, const T* __restrict__ X,
-    const double* __restrict__ w, const uint8_t* __restrict__ cf, int cal, double gamma,
-    int target, int* __restrict__ Pcol, double* __restrict__ Pval, double* __restrict__ lsv,
-    int* __restrict__ rstat, unsigned* status) {
-    __shared__ SearchLds<K> L;
-    const int lane = threadIdx.x;
-    const int64_t i64 = blockIdx.x;
-    if (i64 >= n) return;
-    const int i = (int)i64;
+// The minimiser of a fitted set of size m: back substitution L^T c = z.
+__device__ __forceinline__ void fit_coef(const SetFit& F, int m, double (&coef)[kSearchCal]) {
+#pragma unroll
+    for (int a = kSearchCal - 1; a >= 0; --a) {
+        if (a >= m) continue;
+        double s = F.z[a];
+#pragma unroll
+        for (int b = 0; b < kSearchCal; ++b)
+            if (b > a && b < m) s -= F.L[b][a] * coef[b];
+        coef[a] = s * F.inv[a];
+    }
+}
+
+// The lane's block of size-M sets (consecutive ranks in lexicographic
+// order): the least functional and its rank into (bv, br).  The Cholesky
+// rows of the leading positions are refactored only from the first
+// position that changed, and not at all while an unchanged leading
+// position stays dependent.
+template <int M>
+__device__ __forceinline__ void best_of_size(const double* g, const double* h, double S, int nc,
+                                             int lane, double& bv, int& br) {
+    const int total = binom_small(nc, M);
+    const int per = (total + kWave - 1) / kWave;
+    const int r0 = lane * per, r1 = (r0 + per < total) ? r0 + per : total;
+    if (r0 >= r1) return;
+    int idx[kSearchCal];
+    unrank(r0, nc, M, idx);
+    SetFit F;
+    int lead = fit_rows(g, h, 0, M - 1, idx, F);  // first dependent leading position, or M - 1
+    for (int r = r0;;) {
+        double v;
+        if (lead == M - 1 && last_value<M>(g, h, S, idx, F, &v) && v < bv) {
+            bv = v;
+            br = r;
+        }
+        if (++r >= r1) break;
+        const int q = next_comb(nc, M, idx);
+        if (q < M - 1 && q <= lead) lead = fit_rows(g, h, q, M - 1, idx, F);
+    }
+}
+
+// One row of the search.  FIRST: an F row with more than NCAP candidates is
+// marked for the second pass; otherwise (NCAP = kSearchCand) such a row is
+// left empty with status 4.
+template <typename T, int K, int NCAP, bool FIRST>
+__device__ void search_row(int i, int lane, SearchLds<T, K, NCAP>& L, const int* __restrict__ rp,
+                           const int* __restrict__ ci, const T* __restrict__ av,
+                           const int* __restrict__ rpg, const int* __restrict__ cig,
+                           const T* __restrict__ X, const double* __restrict__ w,
+                           const uint8_t* __restrict__ cf, int cal, double gamma, int target,
+                           int* __restrict__ Pcol, double* __restrict__ Pval,
+                           double* __restrict__ lsv, int* __restrict__ rstat, unsigned* status) {
     int* pc = Pcol + (size_t)i * cal;
     double* pv = Pval + (size_t)i * cal;
     if (cf[i]) {  // a C point interpolates itself
@@ -419,6 +497,27 @@ __global__ __launch_bounds__(kWave) void ls_search_kernel(
             rstat[i] = 0;
         }
         return;
+    }
+    // candidates: C points of row i of the pattern, i excluded, in column order
+    const int g0 = rpg[i], g1 = rpg[i + 1];
+    int nc = 0;
+    for (int e0 = g0; e0 < g1; e0 += kWave) {
+        const int e = e0 + lane;
+        const int j = e < g1 ? cig[e] : -1;
+        const bool isc = j >= 0 && j != i && cf[j] != 0;
+        const uint64_t bal = __ballot(isc);
+        const int pos = nc + __popcll(bal & ((lane == 0) ? 0ull : (~0ull >> (64 - lane))));
+        if (isc && pos < NCAP) L.cand[pos] = j;
+        nc += __popcll(bal);
+    }
+    if (FIRST && nc > NCAP) {
+        if (lane == 0) rstat[i] = kSearchMarked;
+        return;
+    }
+    bool over = false;
+    if (nc > NCAP) {
+        over = true;
+        nc = NCAP;
     }
     int st = 0;
     // target (FP64): lane k holds t_k
@@ -441,36 +540,19 @@ __global__ __launch_bounds__(kWave) void ls_search_kernel(
     }
     st = __shfl(st, 0, kWave);
     if (st == 3 && lane == 0) flag(status, AD_STAT_ZERO_DIAG);
-    // candidates: C points of row i of the pattern, i excluded, in column order
-    const int g0 = rpg[i], g1 = rpg[i + 1];
-    int nc = 0;
-    bool over = false;
-    for (int e0 = g0; e0 < g1; e0 += kWave) {
-        const int e = e0 + lane;
-        const int j = e < g1 ? cig[e] : -1;
-        const bool isc = j >= 0 && j != i && cf[j] != 0;
-        const uint64_t bal = __ballot(isc);
-        const int pos = nc + __popcll(bal & ((lane == 0) ? 0ull : (~0ull >> (64 - lane))));
-        if (isc && pos < kSearchCand) L.cand[pos] = j;
-        nc += __popcll(bal);
-    }
-    if (nc > kSearchCand) {
-        over = true;
-        nc = kSearchCand;
-    }
-    __syncthreads();
-    // candidate rows (FP64) and the target's functional S = <t, t>_w
+    wave_sync_lds();
+    // candidate rows and the target's functional S = <t, t>_w
     for (int q = lane; q < nc * K; q += kWave) {
         const int a = q / K, k = q % K;
-        L.x[a][k] = (double)X[(size_t)L.cand[a] * K + k];
+        L.x[a][k] = X[(size_t)L.cand[a] * K + k];
     }
-    __syncthreads();
+    wave_sync_lds();
     double S = 0.0;
     for (int k = 0; k < K; ++k) S = fma(L.w[k] * L.t[k], L.t[k], S);
     // h_a and the Gram matrix of the candidates
     if (lane < nc) {
         double s = 0.0;
-        for (int k = 0; k < K; ++k) s = fma(L.w[k] * L.x[lane][k], L.t[k], s);
+        for (int k = 0; k < K; ++k) s = fma(L.w[k] * (double)L.x[lane][k], L.t[k], s);
         L.h[lane] = s;
     }
     const int npair = nc * (nc + 1) / 2;
@@ -480,73 +562,84 @@ __global__ __launch_bounds__(kWave) void ls_search_kernel(
         while ((a + 1) * (a + 2) / 2 <= p) ++a;
         const int b = p - a * (a + 1) / 2;
         double s = 0.0;
-        for (int k = 0; k < K; ++k) s = fma(L.w[k] * L.x[a][k], L.x[b][k], s);
+        for (int k = 0; k < K; ++k) s = fma(L.w[k] * (double)L.x[a][k], (double)L.x[b][k], s);
         L.g[p] = s;
     }
-    __syncthreads();
+    wave_sync_lds();
 
-    // best set of each size, then the penalty rule against the incumbent
-    int inc_m = 0;
-    int inc_idx[kSearchCal] = {0, 0, 0, 0};
-    double inc_v = 0.0;
+    // best set of each size (its value and rank; rank = total: none fitted)
     // a row past the candidate cap is left empty (status 4)
     const int mmax = over ? 0 : (cal < nc ? cal : nc);
+    double bvs[kSearchCal];
+    int brs[kSearchCal];
+#pragma unroll
+    for (int q = 0; q < kSearchCal; ++q) {
+        bvs[q] = INFINITY;
+        brs[q] = 0x7fffffff;
+    }
     for (int m = 1; m <= mmax; ++m) {
-        const int64_t total = binom_small(nc, m);
-        const int64_t per = (total + kWave - 1) / kWave;
-        const int64_t r0 = (int64_t)lane * per, r1 = (r0 + per < total) ? r0 + per : total;
+        const int total = binom_small(nc, m);
         double bv = INFINITY;
-        int64_t br = total;
-        if (r0 < r1) {
-            int idx[kSearchCal];
-            unrank(r0, nc, m, idx);
-            for (int64_t r = r0; r < r1; ++r) {
-                double v;
-                if (subset_fit(L.g, L.h, S, m, idx, &v, nullptr) && v < bv) {
-                    bv = v;
-                    br = r;
-                }
-                next_comb(nc, m, idx);
-            }
+        int br = total;
+        switch (m) {
+            case 1: best_of_size<1>(L.g, L.h, S, nc, lane, bv, br); break;
+            case 2: best_of_size<2>(L.g, L.h, S, nc, lane, bv, br); break;
+            case 3: best_of_size<3>(L.g, L.h, S, nc, lane, bv, br); break;
+            default: best_of_size<4>(L.g, L.h, S, nc, lane, bv, br); break;
         }
         // least (value, rank) over the wave: lanes hold increasing rank blocks
 #pragma unroll
         for (int o = kWave / 2; o > 0; o >>= 1) {
             const double ov = __shfl_xor(bv, o, kWave);
-            const int64_t orr = __shfl_xor(br, o, kWave);
+            const int orr = __shfl_xor(br, o, kWave);
             if (ov < bv || (ov == bv && orr < br)) {
                 bv = ov;
                 br = orr;
             }
         }
-        if (br >= total) continue;  // every set of this size was dependent
-        int idx[kSearchCal];
-        unrank(br, nc, m, idx);
+        if (br >= total) br = 0x7fffffff;  // every set of this size was dependent
+#pragma unroll
+        for (int q = 0; q < kSearchCal; ++q)
+            if (q == m - 1) {
+                bvs[q] = bv;
+                brs[q] = br;
+            }
+    }
+    // the penalty rule: a scan in increasing size against the incumbent
+    int inc_m = 0, inc_r = 0;
+    double inc_v = 0.0;
+#pragma unroll
+    for (int q = 0; q < kSearchCal; ++q) {
+        const int m = q + 1;
+        if (m > mmax || brs[q] == 0x7fffffff) continue;
         bool take = inc_m == 0;
         if (!take) {
-            const double rel = S > 0.0 ? bv / S : 0.0;
+            const double rel = S > 0.0 ? bvs[q] / S : 0.0;
             const double inc_rel = S > 0.0 ? inc_v / S : 0.0;
             take = rel < pow(inc_rel, gamma * (double)(m - inc_m));
         }
         if (take) {
             inc_m = m;
-            inc_v = bv;
-#pragma unroll
-            for (int q = 0; q < kSearchCal; ++q) inc_idx[q] = idx[q];
+            inc_v = bvs[q];
+            inc_r = brs[q];
         }
     }
+    int inc_idx[kSearchCal] = {0, 0, 0, 0};
+    if (inc_m > 0) unrank(inc_r, nc, inc_m, inc_idx);
 
     // the chosen set: weights by its Cholesky solve, functional by definition
     double coef[kSearchCal] = {0.0, 0.0, 0.0, 0.0};
     double val;
     if (inc_m > 0) {
-        subset_fit(L.g, L.h, S, inc_m, inc_idx, &val, coef);
+        SetFit F;
+        fit_rows(L.g, L.h, 0, inc_m, inc_idx, F);
+        fit_coef(F, inc_m, coef);
         double r = 0.0;
         if (lane < K) {
             r = L.t[lane];
 #pragma unroll
             for (int a = 0; a < kSearchCal; ++a)
-                if (a < inc_m) r -= coef[a] * L.x[inc_idx[a]][lane];
+                if (a < inc_m) r -= coef[a] * (double)L.x[inc_idx[a]][lane];
             r = L.w[lane] * r * r;
         }
 #pragma unroll
@@ -572,6 +665,37 @@ __global__ __launch_bounds__(kWave) void ls_search_kernel(
         rstat[i] = over ? 4 : (inc_m == 0 ? (st ? st : 1) : st);
         if (over) flag(status, AD_STAT_SEARCH_CAP);
     }
+    wave_sync_lds();  // the slice is reused by the wavefront's next row
+}
+
+// Each wavefront takes a chunk of 64 consecutive rows.  FIRST: every row of
+// the chunk; second pass: the chunk's rows marked by the first.
+template <typename T, int K, int NCAP, int WAVES, bool FIRST>
+__global__ __launch_bounds__(kWave* WAVES) void ls_search_kernel(
+    int n, const int* __restrict__ rp, const int* __restrict__ ci, const T* __restrict__ av,
+    const int* __restrict__ rpg, const int* __restrict__ cig, const T* __restrict__ X,
+    const double* __restrict__ w, const uint8_t* __restrict__ cf, int cal, double gamma,
+    int target, int* __restrict__ Pcol, double* __restrict__ Pval, double* __restrict__ lsv,
+    int* __restrict__ rstat, unsigned* status) {
+    __shared__ SearchLds<T, K, NCAP> L[WAVES];
+    const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
+    const int64_t i0 = ((int64_t)blockIdx.x * WAVES + wv) * kWave;
+    if (i0 >= n) return;  // whole wavefront
+    const int i1 = (int)(i0 + kWave < n ? i0 + kWave : n);
+    if (FIRST) {
+        for (int i = (int)i0; i < i1; ++i)
+            search_row<T, K, NCAP, true>(i, lane, L[wv], rp, ci, av, rpg, cig, X, w, cf, cal,
+                                         gamma, target, Pcol, Pval, lsv, rstat, status);
+    } else {
+        const int me = (int)i0 + lane;
+        uint64_t marked = __ballot(me < i1 && rstat[me] == kSearchMarked);
+        while (marked) {
+            const int q = __builtin_ctzll(marked);
+            marked &= marked - 1;
+            search_row<T, K, NCAP, false>((int)i0 + q, lane, L[wv], rp, ci, av, rpg, cig, X, w,
+                                          cf, cal, gamma, target, Pcol, Pval, lsv, rstat, status);
+        }
+    }
 }
 
 template <typename T>
@@ -581,7 +705,14 @@ static int ls_search_dispatch(int K, const ad_csr* A, const int* rpg, const int*
                               int* rstat, unsigned* status, hipStream_t s) {
     return with_k<T>(K, [&](auto kc) {
         constexpr int KK = decltype(kc)::value;
-        ls_search_kernel<T, KK><<<dim3((unsigned)A->n), dim3(kWave), 0, s>>>(
+        constexpr int W1 = 4, W2 = 1;
+        const int64_t chunks = ((int64_t)A->n + kWave - 1) / kWave;
+        const unsigned g1 = (unsigned)((chunks + W1 - 1) / W1);
+        const unsigned g2 = (unsigned)((chunks + W2 - 1) / W2);
+        ls_search_kernel<T, KK, kSearchFast, W1, true><<<dim3(g1), dim3(kWave * W1), 0, s>>>(
+            A->n, A->row_ptr, A->col, (const T*)A->val, rpg, cig, (const T*)X, w, cf, cal, gamma,
+            target, Pcol, Pval, lsv, rstat, status);
+        ls_search_kernel<T, KK, kSearchCand, W2, false><<<dim3(g2), dim3(kWave * W2), 0, s>>>(
             A->n, A->row_ptr, A->col, (const T*)A->val, rpg, cig, (const T*)X, w, cf, cal, gamma,
             target, Pcol, Pval, lsv, rstat, status);
         return (int)AD_OK;

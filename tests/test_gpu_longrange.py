@@ -145,38 +145,45 @@ def _scan_sizes(best_rel, gamma, tol=1e-6):
     return inc_m, near
 
 
-def check_search(A, G, x, w, cf, cal, gamma, target, got, dt):
-    """GPU search results `got` against the oracle (see the module doc)."""
-    Gp = oracle.Pattern(A.n, to_np(G.row_ptr), to_np(G.col))
+def check_search(A, G, x, w, cf, cal, gamma, target, got, dt, rows=None, Gp=None):
+    """GPU search results `got` against the oracle (see the module doc), on
+    every row or on the given rows."""
+    if Gp is None:
+        Gp = oracle.Pattern(A.n, to_np(G.row_ptr), to_np(G.col))
     tg = oracle.TARGET_PLAIN if target == "plain" else oracle.TARGET_RESIDUAL
-    Rc, Rv, Rl, Rs, best, nc = oracle.ls_search(A, Gp, x, w, cf, cal, gamma, tg)
+    Rc, Rv, Rl, Rs, best, nc = oracle.ls_search(A, Gp, x, w, cf, cal, gamma, tg, rows=rows)
     Pc, Pv, ls, st = (to_np(t) for t in got)
-    assert np.array_equal(st, Rs), "status differ at %s" % np.nonzero(st != Rs)[0][:5]
+    ids = np.arange(A.n) if rows is None else np.asarray(rows)
+    Pc, Pv, ls, st, cfr = Pc[ids], Pv[ids], ls[ids], st[ids], cf[ids]
+    assert np.array_equal(st, Rs), "status differ at %s" % ids[np.nonzero(st != Rs)[0][:5]]
     same = np.all(Pc == Rc, axis=1)
     diff_rows = np.nonzero(~same)[0]
-    say("  rows %d, F rows %d, sets differ in %d rows" % (A.n, int((cf == 0).sum()), len(diff_rows)))
+    say("  rows %d, F rows %d, sets differ in %d rows; candidates %d..%d"
+        % (len(ids), int((cfr == 0).sum()), len(diff_rows), nc.min(), nc.max()))
     S = best[:, 0]
-    for i in diff_rows:
-        assert cf[i] == 0
-        mine = [c for c in Pc[i] if c >= 0]
+    for q in diff_rows:
+        i = ids[q]
+        assert cfr[q] == 0
+        mine = [c for c in Pc[q] if c >= 0]
         m_g = len(mine)
         assert m_g >= 1
-        pv, lv, rd = oracle.ls_fit_sets(A, x, w, np.array([list(Pc[i])]), [i], tg)
+        pv, lv, rd = oracle.ls_fit_sets(A, x, w, np.array([list(Pc[q])]), [i], tg)
         assert rd[0] == 0
-        rel = lv[0] / S[i] if S[i] > 0 else 0.0
+        rel = lv[0] / S[q] if S[q] > 0 else 0.0
         # a (near-)best set of its size ...
-        assert rel <= best[i, m_g] * (1 + 1e-7) + 1e-13, (i, rel, best[i, m_g])
+        assert rel <= best[q, m_g] * (1 + 1e-7) + 1e-13, (i, rel, best[q, m_g])
         # ... and a size the penalty scan reaches within rounding
-        m_o, near = _scan_sizes(list(best[i]), gamma)
+        m_o, near = _scan_sizes(list(best[q]), gamma)
         assert m_g == m_o or near, (i, m_g, m_o)
-    assert len(diff_rows) <= max(2, 0.002 * A.n)
-    ok = same & (cf == 0)
+    assert len(diff_rows) <= max(2, 0.002 * len(ids))
+    ok = same & (cfr == 0)
     perr = np.abs(Pv - Rv)[ok] / np.maximum(1.0, np.abs(Rv[ok]))
     assert np.all(perr <= 1e-6), perr.max()
     lerr = np.abs(ls - Rl)[ok]
     assert np.all(lerr <= 1e-6 * np.abs(Rl[ok]) + 1e-12 * S[ok]), lerr.max()
-    c = cf != 0
-    assert np.all(Pc[c, 0] == np.nonzero(c)[0]) and np.all(Pv[c, 0] == 1.0)
+    c = cfr != 0
+    assert np.all(Pc[c, 0] == ids[c]) and np.all(Pv[c, 0] == 1.0)
+    return nc
 
 
 @pytest.mark.parametrize("dt", [torch.float64, torch.float32])
@@ -218,6 +225,73 @@ def test_search_weights_gamma_and_graph_rows(gamma):
     got = ad.ls_interp_search(Ad, G, X, torch.as_tensor(cf, device="cuda"), 3, gamma,
                               w=torch.as_tensor(w, device="cuda"))
     check_search(A, G, x, w, cf, 3, gamma, "plain", got, torch.float64)
+    assert ad.status(clear=True) == 0
+
+
+@pytest.mark.parametrize("dt,target,d,cal", [(torch.float64, "plain", 4, 2),
+                                             (torch.float32, "residual", 4, 3),
+                                             (torch.float64, "residual", 5, 2),
+                                             (torch.float32, "plain", 6, 2)])
+def test_search_rows_past_the_first_pass(dt, target, d, cal):
+    """Rows with 33 to 64 candidates are searched by the second pass: an
+    interior F row of the 9-point operator has 2d(d + 1) C-points in the
+    pattern of A^d (40, 60 and 84 for d = 4, 5, 6); rows near the boundary
+    have fewer and stay in the first pass, and A^6's interior rows, past
+    64, are left empty with status 4."""
+    ad = lib()
+    N, K = 17, 16
+    A = W.rotated_anisotropic_9pt(N, 1e-3, math.pi / 6)
+    if dt == torch.float32:
+        A = W.CSR(A.n, A.row_ptr, A.col, A.val.astype(np.float32).astype(np.float64))
+    Ad = dev_csr(A, dt)
+    color = torch.as_tensor(W.red_black((N, N)), device="cuda")
+    X = ad.setup_testvectors(Ad, K, seed=6, relax="gs", sweeps=4, color=color, ncolors=2)
+    x = to_np(X).astype(np.float64)
+    cf = W.cf_red_is_coarse((N, N))
+    G = ad.power_graph(Ad, d)
+    say("search past the first pass: %s %s d=%d caliber=%d" % (dt, target, d, cal))
+    got = ad.ls_interp_search(Ad, G, X, torch.as_tensor(cf, device="cuda"), cal, 1.5,
+                              target=target)
+    rp, col = to_np(G.row_ptr), to_np(G.col)
+    rid = np.repeat(np.arange(A.n), np.diff(rp))
+    nc = np.bincount(rid, weights=(cf[col] != 0) & (col != rid), minlength=A.n).astype(int)
+    F = cf == 0
+    assert np.any((nc[F] > 32) & (nc[F] <= 64)) and np.any((nc[F] <= 32) & (nc[F] > 0))
+    assert nc[F].max() == {4: 40, 5: 60, 6: 84}[d]
+    # rows past the cap: empty, status 4, functional of the empty set
+    over = np.nonzero(F & (nc > 64))[0]
+    Pc, _, ls, st = (to_np(t) for t in got)
+    assert np.all(st[over] == 4) and np.all(Pc[over] == -1)
+    T = x if target == "plain" else None
+    if T is not None:
+        assert np.allclose(ls[over], (T[over] * T[over]).sum(1), rtol=1e-12, atol=0)
+    assert bool(ad.status(clear=True) & ad.STAT_SEARCH_CAP) == (len(over) > 0)
+    rows = np.nonzero(~(F & (nc > 64)))[0].astype(np.int32)
+    check_search(A, G, x, None, cf, cal, 1.5, target, got, dt, rows=rows)
+
+
+def test_search_full_size_sampled():
+    """The bench's long-range configuration: the 2048^2 anisotropic 9-point
+    operator in FP32, test vectors from 5 colour-phase sweeps, the pattern
+    of A^2, caliber 4, gamma 1.5; 2048 sampled rows against the oracle."""
+    ad = lib()
+    ad.status(clear=True)
+    wl = W.workload(2, "f32")
+    A = wl.A
+    Ad = dev_csr(A, torch.float32)
+    color = torch.as_tensor(wl.color, device="cuda")
+    X = ad.setup_testvectors(Ad, wl.K, seed=wl.tv_seed, relax="gs", sweeps=wl.sweeps,
+                             color=color, ncolors=wl.ncolors)
+    G = ad.power_graph(Ad, 2)
+    say("search full size: n %d, pattern entries %d" % (A.n, G.nnz))
+    got = ad.ls_interp_search(Ad, G, X, torch.as_tensor(wl.cf, device="cuda"), 4, 1.5)
+    rng = np.random.default_rng(5)
+    rows = np.unique(np.concatenate([rng.choice(A.n, 2048, replace=False), [0, 1, A.n - 1]]))
+    rows = rows.astype(np.int32)
+    Gp = oracle.Pattern(A.n, to_np(G.row_ptr), to_np(G.col))
+    check_search(A, G, to_np(X).astype(np.float64), None, wl.cf, 4, 1.5, "plain", got,
+                 torch.float32, rows=rows, Gp=Gp)
+    assert np.all(to_np(got[3]) == 0)
     assert ad.status(clear=True) == 0
 
 
