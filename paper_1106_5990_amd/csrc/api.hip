@@ -1127,7 +1127,10 @@ struct GalerkinCtx {
         w.pt = b.get<int64_t>((size_t)n + 1);
         w.ptkey = b.get<int64_t>((size_t)n * caliber);
         w.maxslots = b.get<int>(1);
-        ok = w.flags && w.scan && w.scan_tmp && w.cidx && w.cnt && w.pt && w.ptkey && w.maxslots;
+        w.spill = b.get<int>(n);
+        w.nspill = b.get<int>(1);
+        ok = w.flags && w.scan && w.scan_tmp && w.cidx && w.cnt && w.pt && w.ptkey && w.maxslots &&
+             w.spill && w.nspill;
     }
 };
 

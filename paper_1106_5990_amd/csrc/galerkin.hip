@@ -119,23 +119,31 @@ __global__ __launch_bounds__(kBlock) void gal_slots_kernel(int nc, const int* __
     atomicMax(maxslots, v);
 }
 
-// One coarse row per workgroup of one wavefront.  count pass: cnt[I] =
-// distinct columns; fill pass (rpc given): colc / valc.
+// Coarse rows by product keys and a sort, one row at a time per workgroup
+// of one wavefront: the rows the lane kernel below could not hold.  count
+// pass: cnt[I] = distinct columns; fill pass (rpc given): colc / valc.
+struct GalRowLds {
+    int64_t key[kGalCap];
+    double val[kGalCap];
+    int s_i[kGalT];
+    double s_p[kGalT];
+    int s_base[kGalT + 1];
+};
+
 template <typename TA>
-__global__ __launch_bounds__(kGalWave) void galerkin_row_kernel(
-    int n, int nc, const int* __restrict__ rp, const int* __restrict__ ci, const TA* __restrict__ av,
-    int cal, const int* __restrict__ Pc, const double* __restrict__ Pv,
-    const int* __restrict__ cidx, const int64_t* __restrict__ pt,
-    const int64_t* __restrict__ ptkey, const int* __restrict__ rpc, int* __restrict__ cnt,
-    int* __restrict__ colc, double* __restrict__ valc) {
-    __shared__ int64_t key[kGalCap];
-    __shared__ double val[kGalCap];
-    __shared__ int s_i[kGalT];
-    __shared__ double s_p[kGalT];
-    __shared__ int s_base[kGalT + 1];
-    const int I = blockIdx.x;
+__device__ void galerkin_row_wave(int I, GalRowLds& L, int n, const int* __restrict__ rp,
+                                  const int* __restrict__ ci, const TA* __restrict__ av, int cal,
+                                  const int* __restrict__ Pc, const double* __restrict__ Pv,
+                                  const int* __restrict__ cidx, const int64_t* __restrict__ pt,
+                                  const int64_t* __restrict__ ptkey, const int* __restrict__ rpc,
+                                  int* __restrict__ cnt, int* __restrict__ colc,
+                                  double* __restrict__ valc) {
+    int64_t* key = L.key;
+    double* val = L.val;
+    int* s_i = L.s_i;
+    double* s_p = L.s_p;
+    int* s_base = L.s_base;
     const int lane = threadIdx.x;
-    if (I >= nc) return;
     const int64_t t0 = pt[I];
     const int nt = (int)(pt[I + 1] - t0);  // <= kGalT (checked on the host)
     int len = 0;
@@ -219,6 +227,7 @@ __global__ __launch_bounds__(kGalWave) void galerkin_row_kernel(
     }
     if (!rpc) {
         if (lane == kGalWave - 1) cnt[I] = sincl;
+        __syncthreads();  // LDS is reused by the workgroup's next row
         return;
     }
     int rank = sincl - starts;
@@ -234,6 +243,102 @@ __global__ __launch_bounds__(kGalWave) void galerkin_row_kernel(
         colc[out0 + rank] = (int)J;
         valc[out0 + rank] = acc;
         ++rank;
+    }
+    __syncthreads();  // LDS is reused by the workgroup's next row
+}
+
+template <typename TA>
+__global__ __launch_bounds__(kGalWave) void galerkin_row_kernel(
+    int n, const int* __restrict__ rp, const int* __restrict__ ci, const TA* __restrict__ av,
+    int cal, const int* __restrict__ Pc, const double* __restrict__ Pv,
+    const int* __restrict__ cidx, const int64_t* __restrict__ pt,
+    const int64_t* __restrict__ ptkey, const int* __restrict__ rpc, int* __restrict__ cnt,
+    int* __restrict__ colc, double* __restrict__ valc, const int* __restrict__ rows,
+    const int* __restrict__ nrows) {
+    __shared__ GalRowLds L;
+    const int m = *nrows;
+    for (int x = blockIdx.x; x < m; x += gridDim.x)
+        galerkin_row_wave<TA>(rows[x], L, n, rp, ci, av, cal, Pc, Pv, cidx, pt, ptkey, rpc, cnt,
+                              colc, valc);
+}
+
+// One coarse row per lane: the row's products in the order the expansion
+// generates them (P^T entries by (i, slot), then row i of A, then row j's
+// slots), each added into the lane's LDS map of distinct coarse columns,
+// kept sorted by column (binary search, insertion by shifting).  Products
+// and sums are explicitly rounded, so each coefficient is the same sum as
+// the sort kernel's.  A row with more than kGalMap distinct columns is
+// appended to the spill list (in no particular order) and left to the sort
+// kernel.  count pass (FILL false): cnt[I]; fill pass: colc / valc.
+constexpr int kGalMap = 32;
+
+template <typename TA, bool FILL>
+__global__ __launch_bounds__(kWave) void galerkin_lane_kernel(
+    int n, int nc, const int* __restrict__ rp, const int* __restrict__ ci,
+    const TA* __restrict__ av, int cal, const int* __restrict__ Pc, const double* __restrict__ Pv,
+    const int* __restrict__ cidx, const int64_t* __restrict__ pt,
+    const int64_t* __restrict__ ptkey, const int* __restrict__ rpc, int* __restrict__ cnt,
+    int* __restrict__ colc, double* __restrict__ valc, int* __restrict__ spill,
+    int* __restrict__ nspill) {
+    __shared__ int mcol[kGalMap][kWave];
+    __shared__ double mval[FILL ? kGalMap : 1][kWave];
+    const int lane = threadIdx.x;
+    const int64_t I64 = (int64_t)blockIdx.x * kWave + lane;
+    if (I64 >= nc) return;  // no workgroup barriers below
+    const int I = (int)I64;
+    int m = 0;
+    bool over = false;
+    const int64_t t1 = pt[I + 1];
+    for (int64_t t = pt[I]; t < t1 && !over; ++t) {
+        const int64_t k = ptkey[t];
+        const int i = (int)(k / cal);
+        const double piI = Pv[k];
+        const int e1 = rp[i + 1];
+        for (int e = rp[i]; e < e1 && !over; ++e) {
+            const int j = ci[e];
+            const double pa = __dmul_rn(piI, (double)av[e]);
+            for (int q = 0; q < cal; ++q) {
+                const int c = Pc[(int64_t)j * cal + q];
+                if (c < 0 || c >= n) continue;
+                const int J = cidx[c];
+                if (J < 0) continue;
+                const double prod = __dmul_rn(pa, Pv[(int64_t)j * cal + q]);
+                int lo = 0, hi = m;  // first map position whose column is >= J
+                while (lo < hi) {
+                    const int mid = (lo + hi) >> 1;
+                    if (mcol[mid][lane] < J) lo = mid + 1;
+                    else hi = mid;
+                }
+                if (lo < m && mcol[lo][lane] == J) {
+                    if (FILL) mval[lo][lane] = __dadd_rn(mval[lo][lane], prod);
+                    continue;
+                }
+                if (m == kGalMap) {
+                    over = true;
+                    break;
+                }
+                for (int x = m; x > lo; --x) {
+                    mcol[x][lane] = mcol[x - 1][lane];
+                    if (FILL) mval[x][lane] = mval[x - 1][lane];
+                }
+                mcol[lo][lane] = J;
+                if (FILL) mval[lo][lane] = prod;
+                ++m;
+            }
+        }
+    }
+    if (over) {
+        spill[atomicAdd(nspill, 1)] = I;
+        return;
+    }
+    if (!FILL) {
+        cnt[I] = m;
+        return;
+    }
+    const int64_t o = rpc[I];
+    for (int x = 0; x < m; ++x) {
+        colc[o + x] = mcol[x][lane];
+        valc[o + x] = mval[x][lane];
     }
 }
 
@@ -500,6 +605,40 @@ int galerkin_transpose(const GalerkinIn& g, GalerkinWork& w, int nc, unsigned* s
     return AD_OK;
 }
 
+// The products of every coarse row: the lane kernel, then the sort kernel
+// on the rows it spilled (count pass: rpc == nullptr, counts into cnt).
+template <typename TA>
+static int galerkin_products_t(const GalerkinIn& g, GalerkinWork& w, int nc, const int* rpc,
+                               int* cnt, int* colc, double* valc, hipStream_t s) {
+    int rc;
+    if ((rc = launch_fill_i32(w.nspill, 1, 0, s))) return rc;
+    const unsigned nb = nblocks(nc, kWave);
+    if (rpc)
+        galerkin_lane_kernel<TA, true><<<dim3(nb), dim3(kWave), 0, s>>>(
+            g.n, nc, g.rp, g.ci, (const TA*)g.av, g.cal, g.Pc, g.Pv, w.cidx, w.pt, w.ptkey, rpc,
+            cnt, colc, valc, w.spill, w.nspill);
+    else
+        galerkin_lane_kernel<TA, false><<<dim3(nb), dim3(kWave), 0, s>>>(
+            g.n, nc, g.rp, g.ci, (const TA*)g.av, g.cal, g.Pc, g.Pv, w.cidx, w.pt, w.ptkey, rpc,
+            cnt, colc, valc, w.spill, w.nspill);
+    AD_HIP(hipGetLastError());
+    // a fixed grid walks the spill list (its length stays on the device)
+    const unsigned grid = (unsigned)(nc < 1024 ? nc : 1024);
+    galerkin_row_kernel<TA><<<dim3(grid), dim3(kGalWave), 0, s>>>(
+        g.n, g.rp, g.ci, (const TA*)g.av, g.cal, g.Pc, g.Pv, w.cidx, w.pt, w.ptkey, rpc, cnt, colc,
+        valc, w.spill, w.nspill);
+    AD_HIP(hipGetLastError());
+    return AD_OK;
+}
+
+static int galerkin_products(const GalerkinIn& g, GalerkinWork& w, int nc, const int* rpc,
+                             int* cnt, int* colc, double* valc, hipStream_t s) {
+    if (nc == 0) return AD_OK;
+    return g.dtype == AD_F32
+               ? galerkin_products_t<float>(g, w, nc, rpc, cnt, colc, valc, s)
+               : galerkin_products_t<double>(g, w, nc, rpc, cnt, colc, valc, s);
+}
+
 int galerkin_rows_run(const GalerkinIn& g, GalerkinWork& w, int nc, int* rpc, int64_t* nnz_c,
                       hipStream_t s) {
     int rc;
@@ -511,17 +650,7 @@ int galerkin_rows_run(const GalerkinIn& g, GalerkinWork& w, int nc, int* rpc, in
     AD_HIP(hipMemcpyAsync(&mx, w.maxslots, sizeof mx, hipMemcpyDeviceToHost, s));
     AD_HIP(hipStreamSynchronize(s));
     if (mx > kGalCap) return AD_EUNSUPPORTED;
-    if (nc > 0) {
-        if (g.dtype == AD_F32)
-            galerkin_row_kernel<float><<<dim3(nc), dim3(kGalWave), 0, s>>>(
-                g.n, nc, g.rp, g.ci, (const float*)g.av, g.cal, g.Pc, g.Pv, w.cidx, w.pt, w.ptkey,
-                nullptr, w.cnt, nullptr, nullptr);
-        else
-            galerkin_row_kernel<double><<<dim3(nc), dim3(kGalWave), 0, s>>>(
-                g.n, nc, g.rp, g.ci, (const double*)g.av, g.cal, g.Pc, g.Pv, w.cidx, w.pt, w.ptkey,
-                nullptr, w.cnt, nullptr, nullptr);
-        AD_HIP(hipGetLastError());
-    }
+    if ((rc = galerkin_products(g, w, nc, nullptr, w.cnt, nullptr, nullptr, s))) return rc;
     // row pointers: exclusive scan of the counts (int64), narrowed to int32
     if ((rc = launch_excl_scan(w.cnt, nc, w.scan, w.scan_tmp, s))) return rc;
     int64_t tot = 0;
@@ -535,17 +664,7 @@ int galerkin_rows_run(const GalerkinIn& g, GalerkinWork& w, int nc, int* rpc, in
 
 int galerkin_cols_run(const GalerkinIn& g, GalerkinWork& w, int nc, const int* rpc, int* colc,
                       double* valc, hipStream_t s) {
-    if (nc == 0) return AD_OK;
-    if (g.dtype == AD_F32)
-        galerkin_row_kernel<float><<<dim3(nc), dim3(kGalWave), 0, s>>>(
-            g.n, nc, g.rp, g.ci, (const float*)g.av, g.cal, g.Pc, g.Pv, w.cidx, w.pt, w.ptkey, rpc,
-            nullptr, colc, valc);
-    else
-        galerkin_row_kernel<double><<<dim3(nc), dim3(kGalWave), 0, s>>>(
-            g.n, nc, g.rp, g.ci, (const double*)g.av, g.cal, g.Pc, g.Pv, w.cidx, w.pt, w.ptkey, rpc,
-            nullptr, colc, valc);
-    AD_HIP(hipGetLastError());
-    return AD_OK;
+    return galerkin_products(g, w, nc, rpc, nullptr, colc, valc, s);
 }
 
 // diagonal entries of the row-major nc x nc matrix M set to 1 (M zeroed)

@@ -282,6 +282,8 @@ struct GalerkinWork {
     int64_t* pt;        // n + 1
     int64_t* ptkey;     // n * cal
     int* maxslots;      // 1
+    int* spill;         // n: coarse rows left to the sort kernel
+    int* nspill;        // 1
 };
 int galerkin_prepare(const GalerkinIn& g, GalerkinWork& w, int* nc_out, hipStream_t s);
 int galerkin_transpose(const GalerkinIn& g, GalerkinWork& w, int nc, unsigned* status,

@@ -64,6 +64,56 @@ def test_galerkin_bitwise(kind, N, longrange):
     assert lib().status(clear=True) == 0
 
 
+def test_galerkin_wide_rows_take_the_sort_kernel():
+    """Interpolation from random C points of a random geometric graph gives
+    coarse rows of more than 32 distinct columns (left by the lane kernel
+    to the sort kernel) beside narrower ones; A_c bit for bit either way."""
+    say("galerkin: wide coarse rows")
+    G = W.rgg_laplacian(600, 8.0, (3, 3), shift=0.5)
+    rng = np.random.default_rng(7)
+    cf = (rng.random(G.n) < 0.3).astype(np.uint8)
+    C = np.nonzero(cf)[0]
+    Pc = -np.ones((G.n, 3), np.int32)
+    Pv = np.zeros((G.n, 3))
+    for i in range(G.n):
+        if cf[i]:
+            Pc[i, 0], Pv[i, 0] = i, 1.0
+        else:
+            k = 1 + i % 3
+            Pc[i, :k] = np.sort(rng.choice(C, k, replace=False))
+            Pv[i, :k] = rng.random(k) - 0.3
+    Ac, ref = compare(G, Pc, Pv, cf)
+    ln = np.diff(ref.row_ptr)
+    say("  nc %d, row lengths %d..%d, %d rows past 32" % (ref.n, ln.min(), ln.max(), (ln > 32).sum()))
+    assert np.any(ln > 32) and np.any(ln <= 32)
+    assert lib().status(clear=True) == 0
+
+
+def test_galerkin_full_size():
+    """The 2048^2 anisotropic 9-point operator (FP32) with the CR coarse
+    grid and LS rows of its test vectors, as the bench forms it: A_c bit
+    for bit the oracle's over all 1.17 M coarse rows."""
+    say("galerkin full size")
+    ad = lib()
+    wl = W.workload(2, "f32")
+    A32 = W.CSR(wl.A.n, wl.A.row_ptr, wl.A.col, wl.A.val.astype(np.float32).astype(np.float64))
+    Ad = dev_csr(A32, torch.float32)
+    color = torch.as_tensor(wl.color, device="cuda")
+    X = ad.setup_testvectors(Ad, wl.K, seed=wl.tv_seed, relax="gs", sweeps=wl.sweeps,
+                             color=color, ncolors=wl.ncolors)
+    mu = ad.algebraic_distance(Ad, X)
+    cf, _, _ = ad.cr_coarsening(Ad, color, 2, mu, wl.theta, seed=1)
+    Pc, Pv, _, _ = ad.ls_interp(Ad, X, cf, mu, wl.caliber)
+    Ac = ad.galerkin(Ad, Pc, Pv, cf)
+    ref = oracle.galerkin(A32, to_np(Pc), to_np(Pv), to_np(cf))
+    say("  nc %d nnz_c %d" % (ref.n, ref.nnz))
+    assert Ac.n == ref.n
+    assert np.array_equal(to_np(Ac.row_ptr), ref.row_ptr)
+    assert np.array_equal(to_np(Ac.col), ref.col)
+    assert np.array_equal(to_np(Ac.val), ref.val)
+    assert ad.status(clear=True) == 0
+
+
 def test_galerkin_fp32_operator():
     A, color, cf, Pc, Pv = setup("aniso9", 32)
     A32 = W.CSR(A.n, A.row_ptr, A.col, A.val.astype(np.float32).astype(np.float64))
