@@ -151,16 +151,87 @@ __device__ __forceinline__ void pow_init(PowLds& L, int wv, int lane) {
     wave_sync_lds();
 }
 
+// ---------------------------------------------------------------- lane rows
+// For d <= 2 a row of A^d is {i} with N(i) and, for d = 2, N(j) of every j in
+// N(i): one lane per row merges these into its own LDS list, kept sorted
+// (binary search, insertion by shifting), of at most kPowLane entries.  The
+// count pass marks a row that outgrows the list (kPowMarked) for the
+// hash-set kernels; the fill pass takes the rows whose length (from the row
+// pointers) is at most kPowLane, keeping the kPowLane smallest columns.
+constexpr int kPowLane = 64;
+constexpr int kPowMarked = -2;
+
+template <bool FILL>
+__global__ __launch_bounds__(kWave) void pow_lane_kernel(int n, int d, const int* __restrict__ rp,
+                                                         const int* __restrict__ ci,
+                                                         int* __restrict__ cnt,
+                                                         const int* __restrict__ rpd,
+                                                         int* __restrict__ cid, unsigned* status) {
+    __shared__ int lst[kPowLane][kWave];
+    const int lane = threadIdx.x;
+    const int64_t i64 = (int64_t)blockIdx.x * kWave + lane;
+    if (i64 >= n) return;  // no workgroup barriers below
+    const int i = (int)i64;
+    int room = 0;
+    if (FILL) {
+        room = rpd[i + 1] - rpd[i];
+        if (room > kPowLane) return;  // a row for the hash-set kernel
+    }
+    int m = 0;
+    bool over = false;
+    auto insert = [&](int v) {
+        int lo = 0, hi = m;  // first position whose entry is >= v
+        while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if (lst[mid][lane] < v) lo = mid + 1;
+            else hi = mid;
+        }
+        if (lo < m && lst[lo][lane] == v) return;
+        if (m == kPowLane) {  // full: keep the kPowLane smallest
+            over = true;
+            if (lo == m) return;
+            --m;
+        }
+        for (int x = m; x > lo; --x) lst[x][lane] = lst[x - 1][lane];
+        lst[lo][lane] = v;
+        ++m;
+    };
+    insert(i);
+    const int e0 = rp[i], e1 = rp[i + 1];
+    for (int e = e0; e < e1; ++e) insert(ci[e]);
+    if (d == 2) {
+        for (int e = e0; e < e1 && (FILL || !over); ++e) {
+            const int j = ci[e];
+            const int f1 = rp[j + 1];
+            for (int f = rp[j]; f < f1 && (FILL || !over); ++f) insert(ci[f]);
+        }
+    }
+    if (!FILL) {
+        cnt[i] = over ? kPowMarked : m;
+        return;
+    }
+    // row pointers that do not match this row's length are flagged, and no
+    // entry is written outside the row
+    if (over || m != room) flag(status, AD_STAT_PATTERN);
+    const int cw = room < m ? room : m;
+    int* out = cid + rpd[i];
+    for (int x = 0; x < cw; ++x) out[x] = lst[x][lane];
+}
+
+// The hash-set kernels: every row (d > 2), or only the rows the lane
+// kernel left (count pass: marked; fill pass: longer than kPowLane).
 __global__ __launch_bounds__(kWave* kPowWaves) void pow_count_kernel(int n, int d,
                                                                      const int* __restrict__ rp,
                                                                      const int* __restrict__ ci,
-                                                                     int* __restrict__ cnt) {
+                                                                     int* __restrict__ cnt,
+                                                                     bool marked) {
     __shared__ PowLds L;
     const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
     const int64_t i0 = ((int64_t)blockIdx.x * kPowWaves + wv) * kPowRows;
     if (i0 >= n) return;  // whole wavefront
     pow_init(L, wv, lane);
     for (int64_t i = i0; i < i0 + kPowRows && i < n; ++i) {
+        if (marked && cnt[i] != kPowMarked) continue;
         const int c = pow_row((int)i, d, rp, ci, L, wv, lane);
         if (lane == 0) cnt[i] = c;
         pow_clear(L, wv, lane);
@@ -169,13 +240,14 @@ __global__ __launch_bounds__(kWave* kPowWaves) void pow_count_kernel(int n, int 
 
 __global__ __launch_bounds__(kWave* kPowWaves) void pow_fill_kernel(
     int n, int d, const int* __restrict__ rp, const int* __restrict__ ci,
-    const int* __restrict__ rpd, int* __restrict__ cid, unsigned* status) {
+    const int* __restrict__ rpd, int* __restrict__ cid, int lane_rows, unsigned* status) {
     __shared__ PowLds L;
     const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
     const int64_t i0 = ((int64_t)blockIdx.x * kPowWaves + wv) * kPowRows;
     if (i0 >= n) return;  // whole wavefront
     pow_init(L, wv, lane);
     for (int64_t i = i0; i < i0 + kPowRows && i < n; ++i) {
+        if (rpd[i + 1] - rpd[i] <= lane_rows) continue;  // done by the lane kernel
         const int c = pow_row((int)i, d, rp, ci, L, wv, lane);
         pow_clear(L, wv, lane);
         if (c < 0) continue;  // the count pass refused such a matrix
@@ -248,9 +320,16 @@ int launch_pow_rows(int n, int d, const int* rp, const int* ci, int* rpd, void* 
     int rc;
     if ((rc = launch_fill_i32(bad, 1, 0, s))) return rc;
     if (n > 0) {
+        const bool lanes = d <= 2;
+        if (lanes) {
+            const unsigned nl = (unsigned)(((int64_t)n + kWave - 1) / kWave);
+            pow_lane_kernel<false><<<dim3(nl), dim3(kWave), 0, s>>>(n, d, rp, ci, cnt, nullptr,
+                                                                   nullptr, nullptr);
+            AD_HIP(hipGetLastError());
+        }
         const int64_t per = (int64_t)kPowWaves * kPowRows;
         const unsigned nb = (unsigned)(((int64_t)n + per - 1) / per);
-        pow_count_kernel<<<dim3(nb), dim3(kWave * kPowWaves), 0, s>>>(n, d, rp, ci, cnt);
+        pow_count_kernel<<<dim3(nb), dim3(kWave * kPowWaves), 0, s>>>(n, d, rp, ci, cnt, lanes);
         AD_HIP(hipGetLastError());
     }
     if ((rc = launch_excl_scan(cnt, n, pre, (int64_t*)(w + o_sc), s))) return rc;
@@ -266,10 +345,17 @@ int launch_pow_rows(int n, int d, const int* rp, const int* ci, int* rpd, void* 
 int launch_pow_cols(int n, int d, const int* rp, const int* ci, const int* rpd, int* cid,
                     unsigned* status, hipStream_t s) {
     if (n == 0) return AD_OK;
+    const bool lanes = d <= 2;
+    if (lanes) {
+        const unsigned nl = (unsigned)(((int64_t)n + kWave - 1) / kWave);
+        pow_lane_kernel<true><<<dim3(nl), dim3(kWave), 0, s>>>(n, d, rp, ci, nullptr, rpd, cid,
+                                                              status);
+        AD_HIP(hipGetLastError());
+    }
     const int64_t per = (int64_t)kPowWaves * kPowRows;
     const unsigned nb = (unsigned)(((int64_t)n + per - 1) / per);
     pow_fill_kernel<<<dim3(nb), dim3(kWave * kPowWaves), 0, s>>>(n, d, rp, ci, rpd, cid,
-                                                                   status);
+                                                                   lanes ? kPowLane : -1, status);
     AD_HIP(hipGetLastError());
     return AD_OK;
 }

@@ -37,6 +37,8 @@ def _asym(n, seed, density):
 def _matrices():
     return {"lap5": W.laplacian_2d_5pt(33), "aniso9": W.rotated_anisotropic_9pt(30, 1e-3, 0.4),
             "rgg": W.rgg_laplacian(2000, 8.0, 11), "asym": _asym(300, 4, 0.01),
+            # rows of A^2 from 16 to 97 entries: both sides of the per-lane list
+            "rgg20": W.rgg_laplacian(1500, 20.0, 12),
             "lap3d": W.lognormal_3d_7pt(12, 1.0, 3), "one": W.laplacian_2d_5pt(1)}
 
 
@@ -273,7 +275,8 @@ def test_search_rows_past_the_first_pass(dt, target, d, cal):
 def test_search_full_size_sampled():
     """The bench's long-range configuration: the 2048^2 anisotropic 9-point
     operator in FP32, test vectors from 5 colour-phase sweeps, the pattern
-    of A^2, caliber 4, gamma 1.5; 2048 sampled rows against the oracle."""
+    of A^2 (every row against the oracle's), caliber 4, gamma 1.5; 2048
+    sampled rows of the search against the oracle."""
     ad = lib()
     ad.status(clear=True)
     wl = W.workload(2, "f32")
@@ -284,6 +287,8 @@ def test_search_full_size_sampled():
                              color=color, ncolors=wl.ncolors)
     G = ad.power_graph(Ad, 2)
     say("search full size: n %d, pattern entries %d" % (A.n, G.nnz))
+    R = oracle.power_pattern(A, 2)
+    assert np.array_equal(to_np(G.row_ptr), R.row_ptr) and np.array_equal(to_np(G.col), R.col)
     got = ad.ls_interp_search(Ad, G, X, torch.as_tensor(wl.cf, device="cuda"), 4, 1.5)
     rng = np.random.default_rng(5)
     rows = np.unique(np.concatenate([rng.choice(A.n, 2048, replace=False), [0, 1, A.n - 1]]))
