@@ -532,6 +532,44 @@ __device__ __forceinline__ void fit_coef(const SetFit& F, int m, double (&coef)[
     }
 }
 
+// x^e for x >= 0, e >= 0 from exp(e log x), both by series: log by
+// reduction to m 2^k with m in [sqrt(1/2), sqrt(2)) and log m =
+// 2 atanh((m - 1) / (m + 1)) (odd-power series, 12 terms), exp by
+// reduction to r + j ln 2 with |r| <= ln 2 / 2 and the Taylor series of e^r
+// (18 terms), ln 2 split in a high and a low part.  The relative error
+// grows with |e log x| (about 1e-13 at e log x = -660, a few 1e-16 for
+// |e log x| below 1); only the penalty rule's comparisons use it, where a
+// library pow would set the register count of the whole kernel.
+__device__ __forceinline__ double pow_series(double x, double e) {
+    if (e == 0.0) return 1.0;
+    if (!(x > 0.0)) return 0.0;
+    if (isinf(x)) return x;
+    constexpr double kLn2Hi = 6.93147180369123816490e-01;  // leading bits of ln 2
+    constexpr double kLn2Lo = 1.90821492927058770002e-10;  // ln 2 - kLn2Hi
+    int k = 0;
+    double m = frexp(x, &k);  // x = m 2^k, m in [1/2, 1)
+    if (m < 0.70710678118654752440) {
+        m *= 2.0;
+        --k;
+    }
+    const double sr = (m - 1.0) / (m + 1.0);
+    const double s2 = sr * sr;
+    double poly = 1.0 / 23.0;
+#pragma unroll
+    for (int j = 21; j >= 1; j -= 2) poly = fma(poly, s2, 1.0 / (double)j);
+    const double logx_lo = 2.0 * sr * poly + (double)k * kLn2Lo;
+    const double y_hi = e * (double)k * kLn2Hi, y_lo = e * logx_lo;
+    const double y = y_hi + y_lo;
+    if (y < -745.2) return 0.0;
+    if (y > 709.7) return INFINITY;
+    const double jn = rint(y * 1.44269504088896340736);
+    const double r = (y_hi - jn * kLn2Hi) + (y_lo - jn * kLn2Lo);
+    double t = 1.0;
+#pragma unroll
+    for (int j = 18; j >= 1; --j) t = fma(t, r * (1.0 / (double)j), 1.0);
+    return ldexp(t, (int)jn);
+}
+
 // The lane's block of size-M sets (consecutive ranks in lexicographic
 // order): the least functional and its rank into (bv, br).  The Cholesky
 // rows of the leading positions are refactored only from the first
@@ -634,10 +672,12 @@ __device__ void search_row(int i, int lane, SearchLds<T, K, NCAP>& L, const int*
     }
     wave_sync_lds();
     double S = 0.0;
+#pragma unroll 4
     for (int k = 0; k < K; ++k) S = fma(L.w[k] * L.t[k], L.t[k], S);
     // h_a and the Gram matrix of the candidates
     if (lane < nc) {
         double s = 0.0;
+#pragma unroll 4
         for (int k = 0; k < K; ++k) s = fma(L.w[k] * (double)L.x[lane][k], L.t[k], s);
         L.h[lane] = s;
     }
@@ -648,6 +688,7 @@ __device__ void search_row(int i, int lane, SearchLds<T, K, NCAP>& L, const int*
         while ((a + 1) * (a + 2) / 2 <= p) ++a;
         const int b = p - a * (a + 1) / 2;
         double s = 0.0;
+#pragma unroll 4
         for (int k = 0; k < K; ++k) s = fma(L.w[k] * (double)L.x[a][k], (double)L.x[b][k], s);
         L.g[p] = s;
     }
@@ -702,7 +743,7 @@ __device__ void search_row(int i, int lane, SearchLds<T, K, NCAP>& L, const int*
         if (!take) {
             const double rel = S > 0.0 ? bvs[q] / S : 0.0;
             const double inc_rel = S > 0.0 ? inc_v / S : 0.0;
-            take = rel < pow(inc_rel, gamma * (double)(m - inc_m));
+            take = rel < pow_series(inc_rel, gamma * (double)(m - inc_m));
         }
         if (take) {
             inc_m = m;
