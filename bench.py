@@ -246,13 +246,23 @@ KERNEL_SYMBOL = {"gs_phase": "gs_phase_perm_kernel", "jacobi": "jacobi_kernel",
                  "batch_algdist": "batch_algdist_kernel"}
 
 
+# sources of the kernels the counter summaries describe (relaxation, start,
+# distances, LS rows, the batch) and of their launch shapes; with every header
+COUNTED_SOURCES = ("relax.hip", "distance.hip", "interp.hip", "batched.hip", "util.hip",
+                   "autotune.hip")
+
+
 def source_hash():
-    """Hash of the HIP sources: counter summaries are valid only for it."""
+    """Hash of the sources the counted kernels are built from (COUNTED_SOURCES
+    and every header): counter summaries are valid only for it."""
     import glob
     import hashlib
-    here = os.path.dirname(os.path.abspath(__file__))
+    csrc = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_1106_5990_amd", "csrc")
+    files = [os.path.join(csrc, f) for f in COUNTED_SOURCES]
+    files += sorted(glob.glob(os.path.join(csrc, "*.h")))
     h = hashlib.sha256()
-    for p in sorted(glob.glob(os.path.join(here, "paper_1106_5990_amd", "csrc", "*"))):
+    for p in files:
+        h.update(os.path.basename(p).encode())
         with open(p, "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]
