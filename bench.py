@@ -262,6 +262,8 @@ def source_hash():
     files += sorted(glob.glob(os.path.join(csrc, "*.h")))
     h = hashlib.sha256()
     for p in files:
+        if not os.path.exists(p):
+            continue
         h.update(os.path.basename(p).encode())
         with open(p, "rb") as f:
             h.update(f.read())
