@@ -35,6 +35,47 @@ __global__ __launch_bounds__(kBlock) void col_count_kernel(int64_t nnz, const in
     if (e < nnz) atomicAdd(&cnt[ci[e]], 1);
 }
 
+// Structurally symmetric patterns: the rows of column j are the columns of
+// row j, so entry (i, j) goes to the position of i in row j (binary search)
+// and every column comes out in increasing row order with no atomics.  An
+// entry whose transpose is missing, repeated or outside column j's segment
+// sets *asym; the general path below then redoes the whole index.  Also
+// writes the diagonal (when diag is not null).
+__global__ __launch_bounds__(kBlock) void col_fill_sym_kernel(
+    int n, const int* __restrict__ rp, const int* __restrict__ ci, const double* __restrict__ av,
+    const int64_t* __restrict__ cp, int* __restrict__ trow, int* __restrict__ tent,
+    double* __restrict__ diag, int* __restrict__ asym, unsigned* status) {
+    const int64_t i64 = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i64 >= n) return;
+    const int i = (int)i64;
+    double d = 0.0;
+    bool bad = false;
+    for (int e = rp[i]; e < rp[i + 1]; ++e) {
+        const int j = ci[e];
+        if (diag && j == i) d = av[e];
+        const int r0 = rp[j], r1 = rp[j + 1];
+        int lo = r0, hi = r1;  // first entry of row j whose column is >= i
+        while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if (ci[mid] < i) lo = mid + 1;
+            else hi = mid;
+        }
+        const int64_t pos = lo - r0;
+        if (lo < r1 && ci[lo] == i && (lo + 1 == r1 || ci[lo + 1] != i) &&
+            pos < cp[j + 1] - cp[j]) {
+            trow[cp[j] + pos] = i;
+            tent[cp[j] + pos] = e;
+        } else {
+            bad = true;
+        }
+    }
+    if (bad) atomicOr(asym, 1);
+    if (diag) {
+        diag[i] = d;
+        if (d == 0.0) flag(status, AD_STAT_ZERO_DIAG);
+    }
+}
+
 // Row i's entries go to their columns' segments in arrival order (cur
 // zeroed by the caller); the per-column sort below fixes the order.  Also
 // writes the diagonal (when diag is not null).
@@ -46,9 +87,10 @@ __global__ __launch_bounds__(kBlock) void col_fill_kernel(int n, const int* __re
                                                           int* __restrict__ trow,
                                                           int* __restrict__ tent,
                                                           double* __restrict__ diag,
+                                                          const int* __restrict__ asym,
                                                           unsigned* status) {
     const int64_t i64 = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (i64 >= n) return;
+    if (i64 >= n || *asym == 0) return;
     const int i = (int)i64;
     double d = 0.0;
     for (int e = rp[i]; e < rp[i + 1]; ++e) {
@@ -68,9 +110,10 @@ __global__ __launch_bounds__(kBlock) void col_fill_kernel(int n, const int* __re
 // hold a handful of entries), one column per thread.
 __global__ __launch_bounds__(kBlock) void col_sort_kernel(int n, const int64_t* __restrict__ cp,
                                                           int* __restrict__ trow,
-                                                          int* __restrict__ tent) {
+                                                          int* __restrict__ tent,
+                                                          const int* __restrict__ asym) {
     const int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (j >= n) return;
+    if (j >= n || *asym == 0) return;
     const int64_t a = cp[j], b = cp[j + 1];
     for (int64_t f = a + 1; f < b; ++f) {
         const int r = trow[f], t = tent[f];
@@ -412,10 +455,18 @@ int launch_csc_index(int n, int64_t nnz, const int* rp, const int* ci, const dou
     col_count_kernel<<<dim3(nblk_e > 0 ? nblk_e : 1), dim3(kBlock), 0, s>>>(nnz, ci, cnt);
     AD_HIP(hipGetLastError());
     if ((rc = launch_excl_scan(cnt, n, cp, sc, s))) return rc;
+    // the scan's workspace, free again, holds the asymmetry flag
+    int* asym = (int*)sc;
+    if ((rc = launch_fill_i32(asym, 1, 0, s))) return rc;
+    col_fill_sym_kernel<<<dim3(nblk_n), dim3(kBlock), 0, s>>>(n, rp, ci, av, cp, trow, tent, diag,
+                                                              asym, status);
+    AD_HIP(hipGetLastError());
+    // the general path (arrival order, then a sort per column) runs only
+    // when the flag is set
     if ((rc = launch_fill_i32(cnt, n, 0, s))) return rc;
     col_fill_kernel<<<dim3(nblk_n), dim3(kBlock), 0, s>>>(n, rp, ci, av, cp, cnt, trow, tent, diag,
-                                                          status);
-    col_sort_kernel<<<dim3(nblk_n), dim3(kBlock), 0, s>>>(n, cp, trow, tent);
+                                                          asym, status);
+    col_sort_kernel<<<dim3(nblk_n), dim3(kBlock), 0, s>>>(n, cp, trow, tent, asym);
     AD_HIP(hipGetLastError());
     return AD_OK;
 }

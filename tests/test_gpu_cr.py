@@ -93,17 +93,34 @@ def test_cr_candidates_bitwise(n):
     assert np.array_equal(to_np(z32), oracle.cr_candidates(cf, u32, 0.3))
 
 
+def drop_offdiagonal(A, frac, seed):
+    """A with a random fraction of its off-diagonal entries removed: the
+    pattern is no longer structurally symmetric."""
+    rng = np.random.default_rng(seed)
+    keep = (A.col == A.row_ids()) | (rng.random(A.nnz) >= frac)
+    rid = A.row_ids()[keep]
+    rp = np.zeros(A.n + 1, np.int64)
+    np.cumsum(np.bincount(rid, minlength=A.n), out=rp[1:])
+    return W.CSR(A.n, rp.astype(np.int32), A.col[keep], A.val[keep])
+
+
 @pytest.mark.parametrize("kind,n,p_strong,p_z", [("rgg", 300, 0.5, 0.7), ("rgg", 40000, 0.4, 0.6),
                                                  ("grid", 250, 1.0, 1.0), ("grid", 401, 0.6, 0.3),
-                                                 ("rgg", 5000, 0.0, 0.5), ("rgg", 5000, 0.5, 0.0)])
+                                                 ("rgg", 5000, 0.0, 0.5), ("rgg", 5000, 0.5, 0.0),
+                                                 ("asym", 6000, 0.5, 0.6)])
 def test_independent_set_bitwise(kind, n, p_strong, p_z):
     """Random strong graphs (not symmetric) on geometric graphs and 9-point
     grids (many equal weights: the hash decides), candidate sets of every
-    density, no strong entries (every candidate is chosen), no candidates."""
+    density, no strong entries (every candidate is chosen), no candidates;
+    and a structurally asymmetric pattern (the column index's general
+    path)."""
     say("independent set %s n=%d" % (kind, n))
     ad = lib()
     rng = np.random.default_rng(n)
-    A = W.rgg_laplacian(n, 10.0, (n, 2)) if kind == "rgg" else aniso(n)
+    if kind == "asym":
+        A = drop_offdiagonal(W.rgg_laplacian(n, 10.0, (n, 2)), 0.1, n)
+    else:
+        A = W.rgg_laplacian(n, 10.0, (n, 2)) if kind == "rgg" else aniso(n)
     strong = (rng.random(A.nnz) < p_strong).astype(np.uint8)
     strong[A.col == A.row_ids()] = 0
     z = (rng.random(A.n) < p_z).astype(np.uint8)
