@@ -786,39 +786,69 @@ def cr_leg(args, torch, ad, W, flush):
 
 def quality_leg(args, torch, ad, W, flush):
     """The whole two-level setup on the GPU and the two-grid quality of
-    Sec. 5.2: K = 8 test vectors with 40 colour-phase sweeps, distances,
-    CR coarsening (theta 0.5, nu 5, delta 0.7), LS interpolation (caliber
-    4), A_c = P^T A P and the two-grid rate (100 cycles, 2 + 2 sweeps, four
-    random starts), on the 7-point rotated anisotropy and the 9-point one at
-    the paper's sizes; and the Galerkin product on the full 2048^2 operator
-    with the CR coarse grid and LS rows of the step's test vectors."""
+    Sec. 5.2: K = 8 test vectors with 40 Gauss-Seidel sweeps, distances,
+    CR coarsening (theta 0.5, nu 5, delta 0.7), interpolation with caliber
+    4, A_c = P^T A P and the two-grid rate (100 cycles, 2 + 2 sweeps, four
+    random starts).  Gauss-Seidel runs in the four-colour (ix mod 2, iy mod
+    2) order, a valid colouring of the 7- and 9-point stencils (the
+    checkerboard leaves diagonal neighbours in one colour, which makes the
+    smoother Jacobi-like along them).  Interpolation on each CR grid three
+    ways: LS rows on the C-neighbours of A (d_LS = 1), and the set search
+    over the C points of the patterns of A^2 and A^4 (gamma 1.5; the paper's
+    Table 1 uses d_LS = 4).  Cases: the 7-point rotated anisotropy with
+    eps 1e-2 at alpha 0, pi/4, -pi/4, pi/8 on 64^2, alpha pi/4 also on
+    128^2, and the 9-point one (eps 1e-3, alpha pi/6) on 128^2; and the
+    Galerkin product on the full 2048^2 operator with the CR coarse grid and
+    LS rows of the step's test vectors."""
     import math
-    res = {"cases": []}
-    for name, gen, N in (("fd7 eps 1e-2 alpha pi/4", lambda N: W.rotated_anisotropic_7pt(N, 1e-2, math.pi / 4), 64),
-                         ("fd7 eps 1e-2 alpha pi/4", lambda N: W.rotated_anisotropic_7pt(N, 1e-2, math.pi / 4), 128),
-                         ("9pt eps 1e-3 alpha pi/6", lambda N: W.rotated_anisotropic_9pt(N, 1e-3, math.pi / 6), 128)):
+    res = {"cases": [], "smoother": "Gauss-Seidel, four-colour order, 2 + 2 sweeps"}
+    f7 = W.rotated_anisotropic_7pt
+    cases = [("fd7 eps 1e-2 alpha 0", lambda N: f7(N, 1e-2, 0.0), 64),
+             ("fd7 eps 1e-2 alpha pi/4", lambda N: f7(N, 1e-2, math.pi / 4), 64),
+             ("fd7 eps 1e-2 alpha -pi/4", lambda N: f7(N, 1e-2, -math.pi / 4), 64),
+             ("fd7 eps 1e-2 alpha pi/8", lambda N: f7(N, 1e-2, math.pi / 8), 64),
+             ("fd7 eps 1e-2 alpha pi/4", lambda N: f7(N, 1e-2, math.pi / 4), 128),
+             ("9pt eps 1e-3 alpha pi/6", lambda N: W.rotated_anisotropic_9pt(N, 1e-3, math.pi / 6),
+              128)]
+    for name, gen, N in cases:
         Ah = gen(N)
         A = ad.Csr.from_host(Ah, dtype=torch.float64)
-        color = torch.as_tensor(W.red_black((N, N)), device="cuda")
+        color = torch.as_tensor(W.four_colour_2d(N), device="cuda")
         t0 = time.perf_counter()
-        X = ad.setup_testvectors(A, 8, seed=3, relax="gs", sweeps=40, color=color, ncolors=2)
+        X = ad.setup_testvectors(A, 8, seed=3, relax="gs", sweeps=40, color=color, ncolors=4)
         mu = ad.algebraic_distance(A, X)
-        cf, rho_cr, nc_cr = ad.cr_coarsening(A, color, 2, mu, 0.5, seed=1)
+        cf, rho_cr, nc_cr = ad.cr_coarsening(A, color, 4, mu, 0.5, seed=1)
         Pc, Pv, ls, st = ad.ls_interp(A, X, cf, mu, 4)
         Ac = ad.galerkin(A, Pc, Pv, cf)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         E0 = torch.rand((A.n, 4), dtype=torch.float64, device="cuda", generator=torch.Generator(
             device="cuda").manual_seed(5)) * 2 - 1
-        rho, hist = ad.two_grid_rate(A, color, 2, Pc, Pv, cf, Ac, E0, iters=100)
+        rho, hist = ad.two_grid_rate(A, color, 4, Pc, Pv, cf, Ac, E0, iters=100)
         t2 = time.perf_counter()
-        res["cases"].append({
-            "operator": "%s, %d^2" % (name, N), "rows": A.n, "coarse": Ac.n,
-            "cr_stages": len(rho_cr) - 1, "rho_f": [round(r, 4) for r in rho_cr],
-            "two_grid_rho": [round(float(r), 4) for r in rho],
-            "gamma_o": round((A.nnz + Ac.nnz) / A.nnz, 3), "gamma_g": round(Ac.n / A.n, 3),
-            "setup_ms": round((t1 - t0) * 1e3, 1), "two_grid_100_cycles_ms": round((t2 - t1) * 1e3, 1)})
-        log("two-grid %s %d^2: rho %s" % (name, N, np.round(rho, 4)))
+        case = {"operator": "%s, %d^2" % (name, N), "rows": A.n, "coarse": Ac.n,
+                "cr_stages": len(rho_cr) - 1, "rho_f": [round(r, 4) for r in rho_cr],
+                "gamma_g": round(Ac.n / A.n, 3),
+                "ls_d1": {"two_grid_rho": [round(float(r), 4) for r in rho],
+                          "gamma_o": round((A.nnz + Ac.nnz) / A.nnz, 3)},
+                "setup_ms": round((t1 - t0) * 1e3, 1),
+                "two_grid_100_cycles_ms": round((t2 - t1) * 1e3, 1)}
+        line = ["d1 %s" % np.round(rho, 3)]
+        # the same C points, interpolation by the set search over the C
+        # points of the pattern of A^d (caliber 4, gamma 1.5; Sec. 4.3)
+        for d in (2, 4):
+            G = ad.power_graph(A, d)
+            Ps, Pvs, _, st_s = ad.ls_interp_search(A, G, X, cf, 4, 1.5)
+            Acs = ad.galerkin(A, Ps, Pvs, cf)
+            rho_s, _ = ad.two_grid_rate(A, color, 4, Ps, Pvs, cf, Acs, E0, iters=100)
+            sv, sc = np.unique(st_s.cpu().numpy(), return_counts=True)
+            case["search_d%d" % d] = {"two_grid_rho": [round(float(r), 4) for r in rho_s],
+                                      "gamma_o": round((A.nnz + Acs.nnz) / A.nnz, 3),
+                                      "status_counts": {str(k): int(v) for k, v in zip(sv, sc)}}
+            line.append("d%d %s" % (d, np.round(rho_s, 3)))
+            del G, Ps, Pvs, Acs
+        res["cases"].append(case)
+        log("two-grid %s %d^2: %s" % (name, N, "; ".join(line)))
         del A, X, mu, cf, Pc, Pv, Ac, E0
     # the Galerkin product at full size
     wl = W.workload(2, "f32", size=args.size)
