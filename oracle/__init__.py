@@ -306,7 +306,9 @@ def _sig_cr(L):
             ("oracle_cr_candidates", None, [i32, P, P, f64, P]),
             ("oracle_independent_set", i32, [i32, P, P, P, P, u64, P]),
             ("oracle_cr_coarsen", i32, [i32, P, P, P, P, i32, P, f64, i32, f64, i32, u64, P, P,
-                                        P])):
+                                        P]),
+            ("oracle_cr_coarsen_graph", i32, [i32, P, P, P, P, P, P, i32, P, f64, i32, f64, i32,
+                                              u64, P, P, P])):
         fn = getattr(L, name)
         fn.restype = res
         fn.argtypes = args
@@ -348,8 +350,10 @@ def independent_set(A, strong, z, seed: int):
 
 
 def cr_coarsen(A, color, ncolors: int, mu, theta: float, nu: int = 5, delta: float = 0.7,
-               max_stages: int = 20, seed: int = 0, cf0=None):
-    """Algorithm 1 of Sec. 4.2: (cf, rho per stage, |C| per stage)."""
+               max_stages: int = 20, seed: int = 0, cf0=None, G=None):
+    """Algorithm 1 of Sec. 4.2: (cf, rho per stage, |C| per stage).  With a
+    pattern G (e.g. power_pattern(A, d)) the strength graph M^d and the
+    independent set live on G, mu given per entry of G; CR relaxes with A."""
     L = _sig_cr(lib())
     n, rp, ci, va = _csr(A)
     col = np.ascontiguousarray(color, dtype=np.int32)
@@ -358,9 +362,18 @@ def cr_coarsen(A, color, ncolors: int, mu, theta: float, nu: int = 5, delta: flo
           else np.ascontiguousarray(cf0, dtype=np.uint8).copy())
     rho = np.zeros(max_stages + 1)
     nc = np.zeros(max_stages + 1, dtype=np.int64)
-    s = L.oracle_cr_coarsen(n, _p(rp), _p(ci), _p(va), _p(col), int(ncolors), _p(mu),
-                            float(theta), int(nu), float(delta), int(max_stages),
-                            seed & (2**64 - 1), _p(cf), _p(rho), _p(nc))
+    if G is None:
+        s = L.oracle_cr_coarsen(n, _p(rp), _p(ci), _p(va), _p(col), int(ncolors), _p(mu),
+                                float(theta), int(nu), float(delta), int(max_stages),
+                                seed & (2**64 - 1), _p(cf), _p(rho), _p(nc))
+    else:
+        rpg = np.ascontiguousarray(G.row_ptr, dtype=np.int32)
+        cig = np.ascontiguousarray(G.col, dtype=np.int32)
+        assert len(mu) == len(cig)
+        s = L.oracle_cr_coarsen_graph(n, _p(rp), _p(ci), _p(va), _p(rpg), _p(cig), _p(col),
+                                      int(ncolors), _p(mu), float(theta), int(nu), float(delta),
+                                      int(max_stages), seed & (2**64 - 1), _p(cf), _p(rho),
+                                      _p(nc))
     return cf, rho[:s + 1], nc[:s + 1]
 
 

@@ -1232,17 +1232,20 @@ int oracle_independent_set(int n, const int *rp, const int *ci, const unsigned c
  * distances mu of the pattern), C grown by the independent set of Z, and
  * CR again.  Stops also when Z is empty or after max_stages growth steps.
  * rho[s] and ncoarse[s] record rho_f and |C| after s growth steps
- * (arrays of max_stages + 1).  Returns the number of growth steps. */
-int oracle_cr_coarsen(int n, const int *rp, const int *ci, const double *a, const int *color,
-                      int ncolors, const double *mu, double theta, int nu, double delta,
-                      int max_stages, uint64_t seed, unsigned char *cf, double *rho,
-                      int64_t *ncoarse)
+ * (arrays of max_stages + 1).  Returns the number of growth steps.
+ * The strength graph and the independent set live on the pattern
+ * (rpg, cig) with mu given per entry of it: the graph of A^d for M^d
+ * (Sec. 4.2), the pattern of A itself for d = 1; CR relaxes with A. */
+int oracle_cr_coarsen_graph(int n, const int *rp, const int *ci, const double *a,
+                            const int *rpg, const int *cig, const int *color, int ncolors,
+                            const double *mu, double theta, int nu, double delta, int max_stages,
+                            uint64_t seed, unsigned char *cf, double *rho, int64_t *ncoarse)
 {
     double *u = (double *)malloc(sizeof(double) * (size_t)(n ? n : 1));
     unsigned char *z = (unsigned char *)malloc((size_t)(n ? n : 1));
     unsigned char *fm = (unsigned char *)malloc((size_t)(n ? n : 1));
     unsigned char *sel = (unsigned char *)malloc((size_t)(n ? n : 1));
-    int64_t nnz = n ? rp[n] : 0;
+    int64_t nnz = n ? rpg[n] : 0;
     unsigned char *strong = (unsigned char *)malloc((size_t)(nnz ? nnz : 1));
     int stage = 0, i;
     int64_t nc = 0;
@@ -1257,8 +1260,8 @@ int oracle_cr_coarsen(int n, const int *rp, const int *ci, const double *a, cons
         for (i = 0; i < n; ++i) any |= z[i];
         if (!any) break;
         for (i = 0; i < n; ++i) fm[i] = (unsigned char)!cf[i];
-        oracle_strength(n, rp, ci, mu, theta, fm, strong, NULL);
-        oracle_independent_set(n, rp, ci, strong, z, seed + (uint64_t)stage, sel);
+        oracle_strength(n, rpg, cig, mu, theta, fm, strong, NULL);
+        oracle_independent_set(n, rpg, cig, strong, z, seed + (uint64_t)stage, sel);
         for (i = 0; i < n; ++i)
             if (sel[i]) {
                 cf[i] = 1;
@@ -1271,6 +1274,16 @@ int oracle_cr_coarsen(int n, const int *rp, const int *ci, const double *a, cons
     }
     free(u); free(z); free(fm); free(sel); free(strong);
     return stage;
+}
+
+/* Algorithm 1 with M^1: the strength graph on the pattern of A */
+int oracle_cr_coarsen(int n, const int *rp, const int *ci, const double *a, const int *color,
+                      int ncolors, const double *mu, double theta, int nu, double delta,
+                      int max_stages, uint64_t seed, unsigned char *cf, double *rho,
+                      int64_t *ncoarse)
+{
+    return oracle_cr_coarsen_graph(n, rp, ci, a, rp, ci, color, ncolors, mu, theta, nu, delta,
+                                   max_stages, seed, cf, rho, ncoarse);
 }
 
 /* ====================================================================== */

@@ -209,3 +209,51 @@ def test_coarsening_loop_invariants(wl):
         c = c | sel
         assert c.sum() == nc[s + 1]
     assert np.array_equal(c, cf)
+
+
+def test_coarsening_on_a_pattern_equal_to_a_gives_the_plain_call():
+    w = W.workload(2, size=20)
+    A = w.A
+    X, _ = oracle.color_gs(A, oracle.tv_init(A.n, 8, 2), w.color, 2, 5)
+    mu = oracle.algdist(A, X)
+    got = oracle.cr_coarsen(A, w.color, 2, mu, 0.25, seed=4,
+                            G=oracle.Pattern(A.n, A.row_ptr, A.col))
+    want = oracle.cr_coarsen(A, w.color, 2, mu, 0.25, seed=4)
+    for g, r in zip(got, want):
+        assert np.array_equal(g, r)
+
+
+def test_coarsening_loop_on_the_graph_of_a_squared():
+    """Algorithm 1 with M^2 (Sec. 4.2): the strength graph and the
+    independent set on the graph of A^2 with distances on it, CR relaxing
+    with A.  Replayed by hand from the building blocks: each growth step
+    adds an independent set of the candidates in the symmetric closure of
+    that step's strength graph on A^2, whose edges reach two steps in A."""
+    w = W.workload(2, size=24)
+    A = w.A
+    X, _ = oracle.color_gs(A, oracle.tv_init(A.n, 8, 5), w.color, 2, 5)
+    G = oracle.power_pattern(A, 2)
+    mu = oracle.algdist_graph(A, G, X)
+    cf, rho, nc = oracle.cr_coarsen(A, w.color, 2, mu, 0.25, seed=9, G=G)
+    assert len(rho) >= 2 and rho[0] > 0.7
+    assert rho[-1] <= 0.7 or len(rho) == 21
+    Gc = W.CSR(A.n, G.row_ptr, G.col, np.zeros(len(G.col)))
+    c = np.zeros(A.n, np.uint8)
+    for s in range(len(rho) - 1):
+        r, u = oracle.cr_rate(A, w.color, 2, c, 5)
+        assert r == rho[s]
+        z = oracle.cr_candidates(c, u, 1.0 - r)
+        strong, _ = oracle.strength(Gc, mu, 0.25, fmask=(c == 0).astype(np.uint8))
+        sel = oracle.independent_set(Gc, strong, z, 9 + s)
+        nb = _neighbours(Gc, strong)
+        for i in np.nonzero(sel)[0]:
+            assert not any(sel[j] for j in nb[i])
+        c = c | sel
+        assert c.sum() == nc[s + 1]
+    assert np.array_equal(c, cf)
+    # M^2 has strong edges two steps away in A (the first stage's graph)
+    strong, _ = oracle.strength(Gc, mu, 0.25, fmask=np.ones(A.n, np.uint8))
+    rid = Gc.row_ids()
+    in_a = set(zip(A.row_ids().tolist(), A.col.tolist()))
+    far = [(int(i), int(j)) for i, j, st in zip(rid, Gc.col, strong) if st and (i, j) not in in_a]
+    assert len(far) > 0
