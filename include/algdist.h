@@ -527,6 +527,19 @@ int cr_coarsening(ad_handle h, const ad_csr *A, const int32_t *color, int32_t nc
                   uint64_t seed, uint8_t *cf, double *rho, int64_t *ncoarse, int32_t *nstages,
                   void *stream);
 
+/* cr_coarsening with the strength graph M^d of Sec. 4.2: the strength
+ * graph and the independent set live on the pattern G (row_ptr_g [n+1],
+ * col_g [nnz_g], device, rows sorted; e.g. from power_graph_rows /
+ * power_graph_cols for the graph of A^d) with mu_g one distance per entry
+ * of G in A's dtype (e.g. from algebraic_distance_graph); the F-relaxation
+ * sweeps and rho_f use A.  Arguments, outputs, synchronisation and errors
+ * as cr_coarsening; G = A's pattern gives cr_coarsening's result. */
+int cr_coarsening_graph(ad_handle h, const ad_csr *A, int64_t nnz_g, const int32_t *row_ptr_g,
+                        const int32_t *col_g, const int32_t *color, int32_t ncolors,
+                        const void *mu_g, double theta, int32_t nu, double delta,
+                        int32_t max_stages, uint64_t seed, uint8_t *cf, double *rho,
+                        int64_t *ncoarse, int32_t *nstages, void *stream);
+
 /* ------------------------------------------------------------------ */
 /* Galerkin coarse operator and the two-grid method (Sec. 5.2).          */
 /* Synchronous; the calls allocate their own device buffers.            */

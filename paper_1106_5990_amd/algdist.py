@@ -97,6 +97,8 @@ _SIGS = {
     "independent_set": (_i32, [_P, _CSRP, _P, _P, _u64, _P, C.POINTER(C.c_int64), _P]),
     "cr_coarsening": (_i32, [_P, _CSRP, _P, _i32, _P, _f64, _i32, _f64, _i32, _u64, _P, _P, _P,
                              C.POINTER(C.c_int32), _P]),
+    "cr_coarsening_graph": (_i32, [_P, _CSRP, _i64, _P, _P, _P, _i32, _P, _f64, _i32, _f64, _i32,
+                                   _u64, _P, _P, _P, C.POINTER(C.c_int32), _P]),
 }
 for _name, (_res, _args) in _SIGS.items():
     _fn = getattr(_lib, _name)
@@ -625,17 +627,28 @@ def independent_set(A: Csr, strong: torch.Tensor, z: torch.Tensor, seed: int,
 
 def cr_coarsening(A: Csr, color: torch.Tensor, ncolors: int, mu: torch.Tensor, theta: float = 0.25,
                   nu: int = 5, delta: float = 0.7, max_stages: int = 20, seed: int = 0,
-                  cf: Optional[torch.Tensor] = None, stream=None):
+                  cf: Optional[torch.Tensor] = None, G: Optional[Pattern] = None, stream=None):
     """Algorithm 1 (cr_coarsening): (cf, rho per stage, |C| per stage); cf
-    is updated in place when given (its entries are C_0)."""
+    is updated in place when given (its entries are C_0).  With a pattern G
+    (e.g. power_graph(A, d)) the strength graph and the independent set
+    live on G and mu holds one distance per entry of G
+    (cr_coarsening_graph)."""
     h = handle(A.device.index)
     cf = cf if cf is not None else torch.zeros(A.n, dtype=torch.uint8, device=A.device)
     rho = (C.c_double * (max_stages + 1))()
     nc = (C.c_int64 * (max_stages + 1))()
     ns = C.c_int32(0)
-    _check(_lib.cr_coarsening(h, A.ref(), _ptr(color), int(ncolors), _ptr(mu), float(theta), int(nu),
-                              float(delta), int(max_stages), seed & (2 ** 64 - 1), _ptr(cf), rho, nc,
-                              C.byref(ns), _stream(stream)), h, "cr_coarsening")
+    if G is None:
+        rc = _lib.cr_coarsening(h, A.ref(), _ptr(color), int(ncolors), _ptr(mu), float(theta),
+                                int(nu), float(delta), int(max_stages), seed & (2 ** 64 - 1),
+                                _ptr(cf), rho, nc, C.byref(ns), _stream(stream))
+        _check(rc, h, "cr_coarsening")
+    else:
+        rc = _lib.cr_coarsening_graph(h, A.ref(), G.nnz, _ptr(G.row_ptr), _ptr(G.col), _ptr(color),
+                                      int(ncolors), _ptr(mu), float(theta), int(nu), float(delta),
+                                      int(max_stages), seed & (2 ** 64 - 1), _ptr(cf), rho, nc,
+                                      C.byref(ns), _stream(stream))
+        _check(rc, h, "cr_coarsening_graph")
     k = ns.value + 1
     return cf, list(rho)[:k], list(nc)[:k]
 

@@ -1007,19 +1007,19 @@ int independent_set(ad_handle h, const ad_csr* A, const uint8_t* strong, const u
     return AD_OK;
 }
 
-int cr_coarsening(ad_handle h, const ad_csr* A, const int32_t* color, int32_t ncolors,
-                  const void* mu, double theta, int32_t nu, double delta, int32_t max_stages,
-                  uint64_t seed, uint8_t* cf, double* rho, int64_t* ncoarse, int32_t* nstages,
-                  void* stream) {
-    if (!h) return AD_EINVAL;
-    h->err.clear();
-    int rc = check_cr_args(h, A, color, ncolors, cf, nu);
-    if (rc) return rc;
+// Algorithm 1 with the strength graph and the independent set on the
+// pattern G (nnz_g entries; mu per entry of G); CR relaxes with A.
+static int cr_coarsening_on(ad_handle h, const ad_csr* A, int64_t nnz_g, const int32_t* rpg,
+                            const int32_t* cig, const int32_t* color, int32_t ncolors,
+                            const void* mu, double theta, int32_t nu, double delta,
+                            int32_t max_stages, uint64_t seed, uint8_t* cf, double* rho,
+                            int64_t* ncoarse, int32_t* nstages, void* stream) {
+    int rc;
     if (!(theta > 0.0 && theta < 1.0)) return fail(h, AD_EINVAL, "theta = %g outside (0, 1)", theta);
     if (!(delta >= 0.0)) return fail(h, AD_EINVAL, "delta = %g", delta);
     if (max_stages < 0) return fail(h, AD_EINVAL, "max_stages = %d", max_stages);
     if (!rho || !ncoarse || !nstages) return fail(h, AD_EINVAL, "rho, ncoarse or nstages is NULL");
-    if (A->nnz > 0 && !mu) return fail(h, AD_EINVAL, "mu is NULL");
+    if (nnz_g > 0 && !mu) return fail(h, AD_EINVAL, "mu is NULL");
     *nstages = 0;
     if (A->n == 0) {
         rho[0] = 0.0;
@@ -1029,7 +1029,8 @@ int cr_coarsening(ad_handle h, const ad_csr* A, const int32_t* color, int32_t nc
     AD_HIP(hipSetDevice(h->device));
     hipStream_t s = (hipStream_t)stream;
     const int n = A->n;
-    const int64_t nnz = A->nnz;
+    const int64_t nnz = nnz_g;
+    const ad_csr Gp{n, nnz_g, rpg, cig, nullptr, A->dtype};  // pattern only
     const size_t vs = dsize(A->dtype);
     DevBufs b;
     int* fcol = b.get<int>(n);
@@ -1055,8 +1056,8 @@ int cr_coarsening(ad_handle h, const ad_csr* A, const int32_t* color, int32_t nc
         return fail(h, AD_ENOMEM, "cr_coarsening buffers");
     {
         TimedScope ts(h, "cr_index", s);
-        if ((rc = launch_csc_index(n, nnz, A->row_ptr, A->col, nullptr, cnt_c, cp, sc, trow, tent,
-                                   nullptr, h->status, s)))
+        if ((rc = launch_csc_index(n, nnz, rpg, cig, nullptr, cnt_c, cp, sc, trow, tent, nullptr,
+                                   h->status, s)))
             return fail(h, rc, "cr_coarsening: column index");
     }
     double r = 0.0, hn[3];
@@ -1071,13 +1072,13 @@ int cr_coarsening(ad_handle h, const ad_csr* A, const int32_t* color, int32_t nc
             TimedScope ts(h, "cr_select", s);
             if ((rc = launch_cr_candidates(A->dtype, n, cf, U, 2, nd, 1.0 - r, z, s)) ||
                 (rc = launch_cr_fmask(n, cf, fm, s)) ||
-                (rc = launch_strength(A->dtype, A, mu, theta, fm, strong, nullptr, s)))
+                (rc = launch_strength(A->dtype, &Gp, mu, theta, fm, strong, nullptr, s)))
                 return fail(h, rc, "cr_coarsening: candidates / strength");
         }
         int64_t added = 0;
         {
             TimedScope ts(h, "independent_set", s);
-            if ((rc = run_independent_set(n, A->row_ptr, A->col, strong, cp, trow, tent, z,
+            if ((rc = run_independent_set(n, rpg, cig, strong, cp, trow, tent, z,
                                           seed + (uint64_t)stage, lam, hh, state, left, nullptr,
                                           cf, &added, s)))
                 return fail(h, rc, "cr_coarsening: independent set");
@@ -1092,6 +1093,33 @@ int cr_coarsening(ad_handle h, const ad_csr* A, const int32_t* color, int32_t nc
     }
     *nstages = stage;
     return AD_OK;
+}
+
+
+int cr_coarsening(ad_handle h, const ad_csr* A, const int32_t* color, int32_t ncolors,
+                  const void* mu, double theta, int32_t nu, double delta, int32_t max_stages,
+                  uint64_t seed, uint8_t* cf, double* rho, int64_t* ncoarse, int32_t* nstages,
+                  void* stream) {
+    if (!h) return AD_EINVAL;
+    h->err.clear();
+    int rc = check_cr_args(h, A, color, ncolors, cf, nu);
+    if (rc) return rc;
+    return cr_coarsening_on(h, A, A->nnz, A->row_ptr, A->col, color, ncolors, mu, theta, nu, delta,
+                            max_stages, seed, cf, rho, ncoarse, nstages, stream);
+}
+
+int cr_coarsening_graph(ad_handle h, const ad_csr* A, int64_t nnz_g, const int32_t* row_ptr_g,
+                        const int32_t* col_g, const int32_t* color, int32_t ncolors,
+                        const void* mu_g, double theta, int32_t nu, double delta,
+                        int32_t max_stages, uint64_t seed, uint8_t* cf, double* rho,
+                        int64_t* ncoarse, int32_t* nstages, void* stream) {
+    if (!h) return AD_EINVAL;
+    h->err.clear();
+    int rc = check_cr_args(h, A, color, ncolors, cf, nu);
+    if (rc) return rc;
+    if ((rc = check_pattern(h, A->n, nnz_g, row_ptr_g, col_g))) return rc;
+    return cr_coarsening_on(h, A, nnz_g, row_ptr_g, col_g, color, ncolors, mu_g, theta, nu, delta,
+                            max_stages, seed, cf, rho, ncoarse, nstages, stream);
 }
 
 }  // extern "C"

@@ -196,6 +196,40 @@ def test_cr_coarsening_matches_oracle(kind, N, seed, delta):
     assert ad.status(clear=True) == 0
 
 
+@pytest.mark.parametrize("kind,N,seed,delta", [("aniso9", 64, 3, 0.7), ("lognormal", 80, 7, 0.4),
+                                                ("lap5", 60, 2, 0.3)])
+def test_cr_coarsening_on_the_graph_of_a_squared(kind, N, seed, delta):
+    """Algorithm 1 with M^2 (Sec. 4.2): strength graph and independent set
+    on the pattern of A^2 (the GPU's, equal to the oracle's), distances on
+    it; C points bit for bit the oracle's, rho_f per stage to 1e-12."""
+    say("cr_coarsening on A^2: %s N=%d delta=%g" % (kind, N, delta))
+    ad = lib()
+    A = operator(kind, N)
+    color = W.red_black((N, N))
+    X = oracle.tv_init(A.n, 8, seed)
+    X, _ = oracle.color_gs(A, X, color, 2, 5)
+    Gh = oracle.power_pattern(A, 2)
+    mu = oracle.algdist_graph(A, Gh, X)
+    cf_ref, rho_ref, nc_ref = oracle.cr_coarsen(A, color, 2, mu, 0.25, nu=5, delta=delta,
+                                                max_stages=20, seed=seed, G=Gh)
+    Ad = dev_csr(A, torch.float64)
+    G = ad.power_graph(Ad, 2)
+    assert np.array_equal(to_np(G.row_ptr), Gh.row_ptr) and np.array_equal(to_np(G.col), Gh.col)
+    cf, rho, nc = ad.cr_coarsening(Ad, gpu(color), 2, gpu(mu), 0.25, nu=5, delta=delta,
+                                   max_stages=20, seed=seed, G=G)
+    say("  stages %d |C| %s rho %s" % (len(rho_ref) - 1, list(nc_ref), np.round(rho_ref, 4).tolist()))
+    assert np.array_equal(to_np(cf), cf_ref)
+    assert nc == list(nc_ref)
+    assert np.allclose(rho, rho_ref, rtol=1e-12, atol=0)
+    # G = A's own pattern gives the plain call's result
+    mu1 = gpu(oracle.algdist(A, X))
+    c1, r1, _ = ad.cr_coarsening(Ad, gpu(color), 2, mu1, 0.25, seed=seed,
+                                 G=ad.Pattern(Ad.row_ptr, Ad.col))
+    c2, r2, _ = ad.cr_coarsening(Ad, gpu(color), 2, mu1, 0.25, seed=seed)
+    assert torch.equal(c1, c2) and r1 == r2
+    assert ad.status(clear=True) == 0
+
+
 def test_cr_coarsening_from_a_given_c0_and_limits():
     ad = lib()
     N = 48
