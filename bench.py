@@ -794,8 +794,9 @@ def quality_leg(args, torch, ad, W, flush):
     checkerboard leaves diagonal neighbours in one colour, which makes the
     smoother Jacobi-like along them).  Interpolation on each CR grid three
     ways: LS rows on the C-neighbours of A (d_LS = 1), and the set search
-    over the C points of the patterns of A^2 and A^4 (gamma 1.5; the paper's
-    Table 1 uses d_LS = 4).  Cases: the 7-point rotated anisotropy with
+    over the C points of the patterns of A^2 and A^4 (gamma 1.5); and the
+    paper's configuration for its Table 1, CR on the strength graph M^2
+    with the search on A^4.  Cases: the 7-point rotated anisotropy with
     eps 1e-2 at alpha 0, pi/4, -pi/4, pi/8 on 64^2, alpha pi/4 also on
     128^2, and the 9-point one (eps 1e-3, alpha pi/6) on 128^2; and the
     Galerkin product on the full 2048^2 operator with the CR coarse grid and
@@ -847,6 +848,21 @@ def quality_leg(args, torch, ad, W, flush):
                                       "status_counts": {str(k): int(v) for k, v in zip(sv, sc)}}
             line.append("d%d %s" % (d, np.round(rho_s, 3)))
             del G, Ps, Pvs, Acs
+        # the paper's configuration: CR on the strength graph M^2 (distances
+        # on the pattern of A^2), then the set search on A^4
+        G2 = ad.power_graph(A, 2)
+        mu2 = ad.algebraic_distance_graph(A, G2, X)
+        cf2, rho_cr2, _ = ad.cr_coarsening(A, color, 4, mu2, 0.5, seed=1, G=G2)
+        G4 = ad.power_graph(A, 4)
+        P2, Pv2, _, _ = ad.ls_interp_search(A, G4, X, cf2, 4, 1.5)
+        Ac2 = ad.galerkin(A, P2, Pv2, cf2)
+        rho2, _ = ad.two_grid_rate(A, color, 4, P2, Pv2, cf2, Ac2, E0, iters=100)
+        case["cr_m2_search_d4"] = {"two_grid_rho": [round(float(r), 4) for r in rho2],
+                                   "rho_f": [round(r, 4) for r in rho_cr2],
+                                   "gamma_g": round(Ac2.n / A.n, 3),
+                                   "gamma_o": round((A.nnz + Ac2.nnz) / A.nnz, 3)}
+        line.append("CR on M^2 + d4 %s" % np.round(rho2, 3))
+        del G2, mu2, cf2, G4, P2, Pv2, Ac2
         res["cases"].append(case)
         log("two-grid %s %d^2: %s" % (name, N, "; ".join(line)))
         del A, X, mu, cf, Pc, Pv, Ac, E0
