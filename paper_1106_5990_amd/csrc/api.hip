@@ -990,17 +990,17 @@ int independent_set(ad_handle h, const ad_csr* A, const uint8_t* strong, const u
         int64_t* sc = (int64_t*)b.get<char>((size_t)scan_workspace_bytes(n));
         int* trow = b.get<int>((size_t)nnz);
         int* tent = b.get<int>((size_t)nnz);
-        int* lam = b.get<int>(n);
-        uint64_t* hh = b.get<uint64_t>(n);
+        MisKey* key = b.get<MisKey>(n);
         int8_t* state = b.get<int8_t>(n);
         int* left = b.get<int>(1);
-        if (!cnt_c || !cp || !sc || !trow || !tent || !lam || !hh || !state || !left)
+        if (!cnt_c || !cp || !sc || !trow || !tent || !key || !state || !left)
             return fail(h, AD_ENOMEM, "independent_set buffers");
         TimedScope ts(h, "independent_set", s);
         if ((rc = launch_csc_index(n, nnz, A->row_ptr, A->col, nullptr, cnt_c, cp, sc, trow, tent,
                                    nullptr, h->status, s)) ||
-            (rc = run_independent_set(n, A->row_ptr, A->col, strong, cp, trow, tent, z, seed, lam,
-                                      hh, state, left, sel, nullptr, &cnt, s)))
+            (rc = run_independent_set(n, A->row_ptr, A->col, strong, cp, trow, tent,
+                                      (const int*)sc, z, seed, key, state, left, sel, nullptr,
+                                      &cnt, s)))
             return fail(h, rc, "independent_set");
     }
     if (count) *count = cnt;
@@ -1047,12 +1047,11 @@ static int cr_coarsening_on(ad_handle h, const ad_csr* A, int64_t nnz_g, const i
     int64_t* sc = (int64_t*)b.get<char>((size_t)scan_workspace_bytes(n));
     int* trow = b.get<int>((size_t)nnz);
     int* tent = b.get<int>((size_t)nnz);
-    int* lam = b.get<int>(n);
-    uint64_t* hh = b.get<uint64_t>(n);
+    MisKey* key = b.get<MisKey>(n);
     int8_t* state = b.get<int8_t>(n);
     int* left = b.get<int>(1);
     if (!fcol || !U0 || !U || !part || !nd || !cstat || !z || !fm || !strong || !cnt_c || !cp ||
-        !sc || !trow || !tent || !lam || !hh || !state || !left)
+        !sc || !trow || !tent || !key || !state || !left)
         return fail(h, AD_ENOMEM, "cr_coarsening buffers");
     {
         TimedScope ts(h, "cr_index", s);
@@ -1078,9 +1077,9 @@ static int cr_coarsening_on(ad_handle h, const ad_csr* A, int64_t nnz_g, const i
         int64_t added = 0;
         {
             TimedScope ts(h, "independent_set", s);
-            if ((rc = run_independent_set(n, rpg, cig, strong, cp, trow, tent, z,
-                                          seed + (uint64_t)stage, lam, hh, state, left, nullptr,
-                                          cf, &added, s)))
+            if ((rc = run_independent_set(n, rpg, cig, strong, cp, trow, tent, (const int*)sc, z,
+                                          seed + (uint64_t)stage, key, state, left, nullptr, cf,
+                                          &added, s)))
                 return fail(h, rc, "cr_coarsening: independent set");
         }
         if (added == 0) break;  // no candidate: nothing can grow C

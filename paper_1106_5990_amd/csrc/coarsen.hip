@@ -151,21 +151,58 @@ __device__ __forceinline__ bool outranks(int lj, uint64_t hj, int j, int li, uin
     return j > i;
 }
 
-// lam[i] = strong entries in column i; h[i]; state 1 for candidates, else 0.
+// key[i] = (h_i, lam_i = strong entries in column i); state 1 for
+// candidates, else 0.
 __global__ __launch_bounds__(kBlock) void mis_init_kernel(int n, const int64_t* __restrict__ cp,
                                                           const int* __restrict__ tent,
                                                           const uint8_t* __restrict__ strong,
                                                           const uint8_t* __restrict__ z,
-                                                          uint64_t seed, int* __restrict__ lam,
-                                                          uint64_t* __restrict__ hh,
+                                                          uint64_t seed, MisKey* __restrict__ key,
                                                           int8_t* __restrict__ state) {
     const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (i >= n) return;
     int c = 0;
     for (int64_t f = cp[i]; f < cp[i + 1]; ++f) c += strong[tent[f]] != 0;
-    lam[i] = c;
-    hh[i] = splitmix64_at(seed, (uint64_t)i);
+    MisKey k;
+    k.h = splitmix64_at(seed, (uint64_t)i);
+    k.lam = c;
+    k.pad = 0;
+    key[i] = k;
     state[i] = z[i] ? 1 : 0;
+}
+
+// Calls f(j) for every neighbour j != i with a strong entry (i, j) or
+// (j, i), until f returns true (then true).  With a structurally symmetric
+// pattern the k-th entry of column i is (row i's k-th column, i), so both
+// directions of an edge are read in one pass over row i.
+template <typename F>
+__device__ __forceinline__ bool any_strong_neighbour(int i, bool sym, const int* __restrict__ rp,
+                                                     const int* __restrict__ ci,
+                                                     const uint8_t* __restrict__ strong,
+                                                     const int64_t* __restrict__ cp,
+                                                     const int* __restrict__ trow,
+                                                     const int* __restrict__ tent, F&& f) {
+    const int e0 = rp[i], e1 = rp[i + 1];
+    if (sym) {
+        const int64_t f0 = cp[i];
+        for (int e = e0; e < e1; ++e) {
+            const int j = ci[e];
+            if (j == i || !(strong[e] || strong[tent[f0 + (e - e0)]])) continue;
+            if (f(j)) return true;
+        }
+        return false;
+    }
+    for (int e = e0; e < e1; ++e) {
+        const int j = ci[e];
+        if (j == i || !strong[e]) continue;
+        if (f(j)) return true;
+    }
+    for (int64_t g = cp[i]; g < cp[i + 1]; ++g) {
+        const int j = trow[g];
+        if (j == i || !strong[tent[g]]) continue;
+        if (f(j)) return true;
+    }
+    return false;
 }
 
 // An undecided candidate with no undecided or chosen neighbour that
@@ -174,27 +211,19 @@ __global__ __launch_bounds__(kBlock) void mis_init_kernel(int n, const int64_t* 
 __global__ __launch_bounds__(kBlock) void mis_select_kernel(
     int n, const int* __restrict__ rp, const int* __restrict__ ci,
     const uint8_t* __restrict__ strong, const int64_t* __restrict__ cp,
-    const int* __restrict__ trow, const int* __restrict__ tent, const int* __restrict__ lam,
-    const uint64_t* __restrict__ hh, int8_t* state) {
+    const int* __restrict__ trow, const int* __restrict__ tent, const int* __restrict__ asym,
+    const MisKey* __restrict__ key, int8_t* state) {
     const int64_t i64 = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (i64 >= n) return;
     const int i = (int)i64;
     if (state[i] != 1) return;
-    const int li = lam[i];
-    const uint64_t hi = hh[i];
-    for (int e = rp[i]; e < rp[i + 1]; ++e) {
-        const int j = ci[e];
-        if (j == i || !strong[e]) continue;
-        if (state[j] != 0 && outranks(lam[j], hh[j], j, li, hi, i))
-            return;
-    }
-    for (int64_t f = cp[i]; f < cp[i + 1]; ++f) {
-        const int j = trow[f];
-        if (j == i || !strong[tent[f]]) continue;
-        if (state[j] != 0 && outranks(lam[j], hh[j], j, li, hi, i))
-            return;
-    }
-    state[i] = 2;
+    const MisKey ki = key[i];
+    const bool beaten = any_strong_neighbour(i, *asym == 0, rp, ci, strong, cp, trow, tent, [&](int j) {
+        if (state[j] == 0) return false;
+        const MisKey kj = key[j];
+        return outranks(kj.lam, kj.h, j, ki.lam, ki.h, i);
+    });
+    if (!beaten) state[i] = 2;
 }
 
 // Undecided candidates next to a chosen point drop out (state 0); the rest
@@ -202,22 +231,16 @@ __global__ __launch_bounds__(kBlock) void mis_select_kernel(
 __global__ __launch_bounds__(kBlock) void mis_drop_kernel(
     int n, const int* __restrict__ rp, const int* __restrict__ ci,
     const uint8_t* __restrict__ strong, const int64_t* __restrict__ cp,
-    const int* __restrict__ trow, const int* __restrict__ tent, int8_t* state, int* left) {
+    const int* __restrict__ trow, const int* __restrict__ tent, const int* __restrict__ asym,
+    int8_t* state, int* left) {
     __shared__ int cnt;
     if (threadIdx.x == 0) cnt = 0;
     __syncthreads();
     const int64_t i64 = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (i64 < n && state[i64] == 1) {
         const int i = (int)i64;
-        bool out = false;
-        for (int e = rp[i]; e < rp[i + 1] && !out; ++e) {
-            const int j = ci[e];
-            if (j != i && strong[e] && state[j] == 2) out = true;
-        }
-        for (int64_t f = cp[i]; f < cp[i + 1] && !out; ++f) {
-            const int j = trow[f];
-            if (j != i && strong[tent[f]] && state[j] == 2) out = true;
-        }
+        const bool out = any_strong_neighbour(i, *asym == 0, rp, ci, strong, cp, trow, tent,
+                                              [&](int j) { return state[j] == 2; });
         if (out) state[i] = 0;
         else atomicAdd(&cnt, 1);
     }
@@ -305,13 +328,13 @@ int launch_cr_candidates(int dtype, int n, const uint8_t* cf, const void* U, int
 // The rounds of the independent set (synchronises the stream once per
 // round).  *count receives the size of the set.
 int run_independent_set(int n, const int* rp, const int* ci, const uint8_t* strong,
-                        const int64_t* cp, const int* trow, const int* tent, const uint8_t* z,
-                        uint64_t seed, int* lam, uint64_t* hh, int8_t* state, int* left,
+                        const int64_t* cp, const int* trow, const int* tent, const int* asym,
+                        const uint8_t* z, uint64_t seed, MisKey* key, int8_t* state, int* left,
                         uint8_t* sel, uint8_t* cf, int64_t* count, hipStream_t s) {
     *count = 0;
     if (n == 0) return AD_OK;
     const unsigned nb = blocks_for(n, kBlock);
-    mis_init_kernel<<<dim3(nb), dim3(kBlock), 0, s>>>(n, cp, tent, strong, z, seed, lam, hh, state);
+    mis_init_kernel<<<dim3(nb), dim3(kBlock), 0, s>>>(n, cp, tent, strong, z, seed, key, state);
     AD_HIP(hipGetLastError());
     // every round chooses the highest undecided candidate, so n rounds bound
     // the loop; the host looks at the count of undecided points after every
@@ -322,9 +345,9 @@ int run_independent_set(int n, const int* rp, const int* ci, const uint8_t* stro
             int rc = launch_fill_i32(left, 1, 0, s);
             if (rc) return rc;
             mis_select_kernel<<<dim3(nb), dim3(kBlock), 0, s>>>(n, rp, ci, strong, cp, trow, tent,
-                                                                lam, hh, state);
+                                                                asym, key, state);
             mis_drop_kernel<<<dim3(nb), dim3(kBlock), 0, s>>>(n, rp, ci, strong, cp, trow, tent,
-                                                              state, left);
+                                                              asym, state, left);
         }
         AD_HIP(hipGetLastError());
         int h_left = 0;

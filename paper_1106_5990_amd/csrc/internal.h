@@ -256,9 +256,18 @@ int launch_cr_norms(int dtype, int n, const uint8_t* cf, const void* U, double* 
                     double* norms, hipStream_t s);
 int launch_cr_candidates(int dtype, int n, const uint8_t* cf, const void* U, int stride,
                          const double* norms, double tol, uint8_t* z, hipStream_t s);
+// priority of a vertex in the independent set: (lam, h, index), loaded
+// as one 16-byte record
+struct alignas(16) MisKey {
+    uint64_t h;
+    int lam;
+    int pad;
+};
+// asym: the flag launch_csc_index left (0: the pattern is structurally
+// symmetric and column i lists row i's columns in order)
 int run_independent_set(int n, const int* rp, const int* ci, const uint8_t* strong,
-                        const int64_t* cp, const int* trow, const int* tent, const uint8_t* z,
-                        uint64_t seed, int* lam, uint64_t* hh, int8_t* state, int* left,
+                        const int64_t* cp, const int* trow, const int* tent, const int* asym,
+                        const uint8_t* z, uint64_t seed, MisKey* key, int8_t* state, int* left,
                         uint8_t* sel, uint8_t* cf, int64_t* count, hipStream_t s);
 
 // ---- galerkin.hip
