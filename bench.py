@@ -1010,6 +1010,47 @@ def cpu_baseline(idx, side, threads, min_seconds=10.0, max_passes=8):
                      "cpu_model": cpu_model()}}
 
 
+def cpu_baseline_setup(side, search_rows=8192):
+    """The oracle, single-threaded, on the setup calls the long-range,
+    coarsening and Galerkin legs time, on the anisotropic workload (FP32
+    values, as those legs use): the pattern of A^2 (whole matrix), the set
+    search at depth 2 (caliber 4, gamma 1.5) on a sample of rows, CR
+    coarsening (theta 0.25, from C_0 empty) and the Galerkin product of its
+    C points with LS rows (whole matrix).  Inputs (test vectors, distances,
+    LS rows) come from the oracle too and are not timed."""
+    import oracle
+    from paper_1106_5990_amd import workloads as W
+    wl = W.workload(2, "f32", size=side)
+    A = W.CSR(wl.A.n, wl.A.row_ptr, wl.A.col, wl.A.val.astype(np.float32).astype(np.float64))
+    X = oracle.tv_init(A.n, wl.K, wl.tv_seed)
+    X, _ = oracle.color_gs(A, X, wl.color, wl.ncolors, wl.sweeps)
+    res = {"workload": wl.name, "cores": 1, "kind": "oracle"}
+    t0 = time.perf_counter()
+    G = oracle.power_pattern(A, 2)
+    res["power_graph_A2_s"] = round(time.perf_counter() - t0, 3)
+    rng = np.random.default_rng(0)
+    rows = np.sort(rng.choice(A.n, min(search_rows, A.n), replace=False)).astype(np.int32)
+    t0 = time.perf_counter()
+    oracle.ls_search(A, G, X, None, wl.cf, 4, 1.5, rows=rows)
+    dt = time.perf_counter() - t0
+    nf = int((wl.cf[rows] == 0).sum())
+    res["ls_search"] = {"F_rows_per_s": round(nf / dt, 1), "sample": "%d rows (%d F rows), %.2f s"
+                        % (len(rows), nf, dt)}
+    del G
+    mu = oracle.algdist(A, X)
+    t0 = time.perf_counter()
+    cf, rho, nc = oracle.cr_coarsen(A, wl.color, wl.ncolors, mu, wl.theta, seed=1)
+    res["cr_coarsening_s"] = round(time.perf_counter() - t0, 3)
+    res["cr_coarse_points"] = [int(c) for c in nc]
+    Pc, Pv, _, _ = oracle.ls_interp(A, X, None, cf, mu, wl.caliber)
+    t0 = time.perf_counter()
+    Ac = oracle.galerkin(A, Pc, Pv, cf)
+    res["galerkin_s"] = round(time.perf_counter() - t0, 3)
+    res["galerkin_coarse_rows"] = int(Ac.n)
+    log("cpu baseline (setup calls): %s" % json.dumps(res))
+    return res
+
+
 # ------------------------------------------------------------------ main
 def main():
     args = parse()
@@ -1130,6 +1171,24 @@ def main():
         threads = args.cpu_threads or min(16, host_threads())
         log("cpu baseline: oracle on a side-%d sample" % side)
         out["cpu_baseline"] = cpu_baseline(idx, side, threads)
+        if args.longrange or args.cr or args.quality:
+            st = cpu_baseline_setup(args.size)
+            # GPU over oracle where the same call was timed on the GPU
+            ratio = {}
+            lr = out.get("longrange", {})
+            if "power_graph_ms" in lr:
+                ratio["power_graph"] = round(st["power_graph_A2_s"] * 1e3 / lr["power_graph_ms"], 1)
+            if "ls_search_F_rows_per_s" in lr:
+                ratio["ls_search"] = round(lr["ls_search_F_rows_per_s"]
+                                           / st["ls_search"]["F_rows_per_s"], 1)
+            if "ms" in out.get("cr_coarsening", {}):
+                ratio["cr_coarsening"] = round(st["cr_coarsening_s"] * 1e3
+                                               / out["cr_coarsening"]["ms"], 1)
+            gal = out.get("two_grid", {}).get("galerkin_full", {})
+            if "ms" in gal:
+                ratio["galerkin"] = round(st["galerkin_s"] * 1e3 / gal["ms"], 1)
+            st["gpu_speedup"] = ratio
+            out["cpu_baseline"]["setup_calls"] = st
     print(json.dumps(out), flush=True)
 
 
