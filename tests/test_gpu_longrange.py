@@ -74,6 +74,33 @@ def test_power_graph_limits():
     assert ad.status(clear=True) == 0
 
 
+@pytest.mark.parametrize("d,mat", [(2, "aniso9"), (2, "rgg20"), (3, "aniso9")])
+def test_power_graph_cols_with_foreign_row_pointers(d, mat):
+    """power_graph_cols with row pointers that do not match A^d (rows one
+    entry short or long, alternately): the pattern flag is raised, each row
+    holds the first min(room, |row|) columns of the true row, and nothing
+    lands outside the rows (a guard region after the last row stays)."""
+    ad = lib()
+    A = _matrices()[mat]
+    Ad = dev_csr(A, torch.float64)
+    R = oracle.power_pattern(A, d)
+    cnt = np.diff(R.row_ptr).astype(np.int64)
+    room = np.maximum(cnt + np.where(np.arange(A.n) % 2 == 0, -1, 1), 0)
+    rpd = np.concatenate([[0], np.cumsum(room)]).astype(np.int32)
+    guard = 4096
+    col = torch.full((int(rpd[-1]) + guard,), -7, dtype=torch.int32, device="cuda")
+    ad.status(clear=True)
+    rc = ad._lib.power_graph_cols(ad.handle(0), Ad.ref(), d, ad._ptr(torch.as_tensor(rpd, device="cuda")),
+                                  ad._ptr(col), ad._stream())
+    assert rc == 0
+    got = to_np(col)
+    assert ad.status(clear=True) & ad.STAT_PATTERN
+    assert np.all(got[int(rpd[-1]):] == -7)
+    for i in range(A.n):
+        w = min(room[i], cnt[i])
+        assert np.array_equal(got[rpd[i]:rpd[i] + w], R.col[R.row_ptr[i]:R.row_ptr[i] + w]), i
+
+
 def _graph_csr(G, n):
     rp, col = to_np(G.row_ptr), to_np(G.col)
     return W.CSR(n, rp, col, np.zeros(len(col)))
