@@ -1253,11 +1253,13 @@ int two_grid_rate(ad_handle h, const ad_csr* A, const int32_t* color, int32_t nc
     double* L = c.b.get<double>((size_t)nc * nc);
     double* Li = c.b.get<double>((size_t)nc * nc);
     double* LiT = c.b.get<double>((size_t)nc * nc);
+    double* Wblk = (double*)c.b.get<char>(coarse_factor_workspace(nc));
     int* bad = c.b.get<int>(1);
     const int nb = two_grid_blocks(n, K);
     double* part = c.b.get<double>((size_t)nb * K);
     double* hd = c.b.get<double>((size_t)(iters + 1) * K);
-    if (!c.ok || !E[0] || !E[1] || !R || !Rc || !L || !Li || !LiT || !bad || !part || !hd)
+    if (!c.ok || !E[0] || !E[1] || !R || !Rc || !L || !Li || !LiT || !Wblk || !bad || !part ||
+        !hd)
         return fail(h, AD_ENOMEM, "two_grid_rate buffers");
     int ncl = 0;
     if ((rc = galerkin_prepare(c.g, c.w, &ncl, s)) ||
@@ -1266,7 +1268,7 @@ int two_grid_rate(ad_handle h, const ad_csr* A, const int32_t* color, int32_t nc
     if (ncl != nc) return fail(h, AD_EINVAL, "nc = %d but cf marks %d coarse points", nc, ncl);
     {
         TimedScope ts(h, "coarse_factor", s);
-        if ((rc = coarse_factor(nc, row_ptr_c, col_c, val_c, L, Li, LiT, bad, s)))
+        if ((rc = coarse_factor(nc, row_ptr_c, col_c, val_c, L, Li, LiT, Wblk, bad, s)))
             return fail(h, rc, "two_grid_rate: coarse factorisation");
     }
     int hbad = 0;

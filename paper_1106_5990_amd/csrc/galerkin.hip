@@ -354,66 +354,185 @@ __global__ __launch_bounds__(kBlock) void dense_scatter_kernel(int nc, const int
     for (int e = rpc[I]; e < rpc[I + 1]; ++e) L[I * nc + colc[e]] = valc[e];
 }
 
-// sum_{p < m} x[p] y[p] over one wavefront (lanes stride p), fixed order
-__device__ __forceinline__ double wave_dot(const double* __restrict__ x,
-                                           const double* __restrict__ y, int m, int lane) {
-    double s = 0.0;
-    for (int p = lane; p < m; p += kWave) s += x[p] * y[p];
-#pragma unroll
-    for (int o = kWave / 2; o > 0; o >>= 1) s += __shfl_xor(s, o, kWave);
-    return s;
-}
+// Blocked Cholesky and inverse of the dense coarse matrix, in 64-wide
+// blocks: the diagonal block is factored in LDS by one workgroup, which also
+// forms its inverse W; the block column below is L_panel = A_panel W^T and
+// the trailing matrix loses L_panel L_panel^T (64 x 64 output tiles, FP64
+// FMA, operands staged in LDS 16 columns of the inner dimension at a time).
+// The inverse X = L^{-1} follows by blocked forward substitution of the
+// identity: block row k becomes W_k times itself, then the rows below lose
+// L_{., k} times it.
+constexpr int kDb = 64;   // block width
+constexpr int kDk = 16;   // inner-dimension chunk staged in LDS
 
-// Cholesky, column k (left-looking): L_kk = sqrt(a_kk - sum_{p<k} L_kp^2);
-// bad on a non-positive pivot.  One wavefront.
-__global__ __launch_bounds__(kWave) void chol_diag_kernel(int nc, int k, double* __restrict__ L,
-                                                          int* bad) {
-    const int lane = threadIdx.x;
-    const double* row = L + (int64_t)k * nc;
-    const double s = wave_dot(row, row, k, lane);
-    if (lane == 0) {
-        const double d = L[(int64_t)k * nc + k] - s;
-        if (!(d > 0.0)) *bad = 1;
-        L[(int64_t)k * nc + k] = d > 0.0 ? sqrt(d) : 1.0;
+// Factor the diagonal block at (kb, kb) of width b in place (lower part) and
+// write W = L_kk^{-1} (64 x 64 row-major, zero outside its lower b x b
+// part) to Wk.  A non-positive pivot sets *bad and is replaced by 1.
+__global__ __launch_bounds__(kBlock) void chol_block_kernel(int nc, int kb, int b,
+                                                            double* __restrict__ L,
+                                                            double* __restrict__ Wk, int* bad) {
+    __shared__ double T[kDb][kDb + 1];
+    __shared__ double Wl[kDb][kDb + 1];
+    const int t = threadIdx.x;
+    for (int q = t; q < kDb * kDb; q += kBlock) {
+        const int r = q / kDb, c = q % kDb;
+        T[r][c] = (r < b && c < b) ? L[(int64_t)(kb + r) * nc + kb + c] : 0.0;
+    }
+    __syncthreads();
+    for (int j = 0; j < b; ++j) {
+        if (t == 0) {
+            const double d = T[j][j];
+            if (!(d > 0.0)) *bad = 1;
+            T[j][j] = d > 0.0 ? sqrt(d) : 1.0;
+        }
+        __syncthreads();
+        for (int r = j + 1 + t; r < b; r += kBlock) T[r][j] /= T[j][j];
+        __syncthreads();
+        const int w = b - j - 1;
+        for (int q = t; q < w * w; q += kBlock) {
+            const int r = j + 1 + q / w, c = j + 1 + q % w;
+            if (c <= r) T[r][c] -= T[r][j] * T[c][j];
+        }
+        __syncthreads();
+    }
+    // column c of W by forward substitution of the unit vector e_c
+    if (t < b) {
+        const int c = t;
+        for (int r = 0; r < c; ++r) Wl[r][c] = 0.0;
+        for (int r = c; r < b; ++r) {
+            double v = (r == c) ? 1.0 : 0.0;
+            for (int p = c; p < r; ++p) v -= T[r][p] * Wl[p][c];
+            Wl[r][c] = v / T[r][r];
+        }
+    }
+    __syncthreads();
+    for (int q = t; q < kDb * kDb; q += kBlock) {
+        const int r = q / kDb, c = q % kDb;
+        if (r < b && c < b && c <= r) L[(int64_t)(kb + r) * nc + kb + c] = T[r][c];
+        Wk[q] = (r < b && c < b && c <= r) ? Wl[r][c] : 0.0;
     }
 }
 
-// L_ik = (a_ik - sum_{p<k} L_ip L_kp) / L_kk for i > k, one wavefront per row
-__global__ __launch_bounds__(kBlock) void chol_col_kernel(int nc, int k, double* __restrict__ L) {
-    const int lane = threadIdx.x & (kWave - 1);
-    const int64_t i = k + 1 + (int64_t)blockIdx.x * kWavesPerBlock + threadIdx.x / kWave;
-    if (i >= nc) return;
-    const double s = wave_dot(L + i * nc, L + (int64_t)k * nc, k, lane);
-    if (lane == 0) L[i * nc + k] = (L[i * nc + k] - s) / L[(int64_t)k * nc + k];
+enum DenseTile { kTilePanel, kTileSyrk, kTileInvDiag, kTileInvUpdate };
+
+// One 64 x 64 output tile: acc[r][c] = sum_{p < b} Aop(r, p) Bop(p, c), then
+// stored (panel, inverse diagonal) or subtracted (updates); 256 threads, 4 x 4
+// outputs each.  Operands by mode, with base = kb + b:
+//   panel:       rows base.. of L, cols kb..;  A = L[r][kb + p], B = W[c][p]
+//   syrk:        tile (tr >= tc) of L at (base + 64 tr, base + 64 tc);
+//                A = L[r][kb + p], B = L[c][kb + p]
+//   inv diag:    rows kb.. of X, cols 64 x;  A = W[r][p], B = X[kb + p][c]
+//   inv update:  rows base.. of X, cols 64 x;  A = L[r][kb + p], B = X[kb + p][c]
+// In the in-place modes the tile's operand loads all precede its stores.
+template <int MODE>
+__global__ __launch_bounds__(kBlock) void dense_tile_kernel(int nc, int kb, int b,
+                                                            double* __restrict__ L,
+                                                            const double* __restrict__ Wk,
+                                                            double* __restrict__ X) {
+    __shared__ double As[kDb][kDk + 1];
+    __shared__ double Bs[kDk][kDb + 1];
+    const int t = threadIdx.x;
+    const int tx = t % 16, ty = t / 16;
+    const int base = kb + b;
+    int R0, C0, rmax, cmax;
+    if (MODE == kTilePanel) {
+        R0 = base + blockIdx.x * kDb; C0 = kb; rmax = nc; cmax = base;
+    } else if (MODE == kTileSyrk) {
+        if (blockIdx.x > blockIdx.y) return;
+        R0 = base + blockIdx.y * kDb; C0 = base + blockIdx.x * kDb; rmax = nc; cmax = nc;
+    } else if (MODE == kTileInvDiag) {
+        R0 = kb; C0 = blockIdx.x * kDb; rmax = base; cmax = base;
+    } else {
+        R0 = base + blockIdx.y * kDb; C0 = blockIdx.x * kDb; rmax = nc; cmax = base;
+    }
+    double acc[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = 0.0;
+    for (int k0 = 0; k0 < b; k0 += kDk) {
+        // A chunk: 64 rows x 16; each thread 4 consecutive p of one row
+        for (int q = t; q < kDb * kDk / 4; q += kBlock) {
+            const int r = q / (kDk / 4), p0 = (q % (kDk / 4)) * 4;
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int p = k0 + p0 + u;
+                double v = 0.0;
+                if (R0 + r < rmax && p < b) {
+                    if (MODE == kTileInvDiag) v = Wk[r * kDb + p];
+                    else v = L[(int64_t)(R0 + r) * nc + kb + p];
+                }
+                As[r][p0 + u] = v;
+            }
+        }
+        // B chunk: 16 x 64
+        for (int q = t; q < kDb * kDk / 4; q += kBlock) {
+            if (MODE == kTilePanel || MODE == kTileSyrk) {
+                const int c = q / (kDk / 4), p0 = (q % (kDk / 4)) * 4;
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int p = k0 + p0 + u;
+                    double v = 0.0;
+                    if (C0 + c < cmax && p < b)
+                        v = (MODE == kTilePanel) ? Wk[c * kDb + p]
+                                                 : L[(int64_t)(C0 + c) * nc + kb + p];
+                    Bs[p0 + u][c] = v;
+                }
+            } else {
+                const int pp = q / (kDb / 4), c0 = (q % (kDb / 4)) * 4;
+                const int p = k0 + pp;
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int c = c0 + u;
+                    Bs[pp][c] = (p < b && C0 + c < cmax) ? X[(int64_t)(kb + p) * nc + C0 + c] : 0.0;
+                }
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int kk = 0; kk < kDk; ++kk) {
+            double a[4], bb[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) a[i] = As[ty * 4 + i][kk];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) bb[j] = Bs[kk][tx * 4 + j];
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) acc[i][j] = fma(a[i], bb[j], acc[i][j]);
+        }
+        __syncthreads();
+    }
+    double* C = (MODE == kTilePanel || MODE == kTileSyrk) ? L : X;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int r = R0 + ty * 4 + i;
+        if (r >= rmax) continue;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int c = C0 + tx * 4 + j;
+            if (c >= cmax) continue;
+            double* dst = C + (int64_t)r * nc + c;
+            if (MODE == kTilePanel || MODE == kTileInvDiag) *dst = acc[i][j];
+            else *dst -= acc[i][j];
+        }
+    }
 }
 
-// L^{-1} by forward substitution of all unit vectors at once, step k:
-// rows i > k of B (initially I) lose L_ik x_k, where x_k = B[k,:] / L_kk is
-// final once the steps before k are done (only columns j <= k are nonzero).
-// One wavefront per row i.
-__global__ __launch_bounds__(kBlock) void inv_update_kernel(int nc, int k,
-                                                            const double* __restrict__ L,
-                                                            double* __restrict__ B) {
-    const int lane = threadIdx.x & (kWave - 1);
-    const int64_t i = k + 1 + (int64_t)blockIdx.x * kWavesPerBlock + threadIdx.x / kWave;
-    if (i >= nc) return;
-    const double f = L[i * nc + k] / L[(int64_t)k * nc + k];
-    if (f == 0.0) return;
-    for (int64_t j = lane; j <= k; j += kWave) B[i * nc + j] -= f * B[(int64_t)k * nc + j];
-}
-
-// Li[i][j] = B[i][j] / L_ii (j <= i), and its transpose LiT[j][i]
-__global__ __launch_bounds__(kBlock) void inv_scale_kernel(int nc, const double* __restrict__ L,
-                                                           double* __restrict__ B,
-                                                           double* __restrict__ BT) {
-    const int lane = threadIdx.x & (kWave - 1);
-    const int64_t i = (int64_t)blockIdx.x * kWavesPerBlock + threadIdx.x / kWave;
-    if (i >= nc) return;
-    const double d = L[i * nc + i];
-    for (int64_t j = lane; j <= i; j += kWave) {
-        const double v = B[i * nc + j] / d;
-        B[i * nc + j] = v;
-        BT[j * nc + i] = v;
+// LiT = Li^T through 32 x 32 LDS tiles (Li's upper part is zero)
+__global__ __launch_bounds__(kBlock) void dense_transpose_kernel(int nc, const double* __restrict__ Li,
+                                                                 double* __restrict__ LiT) {
+    __shared__ double tl[32][33];
+    const int tx = threadIdx.x % 32, ty = threadIdx.x / 32;  // 32 x 8
+    const int bx = blockIdx.x, by = blockIdx.y;
+    for (int r = ty; r < 32; r += 8) {
+        const int i = by * 32 + r, j = bx * 32 + tx;
+        tl[r][tx] = (i < nc && j < nc) ? Li[(int64_t)i * nc + j] : 0.0;
+    }
+    __syncthreads();
+    for (int r = ty; r < 32; r += 8) {
+        const int j = bx * 32 + r, i = by * 32 + tx;
+        if (i < nc && j < nc) LiT[(int64_t)j * nc + i] = tl[tx][r];
     }
 }
 
@@ -673,27 +792,47 @@ __global__ __launch_bounds__(kBlock) void identity_kernel(int nc, double* __rest
     if (i < nc) M[i * nc + i] = 1.0;
 }
 
+size_t coarse_factor_workspace(int nc) {
+    return sizeof(double) * (size_t)((nc + kDb - 1) / kDb) * kDb * kDb;
+}
+
 int coarse_factor(int nc, const int* rpc, const int* colc, const double* valc, double* L,
-                  double* Li, double* LiT, int* bad, hipStream_t s) {
+                  double* Li, double* LiT, double* Wblk, int* bad, hipStream_t s) {
     if (nc > kCoarseSolveMax) return AD_EUNSUPPORTED;
+    if (nc == 0) return launch_fill_i32(bad, 1, 0, s);
     int rc;
     if ((rc = launch_fill_f64(L, (int64_t)nc * nc, 0.0, s))) return rc;
     if ((rc = launch_fill_f64(Li, (int64_t)nc * nc, 0.0, s))) return rc;
-    if ((rc = launch_fill_f64(LiT, (int64_t)nc * nc, 0.0, s))) return rc;
     if ((rc = launch_fill_i32(bad, 1, 0, s))) return rc;
     dense_scatter_kernel<<<dim3(nblocks(nc, kBlock)), dim3(kBlock), 0, s>>>(nc, rpc, colc, valc, L);
-    for (int k = 0; k < nc; ++k) {
-        chol_diag_kernel<<<dim3(1), dim3(kWave), 0, s>>>(nc, k, L, bad);
-        if (k + 1 < nc)
-            chol_col_kernel<<<dim3(nblocks(nc - k - 1, kWavesPerBlock)), dim3(kBlock), 0, s>>>(nc, k,
-                                                                                             L);
+    for (int kb = 0; kb < nc; kb += kDb) {
+        const int b = (nc - kb < kDb) ? nc - kb : kDb;
+        double* Wk = Wblk + (size_t)(kb / kDb) * kDb * kDb;
+        chol_block_kernel<<<dim3(1), dim3(kBlock), 0, s>>>(nc, kb, b, L, Wk, bad);
+        const int m = nc - kb - b;
+        if (m > 0) {
+            const unsigned T = (unsigned)((m + kDb - 1) / kDb);
+            dense_tile_kernel<kTilePanel><<<dim3(T), dim3(kBlock), 0, s>>>(nc, kb, b, L, Wk, Li);
+            dense_tile_kernel<kTileSyrk><<<dim3(T, T), dim3(kBlock), 0, s>>>(nc, kb, b, L, Wk, Li);
+        }
     }
-    // L^{-1} (in Li) and its transpose (in LiT)
+    AD_HIP(hipGetLastError());
+    // L^{-1} (in Li, from the identity) and its transpose (in LiT)
     identity_kernel<<<dim3(nblocks(nc, kBlock)), dim3(kBlock), 0, s>>>(nc, Li);
-    for (int k = 0; k + 1 < nc; ++k)
-        inv_update_kernel<<<dim3(nblocks(nc - k - 1, kWavesPerBlock)), dim3(kBlock), 0, s>>>(nc, k, L,
-                                                                                           Li);
-    inv_scale_kernel<<<dim3(nblocks(nc, kWavesPerBlock)), dim3(kBlock), 0, s>>>(nc, L, Li, LiT);
+    for (int kb = 0; kb < nc; kb += kDb) {
+        const int b = (nc - kb < kDb) ? nc - kb : kDb;
+        const double* Wk = Wblk + (size_t)(kb / kDb) * kDb * kDb;
+        const unsigned Tc = (unsigned)((kb + b + kDb - 1) / kDb);
+        dense_tile_kernel<kTileInvDiag><<<dim3(Tc), dim3(kBlock), 0, s>>>(nc, kb, b, L, Wk, Li);
+        const int m = nc - kb - b;
+        if (m > 0) {
+            const unsigned Tr = (unsigned)((m + kDb - 1) / kDb);
+            dense_tile_kernel<kTileInvUpdate><<<dim3(Tc, Tr), dim3(kBlock), 0, s>>>(nc, kb, b, L, Wk,
+                                                                                    Li);
+        }
+    }
+    const unsigned T32 = (unsigned)((nc + 31) / 32);
+    dense_transpose_kernel<<<dim3(T32, T32), dim3(kBlock), 0, s>>>(nc, Li, LiT);
     AD_HIP(hipGetLastError());
     return AD_OK;
 }

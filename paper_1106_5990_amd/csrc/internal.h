@@ -301,8 +301,9 @@ int galerkin_rows_run(const GalerkinIn& g, GalerkinWork& w, int nc, int* rpc, in
                       hipStream_t s);
 int galerkin_cols_run(const GalerkinIn& g, GalerkinWork& w, int nc, const int* rpc, int* colc,
                       double* valc, hipStream_t s);
+size_t coarse_factor_workspace(int nc);  // bytes of coarse_factor's Wblk
 int coarse_factor(int nc, const int* rpc, const int* colc, const double* valc, double* L,
-                  double* Li, double* LiT, int* bad, hipStream_t s);
+                  double* Li, double* LiT, double* Wblk, int* bad, hipStream_t s);
 int coarse_correction(const GalerkinIn& g, const GalerkinWork& w, int nc, int K, const double* Li,
                       const double* LiT, double* E, double* R, double* Rc, hipStream_t s);
 int a_norms_sq(const GalerkinIn& g, int K, const double* E, double* part, double* out,
