@@ -232,3 +232,25 @@ def test_two_grid_is_exact_with_the_ideal_interpolation():
     rho, hist = ad.two_grid_rate(dev_csr(A, torch.float64), gpu(color), 2, gpu(Pc), gpu(Pv),
                                  gpu(cf), Ac, gpu(E0), iters=2, pre=1, post=0)
     assert np.all(hist[1] <= 1e-13 * hist[0])
+
+
+@pytest.mark.parametrize("where", ["first block", "third block"])
+def test_two_grid_refuses_a_coarse_operator_that_is_not_positive_definite(where):
+    """A negative diagonal entry makes A_c indefinite: the blocked
+    factorisation meets a non-positive pivot (in the first 64-wide block, or
+    in the third) and the call fails with AD_ESTRUCT."""
+    ad = lib()
+    n = 301
+    A = lap1d(n)
+    cf, Pc, Pv = linear_1d(n)
+    i = 1 if where == "first block" else 281  # a C point: coarse index 0 or 140
+    val = A.val.copy()
+    val[(A.row_ids() == i) & (A.col == i)] = -50.0
+    B = W.CSR(n, A.row_ptr, A.col, val)
+    Ac, _ = compare(B, Pc, Pv, cf)
+    color = (1 - cf).astype(np.int32)
+    E0 = oracle.tv_init(n, 2, 3)
+    with pytest.raises(ad.AlgdistError, match="AD_ESTRUCT"):
+        ad.two_grid_rate(dev_csr(B, torch.float64), gpu(color), 2, gpu(Pc), gpu(Pv), gpu(cf), Ac,
+                         gpu(E0), iters=2)
+    ad.status(clear=True)
