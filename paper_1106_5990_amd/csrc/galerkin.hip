@@ -536,7 +536,9 @@ __global__ __launch_bounds__(kBlock) void dense_transpose_kernel(int nc, const d
     }
 }
 
-// Y[i][k] = sum_{j <= i} Li[i][j] B[j][k]   (Y = L^{-1} B), one wavefront per row
+// Y[i][k] = sum_{j <= i} Li[i][j] B[j][k]   (Y = L^{-1} B), one wavefront per
+// row: each Li entry is read once per kApplyK columns
+constexpr int kApplyK = 8;
 __global__ __launch_bounds__(kBlock) void lower_apply_kernel(int nc, int K,
                                                              const double* __restrict__ Li,
                                                              const double* __restrict__ B,
@@ -544,16 +546,28 @@ __global__ __launch_bounds__(kBlock) void lower_apply_kernel(int nc, int K,
     const int lane = threadIdx.x & (kWave - 1);
     const int64_t i = (int64_t)blockIdx.x * kWavesPerBlock + threadIdx.x / kWave;
     if (i >= nc) return;
-    for (int k = 0; k < K; ++k) {
-        double s = 0.0;
-        for (int64_t j = lane; j <= i; j += kWave) s += Li[i * nc + j] * B[j * K + k];
+    for (int k0 = 0; k0 < K; k0 += kApplyK) {
+        double s[kApplyK];
 #pragma unroll
-        for (int o = kWave / 2; o > 0; o >>= 1) s += __shfl_xor(s, o, kWave);
-        if (lane == 0) Y[i * K + k] = s;
+        for (int k = 0; k < kApplyK; ++k) s[k] = 0.0;
+        for (int64_t j = lane; j <= i; j += kWave) {
+            const double l = Li[i * nc + j];
+#pragma unroll
+            for (int k = 0; k < kApplyK; ++k)
+                if (k0 + k < K) s[k] += l * B[j * K + k0 + k];
+        }
+#pragma unroll
+        for (int k = 0; k < kApplyK; ++k) {
+            double v = s[k];
+#pragma unroll
+            for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+            if (lane == 0 && k0 + k < K) Y[i * K + k0 + k] = v;
+        }
     }
 }
 
-// X[j][k] = sum_{i >= j} LiT[j][i] Y[i][k]   (X = L^{-T} Y), one wavefront per row
+// X[j][k] = sum_{i >= j} LiT[j][i] Y[i][k]   (X = L^{-T} Y), one wavefront per
+// row, each LiT entry read once per kApplyK columns
 __global__ __launch_bounds__(kBlock) void upper_apply_kernel(int nc, int K,
                                                              const double* __restrict__ LiT,
                                                              const double* __restrict__ Y,
@@ -561,12 +575,23 @@ __global__ __launch_bounds__(kBlock) void upper_apply_kernel(int nc, int K,
     const int lane = threadIdx.x & (kWave - 1);
     const int64_t j = (int64_t)blockIdx.x * kWavesPerBlock + threadIdx.x / kWave;
     if (j >= nc) return;
-    for (int k = 0; k < K; ++k) {
-        double s = 0.0;
-        for (int64_t i = j + lane; i < nc; i += kWave) s += LiT[j * nc + i] * Y[i * K + k];
+    for (int k0 = 0; k0 < K; k0 += kApplyK) {
+        double s[kApplyK];
 #pragma unroll
-        for (int o = kWave / 2; o > 0; o >>= 1) s += __shfl_xor(s, o, kWave);
-        if (lane == 0) X[j * K + k] = s;
+        for (int k = 0; k < kApplyK; ++k) s[k] = 0.0;
+        for (int64_t i = j + lane; i < nc; i += kWave) {
+            const double l = LiT[j * nc + i];
+#pragma unroll
+            for (int k = 0; k < kApplyK; ++k)
+                if (k0 + k < K) s[k] += l * Y[i * K + k0 + k];
+        }
+#pragma unroll
+        for (int k = 0; k < kApplyK; ++k) {
+            double v = s[k];
+#pragma unroll
+            for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+            if (lane == 0 && k0 + k < K) X[j * K + k0 + k] = v;
+        }
     }
 }
 

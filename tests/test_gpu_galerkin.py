@@ -254,3 +254,17 @@ def test_two_grid_refuses_a_coarse_operator_that_is_not_positive_definite(where)
         ad.two_grid_rate(dev_csr(B, torch.float64), gpu(color), 2, gpu(Pc), gpu(Pv), gpu(cf), Ac,
                          gpu(E0), iters=2)
     ad.status(clear=True)
+
+
+def test_two_grid_with_sixteen_starts():
+    """K = 16 columns (the coarse applies take 8 columns per pass over the
+    inverse): history and rates against the oracle."""
+    ad = lib()
+    A, color, cf, Pc, Pv = setup("aniso9", 24)
+    Ac, Ac_ref = compare(A, Pc, Pv, cf)
+    E0 = oracle.tv_init(A.n, 16, 21)
+    rho_ref, bad, hist_ref = oracle.two_grid(A, color, 2, Pc, Pv, cf, Ac_ref, E0, iters=30)
+    rho, hist = ad.two_grid_rate(dev_csr(A, torch.float64), gpu(color), 2, gpu(Pc), gpu(Pv),
+                                 gpu(cf), Ac, gpu(E0), iters=30)
+    assert np.allclose(hist, hist_ref, rtol=1e-8, atol=0)
+    assert np.allclose(rho, rho_ref, rtol=1e-9, atol=0)
