@@ -214,6 +214,9 @@ def kernel_bytes(wl, s):
         # written once
         out["color_partition"] = n * 4 * 11 + nnz * (8 + 2 * s)
         out["tv_init"] = panel + n * 4
+        if K * s >= 16:
+            # the entry copy also writes the hash start panel (no start launch)
+            out["color_partition"] += panel
     out["algdist"] = (n + 1) * 4 + nnz * 4 + panel + nnz * s + nnz + n * 4
     F = wl.cf == 0
     nnzF = int(deg[F].sum())

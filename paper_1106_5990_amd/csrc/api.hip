@@ -381,15 +381,19 @@ int gs_sweeps(ad_handle h, const ad_csr* A, int K, uint64_t seed, const void* X0
     int32_t* rowlist = (int32_t*)(ws + o_rl);
     int32_t* seg = (int32_t*)(ws + o_seg);
     PermCsr pc{n, rowlist, seg, (int32_t*)(ws + o_rpp), (int32_t*)(ws + o_colp), ws + o_valp};
+    const bool fuse_start = !X0 && K * (int)dsize(dt) >= 16;
     {
         TimedScope ts(h, "color_partition", s);
         rc = launch_color_partition(n, color, ncolors, A->row_ptr, rowlist, (int32_t*)(ws + o_inv),
                                     seg, (int32_t*)(ws + o_cnt), nblk, (int32_t*)(ws + o_rpp),
                                     color_status, s);
-        if (!rc) rc = launch_perm_setup(dt, A, pc, (int32_t*)(ws + o_inv), s);
+        // the hash start is written by the entry copy when its rows are whole
+        // 16-byte chunks; a given X0, or narrower rows, take their own launch
+        if (!rc) rc = launch_perm_setup(dt, A, pc, (int32_t*)(ws + o_inv), s, K, seed,
+                                        fuse_start ? P[0] : nullptr);
         if (rc) return fail(h, rc, "colour partition launch");
     }
-    {
+    if (!fuse_start) {
         TimedScope ts(h, "tv_init", s);
         if ((rc = launch_start_perm(dt, n, K, rowlist, seed, X0, P[0], s)))
             return fail(h, rc, "start launch");

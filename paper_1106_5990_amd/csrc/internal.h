@@ -174,7 +174,8 @@ struct PermCsr {
     const int32_t* colpp;    // nnz
     const void* valpp;       // nnz values of the CSR's dtype
 };
-int launch_perm_setup(int dtype, const ad_csr* A, PermCsr& P, int32_t* inv, hipStream_t s);
+int launch_perm_setup(int dtype, const ad_csr* A, PermCsr& P, int32_t* inv, hipStream_t s,
+                      int K = 0, uint64_t seed = 0, void* Xp = nullptr);
 int launch_gs_phase_perm(int dtype, int K, const PermCsr& P, int c, int ncolors, const void* Xold,
                          void* Xnew, void* Xnat, int write_perm, unsigned* status,
                          const LaunchCfg& cfg, hipStream_t s);

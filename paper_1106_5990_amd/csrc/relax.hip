@@ -394,7 +394,10 @@ int launch_color_partition(int n, const int32_t* color, int ncolors, const int32
 // loads; each row's entries land as one contiguous run, and rows that are
 // neighbours in a colour are neighbours in the copy); a lane finds the row
 // of its entry by binary search over the starts.  colpp = inv[col],
-// valpp = val.
+// valpp = val.  With Xp (K * sizeof(T) >= 16), the wavefront also writes the
+// hash start rows of its natural rows at their permuted positions, the same
+// values start_perm_kernel forms, so that the start's integer work overlaps
+// the copy's memory traffic instead of running as a launch of its own.
 constexpr int kCopyRows = 64;
 constexpr int kPermUnroll = 4;
 
@@ -402,15 +405,17 @@ template <typename T>
 __global__ __launch_bounds__(kBlock) void permute_entries_kernel(
     int n, const int* __restrict__ rp, const int* __restrict__ ci, const T* __restrict__ av,
     const int* __restrict__ inv, const int* __restrict__ rpp, int* __restrict__ colpp,
-    T* __restrict__ valpp) {
+    T* __restrict__ valpp, int K, uint64_t seed, T* __restrict__ Xp) {
     __shared__ int s_rp[kWavesPerBlock][kCopyRows + 1];  // natural starts, then the end
     __shared__ int s_dst[kWavesPerBlock][kCopyRows];     // permuted starts
+    __shared__ int s_inv[kWavesPerBlock][kCopyRows];
     const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
     const int64_t r0 = ((int64_t)blockIdx.x * kWavesPerBlock + wv) * kCopyRows;
     const int rl = r0 < n ? (int)min<int64_t>(kCopyRows, n - r0) : 0;
     if (lane < rl) {
         s_rp[wv][lane] = rp[r0 + lane];
-        s_dst[wv][lane] = rpp[inv[r0 + lane]];
+        s_inv[wv][lane] = inv[r0 + lane];
+        s_dst[wv][lane] = rpp[s_inv[wv][lane]];
     }
     if (lane == 0 && rl > 0) s_rp[wv][rl] = rp[r0 + rl];
     __syncthreads();
@@ -446,6 +451,21 @@ __global__ __launch_bounds__(kBlock) void permute_entries_kernel(
                 colpp[dd[u]] = jj[u];
                 valpp[dd[u]] = vv[u];
             }
+    }
+    if (Xp) {
+        // the start rows of these natural rows at their permuted positions
+        constexpr int E = 16 / sizeof(T);
+        const int cpr = K / E;  // chunks per row (K >= E here)
+        for (int q = lane; q < rl * cpr; q += kWave) {
+            const int r = q / cpr, k0 = (q % cpr) * E;
+            const int64_t nat = r0 + r;
+            uint64_t z = splitmix64_state(seed, (uint64_t)(nat * K + k0));
+            Frag<T, E> f;
+#pragma unroll
+            for (int u = 0; u < E; ++u, z += kSplitmixGamma)
+                f.v[u] = (T)uniform_pm1(splitmix64_mix(z));
+            store_frag<T, E>(Xp + (int64_t)s_inv[wv][r] * K + k0, f);
+        }
     }
 }
 
@@ -626,8 +646,10 @@ int launch_gs_phase_perm(int dtype, int K, const PermCsr& P, int c, int ncolors,
 }
 
 // The colour-major entries of P (whose rowlist, row pointers and inverse inv
-// the partition wrote).
-int launch_perm_setup(int dtype, const ad_csr* A, PermCsr& P, int32_t* inv, hipStream_t s) {
+// the partition wrote); with Xp, also the hash start panel (seed, K columns)
+// in colour-major row order.
+int launch_perm_setup(int dtype, const ad_csr* A, PermCsr& P, int32_t* inv, hipStream_t s,
+                      int K, uint64_t seed, void* Xp) {
     const int n = A->n;
     if (n == 0) return AD_OK;
     const int64_t rows_per_block = (int64_t)kCopyRows * kWavesPerBlock;
@@ -635,11 +657,11 @@ int launch_perm_setup(int dtype, const ad_csr* A, PermCsr& P, int32_t* inv, hipS
     if (dtype == AD_F32)
         permute_entries_kernel<float><<<dim3(cb), dim3(kBlock), 0, s>>>(
             n, A->row_ptr, A->col, (const float*)A->val, inv, P.rpp, (int32_t*)P.colpp,
-            (float*)P.valpp);
+            (float*)P.valpp, K, seed, (float*)Xp);
     else
         permute_entries_kernel<double><<<dim3(cb), dim3(kBlock), 0, s>>>(
             n, A->row_ptr, A->col, (const double*)A->val, inv, P.rpp, (int32_t*)P.colpp,
-            (double*)P.valpp);
+            (double*)P.valpp, K, seed, (double*)Xp);
     AD_HIP(hipGetLastError());
     return AD_OK;
 }
