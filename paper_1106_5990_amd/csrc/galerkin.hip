@@ -358,7 +358,7 @@ __global__ __launch_bounds__(kBlock) void dense_scatter_kernel(int nc, const int
 // blocks: the diagonal block is factored in LDS by one workgroup, which also
 // forms its inverse W; the block column below is L_panel = A_panel W^T and
 // the trailing matrix loses L_panel L_panel^T (64 x 64 output tiles, FP64
-// FMA, operands staged in LDS 16 columns of the inner dimension at a time).
+// MFMA, operands staged in LDS 16 columns of the inner dimension at a time).
 // The inverse X = L^{-1} follows by blocked forward substitution of the
 // identity: block row k becomes W_k times itself, then the rows below lose
 // L_{., k} times it.
@@ -416,8 +416,8 @@ __global__ __launch_bounds__(kBlock) void chol_block_kernel(int nc, int kb, int 
 enum DenseTile { kTilePanel, kTileSyrk, kTileInvDiag, kTileInvUpdate };
 
 // One 64 x 64 output tile: acc[r][c] = sum_{p < b} Aop(r, p) Bop(p, c), then
-// stored (panel, inverse diagonal) or subtracted (updates); 256 threads, 4 x 4
-// outputs each.  Operands by mode, with base = kb + b:
+// stored (panel, inverse diagonal) or subtracted (updates); 256 threads, the
+// products on the FP64 matrix cores.  Operands by mode, with base = kb + b:
 //   panel:       rows base.. of L, cols kb..;  A = L[r][kb + p], B = W[c][p]
 //   syrk:        tile (tr >= tc) of L at (base + 64 tr, base + 64 tc);
 //                A = L[r][kb + p], B = L[c][kb + p]
@@ -432,7 +432,6 @@ __global__ __launch_bounds__(kBlock) void dense_tile_kernel(int nc, int kb, int 
     __shared__ double As[kDb][kDk + 1];
     __shared__ double Bs[kDk][kDb + 1];
     const int t = threadIdx.x;
-    const int tx = t % 16, ty = t / 16;
     const int base = kb + b;
     int R0, C0, rmax, cmax;
     if (MODE == kTilePanel) {
@@ -445,11 +444,16 @@ __global__ __launch_bounds__(kBlock) void dense_tile_kernel(int nc, int kb, int 
     } else {
         R0 = base + blockIdx.y * kDb; C0 = blockIdx.x * kDb; rmax = nc; cmax = base;
     }
-    double acc[4][4];
+    // matrix cores: wavefront w owns rows 16 w .. 16 w + 15 of the tile as
+    // four 16 x 16 blocks, each accumulated by FP64 MFMA 16 x 16 x 4 steps
+    // (lane l feeds A[16 w + l % 16][k + l / 16] and B[k + l / 16][16 jb + l % 16]
+    // and holds D[l / 16 + 4 v][l % 16], v = 0..3)
+    const int lane = t & (kWave - 1), w = t / kWave;
+    const int l16 = lane & 15, lq = lane >> 4;
+    typedef double double4_t __attribute__((ext_vector_type(4)));
+    double4_t acc[4];
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = 0.0;
+    for (int jb = 0; jb < 4; ++jb) acc[jb] = double4_t{0.0, 0.0, 0.0, 0.0};
     for (int k0 = 0; k0 < b; k0 += kDk) {
         // A chunk: 64 rows x 16; each thread 4 consecutive p of one row
         for (int q = t; q < kDb * kDk / 4; q += kBlock) {
@@ -490,31 +494,27 @@ __global__ __launch_bounds__(kBlock) void dense_tile_kernel(int nc, int kb, int 
         }
         __syncthreads();
 #pragma unroll
-        for (int kk = 0; kk < kDk; ++kk) {
-            double a[4], bb[4];
+        for (int st = 0; st < kDk / 4; ++st) {
+            const double a = As[w * 16 + l16][st * 4 + lq];
 #pragma unroll
-            for (int i = 0; i < 4; ++i) a[i] = As[ty * 4 + i][kk];
-#pragma unroll
-            for (int j = 0; j < 4; ++j) bb[j] = Bs[kk][tx * 4 + j];
-#pragma unroll
-            for (int i = 0; i < 4; ++i)
-#pragma unroll
-                for (int j = 0; j < 4; ++j) acc[i][j] = fma(a[i], bb[j], acc[i][j]);
+            for (int jb = 0; jb < 4; ++jb) {
+                const double bv = Bs[st * 4 + lq][jb * 16 + l16];
+                acc[jb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bv, acc[jb], 0, 0, 0);
+            }
         }
         __syncthreads();
     }
     double* C = (MODE == kTilePanel || MODE == kTileSyrk) ? L : X;
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        const int r = R0 + ty * 4 + i;
-        if (r >= rmax) continue;
+    for (int jb = 0; jb < 4; ++jb) {
+        const int c = C0 + jb * 16 + l16;
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int c = C0 + tx * 4 + j;
-            if (c >= cmax) continue;
+        for (int v = 0; v < 4; ++v) {
+            const int r = R0 + w * 16 + lq + 4 * v;
+            if (r >= rmax || c >= cmax) continue;
             double* dst = C + (int64_t)r * nc + c;
-            if (MODE == kTilePanel || MODE == kTileInvDiag) *dst = acc[i][j];
-            else *dst -= acc[i][j];
+            if (MODE == kTilePanel || MODE == kTileInvDiag) *dst = acc[jb][v];
+            else *dst -= acc[jb][v];
         }
     }
 }
