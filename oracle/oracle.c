@@ -894,9 +894,13 @@ int oracle_algdist_graph(int n, const int *rp, const int *ci, const double *a, c
 /* eq:LSfuncrowi / eq:modls for a given set W): Householder QR of the      */
 /* sqrt(w)-scaled K x m system.  Returns 1 (and nothing else) when a       */
 /* column is numerically dependent on the ones before it (the part of it   */
-/* the earlier reflections leave, squared, <= 1e-12 of its squared norm),  */
-/* else 0 with coef[0..m) the minimiser and *val the functional at it,     */
-/* evaluated by its definition.  M: K*m scratch, b, v: K scratch.          */
+/* the earlier reflections leave, squared, <= 1e-8 of its squared norm,   */
+/* i.e. a relative part below 1e-4: the reading of the basis condition of  */
+/* the uniqueness remark in Sec. 3.1 for the search; a set closer to       */
+/* dependence fits through cancelling weights, and its functional is not   */
+/* resolvable from FP64 normal equations), else 0 with coef[0..m) the      */
+/* minimiser and *val the functional at it, evaluated by its definition.   */
+/* M: K*m scratch, b, v: K scratch.                                        */
 /* ---------------------------------------------------------------------- */
 static int qr_fit(int K, const double *X, const double *w, const double *t, const int *cols,
                   int m, double *coef, double *val, double *M, double *b, double *v)
@@ -911,7 +915,7 @@ static int qr_fit(int K, const double *X, const double *w, const double *t, cons
         double full = 0.0, tail = 0.0, alpha, vnorm2, dot;
         for (k = 0; k < K; ++k) full += col[k] * col[k];
         for (k = s; k < K; ++k) tail += col[k] * col[k];
-        if (s >= K || tail <= 1e-12 * full) return 1;
+        if (s >= K || tail <= 1e-8 * full) return 1;
         alpha = (col[s] > 0.0) ? -sqrt(tail) : sqrt(tail);
         for (k = 0; k < K; ++k) v[k] = 0.0;
         for (k = s; k < K; ++k) v[k] = col[k];
@@ -988,7 +992,7 @@ void oracle_ls_fit_sets(int n, const int *rp, const int *ci, const double *a, in
 /* are N_i = C-points of row i of the graph G (eq:nbhd with G the pattern  */
 /* of A^{d_LS}), i excluded, in increasing column order.  Every W within   */
 /* N_i with 1 <= |W| <= caliber is fitted (qr_fit; a numerically dependent */
-/* W is skipped: its span is that of a smaller set already visited), and   */
+/* W is skipped: within the rule its span is a smaller set's), and         */
 /* for each size m the least functional best_m is kept (ties: the first W  */
 /* in lexicographic order of candidate positions).  Values are normalised  */
 /* by the functional of the empty set, S = sum_k w_k t_k^2 (the reading of */

@@ -326,6 +326,28 @@ def test_search_exact_recovery_and_dependent_sets():
     assert ls[0] < 1e-24 * float(w @ (X[i] * X[i]))
 
 
+@pytest.mark.parametrize("rel2,dep", [(1e-10, 1), (3e-9, 1), (3e-8, 0), (1e-6, 0)])
+def test_fit_sets_dependence_rule(rel2, dep):
+    """The search's dependence rule in closed form: x_c = x_a + delta u with
+    u orthogonal to x_a and |u| = |x_a| leaves x_c a part orthogonal to x_a
+    whose squared norm is delta^2 / (1 + delta^2) of |x_c|^2; the set
+    {a, c} is dependent exactly when that is <= 1e-8 (in either order)."""
+    A, X, w, cf = _search_case(6, n=12, K=8, density=0.4)
+    X = X.copy()
+    a, c, i = 0, 1, 2
+    u = X[3] - (X[3] @ X[a]) / (X[a] @ X[a]) * X[a]
+    u *= np.linalg.norm(X[a]) / np.linalg.norm(u)
+    d2 = rel2 / (1.0 - rel2)  # delta^2 with delta^2 / (1 + delta^2) = rel2
+    X[c] = X[a] + np.sqrt(d2) * u
+    for pair in ([a, c], [c, a]):
+        sets = np.array([pair + [-1, -1]], dtype=np.int32)
+        pv, lv, rd = oracle.ls_fit_sets(A, X, None, sets, [i])
+        assert rd[0] == dep, (pair, rel2)
+        if not dep:
+            sol, *_ = np.linalg.lstsq(X[pair].T, X[i], rcond=None)
+            assert np.allclose(pv[0][:2], sol, rtol=1e-6, atol=1e-9)
+
+
 @pytest.mark.parametrize("seed", range(2))
 def test_fit_sets_matches_lstsq(seed):
     A, X, w, cf = _search_case(seed + 20)
