@@ -13,17 +13,21 @@
 //
 // Interpolatory-set search.  One wavefront per F row: the row's candidates
 // (the C-points of its row of the pattern, i excluded, in column order) and
-// their panel rows are staged in LDS as FP64, with the target and the FP64
+// their panel rows are staged in LDS, with the FP64 target and the FP64
 // Gram matrix G_ab = <x_a, x_b>_w and h_a = <x_a, t>_w of all candidates.
 // Every set W of each size m <= caliber is then a small Cholesky on
-// entries of G: LS_W = S - |L^{-1} h_W|^2 with S = <t, t>_w (a set with a
-// pivot <= 1e-12 of its Gram diagonal is numerically dependent and
-// skipped).  Lanes take consecutive blocks of the sets in lexicographic
-// order (the first unranked, the rest by successor); the least (value,
-// rank) over the wave is that size's best.  The size is chosen by the
-// penalty rule in increasing size against the incumbent, on values
-// relative to S; the chosen set's weights come from its Cholesky solve and
-// its functional is evaluated by definition.
+// entries of G (a set with a pivot <= kSearchDep = 1e-8 of its Gram
+// diagonal is numerically dependent and skipped: the Gram entries carry
+// rounding of order eps |x_a| |x_b|, which earlier small pivots amplify, so
+// a smaller pivot can be rounding alone), whose back substitution gives the
+// minimiser; LS_W is then evaluated by its definition from the rows in LDS.
+// Lanes take consecutive blocks of the sets in lexicographic order (the
+// first unranked, the rest by successor); the least (value, rank) over the
+// wave is that size's best.  The size is chosen by the penalty rule in
+// increasing size against the incumbent, on values relative to
+// S = <t, t>_w; the chosen set's weights come from its Cholesky solve and
+// its functional is evaluated by definition once more, lanes over k.
+
 #include <math.h>
 
 #include "device.h"
@@ -438,19 +442,20 @@ __device__ __forceinline__ double gram_ab(const double* g, int ia, int ib) {
     return g[(((unsigned)ia * (unsigned)(ia + 1)) >> 1) + (unsigned)ib];
 }
 
+// A pivot at or below this fraction of its Gram diagonal marks a dependent set.
+constexpr double kSearchDep = 1e-8;
+
 // Cholesky factor of G_W for the leading positions of W: the off-diagonal
-// rows of L, the reciprocals of its diagonal, z = L^{-1} h_W and the running
-// sums of z^2.
+// rows of L, the reciprocals of its diagonal and z = L^{-1} h_W.
 struct SetFit {
     double L[kSearchCal][kSearchCal];
     double inv[kSearchCal];
     double z[kSearchCal];
-    double zz[kSearchCal];
 };
 
 // Rows [from, upto) of the factor of G_W (W = candidates idx[...]), rows
 // below `from` already in F.  Returns the first position whose pivot fails
-// the dependence rule (<= 1e-12 of its Gram diagonal), or upto.
+// the dependence rule (<= kSearchDep of its Gram diagonal), or upto.
 __device__ __forceinline__ int fit_rows(const double* g, const double* h, int from, int upto,
                                         const int (&idx)[kSearchCal], SetFit& F) {
 #pragma unroll
@@ -475,7 +480,7 @@ __device__ __forceinline__ int fit_rows(const double* g, const double* h, int fr
             if (b >= a) break;
             piv -= F.L[a][b] * F.L[a][b];
         }
-        if (!(piv > 1e-12 * gaa)) return a;
+        if (!(piv > kSearchDep * gaa)) return a;
         F.inv[a] = 1.0 / sqrt(piv);
         double s = h[idx[a]];
 #pragma unroll
@@ -484,25 +489,30 @@ __device__ __forceinline__ int fit_rows(const double* g, const double* h, int fr
             s -= F.L[a][b] * F.z[b];
         }
         F.z[a] = s * F.inv[a];
-        F.zz[a] = (a == 0 ? 0.0 : F.zz[a > 0 ? a - 1 : 0]) + F.z[a] * F.z[a];
     }
     return upto;
 }
 
 // The functional of the set whose leading M - 1 positions are factored in
-// F: with the last row l = L_{M-1, <M-1} and pivot p, the set's z^T z is
-// the leading sum plus (h - l . z)^2 / p, so no square root is taken.
+// F, by its definition: the last row l = L_{M-1, <M-1} and pivot p complete
+// the factor, back substitution L^T c = z gives the minimiser (its last
+// entry is (h - l . z) / p, so no square root is taken), and the value is
+// sum_k w_k (t_k - sum_a c_a x_{a,k})^2 over the candidate rows in LDS.
+// The shorter form S - |z|^2 cancels: it cannot resolve a value much below
+// eps S, nor one of a set whose weights cancel, and a value it rounds to
+// zero or below would pass the penalty rule as an exact fit; the residual
+// form is off only by |X_W dc|^2, second order in the minimiser's error.
 // false when the last pivot fails the dependence rule.
-template <int M>
-__device__ __forceinline__ bool last_value(const double* g, const double* h, double S,
+template <int M, typename T, int K, int NCAP>
+__device__ __forceinline__ bool last_value(const SearchLds<T, K, NCAP>& Ls,
                                            const int (&idx)[kSearchCal], const SetFit& F,
                                            double* val) {
     constexpr int A = M - 1;
-    const double gaa = gram_ab(g, idx[A], idx[A]);
+    const double gaa = gram_ab(Ls.g, idx[A], idx[A]);
     double l[kSearchCal];
 #pragma unroll
     for (int b = 0; b < A; ++b) {
-        double s = gram_ab(g, idx[A], idx[b]);
+        double s = gram_ab(Ls.g, idx[A], idx[b]);
 #pragma unroll
         for (int c = 0; c < b; ++c) s -= l[c] * F.L[b][c];
         l[b] = s * F.inv[b];
@@ -510,12 +520,28 @@ __device__ __forceinline__ bool last_value(const double* g, const double* h, dou
     double piv = gaa;
 #pragma unroll
     for (int b = 0; b < A; ++b) piv -= l[b] * l[b];
-    if (!(piv > 1e-12 * gaa)) return false;
-    double t = h[idx[A]];
+    if (!(piv > kSearchDep * gaa)) return false;
+    double t = Ls.h[idx[A]];
 #pragma unroll
     for (int b = 0; b < A; ++b) t -= l[b] * F.z[b];
-    const double v = S - ((A > 0 ? F.zz[A > 0 ? A - 1 : 0] : 0.0) + t * t / piv);
-    *val = v > 0.0 ? v : 0.0;
+    double c[kSearchCal];
+    c[A] = t / piv;
+#pragma unroll
+    for (int b = A - 1; b >= 0; --b) {
+        double s = F.z[b] - l[b] * c[A];
+#pragma unroll
+        for (int a = b + 1; a < A; ++a) s -= F.L[a][b] * c[a];
+        c[b] = s * F.inv[b];
+    }
+    double v = 0.0;
+#pragma unroll 1
+    for (int k = 0; k < K; ++k) {
+        double r = Ls.t[k];
+#pragma unroll
+        for (int a = 0; a < M; ++a) r -= c[a] * (double)Ls.x[idx[a]][k];
+        v = fma(Ls.w[k] * r, r, v);
+    }
+    *val = v;
     return true;
 }
 
@@ -575,9 +601,11 @@ __device__ __forceinline__ double pow_series(double x, double e) {
 // rows of the leading positions are refactored only from the first
 // position that changed, and not at all while an unchanged leading
 // position stays dependent.
-template <int M>
-__device__ __forceinline__ void best_of_size(const double* g, const double* h, double S, int nc,
-                                             int lane, double& bv, int& br) {
+template <int M, typename T, int K, int NCAP>
+__device__ __forceinline__ void best_of_size(const SearchLds<T, K, NCAP>& Ls, int nc, int lane,
+                                             double& bv, int& br) {
+    const double* g = Ls.g;
+    const double* h = Ls.h;
     const int total = binom_small(nc, M);
     const int per = (total + kWave - 1) / kWave;
     const int r0 = lane * per, r1 = (r0 + per < total) ? r0 + per : total;
@@ -588,7 +616,7 @@ __device__ __forceinline__ void best_of_size(const double* g, const double* h, d
     int lead = fit_rows(g, h, 0, M - 1, idx, F);  // first dependent leading position, or M - 1
     for (int r = r0;;) {
         double v;
-        if (lead == M - 1 && last_value<M>(g, h, S, idx, F, &v) && v < bv) {
+        if (lead == M - 1 && last_value<M>(Ls, idx, F, &v) && v < bv) {
             bv = v;
             br = r;
         }
@@ -709,10 +737,10 @@ __device__ void search_row(int i, int lane, SearchLds<T, K, NCAP>& L, const int*
         double bv = INFINITY;
         int br = total;
         switch (m) {
-            case 1: best_of_size<1>(L.g, L.h, S, nc, lane, bv, br); break;
-            case 2: best_of_size<2>(L.g, L.h, S, nc, lane, bv, br); break;
-            case 3: best_of_size<3>(L.g, L.h, S, nc, lane, bv, br); break;
-            default: best_of_size<4>(L.g, L.h, S, nc, lane, bv, br); break;
+            case 1: best_of_size<1>(L, nc, lane, bv, br); break;
+            case 2: best_of_size<2>(L, nc, lane, bv, br); break;
+            case 3: best_of_size<3>(L, nc, lane, bv, br); break;
+            default: best_of_size<4>(L, nc, lane, bv, br); break;
         }
         // least (value, rank) over the wave: lanes hold increasing rank blocks
 #pragma unroll

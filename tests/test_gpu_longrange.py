@@ -237,6 +237,39 @@ def test_search_matches_the_oracle(dt, target, d, cal):
     assert ad.status(clear=True) == 0
 
 
+@pytest.mark.parametrize("target", ["residual", "plain"])
+def test_search_near_exact_fits(target):
+    """The setup of the two-grid tables on the 7-point operator with eps
+    1e-4, alpha pi/4 on 64^2: 8 test vectors of 40 Gauss-Seidel sweeps, CR
+    on the strength graph M^2, the search over the C points of A^4.  Near
+    the corners the vectors are nearly of low rank: sets of 4 fit the
+    target to about 1e-20 of its squared norm, and sets of nearly dependent
+    rows fit it through cancelling weights.  The search still agrees with
+    the oracle, its weights stay moderate, and the Galerkin operator is
+    positive definite (the two-grid cycle runs)."""
+    ad = lib()
+    N = 64
+    A = W.rotated_anisotropic_7pt(N, 1e-4, math.pi / 4)
+    Ad = dev_csr(A, torch.float64)
+    color = torch.as_tensor(W.four_colour_2d(N), device="cuda")
+    X = ad.setup_testvectors(Ad, 8, seed=3, relax="gs", sweeps=40, color=color, ncolors=4)
+    G2 = ad.power_graph(Ad, 2)
+    mu2 = ad.algebraic_distance_graph(Ad, G2, X)
+    cf, _, _ = ad.cr_coarsening(Ad, color, 4, mu2, 0.5, seed=1, G=G2)
+    G4 = ad.power_graph(Ad, 4)
+    say("search on A^4 after CR on M^2, eps 1e-4, alpha pi/4, 64^2, %s target" % target)
+    got = ad.ls_interp_search(Ad, G4, X, cf, 4, 1.5, target=target)
+    check_search(A, G4, to_np(X), None, to_np(cf), 4, 1.5, target, got, torch.float64)
+    Pc, Pv, _, _ = got
+    assert float(Pv.abs().max()) < 1e3
+    Ac = ad.galerkin(Ad, Pc, Pv, cf)
+    E0 = torch.rand((A.n, 2), dtype=torch.float64, device="cuda",
+                    generator=torch.Generator(device="cuda").manual_seed(5)) * 2 - 1
+    rho, _ = ad.two_grid_rate(Ad, color, 4, Pc, Pv, cf, Ac, E0, iters=10)
+    assert all(0.0 <= float(r) < 1.0 for r in rho)
+    assert ad.status(clear=True) == 0
+
+
 @pytest.mark.parametrize("gamma", [1.0, 1.5, 3.0])
 def test_search_weights_gamma_and_graph_rows(gamma):
     """Weighted functional, other gammas, a random graph with a random C/F
