@@ -47,6 +47,7 @@ Prints ONE JSON line.
 """
 import argparse
 import json
+import math
 import os
 import sys
 import tempfile
@@ -787,88 +788,80 @@ def cr_leg(args, torch, ad, W, flush):
     return res
 
 
+# Table 1 (Sec. 5.5): the paper's two-grid rate rho with (gamma_g, gamma_o)
+# for N = 32, 64, 128 (d = 2, d_LS = 4, theta_ad 0.5), per (eps, alpha)
+TABLE1 = {
+    (0.1, "pi/4"): ((.10, .35, 1.5), (.22, .30, 1.5), (.22, .27, 1.5)),
+    (0.1, "-pi/4"): ((.31, .35, 1.7), (.36, .34, 1.7), (.48, .32, 1.7)),
+    (0.1, "pi/8"): ((.32, .27, 1.4), (.39, .24, 1.5), (.35, .25, 1.5)),
+    (0.1, "0"): ((.19, .34, 1.6), (.20, .37, 1.7), (.24, .38, 1.7)),
+    (1e-4, "pi/4"): ((.26, .35, 1.5), (.26, .34, 1.5), (.23, .36, 1.5)),
+    (1e-4, "-pi/4"): ((.28, .46, 1.9), (.33, .45, 1.9), (.38, .41, 1.9)),
+    (1e-4, "pi/8"): ((.30, .43, 1.8), (.48, .38, 1.8), (.51, .36, 1.8)),
+    (1e-4, "0"): ((.05, .34, 1.6), (.06, .35, 1.6), (.06, .38, 1.7)),
+    (0.0, "pi/4"): ((.06, .33, 1.4), (.06, .34, 1.4), (.06, .36, 1.5)),
+    (0.0, "-pi/4"): ((.28, .46, 1.9), (.35, .43, 1.9), (.37, .41, 1.9)),
+    (0.0, "pi/8"): ((.30, .43, 1.8), (.49, .38, 1.8), (.52, .36, 1.8)),
+    (0.0, "0"): ((.05, .34, 1.3), (.06, .35, 1.3), (.06, .38, 1.4)),
+}
+ALPHAS = {"pi/4": math.pi / 4, "-pi/4": -math.pi / 4, "pi/8": math.pi / 8, "0": 0.0}
+
+
 def quality_leg(args, torch, ad, W, flush):
     """The whole two-level setup on the GPU and the two-grid quality of
-    Sec. 5.2: K = 8 test vectors with 40 Gauss-Seidel sweeps, distances,
-    CR coarsening (theta 0.5, nu 5, delta 0.7), interpolation with caliber
-    4, A_c = P^T A P and the two-grid rate (100 cycles, 2 + 2 sweeps, four
-    random starts).  Gauss-Seidel runs in the four-colour (ix mod 2, iy mod
-    2) order, a valid colouring of the 7- and 9-point stencils (the
-    checkerboard leaves diagonal neighbours in one colour, which makes the
-    smoother Jacobi-like along them).  Interpolation on each CR grid three
-    ways: LS rows on the C-neighbours of A (d_LS = 1), and the set search
-    over the C points of the patterns of A^2 and A^4 (gamma 1.5); and the
-    paper's configuration for its Table 1, CR on the strength graph M^2
-    with the search on A^4.  Cases: the 7-point rotated anisotropy with
-    eps 1e-2 at alpha 0, pi/4, -pi/4, pi/8 on 64^2, alpha pi/4 also on
-    128^2, and the 9-point one (eps 1e-3, alpha pi/6) on 128^2; and the
-    Galerkin product on the full 2048^2 operator with the CR coarse grid and
-    LS rows of the step's test vectors."""
-    import math
-    res = {"cases": [], "smoother": "Gauss-Seidel, four-colour order, 2 + 2 sweeps"}
+    Sec. 5.2, on every case of Table 1 (the 7-point rotated anisotropy,
+    eps 0.1, 1e-4, 0; alpha pi/4, -pi/4, pi/8, 0; N = 32, 64, 128) in the
+    paper's configuration: K = 8 test vectors with 40 Gauss-Seidel sweeps,
+    distances on the pattern of A^2, CR coarsening on the strength graph
+    M^2 (theta 0.5, nu 5, delta 0.7), interpolation by the set search over
+    the C points of A^4 (caliber 4, gamma 1.5) on the functional of
+    eq:modls (residual target), A_c = P^T A P and the two-grid rate (100
+    cycles, 2 + 2 sweeps, four random starts); the same grid with the plain
+    target of eq:LSfuncrowi beside it.  Gauss-Seidel runs in the four-colour
+    (ix mod 2, iy mod 2) order, a valid colouring of the 7-point stencil
+    (the checkerboard leaves the diagonal neighbours in one colour, which
+    makes the smoother Jacobi-like along them).  Also the Galerkin product
+    on the full 2048^2 operator with the CR coarse grid and LS rows of the
+    step's test vectors."""
+    res = {"cases": [], "smoother": "Gauss-Seidel, four-colour order, 2 + 2 sweeps",
+           "config": "CR on M^2 (d = 2), set search on A^4 (d_LS = 4), caliber 4, gamma 1.5, "
+                     "K = 8, 40 sweeps, theta 0.5, nu 5, delta 0.7; rho = max over 4 starts",
+           "paper": "Table 1 (Sec. 5.5): rho (gamma_g, gamma_o)"}
     f7 = W.rotated_anisotropic_7pt
-    cases = [("fd7 eps 1e-2 alpha 0", lambda N: f7(N, 1e-2, 0.0), 64),
-             ("fd7 eps 1e-2 alpha pi/4", lambda N: f7(N, 1e-2, math.pi / 4), 64),
-             ("fd7 eps 1e-2 alpha -pi/4", lambda N: f7(N, 1e-2, -math.pi / 4), 64),
-             ("fd7 eps 1e-2 alpha pi/8", lambda N: f7(N, 1e-2, math.pi / 8), 64),
-             ("fd7 eps 1e-2 alpha pi/4", lambda N: f7(N, 1e-2, math.pi / 4), 128),
-             ("9pt eps 1e-3 alpha pi/6", lambda N: W.rotated_anisotropic_9pt(N, 1e-3, math.pi / 6),
-              128)]
-    for name, gen, N in cases:
-        Ah = gen(N)
-        A = ad.Csr.from_host(Ah, dtype=torch.float64)
-        color = torch.as_tensor(W.four_colour_2d(N), device="cuda")
-        t0 = time.perf_counter()
-        X = ad.setup_testvectors(A, 8, seed=3, relax="gs", sweeps=40, color=color, ncolors=4)
-        mu = ad.algebraic_distance(A, X)
-        cf, rho_cr, nc_cr = ad.cr_coarsening(A, color, 4, mu, 0.5, seed=1)
-        Pc, Pv, ls, st = ad.ls_interp(A, X, cf, mu, 4)
-        Ac = ad.galerkin(A, Pc, Pv, cf)
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        E0 = torch.rand((A.n, 4), dtype=torch.float64, device="cuda", generator=torch.Generator(
-            device="cuda").manual_seed(5)) * 2 - 1
-        rho, hist = ad.two_grid_rate(A, color, 4, Pc, Pv, cf, Ac, E0, iters=100)
-        t2 = time.perf_counter()
-        case = {"operator": "%s, %d^2" % (name, N), "rows": A.n, "coarse": Ac.n,
-                "cr_stages": len(rho_cr) - 1, "rho_f": [round(r, 4) for r in rho_cr],
-                "gamma_g": round(Ac.n / A.n, 3),
-                "ls_d1": {"two_grid_rho": [round(float(r), 4) for r in rho],
-                          "gamma_o": round((A.nnz + Ac.nnz) / A.nnz, 3)},
-                "setup_ms": round((t1 - t0) * 1e3, 1),
-                "two_grid_100_cycles_ms": round((t2 - t1) * 1e3, 1)}
-        line = ["d1 %s" % np.round(rho, 3)]
-        # the same C points, interpolation by the set search over the C
-        # points of the pattern of A^d (caliber 4, gamma 1.5; Sec. 4.3)
-        for d in (2, 4):
-            G = ad.power_graph(A, d)
-            Ps, Pvs, _, st_s = ad.ls_interp_search(A, G, X, cf, 4, 1.5)
-            Acs = ad.galerkin(A, Ps, Pvs, cf)
-            rho_s, _ = ad.two_grid_rate(A, color, 4, Ps, Pvs, cf, Acs, E0, iters=100)
-            sv, sc = np.unique(st_s.cpu().numpy(), return_counts=True)
-            case["search_d%d" % d] = {"two_grid_rho": [round(float(r), 4) for r in rho_s],
-                                      "gamma_o": round((A.nnz + Acs.nnz) / A.nnz, 3),
-                                      "status_counts": {str(k): int(v) for k, v in zip(sv, sc)}}
-            line.append("d%d %s" % (d, np.round(rho_s, 3)))
-            del G, Ps, Pvs, Acs
-        # the paper's configuration: CR on the strength graph M^2 (distances
-        # on the pattern of A^2), then the set search on A^4
-        G2 = ad.power_graph(A, 2)
-        mu2 = ad.algebraic_distance_graph(A, G2, X)
-        cf2, rho_cr2, _ = ad.cr_coarsening(A, color, 4, mu2, 0.5, seed=1, G=G2)
-        G4 = ad.power_graph(A, 4)
-        P2, Pv2, _, _ = ad.ls_interp_search(A, G4, X, cf2, 4, 1.5)
-        Ac2 = ad.galerkin(A, P2, Pv2, cf2)
-        rho2, _ = ad.two_grid_rate(A, color, 4, P2, Pv2, cf2, Ac2, E0, iters=100)
-        case["cr_m2_search_d4"] = {"two_grid_rho": [round(float(r), 4) for r in rho2],
-                                   "rho_f": [round(r, 4) for r in rho_cr2],
-                                   "gamma_g": round(Ac2.n / A.n, 3),
-                                   "gamma_o": round((A.nnz + Ac2.nnz) / A.nnz, 3)}
-        line.append("CR on M^2 + d4 %s" % np.round(rho2, 3))
-        del G2, mu2, cf2, G4, P2, Pv2, Ac2
-        res["cases"].append(case)
-        log("two-grid %s %d^2: %s" % (name, N, "; ".join(line)))
-        del A, X, mu, cf, Pc, Pv, Ac, E0
+    for (eps, aname), paper in TABLE1.items():
+        for N, (p_rho, p_gg, p_go) in zip((32, 64, 128), paper):
+            Ah = f7(N, eps, ALPHAS[aname])
+            A = ad.Csr.from_host(Ah, dtype=torch.float64)
+            color = torch.as_tensor(W.four_colour_2d(N), device="cuda")
+            t0 = time.perf_counter()
+            X = ad.setup_testvectors(A, 8, seed=3, relax="gs", sweeps=40, color=color, ncolors=4)
+            G2 = ad.power_graph(A, 2)
+            mu2 = ad.algebraic_distance_graph(A, G2, X)
+            cf, rho_cr, _ = ad.cr_coarsening(A, color, 4, mu2, 0.5, seed=1, G=G2)
+            G4 = ad.power_graph(A, 4)
+            E0 = torch.rand((A.n, 4), dtype=torch.float64, device="cuda", generator=torch.Generator(
+                device="cuda").manual_seed(5)) * 2 - 1
+            case = {"eps": eps, "alpha": aname, "N": N, "rows": A.n,
+                    "gamma_g": round(int(cf.sum()) / A.n, 3), "cr_stages": len(rho_cr) - 1,
+                    "rho_f": round(float(rho_cr[-1]), 3),
+                    "paper": {"rho": p_rho, "gamma_g": p_gg, "gamma_o": p_go}}
+            line = []
+            for target in ("residual", "plain"):
+                P, Pv, _, _ = ad.ls_interp_search(A, G4, X, cf, 4, 1.5, target=target)
+                Ac = ad.galerkin(A, P, Pv, cf)
+                rho, _ = ad.two_grid_rate(A, color, 4, P, Pv, cf, Ac, E0, iters=100)
+                case[target] = {"rho": round(float(max(rho)), 3),
+                                "rho_starts": [round(float(r), 4) for r in rho],
+                                "gamma_o": round((A.nnz + Ac.nnz) / A.nnz, 3)}
+                line.append("%s %.2f (%.2f, %.2f)" % (target, max(rho), case["gamma_g"],
+                                                      case[target]["gamma_o"]))
+                del P, Pv, Ac
+            torch.cuda.synchronize()
+            case["ms"] = round((time.perf_counter() - t0) * 1e3, 1)
+            res["cases"].append(case)
+            log("two-grid eps %g alpha %s %d^2: %s; paper %.2f (%.2f, %.1f)"
+                % (eps, aname, N, "; ".join(line), p_rho, p_gg, p_go))
+            del A, X, G2, mu2, cf, G4, E0
     # the Galerkin product at full size
     wl = W.workload(2, "f32", size=args.size)
     A = ad.Csr.from_host(wl.A, dtype=torch.float32)
