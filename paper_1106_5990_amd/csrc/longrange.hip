@@ -444,6 +444,8 @@ __device__ __forceinline__ double gram_ab(const double* g, int ia, int ib) {
 
 // A pivot at or below this fraction of its Gram diagonal marks a dependent set.
 constexpr double kSearchDep = 1e-8;
+// Bound on the short form's rounding, in units of S + M sum_a c_a^2 G_aa.
+constexpr double kSearchRound = 1e-12;
 
 // Cholesky factor of G_W for the leading positions of W: the off-diagonal
 // rows of L, the reciprocals of its diagonal and z = L^{-1} h_W.
@@ -494,17 +496,22 @@ __device__ __forceinline__ int fit_rows(const double* g, const double* h, int fr
 }
 
 // The functional of the set whose leading M - 1 positions are factored in
-// F, by its definition: the last row l = L_{M-1, <M-1} and pivot p complete
-// the factor, back substitution L^T c = z gives the minimiser (its last
-// entry is (h - l . z) / p, so no square root is taken), and the value is
-// sum_k w_k (t_k - sum_a c_a x_{a,k})^2 over the candidate rows in LDS.
-// The shorter form S - |z|^2 cancels: it cannot resolve a value much below
-// eps S, nor one of a set whose weights cancel, and a value it rounds to
-// zero or below would pass the penalty rule as an exact fit; the residual
-// form is off only by |X_W dc|^2, second order in the minimiser's error.
-// false when the last pivot fails the dependence rule.
+// F, against the lane's best value `cut`.  The last row l = L_{M-1, <M-1}
+// and pivot p complete the factor; back substitution L^T c = z gives the
+// minimiser (its last entry (h - l . z) / p, no square root).  The short
+// form S - |z|^2 cancels: it cannot resolve a value much below eps S, nor
+// one of a set whose weights cancel, and a value it rounds to zero or below
+// would pass the penalty rule as an exact fit.  Its error is within
+// kSearchRound (S + M sum_a c_a^2 G_aa) (rounding of the Gram entries
+// carried through the minimiser; 1.7 eps times that bound at most over
+// 27 000 sets of near-exact and nearly dependent fits), so a set whose
+// short form minus that bound is not below `cut` cannot beat the lane's
+// best and is dropped; every other set is evaluated by its definition,
+// sum_k w_k (t_k - sum_a c_a x_{a,k})^2 over the candidate rows in LDS,
+// off only by |X_W dc|^2.  false when the last pivot fails the dependence
+// rule or the set is dropped.
 template <int M, typename T, int K, int NCAP>
-__device__ __forceinline__ bool last_value(const SearchLds<T, K, NCAP>& Ls,
+__device__ __forceinline__ bool last_value(const SearchLds<T, K, NCAP>& Ls, double S, double cut,
                                            const int (&idx)[kSearchCal], const SetFit& F,
                                            double* val) {
     constexpr int A = M - 1;
@@ -526,13 +533,18 @@ __device__ __forceinline__ bool last_value(const SearchLds<T, K, NCAP>& Ls,
     for (int b = 0; b < A; ++b) t -= l[b] * F.z[b];
     double c[kSearchCal];
     c[A] = t / piv;
+    double zz = t * c[A];  // z_{M-1}^2
+    double cg = c[A] * c[A] * gaa;
 #pragma unroll
     for (int b = A - 1; b >= 0; --b) {
         double s = F.z[b] - l[b] * c[A];
 #pragma unroll
         for (int a = b + 1; a < A; ++a) s -= F.L[a][b] * c[a];
         c[b] = s * F.inv[b];
+        zz = fma(F.z[b], F.z[b], zz);
+        cg = fma(c[b] * c[b], gram_ab(Ls.g, idx[b], idx[b]), cg);
     }
+    if (S - zz - kSearchRound * (S + (double)M * cg) >= cut) return false;
     double v = 0.0;
 #pragma unroll 1
     for (int k = 0; k < K; ++k) {
@@ -602,8 +614,8 @@ __device__ __forceinline__ double pow_series(double x, double e) {
 // position that changed, and not at all while an unchanged leading
 // position stays dependent.
 template <int M, typename T, int K, int NCAP>
-__device__ __forceinline__ void best_of_size(const SearchLds<T, K, NCAP>& Ls, int nc, int lane,
-                                             double& bv, int& br) {
+__device__ __forceinline__ void best_of_size(const SearchLds<T, K, NCAP>& Ls, double S, int nc,
+                                             int lane, double& bv, int& br) {
     const double* g = Ls.g;
     const double* h = Ls.h;
     const int total = binom_small(nc, M);
@@ -616,7 +628,7 @@ __device__ __forceinline__ void best_of_size(const SearchLds<T, K, NCAP>& Ls, in
     int lead = fit_rows(g, h, 0, M - 1, idx, F);  // first dependent leading position, or M - 1
     for (int r = r0;;) {
         double v;
-        if (lead == M - 1 && last_value<M>(Ls, idx, F, &v) && v < bv) {
+        if (lead == M - 1 && last_value<M>(Ls, S, bv, idx, F, &v) && v < bv) {
             bv = v;
             br = r;
         }
@@ -737,10 +749,10 @@ __device__ void search_row(int i, int lane, SearchLds<T, K, NCAP>& L, const int*
         double bv = INFINITY;
         int br = total;
         switch (m) {
-            case 1: best_of_size<1>(L, nc, lane, bv, br); break;
-            case 2: best_of_size<2>(L, nc, lane, bv, br); break;
-            case 3: best_of_size<3>(L, nc, lane, bv, br); break;
-            default: best_of_size<4>(L, nc, lane, bv, br); break;
+            case 1: best_of_size<1>(L, S, nc, lane, bv, br); break;
+            case 2: best_of_size<2>(L, S, nc, lane, bv, br); break;
+            case 3: best_of_size<3>(L, S, nc, lane, bv, br); break;
+            default: best_of_size<4>(L, S, nc, lane, bv, br); break;
         }
         // least (value, rank) over the wave: lanes hold increasing rank blocks
 #pragma unroll
