@@ -366,11 +366,13 @@ int algebraic_distance_graph(ad_handle h, const ad_csr *A, int64_t nnz_g,
  * the candidates are N_i = the C-points (cf != 0) of row i of the pattern G
  * (eq:nbhd with G the pattern of A^{d_LS}), i excluded.  Every set W within
  * N_i with 1 <= |W| <= caliber is fitted (the LS functional of Sec. 3.1,
- * eq:LSfuncrowi or eq:modls per target, weights w); a set whose Gram
- * matrix has a Cholesky pivot <= 1e-12 of its diagonal is numerically
- * dependent and skipped.  For each size m the set of least functional
- * best_m is kept (ties: the first in lexicographic order of candidate
- * positions).  The size follows the penalty rule of Sec. 4.3 read as a scan
+ * eq:LSfuncrowi or eq:modls per target, weights w): its minimiser by a
+ * Cholesky of its Gram matrix, its functional by definition from the
+ * residual; a set whose Gram matrix has a Cholesky pivot <= 1e-8 of its
+ * diagonal (a column with a part independent of the earlier ones below
+ * 1e-4 of its norm) is numerically dependent and skipped.  For each size m
+ * the set of least functional best_m is kept (ties: the first in
+ * lexicographic order of candidate positions).  The size follows the penalty rule of Sec. 4.3 read as a scan
  * in increasing size against the incumbent, on values relative to the
  * empty set's S = sum_k w_k t_k^2: the incumbent starts at the smallest size
  * with a fitted set and is replaced by size m when
