@@ -849,7 +849,13 @@ def quality_leg(args, torch, ad, W, flush):
             for target in ("residual", "plain"):
                 P, Pv, _, _ = ad.ls_interp_search(A, G4, X, cf, 4, 1.5, target=target)
                 Ac = ad.galerkin(A, P, Pv, cf)
-                rho, _ = ad.two_grid_rate(A, color, 4, P, Pv, cf, Ac, E0, iters=100)
+                try:
+                    rho, _ = ad.two_grid_rate(A, color, 4, P, Pv, cf, Ac, E0, iters=100)
+                except ad.AlgdistError as e:  # e.g. a coarse operator that is not SPD
+                    case[target] = {"error": str(e), "max_abs_P": float(Pv.abs().max())}
+                    line.append("%s error" % target)
+                    del P, Pv, Ac
+                    continue
                 case[target] = {"rho": round(float(max(rho)), 3),
                                 "rho_starts": [round(float(r), 4) for r in rho],
                                 "gamma_o": round((A.nnz + Ac.nnz) / A.nnz, 3)}

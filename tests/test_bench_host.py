@@ -146,3 +146,20 @@ def test_precision_statement_counts_flips_by_band():
     assert out["P_val_scaled_err"]["rows_C_differ"] == int(F[3])
     assert out["P_val_scaled_err"]["max"] == pytest.approx(1e-8, rel=1e-3)
     assert out["mu_rel_err"]["max"] < 2e-7
+
+
+def test_table1_cases():
+    """The quality leg's copy of Table 1 (Sec. 5.5): three anisotropies
+    times four angles, each with rho (gamma_g, gamma_o) for N = 32, 64, 128,
+    every value in the range the table prints; spot entries as printed."""
+    T = bench.TABLE1
+    assert sorted({e for e, _ in T}) == [0.0, 1e-4, 0.1]
+    assert set(bench.ALPHAS) == {a for _, a in T} == {"pi/4", "-pi/4", "pi/8", "0"}
+    assert len(T) == 12
+    for key, rows in T.items():
+        assert len(rows) == 3, key
+        for rho, gg, go in rows:
+            assert 0.0 < rho < 1.0 and 0.2 < gg < 0.5 and 1.0 < go < 2.0, key
+    assert T[(0.1, "pi/4")][0] == (.10, .35, 1.5)
+    assert T[(1e-4, "0")][2] == (.06, .38, 1.7)
+    assert T[(0.0, "pi/8")][1] == (.49, .38, 1.8)
