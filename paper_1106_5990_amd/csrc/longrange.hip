@@ -744,9 +744,16 @@ __device__ void search_row(int i, int lane, SearchLds<T, K, NCAP>& L, const int*
         bvs[q] = INFINITY;
         brs[q] = 0x7fffffff;
     }
+    // A set of size m can win only below the best of the largest smaller size
+    // that has one (prev): a superset's functional is never larger, and the
+    // penalty rule takes size m only below (incumbent / S)^(gamma (m - size))
+    // S, which is below that best whether or not that size was taken.  So prev
+    // starts each lane's screen; a size none of whose sets gets below it is
+    // treated as having none, which changes no choice.
+    double prev = INFINITY;
     for (int m = 1; m <= mmax; ++m) {
         const int total = binom_small(nc, m);
-        double bv = INFINITY;
+        double bv = prev;
         int br = total;
         switch (m) {
             case 1: best_of_size<1>(L, S, nc, lane, bv, br); break;
@@ -764,7 +771,8 @@ __device__ void search_row(int i, int lane, SearchLds<T, K, NCAP>& L, const int*
                 br = orr;
             }
         }
-        if (br >= total) br = 0x7fffffff;  // every set of this size was dependent
+        if (br >= total) br = 0x7fffffff;  // every set dependent, or none below prev
+        else prev = bv;
 #pragma unroll
         for (int q = 0; q < kSearchCal; ++q)
             if (q == m - 1) {
