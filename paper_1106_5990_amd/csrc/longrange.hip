@@ -570,15 +570,23 @@ __device__ __forceinline__ void fit_coef(const SetFit& F, int m, double (&coef)[
     }
 }
 
+// A value equal in every lane of the wavefront, moved to scalar registers.
+__device__ __forceinline__ double wave_uniform(double x) {
+    return __hiloint2double(__builtin_amdgcn_readfirstlane(__double2hiint(x)),
+                            __builtin_amdgcn_readfirstlane(__double2loint(x)));
+}
+
 // x^e for x >= 0, e >= 0 from exp(e log x), both by series: log by
 // reduction to m 2^k with m in [sqrt(1/2), sqrt(2)) and log m =
 // 2 atanh((m - 1) / (m + 1)) (odd-power series, 12 terms), exp by
 // reduction to r + j ln 2 with |r| <= ln 2 / 2 and the Taylor series of e^r
 // (18 terms), ln 2 split in a high and a low part.  The relative error
 // grows with |e log x| (about 1e-13 at e log x = -660, a few 1e-16 for
-// |e log x| below 1); only the penalty rule's comparisons use it, where a
-// library pow would set the register count of the whole kernel.
-__device__ __forceinline__ double pow_series(double x, double e) {
+// |e log x| below 1); only the penalty rule's thresholds use it, where a
+// library pow would set the register count of the whole kernel.  Out of
+// line: called a few times per row, inlined it raised the search kernel
+// from 157 to 179 VGPRs (3 to 2 wavefronts per SIMD).
+__device__ __noinline__ double pow_series(double x, double e) {
     if (e == 0.0) return 1.0;
     if (!(x > 0.0)) return 0.0;
     if (isinf(x)) return x;
@@ -714,6 +722,7 @@ __device__ void search_row(int i, int lane, SearchLds<T, K, NCAP>& L, const int*
     double S = 0.0;
 #pragma unroll 4
     for (int k = 0; k < K; ++k) S = fma(L.w[k] * L.t[k], L.t[k], S);
+    S = wave_uniform(S);
     // h_a and the Gram matrix of the candidates
     if (lane < nc) {
         double s = 0.0;
@@ -744,16 +753,25 @@ __device__ void search_row(int i, int lane, SearchLds<T, K, NCAP>& L, const int*
         bvs[q] = INFINITY;
         brs[q] = 0x7fffffff;
     }
-    // A set of size m can win only below the best of the largest smaller size
-    // that has one (prev): a superset's functional is never larger, and the
-    // penalty rule takes size m only below (incumbent / S)^(gamma (m - size))
-    // S, which is below that best whether or not that size was taken.  So prev
-    // starts each lane's screen; a size none of whose sets gets below it is
-    // treated as having none, which changes no choice.
-    double prev = INFINITY;
+    // The penalty rule takes size m only below thr_m = (incumbent / S)^(gamma
+    // (m - size)) S, the incumbent being the scan's below over the smaller
+    // sizes; thr_m is also below the best of the largest smaller size that has
+    // one (prev: a superset never fits worse).  So min(prev, thr_m), with a
+    // relative slack of 1e-12 against rounding, starts each lane's screen: a
+    // set at or above it cannot be taken, and a size none of whose sets gets
+    // below it is treated as having none, which changes no choice.  run_m,
+    // run_v follow the scan's incumbent size by size.
+    double prev = INFINITY, run_v = 0.0;
+    int run_m = 0;
     for (int m = 1; m <= mmax; ++m) {
         const int total = binom_small(nc, m);
-        double bv = prev;
+        double cut = prev, thr_rel = 0.0;
+        if (run_m > 0) {
+            thr_rel = wave_uniform(
+                pow_series(S > 0.0 ? run_v / S : 0.0, gamma * (double)(m - run_m)));
+            cut = fmin(cut, S * thr_rel * (1.0 + 1e-12));
+        }
+        double bv = cut;
         int br = total;
         switch (m) {
             case 1: best_of_size<1>(L, S, nc, lane, bv, br); break;
@@ -771,8 +789,16 @@ __device__ void search_row(int i, int lane, SearchLds<T, K, NCAP>& L, const int*
                 br = orr;
             }
         }
-        if (br >= total) br = 0x7fffffff;  // every set dependent, or none below prev
-        else prev = bv;
+        if (br >= total) {
+            br = 0x7fffffff;  // every set dependent, or none below the cut: not taken
+        } else {
+            prev = wave_uniform(bv);
+            // the scan's rule (below) for this size: any set found is below thr_m
+            if (run_m == 0 || (S > 0.0 ? bv / S : 0.0) < thr_rel) {
+                run_m = m;
+                run_v = prev;
+            }
+        }
 #pragma unroll
         for (int q = 0; q < kSearchCal; ++q)
             if (q == m - 1) {
