@@ -754,13 +754,14 @@ __device__ void search_row(int i, int lane, SearchLds<T, K, NCAP>& L, const int*
         brs[q] = 0x7fffffff;
     }
     // The penalty rule takes size m only below thr_m = (incumbent / S)^(gamma
-    // (m - size)) S, the incumbent being the scan's below over the smaller
-    // sizes; thr_m is also below the best of the largest smaller size that has
-    // one (prev: a superset never fits worse).  So min(prev, thr_m), with a
-    // relative slack of 1e-12 against rounding, starts each lane's screen: a
-    // set at or above it cannot be taken, and a size none of whose sets gets
-    // below it is treated as having none, which changes no choice.  run_m,
-    // run_v follow the scan's incumbent size by size.
+    // (m - size)) S, where the incumbent is what the scan after this loop
+    // holds once it has passed the smaller sizes (run_m, run_v follow it size
+    // by size with the same rule); and a set of size m below that can also
+    // only lie below prev, the best of the largest smaller size that has one
+    // (a superset never fits worse).  So min(prev, thr_m), with a relative
+    // slack of 1e-12 against rounding, starts each lane's screen: a set at or
+    // above it cannot be taken, and a size none of whose sets gets below it
+    // is treated as having none, which changes no choice.
     double prev = INFINITY, run_v = 0.0;
     int run_m = 0;
     for (int m = 1; m <= mmax; ++m) {
