@@ -268,3 +268,37 @@ def test_two_grid_with_sixteen_starts():
                                  gpu(cf), Ac, gpu(E0), iters=30)
     assert np.allclose(hist, hist_ref, rtol=1e-8, atol=0)
     assert np.allclose(rho, rho_ref, rtol=1e-9, atol=0)
+
+
+@pytest.mark.parametrize("eps", [1e-4, 0.0])
+def test_table1_grid_aligned_case_on_the_gpu(eps):
+    """The whole two-level setup on the GPU for a case Table 1 (Sec. 5.5)
+    prints, rho = .05: the 7-point operator with alpha = 0 on 32^2, 8 test
+    vectors of 40 Gauss-Seidel sweeps, CR on M^2, the set search on A^4 with
+    the functional of eq:modls, A_c and the two-grid rate.  The rate is below
+    0.1, and the oracle's two-grid method on the GPU's P and A_c gives the
+    same rate and history."""
+    ad = lib()
+    N = 32
+    A = W.rotated_anisotropic_7pt(N, eps, 0.0)
+    Ad = dev_csr(A, torch.float64)
+    color = W.four_colour_2d(N)
+    cd = gpu(color)
+    X = ad.setup_testvectors(Ad, 8, seed=3, relax="gs", sweeps=40, color=cd, ncolors=4)
+    G2 = ad.power_graph(Ad, 2)
+    mu2 = ad.algebraic_distance_graph(Ad, G2, X)
+    cf, _, _ = ad.cr_coarsening(Ad, cd, 4, mu2, 0.5, seed=1, G=G2)
+    G4 = ad.power_graph(Ad, 4)
+    Pc, Pv, _, _ = ad.ls_interp_search(Ad, G4, X, cf, 4, 1.5, target="residual")
+    Ac = ad.galerkin(Ad, Pc, Pv, cf)
+    E0 = oracle.tv_init(A.n, 2, 13)
+    rho, hist = ad.two_grid_rate(Ad, cd, 4, Pc, Pv, cf, Ac, gpu(E0), iters=60)
+    say("  eps %g: rho %s, gamma_g %.3f" % (eps, np.round(rho, 4), Ac.n / A.n))
+    assert float(max(rho)) < 0.1
+    Ac_h = oracle.CoarseCSR(Ac.n, to_np(Ac.row_ptr), to_np(Ac.col), to_np(Ac.val))
+    rho_ref, bad, hist_ref = oracle.two_grid(A, color, 4, to_np(Pc), to_np(Pv), to_np(cf), Ac_h,
+                                             E0, iters=60)
+    assert bad == 0
+    assert np.allclose(hist, hist_ref, rtol=1e-8, atol=0)
+    assert np.allclose(rho, rho_ref, rtol=1e-9, atol=0)
+    assert ad.status(clear=True) == 0
